@@ -1,0 +1,161 @@
+"""Throughput of the SGN RK4 hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload: the 1024x512 transversely perturbed line soliton (a = 0.5,
+eps = 0.01, k = 2, x0 = -10) on [-10pi, 10pi] x [-5pi, 5pi], FP64, RK4 with
+dt = 0.005, GMRES tol 1e-10, restart 20, Krasny filter 1e-12.  W untimed
+warm-up steps, then K timed steps (one library call), bracketed by
+device synchronisations; inputs are resident on the GPU before timing.
+
+Prints one JSON line: grid-points x RK4 steps per second, GMRES iterations
+per solve, a roofline entry for the dominant kernel (algorithmic bytes per
+launch / its mean duration from HIP events recorded by the library on its
+stream during the timed steps), and the FP64 oracle timed on the host CPU on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "grid-pts×RK4 steps/s at GMRES tol; iters/solve, plain vs learned"
+UNIT = "grid-pts×RK4 steps/s"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "perturbed_soliton_1024x512"
+PARAMS = dict(a=0.5, eps=0.01, k=2)
+KRASNY = 1e-12
+
+# Algorithmic bytes per grid point of one launch of each timed kernel class
+# (fields read + written once each, FP64): the x-part of the elliptic
+# operator reads E, G (x-half spectra) and h and writes P, Q.
+ALGO_BYTES_PER_POINT = {"row_matvec": 5 * 8}
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=100)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-steps", type=int, default=1)
+    return p.parse_args()
+
+
+def traffic_from_profile(kernel: str):
+    """HBM bytes per launch measured with rocprofv3 counters, if the summary in
+    profiles/ was taken on the kernel source currently in the tree."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{WORKLOAD}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    h = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", text)
+    if not m or not h:
+        return None
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2306_09731_amd", "csrc", "sgn_kernels.hip"), "rb").read()
+    if hashlib.sha256(src).hexdigest() != h.group(1):
+        return None
+    return float(m.group(1))
+
+
+def cpu_baseline(steps: int):
+    import numpy as np  # noqa: F401
+    from oracle import sgn_oracle as O
+    from sgn_inputs import workload
+    box, (h, vx, vy, s), w = workload(WORKLOAD, **PARAMS)
+    g = O.Grid(O.Config(nx=box.nx, ny=box.ny, Lx=box.Lx, Ly=box.Ly, gmres_tol=w["tol"],
+                        gmres_restart=w["restart"], krasny=KRASNY))
+    t0 = time.perf_counter()
+    O.rk4(g, h, vx, vy, s, w["dt"], steps)
+    dt = time.perf_counter() - t0
+    return {"value": box.nx * box.ny * steps / dt, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": f"{steps} RK4 step(s) of the {box.nx}x{box.ny} workload from t=0 "
+                      f"(numpy FP64, single-threaded FFTs), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver is single-GPU.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2306_09731_amd import sgn
+    from sgn_inputs import workload
+
+    box, (h, vx, vy, s), w = workload(WORKLOAD, **PARAMS)
+    dev = torch.device("cuda:0")
+    cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"], gmres_restart=w["restart"],
+                             krasny=KRASNY)
+    ctx = sgn.sgn_init(cfg, dev)
+    th, tvx, tvy, ts = (torch.from_numpy(a).to(dev).contiguous() for a in (h, vx, vy, s))
+    if args.warmup > 0:
+        sgn.sgn_rk4_step(ctx, th, tvx, tvy, ts, w["dt"], args.warmup)
+    dominant = "row_matvec"
+    kind = [k for k, v in sgn.KERNEL_NAMES.items() if v == dominant][0]
+    sgn.sgn_kernel_timing(ctx, kind, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = sgn.sgn_rk4_step(ctx, th, tvx, tvy, ts, w["dt"], args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    launches, kms = sgn.sgn_kernel_time(ctx, kind)
+    sgn.sgn_kernel_timing(ctx, kind, False)
+    npts = box.nx * box.ny
+    value = npts * args.steps / elapsed
+    algo = ALGO_BYTES_PER_POINT[dominant] * npts
+    mean_s = (kms / launches) / 1e3 if launches else float("nan")
+    achieved = algo / mean_s / 1e9 if launches else None
+    traffic = traffic_from_profile(dominant)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": WORKLOAD, "nx": box.nx, "ny": box.ny, "Lx": box.Lx, "Ly": box.Ly,
+            "a": PARAMS["a"], "eps": PARAMS["eps"], "k": PARAMS["k"], "dt": w["dt"],
+            "gmres_tol": w["tol"], "gmres_restart": w["restart"], "krasny": KRASNY,
+            "guess": "plain (warm start from the previous sigma)",
+            "iters_per_solve_mean": info.total_iters / max(info.solves, 1),
+            "iters_per_solve_max": info.max_iters_per_solve,
+            "solves": info.solves,
+        },
+        "roofline": {
+            "kernel": f"k_row_op<{box.nx},0> ({dominant})",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": algo,
+            "mean_launch_us": mean_s * 1e6,
+            "launches": launches,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

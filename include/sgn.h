@@ -1,0 +1,188 @@
+/*
+ * libsgn -- the hot path of a Fourier-spectral / GMRES solver of the 2D
+ * Serre-Green-Naghdi (SGN) equations on one MI355X (gfx950) GPU, after
+ * Gavrilyuk & Klein, "Numerical study of the Serre-Green-Naghdi equations in
+ * 2D" (arXiv 2306.09731).
+ *
+ * The method (paper, Sections 2.2 and 3):
+ *   state       depth h > 0 and the generalized velocity v = grad(phi)
+ *   elliptic    L_h[sigma] = 3 sigma / h^3 - div(grad sigma / h) = -div v   (eq. (sigmav))
+ *   evolution   h_t = -div(h v) + Laplacian(sigma)                           (eq. (1))
+ *               v_t = -grad(|v|^2/2 - |grad sigma|^2/(2 h^2) + g h - 9/2 sigma^2/h^4)  (eq. (2), gradient form)
+ *   space       Fourier collocation on the torus of periods 2 pi Lx x 2 pi Ly;
+ *               derivatives are multiplications by i k
+ *   solver      GMRES on M^-1 L sigma = M^-1 b, left preconditioner
+ *               M = 3 + kx^2 + ky^2 (L at h = 1), warm-started from the last sigma
+ *   time        classical explicit RK4; optional Krasny filter (zero DFT
+ *               coefficients with modulus below a threshold)
+ *   invariants  mass, momentum and energy (Section 2.3)
+ *
+ * Conventions shared by every call
+ *   - Fields are FP64 DEVICE pointers owned by the caller: contiguous,
+ *     row-major [ny][nx] (x contiguous), 256-byte aligned.  Grid points are
+ *     x_j = -pi Lx + j * 2 pi Lx / nx (same in y).
+ *   - Wavenumbers are k = m / L, m in [-n/2, n/2), with the Nyquist mode of
+ *     every derivative set to zero; the preconditioner uses the same k, with
+ *     M = 3 / h_inf^3 + (kx^2 + ky^2) / h_inf (= 3 + k^2 for h_inf = 1).
+ *   - The library never allocates device memory: all scratch lives in the
+ *     caller's workspace (sgn_workspace_bytes).  It allocates a few bytes of
+ *     pinned host memory for status read-back.
+ *   - All work is ordered on the stream given to sgn_init.  The GMRES loop
+ *     reads a status word back once per batch of speculative iterations, so
+ *     the solving calls synchronise that stream before they return.
+ *   - A context is not thread-safe; use one per stream.
+ *   - Argument checks happen on the host before any launch.
+ */
+#ifndef SGN_H
+#define SGN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+  SGN_OK = 0,
+  SGN_ERR_INVALID_ARG = 1,   /* null or misaligned pointer, bad size, tol <= 0, ... */
+  SGN_ERR_UNSUPPORTED = 2,   /* nx or ny not a power of two in [8, 4096], restart > 64 */
+  SGN_ERR_HIP = 3,           /* HIP runtime error; see sgn_last_error */
+  SGN_ERR_NOT_CONVERGED = 4, /* GMRES hit gmres_max_iters; outputs hold the last iterate */
+  SGN_ERR_CAVITATION = 5,    /* min h <= 0 (the method assumes h > 0, Section 1) */
+  SGN_ERR_NONFINITE = 6      /* NaN or Inf in the state */
+};
+
+enum { SGN_FP64 = 0 };
+
+/* Problem and solver parameters.  Defaults in brackets (sgn_config_default). */
+typedef struct sgn_config {
+  int32_t nx, ny;          /* grid, powers of two in [8, 4096] */
+  double Lx, Ly;           /* periods are 2 pi Lx, 2 pi Ly; box [-pi L, pi L) */
+  double g;                /* gravity [1] (the paper sets g = h_inf = 1, Section 4) */
+  double h_inf;            /* depth at infinity [1] */
+  int32_t precision;       /* SGN_FP64 */
+  int32_t gmres_restart;   /* restart length m [20], 1..64 */
+  double gmres_tol;        /* stop when ||M^-1 (b - L s)|| <= tol ||M^-1 b|| [1e-10] */
+  int32_t gmres_max_iters; /* total Arnoldi steps per solve [10 * restart] */
+  int32_t batch;           /* 1 */
+  double krasny;           /* Krasny threshold on |DFT| / (nx ny) [0 = off; the paper uses 1e-12] */
+  double invariants_tol;   /* GMRES tolerance of the sigma solve in sgn_invariants [1e-13] */
+} sgn_config;
+
+typedef struct sgn_ctx sgn_ctx;
+
+typedef struct sgn_solve_info {
+  int32_t iters;            /* Arnoldi steps over all cycles */
+  int32_t restarts;         /* completed cycles that did not converge */
+  int32_t converged;        /* 1 if the stopping test was met */
+  int32_t pad;
+  double rel_resid_precond; /* ||M^-1 (b - L s)|| / ||M^-1 b|| at exit (GMRES estimate) */
+  double rel_resid_true;    /* ||b - L s|| / ||b|| (computed by sgn_elliptic_solve only, else -1) */
+} sgn_solve_info;
+
+typedef struct sgn_step_info {
+  int64_t total_iters;         /* Arnoldi steps over all solves */
+  int32_t max_iters_per_solve;
+  int32_t solves;              /* 4 per RK4 step */
+  double min_h;                /* min h after the last step */
+  int32_t any_unconverged;
+  int32_t pad;
+} sgn_step_info;
+
+typedef struct sgn_invariants_out {
+  double mass;          /* integral of (h - h_inf)                      (Section 2.3) */
+  double px, py;        /* integral of h u, u = v - grad(sigma)/h        (Section 2.3) */
+  double energy;        /* integral of h|u|^2/2 + 3 sigma^2/(2 h^3) + g (h - h_inf)^2 / 2 (Section 2.3) */
+  double min_h, max_h;  /* extrema of h on the grid (Section 4.2 monitors the max) */
+  double curl_l2;       /* L2 norm of d_x v_y - d_y v_x (zero for potential flows, Section 2.1) */
+  double spectral_tail; /* largest |DFT(h)| / (nx ny) with |m_x| > nx/4 or |m_y| > ny/4 (Section 3) */
+} sgn_invariants_out;
+
+/* Fill *cfg with the defaults for an nx x ny grid on periods 2 pi Lx x 2 pi Ly. */
+void sgn_config_default(sgn_config* cfg, int32_t nx, int32_t ny, double Lx, double Ly);
+
+/* Bytes of device workspace sgn_init needs for cfg, or 0 if cfg is invalid.
+ * Holds the twiddle tables, the Krylov basis ((restart + 1) fields), the
+ * spectral scratch, the RK4 registers and the reduction scratch. */
+size_t sgn_workspace_bytes(const sgn_config* cfg);
+
+/* Validate cfg, lay out the caller's device workspace (ws, ws_bytes >=
+ * sgn_workspace_bytes(cfg), 256-byte aligned), upload the FP64 twiddle tables
+ * and the GMRES state, and return a context in *out.  hip_stream is a
+ * hipStream_t (NULL = the default stream).  The workspace must outlive the
+ * context.  Errors: SGN_ERR_INVALID_ARG, SGN_ERR_UNSUPPORTED, SGN_ERR_HIP. */
+int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream, sgn_ctx** out);
+
+/* Free the host side of the context (the workspace stays the caller's). */
+int sgn_destroy(sgn_ctx* ctx);
+
+/* Solve L_h sigma = b (eq. (sigmav) with a given right-hand side) by
+ * restarted left-preconditioned GMRES.  h, b: device fields; sigma: device
+ * field, in = initial guess, out = solution.  info may be NULL.  Returns
+ * SGN_ERR_NOT_CONVERGED (sigma = last iterate) if gmres_max_iters is hit. */
+int sgn_elliptic_solve(sgn_ctx* ctx, const double* h, const double* b, double* sigma, sgn_solve_info* info);
+
+/* One evaluation of the right-hand side of the (h, v) system (Section 3):
+ *   b = -div v;  sigma = GMRES(L_h, b; x0 = sigma);
+ *   dh = -div(h v - grad sigma);  dv = -grad B,
+ *   B = |v|^2/2 - |grad sigma|^2/(2 h^2) + g h - 9/2 sigma^2/h^4.
+ * sigma is in/out (warm start in, solution out).  dh, dvx, dvy: outputs. */
+int sgn_rhs(sgn_ctx* ctx, const double* h, const double* vx, const double* vy, double* sigma, double* dh,
+            double* dvx, double* dvy, sgn_solve_info* info);
+
+/* nsteps classical RK4 steps of size dt, in place on (h, vx, vy) (Section 3).
+ * sigma is in/out: the warm start of the first solve, and on return the sigma
+ * of the last RHS evaluation; each solve starts from the previous one's
+ * sigma.  With cfg.krasny > 0 the Krasny filter is applied to h, vx, vy
+ * after every step.  info may be NULL. */
+int sgn_rk4_step(sgn_ctx* ctx, double* h, double* vx, double* vy, double* sigma, double dt, int32_t nsteps,
+                 sgn_step_info* info);
+
+/* Conserved quantities of Section 2.3 for the state (h, vx, vy): sigma is
+ * first solved to cfg.invariants_tol from the guess in sigma (in/out), then
+ * mass, momentum, energy, min/max h, ||curl v|| and the spectral tail of h are
+ * reduced in FP64 and written to the host struct *out. */
+int sgn_invariants(sgn_ctx* ctx, const double* h, const double* vx, const double* vy, double* sigma,
+                   sgn_invariants_out* out);
+
+/* Building blocks of the hot path, exposed for testing.
+ * sgn_derivative: out = d f / dx (axis 0) or d f / dy (axis 1) (Section 3: i k).
+ * sgn_apply_operator: out = L_h s (eq. (3)), or M^-1 L_h s if precondition != 0.
+ * sgn_apply_precond: out = M^-1 r (Section 3).
+ * sgn_krasny_filter: Krasny filter of f in place with threshold cfg.krasny (Section 3).
+ * All fields are device pointers; out may not alias an input. */
+int sgn_derivative(sgn_ctx* ctx, int32_t axis, const double* f, double* out);
+int sgn_apply_operator(sgn_ctx* ctx, const double* h, const double* s, double* out, int32_t precondition);
+int sgn_apply_precond(sgn_ctx* ctx, const double* r, double* out);
+int sgn_krasny_filter(sgn_ctx* ctx, double* f);
+
+/* Measurement support.  While timing is enabled for a kernel class, every
+ * launch of that class is bracketed by HIP events recorded on the context
+ * stream, so its device time can be read without a profiler.
+ * sgn_kernel_timing(ctx, kind, 1) clears the totals and starts timing kind
+ * (one class at a time); (ctx, kind, 0) stops it.  sgn_kernel_time
+ * synchronises the stream and returns the number of timed launches and their
+ * total duration in milliseconds.  Errors: SGN_ERR_INVALID_ARG for an unknown
+ * kind, SGN_ERR_HIP. */
+enum {
+  SGN_KERNEL_ROW_MATVEC = 0,     /* x part of the elliptic operator (Arnoldi step) */
+  SGN_KERNEL_COL_BASIS = 1,      /* new Krylov vector + inverse y transforms */
+  SGN_KERNEL_COL_PRECOND_DOT = 2,/* y part of the operator, M^-1, projections */
+  SGN_KERNEL_GS_UPDATE = 3,      /* Gram-Schmidt update, norms, Givens */
+  SGN_KERNEL_ROW_FLUX = 4,       /* x part of the fluxes + RK4 combine of v_x */
+  SGN_KERNEL_COL_FLUX = 5,       /* y part of the fluxes + RK4 combine of h, v_y */
+  SGN_KERNEL_COUNT = 6
+};
+int sgn_kernel_timing(sgn_ctx* ctx, int32_t kind, int32_t enable);
+int sgn_kernel_time(sgn_ctx* ctx, int32_t kind, int64_t* launches, double* total_ms);
+
+/* Human-readable name of a status code, and the last error of a context. */
+const char* sgn_status_string(int status);
+const char* sgn_last_error(const sgn_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGN_H */

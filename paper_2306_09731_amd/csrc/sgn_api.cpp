@@ -1,0 +1,632 @@
+// C-ABI of libsgn: argument checks, workspace layout, the GMRES control
+// loop and the RK4 / RHS / invariants sequences of kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sgn.h"
+#include "sgn_internal.hpp"
+#include "sgn_launch.hpp"
+
+using sgn::cplx;
+
+struct sgn_ctx {
+  sgn_config cfg;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  sgn::Geom g;
+  size_t vstride;  // complex entries per field
+  sgn::GmresState* st;
+  double* partials;
+  cplx *V, *W, *E, *G, *P, *Q, *R1, *R2, *SIG;
+  double *hs, *vxs, *vys, *acc_h, *acc_vx, *acc_vy;
+  sgn::GmresStatus* hstat;  // pinned host copy of the device status
+  int last_iters;
+  std::string err;
+  // kernel timing (measurement support)
+  int timed_kind = -1;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+  int64_t timed_launches = 0;
+  double timed_ms = 0.0;
+};
+
+namespace {
+
+bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+int check_config(const sgn_config* c) {
+  if (!c) return SGN_ERR_INVALID_ARG;
+  if (!(std::isfinite(c->Lx) && c->Lx > 0 && std::isfinite(c->Ly) && c->Ly > 0)) return SGN_ERR_INVALID_ARG;
+  if (!(std::isfinite(c->g) && c->g > 0 && std::isfinite(c->h_inf) && c->h_inf > 0)) return SGN_ERR_INVALID_ARG;
+  if (!(std::isfinite(c->gmres_tol) && c->gmres_tol > 0)) return SGN_ERR_INVALID_ARG;
+  if (!(std::isfinite(c->invariants_tol) && c->invariants_tol > 0)) return SGN_ERR_INVALID_ARG;
+  if (!(std::isfinite(c->krasny) && c->krasny >= 0)) return SGN_ERR_INVALID_ARG;
+  if (c->gmres_max_iters < 1) return SGN_ERR_INVALID_ARG;
+  if (c->gmres_restart < 1) return SGN_ERR_INVALID_ARG;
+  if (c->gmres_restart > sgn::kMaxRestart) return SGN_ERR_UNSUPPORTED;
+  if (c->precision != SGN_FP64) return SGN_ERR_UNSUPPORTED;
+  if (c->batch != 1) return SGN_ERR_UNSUPPORTED;
+  if (!pow2_in(c->nx, 8, 4096) || !pow2_in(c->ny, 8, 4096)) return SGN_ERR_UNSUPPORTED;
+  return SGN_OK;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t tw, st, partials, fields, total;
+  size_t field_bytes;
+  int nfields;
+};
+
+Layout layout(const sgn_config* c) {
+  Layout L;
+  const size_t n = (size_t)c->nx * c->ny;
+  L.field_bytes = align_up(n * sizeof(double));
+  sgn::Geom g{};
+  g.nx = c->nx;
+  g.ny = c->ny;
+  g.nh = c->nx / 2;
+  const int pblocks = sgn::max_partial_blocks(g);
+  size_t off = 0;
+  L.tw = off;
+  off += align_up((size_t)(c->nx + c->ny) * sizeof(cplx));
+  L.st = off;
+  off += align_up(sizeof(sgn::GmresState));
+  L.partials = off;
+  off += align_up((size_t)pblocks * sgn::kPartialStride * sizeof(double));
+  L.fields = off;
+  // V (restart + 1), W, E, G, P, Q, R1, R2, SIG, hs, vxs, vys, acc_h, acc_vx, acc_vy
+  L.nfields = c->gmres_restart + 1 + 14;
+  off += (size_t)L.nfields * L.field_bytes;
+  L.total = off;
+  return L;
+}
+
+int fail(sgn_ctx* ctx, hipError_t e, const char* what) {
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+  ctx->err = buf;
+  return SGN_ERR_HIP;
+}
+
+#define HIPCK(expr)                                   \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return fail(ctx, e_, #expr); \
+  } while (0)
+
+bool aligned(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+hipEvent_t take_event(sgn_ctx* ctx) {
+  if (!ctx->ev_free.empty()) {
+    hipEvent_t e = ctx->ev_free.back();
+    ctx->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Accumulate the durations of the recorded event pairs (synchronises).
+int drain_timing(sgn_ctx* ctx) {
+  if (ctx->ev_pending.empty()) return SGN_OK;
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  for (auto& pr : ctx->ev_pending) {
+    float ms = 0.f;
+    HIPCK(hipEventElapsedTime(&ms, pr.first, pr.second));
+    ctx->timed_ms += ms;
+    ctx->timed_launches += 1;
+    ctx->ev_free.push_back(pr.first);
+    ctx->ev_free.push_back(pr.second);
+  }
+  ctx->ev_pending.clear();
+  return SGN_OK;
+}
+
+// Brackets one launch with events when its kernel class is being timed.
+struct KernelTimer {
+  sgn_ctx* ctx;
+  hipEvent_t a = nullptr, b = nullptr;
+  KernelTimer(sgn_ctx* c, int kind) : ctx(c) {
+    if (c->timed_kind != kind) return;
+    a = take_event(c);
+    b = take_event(c);
+    if (a && b) (void)hipEventRecord(a, c->stream);
+  }
+  void stop() {
+    if (!a || !b) return;
+    (void)hipEventRecord(b, ctx->stream);
+    ctx->ev_pending.emplace_back(a, b);
+    a = b = nullptr;
+    if (ctx->ev_pending.size() >= 4096) (void)drain_timing(ctx);
+  }
+};
+
+#define TIMED(kind, expr)              \
+  do {                                 \
+    KernelTimer kt_(ctx, kind);        \
+    HIPCK(expr);                       \
+    kt_.stop();                        \
+  } while (0)
+
+int read_status(sgn_ctx* ctx) {
+  HIPCK(hipMemcpyAsync(ctx->hstat, &ctx->st->st, sizeof(sgn::GmresStatus), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  return SGN_OK;
+}
+
+int set_tol(sgn_ctx* ctx, double tol) {
+  HIPCK(hipMemcpyAsync(&ctx->st->tol, &tol, sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));  // tol is a host local
+  return SGN_OK;
+}
+
+// sigma (physical) -> E = F_x sigma, SIG = F sigma, G = F_x d_y sigma
+int load_sigma(sgn_ctx* ctx, const double* sigma) {
+  HIPCK(sgn::launch_row_r2c(ctx->g, sigma, ctx->E, ctx->stream));
+  HIPCK(sgn::launch_col_fwd_eg(ctx->g, ctx->E, ctx->SIG, ctx->G, ctx->stream));
+  return SGN_OK;
+}
+
+int check_state(sgn_ctx* ctx, const double* a, const double* b, const double* c) {
+  HIPCK(sgn::launch_field_stats(a, b, c, (size_t)ctx->g.nx * ctx->g.ny, ctx->st, ctx->partials, ctx->stream));
+  int rc = read_status(ctx);
+  if (rc) return rc;
+  if (ctx->hstat->stat_nonfinite) {
+    ctx->err = "non-finite value in the input";
+    return SGN_ERR_NONFINITE;
+  }
+  if (!(ctx->hstat->stat_minh > 0.0)) {
+    ctx->err = "min h <= 0";
+    return SGN_ERR_CAVITATION;
+  }
+  return SGN_OK;
+}
+
+struct SolveResult {
+  int iters = 0, restarts = 0, converged = 0;
+  double rel_resid = 0.0;
+};
+
+// Restarted GMRES for L_h sigma = b with the warm start held in (SIG, E, G).
+// mode 1: b = -div v from (vx, vy); mode 2: b given (passed as vx).
+// On return (SIG, E, G) hold the solution.
+int run_solve(sgn_ctx* ctx, int mode, const double* h, const double* vx, const double* vy, SolveResult* res) {
+  const sgn::Geom& g = ctx->g;
+  hipStream_t s = ctx->stream;
+  const int m = ctx->cfg.gmres_restart;
+  const int maxit = ctx->cfg.gmres_max_iters;
+  int need_b = 1, flags = 1;
+  int total = 0;
+  res->restarts = 0;
+  res->converged = 0;
+  for (;;) {
+    HIPCK(sgn::launch_row_op(g, mode, ctx->E, ctx->G, h, vx, vy, ctx->P, ctx->Q, ctx->R1, ctx->R2, need_b, 0,
+                             ctx->st, s));
+    // an explicit b (mode 2) has b_hat = F_y(R1) only
+    HIPCK(sgn::launch_col_resid(g, ctx->P, ctx->Q, ctx->R1, mode == 2 ? nullptr : ctx->R2, need_b, flags, ctx->st,
+                                ctx->W, ctx->partials, s));
+    need_b = 0;
+    flags = 0;
+    int j = 0;
+    int batch = ctx->last_iters + 1;
+    if (batch < 1) batch = 1;
+    for (;;) {
+      int nrun = batch;
+      if (nrun > m - j) nrun = m - j;
+      if (nrun > maxit - total - j) nrun = maxit - total - j;
+      for (int it = j; it < j + nrun; ++it) {
+        TIMED(SGN_KERNEL_COL_BASIS,
+              sgn::launch_col_basis_eg(g, ctx->W, ctx->V, ctx->vstride, it, ctx->st, ctx->E, ctx->G, s));
+        TIMED(SGN_KERNEL_ROW_MATVEC, sgn::launch_row_op(g, 0, ctx->E, ctx->G, h, nullptr, nullptr, ctx->P, ctx->Q,
+                                                        nullptr, nullptr, 0, 1, ctx->st, s));
+        TIMED(SGN_KERNEL_COL_PRECOND_DOT, sgn::launch_col_precond_dot(g, ctx->P, ctx->Q, ctx->V, ctx->vstride, it,
+                                                                      ctx->st, ctx->W, ctx->partials, s));
+        TIMED(SGN_KERNEL_GS_UPDATE, sgn::launch_upd(g, ctx->W, ctx->V, ctx->vstride, it, ctx->st, ctx->partials, s));
+      }
+      j += nrun;
+      int rc = read_status(ctx);
+      if (rc) return rc;
+      if (ctx->hstat->done) break;
+      if (j >= m || total + j >= maxit) break;
+      batch = 2;
+    }
+    const sgn::GmresStatus& st = *ctx->hstat;
+    total = st.total_iters;
+    // sigma_hat += V y, and E, G of the new sigma
+    HIPCK(sgn::launch_col_update_eg(g, ctx->SIG, ctx->V, ctx->vstride, ctx->st, ctx->E, ctx->G, s));
+    res->rel_resid = st.beta0 > 0 ? st.resid / st.beta0 : 0.0;
+    if (st.done == 1) {
+      res->converged = 1;
+      break;
+    }
+    if (total >= maxit) break;
+    res->restarts += 1;
+  }
+  res->iters = total;
+  ctx->last_iters = total < m ? total : m;
+  return SGN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sgn_config_default(sgn_config* cfg, int32_t nx, int32_t ny, double Lx, double Ly) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof *cfg);
+  cfg->nx = nx;
+  cfg->ny = ny;
+  cfg->Lx = Lx;
+  cfg->Ly = Ly;
+  cfg->g = 1.0;
+  cfg->h_inf = 1.0;
+  cfg->precision = SGN_FP64;
+  cfg->gmres_restart = 20;
+  cfg->gmres_tol = 1e-10;
+  cfg->gmres_max_iters = 200;
+  cfg->batch = 1;
+  cfg->krasny = 0.0;
+  cfg->invariants_tol = 1e-13;
+}
+
+size_t sgn_workspace_bytes(const sgn_config* cfg) {
+  if (check_config(cfg) != SGN_OK) return 0;
+  return layout(cfg).total;
+}
+
+int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream, sgn_ctx** out) {
+  if (!out) return SGN_ERR_INVALID_ARG;
+  *out = nullptr;
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  const Layout L = layout(cfg);
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0 || ws_bytes < L.total) return SGN_ERR_INVALID_ARG;
+  sgn_ctx* ctx = new sgn_ctx();
+  ctx->cfg = *cfg;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  ctx->ws = static_cast<char*>(ws);
+  ctx->ws_bytes = ws_bytes;
+  ctx->last_iters = cfg->gmres_restart / 2;
+  const int nx = cfg->nx, ny = cfg->ny;
+  sgn::Geom& g = ctx->g;
+  g.nx = nx;
+  g.ny = ny;
+  g.nh = nx / 2;
+  g.inv_Lx = 1.0 / cfg->Lx;
+  g.inv_Ly = 1.0 / cfg->Ly;
+  g.inv_nx = 1.0 / nx;
+  g.inv_ny = 1.0 / ny;
+  g.inv_n = 1.0 / ((double)nx * ny);
+  g.g = cfg->g;
+  g.h_inf = cfg->h_inf;
+  g.m0 = 3.0 / (cfg->h_inf * cfg->h_inf * cfg->h_inf);
+  g.m1 = 1.0 / cfg->h_inf;
+  g.dA = (2.0 * M_PI * cfg->Lx / nx) * (2.0 * M_PI * cfg->Ly / ny);
+  char* base = ctx->ws;
+  cplx* tw = reinterpret_cast<cplx*>(base + L.tw);
+  g.twx = tw;
+  g.twy = tw + nx;
+  ctx->st = reinterpret_cast<sgn::GmresState*>(base + L.st);
+  ctx->partials = reinterpret_cast<double*>(base + L.partials);
+  ctx->vstride = L.field_bytes / sizeof(cplx);
+  char* f = base + L.fields;
+  auto next = [&]() {
+    char* p = f;
+    f += L.field_bytes;
+    return p;
+  };
+  ctx->V = reinterpret_cast<cplx*>(f);
+  f += (size_t)(cfg->gmres_restart + 1) * L.field_bytes;
+  ctx->W = reinterpret_cast<cplx*>(next());
+  ctx->E = reinterpret_cast<cplx*>(next());
+  ctx->G = reinterpret_cast<cplx*>(next());
+  ctx->P = reinterpret_cast<cplx*>(next());
+  ctx->Q = reinterpret_cast<cplx*>(next());
+  ctx->R1 = reinterpret_cast<cplx*>(next());
+  ctx->R2 = reinterpret_cast<cplx*>(next());
+  ctx->SIG = reinterpret_cast<cplx*>(next());
+  ctx->hs = reinterpret_cast<double*>(next());
+  ctx->vxs = reinterpret_cast<double*>(next());
+  ctx->vys = reinterpret_cast<double*>(next());
+  ctx->acc_h = reinterpret_cast<double*>(next());
+  ctx->acc_vx = reinterpret_cast<double*>(next());
+  ctx->acc_vy = reinterpret_cast<double*>(next());
+
+  // FP64 twiddles exp(-2 pi i k / n), from the symmetric angle to keep the
+  // table accurate to a rounding of the exact value
+  std::vector<cplx> htw((size_t)nx + ny);
+  auto fill = [&](cplx* dst, int n) {
+    for (int k = 0; k < n; ++k) {
+      const double a = 2.0 * M_PI * (double)k / (double)n;
+      dst[k] = make_double2(std::cos(a), -std::sin(a));
+    }
+  };
+  fill(htw.data(), nx);
+  fill(htw.data() + nx, ny);
+  sgn::GmresState hst;
+  std::memset(&hst, 0, sizeof hst);
+  hst.tol = cfg->gmres_tol;
+  hst.m = cfg->gmres_restart;
+  hipError_t e = hipMemcpyAsync(tw, htw.data(), htw.size() * sizeof(cplx), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->st, &hst, sizeof hst, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ctx->hstat), sizeof(sgn::GmresStatus), 0);
+  if (e != hipSuccess) {
+    delete ctx;
+    return SGN_ERR_HIP;
+  }
+  *out = ctx;
+  return SGN_OK;
+}
+
+int sgn_destroy(sgn_ctx* ctx) {
+  if (!ctx) return SGN_ERR_INVALID_ARG;
+  (void)drain_timing(ctx);
+  for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
+  if (ctx->hstat) (void)hipHostFree(ctx->hstat);
+  delete ctx;
+  return SGN_OK;
+}
+
+int sgn_elliptic_solve(sgn_ctx* ctx, const double* h, const double* b, double* sigma, sgn_solve_info* info) {
+  if (!ctx || !aligned(h) || !aligned(b) || !aligned(sigma)) return SGN_ERR_INVALID_ARG;
+  int rc = check_state(ctx, h, b, b);
+  if (rc) return rc;
+  rc = load_sigma(ctx, sigma);
+  if (rc) return rc;
+  SolveResult res;
+  rc = run_solve(ctx, 2, h, b, nullptr, &res);
+  if (rc) return rc;
+  HIPCK(sgn::launch_row_c2r(ctx->g, ctx->E, sigma, ctx->stream));
+  if (info) {
+    // ||b - L sigma|| from the final (E, G)
+    HIPCK(sgn::launch_row_op(ctx->g, 2, ctx->E, ctx->G, h, b, nullptr, ctx->P, ctx->Q, ctx->R1, ctx->R2, 0, 0,
+                             ctx->st, ctx->stream));
+    HIPCK(sgn::launch_col_resid(ctx->g, ctx->P, ctx->Q, nullptr, nullptr, 0, 2, ctx->st, nullptr, ctx->partials,
+                                ctx->stream));
+    rc = read_status(ctx);
+    if (rc) return rc;
+    info->iters = res.iters;
+    info->restarts = res.restarts;
+    info->converged = res.converged;
+    info->rel_resid_precond = res.rel_resid;
+    const double bn = ctx->hstat->bnorm;
+    info->rel_resid_true = bn > 0 ? std::sqrt(ctx->hstat->true_resid2) / bn : 0.0;
+  } else {
+    HIPCK(hipStreamSynchronize(ctx->stream));
+  }
+  return res.converged ? SGN_OK : SGN_ERR_NOT_CONVERGED;
+}
+
+int sgn_rhs(sgn_ctx* ctx, const double* h, const double* vx, const double* vy, double* sigma, double* dh,
+            double* dvx, double* dvy, sgn_solve_info* info) {
+  if (!ctx || !aligned(h) || !aligned(vx) || !aligned(vy) || !aligned(sigma) || !aligned(dh) || !aligned(dvx) ||
+      !aligned(dvy))
+    return SGN_ERR_INVALID_ARG;
+  int rc = check_state(ctx, h, vx, vy);
+  if (rc) return rc;
+  rc = load_sigma(ctx, sigma);
+  if (rc) return rc;
+  SolveResult res;
+  rc = run_solve(ctx, 1, h, vx, vy, &res);
+  if (rc) return rc;
+  sgn::RkStage rk{0, 0, 0.0, 0.0, 0.0};
+  double* dhp = reinterpret_cast<double*>(ctx->P);
+  double* qy = reinterpret_cast<double*>(ctx->Q);
+  double* B = reinterpret_cast<double*>(ctx->R1);
+  HIPCK(sgn::launch_row_flux(ctx->g, ctx->E, ctx->G, h, vx, vy, dhp, qy, B, rk, sgn::RkField{nullptr, nullptr, dvx},
+                             ctx->stream));
+  HIPCK(sgn::launch_col_flux(ctx->g, dhp, qy, B, rk, sgn::RkField{nullptr, nullptr, dh},
+                             sgn::RkField{nullptr, nullptr, dvy}, ctx->stream));
+  HIPCK(sgn::launch_row_c2r(ctx->g, ctx->E, sigma, ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  if (info) {
+    info->iters = res.iters;
+    info->restarts = res.restarts;
+    info->converged = res.converged;
+    info->rel_resid_precond = res.rel_resid;
+    info->rel_resid_true = -1.0;
+  }
+  return res.converged ? SGN_OK : SGN_ERR_NOT_CONVERGED;
+}
+
+int sgn_rk4_step(sgn_ctx* ctx, double* h, double* vx, double* vy, double* sigma, double dt, int32_t nsteps,
+                 sgn_step_info* info) {
+  if (!ctx || !aligned(h) || !aligned(vx) || !aligned(vy) || !aligned(sigma) || nsteps < 0 || !std::isfinite(dt))
+    return SGN_ERR_INVALID_ARG;
+  int rc = check_state(ctx, h, vx, vy);
+  if (rc) return rc;
+  rc = load_sigma(ctx, sigma);
+  if (rc) return rc;
+  const sgn::Geom& g = ctx->g;
+  hipStream_t s = ctx->stream;
+  double* dhp = reinterpret_cast<double*>(ctx->P);
+  double* qy = reinterpret_cast<double*>(ctx->Q);
+  double* B = reinterpret_cast<double*>(ctx->R1);
+  int64_t total = 0;
+  int maxper = 0, solves = 0, unconv = 0;
+  for (int step = 0; step < nsteps; ++step) {
+    for (int stage = 0; stage < 4; ++stage) {
+      const double* ih = stage == 0 ? h : ctx->hs;
+      const double* ivx = stage == 0 ? vx : ctx->vxs;
+      const double* ivy = stage == 0 ? vy : ctx->vys;
+      SolveResult res;
+      rc = run_solve(ctx, 1, ih, ivx, ivy, &res);
+      if (rc) return rc;
+      total += res.iters;
+      if (res.iters > maxper) maxper = res.iters;
+      solves += 1;
+      unconv |= !res.converged;
+      sgn::RkStage rk;
+      if (stage < 3) {
+        rk.mode = 1;
+        rk.first = stage == 0;
+        rk.wacc = stage == 0 ? 1.0 / 6.0 : 1.0 / 3.0;
+        rk.cnext = stage == 2 ? dt : 0.5 * dt;
+      } else {
+        rk.mode = 2;
+        rk.first = 0;
+        rk.wacc = 1.0 / 6.0;
+        rk.cnext = 0.0;
+      }
+      rk.dt = dt;
+      const bool last = stage == 3;
+      sgn::RkField fvx{vx, ctx->acc_vx, last ? vx : ctx->vxs};
+      sgn::RkField fh{h, ctx->acc_h, last ? h : ctx->hs};
+      sgn::RkField fvy{vy, ctx->acc_vy, last ? vy : ctx->vys};
+      TIMED(SGN_KERNEL_ROW_FLUX, sgn::launch_row_flux(g, ctx->E, ctx->G, ih, ivx, ivy, dhp, qy, B, rk, fvx, s));
+      TIMED(SGN_KERNEL_COL_FLUX, sgn::launch_col_flux(g, dhp, qy, B, rk, fh, fvy, s));
+    }
+    if (ctx->cfg.krasny > 0.0) {
+      double* fs[3] = {h, vx, vy};
+      for (double* f : fs) {
+        HIPCK(sgn::launch_row_r2c(g, f, ctx->P, s));
+        HIPCK(sgn::launch_col_filter(g, ctx->P, 1, ctx->cfg.krasny, ctx->Q, s));
+        HIPCK(sgn::launch_row_c2r(g, ctx->Q, f, s));
+      }
+    }
+  }
+  HIPCK(sgn::launch_row_c2r(g, ctx->E, sigma, s));
+  HIPCK(sgn::launch_field_stats(h, vx, vy, (size_t)g.nx * g.ny, ctx->st, ctx->partials, s));
+  rc = read_status(ctx);
+  if (rc) return rc;
+  if (info) {
+    info->total_iters = total;
+    info->max_iters_per_solve = maxper;
+    info->solves = solves;
+    info->min_h = ctx->hstat->stat_minh;
+    info->any_unconverged = unconv;
+  }
+  if (ctx->hstat->stat_nonfinite) return SGN_ERR_NONFINITE;
+  if (!(ctx->hstat->stat_minh > 0.0)) return SGN_ERR_CAVITATION;
+  return unconv ? SGN_ERR_NOT_CONVERGED : SGN_OK;
+}
+
+int sgn_invariants(sgn_ctx* ctx, const double* h, const double* vx, const double* vy, double* sigma,
+                   sgn_invariants_out* out) {
+  if (!ctx || !out || !aligned(h) || !aligned(vx) || !aligned(vy) || !aligned(sigma)) return SGN_ERR_INVALID_ARG;
+  int rc = check_state(ctx, h, vx, vy);
+  if (rc) return rc;
+  rc = set_tol(ctx, ctx->cfg.invariants_tol);
+  if (rc) return rc;
+  rc = load_sigma(ctx, sigma);
+  SolveResult res;
+  if (!rc) rc = run_solve(ctx, 1, h, vx, vy, &res);
+  const int rc2 = set_tol(ctx, ctx->cfg.gmres_tol);
+  if (rc) return rc;
+  if (rc2) return rc2;
+  const sgn::Geom& g = ctx->g;
+  double* dyvx = reinterpret_cast<double*>(ctx->R2);
+  HIPCK(sgn::launch_col_dy(g, vx, dyvx, ctx->stream));
+  HIPCK(sgn::launch_row_invariants(g, ctx->E, ctx->G, h, vx, vy, dyvx, ctx->partials, ctx->st, ctx->stream));
+  HIPCK(sgn::launch_row_r2c(g, h, ctx->P, ctx->stream));
+  HIPCK(sgn::launch_col_tail(g, ctx->P, ctx->st, ctx->partials, ctx->stream));
+  HIPCK(sgn::launch_row_c2r(g, ctx->E, sigma, ctx->stream));
+  rc = read_status(ctx);
+  if (rc) return rc;
+  const double* r = ctx->hstat->red;
+  out->mass = r[0];
+  out->px = r[1];
+  out->py = r[2];
+  out->energy = r[3];
+  out->curl_l2 = r[4];
+  out->min_h = r[5];
+  out->max_h = r[6];
+  out->spectral_tail = r[7];
+  return res.converged ? SGN_OK : SGN_ERR_NOT_CONVERGED;
+}
+
+int sgn_derivative(sgn_ctx* ctx, int32_t axis, const double* f, double* out) {
+  if (!ctx || !aligned(f) || !aligned(out) || f == out || (axis != 0 && axis != 1)) return SGN_ERR_INVALID_ARG;
+  if (axis == 0)
+    HIPCK(sgn::launch_row_dx(ctx->g, f, out, ctx->stream));
+  else
+    HIPCK(sgn::launch_col_dy(ctx->g, f, out, ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  return SGN_OK;
+}
+
+int sgn_apply_operator(sgn_ctx* ctx, const double* h, const double* s, double* out, int32_t precondition) {
+  if (!ctx || !aligned(h) || !aligned(s) || !aligned(out) || out == s || out == h) return SGN_ERR_INVALID_ARG;
+  const sgn::Geom& g = ctx->g;
+  hipStream_t st = ctx->stream;
+  HIPCK(sgn::launch_row_r2c(g, s, ctx->E, st));
+  HIPCK(sgn::launch_col_fwd_eg(g, ctx->E, ctx->R1, ctx->G, st));
+  HIPCK(sgn::launch_row_op(g, 0, ctx->E, ctx->G, h, nullptr, nullptr, ctx->P, ctx->Q, nullptr, nullptr, 0, 0, ctx->st,
+                           st));
+  HIPCK(sgn::launch_col_apply(g, ctx->P, ctx->Q, precondition ? 1 : 0, ctx->W, st));
+  HIPCK(sgn::launch_col_inv(g, ctx->W, ctx->R2, st));
+  HIPCK(sgn::launch_row_c2r(g, ctx->R2, out, st));
+  HIPCK(hipStreamSynchronize(st));
+  return SGN_OK;
+}
+
+int sgn_apply_precond(sgn_ctx* ctx, const double* r, double* out) {
+  if (!ctx || !aligned(r) || !aligned(out) || out == r) return SGN_ERR_INVALID_ARG;
+  const sgn::Geom& g = ctx->g;
+  HIPCK(sgn::launch_row_r2c(g, r, ctx->E, ctx->stream));
+  HIPCK(sgn::launch_col_filter(g, ctx->E, 0, 0.0, ctx->P, ctx->stream));
+  HIPCK(sgn::launch_row_c2r(g, ctx->P, out, ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  return SGN_OK;
+}
+
+int sgn_krasny_filter(sgn_ctx* ctx, double* f) {
+  if (!ctx || !aligned(f)) return SGN_ERR_INVALID_ARG;
+  const sgn::Geom& g = ctx->g;
+  HIPCK(sgn::launch_row_r2c(g, f, ctx->E, ctx->stream));
+  HIPCK(sgn::launch_col_filter(g, ctx->E, 1, ctx->cfg.krasny, ctx->P, ctx->stream));
+  HIPCK(sgn::launch_row_c2r(g, ctx->P, f, ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  return SGN_OK;
+}
+
+int sgn_kernel_timing(sgn_ctx* ctx, int32_t kind, int32_t enable) {
+  if (!ctx || kind < 0 || kind >= SGN_KERNEL_COUNT) return SGN_ERR_INVALID_ARG;
+  int rc = drain_timing(ctx);
+  if (rc) return rc;
+  if (enable) {
+    ctx->timed_kind = kind;
+    ctx->timed_launches = 0;
+    ctx->timed_ms = 0.0;
+  } else if (ctx->timed_kind == kind) {
+    ctx->timed_kind = -1;
+  }
+  return SGN_OK;
+}
+
+int sgn_kernel_time(sgn_ctx* ctx, int32_t kind, int64_t* launches, double* total_ms) {
+  if (!ctx || !launches || !total_ms || kind < 0 || kind >= SGN_KERNEL_COUNT) return SGN_ERR_INVALID_ARG;
+  int rc = drain_timing(ctx);
+  if (rc) return rc;
+  const bool mine = ctx->timed_kind == kind;
+  *launches = mine ? ctx->timed_launches : 0;
+  *total_ms = mine ? ctx->timed_ms : 0.0;
+  return SGN_OK;
+}
+
+const char* sgn_status_string(int status) {
+  switch (status) {
+    case SGN_OK: return "ok";
+    case SGN_ERR_INVALID_ARG: return "invalid argument";
+    case SGN_ERR_UNSUPPORTED: return "unsupported configuration";
+    case SGN_ERR_HIP: return "HIP runtime error";
+    case SGN_ERR_NOT_CONVERGED: return "GMRES did not converge";
+    case SGN_ERR_CAVITATION: return "cavitation (min h <= 0)";
+    case SGN_ERR_NONFINITE: return "non-finite value";
+    default: return "unknown status";
+  }
+}
+
+const char* sgn_last_error(const sgn_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+}  // extern "C"

@@ -1,0 +1,194 @@
+// Device-side complex arithmetic and the register/LDS FFT engine used by
+// every spectral pass of the SGN solver (gfx950, FP64).
+//
+// The engine is a Stockham autosort FFT.  An FFT of length N is computed by
+// TPF = N/E threads, each holding E complex values in registers.  The first
+// and the last stage both have radix E, so a thread holds the elements at
+// positions p = t + r*TPF (r = 0..E-1) both on entry and on exit: pointwise
+// work between a forward and an inverse transform (a spectral multiplier, a
+// division by the depth h) needs no data exchange.  Middle stages (radix
+// <= E) exchange through LDS.  Twiddles come from a host-computed FP64 table
+// tw[k] = exp(-2 pi i k / N).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace sgn {
+
+typedef double2 cplx;
+
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ cplx cmulc(cplx a, cplx b) {
+  return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ cplx cscale(cplx a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ cplx mul_i(cplx a) { return make_double2(-a.y, a.x); }   // i a
+__device__ __forceinline__ cplx mul_mi(cplx a) { return make_double2(a.y, -a.x); }  // -i a
+__device__ __forceinline__ cplx conjc(cplx a) { return make_double2(a.x, -a.y); }
+// i*k*a for a real k
+__device__ __forceinline__ cplx mul_ik(cplx a, double k) { return make_double2(-k * a.y, k * a.x); }
+
+// cos(pi m / 8) and sin(pi m / 8), m = 0..8: the twiddles of DFTs up to size 16.
+struct Tw16 {
+  static constexpr double C1 = 0.92387953251128675613;  // cos(pi/8)
+  static constexpr double S1 = 0.38268343236508977173;  // sin(pi/8)
+  static constexpr double R2 = 0.70710678118654752440;  // cos(pi/4)
+};
+
+// Multiply by W_R^k = exp(-+2 pi i k / R) (sign by INV) for compile-time R, k.
+template <int R, int K, bool INV>
+__device__ __forceinline__ cplx twc(cplx a) {
+  constexpr int m = (16 / R) * K;  // angle = pi m / 8, m in [0, 8)
+  static_assert(16 % R == 0 && m < 8, "radix up to 16");
+  if constexpr (m == 0) {
+    return a;
+  } else if constexpr (m == 4) {
+    return INV ? mul_i(a) : mul_mi(a);
+  } else {
+    constexpr double c = (m == 1) ? Tw16::C1 : (m == 2) ? Tw16::R2 : (m == 3) ? Tw16::S1
+                       : (m == 5) ? -Tw16::S1 : (m == 6) ? -Tw16::R2 : -Tw16::C1;
+    constexpr double s = (m == 1) ? Tw16::S1 : (m == 2) ? Tw16::R2 : (m == 3) ? Tw16::C1
+                       : (m == 5) ? Tw16::C1 : (m == 6) ? Tw16::R2 : Tw16::S1;
+    // forward: (c - i s); inverse: (c + i s)
+    return INV ? make_double2(a.x * c - a.y * s, a.x * s + a.y * c)
+               : make_double2(a.x * c + a.y * s, a.y * c - a.x * s);
+  }
+}
+
+template <int R, bool INV, int K = 0>
+__device__ __forceinline__ void combine_halves(cplx* e, cplx* o, cplx* v) {
+  if constexpr (K < R / 2) {
+    cplx t = twc<R, K, INV>(o[K]);
+    v[K] = cadd(e[K], t);
+    v[K + R / 2] = csub(e[K], t);
+    combine_halves<R, INV, K + 1>(e, o, v);
+  }
+}
+
+// In-register DFT of size R (1, 2, 4, 8, 16), natural order in and out.
+template <int R, bool INV>
+__device__ __forceinline__ void dft(cplx* v) {
+  if constexpr (R == 1) {
+    return;
+  } else if constexpr (R == 2) {
+    cplx a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+  } else if constexpr (R == 4) {
+    cplx s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    cplx s13 = cadd(v[1], v[3]);
+    cplx d13 = INV ? mul_i(csub(v[1], v[3])) : mul_mi(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+  } else {
+    cplx e[R / 2], o[R / 2];
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+      e[i] = v[2 * i];
+      o[i] = v[2 * i + 1];
+    }
+    dft<R / 2, INV>(e);
+    dft<R / 2, INV>(o);
+    combine_halves<R, INV>(e, o, v);
+  }
+}
+
+// Elements per thread for a transform of length N.
+template <int N>
+struct FftShape {
+  static constexpr int E = (N <= 8) ? N : (N <= 32) ? 4 : 8;
+  static constexpr int TPF = N / E;
+  static_assert(N == E || N % (E * E) == 0, "plan needs N == E or E^2 | N");
+};
+
+// LDS addressing: row transforms pad one slot every 8 complex values to
+// spread the strided first-stage writes over the banks; column transforms
+// interleave TC columns (lane-fast) and need no padding.
+template <int LS, bool PAD>
+struct LdsMap {
+  __device__ __forceinline__ static int at(int p) { return PAD ? (p + (p >> 3)) * LS : p * LS; }
+  static constexpr int size(int n) { return PAD ? (n + n / 8) * LS : n * LS; }
+};
+
+template <bool INV>
+__device__ __forceinline__ cplx twiddle(const cplx* __restrict__ tw, int idx) {
+  cplx w = tw[idx];
+  return INV ? conjc(w) : w;
+}
+
+// One middle Stockham stage of radix R (< = E) with Ns = product of earlier radices.
+template <int N, int E, int R, int Ns, bool INV, class Map>
+__device__ __forceinline__ void fft_middle_stage(cplx* buf, int t, const cplx* __restrict__ tw) {
+  constexpr int TPF = N / E;
+  constexpr int NB = E / R;  // butterflies per thread
+  cplx w[E];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int j = t + q * TPF;
+#pragma unroll
+    for (int r = 0; r < R; ++r) w[q * R + r] = buf[Map::at(j + r * (N / R))];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int j = t + q * TPF;
+    const int jm = j % Ns;
+#pragma unroll
+    for (int r = 1; r < R; ++r)
+      w[q * R + r] = cmul(w[q * R + r], twiddle<INV>(tw, jm * r * (N / (Ns * R))));
+    dft<R, INV>(&w[q * R]);
+    const int base = (j / Ns) * Ns * R + jm;
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[Map::at(base + r * Ns)] = w[q * R + r];
+  }
+  __syncthreads();
+}
+
+template <int N, int E, int Ns, bool INV, class Map>
+__device__ __forceinline__ void fft_middle_stages(cplx* buf, int t, const cplx* __restrict__ tw) {
+  constexpr int rem = N / (Ns * E);
+  if constexpr (rem > 1) {
+    constexpr int R = rem >= E ? E : rem;
+    fft_middle_stage<N, E, R, Ns, INV, Map>(buf, t, tw);
+    fft_middle_stages<N, E, Ns * R, INV, Map>(buf, t, tw);
+  }
+}
+
+// Full transform of length N on registers v[E] (positions t + r*TPF in and
+// out).  buf: this transform's LDS region (Map addressing).  Unnormalised in
+// both directions.  Ends with a barrier so buf may be reused at once.
+template <int N, bool INV, class Map>
+__device__ __forceinline__ void fft(cplx* v, cplx* buf, int t, const cplx* __restrict__ tw) {
+  constexpr int E = FftShape<N>::E;
+  constexpr int TPF = FftShape<N>::TPF;
+  dft<E, INV>(v);
+  if constexpr (N == E) return;
+  // first stage output (Ns = 1): position t*E + r
+#pragma unroll
+  for (int r = 0; r < E; ++r) buf[Map::at(t * E + r)] = v[r];
+  __syncthreads();
+  fft_middle_stages<N, E, E, INV, Map>(buf, t, tw);
+  // last stage: radix E, Ns = TPF, butterfly j = t, positions t + r*TPF
+#pragma unroll
+  for (int r = 0; r < E; ++r) v[r] = buf[Map::at(t + r * TPF)];
+  __syncthreads();
+#pragma unroll
+  for (int r = 1; r < E; ++r) v[r] = cmul(v[r], twiddle<INV>(tw, t * r));
+  dft<E, INV>(v);
+}
+
+// Signed wavenumber of DFT index p of a length-n transform on a period
+// 2 pi L (inv_L = 1/L), with the Nyquist index mapped to 0.
+__device__ __forceinline__ double wavenumber(int p, int n, double inv_L) {
+  const int h = n >> 1;
+  if (p == h) return 0.0;
+  return (double)(p < h ? p : p - n) * inv_L;
+}
+
+}  // namespace sgn

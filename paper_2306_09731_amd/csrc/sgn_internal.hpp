@@ -1,0 +1,79 @@
+// Internal definitions shared by the kernels and the host runtime of libsgn.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace sgn {
+
+constexpr int kMaxRestart = 64;     // largest GMRES restart length m
+constexpr int kPartialStride = 80;  // doubles per block in the reduction scratch
+constexpr int kMaxPartialBlocks = 4096;
+
+// Grid geometry and spectral constants, passed by value to every kernel.
+struct Geom {
+  int nx, ny, nh;          // nh = nx / 2 complex columns of a half spectrum
+  double inv_Lx, inv_Ly;   // wavenumber k = m / L
+  double inv_nx, inv_ny, inv_n;
+  double g, h_inf;
+  double m0, m1;           // preconditioner symbol M = m0 + m1 (kx^2 + ky^2)
+  double dA;               // cell area dx * dy
+  const double2* twx;      // exp(-2 pi i k / nx), k < nx
+  const double2* twy;      // exp(-2 pi i k / ny), k < ny
+};
+
+// GMRES state kept in device memory.  Written only by the single "last
+// block" of the reduction kernels; read by the following kernels and,
+// through GmresStatus, by the host.
+struct GmresStatus {
+  int32_t done;         // 0 running, 1 converged, 2 cycle full (restart), 3 stopped
+  int32_t jdone;        // Arnoldi steps completed in the current cycle
+  int32_t total_iters;  // Arnoldi steps over the whole solve
+  int32_t zero;         // b == 0: the solution is exactly 0
+  double resid;         // current |g_{j+1}| (preconditioned residual estimate)
+  double beta0;         // ||M^-1 b||
+  double bnorm;         // ||b||
+  double true_resid2;   // ||b - L x||^2 when requested
+  double red[8];        // invariants: mass, Px, Py, energy, |curl v|, min h, max h, tail
+  double stat_minh;     // min h of the last field check
+  int32_t stat_nonfinite;
+  int32_t pad;
+};
+
+struct GmresState {
+  GmresStatus st;
+  double tol;
+  int32_t m;            // restart length
+  int32_t pad0;
+  double beta;          // norm of the newest (not yet normalised) Krylov vector
+  double H[(kMaxRestart + 1) * kMaxRestart];  // H[i + j*(m_max+1)]
+  double cs[kMaxRestart], sn[kMaxRestart];
+  double gv[kMaxRestart + 1];
+  double y[kMaxRestart];
+  double s[kMaxRestart + 1];   // first projection coefficients
+  double s2[kMaxRestart + 1];  // second projection coefficients
+  uint32_t counter;            // last-block ticket counter (reset by the last block)
+  uint32_t pad1[63];
+};
+
+__host__ __device__ inline int hidx(int i, int j) { return i + j * (kMaxRestart + 1); }
+
+// One RK4 stage combine, fused into the flux passes.
+//   mode 0: write k (the right-hand side) to `out`
+//   mode 1: acc = (first ? 0 : acc) + wacc k; out = yn + cnext k
+//   mode 2 (last stage): yn = yn + dt (acc + wacc k)
+struct RkStage {
+  int mode;
+  int first;
+  double wacc;
+  double cnext;
+  double dt;
+};
+
+struct RkField {
+  const double* yn;   // state at the start of the step
+  double* acc;        // accumulator of weighted stage derivatives
+  double* out;        // next stage input (mode 1), k (mode 0) or yn itself (mode 2)
+};
+
+}  // namespace sgn

@@ -1,0 +1,264 @@
+"""ctypes binding of libsgn (include/sgn.h).
+
+Argument marshalling only: every step of the solver runs in the HIP
+library.  PyTorch supplies device memory (the fields and the workspace) and
+the stream.  The library must have been built (python -m
+paper_2306_09731_amd.build); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsgn.so")
+
+SGN_OK = 0
+SGN_ERR_INVALID_ARG = 1
+SGN_ERR_UNSUPPORTED = 2
+SGN_ERR_HIP = 3
+SGN_ERR_NOT_CONVERGED = 4
+SGN_ERR_CAVITATION = 5
+SGN_ERR_NONFINITE = 6
+SGN_FP64 = 0
+SGN_KERNEL_ROW_MATVEC = 0
+SGN_KERNEL_COL_BASIS = 1
+SGN_KERNEL_COL_PRECOND_DOT = 2
+SGN_KERNEL_GS_UPDATE = 3
+SGN_KERNEL_ROW_FLUX = 4
+SGN_KERNEL_COL_FLUX = 5
+KERNEL_NAMES = {0: "row_matvec", 1: "col_basis", 2: "col_precond_dot", 3: "gs_update", 4: "row_flux",
+                5: "col_flux"}
+
+
+class sgn_config(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("Lx", ctypes.c_double), ("Ly", ctypes.c_double),
+        ("g", ctypes.c_double), ("h_inf", ctypes.c_double),
+        ("precision", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
+        ("gmres_tol", ctypes.c_double),
+        ("gmres_max_iters", ctypes.c_int32), ("batch", ctypes.c_int32),
+        ("krasny", ctypes.c_double),
+        ("invariants_tol", ctypes.c_double),
+    ]
+
+
+class sgn_solve_info(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
+        ("converged", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("rel_resid_precond", ctypes.c_double), ("rel_resid_true", ctypes.c_double),
+    ]
+
+
+class sgn_step_info(ctypes.Structure):
+    _fields_ = [
+        ("total_iters", ctypes.c_int64), ("max_iters_per_solve", ctypes.c_int32),
+        ("solves", ctypes.c_int32), ("min_h", ctypes.c_double),
+        ("any_unconverged", ctypes.c_int32), ("pad", ctypes.c_int32),
+    ]
+
+
+class sgn_invariants_out(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double), ("px", ctypes.c_double), ("py", ctypes.c_double),
+        ("energy", ctypes.c_double), ("min_h", ctypes.c_double), ("max_h", ctypes.c_double),
+        ("curl_l2", ctypes.c_double), ("spectral_tail", ctypes.c_double),
+    ]
+
+
+_VP = ctypes.c_void_p
+_SIGNATURES = {
+    "sgn_config_default": (None, [ctypes.POINTER(sgn_config), ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_double, ctypes.c_double]),
+    "sgn_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(sgn_config)]),
+    "sgn_init": (ctypes.c_int, [ctypes.POINTER(sgn_config), _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    "sgn_destroy": (ctypes.c_int, [_VP]),
+    "sgn_elliptic_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(sgn_solve_info)]),
+    "sgn_rhs": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(sgn_solve_info)]),
+    "sgn_rk4_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
+                                    ctypes.POINTER(sgn_step_info)]),
+    "sgn_invariants": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(sgn_invariants_out)]),
+    "sgn_derivative": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP]),
+    "sgn_apply_operator": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int32]),
+    "sgn_apply_precond": (ctypes.c_int, [_VP, _VP, _VP]),
+    "sgn_krasny_filter": (ctypes.c_int, [_VP, _VP]),
+    "sgn_kernel_timing": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
+    "sgn_kernel_time": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_double)]),
+    "sgn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "sgn_last_error": (ctypes.c_char_p, [_VP]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libsgn.so and declare its signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build the HIP library first "
+                           "(python -m paper_2306_09731_amd.build)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class SgnError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+def config_default(nx: int, ny: int, Lx: float, Ly: float, **overrides) -> sgn_config:
+    lib = load_library()
+    cfg = sgn_config()
+    lib.sgn_config_default(ctypes.byref(cfg), nx, ny, Lx, Ly)
+    for k, v in overrides.items():
+        if not hasattr(cfg, k):
+            raise KeyError(k)
+        setattr(cfg, k, v)
+    return cfg
+
+
+def sgn_workspace_bytes(cfg: sgn_config) -> int:
+    return int(load_library().sgn_workspace_bytes(ctypes.byref(cfg)))
+
+
+@dataclasses.dataclass
+class Context:
+    handle: ctypes.c_void_p
+    cfg: sgn_config
+    workspace: object  # torch.Tensor (uint8, device)
+    device: object
+
+    def last_error(self) -> str:
+        msg = load_library().sgn_last_error(self.handle)
+        return msg.decode() if msg else ""
+
+    def close(self):
+        if self.handle:
+            load_library().sgn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check(ctx: Context | None, status: int, allow=(SGN_OK,)):
+    if status in allow:
+        return status
+    lib = load_library()
+    msg = lib.sgn_status_string(status).decode()
+    if ctx is not None:
+        extra = ctx.last_error()
+        if extra:
+            msg = f"{msg}: {extra}"
+    raise SgnError(status, msg)
+
+
+def _field(ctx: Context, t, name: str):
+    import torch
+    cfg = ctx.cfg
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.device != ctx.device \
+            or tuple(t.shape) != (cfg.ny, cfg.nx):
+        raise ValueError(f"{name} must be a contiguous float64 tensor of shape ({cfg.ny}, {cfg.nx}) "
+                         f"on {ctx.device}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def sgn_init(cfg: sgn_config, device="cuda:0", stream=None) -> Context:
+    """Allocate the workspace as a torch tensor and initialise a context on the
+    given (or current) torch stream."""
+    import torch
+    lib = load_library()
+    device = torch.device(device)
+    nbytes = sgn_workspace_bytes(cfg)
+    if nbytes == 0:
+        raise SgnError(SGN_ERR_INVALID_ARG, "invalid configuration")
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    ws_view = ws[off:off + nbytes]
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    handle = ctypes.c_void_p()
+    st = lib.sgn_init(ctypes.byref(cfg), ctypes.c_void_p(ws_view.data_ptr()), nbytes,
+                      ctypes.c_void_p(stream.cuda_stream), ctypes.byref(handle))
+    _check(None, st)
+    return Context(handle=handle, cfg=cfg, workspace=ws, device=device)
+
+
+def sgn_elliptic_solve(ctx: Context, h, b, sigma) -> sgn_solve_info:
+    info = sgn_solve_info()
+    st = load_library().sgn_elliptic_solve(ctx.handle, _field(ctx, h, "h"), _field(ctx, b, "b"),
+                                           _field(ctx, sigma, "sigma"), ctypes.byref(info))
+    _check(ctx, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
+    return info
+
+
+def sgn_rhs(ctx: Context, h, vx, vy, sigma, dh, dvx, dvy) -> sgn_solve_info:
+    info = sgn_solve_info()
+    st = load_library().sgn_rhs(ctx.handle, _field(ctx, h, "h"), _field(ctx, vx, "vx"), _field(ctx, vy, "vy"),
+                                _field(ctx, sigma, "sigma"), _field(ctx, dh, "dh"), _field(ctx, dvx, "dvx"),
+                                _field(ctx, dvy, "dvy"), ctypes.byref(info))
+    _check(ctx, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
+    return info
+
+
+def sgn_rk4_step(ctx: Context, h, vx, vy, sigma, dt: float, nsteps: int = 1) -> sgn_step_info:
+    info = sgn_step_info()
+    st = load_library().sgn_rk4_step(ctx.handle, _field(ctx, h, "h"), _field(ctx, vx, "vx"),
+                                     _field(ctx, vy, "vy"), _field(ctx, sigma, "sigma"), float(dt),
+                                     int(nsteps), ctypes.byref(info))
+    _check(ctx, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
+    return info
+
+
+def sgn_invariants(ctx: Context, h, vx, vy, sigma) -> dict:
+    out = sgn_invariants_out()
+    st = load_library().sgn_invariants(ctx.handle, _field(ctx, h, "h"), _field(ctx, vx, "vx"),
+                                       _field(ctx, vy, "vy"), _field(ctx, sigma, "sigma"), ctypes.byref(out))
+    _check(ctx, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
+    return {name: getattr(out, name) for name, _ in sgn_invariants_out._fields_}
+
+
+def sgn_derivative(ctx: Context, axis: int, f, out):
+    _check(ctx, load_library().sgn_derivative(ctx.handle, int(axis), _field(ctx, f, "f"), _field(ctx, out, "out")))
+
+
+def sgn_apply_operator(ctx: Context, h, s, out, precondition: bool = False):
+    _check(ctx, load_library().sgn_apply_operator(ctx.handle, _field(ctx, h, "h"), _field(ctx, s, "s"),
+                                                  _field(ctx, out, "out"), 1 if precondition else 0))
+
+
+def sgn_apply_precond(ctx: Context, r, out):
+    _check(ctx, load_library().sgn_apply_precond(ctx.handle, _field(ctx, r, "r"), _field(ctx, out, "out")))
+
+
+def sgn_krasny_filter(ctx: Context, f):
+    _check(ctx, load_library().sgn_krasny_filter(ctx.handle, _field(ctx, f, "f")))
+
+
+def sgn_kernel_timing(ctx: Context, kind: int, enable: bool):
+    _check(ctx, load_library().sgn_kernel_timing(ctx.handle, int(kind), 1 if enable else 0))
+
+
+def sgn_kernel_time(ctx: Context, kind: int):
+    """(launches, total_ms) of the timed kernel class since timing was enabled."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(ctx, load_library().sgn_kernel_time(ctx.handle, int(kind), ctypes.byref(n), ctypes.byref(ms)))
+    return int(n.value), float(ms.value)

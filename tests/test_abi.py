@@ -1,0 +1,102 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every symbol include/sgn.h declares, and rejects bad arguments on the host
+before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2306_09731_amd import sgn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sgn.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sgn_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = sgn.load_library()
+    names = declared_functions()
+    assert "sgn_init" in names and "sgn_rk4_step" in names and len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) <= set(sgn._SIGNATURES), set(names) - set(sgn._SIGNATURES)
+
+
+def test_status_strings():
+    lib = sgn.load_library()
+    assert lib.sgn_status_string(0) == b"ok"
+    assert b"converge" in lib.sgn_status_string(sgn.SGN_ERR_NOT_CONVERGED)
+    assert lib.sgn_status_string(99) == b"unknown status"
+
+
+def test_config_default_and_struct_layout():
+    cfg = sgn.config_default(128, 64, 10.0, 5.0)
+    assert (cfg.nx, cfg.ny, cfg.Lx, cfg.Ly) == (128, 64, 10.0, 5.0)
+    assert cfg.g == 1.0 and cfg.h_inf == 1.0 and cfg.gmres_restart == 20
+    assert cfg.gmres_tol == 1e-10 and cfg.gmres_max_iters == 200 and cfg.batch == 1
+    assert ctypes.sizeof(sgn.sgn_config) == 80
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 100), ("ny", 4), ("nx", 8192), ("gmres_restart", 65), ("precision", 1), ("batch", 2),
+])
+def test_workspace_bytes_rejects_unsupported(field, value):
+    cfg = sgn.config_default(128, 64, 10.0, 5.0)
+    setattr(cfg, field, value)
+    assert sgn.sgn_workspace_bytes(cfg) == 0
+    lib = sgn.load_library()
+    h = ctypes.c_void_p()
+    assert lib.sgn_init(ctypes.byref(cfg), ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(h)) \
+        == sgn.SGN_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("field,value", [
+    ("Lx", 0.0), ("Ly", -1.0), ("gmres_tol", 0.0), ("gmres_max_iters", 0), ("h_inf", 0.0),
+    ("krasny", -1.0), ("gmres_restart", 0), ("Lx", float("nan")),
+])
+def test_invalid_config(field, value):
+    cfg = sgn.config_default(128, 64, 10.0, 5.0)
+    setattr(cfg, field, value)
+    assert sgn.sgn_workspace_bytes(cfg) == 0
+    lib = sgn.load_library()
+    h = ctypes.c_void_p()
+    assert lib.sgn_init(ctypes.byref(cfg), ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(h)) \
+        == sgn.SGN_ERR_INVALID_ARG
+
+
+def test_workspace_size_scales_with_grid_and_restart():
+    a = sgn.sgn_workspace_bytes(sgn.config_default(128, 64, 10.0, 5.0))
+    b = sgn.sgn_workspace_bytes(sgn.config_default(256, 64, 10.0, 5.0))
+    c = sgn.sgn_workspace_bytes(sgn.config_default(128, 64, 10.0, 5.0, gmres_restart=40))
+    field = 128 * 64 * 8
+    assert a >= 36 * field and b > a and c - a == 20 * field
+
+
+def test_init_rejects_bad_workspace_without_gpu():
+    lib = sgn.load_library()
+    cfg = sgn.config_default(128, 64, 10.0, 5.0)
+    need = sgn.sgn_workspace_bytes(cfg)
+    h = ctypes.c_void_p()
+    # null, misaligned, too small: all rejected on the host
+    assert lib.sgn_init(ctypes.byref(cfg), None, need, None, ctypes.byref(h)) == sgn.SGN_ERR_INVALID_ARG
+    assert lib.sgn_init(ctypes.byref(cfg), ctypes.c_void_p(4096 + 8), need, None, ctypes.byref(h)) \
+        == sgn.SGN_ERR_INVALID_ARG
+    assert lib.sgn_init(ctypes.byref(cfg), ctypes.c_void_p(4096), need - 1, None, ctypes.byref(h)) \
+        == sgn.SGN_ERR_INVALID_ARG
+    assert lib.sgn_init(None, ctypes.c_void_p(4096), need, None, ctypes.byref(h)) == sgn.SGN_ERR_INVALID_ARG
+
+
+def test_calls_reject_null_context():
+    lib = sgn.load_library()
+    assert lib.sgn_rk4_step(None, None, None, None, None, 0.01, 1, None) == sgn.SGN_ERR_INVALID_ARG
+    assert lib.sgn_rhs(None, None, None, None, None, None, None, None, None) == sgn.SGN_ERR_INVALID_ARG
+    assert lib.sgn_elliptic_solve(None, None, None, None, None) == sgn.SGN_ERR_INVALID_ARG
+    assert lib.sgn_invariants(None, None, None, None, None, None) == sgn.SGN_ERR_INVALID_ARG
+    assert lib.sgn_destroy(None) == sgn.SGN_ERR_INVALID_ARG
+    assert lib.sgn_last_error(None) == b""
