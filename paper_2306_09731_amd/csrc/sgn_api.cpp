@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -27,6 +28,7 @@ struct sgn_ctx {
   double *hs, *vxs, *vys, *acc_h, *acc_vx, *acc_vy;
   sgn::GmresStatus* hstat;  // pinned host copy of the device status
   int last_iters;
+  bool chained;  // chain-parallel Arnoldi kernels (default where the grid allows)
   std::string err;
   // kernel timing (measurement support)
   int timed_kind = -1;
@@ -222,20 +224,28 @@ int run_solve(sgn_ctx* ctx, int mode, const double* h, const double* vx, const d
       int nrun = batch;
       if (nrun > m - j) nrun = m - j;
       if (nrun > maxit - total - j) nrun = maxit - total - j;
+      if (nrun <= 0) break;  // the device sets done at the cycle or iteration cap
       for (int it = j; it < j + nrun; ++it) {
-        TIMED(SGN_KERNEL_COL_BASIS,
-              sgn::launch_col_basis_eg(g, ctx->W, ctx->V, ctx->vstride, it, ctx->st, ctx->E, ctx->G, s));
-        TIMED(SGN_KERNEL_ROW_MATVEC, sgn::launch_row_op(g, 0, ctx->E, ctx->G, h, nullptr, nullptr, ctx->P, ctx->Q,
-                                                        nullptr, nullptr, 0, 1, ctx->st, s));
-        TIMED(SGN_KERNEL_COL_PRECOND_DOT, sgn::launch_col_precond_dot(g, ctx->P, ctx->Q, ctx->V, ctx->vstride, it,
-                                                                      ctx->st, ctx->W, ctx->partials, s));
+        if (ctx->chained) {
+          TIMED(SGN_KERNEL_COL_BASIS,
+                sgn::launch_col_basis2(g, ctx->W, ctx->V, ctx->vstride, it, ctx->st, ctx->E, ctx->G, s));
+          TIMED(SGN_KERNEL_ROW_MATVEC, sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, s));
+          TIMED(SGN_KERNEL_COL_PRECOND_DOT, sgn::launch_col_precond_dot2(g, ctx->P, ctx->Q, ctx->V, ctx->vstride,
+                                                                         it, ctx->st, ctx->W, ctx->partials, s));
+        } else {
+          TIMED(SGN_KERNEL_COL_BASIS,
+                sgn::launch_col_basis_eg(g, ctx->W, ctx->V, ctx->vstride, it, ctx->st, ctx->E, ctx->G, s));
+          TIMED(SGN_KERNEL_ROW_MATVEC, sgn::launch_row_op(g, 0, ctx->E, ctx->G, h, nullptr, nullptr, ctx->P,
+                                                          ctx->Q, nullptr, nullptr, 0, 1, ctx->st, s));
+          TIMED(SGN_KERNEL_COL_PRECOND_DOT, sgn::launch_col_precond_dot(g, ctx->P, ctx->Q, ctx->V, ctx->vstride, it,
+                                                                        ctx->st, ctx->W, ctx->partials, s));
+        }
         TIMED(SGN_KERNEL_GS_UPDATE, sgn::launch_upd(g, ctx->W, ctx->V, ctx->vstride, it, ctx->st, ctx->partials, s));
       }
       j += nrun;
       int rc = read_status(ctx);
       if (rc) return rc;
       if (ctx->hstat->done) break;
-      if (j >= m || total + j >= maxit) break;
       batch = 2;
     }
     const sgn::GmresStatus& st = *ctx->hstat;
@@ -295,6 +305,10 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   ctx->ws = static_cast<char*>(ws);
   ctx->ws_bytes = ws_bytes;
   ctx->last_iters = cfg->gmres_restart / 2;
+  // SGN_ARNOLDI_KERNELS=serial selects the one-chain Arnoldi kernels (a
+  // tuning and testing switch; both variants compute the same quantities)
+  const char* ak = std::getenv("SGN_ARNOLDI_KERNELS");
+  ctx->chained = !(ak && std::strcmp(ak, "serial") == 0);
   const int nx = cfg->nx, ny = cfg->ny;
   sgn::Geom& g = ctx->g;
   g.nx = nx;
@@ -310,6 +324,7 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   g.m0 = 3.0 / (cfg->h_inf * cfg->h_inf * cfg->h_inf);
   g.m1 = 1.0 / cfg->h_inf;
   g.dA = (2.0 * M_PI * cfg->Lx / nx) * (2.0 * M_PI * cfg->Ly / ny);
+  ctx->chained = ctx->chained && sgn::chained_ok(g);
   char* base = ctx->ws;
   cplx* tw = reinterpret_cast<cplx*>(base + L.tw);
   g.twx = tw;
@@ -355,6 +370,7 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   std::memset(&hst, 0, sizeof hst);
   hst.tol = cfg->gmres_tol;
   hst.m = cfg->gmres_restart;
+  hst.maxit = cfg->gmres_max_iters;
   hipError_t e = hipMemcpyAsync(tw, htw.data(), htw.size() * sizeof(cplx), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ctx->st, &hst, sizeof hst, hipMemcpyHostToDevice, ctx->stream);

@@ -102,29 +102,84 @@ __device__ __forceinline__ void dft(cplx* v) {
 // Elements per thread for a transform of length N.
 template <int N>
 struct FftShape {
-  static constexpr int E = (N <= 8) ? N : (N <= 32) ? 4 : 8;
+  static constexpr int E = (N <= 8) ? N : (N >= 4096) ? 8 : 4;
   static constexpr int TPF = N / E;
   static_assert(N == E || N % (E * E) == 0, "plan needs N == E or E^2 | N");
 };
 
-// LDS addressing: row transforms pad one slot every 8 complex values to
-// spread the strided first-stage writes over the banks; column transforms
-// interleave TC columns (lane-fast) and need no padding.
-template <int LS, bool PAD>
-struct LdsMap {
-  __device__ __forceinline__ static int at(int p) { return PAD ? (p + (p >> 3)) * LS : p * LS; }
-  static constexpr int size(int n) { return PAD ? (n + n / 8) * LS : n * LS; }
+// LDS addressing.  Row transforms pad one slot every 8 complex values to
+// spread strided writes over the banks; column transforms interleave the
+// tc columns of a block (lane-fast) with a runtime stride.
+struct RowMap {
+  __device__ __forceinline__ int at(int p) const { return p + (p >> 3); }
+  static constexpr int size(int n) { return n + n / 8; }
+};
+struct ColMap {
+  int tc;
+  __device__ __forceinline__ int at(int p) const { return p * tc; }
 };
 
-template <bool INV>
-__device__ __forceinline__ cplx twiddle(const cplx* __restrict__ tw, int idx) {
-  cplx w = tw[idx];
-  return INV ? conjc(w) : w;
+// Twiddles used by one thread, gathered once per kernel into registers (they
+// are the same for every transform of that length the thread performs; the
+// inverse uses their conjugates).  Layout: the middle stages in order, each
+// with (E/R) butterflies x (R-1) twiddles, then the last stage's E-1.
+template <int N, int E, int Ns>
+constexpr int mid_twiddles() {
+  constexpr int rem = N / (Ns * E);
+  if constexpr (rem > 1) {
+    constexpr int R = rem >= E ? E : rem;
+    return (E / R) * (R - 1) + mid_twiddles<N, E, Ns * R>();
+  } else {
+    return 0;
+  }
 }
 
-// One middle Stockham stage of radix R (< = E) with Ns = product of earlier radices.
-template <int N, int E, int R, int Ns, bool INV, class Map>
-__device__ __forceinline__ void fft_middle_stage(cplx* buf, int t, const cplx* __restrict__ tw) {
+template <int N>
+struct TwiddleSet {
+  static constexpr int E = FftShape<N>::E;
+  static constexpr int MID = (N == E) ? 0 : mid_twiddles<N, E, E>();
+  static constexpr int COUNT = (N == E) ? 1 : MID + (E - 1);
+  cplx w[COUNT];
+};
+
+template <int N, int E, int Ns, int OFF>
+__device__ __forceinline__ void gather_mid_twiddles(cplx* w, int t, const cplx* __restrict__ tw) {
+  constexpr int rem = N / (Ns * E);
+  if constexpr (rem > 1) {
+    constexpr int R = rem >= E ? E : rem;
+    constexpr int TPF = N / E;
+#pragma unroll
+    for (int q = 0; q < E / R; ++q) {
+      const int jm = (t + q * TPF) % Ns;
+#pragma unroll
+      for (int r = 1; r < R; ++r) w[OFF + q * (R - 1) + (r - 1)] = tw[jm * r * (N / (Ns * R))];
+    }
+    gather_mid_twiddles<N, E, Ns * R, OFF + (E / R) * (R - 1)>(w, t, tw);
+  }
+}
+
+// tw: the length-N table exp(-2 pi i k / N); t: the thread's index in its transform.
+template <int N>
+__device__ __forceinline__ void gather_twiddles(TwiddleSet<N>& ts, int t, const cplx* __restrict__ tw) {
+  constexpr int E = FftShape<N>::E;
+  if constexpr (N == E) {
+    ts.w[0] = make_double2(1.0, 0.0);
+  } else {
+    gather_mid_twiddles<N, E, E, 0>(ts.w, t, tw);
+#pragma unroll
+    for (int r = 1; r < E; ++r) ts.w[TwiddleSet<N>::MID + r - 1] = tw[t * r];
+  }
+}
+
+template <bool INV>
+__device__ __forceinline__ cplx twmul(cplx a, cplx w) {
+  return INV ? cmulc(a, w) : cmul(a, w);
+}
+
+// One middle Stockham stage of radix R (<= E); Ns = product of earlier
+// radices; OFF = offset of this stage's twiddles in the thread's set.
+template <int N, int E, int R, int Ns, int OFF, bool INV, class Map>
+__device__ __forceinline__ void fft_middle_stage(cplx* buf, int t, const cplx* w_tw, const Map& map) {
   constexpr int TPF = N / E;
   constexpr int NB = E / R;  // butterflies per thread
   cplx w[E];
@@ -132,7 +187,7 @@ __device__ __forceinline__ void fft_middle_stage(cplx* buf, int t, const cplx* _
   for (int q = 0; q < NB; ++q) {
     const int j = t + q * TPF;
 #pragma unroll
-    for (int r = 0; r < R; ++r) w[q * R + r] = buf[Map::at(j + r * (N / R))];
+    for (int r = 0; r < R; ++r) w[q * R + r] = buf[map.at(j + r * (N / R))];
   }
   __syncthreads();
 #pragma unroll
@@ -140,46 +195,46 @@ __device__ __forceinline__ void fft_middle_stage(cplx* buf, int t, const cplx* _
     const int j = t + q * TPF;
     const int jm = j % Ns;
 #pragma unroll
-    for (int r = 1; r < R; ++r)
-      w[q * R + r] = cmul(w[q * R + r], twiddle<INV>(tw, jm * r * (N / (Ns * R))));
+    for (int r = 1; r < R; ++r) w[q * R + r] = twmul<INV>(w[q * R + r], w_tw[OFF + q * (R - 1) + (r - 1)]);
     dft<R, INV>(&w[q * R]);
     const int base = (j / Ns) * Ns * R + jm;
 #pragma unroll
-    for (int r = 0; r < R; ++r) buf[Map::at(base + r * Ns)] = w[q * R + r];
+    for (int r = 0; r < R; ++r) buf[map.at(base + r * Ns)] = w[q * R + r];
   }
   __syncthreads();
 }
 
-template <int N, int E, int Ns, bool INV, class Map>
-__device__ __forceinline__ void fft_middle_stages(cplx* buf, int t, const cplx* __restrict__ tw) {
+template <int N, int E, int Ns, int OFF, bool INV, class Map>
+__device__ __forceinline__ void fft_middle_stages(cplx* buf, int t, const cplx* w_tw, const Map& map) {
   constexpr int rem = N / (Ns * E);
   if constexpr (rem > 1) {
     constexpr int R = rem >= E ? E : rem;
-    fft_middle_stage<N, E, R, Ns, INV, Map>(buf, t, tw);
-    fft_middle_stages<N, E, Ns * R, INV, Map>(buf, t, tw);
+    fft_middle_stage<N, E, R, Ns, OFF, INV, Map>(buf, t, w_tw, map);
+    fft_middle_stages<N, E, Ns * R, OFF + (E / R) * (R - 1), INV, Map>(buf, t, w_tw, map);
   }
 }
 
 // Full transform of length N on registers v[E] (positions t + r*TPF in and
-// out).  buf: this transform's LDS region (Map addressing).  Unnormalised in
-// both directions.  Ends with a barrier so buf may be reused at once.
+// out).  buf: this transform's LDS region (map addressing); ts: the thread's
+// twiddles.  Unnormalised in both directions.  Ends with a barrier so buf
+// may be reused at once.
 template <int N, bool INV, class Map>
-__device__ __forceinline__ void fft(cplx* v, cplx* buf, int t, const cplx* __restrict__ tw) {
+__device__ __forceinline__ void fft(cplx* v, cplx* buf, int t, const TwiddleSet<N>& ts, const Map& map) {
   constexpr int E = FftShape<N>::E;
   constexpr int TPF = FftShape<N>::TPF;
   dft<E, INV>(v);
   if constexpr (N == E) return;
   // first stage output (Ns = 1): position t*E + r
 #pragma unroll
-  for (int r = 0; r < E; ++r) buf[Map::at(t * E + r)] = v[r];
+  for (int r = 0; r < E; ++r) buf[map.at(t * E + r)] = v[r];
   __syncthreads();
-  fft_middle_stages<N, E, E, INV, Map>(buf, t, tw);
+  fft_middle_stages<N, E, E, 0, INV, Map>(buf, t, ts.w, map);
   // last stage: radix E, Ns = TPF, butterfly j = t, positions t + r*TPF
 #pragma unroll
-  for (int r = 0; r < E; ++r) v[r] = buf[Map::at(t + r * TPF)];
+  for (int r = 0; r < E; ++r) v[r] = buf[map.at(t + r * TPF)];
   __syncthreads();
 #pragma unroll
-  for (int r = 1; r < E; ++r) v[r] = cmul(v[r], twiddle<INV>(tw, t * r));
+  for (int r = 1; r < E; ++r) v[r] = twmul<INV>(v[r], ts.w[TwiddleSet<N>::MID + r - 1]);
   dft<E, INV>(v);
 }
 

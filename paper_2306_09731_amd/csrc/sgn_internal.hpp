@@ -26,7 +26,7 @@ struct Geom {
 // block" of the reduction kernels; read by the following kernels and,
 // through GmresStatus, by the host.
 struct GmresStatus {
-  int32_t done;         // 0 running, 1 converged, 2 cycle full (restart), 3 stopped
+  int32_t done;         // 0 running, 1 converged, 2 cycle full (restart), 3 iteration cap
   int32_t jdone;        // Arnoldi steps completed in the current cycle
   int32_t total_iters;  // Arnoldi steps over the whole solve
   int32_t zero;         // b == 0: the solution is exactly 0
@@ -44,7 +44,7 @@ struct GmresState {
   GmresStatus st;
   double tol;
   int32_t m;            // restart length
-  int32_t pad0;
+  int32_t maxit;        // total Arnoldi steps allowed per solve
   double beta;          // norm of the newest (not yet normalised) Krylov vector
   double H[(kMaxRestart + 1) * kMaxRestart];  // H[i + j*(m_max+1)]
   double cs[kMaxRestart], sn[kMaxRestart];
@@ -52,9 +52,12 @@ struct GmresState {
   double y[kMaxRestart];
   double s[kMaxRestart + 1];   // first projection coefficients
   double s2[kMaxRestart + 1];  // second projection coefficients
-  uint32_t counter;            // last-block ticket counter (reset by the last block)
-  uint32_t pad1[63];
+  // last-block ticket counters: [0] over groups, [32 (1 + g)] within group g
+  // of kTicketGroup blocks (one 128-byte line each); reset by their last user
+  uint32_t ctr[32 * (1 + kMaxPartialBlocks / 16)];
 };
+
+constexpr int kTicketGroup = 16;
 
 __host__ __device__ inline int hidx(int i, int j) { return i + j * (kMaxRestart + 1); }
 

@@ -9,8 +9,9 @@
 //                       kx = nx/2, which every operator here treats alike
 //                       because the Nyquist wavenumber is set to zero.
 // Row passes transform two adjacent real rows as one complex row; column
-// passes transform TC adjacent complex columns per block (coalesced loads of
-// TC*16 bytes per row), two real columns per complex column for physical data.
+// passes transform tc adjacent complex columns per block (loads of tc*16
+// contiguous bytes per row), two real columns per complex column for physical
+// data.
 #include "sgn_fft.hpp"
 #include "sgn_internal.hpp"
 #include "sgn_launch.hpp"
@@ -41,21 +42,51 @@ __constant__ int kKindsInvariants[7] = {0, 0, 0, 0, 0, 1, 2};
 __constant__ int kKindsMax[1] = {2};
 __constant__ int kKindsStats[2] = {1, 2};
 
-__device__ __forceinline__ int flat_tid() { return threadIdx.x + threadIdx.y * blockDim.x; }
-__device__ __forceinline__ int block_threads() { return blockDim.x * blockDim.y; }
+__device__ __forceinline__ int flat_tid() { return threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z); }
+__device__ __forceinline__ int block_threads() { return blockDim.x * blockDim.y * blockDim.z; }
 
-// Every block calls this once after writing its partials.  Returns true in
-// exactly one block (the last to arrive), after an acquire fence.
-__device__ bool last_block_arrive(uint32_t* counter, int nblocks) {
+// Partials travel through device-scope atomic stores and loads, which are
+// performed at the device coherence point (not in an XCD-private L2), so the
+// last-block protocol needs no cache-wide write-back or invalidate.
+__device__ __forceinline__ void partial_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double partial_load(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t ticket(uint32_t* c) {
+  return __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void reset_counter(uint32_t* c) {
+  __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Every block calls this once after writing its partials with partial_store.
+// Returns true in exactly one block (the last to arrive).  Each thread first
+// waits for its own partial stores to complete.  Tickets are taken in two
+// levels (groups of kTicketGroup blocks, then groups) so that no counter sees
+// more than max(kTicketGroup, #groups) same-address atomics.
+__device__ bool last_block_arrive(uint32_t* ctr, int nblocks) {
   __shared__ int s_last;
-  __threadfence();
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (flat_tid() == 0) {
-    const uint32_t prev = atomicAdd(counter, 1u);
-    s_last = (prev == (uint32_t)(nblocks - 1)) ? 1 : 0;
+    const int grp = blockIdx.x / kTicketGroup;
+    const int ngroups = (nblocks + kTicketGroup - 1) / kTicketGroup;
+    const int gsize = min(kTicketGroup, nblocks - grp * kTicketGroup);
+    uint32_t* gc = ctr + 32 * (1 + grp);
+    int last = 0;
+    if (ticket(gc) == (uint32_t)(gsize - 1)) {
+      reset_counter(gc);
+      if (ticket(ctr) == (uint32_t)(ngroups - 1)) {
+        reset_counter(ctr);
+        last = 1;
+      }
+    }
+    s_last = last;
   }
   __syncthreads();
-  if (s_last) __threadfence();
   return s_last != 0;
 }
 
@@ -67,10 +98,17 @@ __device__ void reduce_partials(const double* partials, int nblocks, int nvals, 
   const int lane = tid & 63, wave = tid >> 6, nw = block_threads() >> 6;
   for (int k = wave; k < nvals; k += nw) {
     const int kd = kind ? kind[k] : 0;
-    double s = kd == 0 ? 0.0 : (kd == 1 ? 1e300 : -1e300);
-    for (int b = lane; b < nblocks; b += 64) {
-      const double x = partials[(size_t)b * kPartialStride + k];
-      s = kd == 0 ? s + x : (kd == 1 ? fmin(s, x) : fmax(s, x));
+    const double id = kd == 0 ? 0.0 : (kd == 1 ? 1e300 : -1e300);
+    double s = id;
+    for (int b0 = 0; b0 < nblocks; b0 += 64 * 8) {
+      double x[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int b = b0 + lane + 64 * q;
+        x[q] = b < nblocks ? partial_load(&partials[(size_t)b * kPartialStride + k]) : id;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s = kd == 0 ? s + x[q] : (kd == 1 ? fmin(s, x[q]) : fmax(s, x[q]));
     }
     s = kd == 0 ? wave_sum(s) : (kd == 1 ? wave_min(s) : wave_max(s));
     if (lane == 0) out[k] = s;
@@ -85,6 +123,23 @@ __device__ __forceinline__ void wave_partial(double x, double* red, int k) {
   if ((tid & 63) == 0) red[k * (block_threads() >> 6) + (tid >> 6)] = s;
 }
 
+// Eight values at once (their shuffle chains overlap): a[q] is the thread's
+// contribution to value k0 + q; wave sums go to red[k * nw + wave], k < nvals.
+__device__ __forceinline__ void wave_partials8(double (&a)[8], double* red, int k0, int nvals) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] += __shfl_xor(a[q], o, 64);
+  }
+  const int tid = flat_tid();
+  if ((tid & 63) == 0) {
+    const int nw = block_threads() >> 6, w = tid >> 6;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (k0 + q < nvals) red[(k0 + q) * nw + w] = a[q];
+  }
+}
+
 __device__ __forceinline__ void block_partials_out(const double* red, int nvals, double* partials,
                                                    const int* kind) {
   __syncthreads();
@@ -96,7 +151,7 @@ __device__ __forceinline__ void block_partials_out(const double* red, int nvals,
       const double x = red[k * nw + w];
       s = kd == 0 ? s + x : (kd == 1 ? fmin(s, x) : fmax(s, x));
     }
-    partials[(size_t)blockIdx.x * kPartialStride + k] = s;
+    partial_store(&partials[(size_t)blockIdx.x * kPartialStride + k], s);
   }
 }
 
@@ -104,51 +159,92 @@ __device__ __forceinline__ void block_partials_out(const double* red, int nvals,
 // GMRES scalar work (single thread of the last block)
 // ----------------------------------------------------------------------------
 
-// Finish Arnoldi step j: H(:, j) = s + s2, H(j+1, j) = ||w2||, Givens, test.
+// Finish Arnoldi step j (called by the whole last block; nrm2 and s2 are in
+// LDS):  H(:, j) = s + s2,  H(j+1, j) = ||w1 - V s2||,  apply the previous
+// Givens rotations and a new one, update the residual estimate, test it and,
+// when the solve stops, back-substitute for y.  The serial scalar work runs
+// on one thread from LDS copies of H, cs, sn, g.
 __device__ void gmres_finish_step(GmresState* st, int j, double nrm2, const double* s2) {
-  double* H = st->H;
-  double sum2 = 0.0;
-  for (int i = 0; i <= j; ++i) {
-    H[hidx(i, j)] = st->s[i] + s2[i];
-    st->s2[i] = s2[i];
-    sum2 += s2[i] * s2[i];
+  __shared__ double sh_H[(kMaxRestart + 1) * kMaxRestart];  // column-major (m+1) x (j+1) block
+  __shared__ double sh_cs[kMaxRestart], sh_sn[kMaxRestart], sh_g[kMaxRestart + 1], sh_y[kMaxRestart];
+  __shared__ int sh_stop;
+  const int tid = flat_tid(), nt = block_threads();
+  const int ld = kMaxRestart + 1;
+  // stage: columns 0..j-1 of H (rows 0..l), rotations, g
+  for (int e = tid; e < j * ld; e += nt) sh_H[e] = st->H[e];
+  for (int i = tid; i < j; i += nt) {
+    sh_cs[i] = st->cs[i];
+    sh_sn[i] = st->sn[i];
   }
-  const double b2 = nrm2 - sum2;
-  const double beta = b2 > 0.0 ? sqrt(b2) : 0.0;
-  H[hidx(j + 1, j)] = beta;
-  st->beta = beta;
-  for (int i = 0; i < j; ++i) {
-    const double a = H[hidx(i, j)], b = H[hidx(i + 1, j)];
-    H[hidx(i, j)] = st->cs[i] * a + st->sn[i] * b;
-    H[hidx(i + 1, j)] = -st->sn[i] * a + st->cs[i] * b;
+  for (int i = tid; i <= j; i += nt) {
+    sh_g[i] = st->gv[i];
+    sh_H[j * ld + i] = st->s[i];
   }
-  const double a = H[hidx(j, j)], b = H[hidx(j + 1, j)];
-  const double rho = hypot(a, b);
-  double c = 1.0, s = 0.0;
-  if (rho > 0.0) {
-    c = a / rho;
-    s = b / rho;
+  __syncthreads();
+  if (tid == 0) {
+    double* col = sh_H + j * ld;  // column j, built in place
+    double sum2 = 0.0;
+    for (int i = 0; i <= j; ++i) {
+      col[i] += s2[i];
+      sum2 += s2[i] * s2[i];
+    }
+    const double b2 = nrm2 - sum2;
+    const double beta = b2 > 0.0 ? sqrt(b2) : 0.0;
+    col[j + 1] = beta;
+    for (int i = 0; i < j; ++i) {
+      const double a = col[i], b = col[i + 1];
+      col[i] = sh_cs[i] * a + sh_sn[i] * b;
+      col[i + 1] = -sh_sn[i] * a + sh_cs[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double rho = hypot(a, b);
+    double c = 1.0, s = 0.0;
+    if (rho > 0.0) {
+      c = a / rho;
+      s = b / rho;
+    }
+    col[j] = rho;
+    col[j + 1] = 0.0;
+    sh_cs[j] = c;
+    sh_sn[j] = s;
+    const double gj = sh_g[j];
+    sh_g[j + 1] = -s * gj;
+    sh_g[j] = c * gj;
+    const double resid = fabs(sh_g[j + 1]);
+    const int total = st->st.total_iters + 1;
+    int done = 0;
+    if (resid <= st->tol * st->st.beta0 || beta == 0.0)
+      done = 1;
+    else if (j + 1 >= st->m)
+      done = 2;
+    else if (total >= st->maxit)
+      done = 3;
+    if (done) {  // back substitution R y = g on the (j+1) x (j+1) triangle
+      for (int i = j; i >= 0; --i) {
+        double acc = sh_g[i];
+        for (int l = i + 1; l <= j; ++l) acc -= sh_H[l * ld + i] * sh_y[l];
+        const double d = sh_H[i * ld + i];
+        sh_y[i] = d != 0.0 ? acc / d : 0.0;
+      }
+    }
+    st->beta = beta;
+    st->st.jdone = j + 1;
+    st->st.total_iters = total;
+    st->st.resid = resid;
+    st->st.done = done;
+    sh_stop = done;
   }
-  st->cs[j] = c;
-  st->sn[j] = s;
-  H[hidx(j, j)] = rho;
-  H[hidx(j + 1, j)] = 0.0;
-  st->gv[j + 1] = -s * st->gv[j];
-  st->gv[j] = c * st->gv[j];
-  const double resid = fabs(st->gv[j + 1]);
-  for (int i = j; i >= 0; --i) {
-    double acc = st->gv[i];
-    for (int l = i + 1; l <= j; ++l) acc -= H[hidx(i, l)] * st->y[l];
-    const double d = H[hidx(i, i)];
-    st->y[i] = d != 0.0 ? acc / d : 0.0;
+  __syncthreads();
+  // write back column j, the new rotation, g, s2 and (if stopping) y
+  for (int i = tid; i <= j + 1; i += nt) st->H[j * ld + i] = sh_H[j * ld + i];
+  for (int i = tid; i <= j; i += nt) st->s2[i] = s2[i];
+  if (tid == 0) {
+    st->cs[j] = sh_cs[j];
+    st->sn[j] = sh_sn[j];
   }
-  st->st.jdone = j + 1;
-  st->st.total_iters += 1;
-  st->st.resid = resid;
-  if (resid <= st->tol * st->st.beta0 || beta == 0.0)
-    st->st.done = 1;
-  else if (j + 1 >= st->m)
-    st->st.done = 2;
+  for (int i = tid; i <= j + 1; i += nt) st->gv[i] = sh_g[i];
+  if (sh_stop)
+    for (int i = tid; i <= j; i += nt) st->y[i] = sh_y[i];
 }
 
 // ----------------------------------------------------------------------------
@@ -159,8 +255,7 @@ template <int N>
 struct Row {
   static constexpr int E = FftShape<N>::E;
   static constexpr int TPF = FftShape<N>::TPF;
-  using Map = LdsMap<1, true>;
-  static constexpr int LDS = LdsMap<1, true>::size(N);  // cplx per row pair
+  static constexpr int LDS = RowMap::size(N);  // cplx per row pair
 };
 
 template <int N>
@@ -216,10 +311,10 @@ __device__ __forceinline__ void load_spec_pair(cplx* v, const cplx* __restrict__
 // Split the full spectrum of a packed row pair into the two half spectra.
 template <int N>
 __device__ __forceinline__ void store_spec_pair(const cplx* v, cplx* __restrict__ S, int ya, int t, cplx* buf) {
-  using M = typename Row<N>::Map;
+  const RowMap M;
   constexpr int H = N / 2;
 #pragma unroll
-  for (int r = 0; r < Row<N>::E; ++r) buf[M::at(t + r * Row<N>::TPF)] = v[r];
+  for (int r = 0; r < Row<N>::E; ++r) buf[M.at(t + r * Row<N>::TPF)] = v[r];
   __syncthreads();
   cplx* A = S + (size_t)ya * H;
   cplx* B = A + H;
@@ -227,11 +322,11 @@ __device__ __forceinline__ void store_spec_pair(const cplx* v, cplx* __restrict_
   for (int r = 0; r < Row<N>::E / 2; ++r) {
     const int k = t + r * Row<N>::TPF;
     if (k == 0) {
-      const cplx z0 = buf[M::at(0)], zn = buf[M::at(H)];
+      const cplx z0 = buf[M.at(0)], zn = buf[M.at(H)];
       A[0] = make_double2(z0.x, zn.x);
       B[0] = make_double2(z0.y, zn.y);
     } else {
-      const cplx z = buf[M::at(k)], zc = buf[M::at(N - k)];
+      const cplx z = buf[M.at(k)], zc = buf[M.at(N - k)];
       A[k] = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
       B[k] = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
     }
@@ -242,11 +337,13 @@ __device__ __forceinline__ void store_spec_pair(const cplx* v, cplx* __restrict_
 #define ROW_SETUP(N)                                   \
   constexpr int E = Row<N>::E;                         \
   constexpr int TPF = Row<N>::TPF;                     \
-  using Map = typename Row<N>::Map;                    \
+  const RowMap map;                                    \
   extern __shared__ cplx lds[];                        \
   const int t = threadIdx.x;                           \
   const int ya = 2 * (blockIdx.x * blockDim.y + threadIdx.y); \
   cplx* buf = lds + threadIdx.y * Row<N>::LDS;         \
+  TwiddleSet<N> twx;                                   \
+  gather_twiddles<N>(twx, t, g.twx);                   \
   (void)TPF;
 
 // physical f -> x-half spectra S
@@ -255,7 +352,7 @@ __global__ void __launch_bounds__(512) k_row_r2c(Geom g, const double* __restric
   ROW_SETUP(N)
   cplx v[E];
   load_phys_pair<N>(v, f, ya, t);
-  fft<N, false, Map>(v, buf, t, g.twx);
+  fft<N, false, decltype(map)>(v, buf, t, twx, map);
   store_spec_pair<N>(v, S, ya, t, buf);
 }
 
@@ -265,7 +362,7 @@ __global__ void __launch_bounds__(512) k_row_c2r(Geom g, const cplx* __restrict_
   ROW_SETUP(N)
   cplx v[E];
   load_spec_pair<N>(v, S, ya, t, g.inv_nx);
-  fft<N, true, Map>(v, buf, t, g.twx);
+  fft<N, true, decltype(map)>(v, buf, t, twx, map);
   store_phys_pair<N>(v, f, ya, t);
 }
 
@@ -275,10 +372,10 @@ __global__ void __launch_bounds__(512) k_row_dx(Geom g, const double* __restrict
   ROW_SETUP(N)
   cplx v[E];
   load_phys_pair<N>(v, f, ya, t);
-  fft<N, false, Map>(v, buf, t, g.twx);
+  fft<N, false, decltype(map)>(v, buf, t, twx, map);
 #pragma unroll
   for (int r = 0; r < E; ++r) v[r] = mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Lx) * g.inv_nx);
-  fft<N, true, Map>(v, buf, t, g.twx);
+  fft<N, true, decltype(map)>(v, buf, t, twx, map);
   store_phys_pair<N>(v, out, ya, t);
 }
 
@@ -298,59 +395,142 @@ __global__ void __launch_bounds__(512) k_row_op(Geom g, const cplx* __restrict__
                                                 int need_b, int predicate, const GmresState* __restrict__ st) {
   if (MODE == 0 && predicate && st->st.done) return;
   ROW_SETUP(N)
-  const double* ha = h + (size_t)ya * N;
-  const double* hb = ha + N;
-  cplx v[E], u[E];
+  // every global load first, so their latencies overlap
+  cplx v[E], u[E], w[E], hi[E], x[E], y[E];
   load_spec_pair<N>(v, Es, ya, t, g.inv_nx);
-#pragma unroll
-  for (int r = 0; r < E; ++r) u[r] = mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Lx));
-  fft<N, true, Map>(v, buf, t, g.twx);  // sigma
-  fft<N, true, Map>(u, buf, t, g.twx);  // d_x sigma
+  load_spec_pair<N>(w, Gs, ya, t, g.inv_nx);
+  load_phys_pair<N>(hi, h, ya, t);
+  if constexpr (MODE != 0) load_phys_pair<N>(x, vx, ya, t);
+  if constexpr (MODE == 1) load_phys_pair<N>(y, vy, ya, t);
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const int p = t + r * TPF;
-    const double ia = 1.0 / ha[p], ib = 1.0 / hb[p];
+    hi[r] = make_double2(1.0 / hi[r].x, 1.0 / hi[r].y);
+    u[r] = mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Lx));
+  }
+  fft<N, true, decltype(map)>(v, buf, t, twx, map);  // sigma
+  fft<N, true, decltype(map)>(u, buf, t, twx, map);  // d_x sigma
+  fft<N, true, decltype(map)>(w, buf, t, twx, map);  // d_y sigma
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const double ia = hi[r].x, ib = hi[r].y;
     v[r] = make_double2(3.0 * v[r].x * ia * ia * ia, 3.0 * v[r].y * ib * ib * ib);
     u[r] = make_double2(u[r].x * ia, u[r].y * ib);
+    w[r] = make_double2(w[r].x * ia, w[r].y * ib);
   }
-  fft<N, false, Map>(v, buf, t, g.twx);
-  fft<N, false, Map>(u, buf, t, g.twx);
+  fft<N, false, decltype(map)>(v, buf, t, twx, map);
+  fft<N, false, decltype(map)>(u, buf, t, twx, map);
+  fft<N, false, decltype(map)>(w, buf, t, twx, map);  // A2
 #pragma unroll
   for (int r = 0; r < E; ++r) v[r] = csub(v[r], mul_ik(u[r], wavenumber(t + r * TPF, N, g.inv_Lx)));  // A1
-  load_spec_pair<N>(u, Gs, ya, t, g.inv_nx);
-  fft<N, true, Map>(u, buf, t, g.twx);  // d_y sigma
-#pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const int p = t + r * TPF;
-    u[r] = make_double2(u[r].x / ha[p], u[r].y / hb[p]);
-  }
-  fft<N, false, Map>(u, buf, t, g.twx);  // A2
   if constexpr (MODE == 0) {
     store_spec_pair<N>(v, P, ya, t, buf);
-    store_spec_pair<N>(u, Q, ya, t, buf);
+    store_spec_pair<N>(w, Q, ya, t, buf);
   } else {
-    cplx w[E];
-    load_phys_pair<N>(w, vx, ya, t);
-    fft<N, false, Map>(w, buf, t, g.twx);
+    fft<N, false, decltype(map)>(x, buf, t, twx, map);
     if constexpr (MODE == 1) {
 #pragma unroll
-      for (int r = 0; r < E; ++r) w[r] = mul_ik(w[r], -wavenumber(t + r * TPF, N, g.inv_Lx));
+      for (int r = 0; r < E; ++r) x[r] = mul_ik(x[r], -wavenumber(t + r * TPF, N, g.inv_Lx));
     }
 #pragma unroll
-    for (int r = 0; r < E; ++r) v[r] = csub(w[r], v[r]);
+    for (int r = 0; r < E; ++r) v[r] = csub(x[r], v[r]);
     store_spec_pair<N>(v, P, ya, t, buf);
-    if (need_b) store_spec_pair<N>(w, R1, ya, t, buf);
+    if (need_b) store_spec_pair<N>(x, R1, ya, t, buf);
     if constexpr (MODE == 1) {
-      load_phys_pair<N>(w, vy, ya, t);
-      fft<N, false, Map>(w, buf, t, g.twx);
+      fft<N, false, decltype(map)>(y, buf, t, twx, map);
 #pragma unroll
-      for (int r = 0; r < E; ++r) u[r] = csub(w[r], u[r]);
-      store_spec_pair<N>(u, Q, ya, t, buf);
-      if (need_b) store_spec_pair<N>(w, R2, ya, t, buf);
+      for (int r = 0; r < E; ++r) w[r] = csub(y[r], w[r]);
+      store_spec_pair<N>(w, Q, ya, t, buf);
+      if (need_b) store_spec_pair<N>(y, R2, ya, t, buf);
     } else {
 #pragma unroll
-      for (int r = 0; r < E; ++r) u[r] = make_double2(-u[r].x, -u[r].y);
-      store_spec_pair<N>(u, Q, ya, t, buf);
+      for (int r = 0; r < E; ++r) w[r] = make_double2(-w[r].x, -w[r].y);
+      store_spec_pair<N>(w, Q, ya, t, buf);
+    }
+  }
+}
+
+// The Arnoldi matvec, x part (same result as k_row_op<N, 0>), with its three
+// independent transform chains run concurrently by three thread groups of
+// the block (threadIdx.y % 3):
+//   chain 0: sigma -> 3 sigma / h^3 -> F_x
+//   chain 1: d_x sigma -> / h -> F_x -> (-i kx)
+//   chain 2: d_y sigma -> / h -> F_x                      (= A2)
+// A1 = chain 0 + chain 1 and A2 are split into half spectra through LDS.
+// Block: (TPF, 3 * rows-pairs-per-block).
+template <int N>
+__global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __restrict__ Es, const cplx* __restrict__ Gs,
+                                                      const double* __restrict__ h, cplx* __restrict__ P,
+                                                      cplx* __restrict__ Q, const GmresState* __restrict__ st) {
+  if (st->st.done) return;
+  constexpr int E = Row<N>::E;
+  constexpr int TPF = Row<N>::TPF;
+  constexpr int H = N / 2;
+  const RowMap map;
+  extern __shared__ cplx lds[];
+  const int t = threadIdx.x;
+  const int slot = threadIdx.y / 3, chain = threadIdx.y % 3;
+  const int ya = 2 * (blockIdx.x * (blockDim.y / 3) + slot);
+  cplx* base = lds + slot * 3 * Row<N>::LDS;
+  cplx* buf = base + chain * Row<N>::LDS;
+  TwiddleSet<N> twx;
+  gather_twiddles<N>(twx, t, g.twx);
+  cplx v[E], hi[E];
+  load_spec_pair<N>(v, chain == 2 ? Gs : Es, ya, t, g.inv_nx);
+  load_phys_pair<N>(hi, h, ya, t);
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    hi[r] = make_double2(1.0 / hi[r].x, 1.0 / hi[r].y);
+    if (chain == 1) v[r] = mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Lx));
+  }
+  fft<N, true, RowMap>(v, buf, t, twx, map);
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const double ia = hi[r].x, ib = hi[r].y;
+    if (chain == 0)
+      v[r] = make_double2(3.0 * v[r].x * ia * ia * ia, 3.0 * v[r].y * ib * ib * ib);
+    else
+      v[r] = make_double2(v[r].x * ia, v[r].y * ib);
+  }
+  fft<N, false, RowMap>(v, buf, t, twx, map);
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    if (chain == 1) v[r] = mul_ik(v[r], -wavenumber(t + r * TPF, N, g.inv_Lx));
+    buf[map.at(t + r * TPF)] = v[r];
+  }
+  __syncthreads();
+  // unpack: chains 0 and 1 share A1 = buf0 + buf1 (one k each), chain 2 does A2
+  const cplx* b0 = base;
+  const cplx* b1 = base + Row<N>::LDS;
+  const cplx* b2 = base + 2 * Row<N>::LDS;
+  auto at_A1 = [&](int k) { return cadd(b0[map.at(k)], b1[map.at(k)]); };
+  auto emit = [&](cplx* S, int k, cplx z, cplx zc) {
+    cplx* A = S + (size_t)ya * H;
+    cplx* B = A + H;
+    A[k] = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
+    B[k] = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
+  };
+#pragma unroll
+  for (int r = 0; r < E / 2; ++r) {
+    if ((chain == 2) ? false : (r % 2 != chain)) continue;
+    const int k = t + r * TPF;
+    if (chain == 2) {
+      if (k == 0) {
+        const cplx z0 = b2[map.at(0)], zn = b2[map.at(H)];
+        cplx* A = Q + (size_t)ya * H;
+        A[0] = make_double2(z0.x, zn.x);
+        A[H] = make_double2(z0.y, zn.y);
+      } else {
+        emit(Q, k, b2[map.at(k)], b2[map.at(N - k)]);
+      }
+    } else {
+      if (k == 0) {
+        const cplx z0 = at_A1(0), zn = at_A1(H);
+        cplx* A = P + (size_t)ya * H;
+        A[0] = make_double2(z0.x, zn.x);
+        A[H] = make_double2(z0.y, zn.y);
+      } else {
+        emit(P, k, at_A1(k), at_A1(N - k));
+      }
     }
   }
 }
@@ -377,55 +557,43 @@ __global__ void __launch_bounds__(512) k_row_flux(Geom g, const cplx* __restrict
                                                   double* __restrict__ dhp, double* __restrict__ qy,
                                                   double* __restrict__ Bo, RkStage rk, RkField fvx) {
   ROW_SETUP(N)
-  const size_t oa = (size_t)ya * N, ob = oa + N;
-  cplx v[E], B[E];
-  load_spec_pair<N>(v, Es, ya, t, g.inv_nx);
-  fft<N, true, Map>(v, buf, t, g.twx);  // sigma
+  cplx s[E], sx[E], sy[E], hh[E], ux[E], uy[E];
+  load_spec_pair<N>(s, Es, ya, t, g.inv_nx);
+  load_spec_pair<N>(sy, Gs, ya, t, g.inv_nx);
+  load_phys_pair<N>(hh, h, ya, t);
+  load_phys_pair<N>(ux, vx, ya, t);
+  load_phys_pair<N>(uy, vy, ya, t);
+#pragma unroll
+  for (int r = 0; r < E; ++r) sx[r] = mul_ik(s[r], wavenumber(t + r * TPF, N, g.inv_Lx));
+  fft<N, true, decltype(map)>(s, buf, t, twx, map);   // sigma
+  fft<N, true, decltype(map)>(sx, buf, t, twx, map);  // d_x sigma
+  fft<N, true, decltype(map)>(sy, buf, t, twx, map);  // d_y sigma
+  cplx B[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const int p = t + r * TPF;
-    const double a = h[oa + p], b = h[ob + p];
+    const double a = hh[r].x, b = hh[r].y;
     const double ia = 1.0 / a, ib = 1.0 / b;
-    const double sa = v[r].x * ia * ia, sb = v[r].y * ib * ib;
-    B[r] = make_double2(g.g * a - 4.5 * sa * sa, g.g * b - 4.5 * sb * sb);
+    const double sa = s[r].x * ia * ia, sb = s[r].y * ib * ib;
+    const double rxa = sx[r].x * ia, rxb = sx[r].y * ib, rya = sy[r].x * ia, ryb = sy[r].y * ib;
+    B[r].x = 0.5 * (ux[r].x * ux[r].x + uy[r].x * uy[r].x) - 0.5 * (rxa * rxa + rya * rya) + g.g * a - 4.5 * sa * sa;
+    B[r].y = 0.5 * (ux[r].y * ux[r].y + uy[r].y * uy[r].y) - 0.5 * (rxb * rxb + ryb * ryb) + g.g * b - 4.5 * sb * sb;
+    sx[r] = make_double2(a * ux[r].x - sx[r].x, b * ux[r].y - sx[r].y);  // qx
+    sy[r] = make_double2(a * uy[r].x - sy[r].x, b * uy[r].y - sy[r].y);  // qy
   }
-  load_spec_pair<N>(v, Es, ya, t, g.inv_nx);
-#pragma unroll
-  for (int r = 0; r < E; ++r) v[r] = mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Lx));
-  fft<N, true, Map>(v, buf, t, g.twx);  // d_x sigma
-#pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const int p = t + r * TPF;
-    const double a = h[oa + p], b = h[ob + p];
-    const double ua = vx[oa + p], ub = vx[ob + p];
-    const double ra = v[r].x / a, rb = v[r].y / b;
-    B[r].x += 0.5 * ua * ua - 0.5 * ra * ra;
-    B[r].y += 0.5 * ub * ub - 0.5 * rb * rb;
-    v[r] = make_double2(a * ua - v[r].x, b * ub - v[r].y);  // qx
-  }
-  fft<N, false, Map>(v, buf, t, g.twx);
-#pragma unroll
-  for (int r = 0; r < E; ++r) v[r] = mul_ik(v[r], -wavenumber(t + r * TPF, N, g.inv_Lx) * g.inv_nx);
-  fft<N, true, Map>(v, buf, t, g.twx);
-  store_phys_pair<N>(v, dhp, ya, t);  // -d_x qx
-  load_spec_pair<N>(v, Gs, ya, t, g.inv_nx);
-  fft<N, true, Map>(v, buf, t, g.twx);  // d_y sigma
-#pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const int p = t + r * TPF;
-    const double a = h[oa + p], b = h[ob + p];
-    const double wa = vy[oa + p], wb = vy[ob + p];
-    const double ra = v[r].x / a, rb = v[r].y / b;
-    B[r].x += 0.5 * wa * wa - 0.5 * ra * ra;
-    B[r].y += 0.5 * wb * wb - 0.5 * rb * rb;
-    qy[oa + p] = a * wa - v[r].x;
-    qy[ob + p] = b * wb - v[r].y;
-  }
+  store_phys_pair<N>(sy, qy, ya, t);
   store_phys_pair<N>(B, Bo, ya, t);
-  fft<N, false, Map>(B, buf, t, g.twx);
+  fft<N, false, decltype(map)>(sx, buf, t, twx, map);
+  fft<N, false, decltype(map)>(B, buf, t, twx, map);
 #pragma unroll
-  for (int r = 0; r < E; ++r) B[r] = mul_ik(B[r], -wavenumber(t + r * TPF, N, g.inv_Lx) * g.inv_nx);
-  fft<N, true, Map>(B, buf, t, g.twx);  // k_vx = -d_x B
+  for (int r = 0; r < E; ++r) {
+    const double k = -wavenumber(t + r * TPF, N, g.inv_Lx) * g.inv_nx;
+    sx[r] = mul_ik(sx[r], k);
+    B[r] = mul_ik(B[r], k);
+  }
+  fft<N, true, decltype(map)>(sx, buf, t, twx, map);  // -d_x qx
+  fft<N, true, decltype(map)>(B, buf, t, twx, map);   // k_vx = -d_x B
+  store_phys_pair<N>(sx, dhp, ya, t);
+  const size_t oa = (size_t)ya * N, ob = oa + N;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int p = t + r * TPF;
@@ -444,7 +612,7 @@ __global__ void __launch_bounds__(512) k_row_invariants(Geom g, const cplx* __re
                                                         GmresState* st, int nblocks) {
   constexpr int E = Row<N>::E;
   constexpr int TPF = Row<N>::TPF;
-  using Map = typename Row<N>::Map;
+  const RowMap map;
   extern __shared__ cplx lds[];
   const int t = threadIdx.x;
   // blocks hold at least one full wave; slots past the last row pair read a
@@ -453,6 +621,8 @@ __global__ void __launch_bounds__(512) k_row_invariants(Geom g, const cplx* __re
   const bool rvalid = ya_raw < g.ny;
   const int ya = rvalid ? ya_raw : g.ny - 2;
   cplx* buf = lds + threadIdx.y * Row<N>::LDS;
+  TwiddleSet<N> twx;
+  gather_twiddles<N>(twx, t, g.twx);
   __shared__ double red[7 * 8];
   __shared__ double outv[8];
   const size_t oa = (size_t)ya * N, ob = oa + N;
@@ -462,11 +632,11 @@ __global__ void __launch_bounds__(512) k_row_invariants(Geom g, const cplx* __re
   load_spec_pair<N>(s, Es, ya, t, g.inv_nx);
 #pragma unroll
   for (int r = 0; r < E; ++r) d[r] = mul_ik(s[r], wavenumber(t + r * TPF, N, g.inv_Lx));
-  fft<N, true, Map>(s, buf, t, g.twx);  // sigma
-  fft<N, true, Map>(d, buf, t, g.twx);  // d_x sigma
+  fft<N, true, decltype(map)>(s, buf, t, twx, map);  // sigma
+  fft<N, true, decltype(map)>(d, buf, t, twx, map);  // d_x sigma
   cplx e[E];
   load_spec_pair<N>(e, Gs, ya, t, g.inv_nx);
-  fft<N, true, Map>(e, buf, t, g.twx);  // d_y sigma
+  fft<N, true, decltype(map)>(e, buf, t, twx, map);  // d_y sigma
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int p = t + r * TPF;
@@ -490,10 +660,10 @@ __global__ void __launch_bounds__(512) k_row_invariants(Geom g, const cplx* __re
   }
   // curl v = d_x vy - d_y vx
   load_phys_pair<N>(d, vy, ya, t);
-  fft<N, false, Map>(d, buf, t, g.twx);
+  fft<N, false, decltype(map)>(d, buf, t, twx, map);
 #pragma unroll
   for (int r = 0; r < E; ++r) d[r] = mul_ik(d[r], wavenumber(t + r * TPF, N, g.inv_Lx) * g.inv_nx);
-  fft<N, true, Map>(d, buf, t, g.twx);
+  fft<N, true, decltype(map)>(d, buf, t, twx, map);
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int p = t + r * TPF;
@@ -512,7 +682,7 @@ __global__ void __launch_bounds__(512) k_row_invariants(Geom g, const cplx* __re
     }
   }
   block_partials_out(red, 7, partials, kinds);
-  if (last_block_arrive(&st->counter, nblocks)) {
+  if (last_block_arrive(st->ctr, nblocks)) {
     reduce_partials(partials, nblocks, 7, kinds, outv);
     if (flat_tid() == 0) {
       st->st.red[0] = outv[0] * g.dA;
@@ -522,7 +692,6 @@ __global__ void __launch_bounds__(512) k_row_invariants(Geom g, const cplx* __re
       st->st.red[4] = sqrt(outv[4] * g.dA);
       st->st.red[5] = outv[5];
       st->st.red[6] = outv[6];
-      st->counter = 0;
     }
   }
 }
@@ -535,26 +704,34 @@ template <int N>
 struct Col {
   static constexpr int E = FftShape<N>::E;
   static constexpr int TPF = FftShape<N>::TPF;
-  static constexpr int TC0 = (N >= 2048) ? (131072 / 16) / N : (65536 / 16) / N;  // LDS budget
-  static constexpr int TC1 = TC0 < 16 ? TC0 : 16;
-  static constexpr int TC2 = (512 / TPF) < TC1 ? (512 / TPF) : TC1;
-  static constexpr int TCmin = (64 / TPF) > 1 ? (64 / TPF) : 1;  // at least one wave per block
-  static constexpr int TC = TC2 > TCmin ? TC2 : TCmin;
-  using Map = LdsMap<TC, false>;
-  static constexpr int LDS = TC * N;
 };
+
+// Blocks are dealt to the 8 XCDs round-robin; map them so that the tiles one
+// XCD works on are adjacent (tiles that share cache lines share an L2).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  return (nb & 7) == 0 ? (b & 7) * (nb >> 3) + (b >> 3) : b;
+}
+
+__device__ __forceinline__ double inv_symbol(const Geom& g, double kx, double ky) {
+  return 1.0 / (g.m0 + g.m1 * (kx * kx + ky * ky));
+}
+
+// Weight of a half-spectrum column in a physical inner product:
+// column 0 carries kx = 0 and the Nyquist column once, others stand for +-kx.
+__device__ __forceinline__ double col_weight(int col) { return col == 0 ? 1.0 : 2.0; }
 
 #define COL_SETUP(N)                                         \
   constexpr int E = Col<N>::E;                               \
   constexpr int TPF = Col<N>::TPF;                           \
-  constexpr int TC = Col<N>::TC;                             \
-  using Map = typename Col<N>::Map;                          \
   extern __shared__ cplx lds[];                              \
   const int c = threadIdx.x;                                 \
   const int t = threadIdx.y;                                 \
-  const int col = blockIdx.x * TC + c;                       \
+  const ColMap map{(int)blockDim.x};                         \
+  const int col = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + c; \
   const bool valid = col < g.nh;                             \
   cplx* buf = lds + c;                                       \
+  TwiddleSet<N> twy;                                         \
+  gather_twiddles<N>(twy, t, g.twy);                         \
   (void)valid;
 
 template <int N>
@@ -583,29 +760,29 @@ __global__ void __launch_bounds__(512) k_col_fwd_eg(Geom g, const cplx* __restri
   COL_SETUP(N)
   cplx v[E];
   load_col<N>(v, Ein, g.nh, col, t, valid);
-  fft<N, false, Map>(v, buf, t, g.twy);
+  fft<N, false, decltype(map)>(v, buf, t, twy, map);
   store_col<N>(v, SIG, g.nh, col, t, valid);
 #pragma unroll
   for (int r = 0; r < E; ++r) v[r] = mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Ly) * g.inv_ny);
-  fft<N, true, Map>(v, buf, t, g.twy);
+  fft<N, true, decltype(map)>(v, buf, t, twy, map);
   store_col<N>(v, Gout, g.nh, col, t, valid);
 }
 
 // Inverse y-transforms of a 2D spectrum x: E = F_y^-1 x, G = F_y^-1 (i ky x).
 template <int N>
 __device__ __forceinline__ void col_emit_eg(Geom& g, cplx* v, cplx* buf, int t, int col, bool valid,
-                                            cplx* __restrict__ Eo, cplx* __restrict__ Go) {
+                                            cplx* __restrict__ Eo, cplx* __restrict__ Go, const TwiddleSet<N>& twy) {
   constexpr int E = Col<N>::E, TPF = Col<N>::TPF;
-  using Map = typename Col<N>::Map;
+  const ColMap map{(int)blockDim.x};
   cplx u[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     u[r] = mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Ly) * g.inv_ny);
     v[r] = cscale(v[r], g.inv_ny);
   }
-  fft<N, true, Map>(v, buf, t, g.twy);
+  fft<N, true, decltype(map)>(v, buf, t, twy, map);
   store_col<N>(v, Eo, g.nh, col, t, valid);
-  fft<N, true, Map>(u, buf, t, g.twy);
+  fft<N, true, decltype(map)>(u, buf, t, twy, map);
   store_col<N>(u, Go, g.nh, col, t, valid);
 }
 
@@ -629,17 +806,138 @@ __global__ void __launch_bounds__(512) k_col_basis_eg(Geom g, const cplx* __rest
     cplx x = make_double2(0.0, 0.0);
     if (valid) {
       x = W[idx];
-      for (int i = 0; i < j; ++i) {
-        const cplx b = V[i * vstride + idx];
-        x.x -= coef[i] * b.x;
-        x.y -= coef[i] * b.y;
+      for (int i0 = 0; i0 < j; i0 += 4) {
+        cplx b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[q] = i0 + q < j ? V[(i0 + q) * vstride + idx] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double c = i0 + q < j ? coef[i0 + q] : 0.0;
+          x.x -= c * b[q].x;
+          x.y -= c * b[q].y;
+        }
       }
       x = cscale(x, ib);
       V[j * vstride + idx] = x;
     }
     v[r] = x;
   }
-  col_emit_eg<N>(g, v, buf, t, col, valid, Eo, Go);
+  col_emit_eg<N>(g, v, buf, t, col, valid, Eo, Go, twy);
+}
+
+// Two-chain variants of the Arnoldi column passes: threadIdx.z selects the
+// chain; each chain has its own LDS region of tc x N.
+#define COL2_SETUP(N)                                        \
+  constexpr int E = Col<N>::E;                               \
+  constexpr int TPF = Col<N>::TPF;                           \
+  extern __shared__ cplx lds[];                              \
+  const int c = threadIdx.x;                                 \
+  const int t = threadIdx.y;                                 \
+  const int chain = threadIdx.z;                             \
+  const ColMap map{(int)blockDim.x};                         \
+  const int col = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + c; \
+  const bool valid = col < g.nh;                             \
+  cplx* buf = lds + chain * (blockDim.x * N) + c;            \
+  TwiddleSet<N> twy;                                         \
+  gather_twiddles<N>(twy, t, g.twy);
+
+// Same result as k_col_basis_eg: V_j = (W - sum_{i<j} s2_i V_i) / beta and
+// its inverse y-transforms E (chain 0) and G (chain 1) computed concurrently.
+template <int N>
+__global__ void __launch_bounds__(1024) k_col_basis2(Geom g, const cplx* __restrict__ W, cplx* __restrict__ V,
+                                                     size_t vstride, int j, const GmresState* __restrict__ st,
+                                                     cplx* __restrict__ Eo, cplx* __restrict__ Go) {
+  if (st->st.done) return;
+  COL2_SETUP(N)
+  __shared__ double coef[kMaxRestart + 1];
+  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  const int nthr = blockDim.x * blockDim.y * blockDim.z;
+  for (int i = tid; i < j; i += nthr) coef[i] = st->s2[i];
+  __syncthreads();
+  const double ib = 1.0 / st->beta;
+  cplx v[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int p = t + r * TPF;
+    const size_t idx = (size_t)p * g.nh + col;
+    cplx x = make_double2(0.0, 0.0);
+    if (valid) {
+      x = W[idx];
+      for (int i0 = 0; i0 < j; i0 += 4) {
+        cplx b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[q] = i0 + q < j ? V[(i0 + q) * vstride + idx] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double cf = i0 + q < j ? coef[i0 + q] : 0.0;
+          x.x -= cf * b[q].x;
+          x.y -= cf * b[q].y;
+        }
+      }
+      x = cscale(x, ib);
+      if (chain == 0) V[j * vstride + idx] = x;
+    }
+    v[r] = chain == 0 ? cscale(x, g.inv_ny) : mul_ik(x, wavenumber(p, N, g.inv_Ly) * g.inv_ny);
+  }
+  fft<N, true, ColMap>(v, buf, t, twy, map);
+  store_col<N>(v, chain == 0 ? Eo : Go, g.nh, col, t, valid);
+}
+
+// Same result as k_col_precond_dot: chain 0 transforms P, chain 1 transforms
+// Q (times -i ky); w = (sum) / M is formed through LDS and each chain then
+// owns half of the thread's positions for the store and the projections.
+template <int N>
+__global__ void __launch_bounds__(1024) k_col_precond_dot2(Geom g, const cplx* __restrict__ P,
+                                                           const cplx* __restrict__ Q, const cplx* __restrict__ V,
+                                                           size_t vstride, int j, GmresState* st,
+                                                           cplx* __restrict__ W, double* partials, int nblocks) {
+  if (st->st.done) return;
+  COL2_SETUP(N)
+  __shared__ double red[(kMaxRestart + 1) * 16];
+  __shared__ double outv[kMaxRestart + 1];
+  cplx v[E];
+  load_col<N>(v, chain == 0 ? P : Q, g.nh, col, t, valid);
+  fft<N, false, ColMap>(v, buf, t, twy, map);
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    if (chain == 1) v[r] = mul_ik(v[r], -wavenumber(t + r * TPF, N, g.inv_Ly));
+    buf[map.at(t + r * TPF)] = v[r];
+  }
+  __syncthreads();
+  const cplx* b0 = lds + c;
+  const cplx* b1 = lds + blockDim.x * N + c;
+  const double kx = col * g.inv_Lx;
+  constexpr int EH = E / 2;
+  cplx w[EH];
+#pragma unroll
+  for (int q = 0; q < EH; ++q) {
+    const int p = t + (chain * EH + q) * TPF;
+    w[q] = cscale(cadd(b0[map.at(p)], b1[map.at(p)]), inv_symbol(g, kx, wavenumber(p, N, g.inv_Ly)));
+    if (valid) W[(size_t)p * g.nh + col] = w[q];
+  }
+  const double wt = valid ? col_weight(col) : 0.0;
+  for (int i0 = 0; i0 <= j; i0 += 8) {
+    double a[8];
+#pragma unroll
+    for (int q8 = 0; q8 < 8; ++q8) {
+      double d = 0.0;
+      if (valid && i0 + q8 <= j) {
+#pragma unroll
+        for (int q = 0; q < EH; ++q) {
+          const int p = t + (chain * EH + q) * TPF;
+          const cplx b = V[(i0 + q8) * vstride + (size_t)p * g.nh + col];
+          d += b.x * w[q].x + b.y * w[q].y;
+        }
+      }
+      a[q8] = wt * d;
+    }
+    wave_partials8(a, red, i0, j + 1);
+  }
+  block_partials_out(red, j + 1, partials, nullptr);
+  if (last_block_arrive(st->ctr, nblocks)) {
+    reduce_partials(partials, nblocks, j + 1, nullptr, outv);
+    for (int i = flat_tid(); i <= j; i += block_threads()) st->s[i] = outv[i] * g.inv_n;
+  }
 }
 
 // sigma_hat += sum_{i<k} y_i V_i (or 0 when b == 0), then E, G of sigma_hat.
@@ -663,42 +961,43 @@ __global__ void __launch_bounds__(512) k_col_update_eg(Geom g, cplx* __restrict_
     if (valid) {
       if (!zero) {
         x = SIG[idx];
-        for (int i = 0; i < k; ++i) {
-          const cplx b = V[i * vstride + idx];
-          x.x += coef[i] * b.x;
-          x.y += coef[i] * b.y;
+        for (int i0 = 0; i0 < k; i0 += 4) {
+          cplx b[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) b[q] = i0 + q < k ? V[(i0 + q) * vstride + idx] : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const double c = i0 + q < k ? coef[i0 + q] : 0.0;
+            x.x += c * b[q].x;
+            x.y += c * b[q].y;
+          }
         }
       }
       SIG[idx] = x;
     }
     v[r] = x;
   }
-  col_emit_eg<N>(g, v, buf, t, col, valid, Eo, Go);
+  col_emit_eg<N>(g, v, buf, t, col, valid, Eo, Go, twy);
 }
 
-__device__ __forceinline__ double inv_symbol(const Geom& g, double kx, double ky) {
-  return 1.0 / (g.m0 + g.m1 * (kx * kx + ky * ky));
-}
 
 // F_y(P) - i ky F_y(Q) for the tile; P, Q are x-half spectra (Q may be null).
 template <int N>
 __device__ __forceinline__ void col_combine(Geom& g, cplx* v, cplx* buf, int t, int col, bool valid,
-                                            const cplx* __restrict__ P, const cplx* __restrict__ Q) {
+                                            const cplx* __restrict__ P, const cplx* __restrict__ Q,
+                                            const TwiddleSet<N>& twy) {
   constexpr int E = Col<N>::E, TPF = Col<N>::TPF;
-  using Map = typename Col<N>::Map;
-  load_col<N>(v, P, g.nh, col, t, valid);
-  fft<N, false, Map>(v, buf, t, g.twy);
-  if (Q == nullptr) return;  // second term absent (an explicit b has no y part)
+  const ColMap map{(int)blockDim.x};
   cplx u[E];
-  load_col<N>(u, Q, g.nh, col, t, valid);
-  fft<N, false, Map>(u, buf, t, g.twy);
+  load_col<N>(v, P, g.nh, col, t, valid);
+  if (Q != nullptr) load_col<N>(u, Q, g.nh, col, t, valid);
+  fft<N, false, decltype(map)>(v, buf, t, twy, map);
+  if (Q == nullptr) return;  // second term absent (an explicit b has no y part)
+  fft<N, false, decltype(map)>(u, buf, t, twy, map);
 #pragma unroll
   for (int r = 0; r < E; ++r) v[r] = csub(v[r], mul_ik(u[r], wavenumber(t + r * TPF, N, g.inv_Ly)));
 }
 
-// Weight of a half-spectrum column in a physical inner product:
-// column 0 carries kx = 0 and the Nyquist column once, others stand for +-kx.
-__device__ __forceinline__ double col_weight(int col) { return col == 0 ? 1.0 : 2.0; }
 
 // Arnoldi: w = M^-1 F(L V_j) (= (F_y P - i ky F_y Q) / M), s_i = <V_i, w>, i <= j.
 template <int N>
@@ -711,7 +1010,7 @@ __global__ void __launch_bounds__(512) k_col_precond_dot(Geom g, const cplx* __r
   __shared__ double red[(kMaxRestart + 1) * 16];
   __shared__ double outv[kMaxRestart + 1];
   cplx v[E];
-  col_combine<N>(g, v, buf, t, col, valid, P, Q);
+  col_combine<N>(g, v, buf, t, col, valid, P, Q, twy);
   const double kx = col * g.inv_Lx;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -720,24 +1019,27 @@ __global__ void __launch_bounds__(512) k_col_precond_dot(Geom g, const cplx* __r
   }
   store_col<N>(v, W, g.nh, col, t, valid);
   const double wt = valid ? col_weight(col) : 0.0;
-  for (int i = 0; i <= j; ++i) {
-    double d = 0.0;
-    if (valid) {
+  for (int i0 = 0; i0 <= j; i0 += 8) {
+    double a[8];
 #pragma unroll
-      for (int r = 0; r < E; ++r) {
-        const int p = t + r * TPF;
-        const cplx b = V[i * vstride + (size_t)p * g.nh + col];
-        d += b.x * v[r].x + b.y * v[r].y;
+    for (int q = 0; q < 8; ++q) {
+      double d = 0.0;
+      if (valid && i0 + q <= j) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const int p = t + r * TPF;
+          const cplx b = V[(i0 + q) * vstride + (size_t)p * g.nh + col];
+          d += b.x * v[r].x + b.y * v[r].y;
+        }
       }
+      a[q] = wt * d;
     }
-    wave_partial(wt * d, red, i);
+    wave_partials8(a, red, i0, j + 1);
   }
   block_partials_out(red, j + 1, partials, nullptr);
-  if (last_block_arrive(&st->counter, nblocks)) {
+  if (last_block_arrive(st->ctr, nblocks)) {
     reduce_partials(partials, nblocks, j + 1, nullptr, outv);
     for (int i = flat_tid(); i <= j; i += block_threads()) st->s[i] = outv[i] * g.inv_n;
-    __syncthreads();
-    if (flat_tid() == 0) st->counter = 0;
   }
 }
 
@@ -755,7 +1057,7 @@ __global__ void __launch_bounds__(512) k_col_resid(Geom g, const cplx* __restric
   __shared__ double outv[3];
   const bool true_only = (flags & 2) != 0;
   cplx v[E];
-  col_combine<N>(g, v, buf, t, col, valid, P, Q);
+  col_combine<N>(g, v, buf, t, col, valid, P, Q, twy);
   const double kx = col * g.inv_Lx;
   const double wt = valid ? col_weight(col) : 0.0;
   double nr = 0.0;
@@ -769,7 +1071,7 @@ __global__ void __launch_bounds__(512) k_col_resid(Geom g, const cplx* __restric
   wave_partial(wt * nr, red, 0);
   int nvals = 1;
   if (need_b) {
-    col_combine<N>(g, v, buf, t, col, valid, R1, R2);
+    col_combine<N>(g, v, buf, t, col, valid, R1, R2, twy);
     double nb = 0.0, nbm = 0.0;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
@@ -784,7 +1086,7 @@ __global__ void __launch_bounds__(512) k_col_resid(Geom g, const cplx* __restric
     nvals = 3;
   }
   block_partials_out(red, nvals, partials, nullptr);
-  if (last_block_arrive(&st->counter, nblocks)) {
+  if (last_block_arrive(st->ctr, nblocks)) {
     reduce_partials(partials, nblocks, nvals, nullptr, outv);
     if (flat_tid() == 0) {
       if (true_only) {
@@ -806,7 +1108,6 @@ __global__ void __launch_bounds__(512) k_col_resid(Geom g, const cplx* __restric
         st->st.resid = beta;
         st->st.done = (st->st.zero || beta <= st->tol * st->st.beta0) ? 1 : 0;
       }
-      st->counter = 0;
     }
   }
 }
@@ -819,7 +1120,7 @@ __global__ void __launch_bounds__(512) k_col_inv(Geom g, const cplx* __restrict_
   load_col<N>(v, S, g.nh, col, t, valid);
 #pragma unroll
   for (int r = 0; r < E; ++r) v[r] = cscale(v[r], g.inv_ny);
-  fft<N, true, Map>(v, buf, t, g.twy);
+  fft<N, true, decltype(map)>(v, buf, t, twy, map);
   store_col<N>(v, out, g.nh, col, t, valid);
 }
 
@@ -829,7 +1130,7 @@ __global__ void __launch_bounds__(512) k_col_apply(Geom g, const cplx* __restric
                                                     int precond, cplx* __restrict__ out) {
   COL_SETUP(N)
   cplx v[E];
-  col_combine<N>(g, v, buf, t, col, valid, P, Q);
+  col_combine<N>(g, v, buf, t, col, valid, P, Q, twy);
   if (precond) {
     const double kx = col * g.inv_Lx;
 #pragma unroll
@@ -848,7 +1149,7 @@ __global__ void __launch_bounds__(512) k_col_filter(Geom g, const cplx* __restri
   COL_SETUP(N)
   cplx v[E];
   load_col<N>(v, Sx, g.nh, col, t, valid);
-  fft<N, false, Map>(v, buf, t, g.twy);
+  fft<N, false, decltype(map)>(v, buf, t, twy, map);
   if (op == 0) {
     const double kx = col * g.inv_Lx;
 #pragma unroll
@@ -860,13 +1161,13 @@ __global__ void __launch_bounds__(512) k_col_filter(Geom g, const cplx* __restri
     // column 0 packs two real-signal spectra (kx = 0 and kx = nx/2): split
     // them with the +-ky partner, threshold each, recombine.
 #pragma unroll
-    for (int r = 0; r < E; ++r) buf[Map::at(t + r * TPF)] = v[r];
+    for (int r = 0; r < E; ++r) buf[map.at(t + r * TPF)] = v[r];
     __syncthreads();
     cplx partner[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int p = t + r * TPF;
-      partner[r] = buf[Map::at((N - p) & (N - 1))];
+      partner[r] = buf[map.at((N - p) & (N - 1))];
     }
     __syncthreads();
 #pragma unroll
@@ -885,7 +1186,7 @@ __global__ void __launch_bounds__(512) k_col_filter(Geom g, const cplx* __restri
   }
 #pragma unroll
   for (int r = 0; r < E; ++r) v[r] = cscale(v[r], g.inv_ny);
-  fft<N, true, Map>(v, buf, t, g.twy);
+  fft<N, true, decltype(map)>(v, buf, t, twy, map);
   store_col<N>(v, out, g.nh, col, t, valid);
 }
 
@@ -898,13 +1199,13 @@ __global__ void __launch_bounds__(512) k_col_tail(Geom g, const cplx* __restrict
   __shared__ double outv[1];
   cplx v[E];
   load_col<N>(v, Sx, g.nh, col, t, valid);
-  fft<N, false, Map>(v, buf, t, g.twy);
+  fft<N, false, decltype(map)>(v, buf, t, twy, map);
 #pragma unroll
-  for (int r = 0; r < E; ++r) buf[Map::at(t + r * TPF)] = v[r];
+  for (int r = 0; r < E; ++r) buf[map.at(t + r * TPF)] = v[r];
   __syncthreads();
   cplx partner[E];
 #pragma unroll
-  for (int r = 0; r < E; ++r) partner[r] = buf[Map::at((N - (t + r * TPF)) & (N - 1))];
+  for (int r = 0; r < E; ++r) partner[r] = buf[map.at((N - (t + r * TPF)) & (N - 1))];
   __syncthreads();
   double mx = 0.0;
   if (valid) {
@@ -931,11 +1232,10 @@ __global__ void __launch_bounds__(512) k_col_tail(Geom g, const cplx* __restrict
     if ((tid & 63) == 0) red[tid >> 6] = m;
   }
   block_partials_out(red, 1, partials, kinds);
-  if (last_block_arrive(&st->counter, nblocks)) {
+  if (last_block_arrive(st->ctr, nblocks)) {
     reduce_partials(partials, nblocks, 1, kinds, outv);
     if (flat_tid() == 0) {
       st->st.red[7] = outv[0] * g.inv_n;
-      st->counter = 0;
     }
   }
 }
@@ -946,10 +1246,10 @@ __global__ void __launch_bounds__(512) k_col_dy(Geom g, const double* __restrict
   COL_SETUP(N)
   cplx v[E];
   load_col<N>(v, reinterpret_cast<const cplx*>(f), g.nh, col, t, valid);
-  fft<N, false, Map>(v, buf, t, g.twy);
+  fft<N, false, decltype(map)>(v, buf, t, twy, map);
 #pragma unroll
   for (int r = 0; r < E; ++r) v[r] = mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Ly) * g.inv_ny);
-  fft<N, true, Map>(v, buf, t, g.twy);
+  fft<N, true, decltype(map)>(v, buf, t, twy, map);
   store_col<N>(v, reinterpret_cast<cplx*>(out), g.nh, col, t, valid);
 }
 
@@ -960,15 +1260,15 @@ __global__ void __launch_bounds__(512) k_col_flux(Geom g, const double* __restri
   COL_SETUP(N)
   cplx v[E], u[E];
   load_col<N>(v, reinterpret_cast<const cplx*>(qy), g.nh, col, t, valid);
-  fft<N, false, Map>(v, buf, t, g.twy);
+  load_col<N>(u, reinterpret_cast<const cplx*>(Bf), g.nh, col, t, valid);
+  fft<N, false, decltype(map)>(v, buf, t, twy, map);
 #pragma unroll
   for (int r = 0; r < E; ++r) v[r] = mul_ik(v[r], -wavenumber(t + r * TPF, N, g.inv_Ly) * g.inv_ny);
-  fft<N, true, Map>(v, buf, t, g.twy);  // -d_y qy
-  load_col<N>(u, reinterpret_cast<const cplx*>(Bf), g.nh, col, t, valid);
-  fft<N, false, Map>(u, buf, t, g.twy);
+  fft<N, true, decltype(map)>(v, buf, t, twy, map);  // -d_y qy
+  fft<N, false, decltype(map)>(u, buf, t, twy, map);
 #pragma unroll
   for (int r = 0; r < E; ++r) u[r] = mul_ik(u[r], -wavenumber(t + r * TPF, N, g.inv_Ly) * g.inv_ny);
-  fft<N, true, Map>(u, buf, t, g.twy);  // -d_y B
+  fft<N, true, decltype(map)>(u, buf, t, twy, map);  // -d_y B
   if (!valid) return;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -1012,14 +1312,20 @@ __global__ void __launch_bounds__(kUpdThreads) k_upd(Geom g, cplx* __restrict__ 
     w[e] = ok ? W[idx[e]] : make_double2(0.0, 0.0);
     wt[e] = ok ? col_weight((int)(idx[e] % g.nh)) : 0.0;
   }
-  for (int i = 0; i <= j; ++i) {
-    const double s = coef[i];
+  for (int i0 = 0; i0 <= j; i0 += 4) {
+    cplx b[4][kUpdEpt];
 #pragma unroll
-    for (int e = 0; e < kUpdEpt; ++e) {
-      if (idx[e] < total) {
-        const cplx b = V[i * vstride + idx[e]];
-        w[e].x -= s * b.x;
-        w[e].y -= s * b.y;
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < kUpdEpt; ++e)
+        b[q][e] = (i0 + q <= j && idx[e] < total) ? V[(i0 + q) * vstride + idx[e]] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double s = (i0 + q <= j) ? coef[i0 + q] : 0.0;
+#pragma unroll
+      for (int e = 0; e < kUpdEpt; ++e) {
+        w[e].x -= s * b[q][e].x;
+        w[e].y -= s * b[q][e].y;
       }
     }
   }
@@ -1029,26 +1335,34 @@ __global__ void __launch_bounds__(kUpdThreads) k_upd(Geom g, cplx* __restrict__ 
     if (idx[e] < total) W[idx[e]] = w[e];
     nr += wt[e] * (w[e].x * w[e].x + w[e].y * w[e].y);
   }
-  wave_partial(nr, red, 0);
-  for (int i = 0; i <= j; ++i) {
-    double d = 0.0;
+  // value 0: ||w1||^2; value 1 + i: <V_i, w1> (V_i re-read from cache)
+  for (int k0 = 0; k0 <= j + 1; k0 += 8) {
+    double a[8];
 #pragma unroll
-    for (int e = 0; e < kUpdEpt; ++e) {
-      if (idx[e] < total) {
-        const cplx b = V[i * vstride + idx[e]];
-        d += wt[e] * (b.x * w[e].x + b.y * w[e].y);
+    for (int q = 0; q < 8; ++q) {
+      const int k = k0 + q;
+      double d = 0.0;
+      if (k == 0) {
+        d = nr;
+      } else if (k <= j + 1) {
+#pragma unroll
+        for (int e = 0; e < kUpdEpt; ++e) {
+          if (idx[e] < total) {
+            const cplx b = V[(k - 1) * vstride + idx[e]];
+            d += wt[e] * (b.x * w[e].x + b.y * w[e].y);
+          }
+        }
       }
+      a[q] = d;
     }
-    wave_partial(d, red, i + 1);
+    wave_partials8(a, red, k0, j + 2);
   }
   block_partials_out(red, j + 2, partials, nullptr);
-  if (last_block_arrive(&st->counter, nblocks)) {
+  if (last_block_arrive(st->ctr, nblocks)) {
     reduce_partials(partials, nblocks, j + 2, nullptr, outv);
-    if (tid == 0) {
-      for (int i = 0; i <= j + 1; ++i) outv[i] *= g.inv_n;
-      gmres_finish_step(st, j, outv[0], outv + 1);
-      st->counter = 0;
-    }
+    for (int i = tid; i <= j + 1; i += kUpdThreads) outv[i] *= g.inv_n;
+    __syncthreads();
+    gmres_finish_step(st, j, outv[0], outv + 1);
   }
 }
 
@@ -1071,12 +1385,11 @@ __global__ void __launch_bounds__(256) k_field_stats(const double* __restrict__ 
     red[4 + (threadIdx.x >> 6)] = b;
   }
   block_partials_out(red, 2, partials, kinds);
-  if (last_block_arrive(&st->counter, nblocks)) {
+  if (last_block_arrive(st->ctr, nblocks)) {
     reduce_partials(partials, nblocks, 2, kinds, outv);
     if (threadIdx.x == 0) {
       st->st.stat_minh = outv[0];
       st->st.stat_nonfinite = outv[1] > 0.0 ? 1 : 0;
-      st->counter = 0;
     }
   }
 }
@@ -1099,11 +1412,22 @@ struct RowLaunch {
   static dim3 grid(int ny) { return dim3((ny / 2) / block(ny).y); }
 };
 
+// Column tiles: tc complex columns per block (a runtime choice).  At least
+// one full wave per block, at most 512 threads and 64 KB of LDS (128 KB for
+// the longest columns), and as wide as keeps >= 256 blocks in flight.
 template <int N>
 struct ColLaunch {
-  static dim3 block() { return dim3(Col<N>::TC, Col<N>::TPF); }
-  static size_t lds() { return (size_t)Col<N>::LDS * sizeof(cplx); }
-  static dim3 grid(int nh) { return dim3((nh + Col<N>::TC - 1) / Col<N>::TC); }
+  static int tc(int nh) {
+    constexpr int TPF = Col<N>::TPF;
+    const size_t ldsmax = N >= 2048 ? 131072 : 65536;
+    int t = 1;
+    while (t * TPF < 64) t *= 2;
+    while (t * 2 * TPF <= 512 && (size_t)t * 2 * N * sizeof(cplx) <= ldsmax && nh / (t * 2) >= 256) t *= 2;
+    return t;
+  }
+  static dim3 block(int nh) { return dim3(tc(nh), Col<N>::TPF); }
+  static size_t lds(int nh) { return (size_t)tc(nh) * N * sizeof(cplx); }
+  static dim3 grid(int nh) { return dim3((nh + tc(nh) - 1) / tc(nh)); }
 };
 
 static hipError_t allow_lds(const void* fn, size_t bytes) {
@@ -1122,10 +1446,10 @@ static hipError_t allow_lds(const void* fn, size_t bytes) {
 
 #define COL_LAUNCH(KERNEL, ...)                                                             \
   do {                                                                                      \
-    const size_t lb = ColLaunch<N>::lds();                                                  \
+    const size_t lb = ColLaunch<N>::lds(g.nh);                                              \
     hipError_t e_ = allow_lds(reinterpret_cast<const void*>(KERNEL), lb);                   \
     if (e_ != hipSuccess) return e_;                                                        \
-    hipLaunchKernelGGL(KERNEL, ColLaunch<N>::grid(g.nh), ColLaunch<N>::block(), lb, s, __VA_ARGS__); \
+    hipLaunchKernelGGL(KERNEL, ColLaunch<N>::grid(g.nh), ColLaunch<N>::block(g.nh), lb, s, __VA_ARGS__); \
     return hipGetLastError();                                                               \
   } while (0)
 
@@ -1317,6 +1641,103 @@ static hipError_t col_flux_n(const Geom& g, const double* dhp, const double* qy,
 hipError_t launch_col_flux(const Geom& g, const double* dhp, const double* qy, const double* B, RkStage rk, RkField fh,
                            RkField fvy, hipStream_t s) {
   DISPATCH_NY(col_flux_n, g, dhp, qy, B, rk, fh, fvy, s)
+}
+
+// Chain-parallel Arnoldi passes: usable when the chained block fits.
+template <int N>
+struct Chain {
+  static constexpr bool row_ok = 3 * Row<N>::TPF <= 1024;
+  static int rpb(int ny) {
+    int r = 64 / Row<N>::TPF;
+    if (r < 1) r = 1;
+    while (r > 1 && (r > ny / 2 || 3 * r * Row<N>::TPF > 1024)) r >>= 1;
+    return r;
+  }
+  // column tile for two chains: at least one wave per chain, <= 1024 threads,
+  // LDS <= 128 KB, >= 256 blocks when possible
+  static int tc(int nh) {
+    constexpr int TPF = Col<N>::TPF;
+    int t = 1;
+    while (t * TPF < 64) t *= 2;
+    while (2 * (t * 2) * TPF <= 1024 && (size_t)2 * (t * 2) * N * sizeof(cplx) <= 131072 && nh / (t * 2) >= 256)
+      t *= 2;
+    return t;
+  }
+  static bool col_ok(int nh) { return 2 * tc(nh) * Col<N>::TPF <= 1024 && (size_t)2 * tc(nh) * N * sizeof(cplx) <= 131072; }
+};
+
+template <int N>
+static hipError_t row_matvec3_n(const Geom& g, const cplx* E, const cplx* G, const double* h, cplx* P, cplx* Q,
+                                const GmresState* st, hipStream_t s) {
+  if constexpr (!Chain<N>::row_ok) {
+    return hipErrorNotSupported;
+  } else {
+    const int r = Chain<N>::rpb(g.ny);
+    const dim3 block(Row<N>::TPF, 3 * r);
+    const size_t lb = (size_t)3 * r * Row<N>::LDS * sizeof(cplx);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(k_row_matvec3<N>), lb);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_row_matvec3<N>, dim3((g.ny / 2) / r), block, lb, s, g, E, G, h, P, Q, st);
+    return hipGetLastError();
+  }
+}
+hipError_t launch_row_matvec3(const Geom& g, const cplx* E, const cplx* G, const double* h, cplx* P, cplx* Q,
+                              const GmresState* st, hipStream_t s) {
+  DISPATCH_NX(row_matvec3_n, g, E, G, h, P, Q, st, s)
+}
+
+template <int N>
+static bool col2_ok_n(const Geom& g) { return Chain<N>::col_ok(g.nh); }
+template <int N>
+static bool row3_ok_n(const Geom&) { return Chain<N>::row_ok; }
+bool chained_ok(const Geom& g) {
+  bool r = false, c = false;
+  switch (g.nx) {
+#define X(n) case n: r = row3_ok_n<n>(g); break;
+    SGN_SIZES(X)
+#undef X
+    default: r = false;
+  }
+  switch (g.ny) {
+#define X(n) case n: c = col2_ok_n<n>(g); break;
+    SGN_SIZES(X)
+#undef X
+    default: c = false;
+  }
+  return r && c;
+}
+
+template <int N>
+static hipError_t col_basis2_n(const Geom& g, const cplx* W, cplx* V, size_t vs, int j, const GmresState* st,
+                               cplx* Eo, cplx* Go, hipStream_t s) {
+  const int tc = Chain<N>::tc(g.nh);
+  const dim3 block(tc, Col<N>::TPF, 2);
+  const size_t lb = (size_t)2 * tc * N * sizeof(cplx);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_basis2<N>), lb);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_col_basis2<N>, dim3((g.nh + tc - 1) / tc), block, lb, s, g, W, V, vs, j, st, Eo, Go);
+  return hipGetLastError();
+}
+hipError_t launch_col_basis2(const Geom& g, const cplx* W, cplx* V, size_t vs, int j, const GmresState* st, cplx* Eo,
+                             cplx* Go, hipStream_t s) {
+  DISPATCH_NY(col_basis2_n, g, W, V, vs, j, st, Eo, Go, s)
+}
+
+template <int N>
+static hipError_t col_precond_dot2_n(const Geom& g, const cplx* P, const cplx* Q, const cplx* V, size_t vs, int j,
+                                     GmresState* st, cplx* W, double* partials, hipStream_t s) {
+  const int tc = Chain<N>::tc(g.nh);
+  const dim3 block(tc, Col<N>::TPF, 2);
+  const int nb = (g.nh + tc - 1) / tc;
+  const size_t lb = (size_t)2 * tc * N * sizeof(cplx);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_precond_dot2<N>), lb);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_col_precond_dot2<N>, dim3(nb), block, lb, s, g, P, Q, V, vs, j, st, W, partials, nb);
+  return hipGetLastError();
+}
+hipError_t launch_col_precond_dot2(const Geom& g, const cplx* P, const cplx* Q, const cplx* V, size_t vs, int j,
+                                   GmresState* st, cplx* W, double* partials, hipStream_t s) {
+  DISPATCH_NY(col_precond_dot2_n, g, P, Q, V, vs, j, st, W, partials, s)
 }
 
 int upd_blocks(const Geom& g) {

@@ -11,6 +11,7 @@ h_inf for h and 0 otherwise.  Tolerances:
     accuracy target for the FP64 path).
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -28,12 +29,23 @@ def say(msg):
     print(msg, flush=True)
 
 
-def mk(nx, ny, Lx, Ly, **kw):
+def mk(nx, ny, Lx, Ly, arnoldi=None, **kw):
+    """Context + oracle grid.  arnoldi selects the Arnoldi kernel variant
+    ("chained" or "serial"; None = the library default)."""
     cfg = sgn.config_default(nx, ny, Lx, Ly)
     for k, v in kw.items():
         setattr(cfg, k, v)
-    return sgn.sgn_init(cfg, DEV), O.Grid(O.Config(nx=nx, ny=ny, Lx=Lx, Ly=Ly,
-                                                  **{k: v for k, v in kw.items() if k in O.Config.__dataclass_fields__}))
+    old = os.environ.pop("SGN_ARNOLDI_KERNELS", None)
+    try:
+        if arnoldi is not None:
+            os.environ["SGN_ARNOLDI_KERNELS"] = arnoldi
+        ctx = sgn.sgn_init(cfg, DEV)
+    finally:
+        os.environ.pop("SGN_ARNOLDI_KERNELS", None)
+        if old is not None:
+            os.environ["SGN_ARNOLDI_KERNELS"] = old
+    return ctx, O.Grid(O.Config(nx=nx, ny=ny, Lx=Lx, Ly=Ly,
+                                **{k: v for k, v in kw.items() if k in O.Config.__dataclass_fields__}))
 
 
 def dev(a):
@@ -101,11 +113,12 @@ def test_krasny_filter(nx, ny):
     assert np.abs(host(t) - ref).max() < 1e-14
 
 
+@pytest.mark.parametrize("arnoldi", ["chained", "serial"])
 @pytest.mark.parametrize("nx,ny,restart", [(16, 16, 20), (64, 32, 20), (128, 64, 20), (256, 128, 20),
-                                           (64, 64, 3)])
-def test_elliptic_solve(nx, ny, restart):
-    say(f"elliptic solve {nx}x{ny} m={restart}")
-    ctx, g = mk(nx, ny, 1.5, 1.5, gmres_tol=1e-12, gmres_restart=restart, gmres_max_iters=400)
+                                           (64, 64, 3), (1024, 512, 20)])
+def test_elliptic_solve(nx, ny, restart, arnoldi):
+    say(f"elliptic solve {nx}x{ny} m={restart} {arnoldi}")
+    ctx, g = mk(nx, ny, 1.5, 1.5, arnoldi=arnoldi, gmres_tol=1e-12, gmres_restart=restart, gmres_max_iters=400)
     rng = np.random.default_rng(nx + ny + restart)
     h, vx, vy, s0 = random_state(rng, Box(nx, ny, 1.5, 1.5), amp_h=0.35, kmax=min(6, nx // 2 - 1, ny // 2 - 1))
     b = -(O.d_x(g, vx) + O.d_y(g, vy))
@@ -176,12 +189,13 @@ def run_gpu_rk4(ctx, h, vx, vy, s, dt, n):
     return host(th), host(tvx), host(tvy), host(ts), info
 
 
-def test_rk4_line_soliton_128x64_200_steps():
+@pytest.mark.parametrize("arnoldi", ["chained", "serial"])
+def test_rk4_line_soliton_128x64_200_steps(arnoldi):
     """The 128x64 line soliton workload: a = 0.5 on [-10pi,10pi]x[-5pi,5pi],
     dt = 0.01, 200 steps, GMRES tol 1e-10, restart 20."""
-    say("rk4 line soliton 128x64 x200")
+    say(f"rk4 line soliton 128x64 x200 {arnoldi}")
     box, (h, vx, vy, s), w = workload("line_soliton_128x64")
-    ctx, g = mk(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"], gmres_restart=w["restart"])
+    ctx, g = mk(box.nx, box.ny, box.Lx, box.Ly, arnoldi=arnoldi, gmres_tol=w["tol"], gmres_restart=w["restart"])
     gh, gvx, gvy, gs, info = run_gpu_rk4(ctx, h, vx, vy, s, w["dt"], w["steps"])
     oh, ovx, ovy, os_, oinfo = O.rk4(g, h, vx, vy, s, w["dt"], w["steps"])
     say(f"  gpu iters {info.total_iters} oracle {oinfo.total_iters}")
