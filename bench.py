@@ -34,10 +34,12 @@ WORKLOAD = "perturbed_soliton_1024x512"
 PARAMS = dict(a=0.5, eps=0.01, k=2)
 KRASNY = 1e-12
 
-# Algorithmic bytes per grid point of one launch of each timed kernel class
-# (fields read + written once each, FP64): the x-part of the elliptic
-# operator reads E, G (x-half spectra) and h and writes P, Q.
-ALGO_BYTES_PER_POINT = {"row_matvec": 5 * 8}
+# The roofline entry is for the kernel class with the largest share of device
+# time on this workload: the preconditioned y part of the operator that also
+# forms the new Krylov vector and its projections (kernel C of an Arnoldi
+# step, k_col_precond_new).  Its algorithmic bytes per launch, (j + 5) fields
+# at Arnoldi step j, are summed by the library over the launches that did work.
+DOMINANT = "col_precond_dot"
 
 
 def parse():
@@ -47,7 +49,25 @@ def parse():
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=1)
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="only run a plain device-to-device copy of MIB MiB, --steps times (calibrates the "
+                        "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
     return p.parse_args()
+
+
+def copy_calibration(mib: int, reps: int):
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"copy_mib": mib, "reps": reps, "bytes_read_per_copy": n * 8, "bytes_written_per_copy": n * 8,
+                      "gb_per_s": 2 * n * 8 * reps / dt / 1e9}), flush=True)
 
 
 def traffic_from_profile(kernel: str):
@@ -85,6 +105,9 @@ def cpu_baseline(steps: int):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration, max(args.steps, 1))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver is single-GPU.",
               file=sys.stderr)
@@ -101,7 +124,7 @@ def main():
     th, tvx, tvy, ts = (torch.from_numpy(a).to(dev).contiguous() for a in (h, vx, vy, s))
     if args.warmup > 0:
         sgn.sgn_rk4_step(ctx, th, tvx, tvy, ts, w["dt"], args.warmup)
-    dominant = "row_matvec"
+    dominant = DOMINANT
     kind = [k for k, v in sgn.KERNEL_NAMES.items() if v == dominant][0]
     sgn.sgn_kernel_timing(ctx, kind, True)
     torch.cuda.synchronize()
@@ -109,11 +132,11 @@ def main():
     info = sgn.sgn_rk4_step(ctx, th, tvx, tvy, ts, w["dt"], args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    launches, kms = sgn.sgn_kernel_time(ctx, kind)
+    launches, kms, algo_total = sgn.sgn_kernel_time(ctx, kind)  # events recorded at dispatch start/end
     sgn.sgn_kernel_timing(ctx, kind, False)
     npts = box.nx * box.ny
     value = npts * args.steps / elapsed
-    algo = ALGO_BYTES_PER_POINT[dominant] * npts
+    algo = algo_total / launches if launches else 0.0  # per launch, averaged over all timed launches
     mean_s = (kms / launches) / 1e3 if launches else float("nan")
     achieved = algo / mean_s / 1e9 if launches else None
     traffic = traffic_from_profile(dominant)
@@ -140,7 +163,8 @@ def main():
             "solves": info.solves,
         },
         "roofline": {
-            "kernel": f"k_row_op<{box.nx},0> ({dominant})",
+                    "kernel": f"k_col_precond_new<{box.ny}> (Arnoldi kernel C: M^-1 and y part of the operator, "
+                      f"new basis vector, projections)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -168,15 +168,19 @@ int sgn_krasny_filter(sgn_ctx* ctx, double* f);
  * kind, SGN_ERR_HIP. */
 enum {
   SGN_KERNEL_ROW_MATVEC = 0,     /* x part of the elliptic operator (Arnoldi step) */
-  SGN_KERNEL_COL_BASIS = 1,      /* new Krylov vector + inverse y transforms */
-  SGN_KERNEL_COL_PRECOND_DOT = 2,/* y part of the operator, M^-1, projections */
+  SGN_KERNEL_COL_BASIS = 1,      /* projection of the new vector + inverse y transforms */
+  SGN_KERNEL_COL_PRECOND_DOT = 2,/* y part of the operator, M^-1, new basis vector, projections */
   SGN_KERNEL_GS_UPDATE = 3,      /* Gram-Schmidt update, norms, Givens */
   SGN_KERNEL_ROW_FLUX = 4,       /* x part of the fluxes + RK4 combine of v_x */
   SGN_KERNEL_COL_FLUX = 5,       /* y part of the fluxes + RK4 combine of h, v_y */
   SGN_KERNEL_COUNT = 6
 };
 int sgn_kernel_timing(sgn_ctx* ctx, int32_t kind, int32_t enable);
-int sgn_kernel_time(sgn_ctx* ctx, int32_t kind, int64_t* launches, double* total_ms);
+/* algo_bytes (may be NULL): algorithmic bytes (fields read and written once
+ * each, FP64) of the timed launches that did work, i.e. excluding Arnoldi
+ * steps the device skipped after convergence; counted for the Arnoldi
+ * classes of the default (three-kernel) Arnoldi step. */
+int sgn_kernel_time(sgn_ctx* ctx, int32_t kind, int64_t* launches, double* total_ms, double* algo_bytes);
 
 /* Human-readable name of a status code, and the last error of a context. */
 const char* sgn_status_string(int status);

@@ -24,11 +24,11 @@ struct sgn_ctx {
   size_t vstride;  // complex entries per field
   sgn::GmresState* st;
   double* partials;
-  cplx *V, *W, *E, *G, *P, *Q, *R1, *R2, *SIG;
+  cplx *V, *Z, *W, *E, *G, *P, *Q, *R1, *R2, *SIG;
   double *hs, *vxs, *vys, *acc_h, *acc_vx, *acc_vy;
   sgn::GmresStatus* hstat;  // pinned host copy of the device status
-  int last_iters;
-  bool chained;  // chain-parallel Arnoldi kernels (default where the grid allows)
+  int last_iters[5];  // iterations of the previous solve per slot (RK stages 0-3, other calls 4)
+  int arnoldi;   // 0 serial 4-kernel, 1 chain-parallel 4-kernel, 2 three-kernel (default where allowed)
   std::string err;
   // kernel timing (measurement support)
   int timed_kind = -1;
@@ -36,6 +36,7 @@ struct sgn_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
   int64_t timed_launches = 0;
   double timed_ms = 0.0;
+  double timed_bytes = 0.0;  // algorithmic bytes of the timed launches that did work
 };
 
 namespace {
@@ -83,8 +84,8 @@ Layout layout(const sgn_config* c) {
   L.partials = off;
   off += align_up((size_t)pblocks * sgn::kPartialStride * sizeof(double));
   L.fields = off;
-  // V (restart + 1), W, E, G, P, Q, R1, R2, SIG, hs, vxs, vys, acc_h, acc_vx, acc_vy
-  L.nfields = c->gmres_restart + 1 + 14;
+  // V (restart + 1), Z, W, E, G, P, Q, R1, R2, SIG, hs, vxs, vys, acc_h, acc_vx, acc_vy
+  L.nfields = c->gmres_restart + 1 + 15;
   off += (size_t)L.nfields * L.field_bytes;
   L.total = off;
   return L;
@@ -112,7 +113,8 @@ hipEvent_t take_event(sgn_ctx* ctx) {
     return e;
   }
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  // no system-scope fence: the timing events are never waited on by the host
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -132,7 +134,8 @@ int drain_timing(sgn_ctx* ctx) {
   return SGN_OK;
 }
 
-// Brackets one launch with events when its kernel class is being timed.
+// When a kernel class is being timed, its next launch carries a pair of
+// events that the runtime records at the start and end of the dispatch.
 struct KernelTimer {
   sgn_ctx* ctx;
   hipEvent_t a = nullptr, b = nullptr;
@@ -140,11 +143,11 @@ struct KernelTimer {
     if (c->timed_kind != kind) return;
     a = take_event(c);
     b = take_event(c);
-    if (a && b) (void)hipEventRecord(a, c->stream);
+    if (a && b) sgn::set_launch_events(a, b);
   }
   void stop() {
+    sgn::set_launch_events(nullptr, nullptr);
     if (!a || !b) return;
-    (void)hipEventRecord(b, ctx->stream);
     ctx->ev_pending.emplace_back(a, b);
     a = b = nullptr;
     if (ctx->ev_pending.size() >= 4096) (void)drain_timing(ctx);
@@ -200,7 +203,9 @@ struct SolveResult {
 // Restarted GMRES for L_h sigma = b with the warm start held in (SIG, E, G).
 // mode 1: b = -div v from (vx, vy); mode 2: b given (passed as vx).
 // On return (SIG, E, G) hold the solution.
-int run_solve(sgn_ctx* ctx, int mode, const double* h, const double* vx, const double* vy, SolveResult* res) {
+// slot: which history predicts the iteration count (the RK stage, or 4).
+int run_solve(sgn_ctx* ctx, int mode, const double* h, const double* vx, const double* vy, SolveResult* res,
+              int slot = 4) {
   const sgn::Geom& g = ctx->g;
   hipStream_t s = ctx->stream;
   const int m = ctx->cfg.gmres_restart;
@@ -218,7 +223,12 @@ int run_solve(sgn_ctx* ctx, int mode, const double* h, const double* vx, const d
     need_b = 0;
     flags = 0;
     int j = 0;
-    int batch = ctx->last_iters + 1;
+    const bool fused = ctx->arnoldi == 2;
+    if (fused)  // kernel A of step 0: E, G of the residual
+      TIMED(SGN_KERNEL_COL_BASIS, sgn::launch_col_proj(g, ctx->W, ctx->W, ctx->V, ctx->vstride, 0, ctx->st, ctx->E,
+                                                       ctx->G, ctx->partials, s));
+    // speculative batch: one more step than this slot's previous solve needed
+    int batch = (res->restarts == 0 ? ctx->last_iters[slot] : m) + 1;
     if (batch < 1) batch = 1;
     for (;;) {
       int nrun = batch;
@@ -226,7 +236,16 @@ int run_solve(sgn_ctx* ctx, int mode, const double* h, const double* vx, const d
       if (nrun > maxit - total - j) nrun = maxit - total - j;
       if (nrun <= 0) break;  // the device sets done at the cycle or iteration cap
       for (int it = j; it < j + nrun; ++it) {
-        if (ctx->chained) {
+        if (fused) {
+          TIMED(SGN_KERNEL_ROW_MATVEC, sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, s));
+          TIMED(SGN_KERNEL_COL_PRECOND_DOT,
+                sgn::launch_col_precond_new(g, ctx->P, ctx->Q, ctx->W, ctx->V, ctx->Z, ctx->vstride, it, ctx->st,
+                                            ctx->partials, s));
+          TIMED(SGN_KERNEL_COL_BASIS, sgn::launch_col_proj(g, ctx->Z, ctx->W, ctx->V, ctx->vstride, it + 1, ctx->st,
+                                                           ctx->E, ctx->G, ctx->partials, s));
+          continue;
+        }
+        if (ctx->arnoldi == 1) {
           TIMED(SGN_KERNEL_COL_BASIS,
                 sgn::launch_col_basis2(g, ctx->W, ctx->V, ctx->vstride, it, ctx->st, ctx->E, ctx->G, s));
           TIMED(SGN_KERNEL_ROW_MATVEC, sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, s));
@@ -249,6 +268,21 @@ int run_solve(sgn_ctx* ctx, int mode, const double* h, const double* vx, const d
       batch = 2;
     }
     const sgn::GmresStatus& st = *ctx->hstat;
+    if (fused && ctx->timed_kind >= 0) {
+      // algorithmic bytes of this cycle's launches that did work: steps
+      // j < jdone (kernels B, C) and kernel A for j <= jdone (A_jdone
+      // finished the last step), unless the cycle converged at its start
+      const double fb = 8.0 * (double)g.nx * (double)g.ny;
+      const int jd = st.jdone;
+      const bool ran = !(st.done == 1 && jd == 0 && st.total_iters == total);
+      if (ran) {
+        if (ctx->timed_kind == SGN_KERNEL_ROW_MATVEC) ctx->timed_bytes += 5.0 * jd * fb;
+        if (ctx->timed_kind == SGN_KERNEL_COL_PRECOND_DOT)
+          for (int jj = 0; jj < jd; ++jj) ctx->timed_bytes += (jj + 5) * fb;
+        if (ctx->timed_kind == SGN_KERNEL_COL_BASIS)
+          for (int jj = 0; jj <= jd && jj <= m; ++jj) ctx->timed_bytes += (jj + 4) * fb;
+      }
+    }
     total = st.total_iters;
     // sigma_hat += V y, and E, G of the new sigma
     HIPCK(sgn::launch_col_update_eg(g, ctx->SIG, ctx->V, ctx->vstride, ctx->st, ctx->E, ctx->G, s));
@@ -261,7 +295,7 @@ int run_solve(sgn_ctx* ctx, int mode, const double* h, const double* vx, const d
     res->restarts += 1;
   }
   res->iters = total;
-  ctx->last_iters = total < m ? total : m;
+  ctx->last_iters[slot] = total < m ? total : m;
   return SGN_OK;
 }
 
@@ -304,11 +338,13 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
   ctx->ws = static_cast<char*>(ws);
   ctx->ws_bytes = ws_bytes;
-  ctx->last_iters = cfg->gmres_restart / 2;
-  // SGN_ARNOLDI_KERNELS=serial selects the one-chain Arnoldi kernels (a
-  // tuning and testing switch; both variants compute the same quantities)
+  for (int& li : ctx->last_iters) li = cfg->gmres_restart / 2;
+  // SGN_ARNOLDI_KERNELS = fused | chained | serial selects the Arnoldi
+  // kernels (a tuning and testing switch; all compute the same quantities)
   const char* ak = std::getenv("SGN_ARNOLDI_KERNELS");
-  ctx->chained = !(ak && std::strcmp(ak, "serial") == 0);
+  ctx->arnoldi = 2;
+  if (ak && std::strcmp(ak, "chained") == 0) ctx->arnoldi = 1;
+  if (ak && std::strcmp(ak, "serial") == 0) ctx->arnoldi = 0;
   const int nx = cfg->nx, ny = cfg->ny;
   sgn::Geom& g = ctx->g;
   g.nx = nx;
@@ -324,7 +360,7 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   g.m0 = 3.0 / (cfg->h_inf * cfg->h_inf * cfg->h_inf);
   g.m1 = 1.0 / cfg->h_inf;
   g.dA = (2.0 * M_PI * cfg->Lx / nx) * (2.0 * M_PI * cfg->Ly / ny);
-  ctx->chained = ctx->chained && sgn::chained_ok(g);
+  if (!sgn::chained_ok(g)) ctx->arnoldi = 0;
   char* base = ctx->ws;
   cplx* tw = reinterpret_cast<cplx*>(base + L.tw);
   g.twx = tw;
@@ -340,6 +376,8 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   };
   ctx->V = reinterpret_cast<cplx*>(f);
   f += (size_t)(cfg->gmres_restart + 1) * L.field_bytes;
+  ctx->Z = reinterpret_cast<cplx*>(f);
+  f += L.field_bytes;
   ctx->W = reinterpret_cast<cplx*>(next());
   ctx->E = reinterpret_cast<cplx*>(next());
   ctx->G = reinterpret_cast<cplx*>(next());
@@ -476,7 +514,7 @@ int sgn_rk4_step(sgn_ctx* ctx, double* h, double* vx, double* vy, double* sigma,
       const double* ivx = stage == 0 ? vx : ctx->vxs;
       const double* ivy = stage == 0 ? vy : ctx->vys;
       SolveResult res;
-      rc = run_solve(ctx, 1, ih, ivx, ivy, &res);
+      rc = run_solve(ctx, 1, ih, ivx, ivy, &res, stage);
       if (rc) return rc;
       total += res.iters;
       if (res.iters > maxper) maxper = res.iters;
@@ -614,19 +652,28 @@ int sgn_kernel_timing(sgn_ctx* ctx, int32_t kind, int32_t enable) {
     ctx->timed_kind = kind;
     ctx->timed_launches = 0;
     ctx->timed_ms = 0.0;
+    ctx->timed_bytes = 0.0;
+    // create the events now so that the timed launches make no runtime
+    // allocation calls (they would stall the host and starve the GPU)
+    while (ctx->ev_free.size() < 2 * 4096) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return fail(ctx, hipErrorOutOfMemory, "hipEventCreate");
+      ctx->ev_free.push_back(e);
+    }
   } else if (ctx->timed_kind == kind) {
     ctx->timed_kind = -1;
   }
   return SGN_OK;
 }
 
-int sgn_kernel_time(sgn_ctx* ctx, int32_t kind, int64_t* launches, double* total_ms) {
+int sgn_kernel_time(sgn_ctx* ctx, int32_t kind, int64_t* launches, double* total_ms, double* algo_bytes) {
   if (!ctx || !launches || !total_ms || kind < 0 || kind >= SGN_KERNEL_COUNT) return SGN_ERR_INVALID_ARG;
   int rc = drain_timing(ctx);
   if (rc) return rc;
   const bool mine = ctx->timed_kind == kind;
   *launches = mine ? ctx->timed_launches : 0;
   *total_ms = mine ? ctx->timed_ms : 0.0;
+  if (algo_bytes) *algo_bytes = mine ? ctx->timed_bytes : 0.0;
   return SGN_OK;
 }
 

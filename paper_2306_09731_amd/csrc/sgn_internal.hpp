@@ -7,7 +7,7 @@
 namespace sgn {
 
 constexpr int kMaxRestart = 64;     // largest GMRES restart length m
-constexpr int kPartialStride = 80;  // doubles per block in the reduction scratch
+constexpr int kPartialStride = 136;  // doubles per block in the reduction scratch (>= 2 (m_max + 1))
 constexpr int kMaxPartialBlocks = 4096;
 
 // Grid geometry and spectral constants, passed by value to every kernel.
@@ -52,6 +52,8 @@ struct GmresState {
   double y[kMaxRestart];
   double s[kMaxRestart + 1];   // first projection coefficients
   double s2[kMaxRestart + 1];  // second projection coefficients
+  double cproj[kMaxRestart + 1];  // Gram-corrected projection coefficients (2I - G) s
+  double G[(kMaxRestart + 1) * (kMaxRestart + 1)];  // Gram matrix <V_i, V_k> of the cycle
   // last-block ticket counters: [0] over groups, [32 (1 + g)] within group g
   // of kTicketGroup blocks (one 128-byte line each); reset by their last user
   uint32_t ctr[32 * (1 + kMaxPartialBlocks / 16)];

@@ -12,6 +12,8 @@
 // passes transform tc adjacent complex columns per block (loads of tc*16
 // contiguous bytes per row), two real columns per complex column for physical
 // data.
+#include <hip/hip_ext.h>
+
 #include "sgn_fft.hpp"
 #include "sgn_internal.hpp"
 #include "sgn_launch.hpp"
@@ -164,7 +166,29 @@ __device__ __forceinline__ void block_partials_out(const double* red, int nvals,
 // Givens rotations and a new one, update the residual estimate, test it and,
 // when the solve stops, back-substitute for y.  The serial scalar work runs
 // on one thread from LDS copies of H, cs, sn, g.
+__device__ void gmres_finish_column(GmresState* st, int j, const double* cj, double beta, const double* s2);
+
 __device__ void gmres_finish_step(GmresState* st, int j, double nrm2, const double* s2) {
+  // CGS2: H(:, j) = s + s2, beta = ||w1 - V s2|| = sqrt(||w1||^2 - |s2|^2)
+  __shared__ double colv[kMaxRestart + 1];
+  __shared__ double sh_beta;
+  const int tid = flat_tid(), nt = block_threads();
+  for (int i = tid; i <= j; i += nt) colv[i] = st->s[i] + s2[i];
+  if (tid == 0) {
+    double sum2 = 0.0;
+    for (int i = 0; i <= j; ++i) sum2 += s2[i] * s2[i];
+    const double b2 = nrm2 - sum2;
+    sh_beta = b2 > 0.0 ? sqrt(b2) : 0.0;
+  }
+  __syncthreads();
+  gmres_finish_column(st, j, colv, sh_beta, s2);
+}
+
+// Finish Arnoldi step j given its Hessenberg column cj[0..j] (in LDS) and
+// H(j+1, j) = beta: apply the previous Givens rotations and a new one,
+// update the residual estimate, test it and, when the solve stops,
+// back-substitute for y.  s2 (optional) is stored for the next basis vector.
+__device__ void gmres_finish_column(GmresState* st, int j, const double* cj, double beta, const double* s2) {
   __shared__ double sh_H[(kMaxRestart + 1) * kMaxRestart];  // column-major (m+1) x (j+1) block
   __shared__ double sh_cs[kMaxRestart], sh_sn[kMaxRestart], sh_g[kMaxRestart + 1], sh_y[kMaxRestart];
   __shared__ int sh_stop;
@@ -178,18 +202,11 @@ __device__ void gmres_finish_step(GmresState* st, int j, double nrm2, const doub
   }
   for (int i = tid; i <= j; i += nt) {
     sh_g[i] = st->gv[i];
-    sh_H[j * ld + i] = st->s[i];
+    sh_H[j * ld + i] = cj[i];
   }
   __syncthreads();
   if (tid == 0) {
-    double* col = sh_H + j * ld;  // column j, built in place
-    double sum2 = 0.0;
-    for (int i = 0; i <= j; ++i) {
-      col[i] += s2[i];
-      sum2 += s2[i] * s2[i];
-    }
-    const double b2 = nrm2 - sum2;
-    const double beta = b2 > 0.0 ? sqrt(b2) : 0.0;
+    double* col = sh_H + j * ld;  // column j, rotated in place
     col[j + 1] = beta;
     for (int i = 0; i < j; ++i) {
       const double a = col[i], b = col[i + 1];
@@ -237,7 +254,8 @@ __device__ void gmres_finish_step(GmresState* st, int j, double nrm2, const doub
   __syncthreads();
   // write back column j, the new rotation, g, s2 and (if stopping) y
   for (int i = tid; i <= j + 1; i += nt) st->H[j * ld + i] = sh_H[j * ld + i];
-  for (int i = tid; i <= j; i += nt) st->s2[i] = s2[i];
+  if (s2)
+    for (int i = tid; i <= j; i += nt) st->s2[i] = s2[i];
   if (tid == 0) {
     st->cs[j] = sh_cs[j];
     st->sn[j] = sh_sn[j];
@@ -940,6 +958,189 @@ __global__ void __launch_bounds__(1024) k_col_precond_dot2(Geom g, const cplx* _
   }
 }
 
+// Three-kernel Arnoldi step (kernels A, B, C), one pass over the basis each.
+// Orthogonalisation is classical Gram-Schmidt with the projection
+// coefficients corrected by the Gram matrix of the stored basis,
+// c = (2I - G) s with s = V^T w and G = V^T V (the first-order form of
+// G^{-1} s); this removes the loss of orthogonality that a second CGS pass
+// would remove, without a second pass over the basis.
+//   A_j: u_j = w_{j-1} - sum_{i<j} c_i V_i, ||u_j||^2
+//        (last block: finish step j-1 with H(:, j-1) = c, H(j, j-1) = ||u_j||);
+//        E = F_y^-1 u_j, G = F_y^-1 (i ky u_j)
+//   B_j: the x part of the operator on (E, G)            (k_row_matvec3)
+//   C_j: z = M^-1 F(L u_j);  V_j = u_j / beta_j,  w_j = z / beta_j;
+//        s_i = <V_i, w_j>, G_ij = <V_i, V_j>, i <= j; c = (2I - G) s.
+// The same Krylov basis, Hessenberg matrix and iterates as modified or
+// twice-iterated classical Gram-Schmidt, in exact arithmetic.
+
+// Kernel A.  win: w_{j-1} (or the residual for j = 0); u_j -> W.
+template <int N>
+__global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx* W, const cplx* __restrict__ V,
+                                                   size_t vstride, int j, GmresState* st, cplx* __restrict__ Eo,
+                                                   cplx* __restrict__ Go, double* partials, int nblocks) {
+  if (st->st.done) return;
+  COL2_SETUP(N)
+  __shared__ double coef[kMaxRestart + 1];
+  __shared__ double red[16];
+  __shared__ double outv[1];
+  const int tid = flat_tid(), nthr = block_threads();
+  for (int i = tid; i < j; i += nthr) coef[i] = st->cproj[i];
+  __syncthreads();
+  constexpr int EH = E / 2;
+  cplx u[EH];
+#pragma unroll
+  for (int q = 0; q < EH; ++q) {
+    const int p = t + (chain * EH + q) * TPF;
+    const size_t idx = (size_t)p * g.nh + col;
+    cplx x = make_double2(0.0, 0.0);
+    if (valid) {
+      x = win[idx];
+      for (int i0 = 0; i0 < j; i0 += 4) {
+        cplx b[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b[k] = i0 + k < j ? V[(i0 + k) * vstride + idx] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double cf = i0 + k < j ? coef[i0 + k] : 0.0;
+          x.x -= cf * b[k].x;
+          x.y -= cf * b[k].y;
+        }
+      }
+    }
+    u[q] = x;
+  }
+  __syncthreads();  // every read of win (which may alias W) is done
+  double nr = 0.0;
+#pragma unroll
+  for (int q = 0; q < EH; ++q) {
+    if (valid) W[(size_t)(t + (chain * EH + q) * TPF) * g.nh + col] = u[q];
+    nr += u[q].x * u[q].x + u[q].y * u[q].y;
+  }
+  wave_partial(valid ? col_weight(col) * nr : 0.0, red, 0);
+  // gather all E positions of u for this chain's transform
+  cplx* U = lds + c;  // chain 0's region, free until its transform
+#pragma unroll
+  for (int q = 0; q < EH; ++q) U[map.at(t + (chain * EH + q) * TPF)] = u[q];
+  __syncthreads();
+  cplx v[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) v[r] = U[map.at(t + r * TPF)];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < E; ++r)
+    v[r] = chain == 0 ? cscale(v[r], g.inv_ny) : mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Ly) * g.inv_ny);
+  fft<N, true, ColMap>(v, buf, t, twy, map);
+  store_col<N>(v, chain == 0 ? Eo : Go, g.nh, col, t, valid);
+  block_partials_out(red, 1, partials, nullptr);
+  if (last_block_arrive(st->ctr, nblocks)) {
+    reduce_partials(partials, nblocks, 1, nullptr, outv);
+    const double beta = sqrt(outv[0] * g.inv_n);
+    if (j == 0) {
+      if (tid == 0) st->beta = beta;
+    } else {
+      __syncthreads();
+      gmres_finish_column(st, j - 1, coef, beta, nullptr);
+    }
+  }
+}
+
+// Kernel C.  P, Q: x-part outputs of B_j for u_j; W: u_j; writes V_j and
+// w_j (into Wn), the projections s and the Gram column, then c = (2I - G) s.
+template <int N>
+__global__ void __launch_bounds__(1024) k_col_precond_new(Geom g, const cplx* __restrict__ P,
+                                                          const cplx* __restrict__ Q, const cplx* __restrict__ W,
+                                                          cplx* __restrict__ V, cplx* __restrict__ Wn, size_t vstride,
+                                                          int j, GmresState* st, double* partials, int nblocks) {
+  if (st->st.done) return;
+  COL2_SETUP(N)
+  __shared__ double red[2 * (kMaxRestart + 1) * 16];
+  __shared__ double outv[2 * (kMaxRestart + 1)];
+  const int tid = flat_tid(), nthr = block_threads();
+  const double ib = 1.0 / st->beta;
+  cplx v[E];
+  load_col<N>(v, chain == 0 ? P : Q, g.nh, col, t, valid);
+  fft<N, false, ColMap>(v, buf, t, twy, map);
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    if (chain == 1) v[r] = mul_ik(v[r], -wavenumber(t + r * TPF, N, g.inv_Ly));
+    buf[map.at(t + r * TPF)] = v[r];
+  }
+  __syncthreads();
+  const cplx* b0 = lds + c;
+  const cplx* b1 = lds + blockDim.x * N + c;
+  const double kx = col * g.inv_Lx;
+  constexpr int EH = E / 2;
+  cplx vj[EH], wj[EH];
+#pragma unroll
+  for (int q = 0; q < EH; ++q) {
+    const int p = t + (chain * EH + q) * TPF;
+    const size_t idx = (size_t)p * g.nh + col;
+    const cplx z = cscale(cadd(b0[map.at(p)], b1[map.at(p)]), inv_symbol(g, kx, wavenumber(p, N, g.inv_Ly)));
+    vj[q] = make_double2(0.0, 0.0);
+    wj[q] = make_double2(0.0, 0.0);
+    if (valid) {
+      vj[q] = cscale(W[idx], ib);
+      wj[q] = cscale(z, ib);
+      V[j * vstride + idx] = vj[q];
+      Wn[idx] = wj[q];
+    }
+  }
+  // values 2i: <V_i, w_j>, 2i+1: <V_i, V_j>, i <= j (one pass over V)
+  const double wt = valid ? col_weight(col) : 0.0;
+  const int nv = 2 * (j + 1);
+  double dsj = 0.0, dgj = 0.0;  // the i = j terms, from registers
+#pragma unroll
+  for (int q = 0; q < EH; ++q) {
+    dsj += vj[q].x * wj[q].x + vj[q].y * wj[q].y;
+    dgj += vj[q].x * vj[q].x + vj[q].y * vj[q].y;
+  }
+  size_t pidx[EH];
+#pragma unroll
+  for (int q = 0; q < EH; ++q) pidx[q] = (size_t)(t + (chain * EH + q) * TPF) * g.nh + col;
+  for (int i0 = 0; i0 <= j; i0 += 4) {
+    double a[8];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = i0 + k;
+      double ds = 0.0, dg = 0.0;
+      if (valid && i < j) {
+#pragma unroll
+        for (int q = 0; q < EH; ++q) {
+          const cplx b = V[i * vstride + pidx[q]];
+          ds += b.x * wj[q].x + b.y * wj[q].y;
+          dg += b.x * vj[q].x + b.y * vj[q].y;
+        }
+      } else if (i == j) {
+        ds = dsj;
+        dg = dgj;
+      }
+      a[2 * k] = wt * ds;
+      a[2 * k + 1] = wt * dg;
+    }
+    wave_partials8(a, red, 2 * i0, nv);
+  }
+  block_partials_out(red, nv, partials, nullptr);
+  if (last_block_arrive(st->ctr, nblocks)) {
+    reduce_partials(partials, nblocks, nv, nullptr, outv);
+    constexpr int ld = kMaxRestart + 1;
+    for (int i = tid; i <= j; i += nthr) {
+      outv[2 * i] *= g.inv_n;
+      outv[2 * i + 1] *= g.inv_n;
+      st->s[i] = outv[2 * i];
+      st->G[i * ld + j] = outv[2 * i + 1];
+      st->G[j * ld + i] = outv[2 * i + 1];
+    }
+    __syncthreads();
+    // c_i = 2 s_i - sum_k G_ik s_k, with column j of G from this reduction
+    for (int i = tid; i <= j; i += nthr) {
+      double acc = 0.0;
+      for (int k = 0; k < j; ++k) acc += st->G[i * ld + k] * outv[2 * k];
+      acc += outv[2 * i + 1] * outv[2 * j];  // G_ij s_j
+      st->cproj[i] = 2.0 * outv[2 * i] - acc;
+    }
+  }
+}
+
 // sigma_hat += sum_{i<k} y_i V_i (or 0 when b == 0), then E, G of sigma_hat.
 template <int N>
 __global__ void __launch_bounds__(512) k_col_update_eg(Geom g, cplx* __restrict__ SIG, const cplx* __restrict__ V,
@@ -1395,6 +1596,28 @@ __global__ void __launch_bounds__(256) k_field_stats(const double* __restrict__ 
 }
 
 // ----------------------------------------------------------------------------
+// Launch helper: the next launch can carry a pair of HIP events that the
+// runtime records at the start and end of that dispatch (kernel timing).
+// ----------------------------------------------------------------------------
+
+static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+  t_ev_start = start;
+  t_ev_stop = stop;
+}
+
+template <typename K, typename... Args>
+static void launch(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, Args... args) {
+  if (t_ev_start) {
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, t_ev_start, t_ev_stop, 0u, args...);
+    t_ev_start = t_ev_stop = nullptr;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+  }
+}
+
+// ----------------------------------------------------------------------------
 // Host launchers (dispatch on the transform length)
 // ----------------------------------------------------------------------------
 
@@ -1440,7 +1663,7 @@ static hipError_t allow_lds(const void* fn, size_t bytes) {
     const size_t lb = RowLaunch<N>::lds(g.ny);                                              \
     hipError_t e_ = allow_lds(reinterpret_cast<const void*>(KERNEL), lb);                   \
     if (e_ != hipSuccess) return e_;                                                        \
-    hipLaunchKernelGGL(KERNEL, RowLaunch<N>::grid(g.ny), RowLaunch<N>::block(g.ny), lb, s, __VA_ARGS__); \
+    launch(KERNEL, RowLaunch<N>::grid(g.ny), RowLaunch<N>::block(g.ny), lb, s, __VA_ARGS__); \
     return hipGetLastError();                                                               \
   } while (0)
 
@@ -1449,7 +1672,7 @@ static hipError_t allow_lds(const void* fn, size_t bytes) {
     const size_t lb = ColLaunch<N>::lds(g.nh);                                              \
     hipError_t e_ = allow_lds(reinterpret_cast<const void*>(KERNEL), lb);                   \
     if (e_ != hipSuccess) return e_;                                                        \
-    hipLaunchKernelGGL(KERNEL, ColLaunch<N>::grid(g.nh), ColLaunch<N>::block(g.nh), lb, s, __VA_ARGS__); \
+    launch(KERNEL, ColLaunch<N>::grid(g.nh), ColLaunch<N>::block(g.nh), lb, s, __VA_ARGS__); \
     return hipGetLastError();                                                               \
   } while (0)
 
@@ -1537,7 +1760,7 @@ static hipError_t row_invariants_n(const Geom& g, const cplx* E, const cplx* G, 
   const size_t lb = (size_t)rpb * Row<N>::LDS * sizeof(cplx);
   hipError_t e = allow_lds(reinterpret_cast<const void*>(k_row_invariants<N>), lb);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_row_invariants<N>, dim3(nb), block, lb, s, g, E, G, h, vx, vy, dyvx, partials, st, nb);
+  launch(k_row_invariants<N>, dim3(nb), block, lb, s, g, E, G, h, vx, vy, dyvx, partials, st, nb);
   return hipGetLastError();
 }
 hipError_t launch_row_invariants(const Geom& g, const cplx* E, const cplx* G, const double* h, const double* vx,
@@ -1677,7 +1900,7 @@ static hipError_t row_matvec3_n(const Geom& g, const cplx* E, const cplx* G, con
     const size_t lb = (size_t)3 * r * Row<N>::LDS * sizeof(cplx);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(k_row_matvec3<N>), lb);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_row_matvec3<N>, dim3((g.ny / 2) / r), block, lb, s, g, E, G, h, P, Q, st);
+    launch(k_row_matvec3<N>, dim3((g.ny / 2) / r), block, lb, s, g, E, G, h, P, Q, st);
     return hipGetLastError();
   }
 }
@@ -1715,7 +1938,7 @@ static hipError_t col_basis2_n(const Geom& g, const cplx* W, cplx* V, size_t vs,
   const size_t lb = (size_t)2 * tc * N * sizeof(cplx);
   hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_basis2<N>), lb);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_col_basis2<N>, dim3((g.nh + tc - 1) / tc), block, lb, s, g, W, V, vs, j, st, Eo, Go);
+  launch(k_col_basis2<N>, dim3((g.nh + tc - 1) / tc), block, lb, s, g, W, V, vs, j, st, Eo, Go);
   return hipGetLastError();
 }
 hipError_t launch_col_basis2(const Geom& g, const cplx* W, cplx* V, size_t vs, int j, const GmresState* st, cplx* Eo,
@@ -1732,12 +1955,46 @@ static hipError_t col_precond_dot2_n(const Geom& g, const cplx* P, const cplx* Q
   const size_t lb = (size_t)2 * tc * N * sizeof(cplx);
   hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_precond_dot2<N>), lb);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_col_precond_dot2<N>, dim3(nb), block, lb, s, g, P, Q, V, vs, j, st, W, partials, nb);
+  launch(k_col_precond_dot2<N>, dim3(nb), block, lb, s, g, P, Q, V, vs, j, st, W, partials, nb);
   return hipGetLastError();
 }
 hipError_t launch_col_precond_dot2(const Geom& g, const cplx* P, const cplx* Q, const cplx* V, size_t vs, int j,
                                    GmresState* st, cplx* W, double* partials, hipStream_t s) {
   DISPATCH_NY(col_precond_dot2_n, g, P, Q, V, vs, j, st, W, partials, s)
+}
+
+template <int N>
+static hipError_t col_proj_n(const Geom& g, const cplx* win, cplx* W, const cplx* V, size_t vs, int j, GmresState* st,
+                             cplx* Eo, cplx* Go, double* partials, hipStream_t s) {
+  const int tc = Chain<N>::tc(g.nh);
+  const dim3 block(tc, Col<N>::TPF, 2);
+  const int nb = (g.nh + tc - 1) / tc;
+  const size_t lb = (size_t)2 * tc * N * sizeof(cplx);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_proj<N>), lb);
+  if (e != hipSuccess) return e;
+  launch(k_col_proj<N>, dim3(nb), block, lb, s, g, win, W, V, vs, j, st, Eo, Go, partials, nb);
+  return hipGetLastError();
+}
+hipError_t launch_col_proj(const Geom& g, const cplx* win, cplx* W, const cplx* V, size_t vs, int j, GmresState* st,
+                           cplx* Eo, cplx* Go, double* partials, hipStream_t s) {
+  DISPATCH_NY(col_proj_n, g, win, W, V, vs, j, st, Eo, Go, partials, s)
+}
+
+template <int N>
+static hipError_t col_precond_new_n(const Geom& g, const cplx* P, const cplx* Q, const cplx* W, cplx* V, cplx* Z,
+                                    size_t vs, int j, GmresState* st, double* partials, hipStream_t s) {
+  const int tc = Chain<N>::tc(g.nh);
+  const dim3 block(tc, Col<N>::TPF, 2);
+  const int nb = (g.nh + tc - 1) / tc;
+  const size_t lb = (size_t)2 * tc * N * sizeof(cplx);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_precond_new<N>), lb);
+  if (e != hipSuccess) return e;
+  launch(k_col_precond_new<N>, dim3(nb), block, lb, s, g, P, Q, W, V, Z, vs, j, st, partials, nb);
+  return hipGetLastError();
+}
+hipError_t launch_col_precond_new(const Geom& g, const cplx* P, const cplx* Q, const cplx* W, cplx* V, cplx* Z,
+                                  size_t vs, int j, GmresState* st, double* partials, hipStream_t s) {
+  DISPATCH_NY(col_precond_new_n, g, P, Q, W, V, Z, vs, j, st, partials, s)
 }
 
 int upd_blocks(const Geom& g) {
@@ -1748,7 +2005,7 @@ int upd_blocks(const Geom& g) {
 hipError_t launch_upd(const Geom& g, cplx* W, const cplx* V, size_t vs, int j, GmresState* st, double* partials,
                       hipStream_t s) {
   const int nb = upd_blocks(g);
-  hipLaunchKernelGGL(k_upd, dim3(nb), dim3(kUpdThreads), 0, s, g, W, V, vs, j, st, partials, nb);
+  launch(k_upd, dim3(nb), dim3(kUpdThreads), 0, s, g, W, V, vs, j, st, partials, nb);
   return hipGetLastError();
 }
 
@@ -1756,7 +2013,7 @@ hipError_t launch_field_stats(const double* h, const double* vx, const double* v
                               double* partials, hipStream_t s) {
   int nb = (int)((n + 255) / 256);
   if (nb > 1024) nb = 1024;
-  hipLaunchKernelGGL(k_field_stats, dim3(nb), dim3(256), 0, s, h, vx, vy, n, st, partials, nb);
+  launch(k_field_stats, dim3(nb), dim3(256), 0, s, h, vx, vy, n, st, partials, nb);
   return hipGetLastError();
 }
 

@@ -39,6 +39,8 @@ hipError_t launch_upd(const Geom& g, cplx* W, const cplx* V, size_t vs, int j, G
 hipError_t launch_field_stats(const double* h, const double* vx, const double* vy, size_t n, GmresState* st,
                               double* partials, hipStream_t s);
 int max_partial_blocks(const Geom& g);
+// The next kernel launch records these events at its start and end (null: none).
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
 // chain-parallel Arnoldi passes (same results as row_op mode 0, col_basis_eg,
 // col_precond_dot); chained_ok tells whether this grid can use them
 bool chained_ok(const Geom& g);
@@ -46,6 +48,10 @@ hipError_t launch_row_matvec3(const Geom& g, const cplx* E, const cplx* G, const
                               const GmresState* st, hipStream_t s);
 hipError_t launch_col_basis2(const Geom& g, const cplx* W, cplx* V, size_t vs, int j, const GmresState* st, cplx* Eo,
                              cplx* Go, hipStream_t s);
+hipError_t launch_col_proj(const Geom& g, const cplx* win, cplx* W, const cplx* V, size_t vs, int j, GmresState* st,
+                           cplx* Eo, cplx* Go, double* partials, hipStream_t s);
+hipError_t launch_col_precond_new(const Geom& g, const cplx* P, const cplx* Q, const cplx* W, cplx* V, cplx* Z,
+                                  size_t vs, int j, GmresState* st, double* partials, hipStream_t s);
 hipError_t launch_col_precond_dot2(const Geom& g, const cplx* P, const cplx* Q, const cplx* V, size_t vs, int j,
                                    GmresState* st, cplx* W, double* partials, hipStream_t s);
 

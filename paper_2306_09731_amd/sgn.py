@@ -87,7 +87,7 @@ _SIGNATURES = {
     "sgn_krasny_filter": (ctypes.c_int, [_VP, _VP]),
     "sgn_kernel_timing": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "sgn_kernel_time": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
-                                       ctypes.POINTER(ctypes.c_double)]),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "sgn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sgn_last_error": (ctypes.c_char_p, [_VP]),
 }
@@ -257,8 +257,11 @@ def sgn_kernel_timing(ctx: Context, kind: int, enable: bool):
 
 
 def sgn_kernel_time(ctx: Context, kind: int):
-    """(launches, total_ms) of the timed kernel class since timing was enabled."""
+    """(launches, total_ms, algo_bytes) of the timed kernel class since timing
+    was enabled; algo_bytes counts the launches that did work."""
     n = ctypes.c_int64()
     ms = ctypes.c_double()
-    _check(ctx, load_library().sgn_kernel_time(ctx.handle, int(kind), ctypes.byref(n), ctypes.byref(ms)))
-    return int(n.value), float(ms.value)
+    b = ctypes.c_double()
+    _check(ctx, load_library().sgn_kernel_time(ctx.handle, int(kind), ctypes.byref(n), ctypes.byref(ms),
+                                               ctypes.byref(b)))
+    return int(n.value), float(ms.value), float(b.value)

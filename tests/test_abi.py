@@ -75,6 +75,7 @@ def test_workspace_size_scales_with_grid_and_restart():
     b = sgn.sgn_workspace_bytes(sgn.config_default(256, 64, 10.0, 5.0))
     c = sgn.sgn_workspace_bytes(sgn.config_default(128, 64, 10.0, 5.0, gmres_restart=40))
     field = 128 * 64 * 8
+    # Krylov basis: restart + 1 fields, plus 15 others
     assert a >= 36 * field and b > a and c - a == 20 * field
 
 

@@ -31,7 +31,7 @@ def say(msg):
 
 def mk(nx, ny, Lx, Ly, arnoldi=None, **kw):
     """Context + oracle grid.  arnoldi selects the Arnoldi kernel variant
-    ("chained" or "serial"; None = the library default)."""
+    ("fused", "chained" or "serial"; None = the library default)."""
     cfg = sgn.config_default(nx, ny, Lx, Ly)
     for k, v in kw.items():
         setattr(cfg, k, v)
@@ -113,7 +113,7 @@ def test_krasny_filter(nx, ny):
     assert np.abs(host(t) - ref).max() < 1e-14
 
 
-@pytest.mark.parametrize("arnoldi", ["chained", "serial"])
+@pytest.mark.parametrize("arnoldi", ["fused", "chained", "serial"])
 @pytest.mark.parametrize("nx,ny,restart", [(16, 16, 20), (64, 32, 20), (128, 64, 20), (256, 128, 20),
                                            (64, 64, 3), (1024, 512, 20)])
 def test_elliptic_solve(nx, ny, restart, arnoldi):
@@ -189,7 +189,7 @@ def run_gpu_rk4(ctx, h, vx, vy, s, dt, n):
     return host(th), host(tvx), host(tvy), host(ts), info
 
 
-@pytest.mark.parametrize("arnoldi", ["chained", "serial"])
+@pytest.mark.parametrize("arnoldi", ["fused", "chained", "serial"])
 def test_rk4_line_soliton_128x64_200_steps(arnoldi):
     """The 128x64 line soliton workload: a = 0.5 on [-10pi,10pi]x[-5pi,5pi],
     dt = 0.01, 200 steps, GMRES tol 1e-10, restart 20."""
