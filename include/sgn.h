@@ -69,6 +69,12 @@ typedef struct sgn_config {
   int32_t batch;           /* 1 */
   double krasny;           /* Krasny threshold on |DFT| / (nx ny) [0 = off; the paper uses 1e-12] */
   double invariants_tol;   /* GMRES tolerance of the sigma solve in sgn_invariants [1e-13] */
+  int32_t dealias;         /* [0] 1: after every RK4 step also zero the modes with 3 |m_x| > nx or
+                              3 |m_y| > ny (Orszag's two-thirds rule).  Not part of the paper's
+                              scheme, which filters with the Krasny threshold only; it suppresses
+                              the grid-scale aliasing growth that long runs of transversally
+                              perturbed solitons develop with the Krasny filter alone. */
+  int32_t reserved;        /* must be 0 */
 } sgn_config;
 
 typedef struct sgn_ctx sgn_ctx;
@@ -151,7 +157,8 @@ int sgn_invariants(sgn_ctx* ctx, const double* h, const double* vx, const double
  * sgn_derivative: out = d f / dx (axis 0) or d f / dy (axis 1) (Section 3: i k).
  * sgn_apply_operator: out = L_h s (eq. (3)), or M^-1 L_h s if precondition != 0.
  * sgn_apply_precond: out = M^-1 r (Section 3).
- * sgn_krasny_filter: Krasny filter of f in place with threshold cfg.krasny (Section 3).
+ * sgn_krasny_filter: the per-step spectral filter of f in place: Krasny threshold
+ *   cfg.krasny (Section 3; 0 = none) and, if cfg.dealias, the two-thirds rule.
  * All fields are device pointers; out may not alias an input. */
 int sgn_derivative(sgn_ctx* ctx, int32_t axis, const double* f, double* out);
 int sgn_apply_operator(sgn_ctx* ctx, const double* h, const double* s, double* out, int32_t precondition);

@@ -25,6 +25,9 @@ Readings of the paper used here (where it is silent or garbled):
     the previous evaluation (Section 3);
   * Krasny filter: normalised 2D DFT coefficients |F f| / N below the
     threshold are set to zero in h, v_x, v_y once per completed RK4 step;
+  * optional two-thirds rule (Config.dealias, off by default; Orszag's
+    dealiasing, not part of the paper's scheme): in the same place, modes
+    with 3 |m_x| > nx or 3 |m_y| > ny are set to zero as well;
   * h-equation written as h_t = -D.(h v - D sigma), which equals
     -D.(h v) + Laplacian(sigma) when the Laplacian is D.D (eq. (1)).
 Parity pins for every function live in tests/test_oracle_pins.py.
@@ -54,6 +57,7 @@ class Config:
     gmres_max_iters: int = 200
     krasny: float = 0.0          # 0 disables the filter
     invariants_tol: float = 1e-13
+    dealias: bool = False        # two-thirds rule after each step (not in the paper)
 
 
 class Grid:
@@ -268,6 +272,19 @@ def krasny(grid: Grid, f: np.ndarray, threshold: float) -> np.ndarray:
     return np.real(np.fft.ifft2(c * n))
 
 
+def two_thirds(grid: Grid, f: np.ndarray) -> np.ndarray:
+    """Orszag's two-thirds rule: keep the DFT modes with 3|m_x| <= nx and
+    3|m_y| <= ny (signed indices m in [-N/2, N/2), the Nyquist index included
+    in the discarded set), set the rest to zero."""
+    ny, nx = f.shape
+    mx = np.abs(np.fft.fftfreq(nx) * nx)
+    my = np.abs(np.fft.fftfreq(ny) * ny)
+    keep = (3 * my[:, None] <= ny) & (3 * mx[None, :] <= nx)
+    c = np.fft.fft2(f)
+    c[~keep] = 0.0
+    return np.real(np.fft.ifft2(c))
+
+
 @dataclasses.dataclass
 class StepInfo:
     total_iters: int = 0
@@ -302,6 +319,8 @@ def rk4_step(grid: Grid, h, vx, vy, sigma, dt: float, info: StepInfo | None = No
                 for a, q1, q2, q3, q4 in zip(y0, k1, k2, k3, k4))
     if grid.cfg.krasny > 0.0:
         out = tuple(krasny(grid, f, grid.cfg.krasny) for f in out)
+    if grid.cfg.dealias:
+        out = tuple(two_thirds(grid, f) for f in out)
     info.min_h = float(np.min(out[0]))
     return out[0], out[1], out[2], s4
 

@@ -50,6 +50,8 @@ int check_config(const sgn_config* c) {
   if (!(std::isfinite(c->gmres_tol) && c->gmres_tol > 0)) return SGN_ERR_INVALID_ARG;
   if (!(std::isfinite(c->invariants_tol) && c->invariants_tol > 0)) return SGN_ERR_INVALID_ARG;
   if (!(std::isfinite(c->krasny) && c->krasny >= 0)) return SGN_ERR_INVALID_ARG;
+  if (c->dealias != 0 && c->dealias != 1) return SGN_ERR_INVALID_ARG;
+  if (c->reserved != 0) return SGN_ERR_INVALID_ARG;
   if (c->gmres_max_iters < 1) return SGN_ERR_INVALID_ARG;
   if (c->gmres_restart < 1) return SGN_ERR_INVALID_ARG;
   if (c->gmres_restart > sgn::kMaxRestart) return SGN_ERR_UNSUPPORTED;
@@ -60,6 +62,11 @@ int check_config(const sgn_config* c) {
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// The spectral filter applied to h, v_x, v_y after every RK4 step: the Krasny
+// threshold (Section 3) and, if enabled, the two-thirds rule.
+bool step_filter_on(const sgn_config& c) { return c.krasny > 0.0 || c.dealias != 0; }
+int step_filter_op(const sgn_config& c) { return c.dealias ? 2 : 1; }
 
 struct Layout {
   size_t tw, st, partials, fields, total;
@@ -540,11 +547,11 @@ int sgn_rk4_step(sgn_ctx* ctx, double* h, double* vx, double* vy, double* sigma,
       TIMED(SGN_KERNEL_ROW_FLUX, sgn::launch_row_flux(g, ctx->E, ctx->G, ih, ivx, ivy, dhp, qy, B, rk, fvx, s));
       TIMED(SGN_KERNEL_COL_FLUX, sgn::launch_col_flux(g, dhp, qy, B, rk, fh, fvy, s));
     }
-    if (ctx->cfg.krasny > 0.0) {
+    if (step_filter_on(ctx->cfg)) {
       double* fs[3] = {h, vx, vy};
       for (double* f : fs) {
         HIPCK(sgn::launch_row_r2c(g, f, ctx->P, s));
-        HIPCK(sgn::launch_col_filter(g, ctx->P, 1, ctx->cfg.krasny, ctx->Q, s));
+        HIPCK(sgn::launch_col_filter(g, ctx->P, step_filter_op(ctx->cfg), ctx->cfg.krasny, ctx->Q, s));
         HIPCK(sgn::launch_row_c2r(g, ctx->Q, f, s));
       }
     }
@@ -638,7 +645,7 @@ int sgn_krasny_filter(sgn_ctx* ctx, double* f) {
   if (!ctx || !aligned(f)) return SGN_ERR_INVALID_ARG;
   const sgn::Geom& g = ctx->g;
   HIPCK(sgn::launch_row_r2c(g, f, ctx->E, ctx->stream));
-  HIPCK(sgn::launch_col_filter(g, ctx->E, 1, ctx->cfg.krasny, ctx->P, ctx->stream));
+  HIPCK(sgn::launch_col_filter(g, ctx->E, step_filter_op(ctx->cfg), ctx->cfg.krasny, ctx->P, ctx->stream));
   HIPCK(sgn::launch_row_c2r(g, ctx->P, f, ctx->stream));
   HIPCK(hipStreamSynchronize(ctx->stream));
   return SGN_OK;

@@ -1344,6 +1344,8 @@ __global__ void __launch_bounds__(512) k_col_apply(Geom g, const cplx* __restric
 // x-half spectra -> multiplied by a 2D symbol -> x-half spectra.
 //   op 0: M^-1 (preconditioner)
 //   op 1: Krasny filter, zero modes with |X| / (nx ny) < thr
+//   op 2: op 1, and also zero modes with 3 |m_x| > nx or 3 |m_y| > ny (the
+//         two-thirds rule of Orszag, an option beyond the paper's scheme)
 template <int N>
 __global__ void __launch_bounds__(512) k_col_filter(Geom g, const cplx* __restrict__ Sx, int op, double thr,
                                                      cplx* __restrict__ out) {
@@ -1359,6 +1361,10 @@ __global__ void __launch_bounds__(512) k_col_filter(Geom g, const cplx* __restri
   } else {
     const double T = thr * (double)g.nx * (double)g.ny;
     const double T2 = T * T;
+    const bool dealias = op == 2;
+    // x index of this column (column 0 holds m_x = 0 and m_x = nx/2; the
+    // latter is always outside the two-thirds band).
+    const bool keep_x = !dealias || 3 * col <= g.nx;
     // column 0 packs two real-signal spectra (kx = 0 and kx = nx/2): split
     // them with the +-ky partner, threshold each, recombine.
 #pragma unroll
@@ -1373,15 +1379,18 @@ __global__ void __launch_bounds__(512) k_col_filter(Geom g, const cplx* __restri
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < E; ++r) {
+      const int p = t + r * TPF;
+      const int my = p <= N / 2 ? p : N - p;
+      const bool keep_y = !dealias || 3 * my <= N;
       if (col == 0) {
         const cplx z = v[r], zc = partner[r];
         cplx a = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));   // kx = 0 mode
         cplx b = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));  // kx = nx/2 mode
-        if (a.x * a.x + a.y * a.y < T2) a = make_double2(0.0, 0.0);
-        if (b.x * b.x + b.y * b.y < T2) b = make_double2(0.0, 0.0);
+        if (!keep_y || a.x * a.x + a.y * a.y < T2) a = make_double2(0.0, 0.0);
+        if (dealias || b.x * b.x + b.y * b.y < T2) b = make_double2(0.0, 0.0);
         v[r] = make_double2(a.x - b.y, a.y + b.x);
       } else {
-        if (v[r].x * v[r].x + v[r].y * v[r].y < T2) v[r] = make_double2(0.0, 0.0);
+        if (!(keep_x && keep_y) || v[r].x * v[r].x + v[r].y * v[r].y < T2) v[r] = make_double2(0.0, 0.0);
       }
     }
   }

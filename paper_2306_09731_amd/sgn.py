@@ -42,6 +42,7 @@ class sgn_config(ctypes.Structure):
         ("gmres_max_iters", ctypes.c_int32), ("batch", ctypes.c_int32),
         ("krasny", ctypes.c_double),
         ("invariants_tol", ctypes.c_double),
+        ("dealias", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 

@@ -14,6 +14,8 @@ from .generators import (  # noqa: F401
     soliton_profile,
     line_soliton,
     perturbed_line_soliton,
+    deformed_line_soliton,
+    soliton_plus_gaussian,
     gaussian_hump,
     crossing_solitons,
     random_smooth_field,

@@ -149,6 +149,38 @@ def perturbed_line_soliton(box: Box, a: float, eps: float, k: int, x0: float = -
     return h, vx, np.zeros_like(h), np.zeros_like(h)
 
 
+def deformed_line_soliton(box: Box, c: float = 1.7, x0: float = -10.0, amp: float = 0.1,
+                          h_inf: float = 1.0, g: float = 1.0):
+    """Deformed line solitary wave (Section 4.1, eq. (soldef)): the profile in
+    x - x0 - amp cos(y); v_x = c - (c/h)(1 + (h^2)_xx / 6) with analytic x
+    derivatives, v_y = 0."""
+    p = soliton_params(c=c, h_inf=h_inf, g=g)
+    X, Y = box.mesh()
+    prof = soliton_profile(_periodic_offset(X - x0 - amp * np.cos(Y), box.Lx), p)
+    h = prof["h"]
+    hh_xx = 2.0 * (prof["h1"] ** 2 + h * prof["h2"])
+    vx = c - (c * h_inf / h) * (1.0 + hh_xx / 6.0)
+    return h, vx, np.zeros_like(h), np.zeros_like(h)
+
+
+def soliton_plus_gaussian(box: Box, c: float = 1.7, x0: float = -20.0, sign: float = 1.0, amp: float = 0.1,
+                          h_inf: float = 1.0, g: float = 1.0):
+    """Line solitary wave with a localized Gaussian perturbation (Section 4.2,
+    eq. (solgauss)): h = h_c(x - x0) +- amp exp(-(x - x0)^2 - y^2), v_x from
+    the perturbed h as in eq. (soldef) with analytic derivatives, v_y = 0."""
+    p = soliton_params(c=c, h_inf=h_inf, g=g)
+    X, Y = box.mesh()
+    xi = _periodic_offset(X - x0, box.Lx)
+    prof = soliton_profile(xi, p)
+    e = amp * sign * np.exp(-xi * xi - Y * Y)
+    h = prof["h"] + e
+    h1 = prof["h1"] - 2.0 * xi * e
+    h2 = prof["h2"] + (4.0 * xi * xi - 2.0) * e
+    hh_xx = 2.0 * (h1 * h1 + h * h2)
+    vx = c - (c * h_inf / h) * (1.0 + hh_xx / 6.0)
+    return h, vx, np.zeros_like(h), np.zeros_like(h)
+
+
 def gaussian_hump(box: Box, alpha: float = 0.5, h_inf: float = 1.0):
     """Localized Gaussian h = h_inf + alpha exp(-x^2 - y^2), v = 0 (Section 6,
     eq. (gauss), read with the background depth h_inf added)."""
@@ -160,13 +192,14 @@ def gaussian_hump(box: Box, alpha: float = 0.5, h_inf: float = 1.0):
 
 def crossing_solitons(box: Box, c: float = 1.7, h_inf: float = 1.0, g: float = 1.0):
     """Two crossing line solitary waves, one along x and one along y
-    (Section 5, eq. (cross)), with the far field kept at h_inf:
-    h = h_c(x) + h_c(y) - h_inf, v_x from the x-wave, v_y from the y-wave."""
+    (Section 5, eq. (cross)), summed as the paper writes them:
+    h = h_c(x) + h_c(y), so the far field is 2 h_inf; v_x is the x-wave's
+    velocity and v_y the y-wave's, each built from its own h_c."""
     p = soliton_params(c=c, h_inf=h_inf, g=g)
     X, Y = box.mesh()
     px = soliton_profile(X, p)
     py = soliton_profile(Y, p)
-    h = px["h"] + py["h"] - h_inf
+    h = px["h"] + py["h"]
     return h, px["v"], py["v"], np.zeros_like(h)
 
 

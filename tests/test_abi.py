@@ -40,7 +40,8 @@ def test_config_default_and_struct_layout():
     assert (cfg.nx, cfg.ny, cfg.Lx, cfg.Ly) == (128, 64, 10.0, 5.0)
     assert cfg.g == 1.0 and cfg.h_inf == 1.0 and cfg.gmres_restart == 20
     assert cfg.gmres_tol == 1e-10 and cfg.gmres_max_iters == 200 and cfg.batch == 1
-    assert ctypes.sizeof(sgn.sgn_config) == 80
+    assert cfg.krasny == 0.0 and cfg.dealias == 0 and cfg.reserved == 0
+    assert ctypes.sizeof(sgn.sgn_config) == 88
 
 
 @pytest.mark.parametrize("field,value", [
@@ -58,7 +59,7 @@ def test_workspace_bytes_rejects_unsupported(field, value):
 
 @pytest.mark.parametrize("field,value", [
     ("Lx", 0.0), ("Ly", -1.0), ("gmres_tol", 0.0), ("gmres_max_iters", 0), ("h_inf", 0.0),
-    ("krasny", -1.0), ("gmres_restart", 0), ("Lx", float("nan")),
+    ("krasny", -1.0), ("gmres_restart", 0), ("Lx", float("nan")), ("dealias", 2), ("reserved", 1),
 ])
 def test_invalid_config(field, value):
     cfg = sgn.config_default(128, 64, 10.0, 5.0)

@@ -113,6 +113,44 @@ def test_krasny_filter(nx, ny):
     assert np.abs(host(t) - ref).max() < 1e-14
 
 
+@pytest.mark.parametrize("krasny", [1e-12, 0.0])
+@pytest.mark.parametrize("nx,ny", [(32, 16), (128, 64), (64, 256), (2048, 16)])
+def test_two_thirds_filter(nx, ny, krasny):
+    say(f"two-thirds filter {nx}x{ny} krasny {krasny}")
+    ctx, g = mk(nx, ny, 1.0, 1.0, krasny=krasny, dealias=1)
+    X, Y = np.meshgrid(g.x, g.y)
+    rng = np.random.default_rng(nx + ny)
+    f = 1.0 + 0.3 * np.cos(X) * np.sin(2 * Y)
+    # modes on both sides of the 1/3 band edge in x and y, the Nyquist lines, small modes
+    ex, ey = nx // 3, ny // 3
+    for amp, kx, ky in [(0.1, ex, 0), (0.1, ex + 1, 0), (0.1, 0, ey), (0.1, 0, ey + 1), (0.1, ex, ey),
+                        (0.1, ex + 1, ey), (0.1, ex, -ey - 1), (0.1, nx // 2, 0), (0.1, nx // 2, 3),
+                        (0.1, 0, ny // 2), (0.1, 2, ny // 2), (3e-12, 3, 1), (8e-13, 2, 0), (1e-13, 0, 1)]:
+        f = f + amp * np.cos(kx * X + ky * Y + rng.random())
+    t = dev(f)
+    sgn.sgn_krasny_filter(ctx, t)
+    ref = O.two_thirds(g, O.krasny(g, f, krasny) if krasny > 0 else f)
+    assert np.abs(host(t) - ref).max() < 1e-14
+
+
+def test_rk4_two_thirds_rule():
+    say("rk4 random state with Krasny and the two-thirds rule")
+    nx, ny = 64, 32
+    ctx, g = mk(nx, ny, 1.0, 1.0, gmres_tol=1e-12, krasny=1e-12, dealias=1)
+    rng = np.random.default_rng(19)
+    h, vx, vy, s = random_state(rng, Box(nx, ny, 1.0, 1.0), amp_h=0.2, amp_v=0.1, kmax=12)
+    gh, gvx, gvy, gs, info = run_gpu_rk4(ctx, h, vx, vy, s, 0.005, 5)
+    oh, ovx, ovy, os_, oinfo = O.rk4(g, h, vx, vy, s, 0.005, 5)
+    assert rel(gh, oh, 1.0) < 1e-10 and rel(gvx, ovx) < 1e-10 and rel(gvy, ovy) < 1e-10
+    # the state is band-limited after the step
+    for a in (gh, gvx, gvy):
+        c = np.abs(np.fft.fft2(a)) / a.size
+        mx = np.abs(np.fft.fftfreq(nx) * nx)
+        my = np.abs(np.fft.fftfreq(ny) * ny)
+        outside = (3 * my[:, None] > ny) | (3 * mx[None, :] > nx)
+        assert c[outside].max() < 1e-15
+
+
 @pytest.mark.parametrize("arnoldi", ["fused", "chained", "serial"])
 @pytest.mark.parametrize("nx,ny,restart", [(16, 16, 20), (64, 32, 20), (128, 64, 20), (256, 128, 20),
                                            (64, 64, 3), (1024, 512, 20)])

@@ -268,6 +268,18 @@ def test_krasny_filter_removes_only_small_modes():
     assert np.abs(O.krasny(g, nyq, 1e-12) - 1.0).max() < 1e-15
 
 
+def test_two_thirds_rule_keeps_exactly_the_inner_band():
+    # nx = 32: |m_x| <= 10 kept, 11 dropped; ny = 16: |m_y| <= 5 kept, 6 dropped.
+    g = grid(32, 16, 1.0, 1.0)
+    X, Y = np.meshgrid(g.x, g.y)
+    kept = 0.7 + np.cos(10 * X + 5 * Y) + 0.3 * np.sin(10 * X - 5 * Y) + 0.2 * np.cos(3 * X)
+    dropped = (0.5 * np.cos(11 * X) + 0.4 * np.sin(2 * X + 6 * Y) + 0.3 * np.cos(16 * X)
+               + 0.2 * np.cos(8 * Y) + 0.1 * np.cos(16 * X + 8 * Y))
+    out = O.two_thirds(g, kept + dropped)
+    assert np.abs(out - kept).max() < 1e-14
+    assert np.abs(O.two_thirds(g, dropped)).max() < 1e-14
+
+
 # --- invariants -----------------------------------------------------------------
 
 
