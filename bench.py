@@ -70,14 +70,15 @@ def copy_calibration(mib: int, reps: int):
                       "gb_per_s": 2 * n * 8 * reps / dt / 1e9}), flush=True)
 
 
-def traffic_from_profile(kernel: str):
-    """HBM bytes per launch measured with rocprofv3 counters, if the summary in
-    profiles/ was taken on the kernel source currently in the tree."""
+def traffic_ratio_from_profile(kernel: str):
+    """Measured HBM bytes / algorithmic bytes of the kernel, from the rocprofv3
+    FETCH_SIZE and WRITE_SIZE counters summarised in profiles/, if that summary
+    was taken on the kernel source currently in the tree (else None)."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{WORKLOAD}_counters.txt")
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    m = re.search(r"traffic_over_algorithmic:\s*([0-9.eE+]+)", text)
     h = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", text)
     if not m or not h:
         return None
@@ -139,7 +140,8 @@ def main():
     algo = algo_total / launches if launches else 0.0  # per launch, averaged over all timed launches
     mean_s = (kms / launches) / 1e3 if launches else float("nan")
     achieved = algo / mean_s / 1e9 if launches else None
-    traffic = traffic_from_profile(dominant)
+    ratio = traffic_ratio_from_profile(dominant)
+    traffic = ratio * algo if (ratio is not None and launches) else None  # HBM bytes per launch
     out = {
         "metric": METRIC,
         "value": value,
