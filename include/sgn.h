@@ -56,6 +56,16 @@ enum {
 
 enum { SGN_FP64 = 0 };
 
+/* Initial guess of the sigma solve in each RK4 stage (sgn_config.guess). */
+enum {
+  SGN_GUESS_PREVIOUS = 0,        /* the sigma of the previous RHS evaluation (Section 3) */
+  SGN_GUESS_STAGE_INCREMENT = 1  /* that sigma plus the increment the same stage had over its
+                                    predecessor in the previous step: sigma_i(n) ~ sigma_{i-1}(n)
+                                    + [sigma_i(n-1) - sigma_{i-1}(n-1)].  The increments start at
+                                    zero in each sgn_rk4_step call, so its first step is the same
+                                    as SGN_GUESS_PREVIOUS; 4 extra fields of workspace. */
+};
+
 /* Problem and solver parameters.  Defaults in brackets (sgn_config_default). */
 typedef struct sgn_config {
   int32_t nx, ny;          /* grid, powers of two in [8, 4096] */
@@ -74,7 +84,8 @@ typedef struct sgn_config {
                               scheme, which filters with the Krasny threshold only; it suppresses
                               the grid-scale aliasing growth that long runs of transversally
                               perturbed solitons develop with the Krasny filter alone. */
-  int32_t reserved;        /* must be 0 */
+  int32_t guess;           /* SGN_GUESS_PREVIOUS [default] or SGN_GUESS_STAGE_INCREMENT; only the
+                              starting iterate of GMRES depends on it, not the tolerance met */
 } sgn_config;
 
 typedef struct sgn_ctx sgn_ctx;

@@ -23,6 +23,11 @@ Readings of the paper used here (where it is silent or garbled):
     is <= tol * ||M^-1 b||;
   * warm start: every RHS evaluation starts GMRES from the sigma returned by
     the previous evaluation (Section 3);
+  * optional stage-increment guess (Config.guess = 1, not in the paper): RK
+    stage i of step n starts GMRES from sigma_{i-1}(n) + D_i, where D_i is the
+    increment sigma_i - sigma_{i-1} of the same stage in step n - 1 (zero in
+    the first step of an rk4 call); the converged sigma still meets the same
+    tolerance;
   * Krasny filter: normalised 2D DFT coefficients |F f| / N below the
     threshold are set to zero in h, v_x, v_y once per completed RK4 step;
   * optional two-thirds rule (Config.dealias, off by default; Orszag's
@@ -58,6 +63,7 @@ class Config:
     krasny: float = 0.0          # 0 disables the filter
     invariants_tol: float = 1e-13
     dealias: bool = False        # two-thirds rule after each step (not in the paper)
+    guess: int = 0               # 0: previous sigma (Section 3); 1: stage-increment extrapolation
 
 
 class Grid:
@@ -292,29 +298,39 @@ class StepInfo:
     solves: int = 0
     min_h: float = 0.0
     any_unconverged: bool = False
+    stage_iters: list = dataclasses.field(default_factory=list)   # per solve, in order
+    guess_dist: list = dataclasses.field(default_factory=list)    # max |sigma - guess| per solve
 
 
-def rk4_step(grid: Grid, h, vx, vy, sigma, dt: float, info: StepInfo | None = None):
+def rk4_step(grid: Grid, h, vx, vy, sigma, dt: float, info: StepInfo | None = None, incr=None):
     """One classical RK4 step of (h, v_x, v_y); sigma carries the warm start
-    from one RHS evaluation to the next.  Returns (h, vx, vy, sigma)."""
+    from one RHS evaluation to the next.  With Config.guess = 1, incr is the
+    list of the four stage increments D_i (updated in place).  Returns
+    (h, vx, vy, sigma)."""
     info = info if info is not None else StepInfo()
     y0 = (h, vx, vy)
+    use_incr = grid.cfg.guess == 1 and incr is not None
 
-    def ev(state, s):
-        r = rhs(grid, *state, s)
+    def ev(state, s, stage):
+        guess = s + incr[stage] if use_incr else s
+        r = rhs(grid, *state, guess)
+        if use_incr:
+            incr[stage] = incr[stage] + (r.sigma - guess)
         info.solves += 1
         info.total_iters += r.info.iters
         info.max_iters_per_solve = max(info.max_iters_per_solve, r.info.iters)
         info.any_unconverged |= not r.info.converged
+        info.stage_iters.append(r.info.iters)
+        info.guess_dist.append(float(np.max(np.abs(r.sigma - guess))))
         return (r.dh, r.dvx, r.dvy), r.sigma
 
-    k1, s1 = ev(y0, sigma)
+    k1, s1 = ev(y0, sigma, 0)
     y1 = tuple(a + 0.5 * dt * k for a, k in zip(y0, k1))
-    k2, s2 = ev(y1, s1)
+    k2, s2 = ev(y1, s1, 1)
     y2 = tuple(a + 0.5 * dt * k for a, k in zip(y0, k2))
-    k3, s3 = ev(y2, s2)
+    k3, s3 = ev(y2, s2, 2)
     y3 = tuple(a + dt * k for a, k in zip(y0, k3))
-    k4, s4 = ev(y3, s3)
+    k4, s4 = ev(y3, s3, 3)
     out = tuple(a + dt / 6.0 * (q1 + 2.0 * q2 + 2.0 * q3 + q4)
                 for a, q1, q2, q3, q4 in zip(y0, k1, k2, k3, k4))
     if grid.cfg.krasny > 0.0:
@@ -328,8 +344,9 @@ def rk4_step(grid: Grid, h, vx, vy, sigma, dt: float, info: StepInfo | None = No
 def rk4(grid: Grid, h, vx, vy, sigma, dt: float, nsteps: int):
     """nsteps RK4 steps; returns (h, vx, vy, sigma, StepInfo)."""
     info = StepInfo()
+    incr = [np.zeros_like(h) for _ in range(4)] if grid.cfg.guess == 1 else None
     for _ in range(nsteps):
-        h, vx, vy, sigma = rk4_step(grid, h, vx, vy, sigma, dt, info)
+        h, vx, vy, sigma = rk4_step(grid, h, vx, vy, sigma, dt, info, incr)
     return h, vx, vy, sigma, info
 
 

@@ -25,6 +25,7 @@ struct sgn_ctx {
   sgn::GmresState* st;
   double* partials;
   cplx *V, *Z, *W, *E, *G, *P, *Q, *R1, *R2, *SIG;
+  cplx* D;  // guess 1: four per-stage sigma increments (2D spectra), else null
   double *hs, *vxs, *vys, *acc_h, *acc_vx, *acc_vy;
   sgn::GmresStatus* hstat;  // pinned host copy of the device status
   int last_iters[5];  // iterations of the previous solve per slot (RK stages 0-3, other calls 4)
@@ -51,7 +52,7 @@ int check_config(const sgn_config* c) {
   if (!(std::isfinite(c->invariants_tol) && c->invariants_tol > 0)) return SGN_ERR_INVALID_ARG;
   if (!(std::isfinite(c->krasny) && c->krasny >= 0)) return SGN_ERR_INVALID_ARG;
   if (c->dealias != 0 && c->dealias != 1) return SGN_ERR_INVALID_ARG;
-  if (c->reserved != 0) return SGN_ERR_INVALID_ARG;
+  if (c->guess != SGN_GUESS_PREVIOUS && c->guess != SGN_GUESS_STAGE_INCREMENT) return SGN_ERR_INVALID_ARG;
   if (c->gmres_max_iters < 1) return SGN_ERR_INVALID_ARG;
   if (c->gmres_restart < 1) return SGN_ERR_INVALID_ARG;
   if (c->gmres_restart > sgn::kMaxRestart) return SGN_ERR_UNSUPPORTED;
@@ -91,8 +92,9 @@ Layout layout(const sgn_config* c) {
   L.partials = off;
   off += align_up((size_t)pblocks * sgn::kPartialStride * sizeof(double));
   L.fields = off;
-  // V (restart + 1), Z, W, E, G, P, Q, R1, R2, SIG, hs, vxs, vys, acc_h, acc_vx, acc_vy
-  L.nfields = c->gmres_restart + 1 + 15;
+  // V (restart + 1), Z, W, E, G, P, Q, R1, R2, SIG, hs, vxs, vys, acc_h, acc_vx, acc_vy,
+  // and with the stage-increment guess D_0..D_3
+  L.nfields = c->gmres_restart + 1 + 15 + (c->guess == SGN_GUESS_STAGE_INCREMENT ? 4 : 0);
   off += (size_t)L.nfields * L.field_bytes;
   L.total = off;
   return L;
@@ -212,7 +214,7 @@ struct SolveResult {
 // On return (SIG, E, G) hold the solution.
 // slot: which history predicts the iteration count (the RK stage, or 4).
 int run_solve(sgn_ctx* ctx, int mode, const double* h, const double* vx, const double* vy, SolveResult* res,
-              int slot = 4) {
+              int slot = 4, cplx* D = nullptr) {
   const sgn::Geom& g = ctx->g;
   hipStream_t s = ctx->stream;
   const int m = ctx->cfg.gmres_restart;
@@ -292,7 +294,7 @@ int run_solve(sgn_ctx* ctx, int mode, const double* h, const double* vx, const d
     }
     total = st.total_iters;
     // sigma_hat += V y, and E, G of the new sigma
-    HIPCK(sgn::launch_col_update_eg(g, ctx->SIG, ctx->V, ctx->vstride, ctx->st, ctx->E, ctx->G, s));
+    HIPCK(sgn::launch_col_update_eg(g, ctx->SIG, ctx->V, ctx->vstride, ctx->st, ctx->E, ctx->G, D, s));
     res->rel_resid = st.beta0 > 0 ? st.resid / st.beta0 : 0.0;
     if (st.done == 1) {
       res->converged = 1;
@@ -399,6 +401,11 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   ctx->acc_h = reinterpret_cast<double*>(next());
   ctx->acc_vx = reinterpret_cast<double*>(next());
   ctx->acc_vy = reinterpret_cast<double*>(next());
+  ctx->D = nullptr;
+  if (cfg->guess == SGN_GUESS_STAGE_INCREMENT) {
+    ctx->D = reinterpret_cast<cplx*>(f);
+    f += 4 * L.field_bytes;
+  }
 
   // FP64 twiddles exp(-2 pi i k / n), from the symmetric angle to keep the
   // table accurate to a rounding of the exact value
@@ -515,13 +522,18 @@ int sgn_rk4_step(sgn_ctx* ctx, double* h, double* vx, double* vy, double* sigma,
   double* B = reinterpret_cast<double*>(ctx->R1);
   int64_t total = 0;
   int maxper = 0, solves = 0, unconv = 0;
+  // stage-increment guess: the increments start at zero in every call, so the
+  // first step starts each stage from the previous stage's sigma
+  if (ctx->D) HIPCK(hipMemsetAsync(ctx->D, 0, 4 * ctx->vstride * sizeof(cplx), s));
   for (int step = 0; step < nsteps; ++step) {
     for (int stage = 0; stage < 4; ++stage) {
       const double* ih = stage == 0 ? h : ctx->hs;
       const double* ivx = stage == 0 ? vx : ctx->vxs;
       const double* ivy = stage == 0 ? vy : ctx->vys;
+      cplx* Dst = ctx->D ? ctx->D + (size_t)stage * ctx->vstride : nullptr;
+      if (Dst && step > 0) HIPCK(sgn::launch_col_guess_eg(g, ctx->SIG, Dst, ctx->E, ctx->G, s));
       SolveResult res;
-      rc = run_solve(ctx, 1, ih, ivx, ivy, &res, stage);
+      rc = run_solve(ctx, 1, ih, ivx, ivy, &res, stage, Dst);
       if (rc) return rc;
       total += res.iters;
       if (res.iters > maxper) maxper = res.iters;

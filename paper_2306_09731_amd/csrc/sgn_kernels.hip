@@ -1142,10 +1142,13 @@ __global__ void __launch_bounds__(1024) k_col_precond_new(Geom g, const cplx* __
 }
 
 // sigma_hat += sum_{i<k} y_i V_i (or 0 when b == 0), then E, G of sigma_hat.
+// D (optional): the stage increment of the extrapolated guess, D += (new -
+// old sigma_hat), so that over a solve D collects sigma - guess.
 template <int N>
 __global__ void __launch_bounds__(512) k_col_update_eg(Geom g, cplx* __restrict__ SIG, const cplx* __restrict__ V,
                                                         size_t vstride, const GmresState* __restrict__ st,
-                                                        cplx* __restrict__ Eo, cplx* __restrict__ Go) {
+                                                        cplx* __restrict__ Eo, cplx* __restrict__ Go,
+                                                        cplx* __restrict__ D) {
   COL_SETUP(N)
   __shared__ double coef[kMaxRestart];
   const int tid = flat_tid();
@@ -1160,8 +1163,9 @@ __global__ void __launch_bounds__(512) k_col_update_eg(Geom g, cplx* __restrict_
     const size_t idx = (size_t)p * g.nh + col;
     cplx x = make_double2(0.0, 0.0);
     if (valid) {
+      const cplx old = (D || !zero) ? SIG[idx] : make_double2(0.0, 0.0);
       if (!zero) {
-        x = SIG[idx];
+        x = old;
         for (int i0 = 0; i0 < k; i0 += 4) {
           cplx b[4];
 #pragma unroll
@@ -1175,12 +1179,32 @@ __global__ void __launch_bounds__(512) k_col_update_eg(Geom g, cplx* __restrict_
         }
       }
       SIG[idx] = x;
+      if (D) D[idx] = cadd(D[idx], csub(x, old));
     }
     v[r] = x;
   }
   col_emit_eg<N>(g, v, buf, t, col, valid, Eo, Go, twy);
 }
 
+// Extrapolated initial guess of an RK stage: sigma_hat += D (the increment
+// this stage had over the previous one in the last step), then E, G.
+template <int N>
+__global__ void __launch_bounds__(512) k_col_guess_eg(Geom g, cplx* __restrict__ SIG, const cplx* __restrict__ D,
+                                                       cplx* __restrict__ Eo, cplx* __restrict__ Go) {
+  COL_SETUP(N)
+  cplx v[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const size_t idx = (size_t)(t + r * TPF) * g.nh + col;
+    cplx x = make_double2(0.0, 0.0);
+    if (valid) {
+      x = cadd(SIG[idx], D[idx]);
+      SIG[idx] = x;
+    }
+    v[r] = x;
+  }
+  col_emit_eg<N>(g, v, buf, t, col, valid, Eo, Go, twy);
+}
 
 // F_y(P) - i ky F_y(Q) for the tile; P, Q are x-half spectra (Q may be null).
 template <int N>
@@ -1798,12 +1822,20 @@ hipError_t launch_col_basis_eg(const Geom& g, const cplx* W, cplx* V, size_t vs,
 
 template <int N>
 static hipError_t col_update_eg_n(const Geom& g, cplx* SIG, const cplx* V, size_t vs, const GmresState* st, cplx* Eo,
-                                  cplx* Go, hipStream_t s) {
-  COL_LAUNCH(k_col_update_eg<N>, g, SIG, V, vs, st, Eo, Go);
+                                  cplx* Go, cplx* D, hipStream_t s) {
+  COL_LAUNCH(k_col_update_eg<N>, g, SIG, V, vs, st, Eo, Go, D);
 }
 hipError_t launch_col_update_eg(const Geom& g, cplx* SIG, const cplx* V, size_t vs, const GmresState* st, cplx* Eo,
-                                cplx* Go, hipStream_t s) {
-  DISPATCH_NY(col_update_eg_n, g, SIG, V, vs, st, Eo, Go, s)
+                                cplx* Go, cplx* D, hipStream_t s) {
+  DISPATCH_NY(col_update_eg_n, g, SIG, V, vs, st, Eo, Go, D, s)
+}
+
+template <int N>
+static hipError_t col_guess_eg_n(const Geom& g, cplx* SIG, const cplx* D, cplx* Eo, cplx* Go, hipStream_t s) {
+  COL_LAUNCH(k_col_guess_eg<N>, g, SIG, D, Eo, Go);
+}
+hipError_t launch_col_guess_eg(const Geom& g, cplx* SIG, const cplx* D, cplx* Eo, cplx* Go, hipStream_t s) {
+  DISPATCH_NY(col_guess_eg_n, g, SIG, D, Eo, Go, s)
 }
 
 template <int N>

@@ -21,8 +21,11 @@ hipError_t launch_row_invariants(const Geom& g, const cplx* E, const cplx* G, co
 hipError_t launch_col_fwd_eg(const Geom& g, const cplx* Ein, cplx* SIG, cplx* Go, hipStream_t s);
 hipError_t launch_col_basis_eg(const Geom& g, const cplx* W, cplx* V, size_t vs, int j, const GmresState* st,
                                cplx* Eo, cplx* Go, hipStream_t s);
+// D (may be null): D += (updated - previous) sigma_hat, the guess increment
 hipError_t launch_col_update_eg(const Geom& g, cplx* SIG, const cplx* V, size_t vs, const GmresState* st, cplx* Eo,
-                                cplx* Go, hipStream_t s);
+                                cplx* Go, cplx* D, hipStream_t s);
+// SIG += D, then E, G of SIG (extrapolated initial guess of an RK stage)
+hipError_t launch_col_guess_eg(const Geom& g, cplx* SIG, const cplx* D, cplx* Eo, cplx* Go, hipStream_t s);
 hipError_t launch_col_precond_dot(const Geom& g, const cplx* P, const cplx* Q, const cplx* V, size_t vs, int j,
                                   GmresState* st, cplx* W, double* partials, hipStream_t s);
 hipError_t launch_col_resid(const Geom& g, const cplx* P, const cplx* Q, const cplx* R1, const cplx* R2, int need_b,

@@ -22,6 +22,8 @@ SGN_ERR_NOT_CONVERGED = 4
 SGN_ERR_CAVITATION = 5
 SGN_ERR_NONFINITE = 6
 SGN_FP64 = 0
+SGN_GUESS_PREVIOUS = 0
+SGN_GUESS_STAGE_INCREMENT = 1
 SGN_KERNEL_ROW_MATVEC = 0
 SGN_KERNEL_COL_BASIS = 1
 SGN_KERNEL_COL_PRECOND_DOT = 2
@@ -42,7 +44,7 @@ class sgn_config(ctypes.Structure):
         ("gmres_max_iters", ctypes.c_int32), ("batch", ctypes.c_int32),
         ("krasny", ctypes.c_double),
         ("invariants_tol", ctypes.c_double),
-        ("dealias", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("dealias", ctypes.c_int32), ("guess", ctypes.c_int32),
     ]
 
 

@@ -40,7 +40,7 @@ def test_config_default_and_struct_layout():
     assert (cfg.nx, cfg.ny, cfg.Lx, cfg.Ly) == (128, 64, 10.0, 5.0)
     assert cfg.g == 1.0 and cfg.h_inf == 1.0 and cfg.gmres_restart == 20
     assert cfg.gmres_tol == 1e-10 and cfg.gmres_max_iters == 200 and cfg.batch == 1
-    assert cfg.krasny == 0.0 and cfg.dealias == 0 and cfg.reserved == 0
+    assert cfg.krasny == 0.0 and cfg.dealias == 0 and cfg.guess == sgn.SGN_GUESS_PREVIOUS
     assert ctypes.sizeof(sgn.sgn_config) == 88
 
 
@@ -59,7 +59,7 @@ def test_workspace_bytes_rejects_unsupported(field, value):
 
 @pytest.mark.parametrize("field,value", [
     ("Lx", 0.0), ("Ly", -1.0), ("gmres_tol", 0.0), ("gmres_max_iters", 0), ("h_inf", 0.0),
-    ("krasny", -1.0), ("gmres_restart", 0), ("Lx", float("nan")), ("dealias", 2), ("reserved", 1),
+    ("krasny", -1.0), ("gmres_restart", 0), ("Lx", float("nan")), ("dealias", 2), ("guess", 2), ("guess", -1),
 ])
 def test_invalid_config(field, value):
     cfg = sgn.config_default(128, 64, 10.0, 5.0)
@@ -69,6 +69,13 @@ def test_invalid_config(field, value):
     h = ctypes.c_void_p()
     assert lib.sgn_init(ctypes.byref(cfg), ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(h)) \
         == sgn.SGN_ERR_INVALID_ARG
+
+
+def test_workspace_stage_increment_guess_adds_four_fields():
+    a = sgn.sgn_workspace_bytes(sgn.config_default(128, 64, 10.0, 5.0))
+    b = sgn.sgn_workspace_bytes(sgn.config_default(128, 64, 10.0, 5.0, guess=sgn.SGN_GUESS_STAGE_INCREMENT))
+    field = 128 * 64 * 8
+    assert b - a == 4 * field
 
 
 def test_workspace_size_scales_with_grid_and_restart():

@@ -227,6 +227,37 @@ def run_gpu_rk4(ctx, h, vx, vy, s, dt, n):
     return host(th), host(tvx), host(tvy), host(ts), info
 
 
+@pytest.mark.parametrize("arnoldi", ["fused", "serial"])
+@pytest.mark.parametrize("nx,ny", [(128, 64), (256, 128)])
+def test_rk4_stage_increment_guess(nx, ny, arnoldi):
+    """guess = SGN_GUESS_STAGE_INCREMENT against the oracle with the same
+    option (transversally perturbed soliton, 40 steps, two calls so that the
+    increments restart at zero in the second), and against the plain warm
+    start: same states to the GMRES tolerance, fewer iterations."""
+    say(f"rk4 stage-increment guess {nx}x{ny} {arnoldi}")
+    box = Box(nx, ny, 10.0, 5.0)
+    h, vx, vy, s = perturbed_line_soliton(box, a=0.5, eps=0.01, k=2, x0=-10.0)
+    dt, n = 0.01, 20
+    ctx, g = mk(nx, ny, box.Lx, box.Ly, arnoldi=arnoldi, gmres_tol=1e-12, krasny=1e-12,
+                guess=sgn.SGN_GUESS_STAGE_INCREMENT)
+    th, tvx, tvy, ts = dev(h), dev(vx), dev(vy), dev(s)
+    i1 = sgn.sgn_rk4_step(ctx, th, tvx, tvy, ts, dt, n)
+    i2 = sgn.sgn_rk4_step(ctx, th, tvx, tvy, ts, dt, n)
+    gh, gvx, gvy, gs = host(th), host(tvx), host(tvy), host(ts)
+    oh, ovx, ovy, os_, o1 = O.rk4(g, h, vx, vy, s, dt, n)
+    oh, ovx, ovy, os_, o2 = O.rk4(g, oh, ovx, ovy, os_, dt, n)
+    gi, oi = i1.total_iters + i2.total_iters, o1.total_iters + o2.total_iters
+    ctx0, _ = mk(nx, ny, box.Lx, box.Ly, arnoldi=arnoldi, gmres_tol=1e-12, krasny=1e-12)
+    ph, pvx, pvy, ps, p = run_gpu_rk4(ctx0, h, vx, vy, s, dt, 2 * n)
+    say(f"  iters gpu {gi} oracle {oi} plain warm start {p.total_iters}")
+    assert not (i1.any_unconverged or i2.any_unconverged)
+    assert abs(gi - oi) <= 8
+    assert rel(gh, oh, 1.0) < 1e-10 and rel(gvx, ovx) < 1e-10 and rel(gvy, ovy) < 1e-10
+    assert rel(gs, os_) < 1e-9
+    assert rel(gh, ph, 1.0) < 1e-9 and rel(gvx, pvx) < 1e-9 and rel(gvy, pvy) < 1e-9
+    assert gi < 0.9 * p.total_iters
+
+
 @pytest.mark.parametrize("arnoldi", ["fused", "chained", "serial"])
 def test_rk4_line_soliton_128x64_200_steps(arnoldi):
     """The 128x64 line soliton workload: a = 0.5 on [-10pi,10pi]x[-5pi,5pi],

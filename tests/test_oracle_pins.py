@@ -268,6 +268,44 @@ def test_krasny_filter_removes_only_small_modes():
     assert np.abs(O.krasny(g, nyq, 1e-12) - 1.0).max() < 1e-15
 
 
+def _soliton_guess_run(guess, dt, nsteps, tol=1e-12):
+    from sgn_inputs import Box, line_soliton
+    box = Box(256, 16, 10.0, 1.0)
+    g = grid(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=tol, guess=guess)
+    h, vx, vy, s = line_soliton(box, a=0.5, x0=0.0)
+    return O.rk4(g, h, vx, vy, s, dt, nsteps)
+
+
+def test_stage_increment_guess_is_second_order_and_leaves_the_solution():
+    """The stage-increment guess predicts each stage's sigma to O(dt^2) (the
+    increment of a stage changes by O(dt) per step), where the plain warm start
+    is O(dt) off for the half- and full-step stages; the converged states are
+    the same up to the GMRES tolerance, and the first step is identical."""
+    dist = {}
+    for guess in (0, 1):
+        for dt in (0.02, 0.01):
+            n = int(round(0.08 / dt))
+            h, vx, vy, s, info = _soliton_guess_run(guess, dt, n)
+            # stages of the last step
+            dist[guess, dt] = np.array(info.guess_dist[-4:])
+            if dt == 0.01:
+                final = (h, vx)
+                if guess == 0:
+                    plain, plain_iters = final, info.stage_iters
+                else:
+                    assert info.stage_iters[:4] == plain_iters[:4]       # first step: same guesses
+                    assert sum(info.stage_iters) < sum(plain_iters)      # fewer iterations overall
+                    for a, b in zip(final, plain):
+                        assert np.abs(a - b).max() < 1e-9
+    r0 = dist[0, 0.01] / dist[0, 0.02]
+    r1 = dist[1, 0.01] / dist[1, 0.02]
+    # plain: stages 2 and 4 first order (ratio ~1/2)
+    assert 0.4 < r0[1] < 0.6 and 0.4 < r0[3] < 0.6
+    # increment guess: every stage at least second order (ratio <= ~1/4)
+    assert np.all(r1 < 0.3), r1
+    assert np.all(dist[1, 0.01] < dist[0, 0.01])
+
+
 def test_two_thirds_rule_keeps_exactly_the_inner_band():
     # nx = 32: |m_x| <= 10 kept, 11 dropped; ny = 16: |m_y| <= 5 kept, 6 dropped.
     g = grid(32, 16, 1.0, 1.0)
