@@ -752,6 +752,26 @@ __device__ __forceinline__ double col_weight(int col) { return col == 0 ? 1.0 : 
   gather_twiddles<N>(twy, t, g.twy);                         \
   (void)valid;
 
+// 2D spectra (the Krylov basis, sigma_hat, the residual and the guess
+// increments) are only touched by column passes and are stored column-major,
+// [nx/2][ny], so that a column pass reads and writes them contiguously; x-half
+// spectra, which the row passes produce and consume, stay row-major [ny][nx/2].
+__device__ __forceinline__ size_t sidx(const Geom& g, int p, int col) { return (size_t)col * g.ny + p; }
+
+template <int N>
+__device__ __forceinline__ void load_spec(cplx* v, const cplx* __restrict__ S, int col, int t, bool valid) {
+#pragma unroll
+  for (int r = 0; r < Col<N>::E; ++r)
+    v[r] = valid ? S[(size_t)col * N + t + r * Col<N>::TPF] : make_double2(0.0, 0.0);
+}
+
+template <int N>
+__device__ __forceinline__ void store_spec(const cplx* v, cplx* __restrict__ S, int col, int t, bool valid) {
+  if (!valid) return;
+#pragma unroll
+  for (int r = 0; r < Col<N>::E; ++r) S[(size_t)col * N + t + r * Col<N>::TPF] = v[r];
+}
+
 template <int N>
 __device__ __forceinline__ void load_col(cplx* v, const cplx* __restrict__ S, int nh, int col, int t, bool valid) {
 #pragma unroll
@@ -779,7 +799,7 @@ __global__ void __launch_bounds__(512) k_col_fwd_eg(Geom g, const cplx* __restri
   cplx v[E];
   load_col<N>(v, Ein, g.nh, col, t, valid);
   fft<N, false, decltype(map)>(v, buf, t, twy, map);
-  store_col<N>(v, SIG, g.nh, col, t, valid);
+  store_spec<N>(v, SIG, col, t, valid);
 #pragma unroll
   for (int r = 0; r < E; ++r) v[r] = mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Ly) * g.inv_ny);
   fft<N, true, decltype(map)>(v, buf, t, twy, map);
@@ -820,7 +840,7 @@ __global__ void __launch_bounds__(512) k_col_basis_eg(Geom g, const cplx* __rest
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int p = t + r * TPF;
-    const size_t idx = (size_t)p * g.nh + col;
+    const size_t idx = sidx(g, p, col);
     cplx x = make_double2(0.0, 0.0);
     if (valid) {
       x = W[idx];
@@ -877,7 +897,7 @@ __global__ void __launch_bounds__(1024) k_col_basis2(Geom g, const cplx* __restr
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int p = t + r * TPF;
-    const size_t idx = (size_t)p * g.nh + col;
+    const size_t idx = sidx(g, p, col);
     cplx x = make_double2(0.0, 0.0);
     if (valid) {
       x = W[idx];
@@ -931,7 +951,7 @@ __global__ void __launch_bounds__(1024) k_col_precond_dot2(Geom g, const cplx* _
   for (int q = 0; q < EH; ++q) {
     const int p = t + (chain * EH + q) * TPF;
     w[q] = cscale(cadd(b0[map.at(p)], b1[map.at(p)]), inv_symbol(g, kx, wavenumber(p, N, g.inv_Ly)));
-    if (valid) W[(size_t)p * g.nh + col] = w[q];
+    if (valid) W[sidx(g, p, col)] = w[q];
   }
   const double wt = valid ? col_weight(col) : 0.0;
   for (int i0 = 0; i0 <= j; i0 += 8) {
@@ -943,7 +963,7 @@ __global__ void __launch_bounds__(1024) k_col_precond_dot2(Geom g, const cplx* _
 #pragma unroll
         for (int q = 0; q < EH; ++q) {
           const int p = t + (chain * EH + q) * TPF;
-          const cplx b = V[(i0 + q8) * vstride + (size_t)p * g.nh + col];
+          const cplx b = V[(i0 + q8) * vstride + sidx(g, p, col)];
           d += b.x * w[q].x + b.y * w[q].y;
         }
       }
@@ -991,7 +1011,7 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
 #pragma unroll
   for (int q = 0; q < EH; ++q) {
     const int p = t + (chain * EH + q) * TPF;
-    const size_t idx = (size_t)p * g.nh + col;
+    const size_t idx = sidx(g, p, col);
     cplx x = make_double2(0.0, 0.0);
     if (valid) {
       x = win[idx];
@@ -1013,7 +1033,7 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
   double nr = 0.0;
 #pragma unroll
   for (int q = 0; q < EH; ++q) {
-    if (valid) W[(size_t)(t + (chain * EH + q) * TPF) * g.nh + col] = u[q];
+    if (valid) W[sidx(g, t + (chain * EH + q) * TPF, col)] = u[q];
     nr += u[q].x * u[q].x + u[q].y * u[q].y;
   }
   wave_partial(valid ? col_weight(col) * nr : 0.0, red, 0);
@@ -1074,7 +1094,7 @@ __global__ void __launch_bounds__(1024) k_col_precond_new(Geom g, const cplx* __
 #pragma unroll
   for (int q = 0; q < EH; ++q) {
     const int p = t + (chain * EH + q) * TPF;
-    const size_t idx = (size_t)p * g.nh + col;
+    const size_t idx = sidx(g, p, col);
     const cplx z = cscale(cadd(b0[map.at(p)], b1[map.at(p)]), inv_symbol(g, kx, wavenumber(p, N, g.inv_Ly)));
     vj[q] = make_double2(0.0, 0.0);
     wj[q] = make_double2(0.0, 0.0);
@@ -1096,7 +1116,7 @@ __global__ void __launch_bounds__(1024) k_col_precond_new(Geom g, const cplx* __
   }
   size_t pidx[EH];
 #pragma unroll
-  for (int q = 0; q < EH; ++q) pidx[q] = (size_t)(t + (chain * EH + q) * TPF) * g.nh + col;
+  for (int q = 0; q < EH; ++q) pidx[q] = sidx(g, t + (chain * EH + q) * TPF, col);
   for (int i0 = 0; i0 <= j; i0 += 4) {
     double a[8];
 #pragma unroll
@@ -1160,7 +1180,7 @@ __global__ void __launch_bounds__(512) k_col_update_eg(Geom g, cplx* __restrict_
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int p = t + r * TPF;
-    const size_t idx = (size_t)p * g.nh + col;
+    const size_t idx = sidx(g, p, col);
     cplx x = make_double2(0.0, 0.0);
     if (valid) {
       const cplx old = (D || !zero) ? SIG[idx] : make_double2(0.0, 0.0);
@@ -1195,7 +1215,7 @@ __global__ void __launch_bounds__(512) k_col_guess_eg(Geom g, cplx* __restrict__
   cplx v[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const size_t idx = (size_t)(t + r * TPF) * g.nh + col;
+    const size_t idx = sidx(g, t + r * TPF, col);
     cplx x = make_double2(0.0, 0.0);
     if (valid) {
       x = cadd(SIG[idx], D[idx]);
@@ -1242,7 +1262,7 @@ __global__ void __launch_bounds__(512) k_col_precond_dot(Geom g, const cplx* __r
     const int p = t + r * TPF;
     v[r] = cscale(v[r], inv_symbol(g, kx, wavenumber(p, N, g.inv_Ly)));
   }
-  store_col<N>(v, W, g.nh, col, t, valid);
+  store_spec<N>(v, W, col, t, valid);
   const double wt = valid ? col_weight(col) : 0.0;
   for (int i0 = 0; i0 <= j; i0 += 8) {
     double a[8];
@@ -1253,7 +1273,7 @@ __global__ void __launch_bounds__(512) k_col_precond_dot(Geom g, const cplx* __r
 #pragma unroll
         for (int r = 0; r < E; ++r) {
           const int p = t + r * TPF;
-          const cplx b = V[(i0 + q) * vstride + (size_t)p * g.nh + col];
+          const cplx b = V[(i0 + q) * vstride + sidx(g, p, col)];
           d += b.x * v[r].x + b.y * v[r].y;
         }
       }
@@ -1292,7 +1312,7 @@ __global__ void __launch_bounds__(512) k_col_resid(Geom g, const cplx* __restric
     if (!true_only) v[r] = cscale(v[r], inv_symbol(g, kx, wavenumber(p, N, g.inv_Ly)));
     nr += v[r].x * v[r].x + v[r].y * v[r].y;
   }
-  if (!true_only) store_col<N>(v, W, g.nh, col, t, valid);
+  if (!true_only) store_spec<N>(v, W, col, t, valid);
   wave_partial(wt * nr, red, 0);
   int nvals = 1;
   if (need_b) {
@@ -1342,7 +1362,7 @@ template <int N>
 __global__ void __launch_bounds__(512) k_col_inv(Geom g, const cplx* __restrict__ S, cplx* __restrict__ out) {
   COL_SETUP(N)
   cplx v[E];
-  load_col<N>(v, S, g.nh, col, t, valid);
+  load_spec<N>(v, S, col, t, valid);
 #pragma unroll
   for (int r = 0; r < E; ++r) v[r] = cscale(v[r], g.inv_ny);
   fft<N, true, decltype(map)>(v, buf, t, twy, map);
@@ -1362,7 +1382,7 @@ __global__ void __launch_bounds__(512) k_col_apply(Geom g, const cplx* __restric
     for (int r = 0; r < E; ++r)
       v[r] = cscale(v[r], inv_symbol(g, kx, wavenumber(t + r * TPF, N, g.inv_Ly)));
   }
-  store_col<N>(v, out, g.nh, col, t, valid);
+  store_spec<N>(v, out, col, t, valid);
 }
 
 // x-half spectra -> multiplied by a 2D symbol -> x-half spectra.
@@ -1544,7 +1564,7 @@ __global__ void __launch_bounds__(kUpdThreads) k_upd(Geom g, cplx* __restrict__ 
     idx[e] = (size_t)blockIdx.x * (kUpdThreads * kUpdEpt) + e * kUpdThreads + tid;
     const bool ok = idx[e] < total;
     w[e] = ok ? W[idx[e]] : make_double2(0.0, 0.0);
-    wt[e] = ok ? col_weight((int)(idx[e] % g.nh)) : 0.0;
+    wt[e] = ok ? col_weight((int)(idx[e] / g.ny)) : 0.0;  // column-major 2D spectra
   }
   for (int i0 = 0; i0 <= j; i0 += 4) {
     cplx b[4][kUpdEpt];
@@ -1918,16 +1938,19 @@ struct Chain {
     return r;
   }
   // column tile for two chains: at least one wave per chain, <= 1024 threads,
-  // LDS <= 128 KB, >= 256 blocks when possible
+  // dynamic LDS <= kChainLds (the kernels add up to ~50 KB of static LDS, the
+  // Hessenberg staging of the GMRES finish among it, within 160 KB per block),
+  // >= 256 blocks when possible
+  static constexpr size_t kChainLds = 98304;
   static int tc(int nh) {
     constexpr int TPF = Col<N>::TPF;
     int t = 1;
     while (t * TPF < 64) t *= 2;
-    while (2 * (t * 2) * TPF <= 1024 && (size_t)2 * (t * 2) * N * sizeof(cplx) <= 131072 && nh / (t * 2) >= 256)
+    while (2 * (t * 2) * TPF <= 1024 && (size_t)2 * (t * 2) * N * sizeof(cplx) <= kChainLds && nh / (t * 2) >= 256)
       t *= 2;
     return t;
   }
-  static bool col_ok(int nh) { return 2 * tc(nh) * Col<N>::TPF <= 1024 && (size_t)2 * tc(nh) * N * sizeof(cplx) <= 131072; }
+  static bool col_ok(int nh) { return 2 * tc(nh) * Col<N>::TPF <= 1024 && (size_t)2 * tc(nh) * N * sizeof(cplx) <= kChainLds; }
 };
 
 template <int N>
