@@ -18,9 +18,10 @@
  *   invariants  mass, momentum and energy (Section 2.3)
  *
  * Conventions shared by every call
- *   - Fields are FP64 DEVICE pointers owned by the caller: contiguous,
- *     row-major [ny][nx] (x contiguous), 256-byte aligned.  Grid points are
- *     x_j = -pi Lx + j * 2 pi Lx / nx (same in y).
+ *   - Fields are DEVICE pointers owned by the caller: contiguous, row-major
+ *     [ny][nx] (x contiguous), 256-byte aligned, of double in SGN_FP64 mode
+ *     and of float in SGN_FP32_MIXED mode (hence void* in the signatures).
+ *     Grid points are x_j = -pi Lx + j * 2 pi Lx / nx (same in y).
  *   - Wavenumbers are k = m / L, m in [-n/2, n/2), with the Nyquist mode of
  *     every derivative set to zero; the preconditioner uses the same k, with
  *     M = 3 / h_inf^3 + (kx^2 + ky^2) / h_inf (= 3 + k^2 for h_inf = 1).
@@ -54,7 +55,15 @@ enum {
   SGN_ERR_NONFINITE = 6      /* NaN or Inf in the state */
 };
 
-enum { SGN_FP64 = 0 };
+/* Working precision (sgn_config.precision). */
+enum {
+  SGN_FP64 = 0,       /* everything in FP64 */
+  SGN_FP32_MIXED = 1  /* fields, spectra, the Krylov basis, every FFT, the operator, the fluxes and the
+                         RK4 combine in FP32; inner products and norms accumulated in FP64, and the
+                         GMRES projections, Hessenberg matrix, Givens rotations and invariants in
+                         FP64.  The GMRES tolerance is raised to at least 1e-6 (the attainable residual
+                         of an FP32 operator); results agree with FP64 to about 1e-6 per call. */
+};
 
 /* Initial guess of the sigma solve in each RK4 stage (sgn_config.guess). */
 enum {
@@ -72,7 +81,7 @@ typedef struct sgn_config {
   double Lx, Ly;           /* periods are 2 pi Lx, 2 pi Ly; box [-pi L, pi L) */
   double g;                /* gravity [1] (the paper sets g = h_inf = 1, Section 4) */
   double h_inf;            /* depth at infinity [1] */
-  int32_t precision;       /* SGN_FP64 */
+  int32_t precision;       /* SGN_FP64 [default] or SGN_FP32_MIXED */
   int32_t gmres_restart;   /* restart length m [20], 1..64 */
   double gmres_tol;        /* stop when ||M^-1 (b - L s)|| <= tol ||M^-1 b|| [1e-10] */
   int32_t gmres_max_iters; /* total Arnoldi steps per solve [10 * restart] */
@@ -126,7 +135,7 @@ void sgn_config_default(sgn_config* cfg, int32_t nx, int32_t ny, double Lx, doub
 size_t sgn_workspace_bytes(const sgn_config* cfg);
 
 /* Validate cfg, lay out the caller's device workspace (ws, ws_bytes >=
- * sgn_workspace_bytes(cfg), 256-byte aligned), upload the FP64 twiddle tables
+ * sgn_workspace_bytes(cfg), 256-byte aligned), upload the twiddle tables
  * and the GMRES state, and return a context in *out.  hip_stream is a
  * hipStream_t (NULL = the default stream).  The workspace must outlive the
  * context.  Errors: SGN_ERR_INVALID_ARG, SGN_ERR_UNSUPPORTED, SGN_ERR_HIP. */
@@ -139,29 +148,29 @@ int sgn_destroy(sgn_ctx* ctx);
  * restarted left-preconditioned GMRES.  h, b: device fields; sigma: device
  * field, in = initial guess, out = solution.  info may be NULL.  Returns
  * SGN_ERR_NOT_CONVERGED (sigma = last iterate) if gmres_max_iters is hit. */
-int sgn_elliptic_solve(sgn_ctx* ctx, const double* h, const double* b, double* sigma, sgn_solve_info* info);
+int sgn_elliptic_solve(sgn_ctx* ctx, const void* h, const void* b, void* sigma, sgn_solve_info* info);
 
 /* One evaluation of the right-hand side of the (h, v) system (Section 3):
  *   b = -div v;  sigma = GMRES(L_h, b; x0 = sigma);
  *   dh = -div(h v - grad sigma);  dv = -grad B,
  *   B = |v|^2/2 - |grad sigma|^2/(2 h^2) + g h - 9/2 sigma^2/h^4.
  * sigma is in/out (warm start in, solution out).  dh, dvx, dvy: outputs. */
-int sgn_rhs(sgn_ctx* ctx, const double* h, const double* vx, const double* vy, double* sigma, double* dh,
-            double* dvx, double* dvy, sgn_solve_info* info);
+int sgn_rhs(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, void* sigma, void* dh, void* dvx,
+            void* dvy, sgn_solve_info* info);
 
 /* nsteps classical RK4 steps of size dt, in place on (h, vx, vy) (Section 3).
  * sigma is in/out: the warm start of the first solve, and on return the sigma
  * of the last RHS evaluation; each solve starts from the previous one's
  * sigma.  With cfg.krasny > 0 the Krasny filter is applied to h, vx, vy
  * after every step.  info may be NULL. */
-int sgn_rk4_step(sgn_ctx* ctx, double* h, double* vx, double* vy, double* sigma, double dt, int32_t nsteps,
+int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double dt, int32_t nsteps,
                  sgn_step_info* info);
 
 /* Conserved quantities of Section 2.3 for the state (h, vx, vy): sigma is
  * first solved to cfg.invariants_tol from the guess in sigma (in/out), then
  * mass, momentum, energy, min/max h, ||curl v|| and the spectral tail of h are
  * reduced in FP64 and written to the host struct *out. */
-int sgn_invariants(sgn_ctx* ctx, const double* h, const double* vx, const double* vy, double* sigma,
+int sgn_invariants(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, void* sigma,
                    sgn_invariants_out* out);
 
 /* Building blocks of the hot path, exposed for testing.
@@ -171,10 +180,10 @@ int sgn_invariants(sgn_ctx* ctx, const double* h, const double* vx, const double
  * sgn_krasny_filter: the per-step spectral filter of f in place: Krasny threshold
  *   cfg.krasny (Section 3; 0 = none) and, if cfg.dealias, the two-thirds rule.
  * All fields are device pointers; out may not alias an input. */
-int sgn_derivative(sgn_ctx* ctx, int32_t axis, const double* f, double* out);
-int sgn_apply_operator(sgn_ctx* ctx, const double* h, const double* s, double* out, int32_t precondition);
-int sgn_apply_precond(sgn_ctx* ctx, const double* r, double* out);
-int sgn_krasny_filter(sgn_ctx* ctx, double* f);
+int sgn_derivative(sgn_ctx* ctx, int32_t axis, const void* f, void* out);
+int sgn_apply_operator(sgn_ctx* ctx, const void* h, const void* s, void* out, int32_t precondition);
+int sgn_apply_precond(sgn_ctx* ctx, const void* r, void* out);
+int sgn_krasny_filter(sgn_ctx* ctx, void* f);
 
 /* Measurement support.  While timing is enabled for a kernel class, every
  * launch of that class is bracketed by HIP events recorded on the context

@@ -20,7 +20,14 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsgn.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["sgn_kernels.hip", "sgn_api.cpp"]
+# (source, object name, extra flags): the kernels are compiled once per
+# working precision into their own namespaces.
+SOURCES = [
+    ("sgn_kernels.hip", "sgn_kernels_fp64", ["-DSGN_PREC=64"]),
+    ("sgn_kernels.hip", "sgn_kernels_fp32", ["-DSGN_PREC=32"]),
+    ("sgn_dispatch.cpp", "sgn_dispatch", []),
+    ("sgn_api.cpp", "sgn_api", []),
+]
 
 # Packed FP32 instructions are disabled for all device code.
 HIP_FLAGS = [
@@ -37,10 +44,11 @@ def hipcc() -> str:
     return path
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+def _compile(item) -> str:
+    src, name, extra = item
+    obj = os.path.join(BUILD_DIR, name + ".o")
     lang = [] if src.endswith(".hip") else ["-x", "hip"]
-    cmd = [hipcc(), *HIP_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *HIP_FLAGS, *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compiling {src} failed:\n{r.stderr}")

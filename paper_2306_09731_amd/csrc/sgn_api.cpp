@@ -13,7 +13,7 @@
 #include "sgn_internal.hpp"
 #include "sgn_launch.hpp"
 
-using sgn::cplx;
+typedef double2 cplx;
 
 struct sgn_ctx {
   sgn_config cfg;
@@ -21,12 +21,14 @@ struct sgn_ctx {
   char* ws;
   size_t ws_bytes;
   sgn::Geom g;
-  size_t vstride;  // complex entries per field
+  size_t vstride;      // complex entries (of the working precision) per field
+  size_t field_bytes;  // bytes per field (256-byte multiple)
   sgn::GmresState* st;
   double* partials;
-  cplx *V, *Z, *W, *E, *G, *P, *Q, *R1, *R2, *SIG;
-  cplx* D;  // guess 1: four per-stage sigma increments (2D spectra), else null
-  double *hs, *vxs, *vys, *acc_h, *acc_vx, *acc_vy;
+  // fields of the working precision (FP64 or FP32), untyped on the host
+  void *V, *Z, *W, *E, *G, *P, *Q, *R1, *R2, *SIG;
+  char* D;  // guess 1: four per-stage sigma increments (2D spectra), else null
+  void *hs, *vxs, *vys, *acc_h, *acc_vx, *acc_vy;
   sgn::GmresStatus* hstat;  // pinned host copy of the device status
   int last_iters[5];  // iterations of the previous solve per slot (RK stages 0-3, other calls 4)
   int arnoldi;   // 0 serial 4-kernel, 1 chain-parallel 4-kernel, 2 three-kernel (default where allowed)
@@ -56,13 +58,20 @@ int check_config(const sgn_config* c) {
   if (c->gmres_max_iters < 1) return SGN_ERR_INVALID_ARG;
   if (c->gmres_restart < 1) return SGN_ERR_INVALID_ARG;
   if (c->gmres_restart > sgn::kMaxRestart) return SGN_ERR_UNSUPPORTED;
-  if (c->precision != SGN_FP64) return SGN_ERR_UNSUPPORTED;
+  if (c->precision != SGN_FP64 && c->precision != SGN_FP32_MIXED) return SGN_ERR_UNSUPPORTED;
   if (c->batch != 1) return SGN_ERR_UNSUPPORTED;
   if (!pow2_in(c->nx, 8, 4096) || !pow2_in(c->ny, 8, 4096)) return SGN_ERR_UNSUPPORTED;
   return SGN_OK;
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// GMRES tolerance actually used: an FP32 operator cannot reduce the residual
+// much below 1e-6 relative, so the mixed-precision mode stops there.
+constexpr double kFp32MinTol = 1e-6;
+double effective_tol(const sgn_config& c, double tol) {
+  return c.precision == SGN_FP32_MIXED && tol < kFp32MinTol ? kFp32MinTol : tol;
+}
 
 // The spectral filter applied to h, v_x, v_y after every RK4 step: the Krasny
 // threshold (Section 3) and, if enabled, the two-thirds rule.
@@ -78,15 +87,17 @@ struct Layout {
 Layout layout(const sgn_config* c) {
   Layout L;
   const size_t n = (size_t)c->nx * c->ny;
-  L.field_bytes = align_up(n * sizeof(double));
+  L.field_bytes = align_up(n * (c->precision == SGN_FP32_MIXED ? sizeof(float) : sizeof(double)));
   sgn::Geom g{};
   g.nx = c->nx;
   g.ny = c->ny;
   g.nh = c->nx / 2;
+  g.fp32 = c->precision == SGN_FP32_MIXED;
   const int pblocks = sgn::max_partial_blocks(g);
   size_t off = 0;
   L.tw = off;
-  off += align_up((size_t)(c->nx + c->ny) * sizeof(cplx));
+  off += align_up((size_t)(c->nx + c->ny) * sizeof(double2));  // FP64 twiddles
+  off += align_up((size_t)(c->nx + c->ny) * sizeof(float2));   // FP32 twiddles
   L.st = off;
   off += align_up(sizeof(sgn::GmresState));
   L.partials = off;
@@ -176,21 +187,22 @@ int read_status(sgn_ctx* ctx) {
   return SGN_OK;
 }
 
-int set_tol(sgn_ctx* ctx, double tol) {
+int set_tol(sgn_ctx* ctx, double tol_requested) {
+  const double tol = effective_tol(ctx->cfg, tol_requested);
   HIPCK(hipMemcpyAsync(&ctx->st->tol, &tol, sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   HIPCK(hipStreamSynchronize(ctx->stream));  // tol is a host local
   return SGN_OK;
 }
 
 // sigma (physical) -> E = F_x sigma, SIG = F sigma, G = F_x d_y sigma
-int load_sigma(sgn_ctx* ctx, const double* sigma) {
+int load_sigma(sgn_ctx* ctx, const void* sigma) {
   HIPCK(sgn::launch_row_r2c(ctx->g, sigma, ctx->E, ctx->stream));
   HIPCK(sgn::launch_col_fwd_eg(ctx->g, ctx->E, ctx->SIG, ctx->G, ctx->stream));
   return SGN_OK;
 }
 
-int check_state(sgn_ctx* ctx, const double* a, const double* b, const double* c) {
-  HIPCK(sgn::launch_field_stats(a, b, c, (size_t)ctx->g.nx * ctx->g.ny, ctx->st, ctx->partials, ctx->stream));
+int check_state(sgn_ctx* ctx, const void* a, const void* b, const void* c) {
+  HIPCK(sgn::launch_field_stats(ctx->g, a, b, c, (size_t)ctx->g.nx * ctx->g.ny, ctx->st, ctx->partials, ctx->stream));
   int rc = read_status(ctx);
   if (rc) return rc;
   if (ctx->hstat->stat_nonfinite) {
@@ -213,8 +225,8 @@ struct SolveResult {
 // mode 1: b = -div v from (vx, vy); mode 2: b given (passed as vx).
 // On return (SIG, E, G) hold the solution.
 // slot: which history predicts the iteration count (the RK stage, or 4).
-int run_solve(sgn_ctx* ctx, int mode, const double* h, const double* vx, const double* vy, SolveResult* res,
-              int slot = 4, cplx* D = nullptr) {
+int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void* vy, SolveResult* res,
+              int slot = 4, void* D = nullptr) {
   const sgn::Geom& g = ctx->g;
   hipStream_t s = ctx->stream;
   const int m = ctx->cfg.gmres_restart;
@@ -281,7 +293,7 @@ int run_solve(sgn_ctx* ctx, int mode, const double* h, const double* vx, const d
       // algorithmic bytes of this cycle's launches that did work: steps
       // j < jdone (kernels B, C) and kernel A for j <= jdone (A_jdone
       // finished the last step), unless the cycle converged at its start
-      const double fb = 8.0 * (double)g.nx * (double)g.ny;
+      const double fb = (g.fp32 ? 4.0 : 8.0) * (double)g.nx * (double)g.ny;
       const int jd = st.jdone;
       const bool ran = !(st.done == 1 && jd == 0 && st.total_iters == total);
       if (ran) {
@@ -369,41 +381,46 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   g.m0 = 3.0 / (cfg->h_inf * cfg->h_inf * cfg->h_inf);
   g.m1 = 1.0 / cfg->h_inf;
   g.dA = (2.0 * M_PI * cfg->Lx / nx) * (2.0 * M_PI * cfg->Ly / ny);
+  g.fp32 = cfg->precision == SGN_FP32_MIXED;
   if (!sgn::chained_ok(g)) ctx->arnoldi = 0;
   char* base = ctx->ws;
   cplx* tw = reinterpret_cast<cplx*>(base + L.tw);
+  float2* tw32 = reinterpret_cast<float2*>(base + L.tw + align_up((size_t)(nx + ny) * sizeof(double2)));
   g.twx = tw;
   g.twy = tw + nx;
+  g.twx32 = tw32;
+  g.twy32 = tw32 + nx;
   ctx->st = reinterpret_cast<sgn::GmresState*>(base + L.st);
   ctx->partials = reinterpret_cast<double*>(base + L.partials);
-  ctx->vstride = L.field_bytes / sizeof(cplx);
+  ctx->field_bytes = L.field_bytes;
+  ctx->vstride = L.field_bytes / (g.fp32 ? sizeof(float2) : sizeof(double2));
   char* f = base + L.fields;
   auto next = [&]() {
     char* p = f;
     f += L.field_bytes;
     return p;
   };
-  ctx->V = reinterpret_cast<cplx*>(f);
+  ctx->V = f;
   f += (size_t)(cfg->gmres_restart + 1) * L.field_bytes;
-  ctx->Z = reinterpret_cast<cplx*>(f);
+  ctx->Z = f;
   f += L.field_bytes;
-  ctx->W = reinterpret_cast<cplx*>(next());
-  ctx->E = reinterpret_cast<cplx*>(next());
-  ctx->G = reinterpret_cast<cplx*>(next());
-  ctx->P = reinterpret_cast<cplx*>(next());
-  ctx->Q = reinterpret_cast<cplx*>(next());
-  ctx->R1 = reinterpret_cast<cplx*>(next());
-  ctx->R2 = reinterpret_cast<cplx*>(next());
-  ctx->SIG = reinterpret_cast<cplx*>(next());
-  ctx->hs = reinterpret_cast<double*>(next());
-  ctx->vxs = reinterpret_cast<double*>(next());
-  ctx->vys = reinterpret_cast<double*>(next());
-  ctx->acc_h = reinterpret_cast<double*>(next());
-  ctx->acc_vx = reinterpret_cast<double*>(next());
-  ctx->acc_vy = reinterpret_cast<double*>(next());
+  ctx->W = next();
+  ctx->E = next();
+  ctx->G = next();
+  ctx->P = next();
+  ctx->Q = next();
+  ctx->R1 = next();
+  ctx->R2 = next();
+  ctx->SIG = next();
+  ctx->hs = next();
+  ctx->vxs = next();
+  ctx->vys = next();
+  ctx->acc_h = next();
+  ctx->acc_vx = next();
+  ctx->acc_vy = next();
   ctx->D = nullptr;
   if (cfg->guess == SGN_GUESS_STAGE_INCREMENT) {
-    ctx->D = reinterpret_cast<cplx*>(f);
+    ctx->D = f;
     f += 4 * L.field_bytes;
   }
 
@@ -418,12 +435,17 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   };
   fill(htw.data(), nx);
   fill(htw.data() + nx, ny);
+  // the same tables rounded to FP32 for the mixed-precision kernels
+  std::vector<float2> htw32(htw.size());
+  for (size_t k = 0; k < htw.size(); ++k) htw32[k] = make_float2((float)htw[k].x, (float)htw[k].y);
   sgn::GmresState hst;
   std::memset(&hst, 0, sizeof hst);
-  hst.tol = cfg->gmres_tol;
+  hst.tol = effective_tol(*cfg, cfg->gmres_tol);
   hst.m = cfg->gmres_restart;
   hst.maxit = cfg->gmres_max_iters;
   hipError_t e = hipMemcpyAsync(tw, htw.data(), htw.size() * sizeof(cplx), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(tw32, htw32.data(), htw32.size() * sizeof(float2), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ctx->st, &hst, sizeof hst, hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -445,7 +467,7 @@ int sgn_destroy(sgn_ctx* ctx) {
   return SGN_OK;
 }
 
-int sgn_elliptic_solve(sgn_ctx* ctx, const double* h, const double* b, double* sigma, sgn_solve_info* info) {
+int sgn_elliptic_solve(sgn_ctx* ctx, const void* h, const void* b, void* sigma, sgn_solve_info* info) {
   if (!ctx || !aligned(h) || !aligned(b) || !aligned(sigma)) return SGN_ERR_INVALID_ARG;
   int rc = check_state(ctx, h, b, b);
   if (rc) return rc;
@@ -475,8 +497,8 @@ int sgn_elliptic_solve(sgn_ctx* ctx, const double* h, const double* b, double* s
   return res.converged ? SGN_OK : SGN_ERR_NOT_CONVERGED;
 }
 
-int sgn_rhs(sgn_ctx* ctx, const double* h, const double* vx, const double* vy, double* sigma, double* dh,
-            double* dvx, double* dvy, sgn_solve_info* info) {
+int sgn_rhs(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, void* sigma, void* dh, void* dvx,
+            void* dvy, sgn_solve_info* info) {
   if (!ctx || !aligned(h) || !aligned(vx) || !aligned(vy) || !aligned(sigma) || !aligned(dh) || !aligned(dvx) ||
       !aligned(dvy))
     return SGN_ERR_INVALID_ARG;
@@ -488,9 +510,9 @@ int sgn_rhs(sgn_ctx* ctx, const double* h, const double* vx, const double* vy, d
   rc = run_solve(ctx, 1, h, vx, vy, &res);
   if (rc) return rc;
   sgn::RkStage rk{0, 0, 0.0, 0.0, 0.0};
-  double* dhp = reinterpret_cast<double*>(ctx->P);
-  double* qy = reinterpret_cast<double*>(ctx->Q);
-  double* B = reinterpret_cast<double*>(ctx->R1);
+  void* dhp = ctx->P;
+  void* qy = ctx->Q;
+  void* B = ctx->R1;
   HIPCK(sgn::launch_row_flux(ctx->g, ctx->E, ctx->G, h, vx, vy, dhp, qy, B, rk, sgn::RkField{nullptr, nullptr, dvx},
                              ctx->stream));
   HIPCK(sgn::launch_col_flux(ctx->g, dhp, qy, B, rk, sgn::RkField{nullptr, nullptr, dh},
@@ -507,7 +529,7 @@ int sgn_rhs(sgn_ctx* ctx, const double* h, const double* vx, const double* vy, d
   return res.converged ? SGN_OK : SGN_ERR_NOT_CONVERGED;
 }
 
-int sgn_rk4_step(sgn_ctx* ctx, double* h, double* vx, double* vy, double* sigma, double dt, int32_t nsteps,
+int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double dt, int32_t nsteps,
                  sgn_step_info* info) {
   if (!ctx || !aligned(h) || !aligned(vx) || !aligned(vy) || !aligned(sigma) || nsteps < 0 || !std::isfinite(dt))
     return SGN_ERR_INVALID_ARG;
@@ -517,20 +539,20 @@ int sgn_rk4_step(sgn_ctx* ctx, double* h, double* vx, double* vy, double* sigma,
   if (rc) return rc;
   const sgn::Geom& g = ctx->g;
   hipStream_t s = ctx->stream;
-  double* dhp = reinterpret_cast<double*>(ctx->P);
-  double* qy = reinterpret_cast<double*>(ctx->Q);
-  double* B = reinterpret_cast<double*>(ctx->R1);
+  void* dhp = ctx->P;
+  void* qy = ctx->Q;
+  void* B = ctx->R1;
   int64_t total = 0;
   int maxper = 0, solves = 0, unconv = 0;
   // stage-increment guess: the increments start at zero in every call, so the
   // first step starts each stage from the previous stage's sigma
-  if (ctx->D) HIPCK(hipMemsetAsync(ctx->D, 0, 4 * ctx->vstride * sizeof(cplx), s));
+  if (ctx->D) HIPCK(hipMemsetAsync(ctx->D, 0, 4 * ctx->field_bytes, s));
   for (int step = 0; step < nsteps; ++step) {
     for (int stage = 0; stage < 4; ++stage) {
-      const double* ih = stage == 0 ? h : ctx->hs;
-      const double* ivx = stage == 0 ? vx : ctx->vxs;
-      const double* ivy = stage == 0 ? vy : ctx->vys;
-      cplx* Dst = ctx->D ? ctx->D + (size_t)stage * ctx->vstride : nullptr;
+      const void* ih = stage == 0 ? h : ctx->hs;
+      const void* ivx = stage == 0 ? vx : ctx->vxs;
+      const void* ivy = stage == 0 ? vy : ctx->vys;
+      void* Dst = ctx->D ? ctx->D + (size_t)stage * ctx->field_bytes : nullptr;
       if (Dst && step > 0) HIPCK(sgn::launch_col_guess_eg(g, ctx->SIG, Dst, ctx->E, ctx->G, s));
       SolveResult res;
       rc = run_solve(ctx, 1, ih, ivx, ivy, &res, stage, Dst);
@@ -560,8 +582,8 @@ int sgn_rk4_step(sgn_ctx* ctx, double* h, double* vx, double* vy, double* sigma,
       TIMED(SGN_KERNEL_COL_FLUX, sgn::launch_col_flux(g, dhp, qy, B, rk, fh, fvy, s));
     }
     if (step_filter_on(ctx->cfg)) {
-      double* fs[3] = {h, vx, vy};
-      for (double* f : fs) {
+      void* fs[3] = {h, vx, vy};
+      for (void* f : fs) {
         HIPCK(sgn::launch_row_r2c(g, f, ctx->P, s));
         HIPCK(sgn::launch_col_filter(g, ctx->P, step_filter_op(ctx->cfg), ctx->cfg.krasny, ctx->Q, s));
         HIPCK(sgn::launch_row_c2r(g, ctx->Q, f, s));
@@ -569,7 +591,7 @@ int sgn_rk4_step(sgn_ctx* ctx, double* h, double* vx, double* vy, double* sigma,
     }
   }
   HIPCK(sgn::launch_row_c2r(g, ctx->E, sigma, s));
-  HIPCK(sgn::launch_field_stats(h, vx, vy, (size_t)g.nx * g.ny, ctx->st, ctx->partials, s));
+  HIPCK(sgn::launch_field_stats(g, h, vx, vy, (size_t)g.nx * g.ny, ctx->st, ctx->partials, s));
   rc = read_status(ctx);
   if (rc) return rc;
   if (info) {
@@ -584,7 +606,7 @@ int sgn_rk4_step(sgn_ctx* ctx, double* h, double* vx, double* vy, double* sigma,
   return unconv ? SGN_ERR_NOT_CONVERGED : SGN_OK;
 }
 
-int sgn_invariants(sgn_ctx* ctx, const double* h, const double* vx, const double* vy, double* sigma,
+int sgn_invariants(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, void* sigma,
                    sgn_invariants_out* out) {
   if (!ctx || !out || !aligned(h) || !aligned(vx) || !aligned(vy) || !aligned(sigma)) return SGN_ERR_INVALID_ARG;
   int rc = check_state(ctx, h, vx, vy);
@@ -598,7 +620,7 @@ int sgn_invariants(sgn_ctx* ctx, const double* h, const double* vx, const double
   if (rc) return rc;
   if (rc2) return rc2;
   const sgn::Geom& g = ctx->g;
-  double* dyvx = reinterpret_cast<double*>(ctx->R2);
+  void* dyvx = ctx->R2;
   HIPCK(sgn::launch_col_dy(g, vx, dyvx, ctx->stream));
   HIPCK(sgn::launch_row_invariants(g, ctx->E, ctx->G, h, vx, vy, dyvx, ctx->partials, ctx->st, ctx->stream));
   HIPCK(sgn::launch_row_r2c(g, h, ctx->P, ctx->stream));
@@ -618,7 +640,7 @@ int sgn_invariants(sgn_ctx* ctx, const double* h, const double* vx, const double
   return res.converged ? SGN_OK : SGN_ERR_NOT_CONVERGED;
 }
 
-int sgn_derivative(sgn_ctx* ctx, int32_t axis, const double* f, double* out) {
+int sgn_derivative(sgn_ctx* ctx, int32_t axis, const void* f, void* out) {
   if (!ctx || !aligned(f) || !aligned(out) || f == out || (axis != 0 && axis != 1)) return SGN_ERR_INVALID_ARG;
   if (axis == 0)
     HIPCK(sgn::launch_row_dx(ctx->g, f, out, ctx->stream));
@@ -628,7 +650,7 @@ int sgn_derivative(sgn_ctx* ctx, int32_t axis, const double* f, double* out) {
   return SGN_OK;
 }
 
-int sgn_apply_operator(sgn_ctx* ctx, const double* h, const double* s, double* out, int32_t precondition) {
+int sgn_apply_operator(sgn_ctx* ctx, const void* h, const void* s, void* out, int32_t precondition) {
   if (!ctx || !aligned(h) || !aligned(s) || !aligned(out) || out == s || out == h) return SGN_ERR_INVALID_ARG;
   const sgn::Geom& g = ctx->g;
   hipStream_t st = ctx->stream;
@@ -643,7 +665,7 @@ int sgn_apply_operator(sgn_ctx* ctx, const double* h, const double* s, double* o
   return SGN_OK;
 }
 
-int sgn_apply_precond(sgn_ctx* ctx, const double* r, double* out) {
+int sgn_apply_precond(sgn_ctx* ctx, const void* r, void* out) {
   if (!ctx || !aligned(r) || !aligned(out) || out == r) return SGN_ERR_INVALID_ARG;
   const sgn::Geom& g = ctx->g;
   HIPCK(sgn::launch_row_r2c(g, r, ctx->E, ctx->stream));
@@ -653,7 +675,7 @@ int sgn_apply_precond(sgn_ctx* ctx, const double* r, double* out) {
   return SGN_OK;
 }
 
-int sgn_krasny_filter(sgn_ctx* ctx, double* f) {
+int sgn_krasny_filter(sgn_ctx* ctx, void* f) {
   if (!ctx || !aligned(f)) return SGN_ERR_INVALID_ARG;
   const sgn::Geom& g = ctx->g;
   HIPCK(sgn::launch_row_r2c(g, f, ctx->E, ctx->stream));

@@ -1,5 +1,7 @@
 // Device-side complex arithmetic and the register/LDS FFT engine used by
-// every spectral pass of the SGN solver (gfx950, FP64).
+// every spectral pass of the SGN solver (gfx950).  Included once per working
+// precision: the including file defines SGN_NS (namespace), SGN_REAL and
+// SGN_CPLX (double/double2 or float/float2).
 //
 // The engine is a Stockham autosort FFT.  An FFT of length N is computed by
 // TPF = N/E threads, each holding E complex values in registers.  The first
@@ -13,24 +15,44 @@
 #include <hip/hip_runtime.h>
 
 namespace sgn {
+namespace SGN_NS {
 
-typedef double2 cplx;
+typedef SGN_REAL real;
+typedef SGN_CPLX cplx;
 
-__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ cplx csub(cplx a, cplx b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ cplx make_cplx(real x, real y) {
+  cplx z;
+  z.x = x;
+  z.y = y;
+  return z;
+}
+__device__ __forceinline__ cplx czero() { return make_cplx(real(0), real(0)); }
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return make_cplx(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return make_cplx(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ cplx cmul(cplx a, cplx b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_cplx(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 // a * conj(b)
 __device__ __forceinline__ cplx cmulc(cplx a, cplx b) {
-  return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+  return make_cplx(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
-__device__ __forceinline__ cplx cscale(cplx a, double s) { return make_double2(a.x * s, a.y * s); }
-__device__ __forceinline__ cplx mul_i(cplx a) { return make_double2(-a.y, a.x); }   // i a
-__device__ __forceinline__ cplx mul_mi(cplx a) { return make_double2(a.y, -a.x); }  // -i a
-__device__ __forceinline__ cplx conjc(cplx a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ cplx cscale(cplx a, double s) {
+  const real t = (real)s;
+  return make_cplx(a.x * t, a.y * t);
+}
+__device__ __forceinline__ cplx mul_i(cplx a) { return make_cplx(-a.y, a.x); }   // i a
+__device__ __forceinline__ cplx mul_mi(cplx a) { return make_cplx(a.y, -a.x); }  // -i a
+__device__ __forceinline__ cplx conjc(cplx a) { return make_cplx(a.x, -a.y); }
 // i*k*a for a real k
-__device__ __forceinline__ cplx mul_ik(cplx a, double k) { return make_double2(-k * a.y, k * a.x); }
+__device__ __forceinline__ cplx mul_ik(cplx a, double k) {
+  const real t = (real)k;
+  return make_cplx(-t * a.y, t * a.x);
+}
+// Re(a conj(b)) accumulated in FP64 (exact products of FP32 operands)
+__device__ __forceinline__ double cdot(cplx a, cplx b) {
+  return (double)a.x * (double)b.x + (double)a.y * (double)b.y;
+}
+__device__ __forceinline__ double cnorm2(cplx a) { return (double)a.x * (double)a.x + (double)a.y * (double)a.y; }
 
 // cos(pi m / 8) and sin(pi m / 8), m = 0..8: the twiddles of DFTs up to size 16.
 struct Tw16 {
@@ -49,13 +71,13 @@ __device__ __forceinline__ cplx twc(cplx a) {
   } else if constexpr (m == 4) {
     return INV ? mul_i(a) : mul_mi(a);
   } else {
-    constexpr double c = (m == 1) ? Tw16::C1 : (m == 2) ? Tw16::R2 : (m == 3) ? Tw16::S1
-                       : (m == 5) ? -Tw16::S1 : (m == 6) ? -Tw16::R2 : -Tw16::C1;
-    constexpr double s = (m == 1) ? Tw16::S1 : (m == 2) ? Tw16::R2 : (m == 3) ? Tw16::C1
-                       : (m == 5) ? Tw16::C1 : (m == 6) ? Tw16::R2 : Tw16::S1;
+    constexpr real c = (real)((m == 1) ? Tw16::C1 : (m == 2) ? Tw16::R2 : (m == 3) ? Tw16::S1
+                             : (m == 5) ? -Tw16::S1 : (m == 6) ? -Tw16::R2 : -Tw16::C1);
+    constexpr real s = (real)((m == 1) ? Tw16::S1 : (m == 2) ? Tw16::R2 : (m == 3) ? Tw16::C1
+                             : (m == 5) ? Tw16::C1 : (m == 6) ? Tw16::R2 : Tw16::S1);
     // forward: (c - i s); inverse: (c + i s)
-    return INV ? make_double2(a.x * c - a.y * s, a.x * s + a.y * c)
-               : make_double2(a.x * c + a.y * s, a.y * c - a.x * s);
+    return INV ? make_cplx(a.x * c - a.y * s, a.x * s + a.y * c)
+               : make_cplx(a.x * c + a.y * s, a.y * c - a.x * s);
   }
 }
 
@@ -163,7 +185,7 @@ template <int N>
 __device__ __forceinline__ void gather_twiddles(TwiddleSet<N>& ts, int t, const cplx* __restrict__ tw) {
   constexpr int E = FftShape<N>::E;
   if constexpr (N == E) {
-    ts.w[0] = make_double2(1.0, 0.0);
+    ts.w[0] = make_cplx(real(1), real(0));
   } else {
     gather_mid_twiddles<N, E, E, 0>(ts.w, t, tw);
 #pragma unroll
@@ -246,4 +268,5 @@ __device__ __forceinline__ double wavenumber(int p, int n, double inv_L) {
   return (double)(p < h ? p : p - n) * inv_L;
 }
 
+}  // namespace SGN_NS
 }  // namespace sgn

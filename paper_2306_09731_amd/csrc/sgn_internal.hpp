@@ -20,6 +20,9 @@ struct Geom {
   double dA;               // cell area dx * dy
   const double2* twx;      // exp(-2 pi i k / nx), k < nx
   const double2* twy;      // exp(-2 pi i k / ny), k < ny
+  const float2* twx32;     // the same tables rounded to FP32 (mixed-precision mode)
+  const float2* twy32;
+  int fp32;                // 1: fields, spectra and transforms in FP32; reductions stay FP64
 };
 
 // GMRES state kept in device memory.  Written only by the single "last
@@ -75,10 +78,11 @@ struct RkStage {
   double dt;
 };
 
+// Field pointers of the working precision (double or float arrays).
 struct RkField {
-  const double* yn;   // state at the start of the step
-  double* acc;        // accumulator of weighted stage derivatives
-  double* out;        // next stage input (mode 1), k (mode 0) or yn itself (mode 2)
+  const void* yn;   // state at the start of the step
+  void* acc;        // accumulator of weighted stage derivatives
+  void* out;        // next stage input (mode 1), k (mode 0) or yn itself (mode 2)
 };
 
 }  // namespace sgn

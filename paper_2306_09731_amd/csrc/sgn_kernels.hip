@@ -12,13 +12,38 @@
 // passes transform tc adjacent complex columns per block (loads of tc*16
 // contiguous bytes per row), two real columns per complex column for physical
 // data.
+//
+// This file is compiled once per working precision: SGN_PREC=64 (namespace
+// sgn::p64, double fields) and SGN_PREC=32 (namespace sgn::p32, float fields
+// and transforms).  Reductions, inner products, norms, the GMRES state and
+// every scalar coefficient are FP64 in both.
 #include <hip/hip_ext.h>
 
-#include "sgn_fft.hpp"
+#ifndef SGN_PREC
+#define SGN_PREC 64
+#endif
+#if SGN_PREC == 32
+#define SGN_NS p32
+#define SGN_REAL float
+#define SGN_CPLX float2
+#define TWX(g) ((g).twx32)
+#define TWY(g) ((g).twy32)
+#elif SGN_PREC == 64
+#define SGN_NS p64
+#define SGN_REAL double
+#define SGN_CPLX double2
+#define TWX(g) ((g).twx)
+#define TWY(g) ((g).twy)
+#else
+#error "SGN_PREC must be 32 or 64"
+#endif
+
 #include "sgn_internal.hpp"
 #include "sgn_launch.hpp"
+#include "sgn_fft.hpp"
 
 namespace sgn {
+namespace SGN_NS {
 
 // ----------------------------------------------------------------------------
 // Reductions (deterministic: fixed-order trees, no floating-point atomics)
@@ -277,20 +302,20 @@ struct Row {
 };
 
 template <int N>
-__device__ __forceinline__ void load_phys_pair(cplx* v, const double* __restrict__ f, int ya, int t) {
-  const double* a = f + (size_t)ya * N;
-  const double* b = a + N;
+__device__ __forceinline__ void load_phys_pair(cplx* v, const real* __restrict__ f, int ya, int t) {
+  const real* a = f + (size_t)ya * N;
+  const real* b = a + N;
 #pragma unroll
   for (int r = 0; r < Row<N>::E; ++r) {
     const int p = t + r * Row<N>::TPF;
-    v[r] = make_double2(a[p], b[p]);
+    v[r] = make_cplx(a[p], b[p]);
   }
 }
 
 template <int N>
-__device__ __forceinline__ void store_phys_pair(const cplx* v, double* __restrict__ f, int ya, int t) {
-  double* a = f + (size_t)ya * N;
-  double* b = a + N;
+__device__ __forceinline__ void store_phys_pair(const cplx* v, real* __restrict__ f, int ya, int t) {
+  real* a = f + (size_t)ya * N;
+  real* b = a + N;
 #pragma unroll
   for (int r = 0; r < Row<N>::E; ++r) {
     const int p = t + r * Row<N>::TPF;
@@ -311,16 +336,16 @@ __device__ __forceinline__ void load_spec_pair(cplx* v, const cplx* __restrict__
     cplx z;
     if (p == 0) {
       const cplx a = A[0], b = B[0];
-      z = make_double2(a.x, b.x);
+      z = make_cplx(a.x, b.x);
     } else if (p == H) {
       const cplx a = A[0], b = B[0];
-      z = make_double2(a.y, b.y);
+      z = make_cplx(a.y, b.y);
     } else if (p < H) {
       const cplx a = A[p], b = B[p];
-      z = make_double2(a.x - b.y, a.y + b.x);
+      z = make_cplx(a.x - b.y, a.y + b.x);
     } else {
       const cplx a = A[N - p], b = B[N - p];
-      z = make_double2(a.x + b.y, b.x - a.y);
+      z = make_cplx(a.x + b.y, b.x - a.y);
     }
     v[r] = cscale(z, s);
   }
@@ -341,12 +366,12 @@ __device__ __forceinline__ void store_spec_pair(const cplx* v, cplx* __restrict_
     const int k = t + r * Row<N>::TPF;
     if (k == 0) {
       const cplx z0 = buf[M.at(0)], zn = buf[M.at(H)];
-      A[0] = make_double2(z0.x, zn.x);
-      B[0] = make_double2(z0.y, zn.y);
+      A[0] = make_cplx(z0.x, zn.x);
+      B[0] = make_cplx(z0.y, zn.y);
     } else {
       const cplx z = buf[M.at(k)], zc = buf[M.at(N - k)];
-      A[k] = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
-      B[k] = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
+      A[k] = make_cplx(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
+      B[k] = make_cplx(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
     }
   }
   __syncthreads();
@@ -361,12 +386,12 @@ __device__ __forceinline__ void store_spec_pair(const cplx* v, cplx* __restrict_
   const int ya = 2 * (blockIdx.x * blockDim.y + threadIdx.y); \
   cplx* buf = lds + threadIdx.y * Row<N>::LDS;         \
   TwiddleSet<N> twx;                                   \
-  gather_twiddles<N>(twx, t, g.twx);                   \
+  gather_twiddles<N>(twx, t, TWX(g));                   \
   (void)TPF;
 
 // physical f -> x-half spectra S
 template <int N>
-__global__ void __launch_bounds__(512) k_row_r2c(Geom g, const double* __restrict__ f, cplx* __restrict__ S) {
+__global__ void __launch_bounds__(512) k_row_r2c(Geom g, const real* __restrict__ f, cplx* __restrict__ S) {
   ROW_SETUP(N)
   cplx v[E];
   load_phys_pair<N>(v, f, ya, t);
@@ -376,7 +401,7 @@ __global__ void __launch_bounds__(512) k_row_r2c(Geom g, const double* __restric
 
 // x-half spectra S -> physical f
 template <int N>
-__global__ void __launch_bounds__(512) k_row_c2r(Geom g, const cplx* __restrict__ S, double* __restrict__ f) {
+__global__ void __launch_bounds__(512) k_row_c2r(Geom g, const cplx* __restrict__ S, real* __restrict__ f) {
   ROW_SETUP(N)
   cplx v[E];
   load_spec_pair<N>(v, S, ya, t, g.inv_nx);
@@ -386,7 +411,7 @@ __global__ void __launch_bounds__(512) k_row_c2r(Geom g, const cplx* __restrict_
 
 // out = d/dx f
 template <int N>
-__global__ void __launch_bounds__(512) k_row_dx(Geom g, const double* __restrict__ f, double* __restrict__ out) {
+__global__ void __launch_bounds__(512) k_row_dx(Geom g, const real* __restrict__ f, real* __restrict__ out) {
   ROW_SETUP(N)
   cplx v[E];
   load_phys_pair<N>(v, f, ya, t);
@@ -407,8 +432,8 @@ __global__ void __launch_bounds__(512) k_row_dx(Geom g, const double* __restrict
 // MODE 2: residual with an explicit b (passed in vx): B1 = F_x b, B2 = 0.
 template <int N, int MODE>
 __global__ void __launch_bounds__(512) k_row_op(Geom g, const cplx* __restrict__ Es, const cplx* __restrict__ Gs,
-                                                const double* __restrict__ h, const double* __restrict__ vx,
-                                                const double* __restrict__ vy, cplx* __restrict__ P,
+                                                const real* __restrict__ h, const real* __restrict__ vx,
+                                                const real* __restrict__ vy, cplx* __restrict__ P,
                                                 cplx* __restrict__ Q, cplx* __restrict__ R1, cplx* __restrict__ R2,
                                                 int need_b, int predicate, const GmresState* __restrict__ st) {
   if (MODE == 0 && predicate && st->st.done) return;
@@ -422,7 +447,7 @@ __global__ void __launch_bounds__(512) k_row_op(Geom g, const cplx* __restrict__
   if constexpr (MODE == 1) load_phys_pair<N>(y, vy, ya, t);
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    hi[r] = make_double2(1.0 / hi[r].x, 1.0 / hi[r].y);
+    hi[r] = make_cplx(1.0 / hi[r].x, 1.0 / hi[r].y);
     u[r] = mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Lx));
   }
   fft<N, true, decltype(map)>(v, buf, t, twx, map);  // sigma
@@ -431,9 +456,9 @@ __global__ void __launch_bounds__(512) k_row_op(Geom g, const cplx* __restrict__
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const double ia = hi[r].x, ib = hi[r].y;
-    v[r] = make_double2(3.0 * v[r].x * ia * ia * ia, 3.0 * v[r].y * ib * ib * ib);
-    u[r] = make_double2(u[r].x * ia, u[r].y * ib);
-    w[r] = make_double2(w[r].x * ia, w[r].y * ib);
+    v[r] = make_cplx(3.0 * v[r].x * ia * ia * ia, 3.0 * v[r].y * ib * ib * ib);
+    u[r] = make_cplx(u[r].x * ia, u[r].y * ib);
+    w[r] = make_cplx(w[r].x * ia, w[r].y * ib);
   }
   fft<N, false, decltype(map)>(v, buf, t, twx, map);
   fft<N, false, decltype(map)>(u, buf, t, twx, map);
@@ -461,7 +486,7 @@ __global__ void __launch_bounds__(512) k_row_op(Geom g, const cplx* __restrict__
       if (need_b) store_spec_pair<N>(y, R2, ya, t, buf);
     } else {
 #pragma unroll
-      for (int r = 0; r < E; ++r) w[r] = make_double2(-w[r].x, -w[r].y);
+      for (int r = 0; r < E; ++r) w[r] = make_cplx(-w[r].x, -w[r].y);
       store_spec_pair<N>(w, Q, ya, t, buf);
     }
   }
@@ -477,7 +502,7 @@ __global__ void __launch_bounds__(512) k_row_op(Geom g, const cplx* __restrict__
 // Block: (TPF, 3 * rows-pairs-per-block).
 template <int N>
 __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __restrict__ Es, const cplx* __restrict__ Gs,
-                                                      const double* __restrict__ h, cplx* __restrict__ P,
+                                                      const real* __restrict__ h, cplx* __restrict__ P,
                                                       cplx* __restrict__ Q, const GmresState* __restrict__ st) {
   if (st->st.done) return;
   constexpr int E = Row<N>::E;
@@ -491,13 +516,13 @@ __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __rest
   cplx* base = lds + slot * 3 * Row<N>::LDS;
   cplx* buf = base + chain * Row<N>::LDS;
   TwiddleSet<N> twx;
-  gather_twiddles<N>(twx, t, g.twx);
+  gather_twiddles<N>(twx, t, TWX(g));
   cplx v[E], hi[E];
   load_spec_pair<N>(v, chain == 2 ? Gs : Es, ya, t, g.inv_nx);
   load_phys_pair<N>(hi, h, ya, t);
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    hi[r] = make_double2(1.0 / hi[r].x, 1.0 / hi[r].y);
+    hi[r] = make_cplx(1.0 / hi[r].x, 1.0 / hi[r].y);
     if (chain == 1) v[r] = mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Lx));
   }
   fft<N, true, RowMap>(v, buf, t, twx, map);
@@ -505,9 +530,9 @@ __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __rest
   for (int r = 0; r < E; ++r) {
     const double ia = hi[r].x, ib = hi[r].y;
     if (chain == 0)
-      v[r] = make_double2(3.0 * v[r].x * ia * ia * ia, 3.0 * v[r].y * ib * ib * ib);
+      v[r] = make_cplx(3.0 * v[r].x * ia * ia * ia, 3.0 * v[r].y * ib * ib * ib);
     else
-      v[r] = make_double2(v[r].x * ia, v[r].y * ib);
+      v[r] = make_cplx(v[r].x * ia, v[r].y * ib);
   }
   fft<N, false, RowMap>(v, buf, t, twx, map);
 #pragma unroll
@@ -524,8 +549,8 @@ __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __rest
   auto emit = [&](cplx* S, int k, cplx z, cplx zc) {
     cplx* A = S + (size_t)ya * H;
     cplx* B = A + H;
-    A[k] = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
-    B[k] = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
+    A[k] = make_cplx(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
+    B[k] = make_cplx(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
   };
 #pragma unroll
   for (int r = 0; r < E / 2; ++r) {
@@ -535,8 +560,8 @@ __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __rest
       if (k == 0) {
         const cplx z0 = b2[map.at(0)], zn = b2[map.at(H)];
         cplx* A = Q + (size_t)ya * H;
-        A[0] = make_double2(z0.x, zn.x);
-        A[H] = make_double2(z0.y, zn.y);
+        A[0] = make_cplx(z0.x, zn.x);
+        A[H] = make_cplx(z0.y, zn.y);
       } else {
         emit(Q, k, b2[map.at(k)], b2[map.at(N - k)]);
       }
@@ -544,8 +569,8 @@ __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __rest
       if (k == 0) {
         const cplx z0 = at_A1(0), zn = at_A1(H);
         cplx* A = P + (size_t)ya * H;
-        A[0] = make_double2(z0.x, zn.x);
-        A[H] = make_double2(z0.y, zn.y);
+        A[0] = make_cplx(z0.x, zn.x);
+        A[H] = make_cplx(z0.y, zn.y);
       } else {
         emit(P, k, at_A1(k), at_A1(N - k));
       }
@@ -554,14 +579,17 @@ __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __rest
 }
 
 __device__ __forceinline__ void rk_one(const RkStage& rk, const RkField& f, size_t i, double k) {
+  real* out = static_cast<real*>(f.out);
+  real* acc = static_cast<real*>(f.acc);
+  const real* yn = static_cast<const real*>(f.yn);
   if (rk.mode == 0) {
-    f.out[i] = k;
+    out[i] = k;
   } else if (rk.mode == 1) {
-    const double a = rk.first ? 0.0 : f.acc[i];
-    f.acc[i] = a + rk.wacc * k;
-    f.out[i] = f.yn[i] + rk.cnext * k;
+    const double a = rk.first ? 0.0 : (double)acc[i];
+    acc[i] = a + rk.wacc * k;
+    out[i] = yn[i] + rk.cnext * k;
   } else {
-    f.out[i] = f.yn[i] + rk.dt * (f.acc[i] + rk.wacc * k);
+    out[i] = yn[i] + rk.dt * ((double)acc[i] + rk.wacc * k);
   }
 }
 
@@ -571,9 +599,9 @@ __device__ __forceinline__ void rk_one(const RkStage& rk, const RkField& f, size
 // writes dhp = -d_x qx, qy, B and k_vx = -d_x B (through the RK combine).
 template <int N>
 __global__ void __launch_bounds__(512) k_row_flux(Geom g, const cplx* __restrict__ Es, const cplx* __restrict__ Gs,
-                                                  const double* h, const double* vx, const double* vy,
-                                                  double* __restrict__ dhp, double* __restrict__ qy,
-                                                  double* __restrict__ Bo, RkStage rk, RkField fvx) {
+                                                  const real* h, const real* vx, const real* vy,
+                                                  real* __restrict__ dhp, real* __restrict__ qy,
+                                                  real* __restrict__ Bo, RkStage rk, RkField fvx) {
   ROW_SETUP(N)
   cplx s[E], sx[E], sy[E], hh[E], ux[E], uy[E];
   load_spec_pair<N>(s, Es, ya, t, g.inv_nx);
@@ -595,8 +623,8 @@ __global__ void __launch_bounds__(512) k_row_flux(Geom g, const cplx* __restrict
     const double rxa = sx[r].x * ia, rxb = sx[r].y * ib, rya = sy[r].x * ia, ryb = sy[r].y * ib;
     B[r].x = 0.5 * (ux[r].x * ux[r].x + uy[r].x * uy[r].x) - 0.5 * (rxa * rxa + rya * rya) + g.g * a - 4.5 * sa * sa;
     B[r].y = 0.5 * (ux[r].y * ux[r].y + uy[r].y * uy[r].y) - 0.5 * (rxb * rxb + ryb * ryb) + g.g * b - 4.5 * sb * sb;
-    sx[r] = make_double2(a * ux[r].x - sx[r].x, b * ux[r].y - sx[r].y);  // qx
-    sy[r] = make_double2(a * uy[r].x - sy[r].x, b * uy[r].y - sy[r].y);  // qy
+    sx[r] = make_cplx(a * ux[r].x - sx[r].x, b * ux[r].y - sx[r].y);  // qx
+    sy[r] = make_cplx(a * uy[r].x - sy[r].x, b * uy[r].y - sy[r].y);  // qy
   }
   store_phys_pair<N>(sy, qy, ya, t);
   store_phys_pair<N>(B, Bo, ya, t);
@@ -624,9 +652,9 @@ __global__ void __launch_bounds__(512) k_row_flux(Geom g, const cplx* __restrict
 // Partial sums: mass, Px, Py, energy, |curl v|^2, min h, max h.
 template <int N>
 __global__ void __launch_bounds__(512) k_row_invariants(Geom g, const cplx* __restrict__ Es,
-                                                        const cplx* __restrict__ Gs, const double* __restrict__ h,
-                                                        const double* __restrict__ vx, const double* __restrict__ vy,
-                                                        const double* __restrict__ dyvx, double* partials,
+                                                        const cplx* __restrict__ Gs, const real* __restrict__ h,
+                                                        const real* __restrict__ vx, const real* __restrict__ vy,
+                                                        const real* __restrict__ dyvx, double* partials,
                                                         GmresState* st, int nblocks) {
   constexpr int E = Row<N>::E;
   constexpr int TPF = Row<N>::TPF;
@@ -640,7 +668,7 @@ __global__ void __launch_bounds__(512) k_row_invariants(Geom g, const cplx* __re
   const int ya = rvalid ? ya_raw : g.ny - 2;
   cplx* buf = lds + threadIdx.y * Row<N>::LDS;
   TwiddleSet<N> twx;
-  gather_twiddles<N>(twx, t, g.twx);
+  gather_twiddles<N>(twx, t, TWX(g));
   __shared__ double red[7 * 8];
   __shared__ double outv[8];
   const size_t oa = (size_t)ya * N, ob = oa + N;
@@ -749,7 +777,7 @@ __device__ __forceinline__ double col_weight(int col) { return col == 0 ? 1.0 : 
   const bool valid = col < g.nh;                             \
   cplx* buf = lds + c;                                       \
   TwiddleSet<N> twy;                                         \
-  gather_twiddles<N>(twy, t, g.twy);                         \
+  gather_twiddles<N>(twy, t, TWY(g));                         \
   (void)valid;
 
 // 2D spectra (the Krylov basis, sigma_hat, the residual and the guess
@@ -762,7 +790,7 @@ template <int N>
 __device__ __forceinline__ void load_spec(cplx* v, const cplx* __restrict__ S, int col, int t, bool valid) {
 #pragma unroll
   for (int r = 0; r < Col<N>::E; ++r)
-    v[r] = valid ? S[(size_t)col * N + t + r * Col<N>::TPF] : make_double2(0.0, 0.0);
+    v[r] = valid ? S[(size_t)col * N + t + r * Col<N>::TPF] : make_cplx(0.0, 0.0);
 }
 
 template <int N>
@@ -777,7 +805,7 @@ __device__ __forceinline__ void load_col(cplx* v, const cplx* __restrict__ S, in
 #pragma unroll
   for (int r = 0; r < Col<N>::E; ++r) {
     const int p = t + r * Col<N>::TPF;
-    v[r] = valid ? S[(size_t)p * nh + col] : make_double2(0.0, 0.0);
+    v[r] = valid ? S[(size_t)p * nh + col] : make_cplx(0.0, 0.0);
   }
 }
 
@@ -841,13 +869,13 @@ __global__ void __launch_bounds__(512) k_col_basis_eg(Geom g, const cplx* __rest
   for (int r = 0; r < E; ++r) {
     const int p = t + r * TPF;
     const size_t idx = sidx(g, p, col);
-    cplx x = make_double2(0.0, 0.0);
+    cplx x = make_cplx(0.0, 0.0);
     if (valid) {
       x = W[idx];
       for (int i0 = 0; i0 < j; i0 += 4) {
         cplx b[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) b[q] = i0 + q < j ? V[(i0 + q) * vstride + idx] : make_double2(0.0, 0.0);
+        for (int q = 0; q < 4; ++q) b[q] = i0 + q < j ? V[(i0 + q) * vstride + idx] : make_cplx(0.0, 0.0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const double c = i0 + q < j ? coef[i0 + q] : 0.0;
@@ -877,7 +905,7 @@ __global__ void __launch_bounds__(512) k_col_basis_eg(Geom g, const cplx* __rest
   const bool valid = col < g.nh;                             \
   cplx* buf = lds + chain * (blockDim.x * N) + c;            \
   TwiddleSet<N> twy;                                         \
-  gather_twiddles<N>(twy, t, g.twy);
+  gather_twiddles<N>(twy, t, TWY(g));
 
 // Same result as k_col_basis_eg: V_j = (W - sum_{i<j} s2_i V_i) / beta and
 // its inverse y-transforms E (chain 0) and G (chain 1) computed concurrently.
@@ -898,13 +926,13 @@ __global__ void __launch_bounds__(1024) k_col_basis2(Geom g, const cplx* __restr
   for (int r = 0; r < E; ++r) {
     const int p = t + r * TPF;
     const size_t idx = sidx(g, p, col);
-    cplx x = make_double2(0.0, 0.0);
+    cplx x = make_cplx(0.0, 0.0);
     if (valid) {
       x = W[idx];
       for (int i0 = 0; i0 < j; i0 += 4) {
         cplx b[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) b[q] = i0 + q < j ? V[(i0 + q) * vstride + idx] : make_double2(0.0, 0.0);
+        for (int q = 0; q < 4; ++q) b[q] = i0 + q < j ? V[(i0 + q) * vstride + idx] : make_cplx(0.0, 0.0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const double cf = i0 + q < j ? coef[i0 + q] : 0.0;
@@ -964,7 +992,7 @@ __global__ void __launch_bounds__(1024) k_col_precond_dot2(Geom g, const cplx* _
         for (int q = 0; q < EH; ++q) {
           const int p = t + (chain * EH + q) * TPF;
           const cplx b = V[(i0 + q8) * vstride + sidx(g, p, col)];
-          d += b.x * w[q].x + b.y * w[q].y;
+          d += cdot(b, w[q]);
         }
       }
       a[q8] = wt * d;
@@ -1012,13 +1040,13 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
   for (int q = 0; q < EH; ++q) {
     const int p = t + (chain * EH + q) * TPF;
     const size_t idx = sidx(g, p, col);
-    cplx x = make_double2(0.0, 0.0);
+    cplx x = make_cplx(0.0, 0.0);
     if (valid) {
       x = win[idx];
       for (int i0 = 0; i0 < j; i0 += 4) {
         cplx b[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) b[k] = i0 + k < j ? V[(i0 + k) * vstride + idx] : make_double2(0.0, 0.0);
+        for (int k = 0; k < 4; ++k) b[k] = i0 + k < j ? V[(i0 + k) * vstride + idx] : make_cplx(0.0, 0.0);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const double cf = i0 + k < j ? coef[i0 + k] : 0.0;
@@ -1034,7 +1062,7 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
 #pragma unroll
   for (int q = 0; q < EH; ++q) {
     if (valid) W[sidx(g, t + (chain * EH + q) * TPF, col)] = u[q];
-    nr += u[q].x * u[q].x + u[q].y * u[q].y;
+    nr += cnorm2(u[q]);
   }
   wave_partial(valid ? col_weight(col) * nr : 0.0, red, 0);
   // gather all E positions of u for this chain's transform
@@ -1096,8 +1124,8 @@ __global__ void __launch_bounds__(1024) k_col_precond_new(Geom g, const cplx* __
     const int p = t + (chain * EH + q) * TPF;
     const size_t idx = sidx(g, p, col);
     const cplx z = cscale(cadd(b0[map.at(p)], b1[map.at(p)]), inv_symbol(g, kx, wavenumber(p, N, g.inv_Ly)));
-    vj[q] = make_double2(0.0, 0.0);
-    wj[q] = make_double2(0.0, 0.0);
+    vj[q] = make_cplx(0.0, 0.0);
+    wj[q] = make_cplx(0.0, 0.0);
     if (valid) {
       vj[q] = cscale(W[idx], ib);
       wj[q] = cscale(z, ib);
@@ -1111,8 +1139,8 @@ __global__ void __launch_bounds__(1024) k_col_precond_new(Geom g, const cplx* __
   double dsj = 0.0, dgj = 0.0;  // the i = j terms, from registers
 #pragma unroll
   for (int q = 0; q < EH; ++q) {
-    dsj += vj[q].x * wj[q].x + vj[q].y * wj[q].y;
-    dgj += vj[q].x * vj[q].x + vj[q].y * vj[q].y;
+    dsj += cdot(vj[q], wj[q]);
+    dgj += cnorm2(vj[q]);
   }
   size_t pidx[EH];
 #pragma unroll
@@ -1127,8 +1155,8 @@ __global__ void __launch_bounds__(1024) k_col_precond_new(Geom g, const cplx* __
 #pragma unroll
         for (int q = 0; q < EH; ++q) {
           const cplx b = V[i * vstride + pidx[q]];
-          ds += b.x * wj[q].x + b.y * wj[q].y;
-          dg += b.x * vj[q].x + b.y * vj[q].y;
+          ds += cdot(b, wj[q]);
+          dg += cdot(b, vj[q]);
         }
       } else if (i == j) {
         ds = dsj;
@@ -1181,15 +1209,15 @@ __global__ void __launch_bounds__(512) k_col_update_eg(Geom g, cplx* __restrict_
   for (int r = 0; r < E; ++r) {
     const int p = t + r * TPF;
     const size_t idx = sidx(g, p, col);
-    cplx x = make_double2(0.0, 0.0);
+    cplx x = make_cplx(0.0, 0.0);
     if (valid) {
-      const cplx old = (D || !zero) ? SIG[idx] : make_double2(0.0, 0.0);
+      const cplx old = (D || !zero) ? SIG[idx] : make_cplx(0.0, 0.0);
       if (!zero) {
         x = old;
         for (int i0 = 0; i0 < k; i0 += 4) {
           cplx b[4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) b[q] = i0 + q < k ? V[(i0 + q) * vstride + idx] : make_double2(0.0, 0.0);
+          for (int q = 0; q < 4; ++q) b[q] = i0 + q < k ? V[(i0 + q) * vstride + idx] : make_cplx(0.0, 0.0);
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const double c = i0 + q < k ? coef[i0 + q] : 0.0;
@@ -1216,7 +1244,7 @@ __global__ void __launch_bounds__(512) k_col_guess_eg(Geom g, cplx* __restrict__
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const size_t idx = sidx(g, t + r * TPF, col);
-    cplx x = make_double2(0.0, 0.0);
+    cplx x = make_cplx(0.0, 0.0);
     if (valid) {
       x = cadd(SIG[idx], D[idx]);
       SIG[idx] = x;
@@ -1274,7 +1302,7 @@ __global__ void __launch_bounds__(512) k_col_precond_dot(Geom g, const cplx* __r
         for (int r = 0; r < E; ++r) {
           const int p = t + r * TPF;
           const cplx b = V[(i0 + q) * vstride + sidx(g, p, col)];
-          d += b.x * v[r].x + b.y * v[r].y;
+          d += cdot(b, v[r]);
         }
       }
       a[q] = wt * d;
@@ -1310,7 +1338,7 @@ __global__ void __launch_bounds__(512) k_col_resid(Geom g, const cplx* __restric
   for (int r = 0; r < E; ++r) {
     const int p = t + r * TPF;
     if (!true_only) v[r] = cscale(v[r], inv_symbol(g, kx, wavenumber(p, N, g.inv_Ly)));
-    nr += v[r].x * v[r].x + v[r].y * v[r].y;
+    nr += cnorm2(v[r]);
   }
   if (!true_only) store_spec<N>(v, W, col, t, valid);
   wave_partial(wt * nr, red, 0);
@@ -1322,7 +1350,7 @@ __global__ void __launch_bounds__(512) k_col_resid(Geom g, const cplx* __restric
     for (int r = 0; r < E; ++r) {
       const int p = t + r * TPF;
       const double m = inv_symbol(g, kx, wavenumber(p, N, g.inv_Ly));
-      const double a2 = v[r].x * v[r].x + v[r].y * v[r].y;
+      const double a2 = cnorm2(v[r]);
       nb += a2;
       nbm += a2 * m * m;
     }
@@ -1428,13 +1456,13 @@ __global__ void __launch_bounds__(512) k_col_filter(Geom g, const cplx* __restri
       const bool keep_y = !dealias || 3 * my <= N;
       if (col == 0) {
         const cplx z = v[r], zc = partner[r];
-        cplx a = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));   // kx = 0 mode
-        cplx b = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));  // kx = nx/2 mode
-        if (!keep_y || a.x * a.x + a.y * a.y < T2) a = make_double2(0.0, 0.0);
-        if (dealias || b.x * b.x + b.y * b.y < T2) b = make_double2(0.0, 0.0);
-        v[r] = make_double2(a.x - b.y, a.y + b.x);
+        cplx a = make_cplx(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));   // kx = 0 mode
+        cplx b = make_cplx(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));  // kx = nx/2 mode
+        if (!keep_y || a.x * a.x + a.y * a.y < T2) a = make_cplx(0.0, 0.0);
+        if (dealias || b.x * b.x + b.y * b.y < T2) b = make_cplx(0.0, 0.0);
+        v[r] = make_cplx(a.x - b.y, a.y + b.x);
       } else {
-        if (!(keep_x && keep_y) || v[r].x * v[r].x + v[r].y * v[r].y < T2) v[r] = make_double2(0.0, 0.0);
+        if (!(keep_x && keep_y) || cnorm2(v[r]) < T2) v[r] = make_cplx(0.0, 0.0);
       }
     }
   }
@@ -1470,12 +1498,12 @@ __global__ void __launch_bounds__(512) k_col_tail(Geom g, const cplx* __restrict
       const bool yin = 4 * my > N;
       if (col == 0) {
         const cplx z = v[r], zc = partner[r];
-        const cplx a = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
-        const cplx b = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
+        const cplx a = make_cplx(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
+        const cplx b = make_cplx(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
         if (yin) mx = fmax(mx, sqrt(a.x * a.x + a.y * a.y));
         mx = fmax(mx, sqrt(b.x * b.x + b.y * b.y));  // kx = nx/2 is always outside nx/4
       } else if (yin || 4 * col > g.nx) {
-        mx = fmax(mx, sqrt(v[r].x * v[r].x + v[r].y * v[r].y));
+        mx = fmax(mx, sqrt(cnorm2(v[r])));
       }
     }
   }
@@ -1496,7 +1524,7 @@ __global__ void __launch_bounds__(512) k_col_tail(Geom g, const cplx* __restrict
 
 // out = d/dy f for a physical field (two real columns per complex column).
 template <int N>
-__global__ void __launch_bounds__(512) k_col_dy(Geom g, const double* __restrict__ f, double* __restrict__ out) {
+__global__ void __launch_bounds__(512) k_col_dy(Geom g, const real* __restrict__ f, real* __restrict__ out) {
   COL_SETUP(N)
   cplx v[E];
   load_col<N>(v, reinterpret_cast<const cplx*>(f), g.nh, col, t, valid);
@@ -1509,8 +1537,8 @@ __global__ void __launch_bounds__(512) k_col_dy(Geom g, const double* __restrict
 
 // Fluxes, y part: dh = dhp - d_y qy, k_vy = -d_y B, through the RK combine.
 template <int N>
-__global__ void __launch_bounds__(512) k_col_flux(Geom g, const double* __restrict__ dhp, const double* __restrict__ qy,
-                                                   const double* __restrict__ Bf, RkStage rk, RkField fh, RkField fvy) {
+__global__ void __launch_bounds__(512) k_col_flux(Geom g, const real* __restrict__ dhp, const real* __restrict__ qy,
+                                                   const real* __restrict__ Bf, RkStage rk, RkField fh, RkField fvy) {
   COL_SETUP(N)
   cplx v[E], u[E];
   load_col<N>(v, reinterpret_cast<const cplx*>(qy), g.nh, col, t, valid);
@@ -1563,7 +1591,7 @@ __global__ void __launch_bounds__(kUpdThreads) k_upd(Geom g, cplx* __restrict__ 
   for (int e = 0; e < kUpdEpt; ++e) {
     idx[e] = (size_t)blockIdx.x * (kUpdThreads * kUpdEpt) + e * kUpdThreads + tid;
     const bool ok = idx[e] < total;
-    w[e] = ok ? W[idx[e]] : make_double2(0.0, 0.0);
+    w[e] = ok ? W[idx[e]] : make_cplx(0.0, 0.0);
     wt[e] = ok ? col_weight((int)(idx[e] / g.ny)) : 0.0;  // column-major 2D spectra
   }
   for (int i0 = 0; i0 <= j; i0 += 4) {
@@ -1572,7 +1600,7 @@ __global__ void __launch_bounds__(kUpdThreads) k_upd(Geom g, cplx* __restrict__ 
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int e = 0; e < kUpdEpt; ++e)
-        b[q][e] = (i0 + q <= j && idx[e] < total) ? V[(i0 + q) * vstride + idx[e]] : make_double2(0.0, 0.0);
+        b[q][e] = (i0 + q <= j && idx[e] < total) ? V[(i0 + q) * vstride + idx[e]] : make_cplx(0.0, 0.0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const double s = (i0 + q <= j) ? coef[i0 + q] : 0.0;
@@ -1587,7 +1615,7 @@ __global__ void __launch_bounds__(kUpdThreads) k_upd(Geom g, cplx* __restrict__ 
 #pragma unroll
   for (int e = 0; e < kUpdEpt; ++e) {
     if (idx[e] < total) W[idx[e]] = w[e];
-    nr += wt[e] * (w[e].x * w[e].x + w[e].y * w[e].y);
+    nr += wt[e] * cnorm2(w[e]);
   }
   // value 0: ||w1||^2; value 1 + i: <V_i, w1> (V_i re-read from cache)
   for (int k0 = 0; k0 <= j + 1; k0 += 8) {
@@ -1603,7 +1631,7 @@ __global__ void __launch_bounds__(kUpdThreads) k_upd(Geom g, cplx* __restrict__ 
         for (int e = 0; e < kUpdEpt; ++e) {
           if (idx[e] < total) {
             const cplx b = V[(k - 1) * vstride + idx[e]];
-            d += wt[e] * (b.x * w[e].x + b.y * w[e].y);
+            d += wt[e] * cdot(b, w[e]);
           }
         }
       }
@@ -1621,8 +1649,8 @@ __global__ void __launch_bounds__(kUpdThreads) k_upd(Geom g, cplx* __restrict__ 
 }
 
 // min h and a non-finite flag over (h, vx, vy).
-__global__ void __launch_bounds__(256) k_field_stats(const double* __restrict__ h, const double* __restrict__ vx,
-                                                     const double* __restrict__ vy, size_t n, GmresState* st,
+__global__ void __launch_bounds__(256) k_field_stats(const real* __restrict__ h, const real* __restrict__ vx,
+                                                     const real* __restrict__ vy, size_t n, GmresState* st,
                                                      double* partials, int nblocks) {
   __shared__ double red[2 * 4];
   __shared__ double outv[2];
@@ -1653,13 +1681,7 @@ __global__ void __launch_bounds__(256) k_field_stats(const double* __restrict__ 
 // runtime records at the start and end of that dispatch (kernel timing).
 // ----------------------------------------------------------------------------
 
-static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
-
-void set_launch_events(hipEvent_t start, hipEvent_t stop) {
-  t_ev_start = start;
-  t_ev_stop = stop;
-}
-
+// (t_ev_start / t_ev_stop: namespace sgn, shared by both precisions)
 template <typename K, typename... Args>
 static void launch(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, Args... args) {
   if (t_ev_start) {
@@ -1759,52 +1781,39 @@ static hipError_t allow_lds(const void* fn, size_t bytes) {
   }
 
 template <int N>
-static hipError_t row_r2c_n(const Geom& g, const double* f, cplx* S, hipStream_t s) {
+static hipError_t row_r2c_n(const Geom& g, const real* f, cplx* S, hipStream_t s) {
   ROW_LAUNCH(k_row_r2c<N>, g, f, S);
 }
-hipError_t launch_row_r2c(const Geom& g, const double* f, cplx* S, hipStream_t s) { DISPATCH_NX(row_r2c_n, g, f, S, s) }
 
 template <int N>
-static hipError_t row_c2r_n(const Geom& g, const cplx* S, double* f, hipStream_t s) {
+static hipError_t row_c2r_n(const Geom& g, const cplx* S, real* f, hipStream_t s) {
   ROW_LAUNCH(k_row_c2r<N>, g, S, f);
 }
-hipError_t launch_row_c2r(const Geom& g, const cplx* S, double* f, hipStream_t s) { DISPATCH_NX(row_c2r_n, g, S, f, s) }
 
 template <int N>
-static hipError_t row_dx_n(const Geom& g, const double* f, double* o, hipStream_t s) {
+static hipError_t row_dx_n(const Geom& g, const real* f, real* o, hipStream_t s) {
   ROW_LAUNCH(k_row_dx<N>, g, f, o);
 }
-hipError_t launch_row_dx(const Geom& g, const double* f, double* o, hipStream_t s) { DISPATCH_NX(row_dx_n, g, f, o, s) }
 
 template <int N>
-static hipError_t row_op_n(const Geom& g, int mode, const cplx* E, const cplx* G, const double* h, const double* vx,
-                           const double* vy, cplx* P, cplx* Q, cplx* R1, cplx* R2, int need_b, int pred,
+static hipError_t row_op_n(const Geom& g, int mode, const cplx* E, const cplx* G, const real* h, const real* vx,
+                           const real* vy, cplx* P, cplx* Q, cplx* R1, cplx* R2, int need_b, int pred,
                            const GmresState* st, hipStream_t s) {
   if (mode == 0) ROW_LAUNCH((k_row_op<N, 0>), g, E, G, h, vx, vy, P, Q, R1, R2, need_b, pred, st);
   if (mode == 1) ROW_LAUNCH((k_row_op<N, 1>), g, E, G, h, vx, vy, P, Q, R1, R2, need_b, pred, st);
   ROW_LAUNCH((k_row_op<N, 2>), g, E, G, h, vx, vy, P, Q, R1, R2, need_b, pred, st);
 }
-hipError_t launch_row_op(const Geom& g, int mode, const cplx* E, const cplx* G, const double* h, const double* vx,
-                         const double* vy, cplx* P, cplx* Q, cplx* R1, cplx* R2, int need_b, int pred,
-                         const GmresState* st, hipStream_t s) {
-  DISPATCH_NX(row_op_n, g, mode, E, G, h, vx, vy, P, Q, R1, R2, need_b, pred, st, s)
-}
 
 template <int N>
-static hipError_t row_flux_n(const Geom& g, const cplx* E, const cplx* G, const double* h, const double* vx,
-                             const double* vy, double* dhp, double* qy, double* B, RkStage rk, RkField fvx,
+static hipError_t row_flux_n(const Geom& g, const cplx* E, const cplx* G, const real* h, const real* vx,
+                             const real* vy, real* dhp, real* qy, real* B, RkStage rk, RkField fvx,
                              hipStream_t s) {
   ROW_LAUNCH(k_row_flux<N>, g, E, G, h, vx, vy, dhp, qy, B, rk, fvx);
 }
-hipError_t launch_row_flux(const Geom& g, const cplx* E, const cplx* G, const double* h, const double* vx,
-                           const double* vy, double* dhp, double* qy, double* B, RkStage rk, RkField fvx,
-                           hipStream_t s) {
-  DISPATCH_NX(row_flux_n, g, E, G, h, vx, vy, dhp, qy, B, rk, fvx, s)
-}
 
 template <int N>
-static hipError_t row_invariants_n(const Geom& g, const cplx* E, const cplx* G, const double* h, const double* vx,
-                                   const double* vy, const double* dyvx, double* partials, GmresState* st,
+static hipError_t row_invariants_n(const Geom& g, const cplx* E, const cplx* G, const real* h, const real* vx,
+                                   const real* vy, const real* dyvx, double* partials, GmresState* st,
                                    hipStream_t s) {
   int rpb = 64 / Row<N>::TPF;
   if (rpb < 1) rpb = 1;
@@ -1816,18 +1825,10 @@ static hipError_t row_invariants_n(const Geom& g, const cplx* E, const cplx* G, 
   launch(k_row_invariants<N>, dim3(nb), block, lb, s, g, E, G, h, vx, vy, dyvx, partials, st, nb);
   return hipGetLastError();
 }
-hipError_t launch_row_invariants(const Geom& g, const cplx* E, const cplx* G, const double* h, const double* vx,
-                                 const double* vy, const double* dyvx, double* partials, GmresState* st,
-                                 hipStream_t s) {
-  DISPATCH_NX(row_invariants_n, g, E, G, h, vx, vy, dyvx, partials, st, s)
-}
 
 template <int N>
 static hipError_t col_fwd_eg_n(const Geom& g, const cplx* Ein, cplx* SIG, cplx* Go, hipStream_t s) {
   COL_LAUNCH(k_col_fwd_eg<N>, g, Ein, SIG, Go);
-}
-hipError_t launch_col_fwd_eg(const Geom& g, const cplx* Ein, cplx* SIG, cplx* Go, hipStream_t s) {
-  DISPATCH_NY(col_fwd_eg_n, g, Ein, SIG, Go, s)
 }
 
 template <int N>
@@ -1835,27 +1836,16 @@ static hipError_t col_basis_eg_n(const Geom& g, const cplx* W, cplx* V, size_t v
                                  cplx* Eo, cplx* Go, hipStream_t s) {
   COL_LAUNCH(k_col_basis_eg<N>, g, W, V, vs, j, st, Eo, Go);
 }
-hipError_t launch_col_basis_eg(const Geom& g, const cplx* W, cplx* V, size_t vs, int j, const GmresState* st,
-                               cplx* Eo, cplx* Go, hipStream_t s) {
-  DISPATCH_NY(col_basis_eg_n, g, W, V, vs, j, st, Eo, Go, s)
-}
 
 template <int N>
 static hipError_t col_update_eg_n(const Geom& g, cplx* SIG, const cplx* V, size_t vs, const GmresState* st, cplx* Eo,
                                   cplx* Go, cplx* D, hipStream_t s) {
   COL_LAUNCH(k_col_update_eg<N>, g, SIG, V, vs, st, Eo, Go, D);
 }
-hipError_t launch_col_update_eg(const Geom& g, cplx* SIG, const cplx* V, size_t vs, const GmresState* st, cplx* Eo,
-                                cplx* Go, cplx* D, hipStream_t s) {
-  DISPATCH_NY(col_update_eg_n, g, SIG, V, vs, st, Eo, Go, D, s)
-}
 
 template <int N>
 static hipError_t col_guess_eg_n(const Geom& g, cplx* SIG, const cplx* D, cplx* Eo, cplx* Go, hipStream_t s) {
   COL_LAUNCH(k_col_guess_eg<N>, g, SIG, D, Eo, Go);
-}
-hipError_t launch_col_guess_eg(const Geom& g, cplx* SIG, const cplx* D, cplx* Eo, cplx* Go, hipStream_t s) {
-  DISPATCH_NY(col_guess_eg_n, g, SIG, D, Eo, Go, s)
 }
 
 template <int N>
@@ -1864,10 +1854,6 @@ static hipError_t col_precond_dot_n(const Geom& g, const cplx* P, const cplx* Q,
   const int nb = (int)ColLaunch<N>::grid(g.nh).x;
   COL_LAUNCH(k_col_precond_dot<N>, g, P, Q, V, vs, j, st, W, partials, nb);
 }
-hipError_t launch_col_precond_dot(const Geom& g, const cplx* P, const cplx* Q, const cplx* V, size_t vs, int j,
-                                  GmresState* st, cplx* W, double* partials, hipStream_t s) {
-  DISPATCH_NY(col_precond_dot_n, g, P, Q, V, vs, j, st, W, partials, s)
-}
 
 template <int N>
 static hipError_t col_resid_n(const Geom& g, const cplx* P, const cplx* Q, const cplx* R1, const cplx* R2, int need_b,
@@ -1875,31 +1861,20 @@ static hipError_t col_resid_n(const Geom& g, const cplx* P, const cplx* Q, const
   const int nb = (int)ColLaunch<N>::grid(g.nh).x;
   COL_LAUNCH(k_col_resid<N>, g, P, Q, R1, R2, need_b, flags, st, W, partials, nb);
 }
-hipError_t launch_col_resid(const Geom& g, const cplx* P, const cplx* Q, const cplx* R1, const cplx* R2, int need_b,
-                            int flags, GmresState* st, cplx* W, double* partials, hipStream_t s) {
-  DISPATCH_NY(col_resid_n, g, P, Q, R1, R2, need_b, flags, st, W, partials, s)
-}
 
 template <int N>
 static hipError_t col_inv_n(const Geom& g, const cplx* S, cplx* o, hipStream_t s) {
   COL_LAUNCH(k_col_inv<N>, g, S, o);
 }
-hipError_t launch_col_inv(const Geom& g, const cplx* S, cplx* o, hipStream_t s) { DISPATCH_NY(col_inv_n, g, S, o, s) }
 
 template <int N>
 static hipError_t col_apply_n(const Geom& g, const cplx* P, const cplx* Q, int precond, cplx* o, hipStream_t s) {
   COL_LAUNCH(k_col_apply<N>, g, P, Q, precond, o);
 }
-hipError_t launch_col_apply(const Geom& g, const cplx* P, const cplx* Q, int precond, cplx* o, hipStream_t s) {
-  DISPATCH_NY(col_apply_n, g, P, Q, precond, o, s)
-}
 
 template <int N>
 static hipError_t col_filter_n(const Geom& g, const cplx* Sx, int op, double thr, cplx* o, hipStream_t s) {
   COL_LAUNCH(k_col_filter<N>, g, Sx, op, thr, o);
-}
-hipError_t launch_col_filter(const Geom& g, const cplx* Sx, int op, double thr, cplx* o, hipStream_t s) {
-  DISPATCH_NY(col_filter_n, g, Sx, op, thr, o, s)
 }
 
 template <int N>
@@ -1907,24 +1882,16 @@ static hipError_t col_tail_n(const Geom& g, const cplx* Sx, GmresState* st, doub
   const int nb = (int)ColLaunch<N>::grid(g.nh).x;
   COL_LAUNCH(k_col_tail<N>, g, Sx, st, partials, nb);
 }
-hipError_t launch_col_tail(const Geom& g, const cplx* Sx, GmresState* st, double* partials, hipStream_t s) {
-  DISPATCH_NY(col_tail_n, g, Sx, st, partials, s)
-}
 
 template <int N>
-static hipError_t col_dy_n(const Geom& g, const double* f, double* o, hipStream_t s) {
+static hipError_t col_dy_n(const Geom& g, const real* f, real* o, hipStream_t s) {
   COL_LAUNCH(k_col_dy<N>, g, f, o);
 }
-hipError_t launch_col_dy(const Geom& g, const double* f, double* o, hipStream_t s) { DISPATCH_NY(col_dy_n, g, f, o, s) }
 
 template <int N>
-static hipError_t col_flux_n(const Geom& g, const double* dhp, const double* qy, const double* B, RkStage rk,
+static hipError_t col_flux_n(const Geom& g, const real* dhp, const real* qy, const real* B, RkStage rk,
                              RkField fh, RkField fvy, hipStream_t s) {
   COL_LAUNCH(k_col_flux<N>, g, dhp, qy, B, rk, fh, fvy);
-}
-hipError_t launch_col_flux(const Geom& g, const double* dhp, const double* qy, const double* B, RkStage rk, RkField fh,
-                           RkField fvy, hipStream_t s) {
-  DISPATCH_NY(col_flux_n, g, dhp, qy, B, rk, fh, fvy, s)
 }
 
 // Chain-parallel Arnoldi passes: usable when the chained block fits.
@@ -1954,7 +1921,7 @@ struct Chain {
 };
 
 template <int N>
-static hipError_t row_matvec3_n(const Geom& g, const cplx* E, const cplx* G, const double* h, cplx* P, cplx* Q,
+static hipError_t row_matvec3_n(const Geom& g, const cplx* E, const cplx* G, const real* h, cplx* P, cplx* Q,
                                 const GmresState* st, hipStream_t s) {
   if constexpr (!Chain<N>::row_ok) {
     return hipErrorNotSupported;
@@ -1967,10 +1934,6 @@ static hipError_t row_matvec3_n(const Geom& g, const cplx* E, const cplx* G, con
     launch(k_row_matvec3<N>, dim3((g.ny / 2) / r), block, lb, s, g, E, G, h, P, Q, st);
     return hipGetLastError();
   }
-}
-hipError_t launch_row_matvec3(const Geom& g, const cplx* E, const cplx* G, const double* h, cplx* P, cplx* Q,
-                              const GmresState* st, hipStream_t s) {
-  DISPATCH_NX(row_matvec3_n, g, E, G, h, P, Q, st, s)
 }
 
 template <int N>
@@ -2005,10 +1968,6 @@ static hipError_t col_basis2_n(const Geom& g, const cplx* W, cplx* V, size_t vs,
   launch(k_col_basis2<N>, dim3((g.nh + tc - 1) / tc), block, lb, s, g, W, V, vs, j, st, Eo, Go);
   return hipGetLastError();
 }
-hipError_t launch_col_basis2(const Geom& g, const cplx* W, cplx* V, size_t vs, int j, const GmresState* st, cplx* Eo,
-                             cplx* Go, hipStream_t s) {
-  DISPATCH_NY(col_basis2_n, g, W, V, vs, j, st, Eo, Go, s)
-}
 
 template <int N>
 static hipError_t col_precond_dot2_n(const Geom& g, const cplx* P, const cplx* Q, const cplx* V, size_t vs, int j,
@@ -2021,10 +1980,6 @@ static hipError_t col_precond_dot2_n(const Geom& g, const cplx* P, const cplx* Q
   if (e != hipSuccess) return e;
   launch(k_col_precond_dot2<N>, dim3(nb), block, lb, s, g, P, Q, V, vs, j, st, W, partials, nb);
   return hipGetLastError();
-}
-hipError_t launch_col_precond_dot2(const Geom& g, const cplx* P, const cplx* Q, const cplx* V, size_t vs, int j,
-                                   GmresState* st, cplx* W, double* partials, hipStream_t s) {
-  DISPATCH_NY(col_precond_dot2_n, g, P, Q, V, vs, j, st, W, partials, s)
 }
 
 template <int N>
@@ -2039,10 +1994,6 @@ static hipError_t col_proj_n(const Geom& g, const cplx* win, cplx* W, const cplx
   launch(k_col_proj<N>, dim3(nb), block, lb, s, g, win, W, V, vs, j, st, Eo, Go, partials, nb);
   return hipGetLastError();
 }
-hipError_t launch_col_proj(const Geom& g, const cplx* win, cplx* W, const cplx* V, size_t vs, int j, GmresState* st,
-                           cplx* Eo, cplx* Go, double* partials, hipStream_t s) {
-  DISPATCH_NY(col_proj_n, g, win, W, V, vs, j, st, Eo, Go, partials, s)
-}
 
 template <int N>
 static hipError_t col_precond_new_n(const Geom& g, const cplx* P, const cplx* Q, const cplx* W, cplx* V, cplx* Z,
@@ -2056,28 +2007,115 @@ static hipError_t col_precond_new_n(const Geom& g, const cplx* P, const cplx* Q,
   launch(k_col_precond_new<N>, dim3(nb), block, lb, s, g, P, Q, W, V, Z, vs, j, st, partials, nb);
   return hipGetLastError();
 }
-hipError_t launch_col_precond_new(const Geom& g, const cplx* P, const cplx* Q, const cplx* W, cplx* V, cplx* Z,
-                                  size_t vs, int j, GmresState* st, double* partials, hipStream_t s) {
-  DISPATCH_NY(col_precond_new_n, g, P, Q, W, V, Z, vs, j, st, partials, s)
-}
 
 int upd_blocks(const Geom& g) {
   const size_t total = (size_t)g.nh * g.ny;
   return (int)((total + kUpdThreads * kUpdEpt - 1) / (kUpdThreads * kUpdEpt));
 }
 
-hipError_t launch_upd(const Geom& g, cplx* W, const cplx* V, size_t vs, int j, GmresState* st, double* partials,
+
+
+// ---- public launchers of this precision (untyped pointers, see sgn_launch.hpp)
+#define R_(p) static_cast<const real*>(p)
+#define W_(p) static_cast<real*>(p)
+#define RC_(p) static_cast<const cplx*>(p)
+#define WC_(p) static_cast<cplx*>(p)
+
+hipError_t launch_row_r2c(const Geom& g, const void* f, void* S, hipStream_t s) {
+  DISPATCH_NX(row_r2c_n, g, R_(f), WC_(S), s)
+}
+hipError_t launch_row_c2r(const Geom& g, const void* S, void* f, hipStream_t s) {
+  DISPATCH_NX(row_c2r_n, g, RC_(S), W_(f), s)
+}
+hipError_t launch_row_dx(const Geom& g, const void* f, void* o, hipStream_t s) {
+  DISPATCH_NX(row_dx_n, g, R_(f), W_(o), s)
+}
+hipError_t launch_row_op(const Geom& g, int mode, const void* E, const void* G, const void* h, const void* vx,
+                         const void* vy, void* P, void* Q, void* R1, void* R2, int need_b, int pred,
+                         const GmresState* st, hipStream_t s) {
+  DISPATCH_NX(row_op_n, g, mode, RC_(E), RC_(G), R_(h), R_(vx), R_(vy), WC_(P), WC_(Q), WC_(R1), WC_(R2), need_b,
+              pred, st, s)
+}
+hipError_t launch_row_flux(const Geom& g, const void* E, const void* G, const void* h, const void* vx, const void* vy,
+                           void* dhp, void* qy, void* B, RkStage rk, RkField fvx, hipStream_t s) {
+  DISPATCH_NX(row_flux_n, g, RC_(E), RC_(G), R_(h), R_(vx), R_(vy), W_(dhp), W_(qy), W_(B), rk, fvx, s)
+}
+hipError_t launch_row_invariants(const Geom& g, const void* E, const void* G, const void* h, const void* vx,
+                                 const void* vy, const void* dyvx, double* partials, GmresState* st, hipStream_t s) {
+  DISPATCH_NX(row_invariants_n, g, RC_(E), RC_(G), R_(h), R_(vx), R_(vy), R_(dyvx), partials, st, s)
+}
+hipError_t launch_row_matvec3(const Geom& g, const void* E, const void* G, const void* h, void* P, void* Q,
+                              const GmresState* st, hipStream_t s) {
+  DISPATCH_NX(row_matvec3_n, g, RC_(E), RC_(G), R_(h), WC_(P), WC_(Q), st, s)
+}
+hipError_t launch_col_fwd_eg(const Geom& g, const void* Ein, void* SIG, void* Go, hipStream_t s) {
+  DISPATCH_NY(col_fwd_eg_n, g, RC_(Ein), WC_(SIG), WC_(Go), s)
+}
+hipError_t launch_col_basis_eg(const Geom& g, const void* W, void* V, size_t vs, int j, const GmresState* st, void* Eo,
+                               void* Go, hipStream_t s) {
+  DISPATCH_NY(col_basis_eg_n, g, RC_(W), WC_(V), vs, j, st, WC_(Eo), WC_(Go), s)
+}
+hipError_t launch_col_basis2(const Geom& g, const void* W, void* V, size_t vs, int j, const GmresState* st, void* Eo,
+                             void* Go, hipStream_t s) {
+  DISPATCH_NY(col_basis2_n, g, RC_(W), WC_(V), vs, j, st, WC_(Eo), WC_(Go), s)
+}
+hipError_t launch_col_update_eg(const Geom& g, void* SIG, const void* V, size_t vs, const GmresState* st, void* Eo,
+                                void* Go, void* D, hipStream_t s) {
+  DISPATCH_NY(col_update_eg_n, g, WC_(SIG), RC_(V), vs, st, WC_(Eo), WC_(Go), WC_(D), s)
+}
+hipError_t launch_col_guess_eg(const Geom& g, void* SIG, const void* D, void* Eo, void* Go, hipStream_t s) {
+  DISPATCH_NY(col_guess_eg_n, g, WC_(SIG), RC_(D), WC_(Eo), WC_(Go), s)
+}
+hipError_t launch_col_precond_dot(const Geom& g, const void* P, const void* Q, const void* V, size_t vs, int j,
+                                  GmresState* st, void* W, double* partials, hipStream_t s) {
+  DISPATCH_NY(col_precond_dot_n, g, RC_(P), RC_(Q), RC_(V), vs, j, st, WC_(W), partials, s)
+}
+hipError_t launch_col_precond_dot2(const Geom& g, const void* P, const void* Q, const void* V, size_t vs, int j,
+                                   GmresState* st, void* W, double* partials, hipStream_t s) {
+  DISPATCH_NY(col_precond_dot2_n, g, RC_(P), RC_(Q), RC_(V), vs, j, st, WC_(W), partials, s)
+}
+hipError_t launch_col_proj(const Geom& g, const void* win, void* W, const void* V, size_t vs, int j, GmresState* st,
+                           void* Eo, void* Go, double* partials, hipStream_t s) {
+  DISPATCH_NY(col_proj_n, g, RC_(win), WC_(W), RC_(V), vs, j, st, WC_(Eo), WC_(Go), partials, s)
+}
+hipError_t launch_col_precond_new(const Geom& g, const void* P, const void* Q, const void* W, void* V, void* Z,
+                                  size_t vs, int j, GmresState* st, double* partials, hipStream_t s) {
+  DISPATCH_NY(col_precond_new_n, g, RC_(P), RC_(Q), RC_(W), WC_(V), WC_(Z), vs, j, st, partials, s)
+}
+hipError_t launch_col_resid(const Geom& g, const void* P, const void* Q, const void* R1, const void* R2, int need_b,
+                            int flags, GmresState* st, void* W, double* partials, hipStream_t s) {
+  DISPATCH_NY(col_resid_n, g, RC_(P), RC_(Q), RC_(R1), RC_(R2), need_b, flags, st, WC_(W), partials, s)
+}
+hipError_t launch_col_inv(const Geom& g, const void* S, void* o, hipStream_t s) {
+  DISPATCH_NY(col_inv_n, g, RC_(S), WC_(o), s)
+}
+hipError_t launch_col_apply(const Geom& g, const void* P, const void* Q, int precond, void* o, hipStream_t s) {
+  DISPATCH_NY(col_apply_n, g, RC_(P), RC_(Q), precond, WC_(o), s)
+}
+hipError_t launch_col_filter(const Geom& g, const void* Sx, int op, double thr, void* o, hipStream_t s) {
+  DISPATCH_NY(col_filter_n, g, RC_(Sx), op, thr, WC_(o), s)
+}
+hipError_t launch_col_tail(const Geom& g, const void* Sx, GmresState* st, double* partials, hipStream_t s) {
+  DISPATCH_NY(col_tail_n, g, RC_(Sx), st, partials, s)
+}
+hipError_t launch_col_dy(const Geom& g, const void* f, void* o, hipStream_t s) {
+  DISPATCH_NY(col_dy_n, g, R_(f), W_(o), s)
+}
+hipError_t launch_col_flux(const Geom& g, const void* dhp, const void* qy, const void* B, RkStage rk, RkField fh,
+                           RkField fvy, hipStream_t s) {
+  DISPATCH_NY(col_flux_n, g, R_(dhp), R_(qy), R_(B), rk, fh, fvy, s)
+}
+hipError_t launch_upd(const Geom& g, void* W, const void* V, size_t vs, int j, GmresState* st, double* partials,
                       hipStream_t s) {
   const int nb = upd_blocks(g);
-  launch(k_upd, dim3(nb), dim3(kUpdThreads), 0, s, g, W, V, vs, j, st, partials, nb);
+  launch(k_upd, dim3(nb), dim3(kUpdThreads), 0, s, g, WC_(W), RC_(V), vs, j, st, partials, nb);
   return hipGetLastError();
 }
-
-hipError_t launch_field_stats(const double* h, const double* vx, const double* vy, size_t n, GmresState* st,
+hipError_t launch_field_stats(const Geom&, const void* h, const void* vx, const void* vy, size_t n, GmresState* st,
                               double* partials, hipStream_t s) {
   int nb = (int)((n + 255) / 256);
   if (nb > 1024) nb = 1024;
-  launch(k_field_stats, dim3(nb), dim3(256), 0, s, h, vx, vy, n, st, partials, nb);
+  launch(k_field_stats, dim3(nb), dim3(256), 0, s, R_(h), R_(vx), R_(vy), n, st, partials, nb);
   return hipGetLastError();
 }
 
@@ -2091,4 +2129,5 @@ int max_partial_blocks(const Geom& g) {
   return m;
 }
 
+}  // namespace SGN_NS
 }  // namespace sgn

@@ -1,61 +1,129 @@
-// Host-side launchers of the SGN kernels (defined in sgn_kernels.hip).
+// Host-side launchers of the SGN kernels.
+//
+// The kernels are compiled once per precision (sgn_kernels.hip with
+// SGN_PREC=64 into namespace sgn::p64, with SGN_PREC=32 into sgn::p32); the
+// launchers of namespace sgn dispatch on Geom::fp32.  Field and spectrum
+// pointers are untyped: FP64 arrays (double, double2) in FP64 mode, FP32
+// arrays (float, float2) in the mixed-precision mode.  Reduction scratch and
+// the GMRES state are FP64 in both.
 #pragma once
 #include "sgn_internal.hpp"
 
+// X(name, parameter list, argument list)
+#define SGN_LAUNCHERS(X)                                                                                        \
+  X(row_r2c, (const Geom& g, const void* f, void* S, hipStream_t s), (g, f, S, s))                             \
+  X(row_c2r, (const Geom& g, const void* S, void* f, hipStream_t s), (g, S, f, s))                             \
+  X(row_dx, (const Geom& g, const void* f, void* o, hipStream_t s), (g, f, o, s))                              \
+  X(row_op,                                                                                                     \
+    (const Geom& g, int mode, const void* E, const void* G, const void* h, const void* vx, const void* vy,      \
+     void* P, void* Q, void* R1, void* R2, int need_b, int pred, const GmresState* st, hipStream_t s),           \
+    (g, mode, E, G, h, vx, vy, P, Q, R1, R2, need_b, pred, st, s))                                              \
+  X(row_flux,                                                                                                   \
+    (const Geom& g, const void* E, const void* G, const void* h, const void* vx, const void* vy, void* dhp,     \
+     void* qy, void* B, RkStage rk, RkField fvx, hipStream_t s),                                                \
+    (g, E, G, h, vx, vy, dhp, qy, B, rk, fvx, s))                                                               \
+  X(row_invariants,                                                                                             \
+    (const Geom& g, const void* E, const void* G, const void* h, const void* vx, const void* vy,                \
+     const void* dyvx, double* partials, GmresState* st, hipStream_t s),                                        \
+    (g, E, G, h, vx, vy, dyvx, partials, st, s))                                                                \
+  X(row_matvec3,                                                                                                \
+    (const Geom& g, const void* E, const void* G, const void* h, void* P, void* Q, const GmresState* st,        \
+     hipStream_t s),                                                                                            \
+    (g, E, G, h, P, Q, st, s))                                                                                  \
+  X(col_fwd_eg, (const Geom& g, const void* Ein, void* SIG, void* Go, hipStream_t s), (g, Ein, SIG, Go, s))    \
+  X(col_basis_eg,                                                                                               \
+    (const Geom& g, const void* W, void* V, size_t vs, int j, const GmresState* st, void* Eo, void* Go,         \
+     hipStream_t s),                                                                                            \
+    (g, W, V, vs, j, st, Eo, Go, s))                                                                            \
+  X(col_basis2,                                                                                                 \
+    (const Geom& g, const void* W, void* V, size_t vs, int j, const GmresState* st, void* Eo, void* Go,         \
+     hipStream_t s),                                                                                            \
+    (g, W, V, vs, j, st, Eo, Go, s))                                                                            \
+  X(col_update_eg,                                                                                              \
+    (const Geom& g, void* SIG, const void* V, size_t vs, const GmresState* st, void* Eo, void* Go, void* D,     \
+     hipStream_t s),                                                                                            \
+    (g, SIG, V, vs, st, Eo, Go, D, s))                                                                          \
+  X(col_guess_eg, (const Geom& g, void* SIG, const void* D, void* Eo, void* Go, hipStream_t s),                \
+    (g, SIG, D, Eo, Go, s))                                                                                     \
+  X(col_precond_dot,                                                                                            \
+    (const Geom& g, const void* P, const void* Q, const void* V, size_t vs, int j, GmresState* st, void* W,     \
+     double* partials, hipStream_t s),                                                                          \
+    (g, P, Q, V, vs, j, st, W, partials, s))                                                                    \
+  X(col_precond_dot2,                                                                                           \
+    (const Geom& g, const void* P, const void* Q, const void* V, size_t vs, int j, GmresState* st, void* W,     \
+     double* partials, hipStream_t s),                                                                          \
+    (g, P, Q, V, vs, j, st, W, partials, s))                                                                    \
+  X(col_proj,                                                                                                   \
+    (const Geom& g, const void* win, void* W, const void* V, size_t vs, int j, GmresState* st, void* Eo,        \
+     void* Go, double* partials, hipStream_t s),                                                                \
+    (g, win, W, V, vs, j, st, Eo, Go, partials, s))                                                             \
+  X(col_precond_new,                                                                                            \
+    (const Geom& g, const void* P, const void* Q, const void* W, void* V, void* Z, size_t vs, int j,            \
+     GmresState* st, double* partials, hipStream_t s),                                                          \
+    (g, P, Q, W, V, Z, vs, j, st, partials, s))                                                                 \
+  X(col_resid,                                                                                                  \
+    (const Geom& g, const void* P, const void* Q, const void* R1, const void* R2, int need_b, int flags,        \
+     GmresState* st, void* W, double* partials, hipStream_t s),                                                 \
+    (g, P, Q, R1, R2, need_b, flags, st, W, partials, s))                                                       \
+  X(col_inv, (const Geom& g, const void* S, void* o, hipStream_t s), (g, S, o, s))                             \
+  X(col_apply, (const Geom& g, const void* P, const void* Q, int precond, void* o, hipStream_t s),             \
+    (g, P, Q, precond, o, s))                                                                                   \
+  X(col_filter, (const Geom& g, const void* Sx, int op, double thr, void* o, hipStream_t s),                   \
+    (g, Sx, op, thr, o, s))                                                                                     \
+  X(col_tail, (const Geom& g, const void* Sx, GmresState* st, double* partials, hipStream_t s),                 \
+    (g, Sx, st, partials, s))                                                                                   \
+  X(col_dy, (const Geom& g, const void* f, void* o, hipStream_t s), (g, f, o, s))                              \
+  X(col_flux,                                                                                                   \
+    (const Geom& g, const void* dhp, const void* qy, const void* B, RkStage rk, RkField fh, RkField fvy,        \
+     hipStream_t s),                                                                                            \
+    (g, dhp, qy, B, rk, fh, fvy, s))                                                                            \
+  X(upd, (const Geom& g, void* W, const void* V, size_t vs, int j, GmresState* st, double* partials,           \
+          hipStream_t s),                                                                                       \
+    (g, W, V, vs, j, st, partials, s))                                                                          \
+  X(field_stats,                                                                                                \
+    (const Geom& g, const void* h, const void* vx, const void* vy, size_t n, GmresState* st, double* partials,  \
+     hipStream_t s),                                                                                            \
+    (g, h, vx, vy, n, st, partials, s))
+
+// Meaning of the launchers (all stream-ordered; none allocates):
+//   row_r2c / row_c2r: physical <-> x-half spectra; row_dx: d/dx;
+//   row_op: x part of the elliptic operator (mode 0), or of the residual with
+//     b = -div v (mode 1) or an explicit b (mode 2);
+//   row_matvec3: mode 0 of row_op with three concurrent transform chains;
+//   row_flux / col_flux: fluxes, Bernoulli function and the RK4 combine;
+//   row_invariants / col_tail: invariant densities and the spectral tail;
+//   col_fwd_eg: sigma's 2D spectrum and the inverse y-transforms E, G;
+//   col_basis_eg / col_basis2 / col_precond_dot / col_precond_dot2 / upd: the
+//     four-kernel Arnoldi step (one- and two-chain variants);
+//   col_proj / col_precond_new (with row_matvec3): the three-kernel step;
+//   col_update_eg: sigma_hat += V y (and the guess increment D);
+//   col_guess_eg: sigma_hat += D; col_resid: start of a GMRES cycle;
+//   col_inv / col_apply / col_filter / col_dy: building blocks;
+//   field_stats: min h and a non-finite flag over the state.
+
 namespace sgn {
 
-typedef double2 cplx;
+#define SGN_DECLARE_LAUNCHER(name, params, args) hipError_t launch_##name params;
+SGN_LAUNCHERS(SGN_DECLARE_LAUNCHER)
 
-hipError_t launch_row_r2c(const Geom& g, const double* f, cplx* S, hipStream_t s);
-hipError_t launch_row_c2r(const Geom& g, const cplx* S, double* f, hipStream_t s);
-hipError_t launch_row_dx(const Geom& g, const double* f, double* o, hipStream_t s);
-hipError_t launch_row_op(const Geom& g, int mode, const cplx* E, const cplx* G, const double* h, const double* vx,
-                         const double* vy, cplx* P, cplx* Q, cplx* R1, cplx* R2, int need_b, int pred,
-                         const GmresState* st, hipStream_t s);
-hipError_t launch_row_flux(const Geom& g, const cplx* E, const cplx* G, const double* h, const double* vx,
-                           const double* vy, double* dhp, double* qy, double* B, RkStage rk, RkField fvx,
-                           hipStream_t s);
-hipError_t launch_row_invariants(const Geom& g, const cplx* E, const cplx* G, const double* h, const double* vx,
-                                 const double* vy, const double* dyvx, double* partials, GmresState* st,
-                                 hipStream_t s);
-hipError_t launch_col_fwd_eg(const Geom& g, const cplx* Ein, cplx* SIG, cplx* Go, hipStream_t s);
-hipError_t launch_col_basis_eg(const Geom& g, const cplx* W, cplx* V, size_t vs, int j, const GmresState* st,
-                               cplx* Eo, cplx* Go, hipStream_t s);
-// D (may be null): D += (updated - previous) sigma_hat, the guess increment
-hipError_t launch_col_update_eg(const Geom& g, cplx* SIG, const cplx* V, size_t vs, const GmresState* st, cplx* Eo,
-                                cplx* Go, cplx* D, hipStream_t s);
-// SIG += D, then E, G of SIG (extrapolated initial guess of an RK stage)
-hipError_t launch_col_guess_eg(const Geom& g, cplx* SIG, const cplx* D, cplx* Eo, cplx* Go, hipStream_t s);
-hipError_t launch_col_precond_dot(const Geom& g, const cplx* P, const cplx* Q, const cplx* V, size_t vs, int j,
-                                  GmresState* st, cplx* W, double* partials, hipStream_t s);
-hipError_t launch_col_resid(const Geom& g, const cplx* P, const cplx* Q, const cplx* R1, const cplx* R2, int need_b,
-                            int flags, GmresState* st, cplx* W, double* partials, hipStream_t s);
-hipError_t launch_col_inv(const Geom& g, const cplx* S, cplx* o, hipStream_t s);
-hipError_t launch_col_apply(const Geom& g, const cplx* P, const cplx* Q, int precond, cplx* o, hipStream_t s);
-hipError_t launch_col_filter(const Geom& g, const cplx* Sx, int op, double thr, cplx* o, hipStream_t s);
-hipError_t launch_col_tail(const Geom& g, const cplx* Sx, GmresState* st, double* partials, hipStream_t s);
-hipError_t launch_col_dy(const Geom& g, const double* f, double* o, hipStream_t s);
-hipError_t launch_col_flux(const Geom& g, const double* dhp, const double* qy, const double* B, RkStage rk, RkField fh,
-                           RkField fvy, hipStream_t s);
-hipError_t launch_upd(const Geom& g, cplx* W, const cplx* V, size_t vs, int j, GmresState* st, double* partials,
-                      hipStream_t s);
-hipError_t launch_field_stats(const double* h, const double* vx, const double* vy, size_t n, GmresState* st,
-                              double* partials, hipStream_t s);
+// Largest number of blocks any reduction kernel launches for this grid.
 int max_partial_blocks(const Geom& g);
+// Whether this grid can use the chain-parallel Arnoldi passes.
+bool chained_ok(const Geom& g);
 // The next kernel launch records these events at its start and end (null: none).
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
-// chain-parallel Arnoldi passes (same results as row_op mode 0, col_basis_eg,
-// col_precond_dot); chained_ok tells whether this grid can use them
+// Events for the next launch (consumed by it); shared by both precisions.
+extern thread_local hipEvent_t t_ev_start, t_ev_stop;
+
+namespace p64 {
+SGN_LAUNCHERS(SGN_DECLARE_LAUNCHER)
+int max_partial_blocks(const Geom& g);
 bool chained_ok(const Geom& g);
-hipError_t launch_row_matvec3(const Geom& g, const cplx* E, const cplx* G, const double* h, cplx* P, cplx* Q,
-                              const GmresState* st, hipStream_t s);
-hipError_t launch_col_basis2(const Geom& g, const cplx* W, cplx* V, size_t vs, int j, const GmresState* st, cplx* Eo,
-                             cplx* Go, hipStream_t s);
-hipError_t launch_col_proj(const Geom& g, const cplx* win, cplx* W, const cplx* V, size_t vs, int j, GmresState* st,
-                           cplx* Eo, cplx* Go, double* partials, hipStream_t s);
-hipError_t launch_col_precond_new(const Geom& g, const cplx* P, const cplx* Q, const cplx* W, cplx* V, cplx* Z,
-                                  size_t vs, int j, GmresState* st, double* partials, hipStream_t s);
-hipError_t launch_col_precond_dot2(const Geom& g, const cplx* P, const cplx* Q, const cplx* V, size_t vs, int j,
-                                   GmresState* st, cplx* W, double* partials, hipStream_t s);
+}  // namespace p64
+namespace p32 {
+SGN_LAUNCHERS(SGN_DECLARE_LAUNCHER)
+int max_partial_blocks(const Geom& g);
+bool chained_ok(const Geom& g);
+}  // namespace p32
 
 }  // namespace sgn

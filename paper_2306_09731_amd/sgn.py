@@ -22,6 +22,7 @@ SGN_ERR_NOT_CONVERGED = 4
 SGN_ERR_CAVITATION = 5
 SGN_ERR_NONFINITE = 6
 SGN_FP64 = 0
+SGN_FP32_MIXED = 1
 SGN_GUESS_PREVIOUS = 0
 SGN_GUESS_STAGE_INCREMENT = 1
 SGN_KERNEL_ROW_MATVEC = 0
@@ -171,14 +172,21 @@ def _check(ctx: Context | None, status: int, allow=(SGN_OK,)):
     raise SgnError(status, msg)
 
 
+def field_dtype(cfg: sgn_config):
+    """torch dtype of the fields for this configuration's precision."""
+    import torch
+    return torch.float32 if cfg.precision == SGN_FP32_MIXED else torch.float64
+
+
 def _field(ctx: Context, t, name: str):
     import torch
     cfg = ctx.cfg
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor")
-    if t.dtype != torch.float64 or not t.is_contiguous() or t.device != ctx.device \
+    dt = field_dtype(cfg)
+    if t.dtype != dt or not t.is_contiguous() or t.device != ctx.device \
             or tuple(t.shape) != (cfg.ny, cfg.nx):
-        raise ValueError(f"{name} must be a contiguous float64 tensor of shape ({cfg.ny}, {cfg.nx}) "
+        raise ValueError(f"{name} must be a contiguous {dt} tensor of shape ({cfg.ny}, {cfg.nx}) "
                          f"on {ctx.device}")
     return ctypes.c_void_p(t.data_ptr())
 

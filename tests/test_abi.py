@@ -45,7 +45,7 @@ def test_config_default_and_struct_layout():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("nx", 100), ("ny", 4), ("nx", 8192), ("gmres_restart", 65), ("precision", 1), ("batch", 2),
+    ("nx", 100), ("ny", 4), ("nx", 8192), ("gmres_restart", 65), ("precision", 2), ("batch", 2),
 ])
 def test_workspace_bytes_rejects_unsupported(field, value):
     cfg = sgn.config_default(128, 64, 10.0, 5.0)
@@ -69,6 +69,14 @@ def test_invalid_config(field, value):
     h = ctypes.c_void_p()
     assert lib.sgn_init(ctypes.byref(cfg), ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(h)) \
         == sgn.SGN_ERR_INVALID_ARG
+
+
+def test_workspace_fp32_mode_halves_the_fields():
+    a = sgn.sgn_workspace_bytes(sgn.config_default(256, 128, 10.0, 5.0))
+    b = sgn.sgn_workspace_bytes(sgn.config_default(256, 128, 10.0, 5.0, precision=sgn.SGN_FP32_MIXED))
+    nfields = 21 + 15
+    # FP32 fields are half as large (both twiddle tables exist in either mode)
+    assert a - b == nfields * 256 * 128 * 4
 
 
 def test_workspace_stage_increment_guess_adds_four_fields():
