@@ -111,6 +111,65 @@ def timed_guess_run(sgn, torch, box, state, w, dev, args):
             "note": "same tolerance; the first step of each call uses the plain warm start"}
 
 
+PRECISION_WORKLOAD = "gaussian_2048x2048"
+
+
+def precision_form(sgn, torch, dev, args):
+    """The 2048x2048 Gaussian (h = 1 + 0.5 exp(-r^2), v = 0) in FP64 and in the
+    mixed-precision mode (FP32 fields and transforms, FP64 reductions): K
+    timed steps after W warm-up steps each, the Arnoldi kernel class with the
+    largest share of the FP32 run against the HBM roofline, and the FP32 - FP64
+    difference after the same steps."""
+    import numpy as np
+    from sgn_inputs import workload
+    box, state, w = workload(PRECISION_WORKLOAD)
+    steps = max(1, min(args.steps, 20))
+    warm = min(args.warmup, 5)
+    out, final = {"workload": PRECISION_WORKLOAD, "nx": box.nx, "ny": box.ny, "steps": steps, "warmup": warm}, {}
+    for name, prec, dtype in (("fp64", sgn.SGN_FP64, torch.float64), ("fp32_mixed", sgn.SGN_FP32_MIXED, torch.float32)):
+        cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"], gmres_restart=w["restart"],
+                                 krasny=KRASNY, precision=prec)
+        ctx = sgn.sgn_init(cfg, dev)
+        f = [torch.from_numpy(np.ascontiguousarray(a)).to(dev).to(dtype) for a in state]
+        if warm:
+            sgn.sgn_rk4_step(ctx, *f, w["dt"], warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = sgn.sgn_rk4_step(ctx, *f, w["dt"], steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res = {"value": box.nx * box.ny * steps / el, "unit": UNIT, "ms_per_step": el * 1e3 / steps,
+               "iters_per_solve_mean": info.total_iters / max(info.solves, 1),
+               "gmres_tol_effective": max(w["tol"], 1e-6) if prec == sgn.SGN_FP32_MIXED else w["tol"]}
+        final[name] = [t.double().cpu().numpy() for t in f[:2]]
+        if prec == sgn.SGN_FP32_MIXED:
+            # time every Arnoldi kernel class over the same number of further steps
+            per = {}
+            for kind in (0, 1, 2, 3):
+                sgn.sgn_kernel_timing(ctx, kind, True)
+                sgn.sgn_rk4_step(ctx, *[t.clone() for t in f], w["dt"], steps)
+                n, ms, by = sgn.sgn_kernel_time(ctx, kind)
+                sgn.sgn_kernel_timing(ctx, kind, False)
+                if n:
+                    per[sgn.KERNEL_NAMES[kind]] = (n, ms, by)
+            dom = max(per, key=lambda k: per[k][1])
+            n, ms, by = per[dom]
+            ach = by / (ms * 1e-3) / 1e9 if ms else None
+            res["roofline"] = {"kernel_class": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": ach / HBM_PEAK_GBS if ach else None,
+                               "traffic": None, "algorithmic_bytes_per_launch": by / n,
+                               "mean_launch_us": ms / n * 1e3, "launches": n,
+                               "share_of_arnoldi_kernel_time": ms / sum(v[1] for v in per.values())}
+        out[name] = res
+        ctx.close()
+    h64, v64 = final["fp64"]
+    h32, v32 = final["fp32_mixed"]
+    out["fp32_vs_fp64_after_steps"] = {
+        "h": float(np.abs(h32 - h64).max() / np.abs(h64 - 1.0).max()),
+        "vx": float(np.abs(v32 - v64).max() / max(np.abs(v64).max(), 1e-300))}
+    return out
+
+
 def cpu_baseline(steps: int):
     import numpy as np  # noqa: F401
     from oracle import sgn_oracle as O
@@ -204,6 +263,7 @@ def main():
             "launches": launches,
         },
     }
+    out["precision_form"] = precision_form(sgn, torch, dev, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out), flush=True)

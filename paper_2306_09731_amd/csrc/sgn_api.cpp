@@ -289,19 +289,29 @@ int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void*
       batch = 2;
     }
     const sgn::GmresStatus& st = *ctx->hstat;
-    if (fused && ctx->timed_kind >= 0) {
-      // algorithmic bytes of this cycle's launches that did work: steps
-      // j < jdone (kernels B, C) and kernel A for j <= jdone (A_jdone
-      // finished the last step), unless the cycle converged at its start
+    if (ctx->timed_kind >= 0) {
+      // algorithmic bytes of this cycle's launches that did work (fields of
+      // fb bytes read or written once), unless the cycle converged at its
+      // start.  Three-kernel step j: A (j+4), B 5, C (j+5), with A run for
+      // j <= jdone (A_jdone finished the last step).  Four-kernel step j:
+      // basis (j+4), x part 5, projections (j+4), update (j+3).
       const double fb = (g.fp32 ? 4.0 : 8.0) * (double)g.nx * (double)g.ny;
       const int jd = st.jdone;
       const bool ran = !(st.done == 1 && jd == 0 && st.total_iters == total);
       if (ran) {
         if (ctx->timed_kind == SGN_KERNEL_ROW_MATVEC) ctx->timed_bytes += 5.0 * jd * fb;
-        if (ctx->timed_kind == SGN_KERNEL_COL_PRECOND_DOT)
-          for (int jj = 0; jj < jd; ++jj) ctx->timed_bytes += (jj + 5) * fb;
-        if (ctx->timed_kind == SGN_KERNEL_COL_BASIS)
-          for (int jj = 0; jj <= jd && jj <= m; ++jj) ctx->timed_bytes += (jj + 4) * fb;
+        if (fused) {
+          if (ctx->timed_kind == SGN_KERNEL_COL_PRECOND_DOT)
+            for (int jj = 0; jj < jd; ++jj) ctx->timed_bytes += (jj + 5) * fb;
+          if (ctx->timed_kind == SGN_KERNEL_COL_BASIS)
+            for (int jj = 0; jj <= jd && jj <= m; ++jj) ctx->timed_bytes += (jj + 4) * fb;
+        } else {
+          for (int jj = 0; jj < jd; ++jj) {
+            if (ctx->timed_kind == SGN_KERNEL_COL_BASIS || ctx->timed_kind == SGN_KERNEL_COL_PRECOND_DOT)
+              ctx->timed_bytes += (jj + 4) * fb;
+            if (ctx->timed_kind == SGN_KERNEL_GS_UPDATE) ctx->timed_bytes += (jj + 3) * fb;
+          }
+        }
       }
     }
     total = st.total_iters;
@@ -363,7 +373,10 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   // SGN_ARNOLDI_KERNELS = fused | chained | serial selects the Arnoldi
   // kernels (a tuning and testing switch; all compute the same quantities)
   const char* ak = std::getenv("SGN_ARNOLDI_KERNELS");
-  ctx->arnoldi = 2;
+  // default: the three-kernel step; for columns of 2048 points and more the
+  // four-kernel step with one transform chain per block measured faster
+  ctx->arnoldi = cfg->ny >= 2048 ? 0 : 2;
+  if (ak && std::strcmp(ak, "fused") == 0) ctx->arnoldi = 2;
   if (ak && std::strcmp(ak, "chained") == 0) ctx->arnoldi = 1;
   if (ak && std::strcmp(ak, "serial") == 0) ctx->arnoldi = 0;
   const int nx = cfg->nx, ny = cfg->ny;

@@ -121,10 +121,15 @@ __device__ __forceinline__ void dft(cplx* v) {
   }
 }
 
-// Elements per thread for a transform of length N.
+// Elements per thread for a transform of length N: 4, or 8 for the longest
+// transforms (from 2048 points in FP32, where registers hold twice as many
+// values, from 4096 in FP64).
+#ifndef SGN_E8_MIN
+#define SGN_E8_MIN 4096
+#endif
 template <int N>
 struct FftShape {
-  static constexpr int E = (N <= 8) ? N : (N >= 4096) ? 8 : 4;
+  static constexpr int E = (N <= 8) ? N : (N >= SGN_E8_MIN) ? 8 : 4;
   static constexpr int TPF = N / E;
   static_assert(N == E || N % (E * E) == 0, "plan needs N == E or E^2 | N");
 };
