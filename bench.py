@@ -170,6 +170,49 @@ def precision_form(sgn, torch, dev, args):
     return out
 
 
+def batched_form(sgn, torch, dev, args, per_grid: int = 16):
+    """64 perturbed line solitons, 16 on each of 256x256, 512x512, 1024x512 and
+    1024x1024 (dx = dy = pi/16, seeded amplitudes and transverse perturbations),
+    in the mixed-precision mode: each member has its own context and stream,
+    the Arnoldi schedule comes from the autotuner, and K steps of all members
+    run as one sgn_rk4_step_ensemble call; the same steps run one member after
+    another give the sequential rate."""
+    import numpy as np
+    from sgn_inputs import ENSEMBLE_GRIDS, ensemble_member
+    members, seed, schedules = [], 0, {}
+    for nx, ny in ENSEMBLE_GRIDS:
+        for _ in range(per_grid):
+            box, state, p = ensemble_member(seed, nx, ny)
+            seed += 1
+            cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, krasny=KRASNY, precision=sgn.SGN_FP32_MIXED)
+            ctx = sgn.sgn_init(cfg, dev, stream=torch.cuda.Stream(dev))
+            f = [torch.from_numpy(np.ascontiguousarray(a)).to(dev).to(torch.float32) for a in state]
+            schedules[f"{nx}x{ny}"] = sgn.ARNOLDI_SCHEDULES[sgn.sgn_autotune(ctx)]
+            members.append((ctx, f, p["dt"], nx * ny))
+    ctxs, fields, dts = [m[0] for m in members], [m[1] for m in members], [m[2] for m in members]
+    pts = sum(m[3] for m in members)
+    steps = max(1, min(args.steps, 10))
+    sgn.sgn_rk4_step_ensemble(ctxs, fields, dts, min(args.warmup, 2) or 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = sgn.sgn_rk4_step_ensemble(ctxs, fields, dts, steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for c, f, d in zip(ctxs, fields, dts):
+        sgn.sgn_rk4_step(c, *f, d, steps)
+    torch.cuda.synchronize()
+    el_seq = time.perf_counter() - t0
+    for c in ctxs:
+        c.close()
+    return {"workload": "ensemble of 64 perturbed line solitons (16 each on 256^2, 512^2, 1024x512, 1024^2)",
+            "members": len(members), "points": pts, "precision": "fp32_mixed", "steps": steps,
+            "value": pts * steps / el, "unit": UNIT, "ms_per_step": el * 1e3 / steps,
+            "sequential_value": pts * steps / el_seq, "speedup_vs_sequential": el_seq / el,
+            "iters_per_solve_mean": sum(i.total_iters for i in infos) / max(sum(i.solves for i in infos), 1),
+            "schedules": schedules}
+
+
 def cpu_baseline(steps: int):
     import numpy as np  # noqa: F401
     from oracle import sgn_oracle as O
@@ -264,6 +307,7 @@ def main():
         },
     }
     out["precision_form"] = precision_form(sgn, torch, dev, args)
+    out["batched_form"] = batched_form(sgn, torch, dev, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out), flush=True)

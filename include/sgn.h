@@ -173,6 +173,26 @@ int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double 
 int sgn_invariants(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, void* sigma,
                    sgn_invariants_out* out);
 
+/* Ensembles: nsteps RK4 steps of n independent members at once.  Member i is
+ * its own context ctxs[i] (own grid, precision, workspace and stream; the
+ * contexts must be distinct) with its fields h[i], vx[i], vy[i], sigma[i] and
+ * step dt[i]; each member is advanced exactly as by sgn_rk4_step, on a host
+ * thread of its own, so that the GPU runs the other members' kernels while
+ * one member's thread waits for its GMRES status.  Give the members different
+ * streams for their work to overlap.  infos: NULL or n entries.  Every member
+ * is run; the first non-OK member status is returned. */
+int sgn_rk4_step_ensemble(int32_t n, sgn_ctx* const* ctxs, void* const* h, void* const* vx, void* const* vy,
+                          void* const* sigma, const double* dt, int32_t nsteps, sgn_step_info* infos);
+
+/* Autotuner of the Arnoldi kernel schedule: times a few GMRES solves of a
+ * synthetic smooth problem with each schedule this grid supports (four
+ * kernels with one transform chain per block; four kernels with two chains;
+ * the three-kernel step), keeps the fastest for the context and caches the
+ * choice per (nx, ny, precision, restart, device) for the process.  Uses the
+ * context's RK4 stage buffers (their contents are overwritten) and its stream;
+ * synchronises.  *chosen (may be NULL): 0, 1 or 2 in the order above. */
+int sgn_autotune(sgn_ctx* ctx, int32_t* chosen);
+
 /* Building blocks of the hot path, exposed for testing.
  * sgn_derivative: out = d f / dx (axis 0) or d f / dy (axis 1) (Section 3: i k).
  * sgn_apply_operator: out = L_h s (eq. (3)), or M^-1 L_h s if precondition != 0.

@@ -6,7 +6,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <thread>
+#include <tuple>
 #include <vector>
 
 #include "sgn.h"
@@ -17,6 +21,7 @@ typedef double2 cplx;
 
 struct sgn_ctx {
   sgn_config cfg;
+  int device;  // HIP device current at sgn_init
   hipStream_t stream;
   char* ws;
   size_t ws_bytes;
@@ -366,6 +371,10 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255) != 0 || ws_bytes < L.total) return SGN_ERR_INVALID_ARG;
   sgn_ctx* ctx = new sgn_ctx();
   ctx->cfg = *cfg;
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    delete ctx;
+    return SGN_ERR_HIP;
+  }
   ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
   ctx->ws = static_cast<char*>(ws);
   ctx->ws_bytes = ws_bytes;
@@ -695,6 +704,118 @@ int sgn_krasny_filter(sgn_ctx* ctx, void* f) {
   HIPCK(sgn::launch_col_filter(g, ctx->E, step_filter_op(ctx->cfg), ctx->cfg.krasny, ctx->P, ctx->stream));
   HIPCK(sgn::launch_row_c2r(g, ctx->P, f, ctx->stream));
   HIPCK(hipStreamSynchronize(ctx->stream));
+  return SGN_OK;
+}
+
+int sgn_rk4_step_ensemble(int32_t n, sgn_ctx* const* ctxs, void* const* h, void* const* vx, void* const* vy,
+                          void* const* sigma, const double* dt, int32_t nsteps, sgn_step_info* infos) {
+  if (n < 0 || (n > 0 && (!ctxs || !h || !vx || !vy || !sigma || !dt)) || nsteps < 0) return SGN_ERR_INVALID_ARG;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return SGN_ERR_INVALID_ARG;
+    for (int k = 0; k < i; ++k)
+      if (ctxs[k] == ctxs[i]) return SGN_ERR_INVALID_ARG;  // a context is not thread-safe
+  }
+  std::vector<int> rc(n, SGN_OK);
+  std::vector<std::thread> threads;
+  threads.reserve(n);
+  for (int i = 0; i < n; ++i) {
+    threads.emplace_back([&, i]() {
+      if (hipSetDevice(ctxs[i]->device) != hipSuccess) {
+        rc[i] = SGN_ERR_HIP;
+        return;
+      }
+      rc[i] = sgn_rk4_step(ctxs[i], h[i], vx[i], vy[i], sigma[i], dt[i], nsteps, infos ? &infos[i] : nullptr);
+    });
+  }
+  for (auto& t : threads) t.join();
+  for (int i = 0; i < n; ++i)
+    if (rc[i] != SGN_OK) return rc[i];
+  return SGN_OK;
+}
+
+namespace {
+std::mutex g_tune_mutex;
+std::map<std::tuple<int, int, int, int, int>, int> g_tune_cache;  // (nx, ny, precision, restart, device) -> variant
+}  // namespace
+
+int sgn_autotune(sgn_ctx* ctx, int32_t* chosen) {
+  if (!ctx) return SGN_ERR_INVALID_ARG;
+  const sgn_config& c = ctx->cfg;
+  const auto key = std::make_tuple(c.nx, c.ny, c.precision, c.gmres_restart, ctx->device);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      ctx->arnoldi = it->second;
+      if (chosen) *chosen = it->second;
+      return SGN_OK;
+    }
+  }
+  const sgn::Geom& g = ctx->g;
+  hipStream_t s = ctx->stream;
+  // synthetic smooth problem in the workspace's RK4 stage buffers: depth
+  // h = 1 + 0.3 sin(x) cos(2y), right-hand side b = cos(3x + y), zero guess
+  const size_t npts = (size_t)c.nx * c.ny;
+  std::vector<double> hh(npts), bb(npts);
+  for (int y = 0; y < c.ny; ++y)
+    for (int x = 0; x < c.nx; ++x) {
+      const double X = -M_PI + 2.0 * M_PI * x / c.nx, Y = -M_PI + 2.0 * M_PI * y / c.ny;
+      hh[(size_t)y * c.nx + x] = 1.0 + 0.3 * std::sin(X) * std::cos(2.0 * Y);
+      bb[(size_t)y * c.nx + x] = std::cos(3.0 * X + Y);
+    }
+  auto upload = [&](void* dst, const std::vector<double>& src) -> hipError_t {
+    if (!g.fp32) return hipMemcpyAsync(dst, src.data(), npts * sizeof(double), hipMemcpyHostToDevice, s);
+    std::vector<float> f(src.begin(), src.end());
+    hipError_t e = hipMemcpyAsync(dst, f.data(), npts * sizeof(float), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // f is a host local
+    return e;
+  };
+  HIPCK(upload(ctx->hs, hh));
+  HIPCK(upload(ctx->vxs, bb));
+  HIPCK(hipMemsetAsync(ctx->vys, 0, ctx->field_bytes, s));
+  HIPCK(hipStreamSynchronize(s));
+  std::vector<int> cand = {0};
+  if (sgn::chained_ok(g)) {
+    cand.push_back(1);
+    cand.push_back(2);
+  }
+  hipEvent_t e0, e1;
+  HIPCK(hipEventCreate(&e0));
+  HIPCK(hipEventCreate(&e1));
+  const int saved = ctx->arnoldi;
+  int best = saved;
+  float best_ms = 1e30f;
+  int rc = SGN_OK;
+  for (int v : cand) {
+    ctx->arnoldi = v;
+    float total = 0.0f;
+    for (int rep = 0; rep < 4 && rc == SGN_OK; ++rep) {  // rep 0 warms up
+      rc = load_sigma(ctx, ctx->vys);
+      if (rc) break;
+      if (hipEventRecord(e0, s) != hipSuccess) rc = SGN_ERR_HIP;
+      SolveResult res;
+      if (!rc) rc = run_solve(ctx, 2, ctx->hs, ctx->vxs, nullptr, &res);
+      if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = SGN_ERR_HIP;
+      if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = SGN_ERR_HIP;
+      float ms = 0.0f;
+      if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = SGN_ERR_HIP;
+      if (rep > 0) total += ms;
+    }
+    if (rc) break;
+    if (total < best_ms) {
+      best_ms = total;
+      best = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->arnoldi = rc ? saved : best;
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_cache[key] = best;
+  }
+  if (chosen) *chosen = best;
   return SGN_OK;
 }
 

@@ -89,6 +89,11 @@ _SIGNATURES = {
     "sgn_apply_operator": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int32]),
     "sgn_apply_precond": (ctypes.c_int, [_VP, _VP, _VP]),
     "sgn_krasny_filter": (ctypes.c_int, [_VP, _VP]),
+    "sgn_rk4_step_ensemble": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                             ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                             ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                             ctypes.POINTER(sgn_step_info)]),
+    "sgn_autotune": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32)]),
     "sgn_kernel_timing": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "sgn_kernel_time": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
@@ -236,6 +241,31 @@ def sgn_rk4_step(ctx: Context, h, vx, vy, sigma, dt: float, nsteps: int = 1) -> 
                                      int(nsteps), ctypes.byref(info))
     _check(ctx, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
     return info
+
+
+def sgn_rk4_step_ensemble(ctxs, fields, dts, nsteps: int):
+    """nsteps RK4 steps of every member; fields[i] = (h, vx, vy, sigma) of
+    member i, dts[i] its step.  Returns the list of sgn_step_info."""
+    n = len(ctxs)
+    if not (len(fields) == n and len(dts) == n):
+        raise ValueError("one field tuple and one dt per context")
+    arr = lambda vals: (_VP * max(n, 1))(*vals)
+    ptrs = [[_field(c, f[k], name) for c, f in zip(ctxs, fields)] for k, name in enumerate(("h", "vx", "vy", "sigma"))]
+    infos = (sgn_step_info * max(n, 1))()
+    st = load_library().sgn_rk4_step_ensemble(n, arr([c.handle for c in ctxs]), *(arr(p) for p in ptrs),
+                                              (ctypes.c_double * max(n, 1))(*dts), nsteps, infos)
+    _check(None, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
+    return [infos[i] for i in range(n)]
+
+
+ARNOLDI_SCHEDULES = {0: "four kernels, one chain", 1: "four kernels, two chains", 2: "three kernels"}
+
+
+def sgn_autotune(ctx: Context) -> int:
+    """Pick and keep the fastest Arnoldi kernel schedule for this context."""
+    chosen = ctypes.c_int32()
+    _check(ctx, load_library().sgn_autotune(ctx.handle, ctypes.byref(chosen)))
+    return chosen.value
 
 
 def sgn_invariants(ctx: Context, h, vx, vy, sigma) -> dict:

@@ -18,6 +18,8 @@ from .generators import (  # noqa: F401
     soliton_plus_gaussian,
     gaussian_hump,
     crossing_solitons,
+    ENSEMBLE_GRIDS,
+    ensemble_member,
     random_smooth_field,
     random_state,
     workload,

@@ -203,6 +203,38 @@ def crossing_solitons(box: Box, c: float = 1.7, h_inf: float = 1.0, g: float = 1
     return h, px["v"], py["v"], np.zeros_like(h)
 
 
+# Ensemble of perturbed line solitons on uneven grids (the batched workload).
+ENSEMBLE_GRIDS = ((256, 256), (512, 512), (1024, 512), (1024, 1024))
+
+
+def ensemble_member(seed: int, nx: int, ny: int, h_inf: float = 1.0, g: float = 1.0):
+    """Member `seed` of the ensemble: grid spacing dx = dy = pi/16 (L = n/32),
+    a line soliton with amplitude a ~ U[0.1, 1.0] at x0 = -pi Lx / 2, times a
+    transverse perturbation 1 + eps P(y), P = sum_{1<=|n|<=8} Re(z_n e^{2 pi i n
+    y / P_y}) with z_n ~ CN(0, 1) exp(-n^2/16), rescaled to max |P| = 1, eps
+    log-uniform in [1e-3, 1e-2]; v_x = c - (c/h)(1 + (h^2)_xx / 6), v_y = 0.
+    Returns (Box, (h, vx, vy, sigma0), params)."""
+    rng = np.random.default_rng(seed)
+    a = float(rng.uniform(0.1, 1.0))
+    eps = float(10.0 ** rng.uniform(-3.0, -2.0))
+    z = (rng.standard_normal(17) + 1j * rng.standard_normal(17)) / math.sqrt(2.0)
+    box = Box(nx, ny, nx / 32.0, ny / 32.0)
+    X, Y = box.mesh()
+    Py = 2.0 * math.pi * box.Ly
+    P = np.zeros(ny)
+    y = box.coords()[1]
+    for i, n in enumerate([m for m in range(-8, 9) if m != 0]):
+        P += np.real(z[i] * math.exp(-n * n / 16.0) * np.exp(2j * math.pi * n * y / Py))
+    P /= np.abs(P).max()
+    f = (1.0 + eps * P)[:, None]
+    p = soliton_params(a=a, h_inf=h_inf, g=g)
+    prof = soliton_profile(_periodic_offset(X + math.pi * box.Lx / 2.0, box.Lx), p)
+    h = prof["h"] * f
+    hh_xx = 2.0 * (prof["h1"] ** 2 + prof["h"] * prof["h2"]) * f * f
+    vx = p.c - (p.c * h_inf / h) * (1.0 + hh_xx / 6.0)
+    return box, (h, vx, np.zeros_like(h), np.zeros_like(h)), dict(a=a, eps=eps, dt=0.005)
+
+
 def random_smooth_field(rng: np.random.Generator, ny: int, nx: int, kmax: int = 6,
                         decay: float = 0.35) -> np.ndarray:
     """Real field sum of random trigonometric modes |m_x|, |m_y| <= kmax with

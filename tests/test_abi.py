@@ -117,3 +117,13 @@ def test_calls_reject_null_context():
     assert lib.sgn_invariants(None, None, None, None, None, None) == sgn.SGN_ERR_INVALID_ARG
     assert lib.sgn_destroy(None) == sgn.SGN_ERR_INVALID_ARG
     assert lib.sgn_last_error(None) == b""
+
+
+def test_ensemble_and_autotune_host_checks():
+    lib = sgn.load_library()
+    null = ctypes.POINTER(ctypes.c_void_p)()
+    dts = (ctypes.c_double * 1)(0.01)
+    assert lib.sgn_rk4_step_ensemble(-1, null, null, null, null, null, dts, 1, None) == sgn.SGN_ERR_INVALID_ARG
+    assert lib.sgn_rk4_step_ensemble(1, null, null, null, null, null, dts, 1, None) == sgn.SGN_ERR_INVALID_ARG
+    assert lib.sgn_rk4_step_ensemble(0, null, null, null, null, null, None, 1, None) == sgn.SGN_OK
+    assert lib.sgn_autotune(None, None) == sgn.SGN_ERR_INVALID_ARG
