@@ -25,9 +25,11 @@
  *   - Wavenumbers are k = m / L, m in [-n/2, n/2), with the Nyquist mode of
  *     every derivative set to zero; the preconditioner uses the same k, with
  *     M = 3 / h_inf^3 + (kx^2 + ky^2) / h_inf (= 3 + k^2 for h_inf = 1).
- *   - The library never allocates device memory: all scratch lives in the
- *     caller's workspace (sgn_workspace_bytes).  It allocates a few bytes of
- *     pinned host memory for status read-back.
+ *   - The library never allocates device memory itself: all scratch lives in
+ *     the caller's workspace (sgn_workspace_bytes).  It allocates a few bytes
+ *     of pinned host memory for status read-back; sgn_rk4_step_graph also
+ *     creates a stream, two events and up to two executable graphs per
+ *     context (HIP runtime objects, released by sgn_destroy).
  *   - All work is ordered on the stream given to sgn_init.  The GMRES loop
  *     reads a status word back once per batch of speculative iterations, so
  *     the solving calls synchronise that stream before they return.
@@ -165,6 +167,27 @@ int sgn_rhs(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, void* s
  * after every step.  info may be NULL. */
 int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double dt, int32_t nsteps,
                  sgn_step_info* info);
+
+/* The same RK4 steps with each step replayed as one captured HIP graph, so
+ * that a step costs no host round trips.  In a graph every solve is a single
+ * GMRES cycle of iter_budget Arnoldi steps (1 <= iter_budget <= gmres_restart;
+ * iter_budget <= 0: automatic), each kernel predicated on the device status,
+ * so the solve stops at convergence exactly as in sgn_rk4_step; a device
+ * counter records any solve that reaches the budget unconverged.  Automatic
+ * budget: the context's previous one, else the first step of the call runs
+ * host-driven and sets it to its largest solve + 2.  If any solve of the call
+ * reaches the budget, the call restores (h, vx, vy, sigma) from a checkpoint
+ * taken at its start (workspace), redoes all nsteps with sgn_rk4_step and
+ * (automatic budget) raises the budget to that run's largest solve + 2.
+ * Results are bitwise those of sgn_rk4_step with the same arguments.  The
+ * graphs are captured on a stream private to the context, ordered after the
+ * work on the context's stream and before work enqueued there later, and are
+ * cached per (h, vx, vy, dt, budget).  Kernel timing (sgn_kernel_timing)
+ * counts host-driven launches only.  *replayed (may be NULL): 1 if graph
+ * replays ran the steps, 0 if the call ran host-driven.  Errors: as
+ * sgn_rk4_step; SGN_ERR_INVALID_ARG for iter_budget > gmres_restart. */
+int sgn_rk4_step_graph(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double dt, int32_t nsteps,
+                       int32_t iter_budget, sgn_step_info* info, int32_t* replayed);
 
 /* Conserved quantities of Section 2.3 for the state (h, vx, vy): sigma is
  * first solved to cfg.invariants_tol from the guess in sigma (in/out), then

@@ -29,7 +29,8 @@ struct sgn_ctx {
   size_t vstride;      // complex entries (of the working precision) per field
   size_t field_bytes;  // bytes per field (256-byte multiple)
   sgn::GmresState* st;
-  double* partials;
+  double* partials;   // block partials of the reductions
+  double* partials2;  // second buffer: kernel C's, reduced by kernel A while it writes its own
   // fields of the working precision (FP64 or FP32), untyped on the host
   void *V, *Z, *W, *E, *G, *P, *Q, *R1, *R2, *SIG;
   char* D;  // guess 1: four per-stage sigma increments (2D spectra), else null
@@ -45,6 +46,20 @@ struct sgn_ctx {
   int64_t timed_launches = 0;
   double timed_ms = 0.0;
   double timed_bytes = 0.0;  // algorithmic bytes of the timed launches that did work
+  // captured RK4 step (sgn_rk4_step_graph)
+  char* ckpt = nullptr;             // h, vx, vy, sigma at the start of a captured call
+  hipStream_t gstream = nullptr;    // private stream: capture and replays
+  hipEvent_t gev[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};  // first step of a call, later steps
+  struct GraphKey {
+    const void *h = nullptr, *vx = nullptr, *vy = nullptr;
+    double dt = 0.0;
+    int budget = 0;
+    bool operator==(const GraphKey& o) const {
+      return h == o.h && vx == o.vx && vy == o.vy && dt == o.dt && budget == o.budget;
+    }
+  } gkey[2];
+  int graph_budget = 0;  // Arnoldi steps per captured solve (0: not yet calibrated)
 };
 
 namespace {
@@ -84,7 +99,7 @@ bool step_filter_on(const sgn_config& c) { return c.krasny > 0.0 || c.dealias !=
 int step_filter_op(const sgn_config& c) { return c.dealias ? 2 : 1; }
 
 struct Layout {
-  size_t tw, st, partials, fields, total;
+  size_t tw, st, partials, partials2, fields, total;
   size_t field_bytes;
   int nfields;
 };
@@ -107,10 +122,12 @@ Layout layout(const sgn_config* c) {
   off += align_up(sizeof(sgn::GmresState));
   L.partials = off;
   off += align_up((size_t)pblocks * sgn::kPartialStride * sizeof(double));
+  L.partials2 = off;
+  off += align_up((size_t)pblocks * sgn::kPartialStride * sizeof(double));
   L.fields = off;
   // V (restart + 1), Z, W, E, G, P, Q, R1, R2, SIG, hs, vxs, vys, acc_h, acc_vx, acc_vy,
-  // and with the stage-increment guess D_0..D_3
-  L.nfields = c->gmres_restart + 1 + 15 + (c->guess == SGN_GUESS_STAGE_INCREMENT ? 4 : 0);
+  // the checkpoint of a captured call (4), and with the stage-increment guess D_0..D_3
+  L.nfields = c->gmres_restart + 1 + 15 + 4 + (c->guess == SGN_GUESS_STAGE_INCREMENT ? 4 : 0);
   off += (size_t)L.nfields * L.field_bytes;
   L.total = off;
   return L;
@@ -226,6 +243,102 @@ struct SolveResult {
   double rel_resid = 0.0;
 };
 
+// ---- kernel sequences shared by the host-driven loop and the captured step
+
+// Start of a GMRES cycle: residual (and b, if need_b) of the current sigma.
+int enqueue_residual(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void* vy, int need_b, int flags) {
+  const sgn::Geom& g = ctx->g;
+  hipStream_t s = ctx->stream;
+  HIPCK(sgn::launch_row_op(g, mode, ctx->E, ctx->G, h, vx, vy, ctx->P, ctx->Q, ctx->R1, ctx->R2, need_b, 0, ctx->st,
+                           s));
+  // an explicit b (mode 2) has b_hat = F_y(R1) only
+  HIPCK(sgn::launch_col_resid(g, ctx->P, ctx->Q, ctx->R1, mode == 2 ? nullptr : ctx->R2, need_b, flags, ctx->st,
+                              ctx->W, ctx->partials, s));
+  if (ctx->arnoldi == 2) {
+    // kernels A and B of step 0: E, G of the residual, its x part
+    TIMED(SGN_KERNEL_COL_BASIS, sgn::launch_col_proj(g, ctx->W, ctx->W, ctx->V, ctx->vstride, 0, ctx->st, ctx->E,
+                                                     ctx->G, ctx->partials, nullptr, s));
+    TIMED(SGN_KERNEL_ROW_MATVEC,
+          sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, ctx->partials, 0, s));
+  }
+  return SGN_OK;
+}
+
+// Arnoldi step `it` of the cycle (every kernel exits at once once the device
+// status says done).
+int enqueue_arnoldi(sgn_ctx* ctx, const void* h, int it) {
+  const sgn::Geom& g = ctx->g;
+  hipStream_t s = ctx->stream;
+  if (ctx->arnoldi == 2) {
+    // C_it, A_it+1, B_it+1: B_it+1 finishes step it, so the device status is
+    // current after every step
+    TIMED(SGN_KERNEL_COL_PRECOND_DOT, sgn::launch_col_precond_new(g, ctx->P, ctx->Q, ctx->W, ctx->V, ctx->Z,
+                                                                  ctx->vstride, it, ctx->st, ctx->partials2, s));
+    TIMED(SGN_KERNEL_COL_BASIS, sgn::launch_col_proj(g, ctx->Z, ctx->W, ctx->V, ctx->vstride, it + 1, ctx->st,
+                                                     ctx->E, ctx->G, ctx->partials, ctx->partials2, s));
+    TIMED(SGN_KERNEL_ROW_MATVEC,
+          sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, ctx->partials, it + 1, s));
+    return SGN_OK;
+  }
+  if (ctx->arnoldi == 1) {
+    TIMED(SGN_KERNEL_COL_BASIS, sgn::launch_col_basis2(g, ctx->W, ctx->V, ctx->vstride, it, ctx->st, ctx->E, ctx->G, s));
+    TIMED(SGN_KERNEL_ROW_MATVEC,
+          sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, nullptr, 0, s));
+    TIMED(SGN_KERNEL_COL_PRECOND_DOT, sgn::launch_col_precond_dot2(g, ctx->P, ctx->Q, ctx->V, ctx->vstride, it,
+                                                                   ctx->st, ctx->W, ctx->partials, s));
+  } else {
+    TIMED(SGN_KERNEL_COL_BASIS, sgn::launch_col_basis_eg(g, ctx->W, ctx->V, ctx->vstride, it, ctx->st, ctx->E, ctx->G, s));
+    TIMED(SGN_KERNEL_ROW_MATVEC, sgn::launch_row_op(g, 0, ctx->E, ctx->G, h, nullptr, nullptr, ctx->P, ctx->Q,
+                                                    nullptr, nullptr, 0, 1, ctx->st, s));
+    TIMED(SGN_KERNEL_COL_PRECOND_DOT, sgn::launch_col_precond_dot(g, ctx->P, ctx->Q, ctx->V, ctx->vstride, it,
+                                                                  ctx->st, ctx->W, ctx->partials, s));
+  }
+  TIMED(SGN_KERNEL_GS_UPDATE, sgn::launch_upd(g, ctx->W, ctx->V, ctx->vstride, it, ctx->st, ctx->partials, s));
+  return SGN_OK;
+}
+
+// RK4 stage `stage` after its solve: fluxes, Bernoulli function and the
+// stage combine (stage input (ih, ivx, ivy); the step's state h, vx, vy).
+int enqueue_stage_flux(sgn_ctx* ctx, int stage, double dt, void* h, void* vx, void* vy, const void* ih,
+                       const void* ivx, const void* ivy) {
+  const sgn::Geom& g = ctx->g;
+  hipStream_t s = ctx->stream;
+  sgn::RkStage rk;
+  if (stage < 3) {
+    rk.mode = 1;
+    rk.first = stage == 0;
+    rk.wacc = stage == 0 ? 1.0 / 6.0 : 1.0 / 3.0;
+    rk.cnext = stage == 2 ? dt : 0.5 * dt;
+  } else {
+    rk.mode = 2;
+    rk.first = 0;
+    rk.wacc = 1.0 / 6.0;
+    rk.cnext = 0.0;
+  }
+  rk.dt = dt;
+  const bool last = stage == 3;
+  sgn::RkField fvx{vx, ctx->acc_vx, last ? vx : ctx->vxs};
+  sgn::RkField fh{h, ctx->acc_h, last ? h : ctx->hs};
+  sgn::RkField fvy{vy, ctx->acc_vy, last ? vy : ctx->vys};
+  TIMED(SGN_KERNEL_ROW_FLUX, sgn::launch_row_flux(g, ctx->E, ctx->G, ih, ivx, ivy, ctx->P, ctx->Q, ctx->R1, rk, fvx, s));
+  TIMED(SGN_KERNEL_COL_FLUX, sgn::launch_col_flux(g, ctx->P, ctx->Q, ctx->R1, rk, fh, fvy, s));
+  return SGN_OK;
+}
+
+// The per-step spectral filter (Krasny, two-thirds rule) of h, vx, vy.
+int enqueue_step_filter(sgn_ctx* ctx, void* h, void* vx, void* vy) {
+  if (!step_filter_on(ctx->cfg)) return SGN_OK;
+  const sgn::Geom& g = ctx->g;
+  hipStream_t s = ctx->stream;
+  void* fs[3] = {h, vx, vy};
+  for (void* f : fs) {
+    HIPCK(sgn::launch_row_r2c(g, f, ctx->P, s));
+    HIPCK(sgn::launch_col_filter(g, ctx->P, step_filter_op(ctx->cfg), ctx->cfg.krasny, ctx->Q, s));
+    HIPCK(sgn::launch_row_c2r(g, ctx->Q, f, s));
+  }
+  return SGN_OK;
+}
+
 // Restarted GMRES for L_h sigma = b with the warm start held in (SIG, E, G).
 // mode 1: b = -div v from (vx, vy); mode 2: b given (passed as vx).
 // On return (SIG, E, G) hold the solution.
@@ -241,18 +354,12 @@ int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void*
   res->restarts = 0;
   res->converged = 0;
   for (;;) {
-    HIPCK(sgn::launch_row_op(g, mode, ctx->E, ctx->G, h, vx, vy, ctx->P, ctx->Q, ctx->R1, ctx->R2, need_b, 0,
-                             ctx->st, s));
-    // an explicit b (mode 2) has b_hat = F_y(R1) only
-    HIPCK(sgn::launch_col_resid(g, ctx->P, ctx->Q, ctx->R1, mode == 2 ? nullptr : ctx->R2, need_b, flags, ctx->st,
-                                ctx->W, ctx->partials, s));
+    int rc0 = enqueue_residual(ctx, mode, h, vx, vy, need_b, flags);
+    if (rc0) return rc0;
     need_b = 0;
     flags = 0;
     int j = 0;
     const bool fused = ctx->arnoldi == 2;
-    if (fused)  // kernel A of step 0: E, G of the residual
-      TIMED(SGN_KERNEL_COL_BASIS, sgn::launch_col_proj(g, ctx->W, ctx->W, ctx->V, ctx->vstride, 0, ctx->st, ctx->E,
-                                                       ctx->G, ctx->partials, s));
     // speculative batch: one more step than this slot's previous solve needed
     int batch = (res->restarts == 0 ? ctx->last_iters[slot] : m) + 1;
     if (batch < 1) batch = 1;
@@ -262,30 +369,8 @@ int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void*
       if (nrun > maxit - total - j) nrun = maxit - total - j;
       if (nrun <= 0) break;  // the device sets done at the cycle or iteration cap
       for (int it = j; it < j + nrun; ++it) {
-        if (fused) {
-          TIMED(SGN_KERNEL_ROW_MATVEC, sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, s));
-          TIMED(SGN_KERNEL_COL_PRECOND_DOT,
-                sgn::launch_col_precond_new(g, ctx->P, ctx->Q, ctx->W, ctx->V, ctx->Z, ctx->vstride, it, ctx->st,
-                                            ctx->partials, s));
-          TIMED(SGN_KERNEL_COL_BASIS, sgn::launch_col_proj(g, ctx->Z, ctx->W, ctx->V, ctx->vstride, it + 1, ctx->st,
-                                                           ctx->E, ctx->G, ctx->partials, s));
-          continue;
-        }
-        if (ctx->arnoldi == 1) {
-          TIMED(SGN_KERNEL_COL_BASIS,
-                sgn::launch_col_basis2(g, ctx->W, ctx->V, ctx->vstride, it, ctx->st, ctx->E, ctx->G, s));
-          TIMED(SGN_KERNEL_ROW_MATVEC, sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, s));
-          TIMED(SGN_KERNEL_COL_PRECOND_DOT, sgn::launch_col_precond_dot2(g, ctx->P, ctx->Q, ctx->V, ctx->vstride,
-                                                                         it, ctx->st, ctx->W, ctx->partials, s));
-        } else {
-          TIMED(SGN_KERNEL_COL_BASIS,
-                sgn::launch_col_basis_eg(g, ctx->W, ctx->V, ctx->vstride, it, ctx->st, ctx->E, ctx->G, s));
-          TIMED(SGN_KERNEL_ROW_MATVEC, sgn::launch_row_op(g, 0, ctx->E, ctx->G, h, nullptr, nullptr, ctx->P,
-                                                          ctx->Q, nullptr, nullptr, 0, 1, ctx->st, s));
-          TIMED(SGN_KERNEL_COL_PRECOND_DOT, sgn::launch_col_precond_dot(g, ctx->P, ctx->Q, ctx->V, ctx->vstride, it,
-                                                                        ctx->st, ctx->W, ctx->partials, s));
-        }
-        TIMED(SGN_KERNEL_GS_UPDATE, sgn::launch_upd(g, ctx->W, ctx->V, ctx->vstride, it, ctx->st, ctx->partials, s));
+        int rc1 = enqueue_arnoldi(ctx, h, it);
+        if (rc1) return rc1;
       }
       j += nrun;
       int rc = read_status(ctx);
@@ -298,7 +383,8 @@ int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void*
       // algorithmic bytes of this cycle's launches that did work (fields of
       // fb bytes read or written once), unless the cycle converged at its
       // start.  Three-kernel step j: A (j+4), B 5, C (j+5), with A run for
-      // j <= jdone (A_jdone finished the last step).  Four-kernel step j:
+      // j <= jdone (A_jdone forms u_jdone before B_jdone stops the cycle) and
+      // B's transforms for j < jdone.  Four-kernel step j:
       // basis (j+4), x part 5, projections (j+4), update (j+3).
       const double fb = (g.fp32 ? 4.0 : 8.0) * (double)g.nx * (double)g.ny;
       const int jd = st.jdone;
@@ -334,6 +420,102 @@ int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void*
   ctx->last_iters[slot] = total < m ? total : m;
   return SGN_OK;
 }
+
+// ---- the captured RK4 step
+
+// One RK4 step for capture: each solve is a single GMRES cycle of `budget`
+// Arnoldi steps, all predicated on the device status (the caller sets the
+// iteration cap to the budget, so the device stops at convergence or there),
+// followed by the solve counters.  kind 0: first step of a call (sigma
+// itself is the guess); kind 1: later steps (stage-increment guess, if on).
+int enqueue_graph_step(sgn_ctx* ctx, int kind, void* h, void* vx, void* vy, double dt, int budget) {
+  const sgn::Geom& g = ctx->g;
+  hipStream_t s = ctx->stream;
+  int rc;
+  for (int stage = 0; stage < 4; ++stage) {
+    const void* ih = stage == 0 ? h : ctx->hs;
+    const void* ivx = stage == 0 ? vx : ctx->vxs;
+    const void* ivy = stage == 0 ? vy : ctx->vys;
+    void* Dst = ctx->D ? ctx->D + (size_t)stage * ctx->field_bytes : nullptr;
+    if (Dst && kind == 1) HIPCK(sgn::launch_col_guess_eg(g, ctx->SIG, Dst, ctx->E, ctx->G, s));
+    if ((rc = enqueue_residual(ctx, 1, ih, ivx, ivy, 1, 1))) return rc;
+    for (int it = 0; it < budget; ++it)
+      if ((rc = enqueue_arnoldi(ctx, ih, it))) return rc;
+    HIPCK(sgn::launch_col_update_eg(g, ctx->SIG, ctx->V, ctx->vstride, ctx->st, ctx->E, ctx->G, Dst, s));
+    HIPCK(sgn::launch_solve_stats(g, ctx->st, s));
+    if ((rc = enqueue_stage_flux(ctx, stage, dt, h, vx, vy, ih, ivx, ivy))) return rc;
+  }
+  return enqueue_step_filter(ctx, h, vx, vy);
+}
+
+// Instantiated graph of one step of this kind, captured on ctx->stream (the
+// private stream) unless the cached one has the same fields, dt and budget.
+int graph_for(sgn_ctx* ctx, int kind, void* h, void* vx, void* vy, double dt, int budget) {
+  sgn_ctx::GraphKey key;
+  key.h = h;
+  key.vx = vx;
+  key.vy = vy;
+  key.dt = dt;
+  key.budget = budget;
+  if (ctx->gexec[kind] && ctx->gkey[kind] == key) return SGN_OK;
+  if (ctx->gexec[kind]) {
+    HIPCK(hipGraphExecDestroy(ctx->gexec[kind]));
+    ctx->gexec[kind] = nullptr;
+  }
+  const int timed = ctx->timed_kind;  // no timing events inside a graph
+  ctx->timed_kind = -1;
+  HIPCK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
+  const int rc = enqueue_graph_step(ctx, kind, h, vx, vy, dt, budget);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
+  ctx->timed_kind = timed;
+  if (rc || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc ? rc : fail(ctx, e, "hipStreamEndCapture");
+  }
+  hipGraphExec_t x = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&x, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) return fail(ctx, e2, "hipGraphInstantiate");
+  ctx->gexec[kind] = x;
+  ctx->gkey[kind] = key;
+  return SGN_OK;
+}
+
+int set_maxit(sgn_ctx* ctx, int32_t v) {
+  HIPCK(hipMemcpyAsync(&ctx->st->maxit, &v, sizeof v, hipMemcpyHostToDevice, ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));  // v is a host local
+  return SGN_OK;
+}
+
+// Runs a captured call on the context's private stream, ordered after the
+// work already on the caller's stream and before the work enqueued there
+// later.
+struct PrivateStream {
+  sgn_ctx* ctx;
+  hipStream_t user;
+  bool ok = false;
+  explicit PrivateStream(sgn_ctx* c) : ctx(c), user(c->stream) {
+    if (!c->gstream) {
+      if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess) {
+        c->gstream = nullptr;
+        return;
+      }
+      for (hipEvent_t& e : c->gev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return;
+    }
+    if (hipEventRecord(c->gev[0], user) != hipSuccess) return;
+    if (hipStreamWaitEvent(c->gstream, c->gev[0], 0) != hipSuccess) return;
+    c->stream = c->gstream;
+    ok = true;
+  }
+  ~PrivateStream() {
+    if (!ok) return;
+    (void)hipEventRecord(ctx->gev[1], ctx->gstream);
+    (void)hipStreamWaitEvent(user, ctx->gev[1], 0);
+    ctx->stream = user;
+  }
+};
 
 }  // namespace
 
@@ -414,6 +596,7 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   g.twy32 = tw32 + nx;
   ctx->st = reinterpret_cast<sgn::GmresState*>(base + L.st);
   ctx->partials = reinterpret_cast<double*>(base + L.partials);
+  ctx->partials2 = reinterpret_cast<double*>(base + L.partials2);
   ctx->field_bytes = L.field_bytes;
   ctx->vstride = L.field_bytes / (g.fp32 ? sizeof(float2) : sizeof(double2));
   char* f = base + L.fields;
@@ -440,6 +623,8 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   ctx->acc_h = next();
   ctx->acc_vx = next();
   ctx->acc_vy = next();
+  ctx->ckpt = f;
+  f += 4 * L.field_bytes;
   ctx->D = nullptr;
   if (cfg->guess == SGN_GUESS_STAGE_INCREMENT) {
     ctx->D = f;
@@ -484,6 +669,11 @@ int sgn_destroy(sgn_ctx* ctx) {
   if (!ctx) return SGN_ERR_INVALID_ARG;
   (void)drain_timing(ctx);
   for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
+  for (hipGraphExec_t x : ctx->gexec)
+    if (x) (void)hipGraphExecDestroy(x);
+  for (hipEvent_t e : ctx->gev)
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
   if (ctx->hstat) (void)hipHostFree(ctx->hstat);
   delete ctx;
   return SGN_OK;
@@ -561,9 +751,6 @@ int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double 
   if (rc) return rc;
   const sgn::Geom& g = ctx->g;
   hipStream_t s = ctx->stream;
-  void* dhp = ctx->P;
-  void* qy = ctx->Q;
-  void* B = ctx->R1;
   int64_t total = 0;
   int maxper = 0, solves = 0, unconv = 0;
   // stage-increment guess: the increments start at zero in every call, so the
@@ -583,34 +770,11 @@ int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double 
       if (res.iters > maxper) maxper = res.iters;
       solves += 1;
       unconv |= !res.converged;
-      sgn::RkStage rk;
-      if (stage < 3) {
-        rk.mode = 1;
-        rk.first = stage == 0;
-        rk.wacc = stage == 0 ? 1.0 / 6.0 : 1.0 / 3.0;
-        rk.cnext = stage == 2 ? dt : 0.5 * dt;
-      } else {
-        rk.mode = 2;
-        rk.first = 0;
-        rk.wacc = 1.0 / 6.0;
-        rk.cnext = 0.0;
-      }
-      rk.dt = dt;
-      const bool last = stage == 3;
-      sgn::RkField fvx{vx, ctx->acc_vx, last ? vx : ctx->vxs};
-      sgn::RkField fh{h, ctx->acc_h, last ? h : ctx->hs};
-      sgn::RkField fvy{vy, ctx->acc_vy, last ? vy : ctx->vys};
-      TIMED(SGN_KERNEL_ROW_FLUX, sgn::launch_row_flux(g, ctx->E, ctx->G, ih, ivx, ivy, dhp, qy, B, rk, fvx, s));
-      TIMED(SGN_KERNEL_COL_FLUX, sgn::launch_col_flux(g, dhp, qy, B, rk, fh, fvy, s));
+      rc = enqueue_stage_flux(ctx, stage, dt, h, vx, vy, ih, ivx, ivy);
+      if (rc) return rc;
     }
-    if (step_filter_on(ctx->cfg)) {
-      void* fs[3] = {h, vx, vy};
-      for (void* f : fs) {
-        HIPCK(sgn::launch_row_r2c(g, f, ctx->P, s));
-        HIPCK(sgn::launch_col_filter(g, ctx->P, step_filter_op(ctx->cfg), ctx->cfg.krasny, ctx->Q, s));
-        HIPCK(sgn::launch_row_c2r(g, ctx->Q, f, s));
-      }
-    }
+    rc = enqueue_step_filter(ctx, h, vx, vy);
+    if (rc) return rc;
   }
   HIPCK(sgn::launch_row_c2r(g, ctx->E, sigma, s));
   HIPCK(sgn::launch_field_stats(g, h, vx, vy, (size_t)g.nx * g.ny, ctx->st, ctx->partials, s));
@@ -626,6 +790,93 @@ int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double 
   if (ctx->hstat->stat_nonfinite) return SGN_ERR_NONFINITE;
   if (!(ctx->hstat->stat_minh > 0.0)) return SGN_ERR_CAVITATION;
   return unconv ? SGN_ERR_NOT_CONVERGED : SGN_OK;
+}
+
+int sgn_rk4_step_graph(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double dt, int32_t nsteps,
+                       int32_t iter_budget, sgn_step_info* info, int32_t* replayed) {
+  if (replayed) *replayed = 0;
+  if (!ctx || !aligned(h) || !aligned(vx) || !aligned(vy) || !aligned(sigma) || nsteps < 0 || !std::isfinite(dt) ||
+      iter_budget > ctx->cfg.gmres_restart)
+    return SGN_ERR_INVALID_ARG;
+  if (nsteps == 0) return sgn_rk4_step(ctx, h, vx, vy, sigma, dt, 0, info);
+  PrivateStream ps(ctx);
+  if (!ps.ok) return fail(ctx, hipErrorInvalidValue, "private stream for the captured step");
+  const sgn::Geom& g = ctx->g;
+  hipStream_t s = ctx->stream;
+  int rc = check_state(ctx, h, vx, vy);
+  if (rc) return rc;
+  // checkpoint: a call whose budget turns out too small is redone host-driven
+  const size_t nb = (size_t)g.nx * g.ny * (g.fp32 ? sizeof(float) : sizeof(double));
+  void* fs[4] = {h, vx, vy, sigma};
+  for (int i = 0; i < 4; ++i)
+    HIPCK(hipMemcpyAsync(ctx->ckpt + (size_t)i * ctx->field_bytes, fs[i], nb, hipMemcpyDeviceToDevice, s));
+  const int m = ctx->cfg.gmres_restart;
+  const int cap = m < ctx->cfg.gmres_max_iters ? m : ctx->cfg.gmres_max_iters;
+  int64_t total = 0;
+  int maxper = 0, first = 0;
+  int budget = iter_budget > 0 ? iter_budget : ctx->graph_budget;
+  if (budget > ctx->cfg.gmres_max_iters) budget = ctx->cfg.gmres_max_iters;
+  if (budget <= 0) {
+    // calibration: the first step host-driven; its largest solve plus two
+    sgn_step_info i1;
+    rc = sgn_rk4_step(ctx, h, vx, vy, sigma, dt, 1, &i1);
+    if (rc && rc != SGN_ERR_NOT_CONVERGED) return rc;
+    total = i1.total_iters;
+    maxper = i1.max_iters_per_solve;
+    budget = maxper + 2 < cap ? maxper + 2 : cap;
+    ctx->graph_budget = budget;
+    first = 1;
+    if (rc == SGN_ERR_NOT_CONVERGED) budget = 0;  // needs restarts: stay host-driven
+  }
+  bool ok = budget > 0;
+  if (ok && first < nsteps) {
+    // after a calibration step E, G, SIG and D hold exactly what the host
+    // loop would continue from; otherwise start as the host loop does
+    if (!first) {
+      if ((rc = load_sigma(ctx, sigma))) return rc;
+      if (ctx->D) HIPCK(hipMemsetAsync(ctx->D, 0, 4 * ctx->field_bytes, s));
+    }
+    // with the stage-increment guess the first step of a call differs
+    const bool two = ctx->D != nullptr;
+    if ((!two || !first) && (rc = graph_for(ctx, 0, h, vx, vy, dt, budget))) return rc;
+    if (two && (first || nsteps > 1) && (rc = graph_for(ctx, 1, h, vx, vy, dt, budget))) return rc;
+    HIPCK(hipMemsetAsync(&ctx->st->st.g_fail, 0, 2 * sizeof(int32_t) + sizeof(int64_t), s));
+    if ((rc = set_maxit(ctx, budget))) return rc;
+    for (int step = first; step < nsteps; ++step)
+      HIPCK(hipGraphLaunch(ctx->gexec[two && step > 0 ? 1 : 0], s));
+    if ((rc = set_maxit(ctx, ctx->cfg.gmres_max_iters))) return rc;
+    HIPCK(sgn::launch_row_c2r(g, ctx->E, sigma, s));
+    HIPCK(sgn::launch_field_stats(g, h, vx, vy, (size_t)g.nx * g.ny, ctx->st, ctx->partials, s));
+    if ((rc = read_status(ctx))) return rc;
+    ok = ctx->hstat->g_fail == 0;
+    total += ctx->hstat->g_total;
+    if (ctx->hstat->g_max > maxper) maxper = ctx->hstat->g_max;
+  }
+  if (!ok) {
+    // a solve needed more than the budget: redo the call host-driven from the
+    // checkpoint, and size the next budget from what it needed
+    for (int i = 0; i < 4; ++i)
+      HIPCK(hipMemcpyAsync(fs[i], ctx->ckpt + (size_t)i * ctx->field_bytes, nb, hipMemcpyDeviceToDevice, s));
+    sgn_step_info ih;
+    rc = sgn_rk4_step(ctx, h, vx, vy, sigma, dt, nsteps, &ih);
+    if (iter_budget <= 0) ctx->graph_budget = ih.max_iters_per_solve + 2 < cap ? ih.max_iters_per_solve + 2 : cap;
+    if (info) *info = ih;
+    return rc;
+  }
+  if (first == nsteps) {  // the calibration step was the whole call
+    if ((rc = read_status(ctx))) return rc;
+  }
+  if (info) {
+    info->total_iters = total;
+    info->max_iters_per_solve = maxper;
+    info->solves = 4 * nsteps;
+    info->min_h = ctx->hstat->stat_minh;
+    info->any_unconverged = 0;
+  }
+  if (replayed) *replayed = first < nsteps ? 1 : 0;
+  if (ctx->hstat->stat_nonfinite) return SGN_ERR_NONFINITE;
+  if (!(ctx->hstat->stat_minh > 0.0)) return SGN_ERR_CAVITATION;
+  return SGN_OK;
 }
 
 int sgn_invariants(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, void* sigma,

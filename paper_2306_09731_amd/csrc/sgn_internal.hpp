@@ -41,6 +41,10 @@ struct GmresStatus {
   double stat_minh;     // min h of the last field check
   int32_t stat_nonfinite;
   int32_t pad;
+  // solves of a captured RK4 step (one GMRES cycle each, no host reads):
+  int32_t g_fail;   // solves that stopped at the iteration budget unconverged
+  int32_t g_max;    // largest Arnoldi step count of one solve
+  int64_t g_total;  // Arnoldi steps summed over the solves
 };
 
 struct GmresState {
@@ -49,9 +53,12 @@ struct GmresState {
   int32_t m;            // restart length
   int32_t maxit;        // total Arnoldi steps allowed per solve
   double beta;          // norm of the newest (not yet normalised) Krylov vector
+  int32_t cycle_base;   // Arnoldi steps of the solve before the current cycle
+  int32_t pad2;
   double H[(kMaxRestart + 1) * kMaxRestart];  // H[i + j*(m_max+1)]
   double cs[kMaxRestart], sn[kMaxRestart];
-  double gv[kMaxRestart + 1];
+  double gv[kMaxRestart + 1];  // g_j before rotation j (written when step j - 1 finishes)
+  double gr[kMaxRestart];      // g_j after rotation j
   double y[kMaxRestart];
   double s[kMaxRestart + 1];   // first projection coefficients
   double s2[kMaxRestart + 1];  // second projection coefficients

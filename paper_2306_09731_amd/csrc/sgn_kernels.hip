@@ -118,12 +118,64 @@ __device__ bool last_block_arrive(uint32_t* ctr, int nblocks) {
   return s_last != 0;
 }
 
+// Reduce-scatter of eight values over a wave: on return lane l holds the
+// wave sum of value (l >> 3) & 7.  The first three butterfly levels halve the
+// values each lane carries (4, 2, 1 shuffles), the last three finish one
+// value: 10 shuffles instead of 6 per value.
+__device__ __forceinline__ double wave_sum8_scatter(const double (&a)[8]) {
+  const int lane = flat_tid() & 63;
+  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+  double b[4], c[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) b[i] = (h5 ? a[4 + i] : a[i]) + __shfl_xor(h5 ? a[i] : a[4 + i], 32, 64);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) c[i] = (h4 ? b[2 + i] : b[i]) + __shfl_xor(h4 ? b[i] : b[2 + i], 16, 64);
+  double d = (h3 ? c[1] : c[0]) + __shfl_xor(h3 ? c[0] : c[1], 8, 64);
+  d += __shfl_xor(d, 4, 64);
+  d += __shfl_xor(d, 2, 64);
+  d += __shfl_xor(d, 1, 64);
+  return d;
+}
+
 // kind: 0 sum, 1 min, 2 max.  out[k] (LDS) = reduction over blocks of
 // partials[b * kPartialStride + k], in a fixed order.
+// kAtomic = false: the partials were written by an earlier kernel on the
+// stream (visible to plain loads after the kernel boundary).
+template <bool kAtomic = true>
 __device__ void reduce_partials(const double* partials, int nblocks, int nvals, const int* kind,
                                 double* out) {
   const int tid = flat_tid();
   const int lane = tid & 63, wave = tid >> 6, nw = block_threads() >> 6;
+  if (!kind) {
+    // sums: each wave takes eight values and keeps the loads of 128 blocks in
+    // flight together
+    for (int k0 = 8 * wave; k0 < nvals; k0 += 8 * nw) {
+      double a[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = 0.0;
+      for (int b0 = 0; b0 < nblocks; b0 += 128) {
+        double x[2][8];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int b = b0 + 64 * u + lane;
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            x[u][q] = (b < nblocks && k0 + q < nvals)
+                          ? (kAtomic ? partial_load(&partials[(size_t)b * kPartialStride + k0 + q])
+                                     : partials[(size_t)b * kPartialStride + k0 + q])
+                          : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) a[q] += x[u][q];
+      }
+      const double r = wave_sum8_scatter(a);
+      if ((lane & 7) == 0 && k0 + (lane >> 3) < nvals) out[k0 + (lane >> 3)] = r;
+    }
+    __syncthreads();
+    return;
+  }
   for (int k = wave; k < nvals; k += nw) {
     const int kd = kind ? kind[k] : 0;
     const double id = kd == 0 ? 0.0 : (kd == 1 ? 1e300 : -1e300);
@@ -144,6 +196,27 @@ __device__ void reduce_partials(const double* partials, int nblocks, int nvals, 
   __syncthreads();
 }
 
+// One sum over the blocks' partials (value 0 of each), by the first wave;
+// partials written by an earlier kernel on the stream.  out[0] (LDS).
+__device__ void reduce_partials1(const double* partials, int nblocks, double* out) {
+  const int tid = flat_tid();
+  if (tid < 64) {
+    double a = 0.0;
+    for (int b0 = 0; b0 < nblocks; b0 += 256) {
+      double x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int b = b0 + 64 * u + tid;
+        x[u] = b < nblocks ? partials[(size_t)b * kPartialStride] : 0.0;
+      }
+      a += (x[0] + x[1]) + (x[2] + x[3]);
+    }
+    a = wave_sum(a);
+    if (tid == 0) out[0] = a;
+  }
+  __syncthreads();
+}
+
 // Block-level: wave partial of value k goes to red[k * nw + wave].
 __device__ __forceinline__ void wave_partial(double x, double* red, int k) {
   const int tid = flat_tid();
@@ -151,21 +224,12 @@ __device__ __forceinline__ void wave_partial(double x, double* red, int k) {
   if ((tid & 63) == 0) red[k * (block_threads() >> 6) + (tid >> 6)] = s;
 }
 
-// Eight values at once (their shuffle chains overlap): a[q] is the thread's
+// Eight values at once (one reduce-scatter): a[q] is the thread's
 // contribution to value k0 + q; wave sums go to red[k * nw + wave], k < nvals.
 __device__ __forceinline__ void wave_partials8(double (&a)[8], double* red, int k0, int nvals) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) a[q] += __shfl_xor(a[q], o, 64);
-  }
-  const int tid = flat_tid();
-  if ((tid & 63) == 0) {
-    const int nw = block_threads() >> 6, w = tid >> 6;
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (k0 + q < nvals) red[(k0 + q) * nw + w] = a[q];
-  }
+  const double s = wave_sum8_scatter(a);
+  const int tid = flat_tid(), lane = tid & 63;
+  if ((lane & 7) == 0 && k0 + (lane >> 3) < nvals) red[(k0 + (lane >> 3)) * (block_threads() >> 6) + (tid >> 6)] = s;
 }
 
 __device__ __forceinline__ void block_partials_out(const double* red, int nvals, double* partials,
@@ -184,15 +248,15 @@ __device__ __forceinline__ void block_partials_out(const double* red, int nvals,
 }
 
 // ----------------------------------------------------------------------------
-// GMRES scalar work (single thread of the last block)
+// GMRES scalar work (one thread of a block, from LDS copies)
 // ----------------------------------------------------------------------------
 
+__device__ int gmres_finish_column(GmresState* st, int j, const double* cj, double beta, const double* s2,
+                                   bool write);
+
 // Finish Arnoldi step j (called by the whole last block; nrm2 and s2 are in
-// LDS):  H(:, j) = s + s2,  H(j+1, j) = ||w1 - V s2||,  apply the previous
-// Givens rotations and a new one, update the residual estimate, test it and,
-// when the solve stops, back-substitute for y.  The serial scalar work runs
-// on one thread from LDS copies of H, cs, sn, g.
-__device__ void gmres_finish_column(GmresState* st, int j, const double* cj, double beta, const double* s2);
+// LDS):  H(:, j) = s + s2,  H(j+1, j) = ||w1 - V s2||,  then the Givens
+// update and test of gmres_finish_column.
 
 __device__ void gmres_finish_step(GmresState* st, int j, double nrm2, const double* s2) {
   // CGS2: H(:, j) = s + s2, beta = ||w1 - V s2|| = sqrt(||w1||^2 - |s2|^2)
@@ -207,32 +271,35 @@ __device__ void gmres_finish_step(GmresState* st, int j, double nrm2, const doub
     sh_beta = b2 > 0.0 ? sqrt(b2) : 0.0;
   }
   __syncthreads();
-  gmres_finish_column(st, j, colv, sh_beta, s2);
+  (void)gmres_finish_column(st, j, colv, sh_beta, s2, true);
 }
 
-// Finish Arnoldi step j given its Hessenberg column cj[0..j] (in LDS) and
+// Finish Arnoldi step j given its Hessenberg column cj[0..j] and
 // H(j+1, j) = beta: apply the previous Givens rotations and a new one,
-// update the residual estimate, test it and, when the solve stops,
-// back-substitute for y.  s2 (optional) is stored for the next basis vector.
-__device__ void gmres_finish_column(GmresState* st, int j, const double* cj, double beta, const double* s2) {
-  __shared__ double sh_H[(kMaxRestart + 1) * kMaxRestart];  // column-major (m+1) x (j+1) block
-  __shared__ double sh_cs[kMaxRestart], sh_sn[kMaxRestart], sh_g[kMaxRestart + 1], sh_y[kMaxRestart];
-  __shared__ int sh_stop;
+// update the residual estimate and test it.  Returns the stop code (0 go on,
+// 1 converged, 2 cycle full, 3 iteration cap) in every thread of the block.
+// write: this block stores the step (column j of R, rotation j, g_j after
+// and g_{j+1} before rotation, beta, the status, s2 and, when stopping, the
+// back-substituted y).  Several blocks of one kernel may evaluate the same
+// step, one of them writing: the others read only state that the step leaves
+// unchanged (rotations below j, g_j before rotation, the cycle's iteration
+// base), so each takes the writer's decision.
+__device__ int gmres_finish_column(GmresState* st, int j, const double* cj, double beta, const double* s2,
+                                   bool write) {
+  __shared__ double sh_col[kMaxRestart + 1];
+  __shared__ double sh_cs[kMaxRestart], sh_sn[kMaxRestart];
+  __shared__ double sh_gj, sh_gn, sh_resid;
+  __shared__ int sh_stop, sh_total;
   const int tid = flat_tid(), nt = block_threads();
   const int ld = kMaxRestart + 1;
-  // stage: columns 0..j-1 of H (rows 0..l), rotations, g
-  for (int e = tid; e < j * ld; e += nt) sh_H[e] = st->H[e];
   for (int i = tid; i < j; i += nt) {
     sh_cs[i] = st->cs[i];
     sh_sn[i] = st->sn[i];
   }
-  for (int i = tid; i <= j; i += nt) {
-    sh_g[i] = st->gv[i];
-    sh_H[j * ld + i] = cj[i];
-  }
+  for (int i = tid; i <= j; i += nt) sh_col[i] = cj[i];
   __syncthreads();
   if (tid == 0) {
-    double* col = sh_H + j * ld;  // column j, rotated in place
+    double* col = sh_col;  // column j, rotated in place
     col[j + 1] = beta;
     for (int i = 0; i < j; ++i) {
       const double a = col[i], b = col[i + 1];
@@ -241,20 +308,20 @@ __device__ void gmres_finish_column(GmresState* st, int j, const double* cj, dou
     }
     const double a = col[j], b = col[j + 1];
     const double rho = hypot(a, b);
-    double c = 1.0, s = 0.0;
+    double c = 1.0, sn = 0.0;
     if (rho > 0.0) {
       c = a / rho;
-      s = b / rho;
+      sn = b / rho;
     }
     col[j] = rho;
     col[j + 1] = 0.0;
     sh_cs[j] = c;
-    sh_sn[j] = s;
-    const double gj = sh_g[j];
-    sh_g[j + 1] = -s * gj;
-    sh_g[j] = c * gj;
-    const double resid = fabs(sh_g[j + 1]);
-    const int total = st->st.total_iters + 1;
+    sh_sn[j] = sn;
+    const double gj = st->gv[j];
+    sh_gj = c * gj;
+    sh_gn = -sn * gj;
+    const double resid = fabs(sh_gn);
+    const int total = st->cycle_base + j + 1;
     int done = 0;
     if (resid <= st->tol * st->st.beta0 || beta == 0.0)
       done = 1;
@@ -262,33 +329,49 @@ __device__ void gmres_finish_column(GmresState* st, int j, const double* cj, dou
       done = 2;
     else if (total >= st->maxit)
       done = 3;
-    if (done) {  // back substitution R y = g on the (j+1) x (j+1) triangle
-      for (int i = j; i >= 0; --i) {
-        double acc = sh_g[i];
-        for (int l = i + 1; l <= j; ++l) acc -= sh_H[l * ld + i] * sh_y[l];
-        const double d = sh_H[i * ld + i];
-        sh_y[i] = d != 0.0 ? acc / d : 0.0;
-      }
-    }
-    st->beta = beta;
-    st->st.jdone = j + 1;
-    st->st.total_iters = total;
-    st->st.resid = resid;
-    st->st.done = done;
+    sh_resid = resid;
+    sh_total = total;
     sh_stop = done;
   }
   __syncthreads();
-  // write back column j, the new rotation, g, s2 and (if stopping) y
-  for (int i = tid; i <= j + 1; i += nt) st->H[j * ld + i] = sh_H[j * ld + i];
+  const int stop = sh_stop;
+  if (!write) return stop;
+  for (int i = tid; i <= j + 1; i += nt) st->H[j * ld + i] = sh_col[i];
   if (s2)
     for (int i = tid; i <= j; i += nt) st->s2[i] = s2[i];
+  if (stop) {
+    // back substitution R y = g on the (j+1) x (j+1) triangle (columns below
+    // j of R and the rotated g below j from earlier steps)
+    __shared__ double sh_R[(kMaxRestart + 1) * kMaxRestart];
+    __shared__ double sh_g[kMaxRestart + 1], sh_y[kMaxRestart];
+    for (int e = tid; e < j * ld; e += nt) sh_R[e] = st->H[e];
+    for (int i = tid; i <= j; i += nt) sh_R[j * ld + i] = sh_col[i];
+    for (int i = tid; i < j; i += nt) sh_g[i] = st->gr[i];
+    if (tid == 0) sh_g[j] = sh_gj;
+    __syncthreads();
+    if (tid == 0) {
+      for (int i = j; i >= 0; --i) {
+        double acc = sh_g[i];
+        for (int l = i + 1; l <= j; ++l) acc -= sh_R[l * ld + i] * sh_y[l];
+        const double d = sh_R[i * ld + i];
+        sh_y[i] = d != 0.0 ? acc / d : 0.0;
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i <= j; i += nt) st->y[i] = sh_y[i];
+  }
   if (tid == 0) {
     st->cs[j] = sh_cs[j];
     st->sn[j] = sh_sn[j];
+    st->gr[j] = sh_gj;
+    st->gv[j + 1] = sh_gn;
+    st->beta = beta;
+    st->st.jdone = j + 1;
+    st->st.total_iters = sh_total;
+    st->st.resid = sh_resid;
+    st->st.done = stop;
   }
-  for (int i = tid; i <= j + 1; i += nt) st->gv[i] = sh_g[i];
-  if (sh_stop)
-    for (int i = tid; i <= j; i += nt) st->y[i] = sh_y[i];
+  return stop;
 }
 
 // ----------------------------------------------------------------------------
@@ -504,7 +587,8 @@ __global__ void __launch_bounds__(512) k_row_op(Geom g, const cplx* __restrict__
 template <int N>
 __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __restrict__ Es, const cplx* __restrict__ Gs,
                                                       const real* __restrict__ h, cplx* __restrict__ P,
-                                                      cplx* __restrict__ Q, const GmresState* __restrict__ st) {
+                                                      cplx* __restrict__ Q, GmresState* st,
+                                                      const double* __restrict__ pin, int nbin, int jb) {
   if (st->st.done) return;
   constexpr int E = Row<N>::E;
   constexpr int TPF = Row<N>::TPF;
@@ -518,6 +602,23 @@ __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __rest
   cplx* buf = base + chain * Row<N>::LDS;
   TwiddleSet<N> twx;
   gather_twiddles<N>(twx, t, TWX(g));
+  if (pin) {
+    // three-kernel step: finish Arnoldi step jb - 1 from the nbin block
+    // partials of ||u_jb||^2 written by A_jb (for jb = 0 only beta, the norm
+    // of the residual), in every block; block 0 stores the step
+    __shared__ double nrm[1];
+    __shared__ double cj[kMaxRestart + 1];
+    reduce_partials1(pin, nbin, nrm);
+    const double beta = sqrt(nrm[0] * g.inv_n);
+    const bool writer = blockIdx.x == 0;
+    if (jb == 0) {
+      if (writer && flat_tid() == 0) st->beta = beta;
+    } else {
+      for (int i = flat_tid(); i < jb; i += block_threads()) cj[i] = st->cproj[i];
+      __syncthreads();
+      if (gmres_finish_column(st, jb - 1, cj, beta, nullptr, writer)) return;
+    }
+  }
   cplx v[E], hi[E];
   load_spec_pair<N>(v, chain == 2 ? Gs : Es, ya, t, g.inv_nx);
   load_phys_pair<N>(hi, h, ya, t);
@@ -1013,28 +1114,65 @@ __global__ void __launch_bounds__(1024) k_col_precond_dot2(Geom g, const cplx* _
 // c = (2I - G) s with s = V^T w and G = V^T V (the first-order form of
 // G^{-1} s); this removes the loss of orthogonality that a second CGS pass
 // would remove, without a second pass over the basis.
-//   A_j: u_j = w_{j-1} - sum_{i<j} c_i V_i, ||u_j||^2
-//        (last block: finish step j-1 with H(:, j-1) = c, H(j, j-1) = ||u_j||);
+//   A_j: c = (2I - G) s from the block partials of C_{j-1};
+//        u_j = w_{j-1} - sum_{i<j} c_i V_i, partials of ||u_j||^2;
 //        E = F_y^-1 u_j, G = F_y^-1 (i ky u_j)
-//   B_j: the x part of the operator on (E, G)            (k_row_matvec3)
+//   B_j: finish step j-1 from the partials of A_j (H(:, j-1) = c,
+//        H(j, j-1) = ||u_j||, Givens update, stop test); then the x part
+//        of the operator on (E, G)                       (k_row_matvec3)
 //   C_j: z = M^-1 F(L u_j);  V_j = u_j / beta_j,  w_j = z / beta_j;
-//        s_i = <V_i, w_j>, G_ij = <V_i, V_j>, i <= j; c = (2I - G) s.
+//        partials of s_i = <V_i, w_j>, G_ij = <V_i, V_j>, i <= j.
+// No kernel ends in a single-block reduction: the next kernel on the stream
+// reduces the block partials in every block (identically, in a fixed order)
+// and one of its blocks stores the result, so the serial reduction and GMRES
+// scalar work overlap that kernel's own loads instead of idling the GPU.
 // The same Krylov basis, Hessenberg matrix and iterates as modified or
 // twice-iterated classical Gram-Schmidt, in exact arithmetic.
 
-// Kernel A.  win: w_{j-1} (or the residual for j = 0); u_j -> W.
+// Finish the projections of C_jc in a block of the following kernel A:
+// s_i = <V_i, w_jc> and column jc of the Gram matrix from the nb block
+// partials pin, then c = (2I - G) s into coef (LDS), i <= jc.  write: this
+// block stores s, the new row and column of G and c.  The other blocks read
+// only the Gram entries of earlier steps, which this step does not change.
+__device__ void cgs_coefficients(const Geom& g, GmresState* st, int jc, const double* pin, int nb, double* outv,
+                                 double* coef, bool write) {
+  const int tid = flat_tid(), nthr = block_threads();
+  constexpr int ld = kMaxRestart + 1;
+  reduce_partials<false>(pin, nb, 2 * (jc + 1), nullptr, outv);
+  for (int i = tid; i < 2 * (jc + 1); i += nthr) outv[i] *= g.inv_n;
+  __syncthreads();
+  // c_i = 2 s_i - sum_k G_ik s_k; G_ik, k < jc, from earlier steps, and
+  // G_{i,jc} = <V_i, V_jc> from this reduction
+  for (int i = tid; i <= jc; i += nthr) {
+    double acc = 0.0;
+    for (int k = 0; k < jc; ++k) acc += (i == jc ? outv[2 * k + 1] : st->G[i * ld + k]) * outv[2 * k];
+    acc += outv[2 * i + 1] * outv[2 * jc];
+    coef[i] = 2.0 * outv[2 * i] - acc;
+  }
+  __syncthreads();
+  if (write) {
+    for (int i = tid; i <= jc; i += nthr) {
+      st->s[i] = outv[2 * i];
+      st->G[i * ld + jc] = outv[2 * i + 1];
+      st->G[jc * ld + i] = outv[2 * i + 1];
+      st->cproj[i] = coef[i];
+    }
+  }
+}
+
+// Kernel A.  win: w_{j-1} (or the residual for j = 0); u_j -> W.  pin: the
+// block partials of C_{j-1} (same grid; unused for j = 0).
 template <int N>
 __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx* W, const cplx* __restrict__ V,
                                                    size_t vstride, int j, GmresState* st, cplx* __restrict__ Eo,
-                                                   cplx* __restrict__ Go, double* partials, int nblocks) {
+                                                   cplx* __restrict__ Go, double* partials,
+                                                   const double* __restrict__ pin) {
   if (st->st.done) return;
-  COL2_SETUP(N)
   __shared__ double coef[kMaxRestart + 1];
   __shared__ double red[16];
-  __shared__ double outv[1];
-  const int tid = flat_tid(), nthr = block_threads();
-  for (int i = tid; i < j; i += nthr) coef[i] = st->cproj[i];
-  __syncthreads();
+  __shared__ double outv[2 * (kMaxRestart + 1)];
+  if (j > 0) cgs_coefficients(g, st, j - 1, pin, gridDim.x, outv, coef, blockIdx.x == 0);
+  COL2_SETUP(N)
   constexpr int EH = E / 2;
   cplx u[EH];
 #pragma unroll
@@ -1080,31 +1218,20 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
     v[r] = chain == 0 ? cscale(v[r], g.inv_ny) : mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Ly) * g.inv_ny);
   fft<N, true, ColMap>(v, buf, t, twy, map);
   store_col<N>(v, chain == 0 ? Eo : Go, g.nh, col, t, valid);
-  block_partials_out(red, 1, partials, nullptr);
-  if (last_block_arrive(st->ctr, nblocks)) {
-    reduce_partials(partials, nblocks, 1, nullptr, outv);
-    const double beta = sqrt(outv[0] * g.inv_n);
-    if (j == 0) {
-      if (tid == 0) st->beta = beta;
-    } else {
-      __syncthreads();
-      gmres_finish_column(st, j - 1, coef, beta, nullptr);
-    }
-  }
+  block_partials_out(red, 1, partials, nullptr);  // finished by B_j
 }
 
 // Kernel C.  P, Q: x-part outputs of B_j for u_j; W: u_j; writes V_j and
-// w_j (into Wn), the projections s and the Gram column, then c = (2I - G) s.
+// w_j (into Wn) and the block partials of the projections s and of the Gram
+// column.
 template <int N>
 __global__ void __launch_bounds__(1024) k_col_precond_new(Geom g, const cplx* __restrict__ P,
                                                           const cplx* __restrict__ Q, const cplx* __restrict__ W,
                                                           cplx* __restrict__ V, cplx* __restrict__ Wn, size_t vstride,
-                                                          int j, GmresState* st, double* partials, int nblocks) {
+                                                          int j, const GmresState* st, double* partials) {
   if (st->st.done) return;
   COL2_SETUP(N)
   __shared__ double red[2 * (kMaxRestart + 1) * 16];
-  __shared__ double outv[2 * (kMaxRestart + 1)];
-  const int tid = flat_tid(), nthr = block_threads();
   const double ib = 1.0 / st->beta;
   cplx v[E];
   load_col<N>(v, chain == 0 ? P : Q, g.nh, col, t, valid);
@@ -1168,26 +1295,7 @@ __global__ void __launch_bounds__(1024) k_col_precond_new(Geom g, const cplx* __
     }
     wave_partials8(a, red, 2 * i0, nv);
   }
-  block_partials_out(red, nv, partials, nullptr);
-  if (last_block_arrive(st->ctr, nblocks)) {
-    reduce_partials(partials, nblocks, nv, nullptr, outv);
-    constexpr int ld = kMaxRestart + 1;
-    for (int i = tid; i <= j; i += nthr) {
-      outv[2 * i] *= g.inv_n;
-      outv[2 * i + 1] *= g.inv_n;
-      st->s[i] = outv[2 * i];
-      st->G[i * ld + j] = outv[2 * i + 1];
-      st->G[j * ld + i] = outv[2 * i + 1];
-    }
-    __syncthreads();
-    // c_i = 2 s_i - sum_k G_ik s_k, with column j of G from this reduction
-    for (int i = tid; i <= j; i += nthr) {
-      double acc = 0.0;
-      for (int k = 0; k < j; ++k) acc += st->G[i * ld + k] * outv[2 * k];
-      acc += outv[2 * i + 1] * outv[2 * j];  // G_ij s_j
-      st->cproj[i] = 2.0 * outv[2 * i] - acc;
-    }
-  }
+  block_partials_out(red, nv, partials, nullptr);  // finished by A_{j+1}
 }
 
 // sigma_hat += sum_{i<k} y_i V_i (or 0 when b == 0), then E, G of sigma_hat.
@@ -1370,6 +1478,7 @@ __global__ void __launch_bounds__(512) k_col_resid(Geom g, const cplx* __restric
           st->st.total_iters = 0;
           st->st.zero = 0;
         }
+        st->cycle_base = st->st.total_iters;
         if (need_b) {
           st->st.beta0 = sqrt(outv[1] * g.inv_n);
           st->st.bnorm = sqrt(outv[2] * g.inv_n);
@@ -1677,6 +1786,16 @@ __global__ void __launch_bounds__(256) k_field_stats(const real* __restrict__ h,
   }
 }
 
+// Adds the solve that just finished to the captured-step counters (one GMRES
+// cycle per solve there: anything but convergence counts as a failure).
+__global__ void __launch_bounds__(64) k_solve_stats(GmresState* st) {
+  if (threadIdx.x != 0) return;
+  const int it = st->st.total_iters;
+  st->st.g_total += it;
+  if (it > st->st.g_max) st->st.g_max = it;
+  if (st->st.done != 1) st->st.g_fail += 1;
+}
+
 // ----------------------------------------------------------------------------
 // Launch helper: the next launch can carry a pair of HIP events that the
 // runtime records at the start and end of that dispatch (kernel timing).
@@ -1921,9 +2040,27 @@ struct Chain {
   static bool col_ok(int nh) { return 2 * tc(nh) * Col<N>::TPF <= 1024 && (size_t)2 * tc(nh) * N * sizeof(cplx) <= kChainLds; }
 };
 
+// Blocks of the chain-parallel column kernels (A, C) for this grid.
+template <int N>
+static int col2_blocks_n(const Geom& g) {
+  const int tc = Chain<N>::tc(g.nh);
+  return (g.nh + tc - 1) / tc;
+}
+static int col2_blocks(const Geom& g) {
+  switch (g.ny) {
+#define X(n) \
+  case n:    \
+    return col2_blocks_n<n>(g);
+    SGN_SIZES(X)
+#undef X
+    default:
+      return 0;
+  }
+}
+
 template <int N>
 static hipError_t row_matvec3_n(const Geom& g, const cplx* E, const cplx* G, const real* h, cplx* P, cplx* Q,
-                                const GmresState* st, hipStream_t s) {
+                                GmresState* st, const double* pin, int jb, hipStream_t s) {
   if constexpr (!Chain<N>::row_ok) {
     return hipErrorNotSupported;
   } else {
@@ -1932,7 +2069,8 @@ static hipError_t row_matvec3_n(const Geom& g, const cplx* E, const cplx* G, con
     const size_t lb = (size_t)3 * r * Row<N>::LDS * sizeof(cplx);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(k_row_matvec3<N>), lb);
     if (e != hipSuccess) return e;
-    launch(k_row_matvec3<N>, dim3((g.ny / 2) / r), block, lb, s, g, E, G, h, P, Q, st);
+    launch(k_row_matvec3<N>, dim3((g.ny / 2) / r), block, lb, s, g, E, G, h, P, Q, st, pin, pin ? col2_blocks(g) : 0,
+           jb);
     return hipGetLastError();
   }
 }
@@ -1985,14 +2123,14 @@ static hipError_t col_precond_dot2_n(const Geom& g, const cplx* P, const cplx* Q
 
 template <int N>
 static hipError_t col_proj_n(const Geom& g, const cplx* win, cplx* W, const cplx* V, size_t vs, int j, GmresState* st,
-                             cplx* Eo, cplx* Go, double* partials, hipStream_t s) {
+                             cplx* Eo, cplx* Go, double* partials, const double* pin, hipStream_t s) {
   const int tc = Chain<N>::tc(g.nh);
   const dim3 block(tc, Col<N>::TPF, 2);
   const int nb = (g.nh + tc - 1) / tc;
   const size_t lb = (size_t)2 * tc * N * sizeof(cplx);
   hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_proj<N>), lb);
   if (e != hipSuccess) return e;
-  launch(k_col_proj<N>, dim3(nb), block, lb, s, g, win, W, V, vs, j, st, Eo, Go, partials, nb);
+  launch(k_col_proj<N>, dim3(nb), block, lb, s, g, win, W, V, vs, j, st, Eo, Go, partials, pin);
   return hipGetLastError();
 }
 
@@ -2005,7 +2143,7 @@ static hipError_t col_precond_new_n(const Geom& g, const cplx* P, const cplx* Q,
   const size_t lb = (size_t)2 * tc * N * sizeof(cplx);
   hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_precond_new<N>), lb);
   if (e != hipSuccess) return e;
-  launch(k_col_precond_new<N>, dim3(nb), block, lb, s, g, P, Q, W, V, Z, vs, j, st, partials, nb);
+  launch(k_col_precond_new<N>, dim3(nb), block, lb, s, g, P, Q, W, V, Z, vs, j, st, partials);
   return hipGetLastError();
 }
 
@@ -2046,8 +2184,8 @@ hipError_t launch_row_invariants(const Geom& g, const void* E, const void* G, co
   DISPATCH_NX(row_invariants_n, g, RC_(E), RC_(G), R_(h), R_(vx), R_(vy), R_(dyvx), partials, st, s)
 }
 hipError_t launch_row_matvec3(const Geom& g, const void* E, const void* G, const void* h, void* P, void* Q,
-                              const GmresState* st, hipStream_t s) {
-  DISPATCH_NX(row_matvec3_n, g, RC_(E), RC_(G), R_(h), WC_(P), WC_(Q), st, s)
+                              GmresState* st, const double* pin, int jb, hipStream_t s) {
+  DISPATCH_NX(row_matvec3_n, g, RC_(E), RC_(G), R_(h), WC_(P), WC_(Q), st, pin, jb, s)
 }
 hipError_t launch_col_fwd_eg(const Geom& g, const void* Ein, void* SIG, void* Go, hipStream_t s) {
   DISPATCH_NY(col_fwd_eg_n, g, RC_(Ein), WC_(SIG), WC_(Go), s)
@@ -2076,8 +2214,8 @@ hipError_t launch_col_precond_dot2(const Geom& g, const void* P, const void* Q, 
   DISPATCH_NY(col_precond_dot2_n, g, RC_(P), RC_(Q), RC_(V), vs, j, st, WC_(W), partials, s)
 }
 hipError_t launch_col_proj(const Geom& g, const void* win, void* W, const void* V, size_t vs, int j, GmresState* st,
-                           void* Eo, void* Go, double* partials, hipStream_t s) {
-  DISPATCH_NY(col_proj_n, g, RC_(win), WC_(W), RC_(V), vs, j, st, WC_(Eo), WC_(Go), partials, s)
+                           void* Eo, void* Go, double* partials, const double* pin, hipStream_t s) {
+  DISPATCH_NY(col_proj_n, g, RC_(win), WC_(W), RC_(V), vs, j, st, WC_(Eo), WC_(Go), partials, pin, s)
 }
 hipError_t launch_col_precond_new(const Geom& g, const void* P, const void* Q, const void* W, void* V, void* Z,
                                   size_t vs, int j, GmresState* st, double* partials, hipStream_t s) {
@@ -2110,6 +2248,10 @@ hipError_t launch_upd(const Geom& g, void* W, const void* V, size_t vs, int j, G
                       hipStream_t s) {
   const int nb = upd_blocks(g);
   launch(k_upd, dim3(nb), dim3(kUpdThreads), 0, s, g, WC_(W), RC_(V), vs, j, st, partials, nb);
+  return hipGetLastError();
+}
+hipError_t launch_solve_stats(const Geom&, GmresState* st, hipStream_t s) {
+  launch(k_solve_stats, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
 }
 hipError_t launch_field_stats(const Geom&, const void* h, const void* vx, const void* vy, size_t n, GmresState* st,

@@ -27,9 +27,9 @@
      const void* dyvx, double* partials, GmresState* st, hipStream_t s),                                        \
     (g, E, G, h, vx, vy, dyvx, partials, st, s))                                                                \
   X(row_matvec3,                                                                                                \
-    (const Geom& g, const void* E, const void* G, const void* h, void* P, void* Q, const GmresState* st,        \
-     hipStream_t s),                                                                                            \
-    (g, E, G, h, P, Q, st, s))                                                                                  \
+    (const Geom& g, const void* E, const void* G, const void* h, void* P, void* Q, GmresState* st,              \
+     const double* pin, int jb, hipStream_t s),                                                                 \
+    (g, E, G, h, P, Q, st, pin, jb, s))                                                                         \
   X(col_fwd_eg, (const Geom& g, const void* Ein, void* SIG, void* Go, hipStream_t s), (g, Ein, SIG, Go, s))    \
   X(col_basis_eg,                                                                                               \
     (const Geom& g, const void* W, void* V, size_t vs, int j, const GmresState* st, void* Eo, void* Go,         \
@@ -55,8 +55,8 @@
     (g, P, Q, V, vs, j, st, W, partials, s))                                                                    \
   X(col_proj,                                                                                                   \
     (const Geom& g, const void* win, void* W, const void* V, size_t vs, int j, GmresState* st, void* Eo,        \
-     void* Go, double* partials, hipStream_t s),                                                                \
-    (g, win, W, V, vs, j, st, Eo, Go, partials, s))                                                             \
+     void* Go, double* partials, const double* pin, hipStream_t s),                                             \
+    (g, win, W, V, vs, j, st, Eo, Go, partials, pin, s))                                                        \
   X(col_precond_new,                                                                                            \
     (const Geom& g, const void* P, const void* Q, const void* W, void* V, void* Z, size_t vs, int j,            \
      GmresState* st, double* partials, hipStream_t s),                                                          \
@@ -80,6 +80,7 @@
   X(upd, (const Geom& g, void* W, const void* V, size_t vs, int j, GmresState* st, double* partials,           \
           hipStream_t s),                                                                                       \
     (g, W, V, vs, j, st, partials, s))                                                                          \
+  X(solve_stats, (const Geom& g, GmresState* st, hipStream_t s), (g, st, s))                                 \
   X(field_stats,                                                                                                \
     (const Geom& g, const void* h, const void* vx, const void* vy, size_t n, GmresState* st, double* partials,  \
      hipStream_t s),                                                                                            \
@@ -90,15 +91,21 @@
 //   row_op: x part of the elliptic operator (mode 0), or of the residual with
 //     b = -div v (mode 1) or an explicit b (mode 2);
 //   row_matvec3: mode 0 of row_op with three concurrent transform chains;
+//     with pin (three-kernel step jb) it first finishes step jb - 1 from
+//     the block partials kernel A left in pin;
 //   row_flux / col_flux: fluxes, Bernoulli function and the RK4 combine;
 //   row_invariants / col_tail: invariant densities and the spectral tail;
 //   col_fwd_eg: sigma's 2D spectrum and the inverse y-transforms E, G;
 //   col_basis_eg / col_basis2 / col_precond_dot / col_precond_dot2 / upd: the
 //     four-kernel Arnoldi step (one- and two-chain variants);
-//   col_proj / col_precond_new (with row_matvec3): the three-kernel step;
+//   col_proj / col_precond_new (with row_matvec3): the three-kernel step; each
+//     leaves block partials that the next kernel of the step reduces (col_proj
+//     reads those of col_precond_new from pin, so the two need distinct
+//     partials buffers);
 //   col_update_eg: sigma_hat += V y (and the guess increment D);
 //   col_guess_eg: sigma_hat += D; col_resid: start of a GMRES cycle;
 //   col_inv / col_apply / col_filter / col_dy: building blocks;
+//   solve_stats: adds the finished solve to the captured-step counters;
 //   field_stats: min h and a non-finite flag over the state.
 
 namespace sgn {

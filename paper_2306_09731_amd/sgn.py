@@ -84,6 +84,9 @@ _SIGNATURES = {
     "sgn_rhs": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(sgn_solve_info)]),
     "sgn_rk4_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
                                     ctypes.POINTER(sgn_step_info)]),
+    "sgn_rk4_step_graph": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.POINTER(sgn_step_info),
+                                          ctypes.POINTER(ctypes.c_int32)]),
     "sgn_invariants": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(sgn_invariants_out)]),
     "sgn_derivative": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP]),
     "sgn_apply_operator": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int32]),
@@ -241,6 +244,18 @@ def sgn_rk4_step(ctx: Context, h, vx, vy, sigma, dt: float, nsteps: int = 1) -> 
                                      int(nsteps), ctypes.byref(info))
     _check(ctx, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
     return info
+
+
+def sgn_rk4_step_graph(ctx: Context, h, vx, vy, sigma, dt: float, nsteps: int = 1, iter_budget: int = 0):
+    """sgn_rk4_step with every step replayed as one captured HIP graph.
+    Returns (sgn_step_info, replayed)."""
+    info = sgn_step_info()
+    rep = ctypes.c_int32(0)
+    st = load_library().sgn_rk4_step_graph(ctx.handle, _field(ctx, h, "h"), _field(ctx, vx, "vx"),
+                                           _field(ctx, vy, "vy"), _field(ctx, sigma, "sigma"), float(dt),
+                                           int(nsteps), int(iter_budget), ctypes.byref(info), ctypes.byref(rep))
+    _check(ctx, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
+    return info, bool(rep.value)
 
 
 def sgn_rk4_step_ensemble(ctxs, fields, dts, nsteps: int):

@@ -74,7 +74,7 @@ def test_invalid_config(field, value):
 def test_workspace_fp32_mode_halves_the_fields():
     a = sgn.sgn_workspace_bytes(sgn.config_default(256, 128, 10.0, 5.0))
     b = sgn.sgn_workspace_bytes(sgn.config_default(256, 128, 10.0, 5.0, precision=sgn.SGN_FP32_MIXED))
-    nfields = 21 + 15
+    nfields = 21 + 15 + 4  # basis, working fields, checkpoint of a captured call
     # FP32 fields are half as large (both twiddle tables exist in either mode)
     assert a - b == nfields * 256 * 128 * 4
 
@@ -91,8 +91,8 @@ def test_workspace_size_scales_with_grid_and_restart():
     b = sgn.sgn_workspace_bytes(sgn.config_default(256, 64, 10.0, 5.0))
     c = sgn.sgn_workspace_bytes(sgn.config_default(128, 64, 10.0, 5.0, gmres_restart=40))
     field = 128 * 64 * 8
-    # Krylov basis: restart + 1 fields, plus 15 others
-    assert a >= 36 * field and b > a and c - a == 20 * field
+    # Krylov basis: restart + 1 fields, plus 15 working fields and a 4-field checkpoint
+    assert a >= 40 * field and b > a and c - a == 20 * field
 
 
 def test_init_rejects_bad_workspace_without_gpu():
@@ -127,3 +127,12 @@ def test_ensemble_and_autotune_host_checks():
     assert lib.sgn_rk4_step_ensemble(1, null, null, null, null, null, dts, 1, None) == sgn.SGN_ERR_INVALID_ARG
     assert lib.sgn_rk4_step_ensemble(0, null, null, null, null, null, None, 1, None) == sgn.SGN_OK
     assert lib.sgn_autotune(None, None) == sgn.SGN_ERR_INVALID_ARG
+
+
+def test_graph_step_host_checks():
+    lib = sgn.load_library()
+    rep = ctypes.c_int32(7)
+    assert lib.sgn_rk4_step_graph(None, None, None, None, None, 0.01, 1, 0, None, ctypes.byref(rep)) \
+        == sgn.SGN_ERR_INVALID_ARG
+    assert rep.value == 0  # cleared even on an argument error
+    assert lib.sgn_rk4_step_graph(None, None, None, None, None, 0.01, 1, 0, None, None) == sgn.SGN_ERR_INVALID_ARG
