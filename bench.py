@@ -120,6 +120,33 @@ def timed_guess_run(sgn, torch, box, state, w, dev, args):
             "note": "same tolerance; the first step of each call uses the plain warm start"}
 
 
+def graph_form(sgn, torch, box, state, w, dev, args):
+    """The same K steps (after W warm-up steps) with every RK4 step replayed as
+    one captured HIP graph (sgn_rk4_step_graph, automatic iteration budget),
+    beside the host-driven loop on a fresh context: bitwise the same states."""
+    out = {}
+    for mode in ("host", "graph"):
+        cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"], gmres_restart=w["restart"],
+                                 krasny=KRASNY)
+        ctx = sgn.sgn_init(cfg, dev)
+        f = [torch.from_numpy(a).to(dev).contiguous() for a in state]
+        step = (lambda n: sgn.sgn_rk4_step(ctx, *f, w["dt"], n)) if mode == "host" else \
+            (lambda n: sgn.sgn_rk4_step_graph(ctx, *f, w["dt"], n)[0])
+        if args.warmup > 0:
+            step(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step(args.steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[mode] = {"value": box.nx * box.ny * args.steps / el, "ms_per_step": el * 1e3 / args.steps}
+        out[mode + "_state"] = [t.clone() for t in f]
+        ctx.close()
+    same = all(torch.equal(a, b) for a, b in zip(out.pop("host_state"), out.pop("graph_state")))
+    out["identical_states"] = same
+    return out
+
+
 PRECISION_WORKLOAD = "gaussian_2048x2048"
 
 
@@ -316,6 +343,7 @@ def main():
         },
     }
     if not args.main_only:
+        out["graph_form"] = graph_form(sgn, torch, box, (h, vx, vy, s), w, dev, args)
         out["precision_form"] = precision_form(sgn, torch, dev, args)
         out["batched_form"] = batched_form(sgn, torch, dev, args)
     if not args.no_cpu_baseline:

@@ -260,6 +260,12 @@ int enqueue_residual(sgn_ctx* ctx, int mode, const void* h, const void* vx, cons
                                                      ctx->G, ctx->partials, nullptr, s));
     TIMED(SGN_KERNEL_ROW_MATVEC,
           sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, ctx->partials, 0, s));
+  } else if (ctx->arnoldi == 1) {  // basis kernel of step 0: V_0, E, G
+    TIMED(SGN_KERNEL_COL_BASIS,
+          sgn::launch_col_basis2(g, ctx->W, ctx->V, ctx->vstride, 0, ctx->st, ctx->E, ctx->G, nullptr, s));
+  } else {
+    TIMED(SGN_KERNEL_COL_BASIS,
+          sgn::launch_col_basis_eg(g, ctx->W, ctx->V, ctx->vstride, 0, ctx->st, ctx->E, ctx->G, nullptr, s));
   }
   return SGN_OK;
 }
@@ -280,20 +286,28 @@ int enqueue_arnoldi(sgn_ctx* ctx, const void* h, int it) {
           sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, ctx->partials, it + 1, s));
     return SGN_OK;
   }
-  if (ctx->arnoldi == 1) {
-    TIMED(SGN_KERNEL_COL_BASIS, sgn::launch_col_basis2(g, ctx->W, ctx->V, ctx->vstride, it, ctx->st, ctx->E, ctx->G, s));
+  // four-kernel step it: x part, projections, update, and the basis kernel of
+  // step it + 1, which finishes step it (so the status is current)
+  const bool two = ctx->arnoldi == 1;
+  if (two) {
     TIMED(SGN_KERNEL_ROW_MATVEC,
           sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, nullptr, 0, s));
     TIMED(SGN_KERNEL_COL_PRECOND_DOT, sgn::launch_col_precond_dot2(g, ctx->P, ctx->Q, ctx->V, ctx->vstride, it,
-                                                                   ctx->st, ctx->W, ctx->partials, s));
+                                                                   ctx->st, ctx->W, ctx->partials2, s));
   } else {
-    TIMED(SGN_KERNEL_COL_BASIS, sgn::launch_col_basis_eg(g, ctx->W, ctx->V, ctx->vstride, it, ctx->st, ctx->E, ctx->G, s));
     TIMED(SGN_KERNEL_ROW_MATVEC, sgn::launch_row_op(g, 0, ctx->E, ctx->G, h, nullptr, nullptr, ctx->P, ctx->Q,
                                                     nullptr, nullptr, 0, 1, ctx->st, s));
     TIMED(SGN_KERNEL_COL_PRECOND_DOT, sgn::launch_col_precond_dot(g, ctx->P, ctx->Q, ctx->V, ctx->vstride, it,
-                                                                  ctx->st, ctx->W, ctx->partials, s));
+                                                                  ctx->st, ctx->W, ctx->partials2, s));
   }
-  TIMED(SGN_KERNEL_GS_UPDATE, sgn::launch_upd(g, ctx->W, ctx->V, ctx->vstride, it, ctx->st, ctx->partials, s));
+  TIMED(SGN_KERNEL_GS_UPDATE, sgn::launch_upd(g, ctx->W, ctx->V, ctx->vstride, it, ctx->st, ctx->partials,
+                                              ctx->partials2, two ? 1 : 0, s));
+  if (two)
+    TIMED(SGN_KERNEL_COL_BASIS, sgn::launch_col_basis2(g, ctx->W, ctx->V, ctx->vstride, it + 1, ctx->st, ctx->E,
+                                                       ctx->G, ctx->partials, s));
+  else
+    TIMED(SGN_KERNEL_COL_BASIS, sgn::launch_col_basis_eg(g, ctx->W, ctx->V, ctx->vstride, it + 1, ctx->st, ctx->E,
+                                                         ctx->G, ctx->partials, s));
   return SGN_OK;
 }
 
@@ -586,6 +600,7 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   g.m1 = 1.0 / cfg->h_inf;
   g.dA = (2.0 * M_PI * cfg->Lx / nx) * (2.0 * M_PI * cfg->Ly / ny);
   g.fp32 = cfg->precision == SGN_FP32_MIXED;
+  g.m = cfg->gmres_restart;
   if (!sgn::chained_ok(g)) ctx->arnoldi = 0;
   char* base = ctx->ws;
   cplx* tw = reinterpret_cast<cplx*>(base + L.tw);

@@ -23,6 +23,7 @@ struct Geom {
   const float2* twx32;     // the same tables rounded to FP32 (mixed-precision mode)
   const float2* twy32;
   int fp32;                // 1: fields, spectra and transforms in FP32; reductions stay FP64
+  int m;                   // GMRES restart length (sizes the back-substitution scratch)
 };
 
 // GMRES state kept in device memory.  Written only by the single "last

@@ -147,16 +147,16 @@ __device__ void reduce_partials(const double* partials, int nblocks, int nvals, 
   const int tid = flat_tid();
   const int lane = tid & 63, wave = tid >> 6, nw = block_threads() >> 6;
   if (!kind) {
-    // sums: each wave takes eight values and keeps the loads of 128 blocks in
+    // sums: each wave takes eight values and keeps the loads of 256 blocks in
     // flight together
     for (int k0 = 8 * wave; k0 < nvals; k0 += 8 * nw) {
       double a[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) a[q] = 0.0;
-      for (int b0 = 0; b0 < nblocks; b0 += 128) {
-        double x[2][8];
+      for (int b0 = 0; b0 < nblocks; b0 += 256) {
+        double x[4][8];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < 4; ++u) {
           const int b = b0 + 64 * u + lane;
 #pragma unroll
           for (int q = 0; q < 8; ++q)
@@ -166,7 +166,7 @@ __device__ void reduce_partials(const double* partials, int nblocks, int nvals, 
                           : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
           for (int q = 0; q < 8; ++q) a[q] += x[u][q];
       }
@@ -254,24 +254,35 @@ __device__ __forceinline__ void block_partials_out(const double* red, int nvals,
 __device__ int gmres_finish_column(GmresState* st, int j, const double* cj, double beta, const double* s2,
                                    bool write);
 
-// Finish Arnoldi step j (called by the whole last block; nrm2 and s2 are in
-// LDS):  H(:, j) = s + s2,  H(j+1, j) = ||w1 - V s2||,  then the Givens
-// update and test of gmres_finish_column.
-
-__device__ void gmres_finish_step(GmresState* st, int j, double nrm2, const double* s2) {
-  // CGS2: H(:, j) = s + s2, beta = ||w1 - V s2|| = sqrt(||w1||^2 - |s2|^2)
+// Finish CGS2 Arnoldi step j in a block of the kernel that follows the
+// update kernel, from its nb block partials (value 0: ||w1||^2; 1 + i:
+// s2_i = <V_i, w1>): H(:, j) = s + s2 and H(j+1, j) = ||w1 - V s2|| =
+// sqrt(||w1||^2 - |s2|^2), then the Givens update and test of
+// gmres_finish_column (write: this block stores the step).  Leaves s2 in the
+// caller's LDS array and H(j+1, j) in beta; returns the stop code.
+__device__ int cgs2_finish(const Geom& g, GmresState* st, int j, const double* pin, int nb, double* s2, double& beta,
+                           bool write) {
+  __shared__ double outv[kMaxRestart + 2];
   __shared__ double colv[kMaxRestart + 1];
   __shared__ double sh_beta;
   const int tid = flat_tid(), nt = block_threads();
-  for (int i = tid; i <= j; i += nt) colv[i] = st->s[i] + s2[i];
+  reduce_partials<false>(pin, nb, j + 2, nullptr, outv);
+  for (int i = tid; i <= j; i += nt) {
+    s2[i] = outv[1 + i] * g.inv_n;
+    colv[i] = st->s[i] + s2[i];
+  }
   if (tid == 0) {
     double sum2 = 0.0;
-    for (int i = 0; i <= j; ++i) sum2 += s2[i] * s2[i];
-    const double b2 = nrm2 - sum2;
+    for (int i = 0; i <= j; ++i) {
+      const double x = outv[1 + i] * g.inv_n;
+      sum2 += x * x;
+    }
+    const double b2 = outv[0] * g.inv_n - sum2;
     sh_beta = b2 > 0.0 ? sqrt(b2) : 0.0;
   }
   __syncthreads();
-  (void)gmres_finish_column(st, j, colv, sh_beta, s2, true);
+  beta = sh_beta;
+  return gmres_finish_column(st, j, colv, sh_beta, s2, write);
 }
 
 // Finish Arnoldi step j given its Hessenberg column cj[0..j] and
@@ -341,19 +352,23 @@ __device__ int gmres_finish_column(GmresState* st, int j, const double* cj, doub
     for (int i = tid; i <= j; i += nt) st->s2[i] = s2[i];
   if (stop) {
     // back substitution R y = g on the (j+1) x (j+1) triangle (columns below
-    // j of R and the rotated g below j from earlier steps)
-    __shared__ double sh_R[(kMaxRestart + 1) * kMaxRestart];
+    // j of R and the rotated g below j from earlier steps); R is staged in
+    // the kernel's dynamic LDS (launched with at least m^2 doubles), which
+    // the block does not use otherwise once it stops
+    extern __shared__ double dyn_lds[];
+    double* sh_R = dyn_lds;
+    const int lr = j + 1;
     __shared__ double sh_g[kMaxRestart + 1], sh_y[kMaxRestart];
-    for (int e = tid; e < j * ld; e += nt) sh_R[e] = st->H[e];
-    for (int i = tid; i <= j; i += nt) sh_R[j * ld + i] = sh_col[i];
+    for (int e = tid; e < j * lr; e += nt) sh_R[e] = st->H[(e / lr) * ld + e % lr];
+    for (int i = tid; i <= j; i += nt) sh_R[j * lr + i] = sh_col[i];
     for (int i = tid; i < j; i += nt) sh_g[i] = st->gr[i];
     if (tid == 0) sh_g[j] = sh_gj;
     __syncthreads();
     if (tid == 0) {
       for (int i = j; i >= 0; --i) {
         double acc = sh_g[i];
-        for (int l = i + 1; l <= j; ++l) acc -= sh_R[l * ld + i] * sh_y[l];
-        const double d = sh_R[i * ld + i];
+        for (int l = i + 1; l <= j; ++l) acc -= sh_R[l * lr + i] * sh_y[l];
+        const double d = sh_R[i * lr + i];
         sh_y[i] = d != 0.0 ? acc / d : 0.0;
       }
     }
@@ -590,6 +605,25 @@ __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __rest
                                                       cplx* __restrict__ Q, GmresState* st,
                                                       const double* __restrict__ pin, int nbin, int jb) {
   if (st->st.done) return;
+  if (pin && blockIdx.x == gridDim.x - 1) {
+    // three-kernel step: the extra last block finishes Arnoldi step jb - 1
+    // from the nbin block partials of ||u_jb||^2 written by A_jb (for jb = 0
+    // only beta, the norm of the residual) while the others transform.  A
+    // transform block that misses this block's stop flag only does work
+    // whose result is never used.
+    __shared__ double nrm[1];
+    __shared__ double cj[kMaxRestart + 1];
+    reduce_partials1(pin, nbin, nrm);
+    const double beta = sqrt(nrm[0] * g.inv_n);
+    if (jb == 0) {
+      if (flat_tid() == 0) st->beta = beta;
+    } else {
+      for (int i = flat_tid(); i < jb; i += block_threads()) cj[i] = st->cproj[i];
+      __syncthreads();
+      (void)gmres_finish_column(st, jb - 1, cj, beta, nullptr, true);
+    }
+    return;
+  }
   constexpr int E = Row<N>::E;
   constexpr int TPF = Row<N>::TPF;
   constexpr int H = N / 2;
@@ -602,23 +636,6 @@ __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __rest
   cplx* buf = base + chain * Row<N>::LDS;
   TwiddleSet<N> twx;
   gather_twiddles<N>(twx, t, TWX(g));
-  if (pin) {
-    // three-kernel step: finish Arnoldi step jb - 1 from the nbin block
-    // partials of ||u_jb||^2 written by A_jb (for jb = 0 only beta, the norm
-    // of the residual), in every block; block 0 stores the step
-    __shared__ double nrm[1];
-    __shared__ double cj[kMaxRestart + 1];
-    reduce_partials1(pin, nbin, nrm);
-    const double beta = sqrt(nrm[0] * g.inv_n);
-    const bool writer = blockIdx.x == 0;
-    if (jb == 0) {
-      if (writer && flat_tid() == 0) st->beta = beta;
-    } else {
-      for (int i = flat_tid(); i < jb; i += block_threads()) cj[i] = st->cproj[i];
-      __syncthreads();
-      if (gmres_finish_column(st, jb - 1, cj, beta, nullptr, writer)) return;
-    }
-  }
   cplx v[E], hi[E];
   load_spec_pair<N>(v, chain == 2 ? Gs : Es, ya, t, g.inv_nx);
   load_phys_pair<N>(hi, h, ya, t);
@@ -957,15 +974,15 @@ __device__ __forceinline__ void col_emit_eg(Geom& g, cplx* v, cplx* buf, int t, 
 // Arnoldi: V_j = (W - sum_{i<j} s2_i V_i) / beta, then E, G of V_j.
 template <int N>
 __global__ void __launch_bounds__(512) k_col_basis_eg(Geom g, const cplx* __restrict__ W, cplx* __restrict__ V,
-                                                       size_t vstride, int j, const GmresState* __restrict__ st,
-                                                       cplx* __restrict__ Eo, cplx* __restrict__ Go) {
+                                                       size_t vstride, int j, GmresState* st, cplx* __restrict__ Eo,
+                                                       cplx* __restrict__ Go, const double* __restrict__ pin,
+                                                       int nbin) {
   if (st->st.done) return;
-  COL_SETUP(N)
   __shared__ double coef[kMaxRestart + 1];
-  const int tid = flat_tid();
-  for (int i = tid; i < j; i += block_threads()) coef[i] = st->s2[i];
-  __syncthreads();
-  const double ib = 1.0 / st->beta;
+  double beta = st->beta;  // j = 0: the residual norm
+  if (j > 0 && cgs2_finish(g, st, j - 1, pin, nbin, coef, beta, blockIdx.x == 0)) return;
+  COL_SETUP(N)
+  const double ib = 1.0 / beta;
   cplx v[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -1013,16 +1030,15 @@ __global__ void __launch_bounds__(512) k_col_basis_eg(Geom g, const cplx* __rest
 // its inverse y-transforms E (chain 0) and G (chain 1) computed concurrently.
 template <int N>
 __global__ void __launch_bounds__(1024) k_col_basis2(Geom g, const cplx* __restrict__ W, cplx* __restrict__ V,
-                                                     size_t vstride, int j, const GmresState* __restrict__ st,
-                                                     cplx* __restrict__ Eo, cplx* __restrict__ Go) {
+                                                     size_t vstride, int j, GmresState* st, cplx* __restrict__ Eo,
+                                                     cplx* __restrict__ Go, const double* __restrict__ pin,
+                                                     int nbin) {
   if (st->st.done) return;
-  COL2_SETUP(N)
   __shared__ double coef[kMaxRestart + 1];
-  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
-  const int nthr = blockDim.x * blockDim.y * blockDim.z;
-  for (int i = tid; i < j; i += nthr) coef[i] = st->s2[i];
-  __syncthreads();
-  const double ib = 1.0 / st->beta;
+  double beta = st->beta;  // j = 0: the residual norm
+  if (j > 0 && cgs2_finish(g, st, j - 1, pin, nbin, coef, beta, blockIdx.x == 0)) return;
+  COL2_SETUP(N)
+  const double ib = 1.0 / beta;
   cplx v[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -1057,12 +1073,11 @@ __global__ void __launch_bounds__(1024) k_col_basis2(Geom g, const cplx* __restr
 template <int N>
 __global__ void __launch_bounds__(1024) k_col_precond_dot2(Geom g, const cplx* __restrict__ P,
                                                            const cplx* __restrict__ Q, const cplx* __restrict__ V,
-                                                           size_t vstride, int j, GmresState* st,
-                                                           cplx* __restrict__ W, double* partials, int nblocks) {
+                                                           size_t vstride, int j, const GmresState* st,
+                                                           cplx* __restrict__ W, double* partials) {
   if (st->st.done) return;
   COL2_SETUP(N)
   __shared__ double red[(kMaxRestart + 1) * 16];
-  __shared__ double outv[kMaxRestart + 1];
   cplx v[E];
   load_col<N>(v, chain == 0 ? P : Q, g.nh, col, t, valid);
   fft<N, false, ColMap>(v, buf, t, twy, map);
@@ -1101,11 +1116,7 @@ __global__ void __launch_bounds__(1024) k_col_precond_dot2(Geom g, const cplx* _
     }
     wave_partials8(a, red, i0, j + 1);
   }
-  block_partials_out(red, j + 1, partials, nullptr);
-  if (last_block_arrive(st->ctr, nblocks)) {
-    reduce_partials(partials, nblocks, j + 1, nullptr, outv);
-    for (int i = flat_tid(); i <= j; i += block_threads()) st->s[i] = outv[i] * g.inv_n;
-  }
+  block_partials_out(red, j + 1, partials, nullptr);  // reduced by the update kernel
 }
 
 // Three-kernel Arnoldi step (kernels A, B, C), one pass over the basis each.
@@ -1117,15 +1128,16 @@ __global__ void __launch_bounds__(1024) k_col_precond_dot2(Geom g, const cplx* _
 //   A_j: c = (2I - G) s from the block partials of C_{j-1};
 //        u_j = w_{j-1} - sum_{i<j} c_i V_i, partials of ||u_j||^2;
 //        E = F_y^-1 u_j, G = F_y^-1 (i ky u_j)
-//   B_j: finish step j-1 from the partials of A_j (H(:, j-1) = c,
-//        H(j, j-1) = ||u_j||, Givens update, stop test); then the x part
-//        of the operator on (E, G)                       (k_row_matvec3)
+//   B_j: the x part of the operator on (E, G)            (k_row_matvec3);
+//        one extra block finishes step j-1 from the partials of A_j
+//        (H(:, j-1) = c, H(j, j-1) = ||u_j||, Givens update, stop test)
 //   C_j: z = M^-1 F(L u_j);  V_j = u_j / beta_j,  w_j = z / beta_j;
 //        partials of s_i = <V_i, w_j>, G_ij = <V_i, V_j>, i <= j.
 // No kernel ends in a single-block reduction: the next kernel on the stream
-// reduces the block partials in every block (identically, in a fixed order)
-// and one of its blocks stores the result, so the serial reduction and GMRES
-// scalar work overlap that kernel's own loads instead of idling the GPU.
+// finishes it (A in every block, identically and in a fixed order, with
+// block 0 storing the result; B in one extra block), so the serial reduction
+// and the GMRES scalar work overlap that kernel's own work instead of idling
+// the GPU.
 // The same Krylov basis, Hessenberg matrix and iterates as modified or
 // twice-iterated classical Gram-Schmidt, in exact arithmetic.
 
@@ -1385,12 +1397,11 @@ __device__ __forceinline__ void col_combine(Geom& g, cplx* v, cplx* buf, int t, 
 template <int N>
 __global__ void __launch_bounds__(512) k_col_precond_dot(Geom g, const cplx* __restrict__ P,
                                                           const cplx* __restrict__ Q, const cplx* __restrict__ V,
-                                                          size_t vstride, int j, GmresState* st, cplx* __restrict__ W,
-                                                          double* partials, int nblocks) {
+                                                          size_t vstride, int j, const GmresState* st,
+                                                          cplx* __restrict__ W, double* partials) {
   if (st->st.done) return;
   COL_SETUP(N)
   __shared__ double red[(kMaxRestart + 1) * 16];
-  __shared__ double outv[kMaxRestart + 1];
   cplx v[E];
   col_combine<N>(g, v, buf, t, col, valid, P, Q, twy);
   const double kx = col * g.inv_Lx;
@@ -1418,11 +1429,7 @@ __global__ void __launch_bounds__(512) k_col_precond_dot(Geom g, const cplx* __r
     }
     wave_partials8(a, red, i0, j + 1);
   }
-  block_partials_out(red, j + 1, partials, nullptr);
-  if (last_block_arrive(st->ctr, nblocks)) {
-    reduce_partials(partials, nblocks, j + 1, nullptr, outv);
-    for (int i = flat_tid(); i <= j; i += block_threads()) st->s[i] = outv[i] * g.inv_n;
-  }
+  block_partials_out(red, j + 1, partials, nullptr);  // reduced by the update kernel
 }
 
 // Start of a GMRES cycle: r = M^-1 (b - L sigma) with F(b - L sigma) =
@@ -1685,14 +1692,17 @@ constexpr int kUpdEpt = 4;
 //   s2_i = <V_i, w1>, ||w1||^2; the last block finishes Arnoldi step j.
 __global__ void __launch_bounds__(kUpdThreads) k_upd(Geom g, cplx* __restrict__ W, const cplx* __restrict__ V,
                                                      size_t vstride, int j, GmresState* st, double* partials,
-                                                     int nblocks) {
+                                                     const double* __restrict__ pin, int nbin) {
   if (st->st.done) return;
   __shared__ double coef[kMaxRestart + 1];
   __shared__ double red[(kMaxRestart + 2) * (kUpdThreads / 64)];
-  __shared__ double outv[kMaxRestart + 2];
   const int tid = threadIdx.x;
-  for (int i = tid; i <= j; i += kUpdThreads) coef[i] = st->s[i];
+  // s_i = <V_i, w> from the nbin block partials of the projection kernel
+  reduce_partials<false>(pin, nbin, j + 1, nullptr, coef);
+  for (int i = tid; i <= j; i += kUpdThreads) coef[i] *= g.inv_n;
   __syncthreads();
+  if (blockIdx.x == 0)
+    for (int i = tid; i <= j; i += kUpdThreads) st->s[i] = coef[i];
   const size_t total = (size_t)g.nh * g.ny;
   cplx w[kUpdEpt];
   double wt[kUpdEpt];
@@ -1749,13 +1759,7 @@ __global__ void __launch_bounds__(kUpdThreads) k_upd(Geom g, cplx* __restrict__ 
     }
     wave_partials8(a, red, k0, j + 2);
   }
-  block_partials_out(red, j + 2, partials, nullptr);
-  if (last_block_arrive(st->ctr, nblocks)) {
-    reduce_partials(partials, nblocks, j + 2, nullptr, outv);
-    for (int i = tid; i <= j + 1; i += kUpdThreads) outv[i] *= g.inv_n;
-    __syncthreads();
-    gmres_finish_step(st, j, outv[0], outv + 1);
-  }
+  block_partials_out(red, j + 2, partials, nullptr);  // finished by the next basis kernel
 }
 
 // min h and a non-finite flag over (h, vx, vy).
@@ -1847,6 +1851,13 @@ struct ColLaunch {
   static size_t lds(int nh) { return (size_t)tc(nh) * N * sizeof(cplx); }
   static dim3 grid(int nh) { return dim3((nh + tc(nh) - 1) / tc(nh)); }
 };
+
+// Dynamic LDS of a kernel that may finish an Arnoldi step (finish): at least
+// the m^2 doubles of the back substitution.
+static size_t with_finish_lds(const Geom& g, size_t bytes, bool finish) {
+  const size_t need = finish ? (size_t)g.m * g.m * sizeof(double) : 0;
+  return bytes > need ? bytes : need;
+}
 
 static hipError_t allow_lds(const void* fn, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
@@ -1951,10 +1962,17 @@ static hipError_t col_fwd_eg_n(const Geom& g, const cplx* Ein, cplx* SIG, cplx* 
   COL_LAUNCH(k_col_fwd_eg<N>, g, Ein, SIG, Go);
 }
 
+int upd_blocks(const Geom& g);
+
 template <int N>
-static hipError_t col_basis_eg_n(const Geom& g, const cplx* W, cplx* V, size_t vs, int j, const GmresState* st,
-                                 cplx* Eo, cplx* Go, hipStream_t s) {
-  COL_LAUNCH(k_col_basis_eg<N>, g, W, V, vs, j, st, Eo, Go);
+static hipError_t col_basis_eg_n(const Geom& g, const cplx* W, cplx* V, size_t vs, int j, GmresState* st, cplx* Eo,
+                                 cplx* Go, const double* pin, hipStream_t s) {
+  const size_t lb = with_finish_lds(g, ColLaunch<N>::lds(g.nh), j > 0);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_basis_eg<N>), lb);
+  if (e != hipSuccess) return e;
+  launch(k_col_basis_eg<N>, ColLaunch<N>::grid(g.nh), ColLaunch<N>::block(g.nh), lb, s, g, W, V, vs, j, st, Eo, Go,
+         pin, upd_blocks(g));
+  return hipGetLastError();
 }
 
 template <int N>
@@ -1971,8 +1989,7 @@ static hipError_t col_guess_eg_n(const Geom& g, cplx* SIG, const cplx* D, cplx* 
 template <int N>
 static hipError_t col_precond_dot_n(const Geom& g, const cplx* P, const cplx* Q, const cplx* V, size_t vs, int j,
                                     GmresState* st, cplx* W, double* partials, hipStream_t s) {
-  const int nb = (int)ColLaunch<N>::grid(g.nh).x;
-  COL_LAUNCH(k_col_precond_dot<N>, g, P, Q, V, vs, j, st, W, partials, nb);
+  COL_LAUNCH(k_col_precond_dot<N>, g, P, Q, V, vs, j, st, W, partials);
 }
 
 template <int N>
@@ -2040,7 +2057,24 @@ struct Chain {
   static bool col_ok(int nh) { return 2 * tc(nh) * Col<N>::TPF <= 1024 && (size_t)2 * tc(nh) * N * sizeof(cplx) <= kChainLds; }
 };
 
-// Blocks of the chain-parallel column kernels (A, C) for this grid.
+// Blocks of the single-chain column kernels for this grid.
+template <int N>
+static int col1_blocks_n(const Geom& g) {
+  return (int)ColLaunch<N>::grid(g.nh).x;
+}
+static int col1_blocks(const Geom& g) {
+  switch (g.ny) {
+#define X(n) \
+  case n:    \
+    return col1_blocks_n<n>(g);
+    SGN_SIZES(X)
+#undef X
+    default:
+      return 0;
+  }
+}
+
+// Blocks of the chain-parallel column kernels for this grid.
 template <int N>
 static int col2_blocks_n(const Geom& g) {
   const int tc = Chain<N>::tc(g.nh);
@@ -2066,11 +2100,11 @@ static hipError_t row_matvec3_n(const Geom& g, const cplx* E, const cplx* G, con
   } else {
     const int r = Chain<N>::rpb(g.ny);
     const dim3 block(Row<N>::TPF, 3 * r);
-    const size_t lb = (size_t)3 * r * Row<N>::LDS * sizeof(cplx);
+    const size_t lb = with_finish_lds(g, (size_t)3 * r * Row<N>::LDS * sizeof(cplx), pin != nullptr);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(k_row_matvec3<N>), lb);
     if (e != hipSuccess) return e;
-    launch(k_row_matvec3<N>, dim3((g.ny / 2) / r), block, lb, s, g, E, G, h, P, Q, st, pin, pin ? col2_blocks(g) : 0,
-           jb);
+    const int nb = (g.ny / 2) / r + (pin ? 1 : 0);  // + the block that finishes the step
+    launch(k_row_matvec3<N>, dim3(nb), block, lb, s, g, E, G, h, P, Q, st, pin, pin ? col2_blocks(g) : 0, jb);
     return hipGetLastError();
   }
 }
@@ -2097,14 +2131,14 @@ bool chained_ok(const Geom& g) {
 }
 
 template <int N>
-static hipError_t col_basis2_n(const Geom& g, const cplx* W, cplx* V, size_t vs, int j, const GmresState* st,
-                               cplx* Eo, cplx* Go, hipStream_t s) {
+static hipError_t col_basis2_n(const Geom& g, const cplx* W, cplx* V, size_t vs, int j, GmresState* st, cplx* Eo,
+                               cplx* Go, const double* pin, hipStream_t s) {
   const int tc = Chain<N>::tc(g.nh);
   const dim3 block(tc, Col<N>::TPF, 2);
-  const size_t lb = (size_t)2 * tc * N * sizeof(cplx);
+  const size_t lb = with_finish_lds(g, (size_t)2 * tc * N * sizeof(cplx), j > 0);
   hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_basis2<N>), lb);
   if (e != hipSuccess) return e;
-  launch(k_col_basis2<N>, dim3((g.nh + tc - 1) / tc), block, lb, s, g, W, V, vs, j, st, Eo, Go);
+  launch(k_col_basis2<N>, dim3((g.nh + tc - 1) / tc), block, lb, s, g, W, V, vs, j, st, Eo, Go, pin, upd_blocks(g));
   return hipGetLastError();
 }
 
@@ -2117,7 +2151,7 @@ static hipError_t col_precond_dot2_n(const Geom& g, const cplx* P, const cplx* Q
   const size_t lb = (size_t)2 * tc * N * sizeof(cplx);
   hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_precond_dot2<N>), lb);
   if (e != hipSuccess) return e;
-  launch(k_col_precond_dot2<N>, dim3(nb), block, lb, s, g, P, Q, V, vs, j, st, W, partials, nb);
+  launch(k_col_precond_dot2<N>, dim3(nb), block, lb, s, g, P, Q, V, vs, j, st, W, partials);
   return hipGetLastError();
 }
 
@@ -2190,13 +2224,13 @@ hipError_t launch_row_matvec3(const Geom& g, const void* E, const void* G, const
 hipError_t launch_col_fwd_eg(const Geom& g, const void* Ein, void* SIG, void* Go, hipStream_t s) {
   DISPATCH_NY(col_fwd_eg_n, g, RC_(Ein), WC_(SIG), WC_(Go), s)
 }
-hipError_t launch_col_basis_eg(const Geom& g, const void* W, void* V, size_t vs, int j, const GmresState* st, void* Eo,
-                               void* Go, hipStream_t s) {
-  DISPATCH_NY(col_basis_eg_n, g, RC_(W), WC_(V), vs, j, st, WC_(Eo), WC_(Go), s)
+hipError_t launch_col_basis_eg(const Geom& g, const void* W, void* V, size_t vs, int j, GmresState* st, void* Eo,
+                               void* Go, const double* pin, hipStream_t s) {
+  DISPATCH_NY(col_basis_eg_n, g, RC_(W), WC_(V), vs, j, st, WC_(Eo), WC_(Go), pin, s)
 }
-hipError_t launch_col_basis2(const Geom& g, const void* W, void* V, size_t vs, int j, const GmresState* st, void* Eo,
-                             void* Go, hipStream_t s) {
-  DISPATCH_NY(col_basis2_n, g, RC_(W), WC_(V), vs, j, st, WC_(Eo), WC_(Go), s)
+hipError_t launch_col_basis2(const Geom& g, const void* W, void* V, size_t vs, int j, GmresState* st, void* Eo,
+                             void* Go, const double* pin, hipStream_t s) {
+  DISPATCH_NY(col_basis2_n, g, RC_(W), WC_(V), vs, j, st, WC_(Eo), WC_(Go), pin, s)
 }
 hipError_t launch_col_update_eg(const Geom& g, void* SIG, const void* V, size_t vs, const GmresState* st, void* Eo,
                                 void* Go, void* D, hipStream_t s) {
@@ -2245,9 +2279,10 @@ hipError_t launch_col_flux(const Geom& g, const void* dhp, const void* qy, const
   DISPATCH_NY(col_flux_n, g, R_(dhp), R_(qy), R_(B), rk, fh, fvy, s)
 }
 hipError_t launch_upd(const Geom& g, void* W, const void* V, size_t vs, int j, GmresState* st, double* partials,
-                      hipStream_t s) {
+                      const double* pin, int chained, hipStream_t s) {
   const int nb = upd_blocks(g);
-  launch(k_upd, dim3(nb), dim3(kUpdThreads), 0, s, g, WC_(W), RC_(V), vs, j, st, partials, nb);
+  const int nbin = chained ? col2_blocks(g) : col1_blocks(g);  // blocks of the projection kernel
+  launch(k_upd, dim3(nb), dim3(kUpdThreads), 0, s, g, WC_(W), RC_(V), vs, j, st, partials, pin, nbin);
   return hipGetLastError();
 }
 hipError_t launch_solve_stats(const Geom&, GmresState* st, hipStream_t s) {

@@ -32,13 +32,13 @@
     (g, E, G, h, P, Q, st, pin, jb, s))                                                                         \
   X(col_fwd_eg, (const Geom& g, const void* Ein, void* SIG, void* Go, hipStream_t s), (g, Ein, SIG, Go, s))    \
   X(col_basis_eg,                                                                                               \
-    (const Geom& g, const void* W, void* V, size_t vs, int j, const GmresState* st, void* Eo, void* Go,         \
-     hipStream_t s),                                                                                            \
-    (g, W, V, vs, j, st, Eo, Go, s))                                                                            \
+    (const Geom& g, const void* W, void* V, size_t vs, int j, GmresState* st, void* Eo, void* Go,               \
+     const double* pin, hipStream_t s),                                                                         \
+    (g, W, V, vs, j, st, Eo, Go, pin, s))                                                                       \
   X(col_basis2,                                                                                                 \
-    (const Geom& g, const void* W, void* V, size_t vs, int j, const GmresState* st, void* Eo, void* Go,         \
-     hipStream_t s),                                                                                            \
-    (g, W, V, vs, j, st, Eo, Go, s))                                                                            \
+    (const Geom& g, const void* W, void* V, size_t vs, int j, GmresState* st, void* Eo, void* Go,               \
+     const double* pin, hipStream_t s),                                                                         \
+    (g, W, V, vs, j, st, Eo, Go, pin, s))                                                                       \
   X(col_update_eg,                                                                                              \
     (const Geom& g, void* SIG, const void* V, size_t vs, const GmresState* st, void* Eo, void* Go, void* D,     \
      hipStream_t s),                                                                                            \
@@ -78,8 +78,8 @@
      hipStream_t s),                                                                                            \
     (g, dhp, qy, B, rk, fh, fvy, s))                                                                            \
   X(upd, (const Geom& g, void* W, const void* V, size_t vs, int j, GmresState* st, double* partials,           \
-          hipStream_t s),                                                                                       \
-    (g, W, V, vs, j, st, partials, s))                                                                          \
+          const double* pin, int chained, hipStream_t s),                                                       \
+    (g, W, V, vs, j, st, partials, pin, chained, s))                                                            \
   X(solve_stats, (const Geom& g, GmresState* st, hipStream_t s), (g, st, s))                                 \
   X(field_stats,                                                                                                \
     (const Geom& g, const void* h, const void* vx, const void* vy, size_t n, GmresState* st, double* partials,  \
@@ -91,13 +91,15 @@
 //   row_op: x part of the elliptic operator (mode 0), or of the residual with
 //     b = -div v (mode 1) or an explicit b (mode 2);
 //   row_matvec3: mode 0 of row_op with three concurrent transform chains;
-//     with pin (three-kernel step jb) it first finishes step jb - 1 from
-//     the block partials kernel A left in pin;
+//     with pin (three-kernel step jb) one extra block finishes step jb - 1
+//     from the block partials kernel A left in pin;
 //   row_flux / col_flux: fluxes, Bernoulli function and the RK4 combine;
 //   row_invariants / col_tail: invariant densities and the spectral tail;
 //   col_fwd_eg: sigma's 2D spectrum and the inverse y-transforms E, G;
 //   col_basis_eg / col_basis2 / col_precond_dot / col_precond_dot2 / upd: the
-//     four-kernel Arnoldi step (one- and two-chain variants);
+//     four-kernel Arnoldi step (one- and two-chain variants); upd reduces the
+//     projection kernel's partials (pin; chained: which variant wrote them)
+//     and the basis kernel of step j + 1 finishes step j from upd's;
 //   col_proj / col_precond_new (with row_matvec3): the three-kernel step; each
 //     leaves block partials that the next kernel of the step reduces (col_proj
 //     reads those of col_precond_new from pin, so the two need distinct
