@@ -605,25 +605,6 @@ __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __rest
                                                       cplx* __restrict__ Q, GmresState* st,
                                                       const double* __restrict__ pin, int nbin, int jb) {
   if (st->st.done) return;
-  if (pin && blockIdx.x == gridDim.x - 1) {
-    // three-kernel step: the extra last block finishes Arnoldi step jb - 1
-    // from the nbin block partials of ||u_jb||^2 written by A_jb (for jb = 0
-    // only beta, the norm of the residual) while the others transform.  A
-    // transform block that misses this block's stop flag only does work
-    // whose result is never used.
-    __shared__ double nrm[1];
-    __shared__ double cj[kMaxRestart + 1];
-    reduce_partials1(pin, nbin, nrm);
-    const double beta = sqrt(nrm[0] * g.inv_n);
-    if (jb == 0) {
-      if (flat_tid() == 0) st->beta = beta;
-    } else {
-      for (int i = flat_tid(); i < jb; i += block_threads()) cj[i] = st->cproj[i];
-      __syncthreads();
-      (void)gmres_finish_column(st, jb - 1, cj, beta, nullptr, true);
-    }
-    return;
-  }
   constexpr int E = Row<N>::E;
   constexpr int TPF = Row<N>::TPF;
   constexpr int H = N / 2;
@@ -634,6 +615,24 @@ __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __rest
   const int ya = 2 * (blockIdx.x * (blockDim.y / 3) + slot);
   cplx* base = lds + slot * 3 * Row<N>::LDS;
   cplx* buf = base + chain * Row<N>::LDS;
+  if (pin) {
+    // three-kernel step: finish Arnoldi step jb - 1 from the nbin block
+    // partials of ||u_jb||^2 written by A_jb (for jb = 0 only beta, the norm
+    // of the residual), identically in every block so that every block knows
+    // whether to stop; block 0 stores the step
+    __shared__ double nrm[1];
+    __shared__ double cj[kMaxRestart + 1];
+    reduce_partials1(pin, nbin, nrm);
+    const double beta = sqrt(nrm[0] * g.inv_n);
+    const bool writer = blockIdx.x == 0;
+    if (jb == 0) {
+      if (writer && flat_tid() == 0) st->beta = beta;
+    } else {
+      for (int i = flat_tid(); i < jb; i += block_threads()) cj[i] = st->cproj[i];
+      __syncthreads();
+      if (gmres_finish_column(st, jb - 1, cj, beta, nullptr, writer)) return;
+    }
+  }
   TwiddleSet<N> twx;
   gather_twiddles<N>(twx, t, TWX(g));
   cplx v[E], hi[E];
@@ -1128,16 +1127,17 @@ __global__ void __launch_bounds__(1024) k_col_precond_dot2(Geom g, const cplx* _
 //   A_j: c = (2I - G) s from the block partials of C_{j-1};
 //        u_j = w_{j-1} - sum_{i<j} c_i V_i, partials of ||u_j||^2;
 //        E = F_y^-1 u_j, G = F_y^-1 (i ky u_j)
-//   B_j: the x part of the operator on (E, G)            (k_row_matvec3);
-//        one extra block finishes step j-1 from the partials of A_j
-//        (H(:, j-1) = c, H(j, j-1) = ||u_j||, Givens update, stop test)
+//   B_j: finish step j-1 from the partials of A_j (H(:, j-1) = c,
+//        H(j, j-1) = ||u_j||, Givens update, stop test); then the x part
+//        of the operator on (E, G)                       (k_row_matvec3)
 //   C_j: z = M^-1 F(L u_j);  V_j = u_j / beta_j,  w_j = z / beta_j;
 //        partials of s_i = <V_i, w_j>, G_ij = <V_i, V_j>, i <= j.
 // No kernel ends in a single-block reduction: the next kernel on the stream
-// finishes it (A in every block, identically and in a fixed order, with
-// block 0 storing the result; B in one extra block), so the serial reduction
-// and the GMRES scalar work overlap that kernel's own work instead of idling
-// the GPU.
+// finishes it in every block (identically, in a fixed order), with block 0
+// storing the result, so the serial reduction and the GMRES scalar work no
+// longer idle the GPU at the end of a kernel.  (A single finishing block in B
+// would let the other blocks run a useless transform on the stopping step,
+// which costs more than the short prologue.)
 // The same Krylov basis, Hessenberg matrix and iterates as modified or
 // twice-iterated classical Gram-Schmidt, in exact arithmetic.
 
@@ -1684,7 +1684,7 @@ __global__ void __launch_bounds__(512) k_col_flux(Geom g, const real* __restrict
 // Elementwise kernels
 // ----------------------------------------------------------------------------
 
-constexpr int kUpdThreads = 256;
+constexpr int kUpdThreads = 1024;  // large blocks: fewer partials for the next kernel to reduce
 constexpr int kUpdEpt = 4;
 
 // Gram-Schmidt, both passes of CGS2 in one sweep of memory:
@@ -2103,8 +2103,8 @@ static hipError_t row_matvec3_n(const Geom& g, const cplx* E, const cplx* G, con
     const size_t lb = with_finish_lds(g, (size_t)3 * r * Row<N>::LDS * sizeof(cplx), pin != nullptr);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(k_row_matvec3<N>), lb);
     if (e != hipSuccess) return e;
-    const int nb = (g.ny / 2) / r + (pin ? 1 : 0);  // + the block that finishes the step
-    launch(k_row_matvec3<N>, dim3(nb), block, lb, s, g, E, G, h, P, Q, st, pin, pin ? col2_blocks(g) : 0, jb);
+    launch(k_row_matvec3<N>, dim3((g.ny / 2) / r), block, lb, s, g, E, G, h, P, Q, st, pin, pin ? col2_blocks(g) : 0,
+           jb);
     return hipGetLastError();
   }
 }

@@ -91,7 +91,7 @@
 //   row_op: x part of the elliptic operator (mode 0), or of the residual with
 //     b = -div v (mode 1) or an explicit b (mode 2);
 //   row_matvec3: mode 0 of row_op with three concurrent transform chains;
-//     with pin (three-kernel step jb) one extra block finishes step jb - 1
+//     with pin (three-kernel step jb) every block first finishes step jb - 1
 //     from the block partials kernel A left in pin;
 //   row_flux / col_flux: fluxes, Bernoulli function and the RK4 combine;
 //   row_invariants / col_tail: invariant densities and the spectral tail;
