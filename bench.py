@@ -35,11 +35,12 @@ PARAMS = dict(a=0.5, eps=0.01, k=2)
 KRASNY = 1e-12
 
 # The roofline entry is for the kernel class with the largest share of device
-# time on this workload: the preconditioned y part of the operator that also
-# forms the new Krylov vector and its projections (kernel C of an Arnoldi
-# step, k_col_precond_new).  Its algorithmic bytes per launch, (j + 5) fields
-# at Arnoldi step j, are summed by the library over the launches that did work.
-DOMINANT = "col_precond_dot"
+# time on this workload: the x part of the elliptic operator in the Arnoldi
+# step (kernel B, k_row_matvec3: inverse x-transforms of E and G, the
+# pointwise products with 1/h, forward x-transforms into P and Q).  Its
+# algorithmic bytes per launch, 5 fields (E, G, h read; P, Q written), are
+# summed by the library over the launches that did work.
+DOMINANT = "row_matvec"
 
 
 def parse():
@@ -329,8 +330,8 @@ def main():
             "stage_increment_guess": alt,
         },
         "roofline": {
-                    "kernel": f"k_col_precond_new<{box.ny}> (Arnoldi kernel C: M^-1 and y part of the operator, "
-                      f"new basis vector, projections)",
+            "kernel": f"k_row_matvec3<{box.nx}> (Arnoldi kernel B: x part of the elliptic operator, "
+                      f"three transform chains per row pair)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
