@@ -216,6 +216,45 @@ int sgn_rk4_step_ensemble(int32_t n, sgn_ctx* const* ctxs, void* const* h, void*
  * synchronises.  *chosen (may be NULL): 0, 1 or 2 in the order above. */
 int sgn_autotune(sgn_ctx* ctx, int32_t* chosen);
 
+/* ---- Learned initial guess (a network of the project, not of the paper) ----
+ * The paper starts every GMRES solve from the previous sigma (Section 3).  The
+ * learned guess corrects that warm start: with r0 = b - L sigma_prev (eq. (3))
+ * the exact correction is L^-1 r0, and a network of SGN_CNN_LAYERS 3x3
+ * periodic convolutions (32 channels, ReLU between layers, BF16 weights and
+ * activations, FP32 accumulation on the matrix cores) predicts L^-1 r0 / |r0|
+ * from the three channels r0 / |r0|, M^-1 r0 / |r0| and h - h_inf (|r0| the
+ * RMS).  Fields here are FP32 device arrays; in3 is [H][W][3] (channels last),
+ * targets and outputs are [H][W].  H and W are powers of two, W >= 32.
+ * Parameters (host FP32, SGN_CNN_PARAMS values): per layer l the weights
+ * w[tap][cout][cin] (9 x 32 x 32, tap = 3 ky + kx reading the input at
+ * (y + ky - 1, x + kx - 1) modulo the grid), then the 32 biases; the unused
+ * input channels (3..31) of layer 0 and output channels (1..31) of the last
+ * layer are ignored and get zero gradient. */
+#define SGN_CNN_LAYERS 6
+#define SGN_CNN_PARAMS (SGN_CNN_LAYERS * (9 * 32 * 32 + 32))
+typedef struct sgn_cnn sgn_cnn;
+
+/* Workspace bytes for an H x W network context (weights, Adam moments,
+ * activations, gradient buffers); 0 if H, W are unsupported. */
+size_t sgn_cnn_workspace_bytes(int32_t H, int32_t W);
+/* Lay out the caller's 256-byte aligned device workspace; weights start at
+ * zero.  Work is ordered on hip_stream.  SGN_ERR_UNSUPPORTED for bad sizes. */
+int sgn_cnn_init(int32_t H, int32_t W, void* ws, size_t ws_bytes, void* hip_stream, sgn_cnn** out);
+int sgn_cnn_destroy(sgn_cnn* net);
+/* Copy SGN_CNN_PARAMS host floats in (and reset the Adam state) or out; both synchronise. */
+int sgn_cnn_set_params(sgn_cnn* net, const float* params);
+int sgn_cnn_get_params(sgn_cnn* net, float* params);
+/* out = network(in3), output channel 0 before rounding (stream-ordered). */
+int sgn_cnn_forward(sgn_cnn* net, const float* in3, float* out);
+/* Mean squared error of network(in3) against target and its gradients in all
+ * parameters (grads: host, SGN_CNN_PARAMS floats, may be NULL; loss may be
+ * NULL); synchronises when either is requested. */
+int sgn_cnn_gradients(sgn_cnn* net, const float* in3, const float* target, float* grads, double* loss);
+/* One training step: gradients as above, then Adam (Kingma & Ba, Algorithm 1;
+ * beta1 0.9, beta2 0.999, eps 1e-8, step size lr) on the FP32 master weights. */
+int sgn_cnn_train_step(sgn_cnn* net, const float* in3, const float* target, float lr, double* loss);
+const char* sgn_cnn_last_error(const sgn_cnn* net);
+
 /* Building blocks of the hot path, exposed for testing.
  * sgn_derivative: out = d f / dx (axis 0) or d f / dy (axis 1) (Section 3: i k).
  * sgn_apply_operator: out = L_h s (eq. (3)), or M^-1 L_h s if precondition != 0.

@@ -26,6 +26,7 @@ SOURCES = [
     ("sgn_kernels.hip", "sgn_kernels_fp64", ["-DSGN_PREC=64"]),
     ("sgn_kernels.hip", "sgn_kernels_fp32", ["-DSGN_PREC=32"]),
     ("sgn_dispatch.cpp", "sgn_dispatch", []),
+    ("sgn_cnn.hip", "sgn_cnn", []),
     ("sgn_api.cpp", "sgn_api", []),
 ]
 

@@ -31,6 +31,9 @@ SGN_KERNEL_COL_PRECOND_DOT = 2
 SGN_KERNEL_GS_UPDATE = 3
 SGN_KERNEL_ROW_FLUX = 4
 SGN_KERNEL_COL_FLUX = 5
+SGN_CNN_LAYERS = 6
+SGN_CNN_CH = 32
+SGN_CNN_PARAMS = SGN_CNN_LAYERS * (9 * SGN_CNN_CH * SGN_CNN_CH + SGN_CNN_CH)
 KERNEL_NAMES = {0: "row_matvec", 1: "col_basis", 2: "col_precond_dot", 3: "gs_update", 4: "row_flux",
                 5: "col_flux"}
 
@@ -100,6 +103,16 @@ _SIGNATURES = {
     "sgn_kernel_timing": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "sgn_kernel_time": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "sgn_cnn_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "sgn_cnn_init": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    "sgn_cnn_destroy": (ctypes.c_int, [_VP]),
+    "sgn_cnn_set_params": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float)]),
+    "sgn_cnn_get_params": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float)]),
+    "sgn_cnn_forward": (ctypes.c_int, [_VP, _VP, _VP]),
+    "sgn_cnn_gradients": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(ctypes.c_float),
+                                         ctypes.POINTER(ctypes.c_double)]),
+    "sgn_cnn_train_step": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_float, ctypes.POINTER(ctypes.c_double)]),
+    "sgn_cnn_last_error": (ctypes.c_char_p, [_VP]),
     "sgn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sgn_last_error": (ctypes.c_char_p, [_VP]),
 }
@@ -321,3 +334,111 @@ def sgn_kernel_time(ctx: Context, kind: int):
     _check(ctx, load_library().sgn_kernel_time(ctx.handle, int(kind), ctypes.byref(n), ctypes.byref(ms),
                                                ctypes.byref(b)))
     return int(n.value), float(ms.value), float(b.value)
+
+
+# ---- learned initial guess (network context) ------------------------------
+
+@dataclasses.dataclass
+class CnnContext:
+    handle: ctypes.c_void_p
+    H: int
+    W: int
+    workspace: object
+    device: object
+
+    def last_error(self) -> str:
+        msg = load_library().sgn_cnn_last_error(self.handle)
+        return msg.decode() if msg else ""
+
+    def close(self):
+        if self.handle:
+            load_library().sgn_cnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _cnn_check(net, status, allow=(SGN_OK,)):
+    if status in allow:
+        return status
+    msg = load_library().sgn_status_string(status).decode()
+    extra = net.last_error() if net is not None else ""
+    raise SgnError(status, f"{msg}: {extra}" if extra else msg)
+
+
+def cnn_workspace_bytes(H: int, W: int) -> int:
+    return int(load_library().sgn_cnn_workspace_bytes(H, W))
+
+
+def cnn_init(H: int, W: int, device="cuda:0", stream=None) -> CnnContext:
+    import torch
+    lib = load_library()
+    device = torch.device(device)
+    nbytes = cnn_workspace_bytes(H, W)
+    if nbytes == 0:
+        raise SgnError(SGN_ERR_UNSUPPORTED, f"unsupported network grid {H}x{W}")
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    handle = ctypes.c_void_p()
+    st = lib.sgn_cnn_init(H, W, ctypes.c_void_p(ws.data_ptr() + off), nbytes, ctypes.c_void_p(stream.cuda_stream),
+                          ctypes.byref(handle))
+    _cnn_check(None, st)
+    return CnnContext(handle=handle, H=H, W=W, workspace=ws, device=device)
+
+
+def _f32_array(a, n):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32).reshape(-1)
+    if a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def cnn_set_params(net: CnnContext, params):
+    a = _f32_array(params, SGN_CNN_PARAMS)
+    _cnn_check(net, load_library().sgn_cnn_set_params(net.handle, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+
+def cnn_get_params(net: CnnContext):
+    import numpy as np
+    a = np.empty(SGN_CNN_PARAMS, dtype=np.float32)
+    _cnn_check(net, load_library().sgn_cnn_get_params(net.handle, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return a
+
+
+def _cnn_field(net: CnnContext, t, shape, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+            and tuple(t.shape) == shape):
+        raise ValueError(f"{name}: expected a contiguous float32 CUDA tensor of shape {shape}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def cnn_forward(net: CnnContext, in3, out):
+    _cnn_check(net, load_library().sgn_cnn_forward(net.handle, _cnn_field(net, in3, (net.H, net.W, 3), "in3"),
+                                                   _cnn_field(net, out, (net.H, net.W), "out")))
+
+
+def cnn_gradients(net: CnnContext, in3, target):
+    """(gradients as a float32 array of SGN_CNN_PARAMS values, loss)."""
+    import numpy as np
+    g = np.empty(SGN_CNN_PARAMS, dtype=np.float32)
+    loss = ctypes.c_double()
+    _cnn_check(net, load_library().sgn_cnn_gradients(
+        net.handle, _cnn_field(net, in3, (net.H, net.W, 3), "in3"), _cnn_field(net, target, (net.H, net.W), "target"),
+        g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(loss)))
+    return g, loss.value
+
+
+def cnn_train_step(net: CnnContext, in3, target, lr: float) -> float:
+    loss = ctypes.c_double()
+    _cnn_check(net, load_library().sgn_cnn_train_step(
+        net.handle, _cnn_field(net, in3, (net.H, net.W, 3), "in3"), _cnn_field(net, target, (net.H, net.W), "target"),
+        float(lr), ctypes.byref(loss)))
+    return loss.value
