@@ -255,6 +255,21 @@ int sgn_cnn_gradients(sgn_cnn* net, const float* in3, const float* target, float
 int sgn_cnn_train_step(sgn_cnn* net, const float* in3, const float* target, float lr, double* loss);
 const char* sgn_cnn_last_error(const sgn_cnn* net);
 
+/* Attach a network to a solver context (its grid: H = cfg.ny, W = cfg.nx), or
+ * NULL to detach.  With a network, every solve of sgn_rk4_step starts from
+ * sigma_prev + |r0| net(r0 / |r0|, M^-1 r0 / |r0|, h - h_inf) instead of the
+ * warm start sigma_prev; GMRES then runs to the same tolerance (plain GMRES
+ * judges the guess).  record (device FP32, capacity slots of 4 H W floats, or
+ * NULL): every solve of sgn_rk4_step writes one training sample into slot
+ * (count mod capacity): the network input [H][W][3] of the warm start, then
+ * the target (sigma - sigma_prev) / |r0| [H][W] with sigma the converged
+ * solution.  Needs cfg.guess = SGN_GUESS_PREVIOUS (SGN_ERR_UNSUPPORTED
+ * otherwise); the captured step (sgn_rk4_step_graph) refuses contexts with a
+ * network or recorder attached.  Resets the recorded count. */
+int sgn_learned_guess_attach(sgn_ctx* ctx, sgn_cnn* net, float* record, int32_t capacity);
+/* Samples recorded since the last attach. */
+int sgn_learned_guess_recorded(sgn_ctx* ctx, int64_t* count);
+
 /* Building blocks of the hot path, exposed for testing.
  * sgn_derivative: out = d f / dx (axis 0) or d f / dy (axis 1) (Section 3: i k).
  * sgn_apply_operator: out = L_h s (eq. (3)), or M^-1 L_h s if precondition != 0.

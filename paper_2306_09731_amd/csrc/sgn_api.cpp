@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "sgn.h"
+#include "sgn_cnn_internal.hpp"
 #include "sgn_internal.hpp"
 #include "sgn_launch.hpp"
 
@@ -60,6 +61,11 @@ struct sgn_ctx {
     }
   } gkey[2];
   int graph_budget = 0;  // Arnoldi steps per captured solve (0: not yet calibrated)
+  // learned initial guess (sgn_learned_guess_attach)
+  sgn_cnn* learn_net = nullptr;  // network correcting the warm start, or null
+  float* learn_rec = nullptr;    // recorder: learn_cap slots of (input [n][3], target [n])
+  int32_t learn_cap = 0;
+  int64_t learn_count = 0;       // solves recorded
 };
 
 namespace {
@@ -435,6 +441,60 @@ int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void*
   return SGN_OK;
 }
 
+// ---- the learned initial guess
+
+// Start of a solve with the learned guess or the recorder: r0 = b - L sigma_prev
+// and M^-1 r0 from the GMRES start kernels, their scale |r0| (RMS, in the
+// device state), the network input (into the recorder's slot when recording)
+// and, with a network, sigma_prev replaced by sigma_prev + |r0| net(input).
+// Scratch: V_0, V_1, V_2 (physical r0, M^-1 r0, the guess; the solve
+// overwrites them afterwards), R1, R2 (x-half spectra) and the first
+// checkpoint field (sigma_prev, kept for the recorder's target).
+int learned_start(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, float** slot) {
+  const sgn::Geom& g = ctx->g;
+  hipStream_t s = ctx->stream;
+  const size_t n = (size_t)g.nx * g.ny;
+  char* V = static_cast<char*>(ctx->V);
+  void* r0 = V;
+  void* mr0 = V + ctx->field_bytes;
+  void* sg = V + 2 * ctx->field_bytes;
+  void* sp = ctx->ckpt;
+  HIPCK(sgn::launch_row_op(g, 1, ctx->E, ctx->G, h, vx, vy, ctx->P, ctx->Q, ctx->R1, ctx->R2, 1, 0, ctx->st, s));
+  HIPCK(sgn::launch_col_resid(g, ctx->P, ctx->Q, ctx->R1, ctx->R2, 1, 1, ctx->st, ctx->W, ctx->partials, s));
+  HIPCK(sgn::launch_col_learn(g, ctx->W, ctx->R1, ctx->R2, s));
+  HIPCK(sgn::launch_row_c2r(g, ctx->R1, r0, s));
+  HIPCK(sgn::launch_row_c2r(g, ctx->R2, mr0, s));
+  HIPCK(sgn::launch_row_c2r(g, ctx->E, sp, s));
+  HIPCK(sgn::launch_learn_norm(g, r0, n, ctx->st, ctx->partials, s));
+  float* in3;
+  if (ctx->learn_rec) {
+    *slot = ctx->learn_rec + (size_t)(ctx->learn_count % ctx->learn_cap) * 4 * n;
+    in3 = *slot;
+  } else {
+    in3 = sgn_cnn_in3_buffer(ctx->learn_net);
+  }
+  HIPCK(sgn::launch_learn_pack(g, r0, mr0, h, n, ctx->st, in3, s));
+  if (!ctx->learn_net) return SGN_OK;
+  float* out = sgn_cnn_out_buffer(ctx->learn_net);
+  if (sgn_cnn_forward_on(ctx->learn_net, in3, out, s) != SGN_OK) {
+    ctx->err = "learned guess: network forward pass failed";
+    return SGN_ERR_HIP;
+  }
+  HIPCK(sgn::launch_learn_apply(g, sp, out, ctx->st, sg, n, s));
+  return load_sigma(ctx, sg);
+}
+
+// After the solve: the recorder's target (sigma - sigma_prev) / |r0|.
+int learned_finish(sgn_ctx* ctx, float* slot) {
+  const sgn::Geom& g = ctx->g;
+  const size_t n = (size_t)g.nx * g.ny;
+  void* snew = ctx->ckpt + ctx->field_bytes;
+  HIPCK(sgn::launch_row_c2r(g, ctx->E, snew, ctx->stream));
+  HIPCK(sgn::launch_learn_target(g, snew, ctx->ckpt, ctx->st, slot + 3 * n, n, ctx->stream));
+  ctx->learn_count += 1;
+  return SGN_OK;
+}
+
 // ---- the captured RK4 step
 
 // One RK4 step for capture: each solve is a single GMRES cycle of `budget`
@@ -778,9 +838,12 @@ int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double 
       const void* ivy = stage == 0 ? vy : ctx->vys;
       void* Dst = ctx->D ? ctx->D + (size_t)stage * ctx->field_bytes : nullptr;
       if (Dst && step > 0) HIPCK(sgn::launch_col_guess_eg(g, ctx->SIG, Dst, ctx->E, ctx->G, s));
+      float* slot = nullptr;
+      if ((ctx->learn_net || ctx->learn_rec) && (rc = learned_start(ctx, ih, ivx, ivy, &slot))) return rc;
       SolveResult res;
       rc = run_solve(ctx, 1, ih, ivx, ivy, &res, stage, Dst);
       if (rc) return rc;
+      if (slot && (rc = learned_finish(ctx, slot))) return rc;
       total += res.iters;
       if (res.iters > maxper) maxper = res.iters;
       solves += 1;
@@ -814,6 +877,10 @@ int sgn_rk4_step_graph(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, d
       iter_budget > ctx->cfg.gmres_restart)
     return SGN_ERR_INVALID_ARG;
   if (nsteps == 0) return sgn_rk4_step(ctx, h, vx, vy, sigma, dt, 0, info);
+  if (ctx->learn_net || ctx->learn_rec) {
+    ctx->err = "the captured step does not run the learned guess";
+    return SGN_ERR_UNSUPPORTED;
+  }
   PrivateStream ps(ctx);
   if (!ps.ok) return fail(ctx, hipErrorInvalidValue, "private stream for the captured step");
   const sgn::Geom& g = ctx->g;
@@ -891,6 +958,34 @@ int sgn_rk4_step_graph(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, d
   if (replayed) *replayed = first < nsteps ? 1 : 0;
   if (ctx->hstat->stat_nonfinite) return SGN_ERR_NONFINITE;
   if (!(ctx->hstat->stat_minh > 0.0)) return SGN_ERR_CAVITATION;
+  return SGN_OK;
+}
+
+int sgn_learned_guess_attach(sgn_ctx* ctx, sgn_cnn* net, float* record, int32_t capacity) {
+  if (!ctx || capacity < 0 || (record && capacity == 0) || (reinterpret_cast<uintptr_t>(record) & 15) != 0)
+    return SGN_ERR_INVALID_ARG;
+  if (net) {
+    int H = 0, W = 0;
+    sgn_cnn_grid(net, &H, &W);
+    if (H != ctx->cfg.ny || W != ctx->cfg.nx) {
+      ctx->err = "network grid differs from the solver grid";
+      return SGN_ERR_INVALID_ARG;
+    }
+  }
+  if ((net || record) && ctx->cfg.guess != SGN_GUESS_PREVIOUS) {
+    ctx->err = "the learned guess replaces the warm start; it does not combine with the stage-increment guess";
+    return SGN_ERR_UNSUPPORTED;
+  }
+  ctx->learn_net = net;
+  ctx->learn_rec = record;
+  ctx->learn_cap = record ? capacity : 0;
+  ctx->learn_count = 0;
+  return SGN_OK;
+}
+
+int sgn_learned_guess_recorded(sgn_ctx* ctx, int64_t* count) {
+  if (!ctx || !count) return SGN_ERR_INVALID_ARG;
+  *count = ctx->learn_count;
   return SGN_OK;
 }
 

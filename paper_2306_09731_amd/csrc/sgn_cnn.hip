@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "sgn.h"
+#include "sgn_cnn_internal.hpp"
 
 namespace sgnn {
 
@@ -276,6 +277,8 @@ struct sgn_cnn {
   bf16* act[L + 1];       // act[0] = input, act[l + 1] = output of layer l
   bf16 *d0, *d1;          // gradients in the activations
   float* pred;            // FP32 output channel 0 [H][W]
+  float* in3;             // input staging for the solver's learned guess [H][W][3]
+  float* out;             // output staging for the solver's learned guess [H][W]
   float* part;            // weight-gradient partials [kWgBlocks][PL]
   double* lpart;          // loss partials
   double* hl;             // pinned host copy of the loss partials
@@ -289,7 +292,8 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct CnnLayout {
   size_t total;
-  size_t off_w, off_g, off_m, off_v, off_wf, off_wb, off_act, off_d0, off_d1, off_pred, off_part, off_lpart;
+  size_t off_w, off_g, off_m, off_v, off_wf, off_wb, off_act, off_d0, off_d1, off_pred, off_part, off_lpart, off_in3,
+      off_out;
 };
 
 bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
@@ -315,6 +319,8 @@ CnnLayout cnn_layout(int H, int W) {
   c.off_pred = take(n * 4);
   c.off_part = take((size_t)kWgBlocks * PL * 4);
   c.off_lpart = take(((n + 255) / 256) * 8);
+  c.off_in3 = take(n * 3 * 4);
+  c.off_out = take(n * 4);
   c.total = o;
   return c;
 }
@@ -422,6 +428,8 @@ int sgn_cnn_init(int32_t H, int32_t W, void* ws, size_t ws_bytes, void* hip_stre
   c->pred = reinterpret_cast<float*>(b + Lc.off_pred);
   c->part = reinterpret_cast<float*>(b + Lc.off_part);
   c->lpart = reinterpret_cast<double*>(b + Lc.off_lpart);
+  c->in3 = reinterpret_cast<float*>(b + Lc.off_in3);
+  c->out = reinterpret_cast<float*>(b + Lc.off_out);
   c->t = 0;
   if (hipHostMalloc(reinterpret_cast<void**>(&c->hl), ((c->n + 255) / 256) * 8, 0) != hipSuccess) {
     delete c;
@@ -504,3 +512,21 @@ int sgn_cnn_train_step(sgn_cnn* c, const float* in3, const float* target, float 
 const char* sgn_cnn_last_error(const sgn_cnn* c) { return c ? c->err.c_str() : ""; }
 
 }  // extern "C"
+
+// ---- for the solver's learned guess (sgn_cnn_internal.hpp) ----------------
+int sgn_cnn_grid(const sgn_cnn* c, int* H, int* W) {
+  *H = c->H;
+  *W = c->W;
+  return SGN_OK;
+}
+float* sgn_cnn_in3_buffer(sgn_cnn* c) { return c->in3; }
+float* sgn_cnn_out_buffer(sgn_cnn* c) { return c->out; }
+int sgn_cnn_forward_on(sgn_cnn* c, const float* in3, float* out, hipStream_t s) {
+  const hipStream_t own = c->stream;
+  c->stream = s;
+  int rc = forward_pass(c, in3);
+  if (!rc && hipMemcpyAsync(out, c->pred, (size_t)c->n * sizeof(float), hipMemcpyDeviceToDevice, s) != hipSuccess)
+    rc = SGN_ERR_HIP;
+  c->stream = own;
+  return rc;
+}

@@ -56,6 +56,7 @@ struct GmresState {
   double beta;          // norm of the newest (not yet normalised) Krylov vector
   int32_t cycle_base;   // Arnoldi steps of the solve before the current cycle
   int32_t pad2;
+  double learn_scale;   // learned guess: RMS of the warm start's residual r0
   double H[(kMaxRestart + 1) * kMaxRestart];  // H[i + j*(m_max+1)]
   double cs[kMaxRestart], sn[kMaxRestart];
   double gv[kMaxRestart + 1];  // g_j before rotation j (written when step j - 1 finishes)

@@ -1514,6 +1514,28 @@ __global__ void __launch_bounds__(512) k_col_inv(Geom g, const cplx* __restrict_
   store_col<N>(v, out, g.nh, col, t, valid);
 }
 
+// Learned guess: from W = M^-1 r0_hat (the 2D spectrum the GMRES start forms)
+// the x-half spectra of r0 (out_r = F_y^-1 (M W) / ny) and of M^-1 r0
+// (out_m = F_y^-1 W / ny), for the x-inverse transforms that follow.
+template <int N>
+__global__ void __launch_bounds__(512) k_col_learn(Geom g, const cplx* __restrict__ W, cplx* __restrict__ out_r,
+                                                    cplx* __restrict__ out_m) {
+  COL_SETUP(N)
+  cplx v[E], u[E];
+  load_spec<N>(v, W, col, t, valid);
+  const double kx = col * g.inv_Lx;
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    u[r] = cscale(v[r], g.inv_ny / inv_symbol(g, kx, wavenumber(t + r * TPF, N, g.inv_Ly)));
+    v[r] = cscale(v[r], g.inv_ny);
+  }
+  fft<N, true, decltype(map)>(v, buf, t, twy, map);
+  store_col<N>(v, out_m, g.nh, col, t, valid);
+  __syncthreads();
+  fft<N, true, decltype(map)>(u, buf, t, twy, map);
+  store_col<N>(u, out_r, g.nh, col, t, valid);
+}
+
 // Apply the 2D operator F(L s) (from P, Q) and optionally M^-1; out = 2D spectrum.
 template <int N>
 __global__ void __launch_bounds__(512) k_col_apply(Geom g, const cplx* __restrict__ P, const cplx* __restrict__ Q,
@@ -1762,6 +1784,57 @@ __global__ void __launch_bounds__(kUpdThreads) k_upd(Geom g, cplx* __restrict__ 
   block_partials_out(red, j + 2, partials, nullptr);  // finished by the next basis kernel
 }
 
+// Learned guess, pointwise passes (n points).
+// st->learn_scale = RMS of r0 (block partials, last block).
+__global__ void __launch_bounds__(256) k_learn_norm(const real* __restrict__ r0, size_t n, GmresState* st,
+                                                    double* partials, int nblocks) {
+  __shared__ double red[4];
+  __shared__ double outv[1];
+  double s = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)nblocks * 256) {
+    const double a = r0[i];
+    s += a * a;
+  }
+  wave_partial(s, red, 0);
+  block_partials_out(red, 1, partials, nullptr);
+  if (last_block_arrive(st->ctr, nblocks)) {
+    reduce_partials(partials, nblocks, 1, nullptr, outv);
+    if (threadIdx.x == 0) st->learn_scale = sqrt(outv[0] / (double)n);
+  }
+}
+
+// Network input [n][3] (FP32): r0 / s, M^-1 r0 / s, h - h_inf (0 for s = 0).
+__global__ void __launch_bounds__(256) k_learn_pack(const real* __restrict__ r0, const real* __restrict__ mr0,
+                                                    const real* __restrict__ h, size_t n, double h_inf,
+                                                    const GmresState* __restrict__ st, float* __restrict__ in3) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double s = st->learn_scale;
+  const double is = s > 0.0 ? 1.0 / s : 0.0;
+  in3[3 * i] = (float)(r0[i] * is);
+  in3[3 * i + 1] = (float)(mr0[i] * is);
+  in3[3 * i + 2] = (float)(h[i] - h_inf);
+}
+
+// sig_guess = sig_prev + s * out.
+__global__ void __launch_bounds__(256) k_learn_apply(const real* __restrict__ sig_prev, const float* __restrict__ out,
+                                                     const GmresState* __restrict__ st, real* __restrict__ sig_guess,
+                                                     size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  sig_guess[i] = (real)(sig_prev[i] + st->learn_scale * (double)out[i]);
+}
+
+// Training target (FP32): (sig_new - sig_prev) / s (0 for s = 0).
+__global__ void __launch_bounds__(256) k_learn_target(const real* __restrict__ sig_new, const real* __restrict__ sig_prev,
+                                                      const GmresState* __restrict__ st, float* __restrict__ target,
+                                                      size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double s = st->learn_scale;
+  target[i] = s > 0.0 ? (float)(((double)sig_new[i] - (double)sig_prev[i]) / s) : 0.f;
+}
+
 // min h and a non-finite flag over (h, vx, vy).
 __global__ void __launch_bounds__(256) k_field_stats(const real* __restrict__ h, const real* __restrict__ vx,
                                                      const real* __restrict__ vy, size_t n, GmresState* st,
@@ -1997,6 +2070,11 @@ static hipError_t col_resid_n(const Geom& g, const cplx* P, const cplx* Q, const
                               int flags, GmresState* st, cplx* W, double* partials, hipStream_t s) {
   const int nb = (int)ColLaunch<N>::grid(g.nh).x;
   COL_LAUNCH(k_col_resid<N>, g, P, Q, R1, R2, need_b, flags, st, W, partials, nb);
+}
+
+template <int N>
+static hipError_t col_learn_n(const Geom& g, const cplx* W, cplx* out_r, cplx* out_m, hipStream_t s) {
+  COL_LAUNCH(k_col_learn<N>, g, W, out_r, out_m);
 }
 
 template <int N>
@@ -2258,6 +2336,33 @@ hipError_t launch_col_precond_new(const Geom& g, const void* P, const void* Q, c
 hipError_t launch_col_resid(const Geom& g, const void* P, const void* Q, const void* R1, const void* R2, int need_b,
                             int flags, GmresState* st, void* W, double* partials, hipStream_t s) {
   DISPATCH_NY(col_resid_n, g, RC_(P), RC_(Q), RC_(R1), RC_(R2), need_b, flags, st, WC_(W), partials, s)
+}
+hipError_t launch_col_learn(const Geom& g, const void* W, void* out_r, void* out_m, hipStream_t s) {
+  DISPATCH_NY(col_learn_n, g, RC_(W), WC_(out_r), WC_(out_m), s)
+}
+hipError_t launch_learn_norm(const Geom&, const void* r0, size_t n, GmresState* st, double* partials,
+                             hipStream_t s) {
+  int nb = (int)((n + 255) / 256);
+  if (nb > 1024) nb = 1024;
+  launch(k_learn_norm, dim3(nb), dim3(256), 0, s, R_(r0), n, st, partials, nb);
+  return hipGetLastError();
+}
+hipError_t launch_learn_pack(const Geom& g, const void* r0, const void* mr0, const void* h, size_t n,
+                             const GmresState* st, float* in3, hipStream_t s) {
+  launch(k_learn_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, R_(r0), R_(mr0), R_(h), n, g.h_inf, st,
+         in3);
+  return hipGetLastError();
+}
+hipError_t launch_learn_apply(const Geom&, const void* sig_prev, const float* out, const GmresState* st,
+                              void* sig_guess, size_t n, hipStream_t s) {
+  launch(k_learn_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, R_(sig_prev), out, st, W_(sig_guess), n);
+  return hipGetLastError();
+}
+hipError_t launch_learn_target(const Geom&, const void* sig_new, const void* sig_prev, const GmresState* st,
+                               float* target, size_t n, hipStream_t s) {
+  launch(k_learn_target, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, R_(sig_new), R_(sig_prev), st, target,
+         n);
+  return hipGetLastError();
 }
 hipError_t launch_col_inv(const Geom& g, const void* S, void* o, hipStream_t s) {
   DISPATCH_NY(col_inv_n, g, RC_(S), WC_(o), s)

@@ -81,6 +81,21 @@
           const double* pin, int chained, hipStream_t s),                                                       \
     (g, W, V, vs, j, st, partials, pin, chained, s))                                                            \
   X(solve_stats, (const Geom& g, GmresState* st, hipStream_t s), (g, st, s))                                 \
+  X(col_learn, (const Geom& g, const void* W, void* out_r, void* out_m, hipStream_t s), (g, W, out_r, out_m, s))   \
+  X(learn_norm, (const Geom& g, const void* r0, size_t n, GmresState* st, double* partials, hipStream_t s),       \
+    (g, r0, n, st, partials, s))                                                                                \
+  X(learn_pack,                                                                                                 \
+    (const Geom& g, const void* r0, const void* mr0, const void* h, size_t n, const GmresState* st, float* in3, \
+     hipStream_t s),                                                                                            \
+    (g, r0, mr0, h, n, st, in3, s))                                                                             \
+  X(learn_apply,                                                                                                \
+    (const Geom& g, const void* sig_prev, const float* out, const GmresState* st, void* sig_guess, size_t n,    \
+     hipStream_t s),                                                                                            \
+    (g, sig_prev, out, st, sig_guess, n, s))                                                                    \
+  X(learn_target,                                                                                               \
+    (const Geom& g, const void* sig_new, const void* sig_prev, const GmresState* st, float* target, size_t n,   \
+     hipStream_t s),                                                                                            \
+    (g, sig_new, sig_prev, st, target, n, s))                                                                   \
   X(field_stats,                                                                                                \
     (const Geom& g, const void* h, const void* vx, const void* vy, size_t n, GmresState* st, double* partials,  \
      hipStream_t s),                                                                                            \
@@ -108,6 +123,9 @@
 //   col_guess_eg: sigma_hat += D; col_resid: start of a GMRES cycle;
 //   col_inv / col_apply / col_filter / col_dy: building blocks;
 //   solve_stats: adds the finished solve to the captured-step counters;
+//   col_learn / learn_norm / learn_pack / learn_apply / learn_target: the
+//     learned guess (r0 and M^-1 r0 from the GMRES start, their scale, the
+//     network input, the corrected sigma, the training target);
 //   field_stats: min h and a non-finite flag over the state.
 
 namespace sgn {

@@ -113,6 +113,8 @@ _SIGNATURES = {
                                          ctypes.POINTER(ctypes.c_double)]),
     "sgn_cnn_train_step": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_float, ctypes.POINTER(ctypes.c_double)]),
     "sgn_cnn_last_error": (ctypes.c_char_p, [_VP]),
+    "sgn_learned_guess_attach": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32]),
+    "sgn_learned_guess_recorded": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64)]),
     "sgn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sgn_last_error": (ctypes.c_char_p, [_VP]),
 }
@@ -442,3 +444,32 @@ def cnn_train_step(net: CnnContext, in3, target, lr: float) -> float:
         net.handle, _cnn_field(net, in3, (net.H, net.W, 3), "in3"), _cnn_field(net, target, (net.H, net.W), "target"),
         float(lr), ctypes.byref(loss)))
     return loss.value
+
+
+def learned_guess_attach(ctx: Context, net: CnnContext | None = None, record=None):
+    """Attach a network (or None) and a recorder: record is a float32 CUDA tensor
+    of shape (capacity, 4, H, W) (input channels as [H][W][3] then the target),
+    or None."""
+    import torch
+    cap, ptr = 0, None
+    if record is not None:
+        H, W = ctx.cfg.ny, ctx.cfg.nx
+        if not (isinstance(record, torch.Tensor) and record.is_cuda and record.dtype == torch.float32
+                and record.is_contiguous() and record.dim() == 4 and tuple(record.shape[1:]) == (4, H, W)):
+            raise ValueError(f"record: expected a contiguous float32 CUDA tensor of shape (capacity, 4, {H}, {W})")
+        cap, ptr = record.shape[0], ctypes.c_void_p(record.data_ptr())
+    _check(ctx, load_library().sgn_learned_guess_attach(ctx.handle, net.handle if net is not None else None, ptr, cap))
+    ctx.learned = (net, record)  # keep both alive while attached
+
+
+def learned_guess_recorded(ctx: Context) -> int:
+    n = ctypes.c_int64()
+    _check(ctx, load_library().sgn_learned_guess_recorded(ctx.handle, ctypes.byref(n)))
+    return n.value
+
+
+def record_sample(record, i: int):
+    """(input [H][W][3], target [H][W]) views of recorder slot i."""
+    H, W = record.shape[2], record.shape[3]
+    flat = record[i].reshape(-1)
+    return flat[:3 * H * W].view(H, W, 3), flat[3 * H * W:].view(H, W)
