@@ -148,6 +148,24 @@ def graph_form(sgn, torch, box, state, w, dev, args):
     return out
 
 
+def learned_form(sgn, torch, dev, args):
+    """The learned initial guess with the stored weights (trained by
+    python -m paper_2306_09731_amd.learned on solver-recorded samples) against
+    the paper's warm start, on the held-out oblique crossing solitons (1024^2,
+    tol 1e-8) and on this benchmark's workload: ms per RK4 step, GMRES
+    iterations per solve, and the network's mean squared error on recorded
+    samples beside the zero and M^-1 r0 predictors."""
+    import numpy as np
+    from paper_2306_09731_amd import learned
+    if not os.path.exists(learned.PARAMS_FILE):
+        return {"error": f"missing {os.path.relpath(learned.PARAMS_FILE, ROOT)}"}
+    params = np.load(learned.PARAMS_FILE)
+    steps = max(1, min(args.steps, 40))
+    return {"weights": os.path.relpath(learned.PARAMS_FILE, ROOT),
+            "runs": [learned.evaluate(params, dev, name, steps=steps)
+                     for name in ("crossing_solitons_1024x1024", WORKLOAD)]}
+
+
 PRECISION_WORKLOAD = "gaussian_2048x2048"
 
 
@@ -265,6 +283,11 @@ def cpu_baseline(steps: int):
                       f"(numpy FP64, single-threaded FFTs), {dt:.1f} s"}
 
 
+def progress(msg: str):
+    """One progress line per phase on stderr (the JSON result goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -288,7 +311,9 @@ def main():
         sgn.sgn_rk4_step(ctx, th, tvx, tvy, ts, w["dt"], args.warmup)
     # the same run with the stage-increment initial guess (same tolerance),
     # timed first so that the headline run below is the last thing measured
+    progress("warm-up done")
     alt = None if args.main_only else timed_guess_run(sgn, torch, box, (h, vx, vy, s), w, dev, args)
+    progress("stage-increment guess run done")
     dominant = DOMINANT
     kind = [k for k, v in sgn.KERNEL_NAMES.items() if v == dominant][0]
     sgn.sgn_kernel_timing(ctx, kind, True)
@@ -297,6 +322,7 @@ def main():
     info = sgn.sgn_rk4_step(ctx, th, tvx, tvy, ts, w["dt"], args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    progress(f"timed run done: {elapsed * 1e3 / args.steps:.3f} ms per step")
     launches, kms, algo_total = sgn.sgn_kernel_time(ctx, kind)  # events recorded at dispatch start/end
     sgn.sgn_kernel_timing(ctx, kind, False)
     npts = box.nx * box.ny
@@ -345,8 +371,13 @@ def main():
     }
     if not args.main_only:
         out["graph_form"] = graph_form(sgn, torch, box, (h, vx, vy, s), w, dev, args)
+        progress("graph form done")
+        out["learned_form"] = learned_form(sgn, torch, dev, args)
+        progress("learned form done")
         out["precision_form"] = precision_form(sgn, torch, dev, args)
+        progress("precision form done")
         out["batched_form"] = batched_form(sgn, torch, dev, args)
+        progress("batched form done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out), flush=True)

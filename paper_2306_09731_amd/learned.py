@@ -1,0 +1,211 @@
+"""Training recipe of the learned initial guess (argument marshalling only:
+recording, training and evaluation all run in the library's kernels).
+
+    python -m paper_2306_09731_amd.learned [--out DIR] [--epochs N]
+
+1. Record: RK4 trajectories of the solver at grid spacing dx = dy = 2 pi / 102.4
+   (the spacing of the benchmark workloads) with the recorder attached; every
+   solve writes the network input of its warm start and the target
+   (sigma - sigma_prev) / |r0|.  Sources: transversely perturbed line solitons
+   and Gaussian humps on 1024 x 512, oblique crossing solitons on 512 x 512
+   with amplitudes other than the evaluation's.
+2. Train: Adam over the recorded samples, one sample per step, in a seeded
+   order; the parameters start from He-normal weights (seeded).
+3. Evaluate on two held-out workloads: the oblique crossing solitons on
+   1024 x 1024 (a = 0.4, tol 1e-8) and the 1024 x 512 perturbed soliton
+   (a = 0.5, eps = 0.01, k = 2, tol 1e-10): network MSE on recorded samples
+   beside the zero and M^-1 r0 predictors, GMRES iterations per solve and
+   time per RK4 step with the warm start and with the learned guess.
+
+Writes DIR/learned_guess_params.npy (float32, SGN_CNN_PARAMS values) and
+DIR/learned_guess_summary.json.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+from . import sgn
+
+DT = 0.005
+PKG = os.path.dirname(os.path.abspath(__file__))
+PARAMS_FILE = os.path.join(PKG, "data", "learned_guess_params.npy")
+
+
+def he_params(seed: int = 0) -> np.ndarray:
+    """He-normal weights (std sqrt(2 / (9 fan_in)), fan_in = 3 for the first
+    layer, 32 otherwise), zero biases, in the library's padded layout."""
+    rng = np.random.default_rng(seed)
+    ch = sgn.SGN_CNN_CH
+    out = []
+    dims = [3] + [ch] * (sgn.SGN_CNN_LAYERS - 1) + [1]
+    for l in range(sgn.SGN_CNN_LAYERS):
+        cin, cout = dims[l], dims[l + 1]
+        w = np.zeros((9, ch, ch))
+        w[:, :cout, :cin] = rng.normal(0.0, np.sqrt(2.0 / (9 * cin)), size=(9, cout, cin))
+        out += [w.ravel(), np.zeros(ch)]
+    return np.concatenate(out).astype(np.float32)
+
+
+def _tensors(state, device):
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in state]
+
+
+def training_sources():
+    """(nx, ny, Lx, Ly, state) of the recorded trajectories."""
+    from sgn_inputs import Box, perturbed_line_soliton
+    from sgn_inputs.generators import oblique_crossing_solitons
+    out = []
+    box = Box(1024, 512, 10.0, 5.0)
+    for a, eps, k in ((0.2, 0.05, 1), (0.7, 0.02, 2), (1.0, 0.01, 4), (0.35, 0.05, 2)):
+        out.append((1024, 512, 10.0, 5.0, perturbed_line_soliton(box, a=a, eps=eps, k=k, x0=-10.0)))
+    X, Y = box.mesh()
+    for alpha in (0.3, 0.6):
+        h = 1.0 + alpha * np.exp(-X * X - Y * Y)
+        z = np.zeros_like(h)
+        out.append((1024, 512, 10.0, 5.0, (h, z.copy(), z.copy(), z.copy())))
+    sq = Box(512, 512, 5.0, 5.0)
+    for a in (0.2, 0.7):
+        out.append((512, 512, 5.0, 5.0, oblique_crossing_solitons(sq, a=a)))
+    return out
+
+
+def record(device, steps_per_source: int = 20, warmup_steps: int = 10, tol: float = 1e-10):
+    """Record 4 * steps_per_source samples from each source (one recorder
+    tensor per source)."""
+    import torch
+    recs = []
+    for nx, ny, Lx, Ly, state in training_sources():
+        cfg = sgn.config_default(nx, ny, Lx, Ly, gmres_tol=tol, krasny=1e-12)
+        ctx = sgn.sgn_init(cfg, device)
+        f = _tensors(state, device)
+        sgn.sgn_rk4_step(ctx, *f, DT, warmup_steps)
+        rec = torch.zeros(4 * steps_per_source, 4, ny, nx, dtype=torch.float32, device=device)
+        sgn.learned_guess_attach(ctx, None, rec)
+        sgn.sgn_rk4_step(ctx, *f, DT, steps_per_source)
+        sgn.learned_guess_attach(ctx, None)
+        torch.cuda.synchronize()
+        recs.append(rec)
+        ctx.close()
+    return recs
+
+
+TRAIN_H, TRAIN_W = 512, 1024
+
+
+def training_samples(recs):
+    """(input, target) pairs on the 512 x 1024 training grid: samples of 512 x
+    512 sources are repeated once along x (still periodic fields of the same
+    spacing, which a translation-equivariant network sees alike)."""
+    import torch
+    out = []
+    for rec in recs:
+        for i in range(rec.shape[0]):
+            x, t = sgn.record_sample(rec, i)
+            if x.shape[1] != TRAIN_W:
+                reps = TRAIN_W // x.shape[1]
+                x = torch.cat([x] * reps, dim=1)
+                t = torch.cat([t] * reps, dim=1)
+            out.append((x.contiguous(), t.contiguous()))
+    return out
+
+
+def train(samples, device, epochs: int = 12, seed: int = 0, params=None, log=None):
+    """Adam, one sample per step, in a seeded order; lr 1e-3, then 3e-4 for the
+    last third of the epochs."""
+    import torch
+    net = sgn.cnn_init(TRAIN_H, TRAIN_W, device)
+    sgn.cnn_set_params(net, he_params(seed) if params is None else params)
+    rng = np.random.default_rng(seed)
+    losses = []
+    for epoch in range(epochs):
+        lr = 1e-3 if epoch < (2 * epochs) // 3 else 3e-4
+        ep = [sgn.cnn_train_step(net, *samples[j], lr) for j in rng.permutation(len(samples))]
+        torch.cuda.synchronize()
+        losses.append(float(np.mean(ep)))
+        if log:
+            log(epoch=epoch, loss=losses[-1])
+    return sgn.cnn_get_params(net), losses
+
+
+def evaluate(params, device, name: str, steps: int = 40, warmup_steps: int = 10, record_n: int = 16):
+    """Warm start against the learned guess on a named workload."""
+    import torch
+    from sgn_inputs import workload
+    box, state, w = workload(name)
+    out = {"workload": name, "tol": w["tol"], "steps": steps}
+    for mode in ("warm_start", "learned"):
+        cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"], krasny=1e-12)
+        ctx = sgn.sgn_init(cfg, device)
+        f = _tensors(state, device)
+        sgn.sgn_rk4_step(ctx, *f, DT, warmup_steps)
+        net = None
+        if mode == "learned":
+            net = sgn.cnn_init(box.ny, box.nx, device)
+            sgn.cnn_set_params(net, params)
+            sgn.learned_guess_attach(ctx, net)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = sgn.sgn_rk4_step(ctx, *f, DT, steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[mode] = {"ms_per_step": el * 1e3 / steps, "iters_per_solve": info.total_iters / info.solves,
+                     "value": box.nx * box.ny * steps / el}
+        if mode == "warm_start":
+            # network error on samples of this workload beside the zero and M^-1 r0 predictors
+            rec = torch.zeros(record_n, 4, box.ny, box.nx, dtype=torch.float32, device=device)
+            sgn.learned_guess_attach(ctx, None, rec)
+            sgn.sgn_rk4_step(ctx, *f, DT, record_n // 4)
+            sgn.learned_guess_attach(ctx, None)
+            net = sgn.cnn_init(box.ny, box.nx, device)
+            sgn.cnn_set_params(net, params)
+            pred = torch.empty(box.ny, box.nx, dtype=torch.float32, device=device)
+            e_net, e_zero, e_mr = [], [], []
+            for i in range(record_n):
+                x, t = sgn.record_sample(rec, i)
+                sgn.cnn_forward(net, x.contiguous(), pred)
+                e_net.append(float(((pred - t) ** 2).mean()))
+                e_zero.append(float((t ** 2).mean()))
+                e_mr.append(float(((x[..., 1] - t) ** 2).mean()))
+            out["sample_mse"] = {"network": float(np.mean(e_net)), "zero": float(np.mean(e_zero)),
+                                 "minv_r0": float(np.mean(e_mr))}
+        ctx.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=os.path.dirname(PARAMS_FILE))
+    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--steps-per-source", type=int, default=20)
+    ap.add_argument("--device", default="cuda:0")
+    args = ap.parse_args()
+    t0 = time.time()
+
+    def log(**kw):
+        kw["t"] = round(time.time() - t0, 1)
+        print(json.dumps(kw), flush=True)
+
+    recs = record(args.device, args.steps_per_source)
+    samples = training_samples(recs)
+    del recs
+    log(recorded=len(samples))
+    params, losses = train(samples, args.device, args.epochs, log=log)
+    del samples
+    os.makedirs(args.out, exist_ok=True)
+    np.save(os.path.join(args.out, "learned_guess_params.npy"), params)
+    summary = {"losses": losses, "evaluation": []}
+    for name in ("crossing_solitons_1024x1024", "perturbed_soliton_1024x512"):
+        summary["evaluation"].append(evaluate(params, args.device, name))
+        log(**summary["evaluation"][-1])
+    with open(os.path.join(args.out, "learned_guess_summary.json"), "w") as fh:
+        json.dump(summary, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -293,6 +293,40 @@ def workload(name: str, a: float = 0.5, eps: float = 0.01, k: int = 2):
         st = perturbed_line_soliton(box, a=a, eps=eps, k=k, x0=-10.0)
     elif name == "gaussian_2048x2048":
         st = gaussian_hump(box, alpha=0.5)
+    elif name == "crossing_solitons_1024x1024":
+        st = oblique_crossing_solitons(box, a=0.4)
     else:  # pragma: no cover
         raise KeyError(name)
     return box, st, w
+
+
+def oblique_crossing_solitons(box: Box, a: float = 0.4, slope: float = 0.5, h_inf: float = 1.0, g: float = 1.0):
+    """Two line solitary waves of amplitude a crossing at +- theta, tan theta =
+    slope, on a square torus (Lx = Ly): wave +- travels along (cos theta,
+    +- sin theta).  With slope = 1/2 the phase xi = x cos theta +- y sin theta
+    is periodic on the box (period 2 pi Lx cos theta / 2), so each wave is
+    continued periodically; h = h_inf + sum of the two excesses and v = sum of
+    the two waves' v (the variable of the (h, v) system, eq. (soldef) profile)
+    times their directions, so each wave alone is the exact solitary wave of
+    its direction.  The superposition is initial data, not a solution."""
+    if abs(box.Lx - box.Ly) > 1e-12 or abs(slope - 0.5) > 1e-12:
+        raise ValueError("oblique_crossing_solitons: square box and slope 1/2 only")
+    p = soliton_params(a=a, h_inf=h_inf, g=g)
+    X, Y = box.mesh()
+    ct, st = 2.0 / math.sqrt(5.0), 1.0 / math.sqrt(5.0)
+    period = 2.0 * math.pi * box.Lx * st  # shifts by the box move xi by multiples of this
+    h = np.full_like(X, h_inf)
+    vx = np.zeros_like(X)
+    vy = np.zeros_like(X)
+    for sgn in (1.0, -1.0):
+        xi = X * ct + sgn * Y * st
+        xi = (xi + 0.5 * period) % period - 0.5 * period
+        prof = soliton_profile(xi, p)
+        h += prof["h"] - h_inf
+        vx += prof["v"] * ct
+        vy += sgn * prof["v"] * st
+    return h, vx, vy, np.zeros_like(h)
+
+
+WORKLOADS["crossing_solitons_1024x1024"] = dict(nx=1024, ny=1024, Lx=10.0, Ly=10.0, dt=0.005, steps=400,
+                                                 tol=1e-8, restart=20)

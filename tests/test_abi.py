@@ -136,3 +136,18 @@ def test_graph_step_host_checks():
         == sgn.SGN_ERR_INVALID_ARG
     assert rep.value == 0  # cleared even on an argument error
     assert lib.sgn_rk4_step_graph(None, None, None, None, None, 0.01, 1, 0, None, None) == sgn.SGN_ERR_INVALID_ARG
+
+
+def test_cnn_and_learned_guess_host_checks():
+    lib = sgn.load_library()
+    assert lib.sgn_cnn_workspace_bytes(64, 16) == 0          # W < 32
+    assert lib.sgn_cnn_workspace_bytes(48, 64) == 0          # not a power of two
+    assert lib.sgn_cnn_workspace_bytes(64, 64) > 0
+    h = ctypes.c_void_p()
+    assert lib.sgn_cnn_init(64, 64, None, 0, None, ctypes.byref(h)) == sgn.SGN_ERR_INVALID_ARG
+    assert lib.sgn_cnn_init(64, 16, None, 0, None, ctypes.byref(h)) == sgn.SGN_ERR_UNSUPPORTED
+    assert lib.sgn_cnn_destroy(None) == sgn.SGN_ERR_INVALID_ARG
+    assert lib.sgn_learned_guess_attach(None, None, None, 0) == sgn.SGN_ERR_INVALID_ARG
+    n = ctypes.c_int64()
+    assert lib.sgn_learned_guess_recorded(None, ctypes.byref(n)) == sgn.SGN_ERR_INVALID_ARG
+    assert sgn.SGN_CNN_PARAMS == 6 * (9 * 32 * 32 + 32)

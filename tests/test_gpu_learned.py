@@ -117,3 +117,31 @@ def test_attach_errors():
     sgn.learned_guess_attach(ctx, None)
     _, rep = sgn.sgn_rk4_step_graph(ctx, *f, 0.01, 2)
     assert rep
+
+
+def test_stored_weights_guess_a_small_soliton():
+    """The committed weights (trained at dx = dy = 2 pi / 102.4) on a 256 x 128
+    perturbed soliton of the same spacing: same states as the warm start to
+    the GMRES tolerance, and no more iterations."""
+    from paper_2306_09731_amd import learned
+    params = np.load(learned.PARAMS_FILE)
+    assert params.shape == (sgn.SGN_CNN_PARAMS,) and np.all(np.isfinite(params))
+    box = Box(256, 128, 2.5, 1.25)
+    h, vx, vy, s = perturbed_line_soliton(box, a=0.5, eps=0.02, k=1, x0=-2.5)
+    res = {}
+    for mode in ("warm", "learned"):
+        cfg = sgn.config_default(256, 128, 2.5, 1.25, gmres_tol=1e-10, krasny=1e-12)
+        ctx = sgn.sgn_init(cfg, DEV)
+        f = [torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in (h, vx, vy, s)]
+        sgn.sgn_rk4_step(ctx, *f, 0.005, 5)
+        if mode == "learned":
+            net = sgn.cnn_init(128, 256, DEV)
+            sgn.cnn_set_params(net, params)
+            sgn.learned_guess_attach(ctx, net)
+        info = sgn.sgn_rk4_step(ctx, *f, 0.005, 10)
+        torch.cuda.synchronize()
+        res[mode] = ([a.cpu().numpy() for a in f], info)
+    (fw, iw), (fl, il) = res["warm"], res["learned"]
+    e = max(np.abs(a - b).max() for a, b in zip(fw[:3], fl[:3]))
+    say(f"stored weights, 256x128: iterations {il.total_iters} vs warm start {iw.total_iters}, state difference {e:.1e}")
+    assert il.total_iters <= iw.total_iters and e < 1e-8
