@@ -47,11 +47,12 @@ __device__ __forceinline__ bf16 f2bf(float f) {
 }
 
 // ---------------------------------------------------------------------------
-// Convolution, forward and input gradient.  One wave: 32 consecutive points
-// of a row (A rows) x 32 output channels (B columns); K = 9 taps x 32 input
-// channels in 18 MFMA steps of 16.  Lane l supplies A[l % 32][8 (l / 32) + v]
-// and B[8 (l / 32) + v][l % 32], v < 8, and receives D[8 (v / 4) + 4 (l / 32)
-// + v % 4][l % 32], v < 16.
+// Convolution, forward and input gradient.  A wave computes kTilesPerWave
+// tiles of 32 consecutive points of a row (A rows) x 32 output channels (B
+// columns), holding the layer's weights (the B operands of all 18 MFMA steps)
+// in registers across its tiles; K = 9 taps x 32 input channels in 18 MFMA
+// steps of 16.  Lane l supplies A[l % 32][8 (l / 32) + v] and B[8 (l / 32) +
+// v][l % 32], v < 8, and receives D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32], v < 16.
 // ---------------------------------------------------------------------------
 struct ConvArgs {
   const bf16* x;      // [H][W][C]
@@ -63,37 +64,45 @@ struct ConvArgs {
   int H, W, relu;
 };
 
+constexpr int kTilesPerWave = 4;
+
 __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
   const int lane = threadIdx.x & 63;
-  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (tile * 32 >= a.H * a.W) return;
-  const int p0 = tile * 32;
-  const int y = p0 / a.W, x0 = p0 % a.W;  // W is a multiple of 32: one row per tile
+  const int ntiles = (a.H * a.W) / 32;
+  const int first = (blockIdx.x * 4 + (threadIdx.x >> 6)) * kTilesPerWave;
+  if (first >= ntiles) return;
   const int i = lane & 31, kh = lane >> 5;
-  f16v acc = {};
+  bf8 wv[TAPS][2];
 #pragma unroll
-  for (int tap = 0; tap < TAPS; ++tap) {
-    const int yy = (y + tap / 3 - 1) & (a.H - 1);
-    const int xx = (x0 + i + tap % 3 - 1) & (a.W - 1);
-    const bf16* xp = a.x + ((size_t)yy * a.W + xx) * C + 8 * kh;
-    const bf16* wp = a.w + (size_t)tap * C * C + (size_t)i * C + 8 * kh;
+  for (int tap = 0; tap < TAPS; ++tap)
 #pragma unroll
-    for (int c0 = 0; c0 < C; c0 += 16) {
-      const bf8 av = *reinterpret_cast<const bf8*>(xp + c0);
-      const bf8 bv = *reinterpret_cast<const bf8*>(wp + c0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
-    }
-  }
+    for (int h = 0; h < 2; ++h)
+      wv[tap][h] = *reinterpret_cast<const bf8*>(a.w + (size_t)tap * C * C + (size_t)i * C + 16 * h + 8 * kh);
   const int co = i;
   const float bb = a.bias ? a.bias[co] : 0.f;
+  for (int tile = first; tile < first + kTilesPerWave && tile < ntiles; ++tile) {
+    const int p0 = tile * 32;
+    const int y = p0 / a.W, x0 = p0 % a.W;  // W is a multiple of 32: one row per tile
+    f16v acc = {};
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const size_t p = (size_t)p0 + 8 * (v >> 2) + 4 * kh + (v & 3);
-    float o = acc[v] + bb;
-    if (a.relu) o = fmaxf(o, 0.f);
-    if (a.mask && !(bf2f(a.mask[p * C + co]) > 0.f)) o = 0.f;
-    if (a.y) a.y[p * C + co] = f2bf(o);
-    if (a.y0 && co == 0) a.y0[p] = o;
+    for (int tap = 0; tap < TAPS; ++tap) {
+      const int yy = (y + tap / 3 - 1) & (a.H - 1);
+      const int xx = (x0 + i + tap % 3 - 1) & (a.W - 1);
+      const bf16* xp = a.x + ((size_t)yy * a.W + xx) * C + 8 * kh;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf8*>(xp + 16 * h), wv[tap][h], acc,
+                                                      0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const size_t p = (size_t)p0 + 8 * (v >> 2) + 4 * kh + (v & 3);
+      float o = acc[v] + bb;
+      if (a.relu) o = fmaxf(o, 0.f);
+      if (a.mask && !(bf2f(a.mask[p * C + co]) > 0.f)) o = 0.f;
+      if (a.y) a.y[p * C + co] = f2bf(o);
+      if (a.y0 && co == 0) a.y0[p] = o;
+    }
   }
 }
 
@@ -182,13 +191,22 @@ __global__ void __launch_bounds__(256) k_wgrad(const bf16* __restrict__ dz, cons
   if (tid < C) out[WL + tid] = db;
 }
 
-// g[e] = sum over blocks b (in order) of part[b][e], e < PL.
+// g[e] = sum over blocks b (in order) of part[b][e], e < PL; loads issued
+// 16 blocks ahead, the additions kept in block order.
 __global__ void __launch_bounds__(kRedThreads) k_wgrad_reduce(const float* __restrict__ part, int nblocks,
                                                               float* __restrict__ g) {
   const int e = blockIdx.x * kRedThreads + threadIdx.x;
   if (e >= PL) return;
   float s = 0.f;
-  for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * PL + e];
+  int b = 0;
+  for (; b + 16 <= nblocks; b += 16) {
+    float x[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) x[u] = part[(size_t)(b + u) * PL + e];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += x[u];
+  }
+  for (; b < nblocks; ++b) s += part[(size_t)b * PL + e];
   g[e] = s;
 }
 
@@ -218,15 +236,16 @@ __global__ void __launch_bounds__(256) k_mse_grad(const float* __restrict__ pred
   if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// x[p][c] = in3[p][c] (c < 3), 0 for c >= 3.
+// x[p][c] = in3[p][c] (c < 3), 0 for c >= 3 (four 16-byte stores per point).
 __global__ void __launch_bounds__(256) k_pack3(const float* __restrict__ in3, bf16* __restrict__ x, int n) {
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= n) return;
-  bf16* xp = x + (size_t)p * C;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) xp[c] = f2bf(in3[(size_t)p * 3 + c]);
-#pragma unroll
-  for (int c = 3; c < C; ++c) xp[c] = 0;
+  uint4* xp = reinterpret_cast<uint4*>(x + (size_t)p * C);
+  const uint32_t c0 = f2bf(in3[(size_t)p * 3]), c1 = f2bf(in3[(size_t)p * 3 + 1]), c2 = f2bf(in3[(size_t)p * 3 + 2]);
+  xp[0] = make_uint4(c0 | (c1 << 16), c2, 0u, 0u);
+  xp[1] = make_uint4(0u, 0u, 0u, 0u);
+  xp[2] = make_uint4(0u, 0u, 0u, 0u);
+  xp[3] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // BF16 copies of the weights: wf[l][tap][co][ci] and, for the input gradient,
@@ -342,7 +361,8 @@ int conv(sgn_cnn* c, const bf16* x, const bf16* w, const float* bias, const bf16
          int relu) {
   ConvArgs a{x, w, bias, mask, y, y0, c->H, c->W, relu};
   const int tiles = c->n / 32;
-  hipLaunchKernelGGL(k_conv, dim3((tiles + 3) / 4), dim3(256), 0, c->stream, a);
+  const int per_block = 4 * kTilesPerWave;
+  hipLaunchKernelGGL(k_conv, dim3((tiles + per_block - 1) / per_block), dim3(256), 0, c->stream, a);
   CK(hipGetLastError());
   return SGN_OK;
 }

@@ -145,3 +145,32 @@ def test_stored_weights_guess_a_small_soliton():
     e = max(np.abs(a - b).max() for a, b in zip(fw[:3], fl[:3]))
     say(f"stored weights, 256x128: iterations {il.total_iters} vs warm start {iw.total_iters}, state difference {e:.1e}")
     assert il.total_iters <= iw.total_iters and e < 1e-8
+
+
+def test_recorder_in_fp32_mode():
+    """The recorder's kernels in the mixed-precision mode: the sample of the
+    first solve against the oracle on the FP32-rounded state, within the FP32
+    mode's gates (1e-5; the GMRES tolerance there is 1e-6)."""
+    nx, ny = 128, 64
+    box = Box(nx, ny, 10.0, 5.0)
+    h, vx, vy, s = (np.asarray(a, np.float32).astype(np.float64)
+                    for a in perturbed_line_soliton(box, a=0.5, eps=0.05, k=1, x0=-5.0 * np.pi))
+    cfg = sgn.config_default(nx, ny, box.Lx, box.Ly, gmres_tol=1e-6, precision=sgn.SGN_FP32_MIXED)
+    ctx = sgn.sgn_init(cfg, DEV)
+    f = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV) for a in (h, vx, vy, s)]
+    rec = torch.zeros(4, 4, ny, nx, dtype=torch.float32, device=DEV)
+    sgn.learned_guess_attach(ctx, None, rec)
+    sgn.sgn_rk4_step(ctx, *f, 0.01, 1)
+    torch.cuda.synchronize()
+    g = O.Grid(O.Config(nx=nx, ny=ny, Lx=box.Lx, Ly=box.Ly, gmres_tol=1e-13))
+    in3, target = (a.cpu().numpy().astype(np.float64) for a in sgn.record_sample(rec, 0))
+    b = -(O.d_x(g, vx) + O.d_y(g, vy))
+    r0 = b - O.apply_L(g, h, s)
+    scale = np.sqrt(np.mean(r0 ** 2))
+    ref_in = np.stack([r0 / scale, O.apply_Minv(g, r0) / scale, h - 1.0], axis=-1)
+    sig, _ = O.gmres(g, h, b, s, 1e-13, 20, 400)
+    ref_t = (sig - s) / scale
+    e_in = [np.abs(in3[..., c] - ref_in[..., c]).max() / np.abs(ref_in[..., c]).max() for c in range(3)]
+    e_t = np.abs(target - ref_t).max() / np.abs(ref_t).max()
+    say(f"fp32 recorder sample 0: input errors {[f'{e:.1e}' for e in e_in]}, target error {e_t:.1e}")
+    assert max(e_in) < 1e-5 and e_t < 1e-5
