@@ -152,6 +152,28 @@ int sgn_destroy(sgn_ctx* ctx);
  * SGN_ERR_NOT_CONVERGED (sigma = last iterate) if gmres_max_iters is hit. */
 int sgn_elliptic_solve(sgn_ctx* ctx, const void* h, const void* b, void* sigma, sgn_solve_info* info);
 
+typedef struct sgn_refine_info {
+  int32_t rounds;            /* FP32 correction solves performed */
+  int32_t inner_iters;       /* their GMRES iterations, summed */
+  double rel_resid_first;    /* ||b - L sigma|| / ||b|| of the starting sigma (FP64) */
+  double rel_resid_true;     /* the same for the returned sigma */
+} sgn_refine_info;
+
+/* Mixed-precision iterative refinement of the elliptic solve (the published
+ * method of Wilkinson and Moler applied to eq. (sigmav) with a given b):
+ * repeat r = b - L sigma (FP64, ctx64), stop when ||r|| <= tol ||b||,
+ * solve L d = r in the mixed-precision mode (ctx32: FP32 transforms and
+ * operator, FP64 reductions, its own tolerance of at least 1e-6, d from 0),
+ * sigma += d (FP64).  ctx64 (SGN_FP64) and ctx32 (SGN_FP32_MIXED) describe
+ * the same grid, box, g and h_inf on the current device.  h, b: FP64 device
+ * fields; sigma: FP64 device field, in = initial guess, out = refined
+ * solution.  Uses the checkpoint fields of ctx64's workspace as scratch;
+ * synchronises both contexts' streams.  Returns SGN_ERR_NOT_CONVERGED after
+ * max_rounds corrections without reaching tol (sigma = the last iterate),
+ * SGN_ERR_INVALID_ARG / SGN_ERR_UNSUPPORTED for mismatched contexts. */
+int sgn_elliptic_solve_refined(sgn_ctx* ctx64, sgn_ctx* ctx32, const double* h, const double* b, double* sigma,
+                               double tol, int32_t max_rounds, sgn_refine_info* info);
+
 /* One evaluation of the right-hand side of the (h, v) system (Section 3):
  *   b = -div v;  sigma = GMRES(L_h, b; x0 = sigma);
  *   dh = -div(h v - grad sigma);  dv = -grad B,

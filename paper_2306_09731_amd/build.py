@@ -27,6 +27,7 @@ SOURCES = [
     ("sgn_kernels.hip", "sgn_kernels_fp32", ["-DSGN_PREC=32"]),
     ("sgn_dispatch.cpp", "sgn_dispatch", []),
     ("sgn_cnn.hip", "sgn_cnn", []),
+    ("sgn_refine.hip", "sgn_refine", []),
     ("sgn_api.cpp", "sgn_api", []),
 ]
 

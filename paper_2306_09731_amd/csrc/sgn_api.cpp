@@ -784,6 +784,63 @@ int sgn_elliptic_solve(sgn_ctx* ctx, const void* h, const void* b, void* sigma, 
   return res.converged ? SGN_OK : SGN_ERR_NOT_CONVERGED;
 }
 
+int sgn_elliptic_solve_refined(sgn_ctx* c64, sgn_ctx* c32, const double* h, const double* b, double* sigma,
+                               double tol, int32_t max_rounds, sgn_refine_info* info) {
+  if (!c64 || !c32 || c64 == c32 || !aligned(h) || !aligned(b) || !aligned(sigma) || !(tol > 0.0) ||
+      !std::isfinite(tol) || max_rounds < 1)
+    return SGN_ERR_INVALID_ARG;
+  const sgn_config &a = c64->cfg, &q = c32->cfg;
+  if (a.precision != SGN_FP64 || q.precision != SGN_FP32_MIXED) return SGN_ERR_UNSUPPORTED;
+  if (a.nx != q.nx || a.ny != q.ny || a.Lx != q.Lx || a.Ly != q.Ly || a.g != q.g || a.h_inf != q.h_inf ||
+      c64->device != c32->device)
+    return SGN_ERR_INVALID_ARG;
+  sgn_ctx* ctx = c64;  // for HIPCK
+  const size_t n = (size_t)a.nx * a.ny;
+  const size_t fb = c64->field_bytes;  // >= 8 n bytes
+  double* r64 = reinterpret_cast<double*>(c64->ckpt);
+  float* h32 = reinterpret_cast<float*>(c64->ckpt + fb);
+  float* r32 = reinterpret_cast<float*>(c64->ckpt + 2 * fb);
+  float* d32 = reinterpret_cast<float*>(c64->ckpt + 3 * fb);
+  hipStream_t s = c64->stream;
+  int nb = (int)((n + 255) / 256);
+  if (nb > 1024) nb = 1024;
+  std::vector<double> hp(2 * (size_t)nb);
+  HIPCK(sgn::launch_to_f32(h, h32, n, s));
+  sgn_refine_info inf{};
+  int rc = SGN_OK;
+  for (int round = 0;; ++round) {
+    // r = b - L sigma in FP64, and its norm
+    if ((rc = sgn_apply_operator(c64, h, sigma, r64, 0))) return rc;
+    HIPCK(sgn::launch_refine_resid(b, r64, r32, n, c64->partials, nb, s));
+    HIPCK(hipMemcpyAsync(hp.data(), c64->partials, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    double rr = 0.0, bb = 0.0;
+    for (int i = 0; i < nb; ++i) {
+      rr += hp[2 * (size_t)i];
+      bb += hp[2 * (size_t)i + 1];
+    }
+    const double rel = bb > 0.0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+    if (round == 0) inf.rel_resid_first = rel;
+    inf.rel_resid_true = rel;
+    if (rel <= tol) break;
+    if (round == max_rounds) {
+      rc = SGN_ERR_NOT_CONVERGED;
+      break;
+    }
+    // L d = r in the mixed-precision mode, d from 0
+    HIPCK(hipMemsetAsync(d32, 0, n * sizeof(float), s));
+    HIPCK(hipStreamSynchronize(s));
+    sgn_solve_info si{};
+    const int rs = sgn_elliptic_solve(c32, h32, r32, d32, &si);
+    if (rs != SGN_OK && rs != SGN_ERR_NOT_CONVERGED) return rs;
+    inf.rounds += 1;
+    inf.inner_iters += si.iters;
+    HIPCK(sgn::launch_refine_update(sigma, d32, n, s));
+  }
+  if (info) *info = inf;
+  return rc;
+}
+
 int sgn_rhs(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, void* sigma, void* dh, void* dvx,
             void* dvy, sgn_solve_info* info) {
   if (!ctx || !aligned(h) || !aligned(vx) || !aligned(vy) || !aligned(sigma) || !aligned(dh) || !aligned(dvx) ||

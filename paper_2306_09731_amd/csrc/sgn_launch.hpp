@@ -133,6 +133,15 @@ namespace sgn {
 #define SGN_DECLARE_LAUNCHER(name, params, args) hipError_t launch_##name params;
 SGN_LAUNCHERS(SGN_DECLARE_LAUNCHER)
 
+// Iterative refinement passes (sgn_refine.hip; FP64 residuals, FP32
+// corrections): out = (float) in; r = b - r with r32 = (float) r and per-block
+// partials (sum r^2, sum b^2) in partials[2 block], nblocks <= 1024;
+// sigma += (double) d.
+hipError_t launch_to_f32(const double* in, float* out, size_t n, hipStream_t s);
+hipError_t launch_refine_resid(const double* b, double* r, float* r32, size_t n, double* partials, int nblocks,
+                               hipStream_t s);
+hipError_t launch_refine_update(double* sigma, const float* d, size_t n, hipStream_t s);
+
 // Largest number of blocks any reduction kernel launches for this grid.
 int max_partial_blocks(const Geom& g);
 // Whether this grid can use the chain-parallel Arnoldi passes.

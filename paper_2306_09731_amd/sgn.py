@@ -60,6 +60,11 @@ class sgn_solve_info(ctypes.Structure):
     ]
 
 
+class sgn_refine_info(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("inner_iters", ctypes.c_int32),
+                ("rel_resid_first", ctypes.c_double), ("rel_resid_true", ctypes.c_double)]
+
+
 class sgn_step_info(ctypes.Structure):
     _fields_ = [
         ("total_iters", ctypes.c_int64), ("max_iters_per_solve", ctypes.c_int32),
@@ -85,6 +90,8 @@ _SIGNATURES = {
     "sgn_destroy": (ctypes.c_int, [_VP]),
     "sgn_elliptic_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(sgn_solve_info)]),
     "sgn_rhs": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(sgn_solve_info)]),
+    "sgn_elliptic_solve_refined": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
+                                                  ctypes.POINTER(sgn_refine_info)]),
     "sgn_rk4_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
                                     ctypes.POINTER(sgn_step_info)]),
     "sgn_rk4_step_graph": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
@@ -249,6 +256,17 @@ def sgn_rhs(ctx: Context, h, vx, vy, sigma, dh, dvx, dvy) -> sgn_solve_info:
                                 _field(ctx, sigma, "sigma"), _field(ctx, dh, "dh"), _field(ctx, dvx, "dvx"),
                                 _field(ctx, dvy, "dvy"), ctypes.byref(info))
     _check(ctx, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
+    return info
+
+
+def sgn_elliptic_solve_refined(ctx64: Context, ctx32: Context, h, b, sigma, tol: float,
+                               max_rounds: int = 8) -> sgn_refine_info:
+    """FP64 solution by FP32 corrections (FP64 fields h, b, sigma of ctx64's grid)."""
+    info = sgn_refine_info()
+    st = load_library().sgn_elliptic_solve_refined(ctx64.handle, ctx32.handle, _field(ctx64, h, "h"),
+                                                   _field(ctx64, b, "b"), _field(ctx64, sigma, "sigma"), float(tol),
+                                                   int(max_rounds), ctypes.byref(info))
+    _check(ctx64, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
     return info
 
 
