@@ -251,8 +251,37 @@ __device__ __forceinline__ void block_partials_out(const double* red, int nvals,
 // GMRES scalar work (one thread of a block, from LDS copies)
 // ----------------------------------------------------------------------------
 
+// The state that finishing Arnoldi step j reads, loaded into registers at
+// the start of a kernel so that these loads wait together with those of the
+// block partials instead of after them: thread i < j holds rotation i,
+// thread i <= j (with_cj) the projection coefficient i, thread 0 the scalars.
+struct FinishPre {
+  double cs, sn, cj;
+  double gvj, tol, beta0;
+  int cycle_base, m, maxit;
+};
+
+__device__ __forceinline__ FinishPre finish_prefetch(const GmresState* st, int j, bool with_cj) {
+  FinishPre p{};
+  const int tid = flat_tid();
+  if (tid < j) {
+    p.cs = st->cs[tid];
+    p.sn = st->sn[tid];
+  }
+  if (with_cj && tid <= j) p.cj = st->cproj[tid];
+  if (tid == 0 && j >= 0) {
+    p.gvj = st->gv[j];
+    p.tol = st->tol;
+    p.beta0 = st->st.beta0;
+    p.cycle_base = st->cycle_base;
+    p.m = st->m;
+    p.maxit = st->maxit;
+  }
+  return p;
+}
+
 __device__ int gmres_finish_column(GmresState* st, int j, const double* cj, double beta, const double* s2,
-                                   bool write);
+                                   bool write, const FinishPre* pre = nullptr);
 
 // Finish CGS2 Arnoldi step j in a block of the kernel that follows the
 // update kernel, from its nb block partials (value 0: ||w1||^2; 1 + i:
@@ -296,16 +325,17 @@ __device__ int cgs2_finish(const Geom& g, GmresState* st, int j, const double* p
 // unchanged (rotations below j, g_j before rotation, the cycle's iteration
 // base), so each takes the writer's decision.
 __device__ int gmres_finish_column(GmresState* st, int j, const double* cj, double beta, const double* s2,
-                                   bool write) {
+                                   bool write, const FinishPre* pre) {
   __shared__ double sh_col[kMaxRestart + 1];
   __shared__ double sh_cs[kMaxRestart], sh_sn[kMaxRestart];
   __shared__ double sh_gj, sh_gn, sh_resid;
   __shared__ int sh_stop, sh_total;
   const int tid = flat_tid(), nt = block_threads();
   const int ld = kMaxRestart + 1;
-  for (int i = tid; i < j; i += nt) {
-    sh_cs[i] = st->cs[i];
-    sh_sn[i] = st->sn[i];
+  const FinishPre p = pre ? *pre : finish_prefetch(st, j, false);
+  if (tid < j) {
+    sh_cs[tid] = p.cs;
+    sh_sn[tid] = p.sn;
   }
   for (int i = tid; i <= j; i += nt) sh_col[i] = cj[i];
   __syncthreads();
@@ -328,17 +358,17 @@ __device__ int gmres_finish_column(GmresState* st, int j, const double* cj, doub
     col[j + 1] = 0.0;
     sh_cs[j] = c;
     sh_sn[j] = sn;
-    const double gj = st->gv[j];
+    const double gj = p.gvj;
     sh_gj = c * gj;
     sh_gn = -sn * gj;
     const double resid = fabs(sh_gn);
-    const int total = st->cycle_base + j + 1;
+    const int total = p.cycle_base + j + 1;
     int done = 0;
-    if (resid <= st->tol * st->st.beta0 || beta == 0.0)
+    if (resid <= p.tol * p.beta0 || beta == 0.0)
       done = 1;
-    else if (j + 1 >= st->m)
+    else if (j + 1 >= p.m)
       done = 2;
-    else if (total >= st->maxit)
+    else if (total >= p.maxit)
       done = 3;
     sh_resid = resid;
     sh_total = total;
@@ -622,15 +652,16 @@ __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __rest
     // whether to stop; block 0 stores the step
     __shared__ double nrm[1];
     __shared__ double cj[kMaxRestart + 1];
+    const FinishPre pre = finish_prefetch(st, jb - 1, true);
     reduce_partials1(pin, nbin, nrm);
     const double beta = sqrt(nrm[0] * g.inv_n);
     const bool writer = blockIdx.x == 0;
     if (jb == 0) {
       if (writer && flat_tid() == 0) st->beta = beta;
     } else {
-      for (int i = flat_tid(); i < jb; i += block_threads()) cj[i] = st->cproj[i];
+      if (flat_tid() < jb) cj[flat_tid()] = pre.cj;
       __syncthreads();
-      if (gmres_finish_column(st, jb - 1, cj, beta, nullptr, writer)) return;
+      if (gmres_finish_column(st, jb - 1, cj, beta, nullptr, writer, &pre)) return;
     }
   }
   TwiddleSet<N> twx;
@@ -1150,14 +1181,33 @@ __device__ void cgs_coefficients(const Geom& g, GmresState* st, int jc, const do
                                  double* coef, bool write) {
   const int tid = flat_tid(), nthr = block_threads();
   constexpr int ld = kMaxRestart + 1;
+  // G_ik, i, k < jc, from earlier steps: for jc <= kPreG staged in LDS,
+  // loaded before the partials so that both loads wait together
+  constexpr int kPreG = 20;
+  __shared__ double sG[kPreG * kPreG];
+  const bool pre = jc <= kPreG;
+  const int ng = pre ? jc * jc : 0;
+  double gq[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + u * nthr;
+    gq[u] = e < ng ? st->G[(e / jc) * ld + e % jc] : 0.0;
+  }
   reduce_partials<false>(pin, nb, 2 * (jc + 1), nullptr, outv);
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + u * nthr;
+    if (e < ng) sG[e] = gq[u];
+  }
+  for (int e = tid + 2 * nthr; e < ng; e += nthr) sG[e] = st->G[(e / jc) * ld + e % jc];
   for (int i = tid; i < 2 * (jc + 1); i += nthr) outv[i] *= g.inv_n;
   __syncthreads();
   // c_i = 2 s_i - sum_k G_ik s_k; G_ik, k < jc, from earlier steps, and
   // G_{i,jc} = <V_i, V_jc> from this reduction
   for (int i = tid; i <= jc; i += nthr) {
     double acc = 0.0;
-    for (int k = 0; k < jc; ++k) acc += (i == jc ? outv[2 * k + 1] : st->G[i * ld + k]) * outv[2 * k];
+    for (int k = 0; k < jc; ++k)
+      acc += (i == jc ? outv[2 * k + 1] : (pre ? sG[i * jc + k] : st->G[i * ld + k])) * outv[2 * k];
     acc += outv[2 * i + 1] * outv[2 * jc];
     coef[i] = 2.0 * outv[2 * i] - acc;
   }
