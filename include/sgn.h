@@ -229,14 +229,26 @@ int sgn_invariants(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, 
 int sgn_rk4_step_ensemble(int32_t n, sgn_ctx* const* ctxs, void* const* h, void* const* vx, void* const* vy,
                           void* const* sigma, const double* dt, int32_t nsteps, sgn_step_info* infos);
 
-/* Autotuner of the Arnoldi kernel schedule: times a few GMRES solves of a
- * synthetic smooth problem with each schedule this grid supports (four
- * kernels with one transform chain per block; four kernels with two chains;
- * the three-kernel step), keeps the fastest for the context and caches the
- * choice per (nx, ny, precision, restart, device) for the process.  Uses the
- * context's RK4 stage buffers (their contents are overwritten) and its stream;
- * synchronises.  *chosen (may be NULL): 0, 1 or 2 in the order above. */
+/* Autotuner of the launch schedule: times a few GMRES solves of a synthetic
+ * smooth problem with each Arnoldi schedule this grid supports (four kernels
+ * with one transform chain per block; four kernels with two chains; the
+ * three-kernel step), then, for the fastest, the column tile widths (the
+ * widest tiles that keep 128, 256, 512 or 1024 blocks) and rows per row block
+ * (64, 128 or 256 threads) that give a launch shape not yet timed; keeps the
+ * fastest for the context and caches the choice per (nx, ny, precision,
+ * restart, device) for the process.  All choices compute the same
+ * quantities (reductions may sum in another order).  Uses the context's RK4
+ * stage buffers (their contents are overwritten) and its stream;
+ * synchronises.  *chosen (may be NULL): the schedule, 0, 1 or 2 in the order
+ * above. */
 int sgn_autotune(sgn_ctx* ctx, int32_t* chosen);
+
+/* The context's launch choices: out[0] the Arnoldi schedule (as above),
+ * out[1] the column-tile block target, out[2] the row-block thread target,
+ * out[3], out[4] row pairs per block of the single-chain and three-chain row
+ * kernels, out[5], out[6] columns per tile of the single-chain and two-chain
+ * column kernels (0: no such kernel at this size).  out: 7 host int32. */
+int sgn_launch_shape(const sgn_ctx* ctx, int32_t* out);
 
 /* ---- Learned initial guess (a network of the project, not of the paper) ----
  * The paper starts every GMRES solve from the previous sigma (Section 3).  The

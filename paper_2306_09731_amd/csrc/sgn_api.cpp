@@ -2,6 +2,8 @@
 // loop and the RK4 / RHS / invariants sequences of kernel launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -56,8 +58,10 @@ struct sgn_ctx {
     const void *h = nullptr, *vx = nullptr, *vy = nullptr;
     double dt = 0.0;
     int budget = 0;
+    int arnoldi = 0, tile_blocks = 0, row_threads = 0;  // the launch shapes captured
     bool operator==(const GraphKey& o) const {
-      return h == o.h && vx == o.vx && vy == o.vy && dt == o.dt && budget == o.budget;
+      return h == o.h && vx == o.vx && vy == o.vy && dt == o.dt && budget == o.budget && arnoldi == o.arnoldi &&
+             tile_blocks == o.tile_blocks && row_threads == o.row_threads;
     }
   } gkey[2];
   int graph_budget = 0;  // Arnoldi steps per captured solve (0: not yet calibrated)
@@ -531,6 +535,9 @@ int graph_for(sgn_ctx* ctx, int kind, void* h, void* vx, void* vy, double dt, in
   key.vy = vy;
   key.dt = dt;
   key.budget = budget;
+  key.arnoldi = ctx->arnoldi;
+  key.tile_blocks = ctx->g.tile_blocks;
+  key.row_threads = ctx->g.row_threads;
   if (ctx->gexec[kind] && ctx->gkey[kind] == key) return SGN_OK;
   if (ctx->gexec[kind]) {
     HIPCK(hipGraphExecDestroy(ctx->gexec[kind]));
@@ -661,6 +668,20 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   g.dA = (2.0 * M_PI * cfg->Lx / nx) * (2.0 * M_PI * cfg->Ly / ny);
   g.fp32 = cfg->precision == SGN_FP32_MIXED;
   g.m = cfg->gmres_restart;
+  // launch shapes (tuning and testing switches; sgn_autotune searches them):
+  // SGN_TILE_BLOCKS, the number of blocks below which column tiles stop
+  // widening, and SGN_ROW_THREADS, the threads a row block reaches by taking
+  // several row pairs (powers of two)
+  g.tile_blocks = 256;
+  g.row_threads = 64;
+  if (const char* tb = std::getenv("SGN_TILE_BLOCKS")) {
+    const int v = std::atoi(tb);
+    if (v >= 1 && v <= 4096 && (v & (v - 1)) == 0) g.tile_blocks = v;
+  }
+  if (const char* rt = std::getenv("SGN_ROW_THREADS")) {
+    const int v = std::atoi(rt);
+    if (v >= 64 && v <= 512 && (v & (v - 1)) == 0) g.row_threads = v;
+  }
   if (!sgn::chained_ok(g)) ctx->arnoldi = 0;
   char* base = ctx->ws;
   cplx* tw = reinterpret_cast<cplx*>(base + L.tw);
@@ -1153,7 +1174,10 @@ int sgn_rk4_step_ensemble(int32_t n, sgn_ctx* const* ctxs, void* const* h, void*
 
 namespace {
 std::mutex g_tune_mutex;
-std::map<std::tuple<int, int, int, int, int>, int> g_tune_cache;  // (nx, ny, precision, restart, device) -> variant
+struct TuneChoice {
+  int arnoldi, tile_blocks, row_threads;
+};
+std::map<std::tuple<int, int, int, int, int>, TuneChoice> g_tune_cache;  // (nx, ny, precision, restart, device)
 }  // namespace
 
 int sgn_autotune(sgn_ctx* ctx, int32_t* chosen) {
@@ -1164,12 +1188,14 @@ int sgn_autotune(sgn_ctx* ctx, int32_t* chosen) {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      ctx->arnoldi = it->second;
-      if (chosen) *chosen = it->second;
+      ctx->arnoldi = it->second.arnoldi;
+      ctx->g.tile_blocks = it->second.tile_blocks;
+      ctx->g.row_threads = it->second.row_threads;
+      if (chosen) *chosen = it->second.arnoldi;
       return SGN_OK;
     }
   }
-  const sgn::Geom& g = ctx->g;
+  sgn::Geom& g = ctx->g;
   hipStream_t s = ctx->stream;
   // synthetic smooth problem in the workspace's RK4 stage buffers: depth
   // h = 1 + 0.3 sin(x) cos(2y), right-hand side b = cos(3x + y), zero guess
@@ -1192,20 +1218,16 @@ int sgn_autotune(sgn_ctx* ctx, int32_t* chosen) {
   HIPCK(upload(ctx->vxs, bb));
   HIPCK(hipMemsetAsync(ctx->vys, 0, ctx->field_bytes, s));
   HIPCK(hipStreamSynchronize(s));
-  std::vector<int> cand = {0};
-  if (sgn::chained_ok(g)) {
-    cand.push_back(1);
-    cand.push_back(2);
-  }
   hipEvent_t e0, e1;
   HIPCK(hipEventCreate(&e0));
   HIPCK(hipEventCreate(&e1));
-  const int saved = ctx->arnoldi;
-  int best = saved;
-  float best_ms = 1e30f;
+  const TuneChoice saved{ctx->arnoldi, g.tile_blocks, g.row_threads};
   int rc = SGN_OK;
-  for (int v : cand) {
-    ctx->arnoldi = v;
+  // time one candidate: three solves from zero after a warm-up solve
+  auto time_it = [&](const TuneChoice& t, float* out) {
+    ctx->arnoldi = t.arnoldi;
+    g.tile_blocks = t.tile_blocks;
+    g.row_threads = t.row_threads;
     float total = 0.0f;
     for (int rep = 0; rep < 4 && rc == SGN_OK; ++rep) {  // rep 0 warms up
       rc = load_sigma(ctx, ctx->vys);
@@ -1219,21 +1241,77 @@ int sgn_autotune(sgn_ctx* ctx, int32_t* chosen) {
       if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = SGN_ERR_HIP;
       if (rep > 0) total += ms;
     }
+    *out = total;
+  };
+  // 1. the Arnoldi schedules at the default launch shapes
+  std::vector<int> sched = {0};
+  if (sgn::chained_ok(g)) {
+    sched.push_back(1);
+    sched.push_back(2);
+  }
+  TuneChoice best = saved;
+  float best_ms = 1e30f;
+  for (int v : sched) {
     if (rc) break;
-    if (total < best_ms) {
-      best_ms = total;
-      best = v;
+    const TuneChoice t{v, saved.tile_blocks, saved.row_threads};
+    float ms;
+    time_it(t, &ms);
+    if (!rc && ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  }
+  // 2. for that schedule, the column tile widths and rows per row block that
+  // give launch shapes not yet timed
+  std::vector<std::array<int, 4>> seen;
+  auto shape_of = [&](const TuneChoice& t) {
+    sgn::Geom q = g;
+    q.tile_blocks = t.tile_blocks;
+    q.row_threads = t.row_threads;
+    std::array<int, 4> a{};
+    sgn::launch_shape(q, a.data());
+    return a;
+  };
+  seen.push_back(shape_of(best));
+  const TuneChoice base = best;
+  for (int tb : {128, 256, 512, 1024}) {
+    for (int rt : {64, 128, 256}) {
+      if (rc) break;
+      const TuneChoice t{base.arnoldi, tb, rt};
+      const auto a = shape_of(t);
+      if (std::find(seen.begin(), seen.end(), a) != seen.end()) continue;
+      seen.push_back(a);
+      float ms;
+      time_it(t, &ms);
+      if (!rc && ms < best_ms) {
+        best_ms = ms;
+        best = t;
+      }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  ctx->arnoldi = rc ? saved : best;
+  const TuneChoice use = rc ? saved : best;
+  ctx->arnoldi = use.arnoldi;
+  g.tile_blocks = use.tile_blocks;
+  g.row_threads = use.row_threads;
   if (rc) return rc;
   {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     g_tune_cache[key] = best;
   }
-  if (chosen) *chosen = best;
+  if (chosen) *chosen = best.arnoldi;
+  return SGN_OK;
+}
+
+int sgn_launch_shape(const sgn_ctx* ctx, int32_t* out) {
+  if (!ctx || !out) return SGN_ERR_INVALID_ARG;
+  int a[4];
+  sgn::launch_shape(ctx->g, a);
+  out[0] = ctx->arnoldi;
+  out[1] = ctx->g.tile_blocks;
+  out[2] = ctx->g.row_threads;
+  for (int i = 0; i < 4; ++i) out[3 + i] = a[i];
   return SGN_OK;
 }
 

@@ -18,5 +18,6 @@ SGN_LAUNCHERS(SGN_DEFINE_DISPATCH)
 
 int max_partial_blocks(const Geom& g) { return g.fp32 ? p32::max_partial_blocks(g) : p64::max_partial_blocks(g); }
 bool chained_ok(const Geom& g) { return g.fp32 ? p32::chained_ok(g) : p64::chained_ok(g); }
+void launch_shape(const Geom& g, int* out4) { g.fp32 ? p32::launch_shape(g, out4) : p64::launch_shape(g, out4); }
 
 }  // namespace sgn

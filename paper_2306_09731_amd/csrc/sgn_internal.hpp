@@ -24,6 +24,8 @@ struct Geom {
   const float2* twy32;
   int fp32;                // 1: fields, spectra and transforms in FP32; reductions stay FP64
   int m;                   // GMRES restart length (sizes the back-substitution scratch)
+  int tile_blocks;         // column passes: the widest tiles that still give this many blocks (256)
+  int row_threads;         // row passes: row pairs per block for at least this many threads (64)
 };
 
 // GMRES state kept in device memory.  Written only by the single "last

@@ -1947,32 +1947,36 @@ static void launch(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, A
 
 template <int N>
 struct RowLaunch {
-  static dim3 block(int ny) {
-    int rpb = 64 / Row<N>::TPF;
+  // row pairs per block: enough for g.row_threads threads (at least one
+  // wave), at most 512 threads and no more than there are row pairs
+  static dim3 block(const Geom& g) {
+    int rpb = g.row_threads / Row<N>::TPF;
     if (rpb < 1) rpb = 1;
-    while (rpb > 1 && rpb > ny / 2) rpb >>= 1;
+    while (rpb > 1 && (rpb > g.ny / 2 || rpb * Row<N>::TPF > 512)) rpb >>= 1;
     return dim3(Row<N>::TPF, rpb);
   }
-  static size_t lds(int ny) { return (size_t)block(ny).y * Row<N>::LDS * sizeof(cplx); }
-  static dim3 grid(int ny) { return dim3((ny / 2) / block(ny).y); }
+  static size_t lds(const Geom& g) { return (size_t)block(g).y * Row<N>::LDS * sizeof(cplx); }
+  static dim3 grid(const Geom& g) { return dim3((g.ny / 2) / block(g).y); }
 };
 
 // Column tiles: tc complex columns per block (a runtime choice).  At least
 // one full wave per block, at most 512 threads and 64 KB of LDS (128 KB for
-// the longest columns), and as wide as keeps >= 256 blocks in flight.
+// the longest columns), and as wide as keeps >= g.tile_blocks blocks in
+// flight.
 template <int N>
 struct ColLaunch {
-  static int tc(int nh) {
+  static int tc(const Geom& g) {
     constexpr int TPF = Col<N>::TPF;
     const size_t ldsmax = N >= 2048 ? 131072 : 65536;
     int t = 1;
     while (t * TPF < 64) t *= 2;
-    while (t * 2 * TPF <= 512 && (size_t)t * 2 * N * sizeof(cplx) <= ldsmax && nh / (t * 2) >= 256) t *= 2;
+    while (t * 2 * TPF <= 512 && (size_t)t * 2 * N * sizeof(cplx) <= ldsmax && g.nh / (t * 2) >= g.tile_blocks)
+      t *= 2;
     return t;
   }
-  static dim3 block(int nh) { return dim3(tc(nh), Col<N>::TPF); }
-  static size_t lds(int nh) { return (size_t)tc(nh) * N * sizeof(cplx); }
-  static dim3 grid(int nh) { return dim3((nh + tc(nh) - 1) / tc(nh)); }
+  static dim3 block(const Geom& g) { return dim3(tc(g), Col<N>::TPF); }
+  static size_t lds(const Geom& g) { return (size_t)tc(g) * N * sizeof(cplx); }
+  static dim3 grid(const Geom& g) { return dim3((g.nh + tc(g) - 1) / tc(g)); }
 };
 
 // Dynamic LDS of a kernel that may finish an Arnoldi step (finish): at least
@@ -1989,19 +1993,19 @@ static hipError_t allow_lds(const void* fn, size_t bytes) {
 
 #define ROW_LAUNCH(KERNEL, ...)                                                             \
   do {                                                                                      \
-    const size_t lb = RowLaunch<N>::lds(g.ny);                                              \
+    const size_t lb = RowLaunch<N>::lds(g);                                              \
     hipError_t e_ = allow_lds(reinterpret_cast<const void*>(KERNEL), lb);                   \
     if (e_ != hipSuccess) return e_;                                                        \
-    launch(KERNEL, RowLaunch<N>::grid(g.ny), RowLaunch<N>::block(g.ny), lb, s, __VA_ARGS__); \
+    launch(KERNEL, RowLaunch<N>::grid(g), RowLaunch<N>::block(g), lb, s, __VA_ARGS__); \
     return hipGetLastError();                                                               \
   } while (0)
 
 #define COL_LAUNCH(KERNEL, ...)                                                             \
   do {                                                                                      \
-    const size_t lb = ColLaunch<N>::lds(g.nh);                                              \
+    const size_t lb = ColLaunch<N>::lds(g);                                              \
     hipError_t e_ = allow_lds(reinterpret_cast<const void*>(KERNEL), lb);                   \
     if (e_ != hipSuccess) return e_;                                                        \
-    launch(KERNEL, ColLaunch<N>::grid(g.nh), ColLaunch<N>::block(g.nh), lb, s, __VA_ARGS__); \
+    launch(KERNEL, ColLaunch<N>::grid(g), ColLaunch<N>::block(g), lb, s, __VA_ARGS__); \
     return hipGetLastError();                                                               \
   } while (0)
 
@@ -2090,10 +2094,10 @@ int upd_blocks(const Geom& g);
 template <int N>
 static hipError_t col_basis_eg_n(const Geom& g, const cplx* W, cplx* V, size_t vs, int j, GmresState* st, cplx* Eo,
                                  cplx* Go, const double* pin, hipStream_t s) {
-  const size_t lb = with_finish_lds(g, ColLaunch<N>::lds(g.nh), j > 0);
+  const size_t lb = with_finish_lds(g, ColLaunch<N>::lds(g), j > 0);
   hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_basis_eg<N>), lb);
   if (e != hipSuccess) return e;
-  launch(k_col_basis_eg<N>, ColLaunch<N>::grid(g.nh), ColLaunch<N>::block(g.nh), lb, s, g, W, V, vs, j, st, Eo, Go,
+  launch(k_col_basis_eg<N>, ColLaunch<N>::grid(g), ColLaunch<N>::block(g), lb, s, g, W, V, vs, j, st, Eo, Go,
          pin, upd_blocks(g));
   return hipGetLastError();
 }
@@ -2118,7 +2122,7 @@ static hipError_t col_precond_dot_n(const Geom& g, const cplx* P, const cplx* Q,
 template <int N>
 static hipError_t col_resid_n(const Geom& g, const cplx* P, const cplx* Q, const cplx* R1, const cplx* R2, int need_b,
                               int flags, GmresState* st, cplx* W, double* partials, hipStream_t s) {
-  const int nb = (int)ColLaunch<N>::grid(g.nh).x;
+  const int nb = (int)ColLaunch<N>::grid(g).x;
   COL_LAUNCH(k_col_resid<N>, g, P, Q, R1, R2, need_b, flags, st, W, partials, nb);
 }
 
@@ -2144,7 +2148,7 @@ static hipError_t col_filter_n(const Geom& g, const cplx* Sx, int op, double thr
 
 template <int N>
 static hipError_t col_tail_n(const Geom& g, const cplx* Sx, GmresState* st, double* partials, hipStream_t s) {
-  const int nb = (int)ColLaunch<N>::grid(g.nh).x;
+  const int nb = (int)ColLaunch<N>::grid(g).x;
   COL_LAUNCH(k_col_tail<N>, g, Sx, st, partials, nb);
 }
 
@@ -2163,32 +2167,37 @@ static hipError_t col_flux_n(const Geom& g, const real* dhp, const real* qy, con
 template <int N>
 struct Chain {
   static constexpr bool row_ok = 3 * Row<N>::TPF <= 1024;
-  static int rpb(int ny) {
-    int r = 64 / Row<N>::TPF;
+  // row pairs per block of the three-chain row kernel: g.row_threads threads
+  // per chain when the rows are short, <= 1024 threads in all
+  static int rpb(const Geom& g) {
+    int r = g.row_threads / Row<N>::TPF;
     if (r < 1) r = 1;
-    while (r > 1 && (r > ny / 2 || 3 * r * Row<N>::TPF > 1024)) r >>= 1;
+    while (r > 1 && (r > g.ny / 2 || 3 * r * Row<N>::TPF > 1024)) r >>= 1;
     return r;
   }
   // column tile for two chains: at least one wave per chain, <= 1024 threads,
   // dynamic LDS <= kChainLds (the kernels add up to ~50 KB of static LDS, the
   // Hessenberg staging of the GMRES finish among it, within 160 KB per block),
-  // >= 256 blocks when possible
+  // >= g.tile_blocks blocks when possible
   static constexpr size_t kChainLds = 98304;
-  static int tc(int nh) {
+  static int tc(const Geom& g) {
     constexpr int TPF = Col<N>::TPF;
     int t = 1;
     while (t * TPF < 64) t *= 2;
-    while (2 * (t * 2) * TPF <= 1024 && (size_t)2 * (t * 2) * N * sizeof(cplx) <= kChainLds && nh / (t * 2) >= 256)
+    while (2 * (t * 2) * TPF <= 1024 && (size_t)2 * (t * 2) * N * sizeof(cplx) <= kChainLds &&
+           g.nh / (t * 2) >= g.tile_blocks)
       t *= 2;
     return t;
   }
-  static bool col_ok(int nh) { return 2 * tc(nh) * Col<N>::TPF <= 1024 && (size_t)2 * tc(nh) * N * sizeof(cplx) <= kChainLds; }
+  static bool col_ok(const Geom& g) {
+    return 2 * tc(g) * Col<N>::TPF <= 1024 && (size_t)2 * tc(g) * N * sizeof(cplx) <= kChainLds;
+  }
 };
 
 // Blocks of the single-chain column kernels for this grid.
 template <int N>
 static int col1_blocks_n(const Geom& g) {
-  return (int)ColLaunch<N>::grid(g.nh).x;
+  return (int)ColLaunch<N>::grid(g).x;
 }
 static int col1_blocks(const Geom& g) {
   switch (g.ny) {
@@ -2205,7 +2214,7 @@ static int col1_blocks(const Geom& g) {
 // Blocks of the chain-parallel column kernels for this grid.
 template <int N>
 static int col2_blocks_n(const Geom& g) {
-  const int tc = Chain<N>::tc(g.nh);
+  const int tc = Chain<N>::tc(g);
   return (g.nh + tc - 1) / tc;
 }
 static int col2_blocks(const Geom& g) {
@@ -2226,7 +2235,7 @@ static hipError_t row_matvec3_n(const Geom& g, const cplx* E, const cplx* G, con
   if constexpr (!Chain<N>::row_ok) {
     return hipErrorNotSupported;
   } else {
-    const int r = Chain<N>::rpb(g.ny);
+    const int r = Chain<N>::rpb(g);
     const dim3 block(Row<N>::TPF, 3 * r);
     const size_t lb = with_finish_lds(g, (size_t)3 * r * Row<N>::LDS * sizeof(cplx), pin != nullptr);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(k_row_matvec3<N>), lb);
@@ -2238,7 +2247,45 @@ static hipError_t row_matvec3_n(const Geom& g, const cplx* E, const cplx* G, con
 }
 
 template <int N>
-static bool col2_ok_n(const Geom& g) { return Chain<N>::col_ok(g.nh); }
+static int row_rpb_n(const Geom& g) { return (int)RowLaunch<N>::block(g).y; }
+template <int N>
+static int chain_rpb_n(const Geom& g) {
+  if constexpr (Chain<N>::row_ok) return Chain<N>::rpb(g);
+  return 0;
+}
+template <int N>
+static int col_tc_n(const Geom& g) { return ColLaunch<N>::tc(g); }
+template <int N>
+static int chain_tc_n(const Geom& g) { return Chain<N>::tc(g); }
+
+void launch_shape(const Geom& g, int* out) {
+  out[0] = out[1] = out[2] = out[3] = 0;
+  switch (g.nx) {
+#define X(n)                      \
+  case n:                         \
+    out[0] = row_rpb_n<n>(g);     \
+    out[1] = chain_rpb_n<n>(g);   \
+    break;
+    SGN_SIZES(X)
+#undef X
+    default:
+      break;
+  }
+  switch (g.ny) {
+#define X(n)                      \
+  case n:                         \
+    out[2] = col_tc_n<n>(g);      \
+    out[3] = chain_tc_n<n>(g);    \
+    break;
+    SGN_SIZES(X)
+#undef X
+    default:
+      break;
+  }
+}
+
+template <int N>
+static bool col2_ok_n(const Geom& g) { return Chain<N>::col_ok(g); }
 template <int N>
 static bool row3_ok_n(const Geom&) { return Chain<N>::row_ok; }
 bool chained_ok(const Geom& g) {
@@ -2261,7 +2308,7 @@ bool chained_ok(const Geom& g) {
 template <int N>
 static hipError_t col_basis2_n(const Geom& g, const cplx* W, cplx* V, size_t vs, int j, GmresState* st, cplx* Eo,
                                cplx* Go, const double* pin, hipStream_t s) {
-  const int tc = Chain<N>::tc(g.nh);
+  const int tc = Chain<N>::tc(g);
   const dim3 block(tc, Col<N>::TPF, 2);
   const size_t lb = with_finish_lds(g, (size_t)2 * tc * N * sizeof(cplx), j > 0);
   hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_basis2<N>), lb);
@@ -2273,7 +2320,7 @@ static hipError_t col_basis2_n(const Geom& g, const cplx* W, cplx* V, size_t vs,
 template <int N>
 static hipError_t col_precond_dot2_n(const Geom& g, const cplx* P, const cplx* Q, const cplx* V, size_t vs, int j,
                                      GmresState* st, cplx* W, double* partials, hipStream_t s) {
-  const int tc = Chain<N>::tc(g.nh);
+  const int tc = Chain<N>::tc(g);
   const dim3 block(tc, Col<N>::TPF, 2);
   const int nb = (g.nh + tc - 1) / tc;
   const size_t lb = (size_t)2 * tc * N * sizeof(cplx);
@@ -2286,7 +2333,7 @@ static hipError_t col_precond_dot2_n(const Geom& g, const cplx* P, const cplx* Q
 template <int N>
 static hipError_t col_proj_n(const Geom& g, const cplx* win, cplx* W, const cplx* V, size_t vs, int j, GmresState* st,
                              cplx* Eo, cplx* Go, double* partials, const double* pin, hipStream_t s) {
-  const int tc = Chain<N>::tc(g.nh);
+  const int tc = Chain<N>::tc(g);
   const dim3 block(tc, Col<N>::TPF, 2);
   const int nb = (g.nh + tc - 1) / tc;
   const size_t lb = (size_t)2 * tc * N * sizeof(cplx);
@@ -2299,7 +2346,7 @@ static hipError_t col_proj_n(const Geom& g, const cplx* win, cplx* W, const cplx
 template <int N>
 static hipError_t col_precond_new_n(const Geom& g, const cplx* P, const cplx* Q, const cplx* W, cplx* V, cplx* Z,
                                     size_t vs, int j, GmresState* st, double* partials, hipStream_t s) {
-  const int tc = Chain<N>::tc(g.nh);
+  const int tc = Chain<N>::tc(g);
   const dim3 block(tc, Col<N>::TPF, 2);
   const int nb = (g.nh + tc - 1) / tc;
   const size_t lb = (size_t)2 * tc * N * sizeof(cplx);

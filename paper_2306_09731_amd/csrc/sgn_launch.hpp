@@ -146,6 +146,10 @@ hipError_t launch_refine_update(double* sigma, const float* d, size_t n, hipStre
 int max_partial_blocks(const Geom& g);
 // Whether this grid can use the chain-parallel Arnoldi passes.
 bool chained_ok(const Geom& g);
+// Launch shape of the grid's passes: row pairs per block of the single-chain
+// and three-chain row kernels, columns per tile of the single-chain and
+// two-chain column kernels (0: no such kernel for this size).
+void launch_shape(const Geom& g, int* out4);
 // The next kernel launch records these events at its start and end (null: none).
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 // Events for the next launch (consumed by it); shared by both precisions.
@@ -155,11 +159,13 @@ namespace p64 {
 SGN_LAUNCHERS(SGN_DECLARE_LAUNCHER)
 int max_partial_blocks(const Geom& g);
 bool chained_ok(const Geom& g);
+void launch_shape(const Geom& g, int* out4);
 }  // namespace p64
 namespace p32 {
 SGN_LAUNCHERS(SGN_DECLARE_LAUNCHER)
 int max_partial_blocks(const Geom& g);
 bool chained_ok(const Geom& g);
+void launch_shape(const Geom& g, int* out4);
 }  // namespace p32
 
 }  // namespace sgn

@@ -90,6 +90,7 @@ _SIGNATURES = {
     "sgn_destroy": (ctypes.c_int, [_VP]),
     "sgn_elliptic_solve": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.POINTER(sgn_solve_info)]),
     "sgn_rhs": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(sgn_solve_info)]),
+    "sgn_launch_shape": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32)]),
     "sgn_elliptic_solve_refined": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
                                                   ctypes.POINTER(sgn_refine_info)]),
     "sgn_rk4_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
@@ -257,6 +258,15 @@ def sgn_rhs(ctx: Context, h, vx, vy, sigma, dh, dvx, dvy) -> sgn_solve_info:
                                 _field(ctx, dvy, "dvy"), ctypes.byref(info))
     _check(ctx, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
     return info
+
+
+def sgn_launch_shape(ctx: Context) -> dict:
+    """The context's Arnoldi schedule, tile targets and resulting block shapes."""
+    out = (ctypes.c_int32 * 7)()
+    _check(ctx, load_library().sgn_launch_shape(ctx.handle, out))
+    keys = ("arnoldi", "tile_blocks", "row_threads", "row_pairs_per_block", "row_pairs_per_block3",
+            "cols_per_tile", "cols_per_tile2")
+    return dict(zip(keys, list(out)))
 
 
 def sgn_elliptic_solve_refined(ctx64: Context, ctx32: Context, h, b, sigma, tol: float,

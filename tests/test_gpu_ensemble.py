@@ -64,6 +64,13 @@ def test_autotune_choice_and_result(nx, ny, prec):
     again = sgn.sgn_autotune(ctx)
     say(f"autotune {nx}x{ny} prec {prec}: {sgn.ARNOLDI_SCHEDULES[choice]}")
     assert choice in (0, 1, 2) and again == choice
+    shape = sgn.sgn_launch_shape(ctx)
+    say(f"  launch shape {shape}")
+    assert shape["arnoldi"] == choice and shape["tile_blocks"] in (128, 256, 512, 1024)
+    assert shape["row_threads"] in (64, 128, 256)
+    # a second context of the same grid takes the cached choice without timing
+    ctx2 = sgn.sgn_init(cfg, DEV)
+    assert sgn.sgn_autotune(ctx2) == choice and sgn.sgn_launch_shape(ctx2) == shape
     rng = np.random.default_rng(nx + ny)
     h = 1.0 + 0.3 * random_smooth_field(rng, ny, nx, kmax=5)
     b = random_smooth_field(rng, ny, nx, kmax=5)
@@ -76,3 +83,49 @@ def test_autotune_choice_and_result(nx, ny, prec):
     err = np.abs(sig.double().cpu().numpy() - ref).max() / np.abs(ref).max()
     say(f"  solve after autotune: iters {info.iters}, sigma rel err {err:.1e}")
     assert info.converged and err < (1e-10 if prec == sgn.SGN_FP64 else 1e-5)
+
+
+@pytest.mark.parametrize("nx,ny,prec", [(256, 256, sgn.SGN_FP64), (1024, 512, sgn.SGN_FP64),
+                                        (128, 64, sgn.SGN_FP64), (512, 512, sgn.SGN_FP32_MIXED)])
+def test_launch_shapes_give_the_same_solution(nx, ny, prec, monkeypatch):
+    """Every column tile width and rows-per-block choice the autotuner can
+    make, under every schedule: the same iterations and sigma within rounding
+    of the default shape (the reductions sum in another order), and the
+    oracle's solution within the GMRES tolerance."""
+    rng = np.random.default_rng(3 * nx + ny)
+    h = 1.0 + 0.3 * random_smooth_field(rng, ny, nx, kmax=5)
+    b = random_smooth_field(rng, ny, nx, kmax=5)
+    g = O.Grid(O.Config(nx=nx, ny=ny, Lx=2.0, Ly=1.0))
+    ref, _ = O.gmres(g, h, b, np.zeros_like(b), 1e-13, 20, 400)
+    dt = torch.float32 if prec == sgn.SGN_FP32_MIXED else torch.float64
+    tol = 1e-12 if prec == sgn.SGN_FP64 else 1e-6
+    base = None
+    seen = set()
+    for sched in ("serial", "chained", "fused"):
+        for tb in (256, 128, 512, 1024):
+            for rt in (64, 128, 256):
+                monkeypatch.setenv("SGN_ARNOLDI_KERNELS", sched)
+                monkeypatch.setenv("SGN_TILE_BLOCKS", str(tb))
+                monkeypatch.setenv("SGN_ROW_THREADS", str(rt))
+                ctx = sgn.sgn_init(sgn.config_default(nx, ny, 2.0, 1.0, gmres_tol=tol, precision=prec), DEV)
+                shape = sgn.sgn_launch_shape(ctx)
+                key = tuple(v for k, v in shape.items() if k not in ("tile_blocks", "row_threads"))
+                if key in seen:
+                    continue
+                seen.add(key)
+                sig = torch.zeros(ny, nx, dtype=dt, device=DEV)
+                info = sgn.sgn_elliptic_solve(ctx, torch.from_numpy(h).to(DEV).to(dt),
+                                              torch.from_numpy(b).to(DEV).to(dt), sig)
+                torch.cuda.synchronize()
+                s = sig.double().cpu().numpy()
+                err = np.abs(s - ref).max() / np.abs(ref).max()
+                if base is None:
+                    base = (s, info.iters)
+                d = np.abs(s - base[0]).max() / np.abs(ref).max()
+                say(f"{nx}x{ny} {sched} {shape}: iters {info.iters}, vs first shape {d:.1e}, vs oracle {err:.1e}")
+                assert info.converged
+                if prec == sgn.SGN_FP64:
+                    assert info.iters == base[1] and d < 1e-12 and err < 1e-10
+                else:
+                    assert abs(info.iters - base[1]) <= 1 and d < 1e-5 and err < 1e-5
+    say(f"{nx}x{ny}: {len(seen)} distinct launch shapes")
