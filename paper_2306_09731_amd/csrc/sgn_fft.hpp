@@ -121,11 +121,11 @@ __device__ __forceinline__ void dft(cplx* v) {
   }
 }
 
-// Elements per thread for a transform of length N: 4, or 8 for the longest
-// transforms (from 2048 points in FP32, where registers hold twice as many
-// values, from 4096 in FP64).
+// Elements per thread for a transform of length N: 4, or 8 from 2048 points
+// (half the threads per transform and two fewer LDS exchanges; measured
+// faster there in both precisions, slower at 1024 and 512 points in FP64).
 #ifndef SGN_E8_MIN
-#define SGN_E8_MIN 4096
+#define SGN_E8_MIN 2048
 #endif
 template <int N>
 struct FftShape {

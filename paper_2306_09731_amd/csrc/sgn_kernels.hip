@@ -26,7 +26,6 @@
 #define SGN_NS p32
 #define SGN_REAL float
 #define SGN_CPLX float2
-#define SGN_E8_MIN 2048
 #define TWX(g) ((g).twx32)
 #define TWY(g) ((g).twy32)
 #elif SGN_PREC == 64

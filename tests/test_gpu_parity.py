@@ -62,7 +62,8 @@ def rel(a, ref, bg=0.0):
     return np.abs(a - ref).max() / (scale if scale > 0 else 1.0)
 
 
-SIZES = [(8, 8), (16, 32), (32, 16), (128, 64), (256, 16), (512, 256), (1024, 512), (4096, 8), (8, 4096)]
+SIZES = [(8, 8), (16, 32), (32, 16), (128, 64), (256, 16), (512, 256), (1024, 512), (2048, 16), (16, 2048),
+         (4096, 8), (8, 4096)]
 
 
 @pytest.mark.parametrize("nx,ny", SIZES)
@@ -79,7 +80,8 @@ def test_derivatives(nx, ny):
     assert rel(host(out), O.d_y(g, f)) < 1e-12
 
 
-@pytest.mark.parametrize("nx,ny", [(8, 8), (64, 32), (128, 64), (256, 128), (1024, 512), (16, 1024)])
+@pytest.mark.parametrize("nx,ny", [(8, 8), (64, 32), (128, 64), (256, 128), (1024, 512), (16, 1024), (2048, 32),
+                                   (32, 2048)])
 def test_operator_and_preconditioner(nx, ny):
     say(f"operator {nx}x{ny}")
     ctx, g = mk(nx, ny, 2.0, 1.3)
@@ -153,7 +155,7 @@ def test_rk4_two_thirds_rule():
 
 @pytest.mark.parametrize("arnoldi", ["fused", "chained", "serial"])
 @pytest.mark.parametrize("nx,ny,restart", [(16, 16, 20), (64, 32, 20), (128, 64, 20), (256, 128, 20),
-                                           (64, 64, 3), (1024, 512, 20)])
+                                           (64, 64, 3), (1024, 512, 20), (2048, 32, 20), (32, 2048, 20)])
 def test_elliptic_solve(nx, ny, restart, arnoldi):
     say(f"elliptic solve {nx}x{ny} m={restart} {arnoldi}")
     ctx, g = mk(nx, ny, 1.5, 1.5, arnoldi=arnoldi, gmres_tol=1e-12, gmres_restart=restart, gmres_max_iters=400)
@@ -295,7 +297,19 @@ def test_rk4_krasny_and_random_state():
     assert rel(gh, oh, 1.0) < 1e-10 and rel(gvx, ovx) < 1e-10 and rel(gvy, ovy) < 1e-10
 
 
-@pytest.mark.parametrize("nx,ny", [(128, 64), (64, 128), (256, 256)])
+@pytest.mark.parametrize("nx,ny", [(2048, 16), (16, 2048)])
+def test_rk4_long_transforms(nx, ny):
+    """2048-point rows and columns (eight values per thread in the transforms)."""
+    say(f"rk4 {nx}x{ny}")
+    ctx, g = mk(nx, ny, 1.0, 1.0, gmres_tol=1e-12, krasny=1e-12)
+    rng = np.random.default_rng(nx + 7 * ny)
+    h, vx, vy, s = random_state(rng, Box(nx, ny, 1.0, 1.0), amp_h=0.2, amp_v=0.1, kmax=5)
+    gh, gvx, gvy, gs, info = run_gpu_rk4(ctx, h, vx, vy, s, 0.005, 3)
+    oh, ovx, ovy, os_, oinfo = O.rk4(g, h, vx, vy, s, 0.005, 3)
+    assert rel(gh, oh, 1.0) < 1e-10 and rel(gvx, ovx) < 1e-10 and rel(gvy, ovy) < 1e-10
+
+
+@pytest.mark.parametrize("nx,ny", [(128, 64), (64, 128), (256, 256), (2048, 16), (16, 2048)])
 def test_invariants(nx, ny):
     say(f"invariants {nx}x{ny}")
     ctx, g = mk(nx, ny, 2.0, 1.5)
