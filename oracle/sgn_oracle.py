@@ -145,12 +145,15 @@ def _dot(a, b):
 
 
 def gmres(grid: Grid, h: np.ndarray, b: np.ndarray, x0: np.ndarray, tol: float,
-          restart: int, max_iters: int):
+          restart: int, max_iters: int, record: dict | None = None):
     """Solve L_h x = b by GMRES(restart) applied to M^-1 L_h x = M^-1 b.
 
     Arnoldi with modified Gram-Schmidt; the least-squares problem is kept
     upper triangular with Givens rotations; the stopping test is on the
     preconditioned residual relative to ||M^-1 b||.  Returns (x, SolveInfo).
+    record (tests only): receives, for the first cycle, the basis "V", the
+    Hessenberg matrix before rotation "Hbar" ((k+1) x k) and the residual
+    estimates |g_{j+1}| / ||M^-1 b|| after each step, "resid".
     """
     info = SolveInfo()
     x = np.array(x0, dtype=np.float64, copy=True)
@@ -188,6 +191,8 @@ def gmres(grid: Grid, h: np.ndarray, b: np.ndarray, x0: np.ndarray, tol: float,
                 H[i, j] = _dot(w, V[i])
                 w = w - H[i, j] * V[i]
             H[j + 1, j] = math.sqrt(_dot(w, w))
+            if record is not None and info.restarts == 0:
+                record.setdefault("Hbar", np.zeros((m + 1, m)))[:j + 2, j] = H[:j + 2, j]
             for i in range(j):                           # previous rotations
                 t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
                 H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
@@ -202,6 +207,8 @@ def gmres(grid: Grid, h: np.ndarray, b: np.ndarray, x0: np.ndarray, tol: float,
             total += 1
             k = j + 1
             info.rel_resid_precond = abs(g[j + 1]) / beta0
+            if record is not None and info.restarts == 0:
+                record.setdefault("resid", []).append(abs(g[j + 1]) / beta0)
             if abs(g[j + 1]) <= tol * beta0:
                 done = True
                 break
@@ -210,6 +217,9 @@ def gmres(grid: Grid, h: np.ndarray, b: np.ndarray, x0: np.ndarray, tol: float,
                 done = True
                 break
             V.append(w / hn)
+        if record is not None and info.restarts == 0:
+            record["V"] = list(V)
+            record["Hbar"] = record["Hbar"][:len(V), :k]
         # back substitution for y in R y = g, then x += V y
         y = np.zeros(k)
         for i in range(k - 1, -1, -1):

@@ -143,6 +143,36 @@ def test_gmres_matches_dense_solve_16x16():
     assert np.abs(s2 - s_ref).max() < 1e-10 * np.abs(s_ref).max()
 
 
+def test_gmres_arnoldi_relation_orthonormality_monotone_residual():
+    """Within a cycle: M^-1 L V_k = V_{k+1} Hbar_k (the Arnoldi relation), the
+    basis is orthonormal while the residual is far from round-off (modified
+    Gram-Schmidt loses orthogonality in inverse proportion to the relative
+    residual, the result of Paige, Rozloznik and Strakos, so only the vectors
+    built while the residual estimate is above 1e-6 are held to 1e-9), and the
+    residual estimate never grows (GMRES minimises it over a growing
+    subspace)."""
+    g = grid(16, 16, 1.0, 1.0)
+    rng = np.random.default_rng(12)
+    h, _, _, _ = random_state(rng, Box(16, 16, 1.0, 1.0), amp_h=0.5)
+    b = rng.standard_normal((16, 16))
+    rec = {}
+    s, info = O.gmres(g, h, b, np.zeros_like(b), 1e-13, 30, 400, record=rec)
+    assert info.converged and info.restarts == 0
+    V = np.stack([v.ravel() for v in rec["V"]], axis=1)
+    Hbar = rec["Hbar"]
+    k = Hbar.shape[1]
+    assert k == info.iters and V.shape[1] >= k
+    AV = np.stack([O.apply_Minv(g, O.apply_L(g, h, rec["V"][j])).ravel() for j in range(k - 1)], axis=1)
+    lhs, rhs_ = AV, V[:, :k] @ Hbar[:k, :k - 1]
+    assert np.abs(lhs - rhs_).max() < 1e-12 * np.abs(lhs).max()
+    r = np.array(rec["resid"])
+    q = int(np.argmax(r < 1e-6)) + 1          # vectors V_0..V_q built while r >= 1e-6
+    Vq = V[:, :q + 1]
+    assert np.abs(Vq.T @ Vq - np.eye(q + 1)).max() < 1e-9
+    assert len(r) == k and np.all(r[1:] <= r[:-1] * (1 + 1e-12))
+    assert r[-1] <= 1e-13 and abs(r[-1] - info.rel_resid_precond) < 1e-12
+
+
 def test_gmres_one_iteration_at_unit_depth_and_zero_rhs():
     g = grid(32, 16, 1.0, 1.0)
     rng = np.random.default_rng(6)
