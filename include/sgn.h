@@ -292,8 +292,8 @@ const char* sgn_cnn_last_error(const sgn_cnn* net);
 /* Attach a network to a solver context (its grid: H = cfg.ny, W = cfg.nx), or
  * NULL to detach.  With a network, every solve of sgn_rk4_step starts from
  * sigma_prev + |r0| net(r0 / |r0|, M^-1 r0 / |r0|, h - h_inf) instead of the
- * warm start sigma_prev; GMRES then runs to the same tolerance (plain GMRES
- * judges the guess).  record (device FP32, capacity slots of 4 H W floats, or
+ * warm start sigma_prev; GMRES then runs, unchanged, to the same tolerance
+ * from the corrected guess.  record (device FP32, capacity slots of 4 H W floats, or
  * NULL): every solve of sgn_rk4_step writes one training sample into slot
  * (count mod capacity): the network input [H][W][3] of the warm start, then
  * the target (sigma - sigma_prev) / |r0| [H][W] with sigma the converged

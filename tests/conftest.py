@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests skip cleanly when no GPU is present (the CPU suite selects
-    # -m "not gpu" anyway); on a GPU machine they must run against the HIP library.
+    # -m "not gpu" anyway); with a GPU present they must run against the HIP library.
     try:
         import torch
         have_gpu = torch.cuda.is_available()
