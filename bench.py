@@ -275,7 +275,8 @@ def batched_form(sgn, torch, dev, args, per_grid: int = 16):
     in the mixed-precision mode: each member has its own context and stream,
     the Arnoldi schedule comes from the autotuner, and K steps of all members
     run as one sgn_rk4_step_ensemble call; the same steps run one member after
-    another give the sequential rate."""
+    another give the sequential rate, and with graph replays per member
+    (sgn_rk4_step_ensemble_graph) the graph rate."""
     import numpy as np
     from sgn_inputs import ENSEMBLE_GRIDS, ensemble_member
     members, seed, schedules = [], 0, {}
@@ -297,6 +298,14 @@ def batched_form(sgn, torch, dev, args, per_grid: int = 16):
     infos = sgn.sgn_rk4_step_ensemble(ctxs, fields, dts, steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # the same members with their steps replayed as captured graphs (the
+    # first call captures and calibrates the iteration budgets)
+    sgn.sgn_rk4_step_ensemble(ctxs, fields, dts, min(args.warmup, 2) or 1, graphs=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sgn.sgn_rk4_step_ensemble(ctxs, fields, dts, steps, graphs=True)
+    torch.cuda.synchronize()
+    el_graph = time.perf_counter() - t0
     t0 = time.perf_counter()
     for c, f, d in zip(ctxs, fields, dts):
         sgn.sgn_rk4_step(c, *f, d, steps)
@@ -308,6 +317,7 @@ def batched_form(sgn, torch, dev, args, per_grid: int = 16):
             "members": len(members), "points": pts, "precision": "fp32_mixed", "steps": steps,
             "value": pts * steps / el, "unit": UNIT, "ms_per_step": el * 1e3 / steps,
             "sequential_value": pts * steps / el_seq, "speedup_vs_sequential": el_seq / el,
+            "graph_value": pts * steps / el_graph, "graph_ms_per_step": el_graph * 1e3 / steps,
             "iters_per_solve_mean": sum(i.total_iters for i in infos) / max(sum(i.solves for i in infos), 1),
             "schedules": schedules}
 

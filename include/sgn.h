@@ -204,7 +204,7 @@ int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double 
  * Results are bitwise those of sgn_rk4_step with the same arguments.  The
  * graphs are captured on a stream private to the context, ordered after the
  * work on the context's stream and before work enqueued there later, and are
- * cached per (h, vx, vy, dt, budget).  Kernel timing (sgn_kernel_timing)
+ * cached per (h, vx, vy, dt, budget, launch shapes).  Kernel timing (sgn_kernel_timing)
  * counts host-driven launches only.  *replayed (may be NULL): 1 if graph
  * replays ran the steps, 0 if the call ran host-driven.  Errors: as
  * sgn_rk4_step; SGN_ERR_INVALID_ARG for iter_budget > gmres_restart. */
@@ -228,6 +228,14 @@ int sgn_invariants(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, 
  * is run; the first non-OK member status is returned. */
 int sgn_rk4_step_ensemble(int32_t n, sgn_ctx* const* ctxs, void* const* h, void* const* vx, void* const* vy,
                           void* const* sigma, const double* dt, int32_t nsteps, sgn_step_info* infos);
+
+/* The same, each member's steps run by sgn_rk4_step_graph (automatic
+ * iteration budget) on its thread: no host round trip per solve, so the
+ * members' kernels interleave more densely.  Results are bitwise those of
+ * sgn_rk4_step_ensemble.  A member with a learned guess attached is refused
+ * (SGN_ERR_UNSUPPORTED), as by sgn_rk4_step_graph. */
+int sgn_rk4_step_ensemble_graph(int32_t n, sgn_ctx* const* ctxs, void* const* h, void* const* vx, void* const* vy,
+                                void* const* sigma, const double* dt, int32_t nsteps, sgn_step_info* infos);
 
 /* Autotuner of the launch schedule: times a few GMRES solves of a synthetic
  * smooth problem with each Arnoldi schedule this grid supports (four kernels

@@ -1146,8 +1146,11 @@ int sgn_krasny_filter(sgn_ctx* ctx, void* f) {
   return SGN_OK;
 }
 
-int sgn_rk4_step_ensemble(int32_t n, sgn_ctx* const* ctxs, void* const* h, void* const* vx, void* const* vy,
-                          void* const* sigma, const double* dt, int32_t nsteps, sgn_step_info* infos) {
+namespace {
+// Members on host threads of their own; graphs: each member's steps as
+// captured-graph replays (sgn_rk4_step_graph, automatic budget).
+int run_ensemble(int32_t n, sgn_ctx* const* ctxs, void* const* h, void* const* vx, void* const* vy,
+                 void* const* sigma, const double* dt, int32_t nsteps, sgn_step_info* infos, bool graphs) {
   if (n < 0 || (n > 0 && (!ctxs || !h || !vx || !vy || !sigma || !dt)) || nsteps < 0) return SGN_ERR_INVALID_ARG;
   for (int i = 0; i < n; ++i) {
     if (!ctxs[i]) return SGN_ERR_INVALID_ARG;
@@ -1163,13 +1166,26 @@ int sgn_rk4_step_ensemble(int32_t n, sgn_ctx* const* ctxs, void* const* h, void*
         rc[i] = SGN_ERR_HIP;
         return;
       }
-      rc[i] = sgn_rk4_step(ctxs[i], h[i], vx[i], vy[i], sigma[i], dt[i], nsteps, infos ? &infos[i] : nullptr);
+      sgn_step_info* inf = infos ? &infos[i] : nullptr;
+      rc[i] = graphs ? sgn_rk4_step_graph(ctxs[i], h[i], vx[i], vy[i], sigma[i], dt[i], nsteps, 0, inf, nullptr)
+                     : sgn_rk4_step(ctxs[i], h[i], vx[i], vy[i], sigma[i], dt[i], nsteps, inf);
     });
   }
   for (auto& t : threads) t.join();
   for (int i = 0; i < n; ++i)
     if (rc[i] != SGN_OK) return rc[i];
   return SGN_OK;
+}
+}  // namespace
+
+int sgn_rk4_step_ensemble(int32_t n, sgn_ctx* const* ctxs, void* const* h, void* const* vx, void* const* vy,
+                          void* const* sigma, const double* dt, int32_t nsteps, sgn_step_info* infos) {
+  return run_ensemble(n, ctxs, h, vx, vy, sigma, dt, nsteps, infos, false);
+}
+
+int sgn_rk4_step_ensemble_graph(int32_t n, sgn_ctx* const* ctxs, void* const* h, void* const* vx, void* const* vy,
+                                void* const* sigma, const double* dt, int32_t nsteps, sgn_step_info* infos) {
+  return run_ensemble(n, ctxs, h, vx, vy, sigma, dt, nsteps, infos, true);
 }
 
 namespace {

@@ -82,6 +82,9 @@ class sgn_invariants_out(ctypes.Structure):
 
 
 _VP = ctypes.c_void_p
+_ENSEMBLE_ARGS = [ctypes.c_int32, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                  ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.POINTER(sgn_step_info)]
+
 _SIGNATURES = {
     "sgn_config_default": (None, [ctypes.POINTER(sgn_config), ctypes.c_int32, ctypes.c_int32,
                                   ctypes.c_double, ctypes.c_double]),
@@ -103,10 +106,8 @@ _SIGNATURES = {
     "sgn_apply_operator": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int32]),
     "sgn_apply_precond": (ctypes.c_int, [_VP, _VP, _VP]),
     "sgn_krasny_filter": (ctypes.c_int, [_VP, _VP]),
-    "sgn_rk4_step_ensemble": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
-                                             ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP),
-                                             ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
-                                             ctypes.POINTER(sgn_step_info)]),
+    "sgn_rk4_step_ensemble": (ctypes.c_int, _ENSEMBLE_ARGS),
+    "sgn_rk4_step_ensemble_graph": (ctypes.c_int, _ENSEMBLE_ARGS),
     "sgn_autotune": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32)]),
     "sgn_kernel_timing": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "sgn_kernel_time": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
@@ -301,17 +302,20 @@ def sgn_rk4_step_graph(ctx: Context, h, vx, vy, sigma, dt: float, nsteps: int = 
     return info, bool(rep.value)
 
 
-def sgn_rk4_step_ensemble(ctxs, fields, dts, nsteps: int):
+def sgn_rk4_step_ensemble(ctxs, fields, dts, nsteps: int, graphs: bool = False):
     """nsteps RK4 steps of every member; fields[i] = (h, vx, vy, sigma) of
-    member i, dts[i] its step.  Returns the list of sgn_step_info."""
+    member i, dts[i] its step; graphs: each member's steps as captured-graph
+    replays.  Returns the list of sgn_step_info."""
     n = len(ctxs)
     if not (len(fields) == n and len(dts) == n):
         raise ValueError("one field tuple and one dt per context")
     arr = lambda vals: (_VP * max(n, 1))(*vals)
     ptrs = [[_field(c, f[k], name) for c, f in zip(ctxs, fields)] for k, name in enumerate(("h", "vx", "vy", "sigma"))]
     infos = (sgn_step_info * max(n, 1))()
-    st = load_library().sgn_rk4_step_ensemble(n, arr([c.handle for c in ctxs]), *(arr(p) for p in ptrs),
-                                              (ctypes.c_double * max(n, 1))(*dts), nsteps, infos)
+    lib = load_library()
+    fn = lib.sgn_rk4_step_ensemble_graph if graphs else lib.sgn_rk4_step_ensemble
+    st = fn(n, arr([c.handle for c in ctxs]), *(arr(p) for p in ptrs), (ctypes.c_double * max(n, 1))(*dts), nsteps,
+            infos)
     _check(None, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
     return [infos[i] for i in range(n)]
 

@@ -30,20 +30,39 @@ def member_ctx(seed, nx, ny, precision=sgn.SGN_FP64, stream=None):
     return ctx, f, p["dt"]
 
 
-def test_ensemble_members_match_single_runs():
+@pytest.mark.parametrize("graphs", [False, True])
+def test_ensemble_members_match_single_runs(graphs):
+    """Host-driven members, or members replaying captured graphs (two calls:
+    the first captures, the second replays), against sgn_rk4_step alone with
+    the same calls (a call boundary passes sigma through physical space, so
+    one call of six steps and two of three differ in the last bit)."""
     specs = [(0, 64, 64, sgn.SGN_FP64), (1, 128, 64, sgn.SGN_FP64), (2, 128, 128, sgn.SGN_FP32_MIXED),
              (3, 64, 128, sgn.SGN_FP64), (4, 256, 256, sgn.SGN_FP64)]
     nsteps = 6
     streams = [torch.cuda.Stream(DEV) for _ in specs]
     ens = [member_ctx(seed, nx, ny, prec, st) for (seed, nx, ny, prec), st in zip(specs, streams)]
-    infos = sgn.sgn_rk4_step_ensemble([c for c, _, _ in ens], [f for _, f, _ in ens], [d for _, _, d in ens], nsteps)
+    args = ([c for c, _, _ in ens], [f for _, f, _ in ens], [d for _, _, d in ens])
+    if graphs:
+        i1 = sgn.sgn_rk4_step_ensemble(*args, 3, graphs=True)
+        i2 = sgn.sgn_rk4_step_ensemble(*args, nsteps - 3, graphs=True)
+        infos = [sgn.sgn_step_info() for _ in specs]
+        for a, b, c in zip(infos, i1, i2):
+            a.total_iters, a.solves = b.total_iters + c.total_iters, b.solves + c.solves
+    else:
+        infos = sgn.sgn_rk4_step_ensemble(*args, nsteps)
     torch.cuda.synchronize()
     for (seed, nx, ny, prec), (ctx, f, dt), info in zip(specs, ens, infos):
         ctx1, f1, _ = member_ctx(seed, nx, ny, prec)
-        info1 = sgn.sgn_rk4_step(ctx1, *f1, dt, nsteps)
+        if graphs:
+            a1 = sgn.sgn_rk4_step(ctx1, *f1, dt, 3)
+            info1 = sgn.sgn_rk4_step(ctx1, *f1, dt, nsteps - 3)
+            info1.total_iters += a1.total_iters
+        else:
+            info1 = sgn.sgn_rk4_step(ctx1, *f1, dt, nsteps)
         torch.cuda.synchronize()
         same = all(torch.equal(a, b) for a, b in zip(f, f1))
-        say(f"member {seed} {nx}x{ny} prec {prec}: identical {same}, iters {info.total_iters} / {info1.total_iters}")
+        say(f"member {seed} {nx}x{ny} prec {prec} graphs {graphs}: identical {same}, "
+            f"iters {info.total_iters} / {info1.total_iters}")
         assert same and info.total_iters == info1.total_iters and info.solves == 4 * nsteps
 
 
