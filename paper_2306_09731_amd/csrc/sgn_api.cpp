@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -39,6 +40,7 @@ struct sgn_ctx {
   char* D;  // guess 1: four per-stage sigma increments (2D spectra), else null
   void *hs, *vxs, *vys, *acc_h, *acc_vx, *acc_vy;
   sgn::GmresStatus* hstat;  // pinned host copy of the device status
+  hipEvent_t stat_ev = nullptr;  // recorded after the status copy of a speculative batch
   int last_iters[5];  // iterations of the previous solve per slot (RK stages 0-3, other calls 4)
   int arnoldi;   // 0 serial 4-kernel, 1 chain-parallel 4-kernel, 2 three-kernel (default where allowed)
   std::string err;
@@ -251,6 +253,7 @@ int check_state(sgn_ctx* ctx, const void* a, const void* b, const void* c) {
 struct SolveResult {
   int iters = 0, restarts = 0, converged = 0;
   double rel_resid = 0.0;
+  bool post_done = false;  // the caller's post-solve work ran predicated (run_solve)
 };
 
 // ---- kernel sequences shared by the host-driven loop and the captured step
@@ -324,7 +327,7 @@ int enqueue_arnoldi(sgn_ctx* ctx, const void* h, int it) {
 // RK4 stage `stage` after its solve: fluxes, Bernoulli function and the
 // stage combine (stage input (ih, ivx, ivy); the step's state h, vx, vy).
 int enqueue_stage_flux(sgn_ctx* ctx, int stage, double dt, void* h, void* vx, void* vy, const void* ih,
-                       const void* ivx, const void* ivy) {
+                       const void* ivx, const void* ivy, bool spec = false) {
   const sgn::Geom& g = ctx->g;
   hipStream_t s = ctx->stream;
   sgn::RkStage rk;
@@ -340,6 +343,7 @@ int enqueue_stage_flux(sgn_ctx* ctx, int stage, double dt, void* h, void* vx, vo
     rk.cnext = 0.0;
   }
   rk.dt = dt;
+  rk.pred = spec ? &ctx->st->st : nullptr;
   const bool last = stage == 3;
   sgn::RkField fvx{vx, ctx->acc_vx, last ? vx : ctx->vxs};
   sgn::RkField fh{h, ctx->acc_h, last ? h : ctx->hs};
@@ -367,8 +371,13 @@ int enqueue_step_filter(sgn_ctx* ctx, void* h, void* vx, void* vy) {
 // mode 1: b = -div v from (vx, vy); mode 2: b given (passed as vx).
 // On return (SIG, E, G) hold the solution.
 // slot: which history predicts the iteration count (the RK stage, or 4).
+// post (may be null): enqueues the caller's work that follows the solve.
+// With it, every batch of Arnoldi steps is followed, before the host waits
+// for the status, by the solution update and post(true), all predicated on
+// the solve having converged: the GPU goes on with them while the host reads
+// the status.  res->post_done tells the caller that they did run.
 int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void* vy, SolveResult* res,
-              int slot = 4, void* D = nullptr) {
+              int slot = 4, void* D = nullptr, const std::function<int(bool)>* post = nullptr) {
   const sgn::Geom& g = ctx->g;
   hipStream_t s = ctx->stream;
   const int m = ctx->cfg.gmres_restart;
@@ -377,6 +386,8 @@ int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void*
   int total = 0;
   res->restarts = 0;
   res->converged = 0;
+  res->post_done = false;
+  if (post && !ctx->stat_ev) HIPCK(hipEventCreateWithFlags(&ctx->stat_ev, hipEventDisableTiming));
   for (;;) {
     int rc0 = enqueue_residual(ctx, mode, h, vx, vy, need_b, flags);
     if (rc0) return rc0;
@@ -397,8 +408,18 @@ int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void*
         if (rc1) return rc1;
       }
       j += nrun;
-      int rc = read_status(ctx);
-      if (rc) return rc;
+      if (post) {
+        HIPCK(hipMemcpyAsync(ctx->hstat, &ctx->st->st, sizeof(sgn::GmresStatus), hipMemcpyDeviceToHost, s));
+        HIPCK(hipEventRecord(ctx->stat_ev, s));
+        HIPCK(sgn::launch_col_update_eg(g, ctx->SIG, ctx->V, ctx->vstride, ctx->st, ctx->E, ctx->G, D, 1, s));
+        int rc = (*post)(true);
+        if (rc) return rc;
+        HIPCK(hipEventSynchronize(ctx->stat_ev));
+        res->post_done = ctx->hstat->done == 1;
+      } else {
+        int rc = read_status(ctx);
+        if (rc) return rc;
+      }
       if (ctx->hstat->done) break;
       batch = 2;
     }
@@ -430,8 +451,10 @@ int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void*
       }
     }
     total = st.total_iters;
-    // sigma_hat += V y, and E, G of the new sigma
-    HIPCK(sgn::launch_col_update_eg(g, ctx->SIG, ctx->V, ctx->vstride, ctx->st, ctx->E, ctx->G, D, s));
+    // sigma_hat += V y, and E, G of the new sigma (already enqueued when a
+    // predicated update ran)
+    if (!res->post_done)
+      HIPCK(sgn::launch_col_update_eg(g, ctx->SIG, ctx->V, ctx->vstride, ctx->st, ctx->E, ctx->G, D, 0, s));
     res->rel_resid = st.beta0 > 0 ? st.resid / st.beta0 : 0.0;
     if (st.done == 1) {
       res->converged = 1;
@@ -519,7 +542,7 @@ int enqueue_graph_step(sgn_ctx* ctx, int kind, void* h, void* vx, void* vy, doub
     if ((rc = enqueue_residual(ctx, 1, ih, ivx, ivy, 1, 1))) return rc;
     for (int it = 0; it < budget; ++it)
       if ((rc = enqueue_arnoldi(ctx, ih, it))) return rc;
-    HIPCK(sgn::launch_col_update_eg(g, ctx->SIG, ctx->V, ctx->vstride, ctx->st, ctx->E, ctx->G, Dst, s));
+    HIPCK(sgn::launch_col_update_eg(g, ctx->SIG, ctx->V, ctx->vstride, ctx->st, ctx->E, ctx->G, Dst, 0, s));
     HIPCK(sgn::launch_solve_stats(g, ctx->st, s));
     if ((rc = enqueue_stage_flux(ctx, stage, dt, h, vx, vy, ih, ivx, ivy))) return rc;
   }
@@ -770,6 +793,7 @@ int sgn_destroy(sgn_ctx* ctx) {
   for (hipEvent_t e : ctx->gev)
     if (e) (void)hipEventDestroy(e);
   if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
+  if (ctx->stat_ev) (void)hipEventDestroy(ctx->stat_ev);
   if (ctx->hstat) (void)hipHostFree(ctx->hstat);
   delete ctx;
   return SGN_OK;
@@ -919,15 +943,19 @@ int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double 
       float* slot = nullptr;
       if ((ctx->learn_net || ctx->learn_rec) && (rc = learned_start(ctx, ih, ivx, ivy, &slot))) return rc;
       SolveResult res;
-      rc = run_solve(ctx, 1, ih, ivx, ivy, &res, stage, Dst);
+      // the stage's fluxes follow each batch of Arnoldi steps speculatively
+      // (not with the learned guess, whose finish comes between)
+      const std::function<int(bool)> post = [&](bool spec) {
+        return enqueue_stage_flux(ctx, stage, dt, h, vx, vy, ih, ivx, ivy, spec);
+      };
+      rc = run_solve(ctx, 1, ih, ivx, ivy, &res, stage, Dst, slot ? nullptr : &post);
       if (rc) return rc;
       if (slot && (rc = learned_finish(ctx, slot))) return rc;
       total += res.iters;
       if (res.iters > maxper) maxper = res.iters;
       solves += 1;
       unconv |= !res.converged;
-      rc = enqueue_stage_flux(ctx, stage, dt, h, vx, vy, ih, ivx, ivy);
-      if (rc) return rc;
+      if (!res.post_done && (rc = enqueue_stage_flux(ctx, stage, dt, h, vx, vy, ih, ivx, ivy))) return rc;
     }
     rc = enqueue_step_filter(ctx, h, vx, vy);
     if (rc) return rc;

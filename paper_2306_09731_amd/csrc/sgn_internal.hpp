@@ -87,6 +87,9 @@ struct RkStage {
   double wacc;
   double cnext;
   double dt;
+  // non-null: a launch enqueued before the host knew that the solve had
+  // converged; the kernel does nothing unless pred->done == 1
+  const GmresStatus* pred = nullptr;
 };
 
 // Field pointers of the working precision (double or float arrays).

@@ -750,6 +750,7 @@ __global__ void __launch_bounds__(512) k_row_flux(Geom g, const cplx* __restrict
                                                   const real* h, const real* vx, const real* vy,
                                                   real* __restrict__ dhp, real* __restrict__ qy,
                                                   real* __restrict__ Bo, RkStage rk, RkField fvx) {
+  if (rk.pred && rk.pred->done != 1) return;
   ROW_SETUP(N)
   cplx s[E], sx[E], sy[E], hh[E], ux[E], uy[E];
   load_spec_pair<N>(s, Es, ya, t, g.inv_nx);
@@ -1361,12 +1362,15 @@ __global__ void __launch_bounds__(1024) k_col_precond_new(Geom g, const cplx* __
 
 // sigma_hat += sum_{i<k} y_i V_i (or 0 when b == 0), then E, G of sigma_hat.
 // D (optional): the stage increment of the extrapolated guess, D += (new -
-// old sigma_hat), so that over a solve D collects sigma - guess.
+// old sigma_hat), so that over a solve D collects sigma - guess.  spec: a
+// launch enqueued before the host knew the outcome of the solve; it does
+// nothing unless the solve has converged.
 template <int N>
 __global__ void __launch_bounds__(512) k_col_update_eg(Geom g, cplx* __restrict__ SIG, const cplx* __restrict__ V,
                                                         size_t vstride, const GmresState* __restrict__ st,
                                                         cplx* __restrict__ Eo, cplx* __restrict__ Go,
-                                                        cplx* __restrict__ D) {
+                                                        cplx* __restrict__ D, int spec) {
+  if (spec && st->st.done != 1) return;
   COL_SETUP(N)
   __shared__ double coef[kMaxRestart];
   const int tid = flat_tid();
@@ -1727,6 +1731,7 @@ __global__ void __launch_bounds__(512) k_col_dy(Geom g, const real* __restrict__
 template <int N>
 __global__ void __launch_bounds__(512) k_col_flux(Geom g, const real* __restrict__ dhp, const real* __restrict__ qy,
                                                    const real* __restrict__ Bf, RkStage rk, RkField fh, RkField fvy) {
+  if (rk.pred && rk.pred->done != 1) return;
   COL_SETUP(N)
   cplx v[E], u[E];
   load_col<N>(v, reinterpret_cast<const cplx*>(qy), g.nh, col, t, valid);
@@ -2103,8 +2108,8 @@ static hipError_t col_basis_eg_n(const Geom& g, const cplx* W, cplx* V, size_t v
 
 template <int N>
 static hipError_t col_update_eg_n(const Geom& g, cplx* SIG, const cplx* V, size_t vs, const GmresState* st, cplx* Eo,
-                                  cplx* Go, cplx* D, hipStream_t s) {
-  COL_LAUNCH(k_col_update_eg<N>, g, SIG, V, vs, st, Eo, Go, D);
+                                  cplx* Go, cplx* D, int spec, hipStream_t s) {
+  COL_LAUNCH(k_col_update_eg<N>, g, SIG, V, vs, st, Eo, Go, D, spec);
 }
 
 template <int N>
@@ -2407,8 +2412,8 @@ hipError_t launch_col_basis2(const Geom& g, const void* W, void* V, size_t vs, i
   DISPATCH_NY(col_basis2_n, g, RC_(W), WC_(V), vs, j, st, WC_(Eo), WC_(Go), pin, s)
 }
 hipError_t launch_col_update_eg(const Geom& g, void* SIG, const void* V, size_t vs, const GmresState* st, void* Eo,
-                                void* Go, void* D, hipStream_t s) {
-  DISPATCH_NY(col_update_eg_n, g, WC_(SIG), RC_(V), vs, st, WC_(Eo), WC_(Go), WC_(D), s)
+                                void* Go, void* D, int spec, hipStream_t s) {
+  DISPATCH_NY(col_update_eg_n, g, WC_(SIG), RC_(V), vs, st, WC_(Eo), WC_(Go), WC_(D), spec, s)
 }
 hipError_t launch_col_guess_eg(const Geom& g, void* SIG, const void* D, void* Eo, void* Go, hipStream_t s) {
   DISPATCH_NY(col_guess_eg_n, g, WC_(SIG), RC_(D), WC_(Eo), WC_(Go), s)

@@ -41,8 +41,8 @@
     (g, W, V, vs, j, st, Eo, Go, pin, s))                                                                       \
   X(col_update_eg,                                                                                              \
     (const Geom& g, void* SIG, const void* V, size_t vs, const GmresState* st, void* Eo, void* Go, void* D,     \
-     hipStream_t s),                                                                                            \
-    (g, SIG, V, vs, st, Eo, Go, D, s))                                                                          \
+     int spec, hipStream_t s),                                                                                  \
+    (g, SIG, V, vs, st, Eo, Go, D, spec, s))                                                                    \
   X(col_guess_eg, (const Geom& g, void* SIG, const void* D, void* Eo, void* Go, hipStream_t s),                \
     (g, SIG, D, Eo, Go, s))                                                                                     \
   X(col_precond_dot,                                                                                            \
