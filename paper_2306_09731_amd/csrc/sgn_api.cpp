@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <functional>
 #include <map>
 #include <mutex>
@@ -47,7 +48,7 @@ struct sgn_ctx {
   // kernel timing (measurement support)
   int timed_kind = -1;
   std::vector<hipEvent_t> ev_free;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+  std::deque<std::pair<hipEvent_t, hipEvent_t>> ev_pending;  // oldest first
   int64_t timed_launches = 0;
   double timed_ms = 0.0;
   double timed_bytes = 0.0;  // algorithmic bytes of the timed launches that did work
@@ -204,7 +205,20 @@ struct KernelTimer {
     if (!a || !b) return;
     ctx->ev_pending.emplace_back(a, b);
     a = b = nullptr;
-    if (ctx->ev_pending.size() >= 4096) (void)drain_timing(ctx);
+    // collect finished pairs a few at a time, oldest first, so that the list
+    // stays short without a synchronisation inside the timed work
+    for (int k = 0; k < 2 && ctx->ev_pending.size() > 256; ++k) {
+      const auto pr = ctx->ev_pending.front();
+      if (hipEventQuery(pr.second) != hipSuccess) break;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess) break;
+      ctx->timed_ms += ms;
+      ctx->timed_launches += 1;
+      ctx->ev_free.push_back(pr.first);
+      ctx->ev_free.push_back(pr.second);
+      ctx->ev_pending.pop_front();
+    }
+    if (ctx->ev_pending.size() >= 65536) (void)drain_timing(ctx);
   }
 };
 

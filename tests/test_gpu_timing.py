@@ -1,0 +1,42 @@
+"""The library's per-launch kernel timing (the benchmark's roofline source).
+
+Kernel B (the x part of the operator) runs once per Arnoldi step, so over an
+RK4 run its algorithmic bytes are exactly 5 fields x (8 B x points) x the
+GMRES iterations, whatever the speculative launches; every launch that
+carried events is counted, and the durations are plausible.  The run is long
+enough that finished event pairs are collected while it goes on."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2306_09731_amd import sgn
+from sgn_inputs import workload
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def kind_of(name):
+    return [k for k, v in sgn.KERNEL_NAMES.items() if v == name][0]
+
+
+def test_kernel_b_timing_over_an_rk4_run():
+    box, (h, vx, vy, s), w = workload("perturbed_soliton_1024x512")
+    cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"], gmres_restart=w["restart"],
+                             krasny=1e-12)
+    ctx = sgn.sgn_init(cfg, DEV)
+    f = [torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in (h, vx, vy, s)]
+    sgn.sgn_rk4_step(ctx, *f, w["dt"], 2)
+    k = kind_of("row_matvec")
+    sgn.sgn_kernel_timing(ctx, k, True)
+    info = sgn.sgn_rk4_step(ctx, *f, w["dt"], 20)
+    n, ms, algo = sgn.sgn_kernel_time(ctx, k)
+    sgn.sgn_kernel_timing(ctx, k, False)
+    fb = 8.0 * box.nx * box.ny
+    print(f"kernel B: {n} launches, {ms / n * 1e3:.2f} us mean, {info.total_iters} iterations", flush=True)
+    assert algo == 5 * fb * info.total_iters
+    assert info.total_iters <= n <= info.total_iters + 3 * info.solves
+    assert 1.0 < ms / n * 1e3 < 200.0
+    # timing off: the class reports nothing
+    sgn.sgn_rk4_step(ctx, *f, w["dt"], 1)
+    assert sgn.sgn_kernel_time(ctx, k)[0] == 0
