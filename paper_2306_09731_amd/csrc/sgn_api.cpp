@@ -42,6 +42,7 @@ struct sgn_ctx {
   void *hs, *vxs, *vys, *acc_h, *acc_vx, *acc_vy;
   sgn::GmresStatus* hstat;  // pinned host copy of the device status
   hipEvent_t stat_ev = nullptr;  // recorded after the status copy of a speculative batch
+  int batch_margin = 0;  // Arnoldi steps enqueued beyond the previous solve's count
   int last_iters[5];  // iterations of the previous solve per slot (RK stages 0-3, other calls 4)
   int arnoldi;   // 0 serial 4-kernel, 1 chain-parallel 4-kernel, 2 three-kernel (default where allowed)
   std::string err;
@@ -409,8 +410,9 @@ int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void*
     flags = 0;
     int j = 0;
     const bool fused = ctx->arnoldi == 2;
-    // speculative batch: one more step than this slot's previous solve needed
-    int batch = (res->restarts == 0 ? ctx->last_iters[slot] : m) + 1;
+    // speculative batch: as many steps as this slot's previous solve needed
+    // (plus batch_margin; 0 measured fastest at every size tried)
+    int batch = (res->restarts == 0 ? ctx->last_iters[slot] : m) + ctx->batch_margin;
     if (batch < 1) batch = 1;
     for (;;) {
       int nrun = batch;
@@ -718,6 +720,12 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   if (const char* rt = std::getenv("SGN_ROW_THREADS")) {
     const int v = std::atoi(rt);
     if (v >= 64 && v <= 512 && (v & (v - 1)) == 0) g.row_threads = v;
+  }
+  // SGN_BATCH_MARGIN (0..4): Arnoldi steps enqueued beyond the previous
+  // solve's count before the host reads the status
+  if (const char* bm = std::getenv("SGN_BATCH_MARGIN")) {
+    const int v = std::atoi(bm);
+    if (v >= 0 && v <= 4) ctx->batch_margin = v;
   }
   if (!sgn::chained_ok(g)) ctx->arnoldi = 0;
   char* base = ctx->ws;
