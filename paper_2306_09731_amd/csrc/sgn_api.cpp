@@ -373,12 +373,13 @@ int enqueue_step_filter(sgn_ctx* ctx, void* h, void* vx, void* vy) {
   if (!step_filter_on(ctx->cfg)) return SGN_OK;
   const sgn::Geom& g = ctx->g;
   hipStream_t s = ctx->stream;
-  void* fs[3] = {h, vx, vy};
-  for (void* f : fs) {
-    HIPCK(sgn::launch_row_r2c(g, f, ctx->P, s));
-    HIPCK(sgn::launch_col_filter(g, ctx->P, step_filter_op(ctx->cfg), ctx->cfg.krasny, ctx->Q, s));
-    HIPCK(sgn::launch_row_c2r(g, ctx->Q, f, s));
-  }
+  // the three fields in one launch of each pass; scratch (free between
+  // solves): P, Q, R1 for the x-half spectra, R2, W, Z for the filtered ones
+  void* fl[3] = {ctx->R2, ctx->W, ctx->Z};
+  HIPCK(sgn::launch_row_r2c3(g, sgn::Trio{{h, vx, vy}, {ctx->P, ctx->Q, ctx->R1}}, s));
+  HIPCK(sgn::launch_col_filter3(g, sgn::Trio{{ctx->P, ctx->Q, ctx->R1}, {fl[0], fl[1], fl[2]}},
+                                step_filter_op(ctx->cfg), ctx->cfg.krasny, s));
+  HIPCK(sgn::launch_row_c2r3(g, sgn::Trio{{fl[0], fl[1], fl[2]}, {h, vx, vy}}, s));
   return SGN_OK;
 }
 

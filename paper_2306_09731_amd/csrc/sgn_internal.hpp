@@ -92,6 +92,13 @@ struct RkStage {
   const GmresStatus* pred = nullptr;
 };
 
+// Up to three independent fields for one launch of a pass (blockIdx.y picks
+// one): in[i] is read, out[i] written.
+struct Trio {
+  const void* in[3];
+  void* out[3];
+};
+
 // Field pointers of the working precision (double or float arrays).
 struct RkField {
   const void* yn;   // state at the start of the step

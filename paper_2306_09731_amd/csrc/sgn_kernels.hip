@@ -519,7 +519,9 @@ __device__ __forceinline__ void store_spec_pair(const cplx* v, cplx* __restrict_
 
 // physical f -> x-half spectra S
 template <int N>
-__global__ void __launch_bounds__(512) k_row_r2c(Geom g, const real* __restrict__ f, cplx* __restrict__ S) {
+__global__ void __launch_bounds__(512) k_row_r2c(Geom g, Trio io) {
+  const real* __restrict__ f = static_cast<const real*>(io.in[blockIdx.y]);
+  cplx* __restrict__ S = static_cast<cplx*>(io.out[blockIdx.y]);
   ROW_SETUP(N)
   cplx v[E];
   load_phys_pair<N>(v, f, ya, t);
@@ -529,7 +531,9 @@ __global__ void __launch_bounds__(512) k_row_r2c(Geom g, const real* __restrict_
 
 // x-half spectra S -> physical f
 template <int N>
-__global__ void __launch_bounds__(512) k_row_c2r(Geom g, const cplx* __restrict__ S, real* __restrict__ f) {
+__global__ void __launch_bounds__(512) k_row_c2r(Geom g, Trio io) {
+  const cplx* __restrict__ S = static_cast<const cplx*>(io.in[blockIdx.y]);
+  real* __restrict__ f = static_cast<real*>(io.out[blockIdx.y]);
   ROW_SETUP(N)
   cplx v[E];
   load_spec_pair<N>(v, S, ya, t, g.inv_nx);
@@ -1611,8 +1615,9 @@ __global__ void __launch_bounds__(512) k_col_apply(Geom g, const cplx* __restric
 //   op 2: op 1, and also zero modes with 3 |m_x| > nx or 3 |m_y| > ny (the
 //         two-thirds rule of Orszag, an option beyond the paper's scheme)
 template <int N>
-__global__ void __launch_bounds__(512) k_col_filter(Geom g, const cplx* __restrict__ Sx, int op, double thr,
-                                                     cplx* __restrict__ out) {
+__global__ void __launch_bounds__(512) k_col_filter(Geom g, Trio io, int op, double thr) {
+  const cplx* __restrict__ Sx = static_cast<const cplx*>(io.in[blockIdx.y]);
+  cplx* __restrict__ out = static_cast<cplx*>(io.out[blockIdx.y]);
   COL_SETUP(N)
   cplx v[E];
   load_col<N>(v, Sx, g.nh, col, t, valid);
@@ -2004,6 +2009,29 @@ static hipError_t allow_lds(const void* fn, size_t bytes) {
     return hipGetLastError();                                                               \
   } while (0)
 
+// The same with gridDim.y = NY independent fields (Trio).
+#define ROW_LAUNCH_Y(KERNEL, NY, ...)                                                       \
+  do {                                                                                      \
+    const size_t lb = RowLaunch<N>::lds(g);                                                 \
+    hipError_t e_ = allow_lds(reinterpret_cast<const void*>(KERNEL), lb);                   \
+    if (e_ != hipSuccess) return e_;                                                        \
+    dim3 grid_ = RowLaunch<N>::grid(g);                                                     \
+    grid_.y = (NY);                                                                         \
+    launch(KERNEL, grid_, RowLaunch<N>::block(g), lb, s, __VA_ARGS__);                      \
+    return hipGetLastError();                                                               \
+  } while (0)
+
+#define COL_LAUNCH_Y(KERNEL, NY, ...)                                                       \
+  do {                                                                                      \
+    const size_t lb = ColLaunch<N>::lds(g);                                                 \
+    hipError_t e_ = allow_lds(reinterpret_cast<const void*>(KERNEL), lb);                   \
+    if (e_ != hipSuccess) return e_;                                                        \
+    dim3 grid_ = ColLaunch<N>::grid(g);                                                     \
+    grid_.y = (NY);                                                                         \
+    launch(KERNEL, grid_, ColLaunch<N>::block(g), lb, s, __VA_ARGS__);                      \
+    return hipGetLastError();                                                               \
+  } while (0)
+
 #define COL_LAUNCH(KERNEL, ...)                                                             \
   do {                                                                                      \
     const size_t lb = ColLaunch<N>::lds(g);                                              \
@@ -2043,13 +2071,13 @@ static hipError_t allow_lds(const void* fn, size_t bytes) {
   }
 
 template <int N>
-static hipError_t row_r2c_n(const Geom& g, const real* f, cplx* S, hipStream_t s) {
-  ROW_LAUNCH(k_row_r2c<N>, g, f, S);
+static hipError_t row_r2c_n(const Geom& g, Trio io, int nf, hipStream_t s) {
+  ROW_LAUNCH_Y(k_row_r2c<N>, nf, g, io);
 }
 
 template <int N>
-static hipError_t row_c2r_n(const Geom& g, const cplx* S, real* f, hipStream_t s) {
-  ROW_LAUNCH(k_row_c2r<N>, g, S, f);
+static hipError_t row_c2r_n(const Geom& g, Trio io, int nf, hipStream_t s) {
+  ROW_LAUNCH_Y(k_row_c2r<N>, nf, g, io);
 }
 
 template <int N>
@@ -2146,8 +2174,8 @@ static hipError_t col_apply_n(const Geom& g, const cplx* P, const cplx* Q, int p
 }
 
 template <int N>
-static hipError_t col_filter_n(const Geom& g, const cplx* Sx, int op, double thr, cplx* o, hipStream_t s) {
-  COL_LAUNCH(k_col_filter<N>, g, Sx, op, thr, o);
+static hipError_t col_filter_n(const Geom& g, Trio io, int nf, int op, double thr, hipStream_t s) {
+  COL_LAUNCH_Y(k_col_filter<N>, nf, g, io, op, thr);
 }
 
 template <int N>
@@ -2374,11 +2402,15 @@ int upd_blocks(const Geom& g) {
 #define WC_(p) static_cast<cplx*>(p)
 
 hipError_t launch_row_r2c(const Geom& g, const void* f, void* S, hipStream_t s) {
-  DISPATCH_NX(row_r2c_n, g, R_(f), WC_(S), s)
+  const Trio io{{f, f, f}, {S, S, S}};
+  DISPATCH_NX(row_r2c_n, g, io, 1, s)
 }
 hipError_t launch_row_c2r(const Geom& g, const void* S, void* f, hipStream_t s) {
-  DISPATCH_NX(row_c2r_n, g, RC_(S), W_(f), s)
+  const Trio io{{S, S, S}, {f, f, f}};
+  DISPATCH_NX(row_c2r_n, g, io, 1, s)
 }
+hipError_t launch_row_r2c3(const Geom& g, Trio io, hipStream_t s) { DISPATCH_NX(row_r2c_n, g, io, 3, s) }
+hipError_t launch_row_c2r3(const Geom& g, Trio io, hipStream_t s) { DISPATCH_NX(row_c2r_n, g, io, 3, s) }
 hipError_t launch_row_dx(const Geom& g, const void* f, void* o, hipStream_t s) {
   DISPATCH_NX(row_dx_n, g, R_(f), W_(o), s)
 }
@@ -2472,7 +2504,11 @@ hipError_t launch_col_apply(const Geom& g, const void* P, const void* Q, int pre
   DISPATCH_NY(col_apply_n, g, RC_(P), RC_(Q), precond, WC_(o), s)
 }
 hipError_t launch_col_filter(const Geom& g, const void* Sx, int op, double thr, void* o, hipStream_t s) {
-  DISPATCH_NY(col_filter_n, g, RC_(Sx), op, thr, WC_(o), s)
+  const Trio io{{Sx, Sx, Sx}, {o, o, o}};
+  DISPATCH_NY(col_filter_n, g, io, 1, op, thr, s)
+}
+hipError_t launch_col_filter3(const Geom& g, Trio io, int op, double thr, hipStream_t s) {
+  DISPATCH_NY(col_filter_n, g, io, 3, op, thr, s)
 }
 hipError_t launch_col_tail(const Geom& g, const void* Sx, GmresState* st, double* partials, hipStream_t s) {
   DISPATCH_NY(col_tail_n, g, RC_(Sx), st, partials, s)

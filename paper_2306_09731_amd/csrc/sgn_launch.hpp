@@ -13,6 +13,9 @@
 #define SGN_LAUNCHERS(X)                                                                                        \
   X(row_r2c, (const Geom& g, const void* f, void* S, hipStream_t s), (g, f, S, s))                             \
   X(row_c2r, (const Geom& g, const void* S, void* f, hipStream_t s), (g, S, f, s))                             \
+  X(row_r2c3, (const Geom& g, Trio io, hipStream_t s), (g, io, s))                                              \
+  X(row_c2r3, (const Geom& g, Trio io, hipStream_t s), (g, io, s))                                              \
+  X(col_filter3, (const Geom& g, Trio io, int op, double thr, hipStream_t s), (g, io, op, thr, s))              \
   X(row_dx, (const Geom& g, const void* f, void* o, hipStream_t s), (g, f, o, s))                              \
   X(row_op,                                                                                                     \
     (const Geom& g, int mode, const void* E, const void* G, const void* h, const void* vx, const void* vy,      \
