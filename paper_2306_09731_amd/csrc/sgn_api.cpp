@@ -279,15 +279,16 @@ int enqueue_residual(sgn_ctx* ctx, int mode, const void* h, const void* vx, cons
   hipStream_t s = ctx->stream;
   HIPCK(sgn::launch_row_op(g, mode, ctx->E, ctx->G, h, vx, vy, ctx->P, ctx->Q, ctx->R1, ctx->R2, need_b, 0, ctx->st,
                            s));
-  // an explicit b (mode 2) has b_hat = F_y(R1) only
+  // an explicit b (mode 2) has b_hat = F_y(R1) only.  In the three-kernel
+  // schedule the residual pass also produces E, G of the residual (the work
+  // of kernel A at step 0), and its last block sets beta, which kernel B of
+  // step 0 would otherwise reduce: B_0 runs without a prologue
+  const bool fused = ctx->arnoldi == 2;
   HIPCK(sgn::launch_col_resid(g, ctx->P, ctx->Q, ctx->R1, mode == 2 ? nullptr : ctx->R2, need_b, flags, ctx->st,
-                              ctx->W, ctx->partials, s));
-  if (ctx->arnoldi == 2) {
-    // kernels A and B of step 0: E, G of the residual, its x part
-    TIMED(SGN_KERNEL_COL_BASIS, sgn::launch_col_proj(g, ctx->W, ctx->W, ctx->V, ctx->vstride, 0, ctx->st, ctx->E,
-                                                     ctx->G, ctx->partials, nullptr, s));
+                              ctx->W, ctx->partials, fused ? ctx->E : nullptr, fused ? ctx->G : nullptr, s));
+  if (fused) {
     TIMED(SGN_KERNEL_ROW_MATVEC,
-          sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, ctx->partials, 0, s));
+          sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, nullptr, 0, s));
   } else if (ctx->arnoldi == 1) {  // basis kernel of step 0: V_0, E, G
     TIMED(SGN_KERNEL_COL_BASIS,
           sgn::launch_col_basis2(g, ctx->W, ctx->V, ctx->vstride, 0, ctx->st, ctx->E, ctx->G, nullptr, s));
@@ -445,8 +446,9 @@ int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void*
       // algorithmic bytes of this cycle's launches that did work (fields of
       // fb bytes read or written once), unless the cycle converged at its
       // start.  Three-kernel step j: A (j+4), B 5, C (j+5), with A run for
-      // j <= jdone (A_jdone forms u_jdone before B_jdone stops the cycle) and
-      // B's transforms for j < jdone.  Four-kernel step j:
+      // 1 <= j <= jdone (A_jdone forms u_jdone before B_jdone stops the cycle;
+      // step 0's A is part of the residual pass) and B's transforms for
+      // j < jdone.  Four-kernel step j:
       // basis (j+4), x part 5, projections (j+4), update (j+3).
       const double fb = (g.fp32 ? 4.0 : 8.0) * (double)g.nx * (double)g.ny;
       const int jd = st.jdone;
@@ -456,8 +458,8 @@ int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void*
         if (fused) {
           if (ctx->timed_kind == SGN_KERNEL_COL_PRECOND_DOT)
             for (int jj = 0; jj < jd; ++jj) ctx->timed_bytes += (jj + 5) * fb;
-          if (ctx->timed_kind == SGN_KERNEL_COL_BASIS)
-            for (int jj = 0; jj <= jd && jj <= m; ++jj) ctx->timed_bytes += (jj + 4) * fb;
+          if (ctx->timed_kind == SGN_KERNEL_COL_BASIS)  // step 0's A is part of the residual pass
+            for (int jj = 1; jj <= jd && jj <= m; ++jj) ctx->timed_bytes += (jj + 4) * fb;
         } else {
           for (int jj = 0; jj < jd; ++jj) {
             if (ctx->timed_kind == SGN_KERNEL_COL_BASIS || ctx->timed_kind == SGN_KERNEL_COL_PRECOND_DOT)
@@ -504,7 +506,8 @@ int learned_start(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, f
   void* sg = V + 2 * ctx->field_bytes;
   void* sp = ctx->ckpt;
   HIPCK(sgn::launch_row_op(g, 1, ctx->E, ctx->G, h, vx, vy, ctx->P, ctx->Q, ctx->R1, ctx->R2, 1, 0, ctx->st, s));
-  HIPCK(sgn::launch_col_resid(g, ctx->P, ctx->Q, ctx->R1, ctx->R2, 1, 1, ctx->st, ctx->W, ctx->partials, s));
+  HIPCK(sgn::launch_col_resid(g, ctx->P, ctx->Q, ctx->R1, ctx->R2, 1, 1, ctx->st, ctx->W, ctx->partials, nullptr,
+                              nullptr, s));
   HIPCK(sgn::launch_col_learn(g, ctx->W, ctx->R1, ctx->R2, s));
   HIPCK(sgn::launch_row_c2r(g, ctx->R1, r0, s));
   HIPCK(sgn::launch_row_c2r(g, ctx->R2, mr0, s));
@@ -837,7 +840,7 @@ int sgn_elliptic_solve(sgn_ctx* ctx, const void* h, const void* b, void* sigma, 
     HIPCK(sgn::launch_row_op(ctx->g, 2, ctx->E, ctx->G, h, b, nullptr, ctx->P, ctx->Q, ctx->R1, ctx->R2, 0, 0,
                              ctx->st, ctx->stream));
     HIPCK(sgn::launch_col_resid(ctx->g, ctx->P, ctx->Q, nullptr, nullptr, 0, 2, ctx->st, nullptr, ctx->partials,
-                                ctx->stream));
+                                nullptr, nullptr, ctx->stream));
     rc = read_status(ctx);
     if (rc) return rc;
     info->iters = res.iters;

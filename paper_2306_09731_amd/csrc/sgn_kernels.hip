@@ -1497,7 +1497,8 @@ template <int N>
 __global__ void __launch_bounds__(512) k_col_resid(Geom g, const cplx* __restrict__ P, const cplx* __restrict__ Q,
                                                     const cplx* __restrict__ R1, const cplx* __restrict__ R2,
                                                     int need_b, int flags, GmresState* st, cplx* __restrict__ W,
-                                                    double* partials, int nblocks) {
+                                                    double* partials, int nblocks, cplx* __restrict__ Eo,
+                                                    cplx* __restrict__ Go) {
   COL_SETUP(N)
   __shared__ double red[3 * 16];
   __shared__ double outv[3];
@@ -1515,6 +1516,20 @@ __global__ void __launch_bounds__(512) k_col_resid(Geom g, const cplx* __restric
   }
   if (!true_only) store_spec<N>(v, W, col, t, valid);
   wave_partial(wt * nr, red, 0);
+  if (Eo) {
+    // the start of the three-kernel Arnoldi cycle (kernel A of step 0):
+    // E = F_y^-1 r / ny and G = F_y^-1 (i ky r) / ny of the residual r
+    cplx u[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      u[r] = mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Ly) * g.inv_ny);
+      v[r] = cscale(v[r], g.inv_ny);
+    }
+    fft<N, true, decltype(map)>(v, buf, t, twy, map);
+    store_col<N>(v, Eo, g.nh, col, t, valid);
+    fft<N, true, decltype(map)>(u, buf, t, twy, map);
+    store_col<N>(u, Go, g.nh, col, t, valid);
+  }
   int nvals = 1;
   if (need_b) {
     col_combine<N>(g, v, buf, t, col, valid, R1, R2, twy);
@@ -2153,9 +2168,10 @@ static hipError_t col_precond_dot_n(const Geom& g, const cplx* P, const cplx* Q,
 
 template <int N>
 static hipError_t col_resid_n(const Geom& g, const cplx* P, const cplx* Q, const cplx* R1, const cplx* R2, int need_b,
-                              int flags, GmresState* st, cplx* W, double* partials, hipStream_t s) {
+                              int flags, GmresState* st, cplx* W, double* partials, cplx* Eo, cplx* Go,
+                              hipStream_t s) {
   const int nb = (int)ColLaunch<N>::grid(g).x;
-  COL_LAUNCH(k_col_resid<N>, g, P, Q, R1, R2, need_b, flags, st, W, partials, nb);
+  COL_LAUNCH(k_col_resid<N>, g, P, Q, R1, R2, need_b, flags, st, W, partials, nb, Eo, Go);
 }
 
 template <int N>
@@ -2467,8 +2483,9 @@ hipError_t launch_col_precond_new(const Geom& g, const void* P, const void* Q, c
   DISPATCH_NY(col_precond_new_n, g, RC_(P), RC_(Q), RC_(W), WC_(V), WC_(Z), vs, j, st, partials, s)
 }
 hipError_t launch_col_resid(const Geom& g, const void* P, const void* Q, const void* R1, const void* R2, int need_b,
-                            int flags, GmresState* st, void* W, double* partials, hipStream_t s) {
-  DISPATCH_NY(col_resid_n, g, RC_(P), RC_(Q), RC_(R1), RC_(R2), need_b, flags, st, WC_(W), partials, s)
+                            int flags, GmresState* st, void* W, double* partials, void* Eo, void* Go, hipStream_t s) {
+  DISPATCH_NY(col_resid_n, g, RC_(P), RC_(Q), RC_(R1), RC_(R2), need_b, flags, st, WC_(W), partials, WC_(Eo),
+              WC_(Go), s)
 }
 hipError_t launch_col_learn(const Geom& g, const void* W, void* out_r, void* out_m, hipStream_t s) {
   DISPATCH_NY(col_learn_n, g, RC_(W), WC_(out_r), WC_(out_m), s)

@@ -66,8 +66,8 @@
     (g, P, Q, W, V, Z, vs, j, st, partials, s))                                                                 \
   X(col_resid,                                                                                                  \
     (const Geom& g, const void* P, const void* Q, const void* R1, const void* R2, int need_b, int flags,        \
-     GmresState* st, void* W, double* partials, hipStream_t s),                                                 \
-    (g, P, Q, R1, R2, need_b, flags, st, W, partials, s))                                                       \
+     GmresState* st, void* W, double* partials, void* Eo, void* Go, hipStream_t s),                             \
+    (g, P, Q, R1, R2, need_b, flags, st, W, partials, Eo, Go, s))                                               \
   X(col_inv, (const Geom& g, const void* S, void* o, hipStream_t s), (g, S, o, s))                             \
   X(col_apply, (const Geom& g, const void* P, const void* Q, int precond, void* o, hipStream_t s),             \
     (g, P, Q, precond, o, s))                                                                                   \
