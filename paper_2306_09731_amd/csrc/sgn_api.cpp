@@ -305,14 +305,14 @@ int enqueue_arnoldi(sgn_ctx* ctx, const void* h, int it) {
   const sgn::Geom& g = ctx->g;
   hipStream_t s = ctx->stream;
   if (ctx->arnoldi == 2) {
-    // C_it, A_it+1, B_it+1: B_it+1 finishes step it, so the device status is
-    // current after every step
+    // C_it, A_it+1, B_it+1: A_it+1 finishes step it (and stops the cycle
+    // there when it ends), so the device status is current after every step
     TIMED(SGN_KERNEL_COL_PRECOND_DOT, sgn::launch_col_precond_new(g, ctx->P, ctx->Q, ctx->W, ctx->V, ctx->Z,
                                                                   ctx->vstride, it, ctx->st, ctx->partials2, s));
     TIMED(SGN_KERNEL_COL_BASIS, sgn::launch_col_proj(g, ctx->Z, ctx->W, ctx->V, ctx->vstride, it + 1, ctx->st,
                                                      ctx->E, ctx->G, ctx->partials, ctx->partials2, s));
     TIMED(SGN_KERNEL_ROW_MATVEC,
-          sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, ctx->partials, it + 1, s));
+          sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, nullptr, it + 1, s));
     return SGN_OK;
   }
   // four-kernel step it: x part, projections, update, and the basis kernel of
@@ -445,10 +445,10 @@ int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void*
     if (ctx->timed_kind >= 0) {
       // algorithmic bytes of this cycle's launches that did work (fields of
       // fb bytes read or written once), unless the cycle converged at its
-      // start.  Three-kernel step j: A (j+4), B 5, C (j+5), with A run for
-      // 1 <= j <= jdone (A_jdone forms u_jdone before B_jdone stops the cycle;
-      // step 0's A is part of the residual pass) and B's transforms for
-      // j < jdone.  Four-kernel step j:
+      // start.  Three-kernel step j: A (j+4), B 5, C (j+5), with A's pass for
+      // 1 <= j < jdone (A_jdone stops the cycle before its pass; step 0's A is
+      // part of the residual pass) and B's transforms for j < jdone.
+      // Four-kernel step j:
       // basis (j+4), x part 5, projections (j+4), update (j+3).
       const double fb = (g.fp32 ? 4.0 : 8.0) * (double)g.nx * (double)g.ny;
       const int jd = st.jdone;
@@ -458,8 +458,8 @@ int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void*
         if (fused) {
           if (ctx->timed_kind == SGN_KERNEL_COL_PRECOND_DOT)
             for (int jj = 0; jj < jd; ++jj) ctx->timed_bytes += (jj + 5) * fb;
-          if (ctx->timed_kind == SGN_KERNEL_COL_BASIS)  // step 0's A is part of the residual pass
-            for (int jj = 1; jj <= jd && jj <= m; ++jj) ctx->timed_bytes += (jj + 4) * fb;
+          if (ctx->timed_kind == SGN_KERNEL_COL_BASIS)
+            for (int jj = 1; jj < jd; ++jj) ctx->timed_bytes += (jj + 4) * fb;
         } else {
           for (int jj = 0; jj < jd; ++jj) {
             if (ctx->timed_kind == SGN_KERNEL_COL_BASIS || ctx->timed_kind == SGN_KERNEL_COL_PRECOND_DOT)

@@ -1182,7 +1182,7 @@ __global__ void __launch_bounds__(1024) k_col_precond_dot2(Geom g, const cplx* _
 // block stores s, the new row and column of G and c.  The other blocks read
 // only the Gram entries of earlier steps, which this step does not change.
 __device__ void cgs_coefficients(const Geom& g, GmresState* st, int jc, const double* pin, int nb, double* outv,
-                                 double* coef, bool write) {
+                                 double* coef, bool write, double& beta) {
   const int tid = flat_tid(), nthr = block_threads();
   constexpr int ld = kMaxRestart + 1;
   // G_ik, i, k < jc, from earlier steps: for jc <= kPreG staged in LDS,
@@ -1197,14 +1197,14 @@ __device__ void cgs_coefficients(const Geom& g, GmresState* st, int jc, const do
     const int e = tid + u * nthr;
     gq[u] = e < ng ? st->G[(e / jc) * ld + e % jc] : 0.0;
   }
-  reduce_partials<false>(pin, nb, 2 * (jc + 1), nullptr, outv);
+  reduce_partials<false>(pin, nb, 2 * (jc + 1) + 1, nullptr, outv);
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int e = tid + u * nthr;
     if (e < ng) sG[e] = gq[u];
   }
   for (int e = tid + 2 * nthr; e < ng; e += nthr) sG[e] = st->G[(e / jc) * ld + e % jc];
-  for (int i = tid; i < 2 * (jc + 1); i += nthr) outv[i] *= g.inv_n;
+  for (int i = tid; i < 2 * (jc + 1) + 1; i += nthr) outv[i] *= g.inv_n;
   __syncthreads();
   // c_i = 2 s_i - sum_k G_ik s_k; G_ik, k < jc, from earlier steps, and
   // G_{i,jc} = <V_i, V_jc> from this reduction
@@ -1216,6 +1216,27 @@ __device__ void cgs_coefficients(const Geom& g, GmresState* st, int jc, const do
     coef[i] = 2.0 * outv[2 * i] - acc;
   }
   __syncthreads();
+  // H(jc+1, jc) = ||u|| with u = w - V c: ||u||^2 = ||w||^2 - 2 c.s + c^T G c
+  // (G the Gram matrix of V_0..V_jc), without a pass over u
+  __shared__ double gc[kMaxRestart + 1];
+  __shared__ double sh_beta;
+  for (int i = tid; i <= jc; i += nthr) {
+    double acc = 0.0;
+    for (int k = 0; k <= jc; ++k) {
+      const double gik = k == jc ? outv[2 * i + 1]
+                                 : (i == jc ? outv[2 * k + 1] : (pre ? sG[i * jc + k] : st->G[i * ld + k]));
+      acc += gik * coef[k];
+    }
+    gc[i] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double q = outv[2 * (jc + 1)];
+    for (int i = 0; i <= jc; ++i) q += coef[i] * (gc[i] - 2.0 * outv[2 * i]);
+    sh_beta = q > 0.0 ? sqrt(q) : 0.0;
+  }
+  __syncthreads();
+  beta = sh_beta;
   if (write) {
     for (int i = tid; i <= jc; i += nthr) {
       st->s[i] = outv[2 * i];
@@ -1226,8 +1247,11 @@ __device__ void cgs_coefficients(const Geom& g, GmresState* st, int jc, const do
   }
 }
 
-// Kernel A.  win: w_{j-1} (or the residual for j = 0); u_j -> W.  pin: the
-// block partials of C_{j-1} (same grid; unused for j = 0).
+// Kernel A (j >= 1; the residual pass does step 0's).  win: w_{j-1}; u_j ->
+// W.  pin: the block partials of C_{j-1} (same grid).  Every block first
+// finishes Arnoldi step j - 1 from them (projection coefficients, H(j, j-1)
+// by the Gram identity, Givens update and test; block 0 stores the step)
+// and exits if the cycle stops there, so the last step costs no pass.
 template <int N>
 __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx* W, const cplx* __restrict__ V,
                                                    size_t vstride, int j, GmresState* st, cplx* __restrict__ Eo,
@@ -1235,9 +1259,13 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
                                                    const double* __restrict__ pin) {
   if (st->st.done) return;
   __shared__ double coef[kMaxRestart + 1];
-  __shared__ double red[16];
-  __shared__ double outv[2 * (kMaxRestart + 1)];
-  if (j > 0) cgs_coefficients(g, st, j - 1, pin, gridDim.x, outv, coef, blockIdx.x == 0);
+  __shared__ double outv[2 * (kMaxRestart + 1) + 1];
+  {
+    const FinishPre pre = finish_prefetch(st, j - 1, false);
+    double beta;
+    cgs_coefficients(g, st, j - 1, pin, gridDim.x, outv, coef, blockIdx.x == 0, beta);
+    if (gmres_finish_column(st, j - 1, coef, beta, nullptr, blockIdx.x == 0, &pre)) return;
+  }
   COL2_SETUP(N)
   constexpr int EH = E / 2;
   cplx u[EH];
@@ -1263,13 +1291,9 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
     u[q] = x;
   }
   __syncthreads();  // every read of win (which may alias W) is done
-  double nr = 0.0;
 #pragma unroll
-  for (int q = 0; q < EH; ++q) {
+  for (int q = 0; q < EH; ++q)
     if (valid) W[sidx(g, t + (chain * EH + q) * TPF, col)] = u[q];
-    nr += cnorm2(u[q]);
-  }
-  wave_partial(valid ? col_weight(col) * nr : 0.0, red, 0);
   // gather all E positions of u for this chain's transform
   cplx* U = lds + c;  // chain 0's region, free until its transform
 #pragma unroll
@@ -1284,7 +1308,6 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
     v[r] = chain == 0 ? cscale(v[r], g.inv_ny) : mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Ly) * g.inv_ny);
   fft<N, true, ColMap>(v, buf, t, twy, map);
   store_col<N>(v, chain == 0 ? Eo : Go, g.nh, col, t, valid);
-  block_partials_out(red, 1, partials, nullptr);  // finished by B_j
 }
 
 // Kernel C.  P, Q: x-part outputs of B_j for u_j; W: u_j; writes V_j and
@@ -1297,7 +1320,7 @@ __global__ void __launch_bounds__(1024) k_col_precond_new(Geom g, const cplx* __
                                                           int j, const GmresState* st, double* partials) {
   if (st->st.done) return;
   COL2_SETUP(N)
-  __shared__ double red[2 * (kMaxRestart + 1) * 16];
+  __shared__ double red[(2 * (kMaxRestart + 1) + 1) * 16];
   const double ib = 1.0 / st->beta;
   cplx v[E];
   load_col<N>(v, chain == 0 ? P : Q, g.nh, col, t, valid);
@@ -1361,7 +1384,12 @@ __global__ void __launch_bounds__(1024) k_col_precond_new(Geom g, const cplx* __
     }
     wave_partials8(a, red, 2 * i0, nv);
   }
-  block_partials_out(red, nv, partials, nullptr);  // finished by A_{j+1}
+  // value 2 (j + 1): ||w_j||^2, for H(j+1, j) by the Gram identity
+  double nw2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < EH; ++q) nw2 += cnorm2(wj[q]);
+  wave_partial(wt * nw2, red, nv);
+  block_partials_out(red, nv + 1, partials, nullptr);  // finished by A_{j+1}
 }
 
 // sigma_hat += sum_{i<k} y_i V_i (or 0 when b == 0), then E, G of sigma_hat.
@@ -2384,7 +2412,7 @@ static hipError_t col_proj_n(const Geom& g, const cplx* win, cplx* W, const cplx
   const int tc = Chain<N>::tc(g);
   const dim3 block(tc, Col<N>::TPF, 2);
   const int nb = (g.nh + tc - 1) / tc;
-  const size_t lb = (size_t)2 * tc * N * sizeof(cplx);
+  const size_t lb = with_finish_lds(g, (size_t)2 * tc * N * sizeof(cplx), true);
   hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_proj<N>), lb);
   if (e != hipSuccess) return e;
   launch(k_col_proj<N>, dim3(nb), block, lb, s, g, win, W, V, vs, j, st, Eo, Go, partials, pin);
