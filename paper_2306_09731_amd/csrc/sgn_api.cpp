@@ -281,14 +281,13 @@ int enqueue_residual(sgn_ctx* ctx, int mode, const void* h, const void* vx, cons
                            s));
   // an explicit b (mode 2) has b_hat = F_y(R1) only.  In the three-kernel
   // schedule the residual pass also produces E, G of the residual (the work
-  // of kernel A at step 0), and its last block sets beta, which kernel B of
-  // step 0 would otherwise reduce: B_0 runs without a prologue
+  // of kernel A at step 0); its last block sets beta
   const bool fused = ctx->arnoldi == 2;
   HIPCK(sgn::launch_col_resid(g, ctx->P, ctx->Q, ctx->R1, mode == 2 ? nullptr : ctx->R2, need_b, flags, ctx->st,
                               ctx->W, ctx->partials, fused ? ctx->E : nullptr, fused ? ctx->G : nullptr, s));
   if (fused) {
     TIMED(SGN_KERNEL_ROW_MATVEC,
-          sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, nullptr, 0, s));
+          sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, s));
   } else if (ctx->arnoldi == 1) {  // basis kernel of step 0: V_0, E, G
     TIMED(SGN_KERNEL_COL_BASIS,
           sgn::launch_col_basis2(g, ctx->W, ctx->V, ctx->vstride, 0, ctx->st, ctx->E, ctx->G, nullptr, s));
@@ -310,9 +309,9 @@ int enqueue_arnoldi(sgn_ctx* ctx, const void* h, int it) {
     TIMED(SGN_KERNEL_COL_PRECOND_DOT, sgn::launch_col_precond_new(g, ctx->P, ctx->Q, ctx->W, ctx->V, ctx->Z,
                                                                   ctx->vstride, it, ctx->st, ctx->partials2, s));
     TIMED(SGN_KERNEL_COL_BASIS, sgn::launch_col_proj(g, ctx->Z, ctx->W, ctx->V, ctx->vstride, it + 1, ctx->st,
-                                                     ctx->E, ctx->G, ctx->partials, ctx->partials2, s));
+                                                     ctx->E, ctx->G, ctx->partials2, s));
     TIMED(SGN_KERNEL_ROW_MATVEC,
-          sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, nullptr, it + 1, s));
+          sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, s));
     return SGN_OK;
   }
   // four-kernel step it: x part, projections, update, and the basis kernel of
@@ -320,7 +319,7 @@ int enqueue_arnoldi(sgn_ctx* ctx, const void* h, int it) {
   const bool two = ctx->arnoldi == 1;
   if (two) {
     TIMED(SGN_KERNEL_ROW_MATVEC,
-          sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, nullptr, 0, s));
+          sgn::launch_row_matvec3(g, ctx->E, ctx->G, h, ctx->P, ctx->Q, ctx->st, s));
     TIMED(SGN_KERNEL_COL_PRECOND_DOT, sgn::launch_col_precond_dot2(g, ctx->P, ctx->Q, ctx->V, ctx->vstride, it,
                                                                    ctx->st, ctx->W, ctx->partials2, s));
   } else {

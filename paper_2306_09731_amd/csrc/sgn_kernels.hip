@@ -195,27 +195,6 @@ __device__ void reduce_partials(const double* partials, int nblocks, int nvals, 
   __syncthreads();
 }
 
-// One sum over the blocks' partials (value 0 of each), by the first wave;
-// partials written by an earlier kernel on the stream.  out[0] (LDS).
-__device__ void reduce_partials1(const double* partials, int nblocks, double* out) {
-  const int tid = flat_tid();
-  if (tid < 64) {
-    double a = 0.0;
-    for (int b0 = 0; b0 < nblocks; b0 += 256) {
-      double x[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int b = b0 + 64 * u + tid;
-        x[u] = b < nblocks ? partials[(size_t)b * kPartialStride] : 0.0;
-      }
-      a += (x[0] + x[1]) + (x[2] + x[3]);
-    }
-    a = wave_sum(a);
-    if (tid == 0) out[0] = a;
-  }
-  __syncthreads();
-}
-
 // Block-level: wave partial of value k goes to red[k * nw + wave].
 __device__ __forceinline__ void wave_partial(double x, double* red, int k) {
   const int tid = flat_tid();
@@ -635,8 +614,7 @@ __global__ void __launch_bounds__(512) k_row_op(Geom g, const cplx* __restrict__
 template <int N>
 __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __restrict__ Es, const cplx* __restrict__ Gs,
                                                       const real* __restrict__ h, cplx* __restrict__ P,
-                                                      cplx* __restrict__ Q, GmresState* st,
-                                                      const double* __restrict__ pin, int nbin, int jb) {
+                                                      cplx* __restrict__ Q, const GmresState* st) {
   if (st->st.done) return;
   constexpr int E = Row<N>::E;
   constexpr int TPF = Row<N>::TPF;
@@ -648,25 +626,6 @@ __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __rest
   const int ya = 2 * (blockIdx.x * (blockDim.y / 3) + slot);
   cplx* base = lds + slot * 3 * Row<N>::LDS;
   cplx* buf = base + chain * Row<N>::LDS;
-  if (pin) {
-    // three-kernel step: finish Arnoldi step jb - 1 from the nbin block
-    // partials of ||u_jb||^2 written by A_jb (for jb = 0 only beta, the norm
-    // of the residual), identically in every block so that every block knows
-    // whether to stop; block 0 stores the step
-    __shared__ double nrm[1];
-    __shared__ double cj[kMaxRestart + 1];
-    const FinishPre pre = finish_prefetch(st, jb - 1, true);
-    reduce_partials1(pin, nbin, nrm);
-    const double beta = sqrt(nrm[0] * g.inv_n);
-    const bool writer = blockIdx.x == 0;
-    if (jb == 0) {
-      if (writer && flat_tid() == 0) st->beta = beta;
-    } else {
-      if (flat_tid() < jb) cj[flat_tid()] = pre.cj;
-      __syncthreads();
-      if (gmres_finish_column(st, jb - 1, cj, beta, nullptr, writer, &pre)) return;
-    }
-  }
   TwiddleSet<N> twx;
   gather_twiddles<N>(twx, t, TWX(g));
   cplx v[E], hi[E];
@@ -1255,7 +1214,7 @@ __device__ void cgs_coefficients(const Geom& g, GmresState* st, int jc, const do
 template <int N>
 __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx* W, const cplx* __restrict__ V,
                                                    size_t vstride, int j, GmresState* st, cplx* __restrict__ Eo,
-                                                   cplx* __restrict__ Go, double* partials,
+                                                   cplx* __restrict__ Go,
                                                    const double* __restrict__ pin) {
   if (st->st.done) return;
   __shared__ double coef[kMaxRestart + 1];
@@ -2307,17 +2266,16 @@ static int col2_blocks(const Geom& g) {
 
 template <int N>
 static hipError_t row_matvec3_n(const Geom& g, const cplx* E, const cplx* G, const real* h, cplx* P, cplx* Q,
-                                GmresState* st, const double* pin, int jb, hipStream_t s) {
+                                const GmresState* st, hipStream_t s) {
   if constexpr (!Chain<N>::row_ok) {
     return hipErrorNotSupported;
   } else {
     const int r = Chain<N>::rpb(g);
     const dim3 block(Row<N>::TPF, 3 * r);
-    const size_t lb = with_finish_lds(g, (size_t)3 * r * Row<N>::LDS * sizeof(cplx), pin != nullptr);
+    const size_t lb = (size_t)3 * r * Row<N>::LDS * sizeof(cplx);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(k_row_matvec3<N>), lb);
     if (e != hipSuccess) return e;
-    launch(k_row_matvec3<N>, dim3((g.ny / 2) / r), block, lb, s, g, E, G, h, P, Q, st, pin, pin ? col2_blocks(g) : 0,
-           jb);
+    launch(k_row_matvec3<N>, dim3((g.ny / 2) / r), block, lb, s, g, E, G, h, P, Q, st);
     return hipGetLastError();
   }
 }
@@ -2408,14 +2366,14 @@ static hipError_t col_precond_dot2_n(const Geom& g, const cplx* P, const cplx* Q
 
 template <int N>
 static hipError_t col_proj_n(const Geom& g, const cplx* win, cplx* W, const cplx* V, size_t vs, int j, GmresState* st,
-                             cplx* Eo, cplx* Go, double* partials, const double* pin, hipStream_t s) {
+                             cplx* Eo, cplx* Go, const double* pin, hipStream_t s) {
   const int tc = Chain<N>::tc(g);
   const dim3 block(tc, Col<N>::TPF, 2);
   const int nb = (g.nh + tc - 1) / tc;
   const size_t lb = with_finish_lds(g, (size_t)2 * tc * N * sizeof(cplx), true);
   hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_proj<N>), lb);
   if (e != hipSuccess) return e;
-  launch(k_col_proj<N>, dim3(nb), block, lb, s, g, win, W, V, vs, j, st, Eo, Go, partials, pin);
+  launch(k_col_proj<N>, dim3(nb), block, lb, s, g, win, W, V, vs, j, st, Eo, Go, pin);
   return hipGetLastError();
 }
 
@@ -2473,8 +2431,8 @@ hipError_t launch_row_invariants(const Geom& g, const void* E, const void* G, co
   DISPATCH_NX(row_invariants_n, g, RC_(E), RC_(G), R_(h), R_(vx), R_(vy), R_(dyvx), partials, st, s)
 }
 hipError_t launch_row_matvec3(const Geom& g, const void* E, const void* G, const void* h, void* P, void* Q,
-                              GmresState* st, const double* pin, int jb, hipStream_t s) {
-  DISPATCH_NX(row_matvec3_n, g, RC_(E), RC_(G), R_(h), WC_(P), WC_(Q), st, pin, jb, s)
+                              const GmresState* st, hipStream_t s) {
+  DISPATCH_NX(row_matvec3_n, g, RC_(E), RC_(G), R_(h), WC_(P), WC_(Q), st, s)
 }
 hipError_t launch_col_fwd_eg(const Geom& g, const void* Ein, void* SIG, void* Go, hipStream_t s) {
   DISPATCH_NY(col_fwd_eg_n, g, RC_(Ein), WC_(SIG), WC_(Go), s)
@@ -2503,8 +2461,8 @@ hipError_t launch_col_precond_dot2(const Geom& g, const void* P, const void* Q, 
   DISPATCH_NY(col_precond_dot2_n, g, RC_(P), RC_(Q), RC_(V), vs, j, st, WC_(W), partials, s)
 }
 hipError_t launch_col_proj(const Geom& g, const void* win, void* W, const void* V, size_t vs, int j, GmresState* st,
-                           void* Eo, void* Go, double* partials, const double* pin, hipStream_t s) {
-  DISPATCH_NY(col_proj_n, g, RC_(win), WC_(W), RC_(V), vs, j, st, WC_(Eo), WC_(Go), partials, pin, s)
+                           void* Eo, void* Go, const double* pin, hipStream_t s) {
+  DISPATCH_NY(col_proj_n, g, RC_(win), WC_(W), RC_(V), vs, j, st, WC_(Eo), WC_(Go), pin, s)
 }
 hipError_t launch_col_precond_new(const Geom& g, const void* P, const void* Q, const void* W, void* V, void* Z,
                                   size_t vs, int j, GmresState* st, double* partials, hipStream_t s) {

@@ -30,9 +30,9 @@
      const void* dyvx, double* partials, GmresState* st, hipStream_t s),                                        \
     (g, E, G, h, vx, vy, dyvx, partials, st, s))                                                                \
   X(row_matvec3,                                                                                                \
-    (const Geom& g, const void* E, const void* G, const void* h, void* P, void* Q, GmresState* st,              \
-     const double* pin, int jb, hipStream_t s),                                                                 \
-    (g, E, G, h, P, Q, st, pin, jb, s))                                                                         \
+    (const Geom& g, const void* E, const void* G, const void* h, void* P, void* Q, const GmresState* st,        \
+     hipStream_t s),                                                                                            \
+    (g, E, G, h, P, Q, st, s))                                                                                  \
   X(col_fwd_eg, (const Geom& g, const void* Ein, void* SIG, void* Go, hipStream_t s), (g, Ein, SIG, Go, s))    \
   X(col_basis_eg,                                                                                               \
     (const Geom& g, const void* W, void* V, size_t vs, int j, GmresState* st, void* Eo, void* Go,               \
@@ -58,8 +58,8 @@
     (g, P, Q, V, vs, j, st, W, partials, s))                                                                    \
   X(col_proj,                                                                                                   \
     (const Geom& g, const void* win, void* W, const void* V, size_t vs, int j, GmresState* st, void* Eo,        \
-     void* Go, double* partials, const double* pin, hipStream_t s),                                             \
-    (g, win, W, V, vs, j, st, Eo, Go, partials, pin, s))                                                        \
+     void* Go, const double* pin, hipStream_t s),                                                               \
+    (g, win, W, V, vs, j, st, Eo, Go, pin, s))                                                                  \
   X(col_precond_new,                                                                                            \
     (const Geom& g, const void* P, const void* Q, const void* W, void* V, void* Z, size_t vs, int j,            \
      GmresState* st, double* partials, hipStream_t s),                                                          \
