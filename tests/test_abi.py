@@ -126,7 +126,20 @@ def test_ensemble_and_autotune_host_checks():
     assert lib.sgn_rk4_step_ensemble(-1, null, null, null, null, null, dts, 1, None) == sgn.SGN_ERR_INVALID_ARG
     assert lib.sgn_rk4_step_ensemble(1, null, null, null, null, null, dts, 1, None) == sgn.SGN_ERR_INVALID_ARG
     assert lib.sgn_rk4_step_ensemble(0, null, null, null, null, null, None, 1, None) == sgn.SGN_OK
+    for fn in (lib.sgn_rk4_step_ensemble, lib.sgn_rk4_step_ensemble_graph):
+        assert fn(-1, null, null, null, null, null, dts, 1, None) == sgn.SGN_ERR_INVALID_ARG
+        assert fn(1, null, null, null, null, null, dts, 1, None) == sgn.SGN_ERR_INVALID_ARG
+        assert fn(0, null, null, null, null, null, None, 1, None) == sgn.SGN_OK
     assert lib.sgn_autotune(None, None) == sgn.SGN_ERR_INVALID_ARG
+    out = (ctypes.c_int32 * 7)()
+    assert lib.sgn_launch_shape(None, out) == sgn.SGN_ERR_INVALID_ARG
+
+
+def test_refined_solve_host_checks():
+    lib = sgn.load_library()
+    info = sgn.sgn_refine_info()
+    assert lib.sgn_elliptic_solve_refined(None, None, None, None, None, 1e-10, 4, ctypes.byref(info)) \
+        == sgn.SGN_ERR_INVALID_ARG
 
 
 def test_graph_step_host_checks():
