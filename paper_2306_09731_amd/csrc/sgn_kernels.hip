@@ -259,7 +259,7 @@ __device__ __forceinline__ FinishPre finish_prefetch(const GmresState* st, int j
 }
 
 __device__ int gmres_finish_column(GmresState* st, int j, const double* cj, double beta, const double* s2,
-                                   bool write, const FinishPre* pre = nullptr);
+                                   bool write, const FinishPre* pre = nullptr, bool restart_now = false);
 
 // Finish CGS2 Arnoldi step j in a block of the kernel that follows the
 // update kernel, from its nb block partials (value 0: ||w1||^2; 1 + i:
@@ -303,7 +303,7 @@ __device__ int cgs2_finish(const Geom& g, GmresState* st, int j, const double* p
 // unchanged (rotations below j, g_j before rotation, the cycle's iteration
 // base), so each takes the writer's decision.
 __device__ int gmres_finish_column(GmresState* st, int j, const double* cj, double beta, const double* s2,
-                                   bool write, const FinishPre* pre) {
+                                   bool write, const FinishPre* pre, bool restart_now) {
   __shared__ double sh_col[kMaxRestart + 1];
   __shared__ double sh_cs[kMaxRestart], sh_sn[kMaxRestart];
   __shared__ double sh_gj, sh_gn, sh_resid;
@@ -342,7 +342,9 @@ __device__ int gmres_finish_column(GmresState* st, int j, const double* cj, doub
     const double resid = fabs(sh_gn);
     const int total = p.cycle_base + j + 1;
     int done = 0;
-    if (resid <= p.tol * p.beta0 || beta == 0.0)
+    if (restart_now)
+      done = total >= p.maxit ? 3 : 2;
+    else if (resid <= p.tol * p.beta0 || beta == 0.0)
       done = 1;
     else if (j + 1 >= p.m)
       done = 2;
@@ -1190,9 +1192,13 @@ __device__ void cgs_coefficients(const Geom& g, GmresState* st, int jc, const do
   }
   __syncthreads();
   if (tid == 0) {
-    double q = outv[2 * (jc + 1)];
+    const double w2 = outv[2 * (jc + 1)];
+    double q = w2;
     for (int i = 0; i <= jc; ++i) q += coef[i] * (gc[i] - 2.0 * outv[2 * i]);
-    sh_beta = q > 0.0 ? sqrt(q) : 0.0;
+    // the identity cancels ||w||^2 down to ||u||^2, so its rounding error is
+    // about eps ||w||^2; below 1e-10 ||w||^2 it no longer fixes ||u|| (to
+    // 1e-6 relative or better above): -1 tells the caller so
+    sh_beta = q > 1e-10 * w2 ? sqrt(q) : -1.0;
   }
   __syncthreads();
   beta = sh_beta;
@@ -1223,7 +1229,11 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
     const FinishPre pre = finish_prefetch(st, j - 1, false);
     double beta;
     cgs_coefficients(g, st, j - 1, pin, gridDim.x, outv, coef, blockIdx.x == 0, beta);
-    if (gmres_finish_column(st, j - 1, coef, beta, nullptr, blockIdx.x == 0, &pre)) return;
+    // a new direction too small for the Gram identity to measure: close the
+    // cycle on the columns so far (H(j, j-1) = 0) and restart, so that
+    // convergence is judged on a freshly computed residual
+    const bool unsure = beta < 0.0;
+    if (gmres_finish_column(st, j - 1, coef, unsure ? 0.0 : beta, nullptr, blockIdx.x == 0, &pre, unsure)) return;
   }
   COL2_SETUP(N)
   constexpr int EH = E / 2;
