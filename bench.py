@@ -51,7 +51,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--main-only", action="store_true",
                    help="time only the headline 1024x512 run (no guess, precision or batched forms; for profiler runs)")
-    p.add_argument("--cpu-steps", type=int, default=1)
+    p.add_argument("--cpu-steps", type=int, default=5)
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of MIB MiB, --steps times (calibrates the "
                         "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
