@@ -17,7 +17,8 @@ Readings of the paper used here (where it is silent or garbled):
   * wavenumbers k = m / L for m in [-N/2, N/2) with the Nyquist mode set to 0,
     so the discrete Laplacian is D.D and the preconditioner uses the same k;
   * preconditioner M = 3/h_inf^3 + (kx^2 + ky^2)/h_inf, i.e. the operator L at
-    h = h_inf (Section 3: "L for h = 1", M = 3 + kx^2 + ky^2 at h_inf = 1);
+    h = h_inf (Section 3 takes the operator at unit depth, M = 3 + kx^2 + ky^2
+    for h_inf = 1);
   * GMRES: restarted, left-preconditioned, modified Gram-Schmidt Arnoldi with
     Givens rotations (Saad & Schultz); stop when the preconditioned residual
     is <= tol * ||M^-1 b||;
