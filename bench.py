@@ -41,6 +41,7 @@ KRASNY = 1e-12
 # algorithmic bytes per launch, 5 fields (E, G, h read; P, Q written), are
 # summed by the library over the launches that did work.
 DOMINANT = "row_matvec"
+EVENT_PERIOD = 7  # launches of the timed class per launch that carries events
 
 
 def parse():
@@ -370,7 +371,9 @@ def main():
     progress("stage-increment guess run done")
     dominant = DOMINANT
     kind = [k for k, v in sgn.KERNEL_NAMES.items() if v == dominant][0]
-    sgn.sgn_kernel_timing(ctx, kind, True)
+    # events on every EVENT_PERIOD-th launch of the class: recording them on
+    # every launch costs about 3% of the step
+    sgn.sgn_kernel_timing(ctx, kind, True, EVENT_PERIOD)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     info = sgn.sgn_rk4_step(ctx, th, tvx, tvy, ts, w["dt"], args.steps)
@@ -421,6 +424,7 @@ def main():
             "algorithmic_bytes_per_launch": algo,
             "mean_launch_us": mean_s * 1e6,
             "launches": launches,
+            "events_on_every": EVENT_PERIOD,
         },
     }
     if not args.main_only:

@@ -325,13 +325,15 @@ int sgn_apply_precond(sgn_ctx* ctx, const void* r, void* out);
 int sgn_krasny_filter(sgn_ctx* ctx, void* f);
 
 /* Measurement support.  While timing is enabled for a kernel class, every
- * launch of that class is bracketed by HIP events recorded on the context
- * stream, so its device time can be read without a profiler.
- * sgn_kernel_timing(ctx, kind, 1) clears the totals and starts timing kind
- * (one class at a time); (ctx, kind, 0) stops it.  sgn_kernel_time
- * synchronises the stream and returns the number of timed launches and their
- * total duration in milliseconds.  Errors: SGN_ERR_INVALID_ARG for an unknown
- * kind, SGN_ERR_HIP. */
+ * p-th launch of that class is bracketed by HIP events recorded on the
+ * context stream, so its device time can be read without a profiler.
+ * sgn_kernel_timing(ctx, kind, p) with p >= 1 clears the totals and starts
+ * timing kind (one class at a time); (ctx, kind, 0) stops it.
+ * sgn_kernel_time synchronises the stream and returns the number of launches
+ * of the class while timing was on and their total duration in milliseconds:
+ * the sum over the launches with events, times launches / launches with
+ * events (p = 1: the measured sum).  Errors: SGN_ERR_INVALID_ARG for an
+ * unknown kind or p < 0, SGN_ERR_HIP. */
 enum {
   SGN_KERNEL_ROW_MATVEC = 0,     /* x part of the elliptic operator (Arnoldi step) */
   SGN_KERNEL_COL_BASIS = 1,      /* projection of the new vector + inverse y transforms */

@@ -50,7 +50,9 @@ struct sgn_ctx {
   int timed_kind = -1;
   std::vector<hipEvent_t> ev_free;
   std::deque<std::pair<hipEvent_t, hipEvent_t>> ev_pending;  // oldest first
-  int64_t timed_launches = 0;
+  int64_t timed_launches = 0;  // launches that carried events (durations collected)
+  int64_t timed_all = 0;       // all launches of the class while timing was on
+  int timed_period = 1;        // events on every timed_period-th launch
   double timed_ms = 0.0;
   double timed_bytes = 0.0;  // algorithmic bytes of the timed launches that did work
   // captured RK4 step (sgn_rk4_step_graph)
@@ -190,13 +192,15 @@ int drain_timing(sgn_ctx* ctx) {
   return SGN_OK;
 }
 
-// When a kernel class is being timed, its next launch carries a pair of
-// events that the runtime records at the start and end of the dispatch.
+// When a kernel class is being timed, every timed_period-th launch of it
+// carries a pair of events that the runtime records at the start and end of
+// the dispatch.
 struct KernelTimer {
   sgn_ctx* ctx;
   hipEvent_t a = nullptr, b = nullptr;
   KernelTimer(sgn_ctx* c, int kind) : ctx(c) {
     if (c->timed_kind != kind) return;
+    if (c->timed_all++ % c->timed_period != 0) return;
     a = take_event(c);
     b = take_event(c);
     if (a && b) sgn::set_launch_events(a, b);
@@ -1388,9 +1392,12 @@ int sgn_kernel_timing(sgn_ctx* ctx, int32_t kind, int32_t enable) {
   if (!ctx || kind < 0 || kind >= SGN_KERNEL_COUNT) return SGN_ERR_INVALID_ARG;
   int rc = drain_timing(ctx);
   if (rc) return rc;
+  if (enable < 0) return SGN_ERR_INVALID_ARG;
   if (enable) {
     ctx->timed_kind = kind;
     ctx->timed_launches = 0;
+    ctx->timed_all = 0;
+    ctx->timed_period = enable;
     ctx->timed_ms = 0.0;
     ctx->timed_bytes = 0.0;
     // create the events now so that the timed launches make no runtime
@@ -1411,8 +1418,12 @@ int sgn_kernel_time(sgn_ctx* ctx, int32_t kind, int64_t* launches, double* total
   int rc = drain_timing(ctx);
   if (rc) return rc;
   const bool mine = ctx->timed_kind == kind;
-  *launches = mine ? ctx->timed_launches : 0;
-  *total_ms = mine ? ctx->timed_ms : 0.0;
+  // with sampling, the summed duration is scaled from the launches that
+  // carried events to all launches of the class
+  *launches = mine ? ctx->timed_all : 0;
+  *total_ms = mine && ctx->timed_launches > 0
+                  ? ctx->timed_ms * (double)ctx->timed_all / (double)ctx->timed_launches
+                  : 0.0;
   if (algo_bytes) *algo_bytes = mine ? ctx->timed_bytes : 0.0;
   return SGN_OK;
 }

@@ -355,8 +355,9 @@ def sgn_krasny_filter(ctx: Context, f):
     _check(ctx, load_library().sgn_krasny_filter(ctx.handle, _field(ctx, f, "f")))
 
 
-def sgn_kernel_timing(ctx: Context, kind: int, enable: bool):
-    _check(ctx, load_library().sgn_kernel_timing(ctx.handle, int(kind), 1 if enable else 0))
+def sgn_kernel_timing(ctx: Context, kind: int, enable: bool, period: int = 1):
+    """Start (events on every period-th launch of the class) or stop timing."""
+    _check(ctx, load_library().sgn_kernel_timing(ctx.handle, int(kind), int(period) if enable else 0))
 
 
 def sgn_kernel_time(ctx: Context, kind: int):

@@ -40,3 +40,28 @@ def test_kernel_b_timing_over_an_rk4_run():
     # timing off: the class reports nothing
     sgn.sgn_rk4_step(ctx, *f, w["dt"], 1)
     assert sgn.sgn_kernel_time(ctx, k)[0] == 0
+
+
+def test_sampled_timing_estimates_the_same_mean():
+    """Events on every 7th launch only: the same launch count (all launches
+    are counted) and a mean duration within 10% of timing every launch on an
+    identical run."""
+    box, (h, vx, vy, s), w = workload("perturbed_soliton_1024x512")
+    k = kind_of("row_matvec")
+    res = {}
+    for period in (1, 7):
+        cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"], gmres_restart=w["restart"],
+                                 krasny=1e-12)
+        ctx = sgn.sgn_init(cfg, DEV)
+        f = [torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in (h, vx, vy, s)]
+        sgn.sgn_rk4_step(ctx, *f, w["dt"], 2)
+        sgn.sgn_kernel_timing(ctx, k, True, period)
+        info = sgn.sgn_rk4_step(ctx, *f, w["dt"], 20)
+        n, ms, algo = sgn.sgn_kernel_time(ctx, k)
+        sgn.sgn_kernel_timing(ctx, k, False)
+        res[period] = (n, ms / n, algo, info.total_iters)
+    (n1, m1, a1, i1), (n7, m7, a7, i7) = res[1], res[7]
+    print(f"every launch: {n1} launches, {m1 * 1e3:.2f} us; every 7th: {n7} launches, {m7 * 1e3:.2f} us",
+          flush=True)
+    assert n1 == n7 and a1 == a7 and i1 == i7
+    assert abs(m7 - m1) < 0.1 * m1
