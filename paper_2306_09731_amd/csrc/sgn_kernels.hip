@@ -1773,6 +1773,35 @@ __global__ void __launch_bounds__(512) k_col_flux(Geom g, const real* __restrict
   }
 }
 
+// The same with its two transform chains run concurrently by two thread
+// groups of the block (threadIdx.z): chain 0 forms -d_y qy and the RK combine
+// of h, chain 1 -d_y B and the RK combine of v_y (no exchange between them).
+template <int N>
+__global__ void __launch_bounds__(1024) k_col_flux2(Geom g, const real* __restrict__ dhp, const real* __restrict__ qy,
+                                                    const real* __restrict__ Bf, RkStage rk, RkField fh,
+                                                    RkField fvy) {
+  if (rk.pred && rk.pred->done != 1) return;
+  COL2_SETUP(N)
+  cplx v[E];
+  load_col<N>(v, reinterpret_cast<const cplx*>(chain == 0 ? qy : Bf), g.nh, col, t, valid);
+  fft<N, false, ColMap>(v, buf, t, twy, map);
+#pragma unroll
+  for (int r = 0; r < E; ++r) v[r] = mul_ik(v[r], -wavenumber(t + r * TPF, N, g.inv_Ly) * g.inv_ny);
+  fft<N, true, ColMap>(v, buf, t, twy, map);
+  if (!valid) return;
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const size_t i0 = ((size_t)(t + r * TPF) * g.nh + col) * 2;
+    if (chain == 0) {
+      rk_one(rk, fh, i0, dhp[i0] + v[r].x);
+      rk_one(rk, fh, i0 + 1, dhp[i0 + 1] + v[r].y);
+    } else {
+      rk_one(rk, fvy, i0, v[r].x);
+      rk_one(rk, fvy, i0 + 1, v[r].y);
+    }
+  }
+}
+
 // ----------------------------------------------------------------------------
 // Elementwise kernels
 // ----------------------------------------------------------------------------
@@ -2202,12 +2231,6 @@ static hipError_t col_dy_n(const Geom& g, const real* f, real* o, hipStream_t s)
   COL_LAUNCH(k_col_dy<N>, g, f, o);
 }
 
-template <int N>
-static hipError_t col_flux_n(const Geom& g, const real* dhp, const real* qy, const real* B, RkStage rk,
-                             RkField fh, RkField fvy, hipStream_t s) {
-  COL_LAUNCH(k_col_flux<N>, g, dhp, qy, B, rk, fh, fvy);
-}
-
 // Chain-parallel Arnoldi passes: usable when the chained block fits.
 template <int N>
 struct Chain {
@@ -2238,6 +2261,24 @@ struct Chain {
     return 2 * tc(g) * Col<N>::TPF <= 1024 && (size_t)2 * tc(g) * N * sizeof(cplx) <= kChainLds;
   }
 };
+
+template <int N>
+static hipError_t col_flux_n(const Geom& g, const real* dhp, const real* qy, const real* B, RkStage rk,
+                             RkField fh, RkField fvy, hipStream_t s) {
+  // the two chains in parallel; the radix-8 columns would spill at 1024 threads
+  if constexpr (N < SGN_E8_MIN) {
+    if (Chain<N>::col_ok(g)) {
+      const int tc = Chain<N>::tc(g);
+      const size_t lb = (size_t)2 * tc * N * sizeof(cplx);
+      hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_flux2<N>), lb);
+      if (e != hipSuccess) return e;
+      launch(k_col_flux2<N>, dim3((g.nh + tc - 1) / tc), dim3(tc, Col<N>::TPF, 2), lb, s, g, dhp, qy, B, rk, fh,
+             fvy);
+      return hipGetLastError();
+    }
+  }
+  COL_LAUNCH(k_col_flux<N>, g, dhp, qy, B, rk, fh, fvy);
+}
 
 // Blocks of the single-chain column kernels for this grid.
 template <int N>
