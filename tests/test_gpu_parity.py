@@ -81,7 +81,7 @@ def test_derivatives(nx, ny):
 
 
 @pytest.mark.parametrize("nx,ny", [(8, 8), (64, 32), (128, 64), (256, 128), (1024, 512), (16, 1024), (2048, 32),
-                                   (32, 2048)])
+                                   (32, 2048), (4096, 16), (16, 4096)])
 def test_operator_and_preconditioner(nx, ny):
     say(f"operator {nx}x{ny}")
     ctx, g = mk(nx, ny, 2.0, 1.3)
@@ -155,7 +155,8 @@ def test_rk4_two_thirds_rule():
 
 @pytest.mark.parametrize("arnoldi", ["fused", "chained", "serial"])
 @pytest.mark.parametrize("nx,ny,restart", [(16, 16, 20), (64, 32, 20), (128, 64, 20), (256, 128, 20),
-                                           (64, 64, 3), (1024, 512, 20), (2048, 32, 20), (32, 2048, 20)])
+                                           (64, 64, 3), (1024, 512, 20), (2048, 32, 20), (32, 2048, 20),
+                                           (4096, 16, 20), (16, 4096, 20)])
 def test_elliptic_solve(nx, ny, restart, arnoldi):
     say(f"elliptic solve {nx}x{ny} m={restart} {arnoldi}")
     ctx, g = mk(nx, ny, 1.5, 1.5, arnoldi=arnoldi, gmres_tol=1e-12, gmres_restart=restart, gmres_max_iters=400)
@@ -297,9 +298,11 @@ def test_rk4_krasny_and_random_state():
     assert rel(gh, oh, 1.0) < 1e-10 and rel(gvx, ovx) < 1e-10 and rel(gvy, ovy) < 1e-10
 
 
-@pytest.mark.parametrize("nx,ny", [(2048, 16), (16, 2048)])
+@pytest.mark.parametrize("nx,ny", [(2048, 16), (16, 2048), (4096, 16), (16, 4096)])
 def test_rk4_long_transforms(nx, ny):
-    """2048-point rows and columns (eight values per thread in the transforms)."""
+    """2048-point rows and columns (eight values per thread in the transforms),
+    and the largest supported length, 4096 (the four-kernel schedule: the
+    chained blocks do not fit)."""
     say(f"rk4 {nx}x{ny}")
     ctx, g = mk(nx, ny, 1.0, 1.0, gmres_tol=1e-12, krasny=1e-12)
     rng = np.random.default_rng(nx + 7 * ny)
