@@ -439,23 +439,29 @@ __device__ __forceinline__ void load_spec_pair(cplx* v, const cplx* __restrict__
   constexpr int H = N / 2;
   const cplx* A = S + (size_t)ya * H;
   const cplx* B = A + H;
+  // one unconditional load pair per value, all issued before any is used,
+  // so that they are in flight together
+  cplx la[Row<N>::E], lb[Row<N>::E];
 #pragma unroll
   for (int r = 0; r < Row<N>::E; ++r) {
     const int p = t + r * Row<N>::TPF;
+    const int q = (p == 0 || p == H) ? 0 : (p < H ? p : N - p);
+    la[r] = A[q];
+    lb[r] = B[q];
+  }
+#pragma unroll
+  for (int r = 0; r < Row<N>::E; ++r) {
+    const int p = t + r * Row<N>::TPF;
+    const cplx a = la[r], b = lb[r];
     cplx z;
-    if (p == 0) {
-      const cplx a = A[0], b = B[0];
+    if (p == 0)
       z = make_cplx(a.x, b.x);
-    } else if (p == H) {
-      const cplx a = A[0], b = B[0];
+    else if (p == H)
       z = make_cplx(a.y, b.y);
-    } else if (p < H) {
-      const cplx a = A[p], b = B[p];
+    else if (p < H)
       z = make_cplx(a.x - b.y, a.y + b.x);
-    } else {
-      const cplx a = A[N - p], b = B[N - p];
+    else
       z = make_cplx(a.x + b.y, b.x - a.y);
-    }
     v[r] = cscale(z, s);
   }
 }
@@ -617,7 +623,6 @@ template <int N>
 __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __restrict__ Es, const cplx* __restrict__ Gs,
                                                       const real* __restrict__ h, cplx* __restrict__ P,
                                                       cplx* __restrict__ Q, const GmresState* st) {
-  if (st->st.done) return;
   constexpr int E = Row<N>::E;
   constexpr int TPF = Row<N>::TPF;
   constexpr int H = N / 2;
@@ -628,11 +633,14 @@ __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __rest
   const int ya = 2 * (blockIdx.x * (blockDim.y / 3) + slot);
   cplx* base = lds + slot * 3 * Row<N>::LDS;
   cplx* buf = base + chain * Row<N>::LDS;
+  // the loads (in bounds whatever the state) are issued before the GMRES
+  // status is tested, so that its round trip overlaps theirs
   TwiddleSet<N> twx;
   gather_twiddles<N>(twx, t, TWX(g));
   cplx v[E], hi[E];
   load_spec_pair<N>(v, chain == 2 ? Gs : Es, ya, t, g.inv_nx);
   load_phys_pair<N>(hi, h, ya, t);
+  if (st->st.done) return;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     hi[r] = make_cplx(1.0 / hi[r].x, 1.0 / hi[r].y);
@@ -715,7 +723,6 @@ __global__ void __launch_bounds__(512) k_row_flux(Geom g, const cplx* __restrict
                                                   const real* h, const real* vx, const real* vy,
                                                   real* __restrict__ dhp, real* __restrict__ qy,
                                                   real* __restrict__ Bo, RkStage rk, RkField fvx) {
-  if (rk.pred && rk.pred->done != 1) return;
   ROW_SETUP(N)
   cplx s[E], sx[E], sy[E], hh[E], ux[E], uy[E];
   load_spec_pair<N>(s, Es, ya, t, g.inv_nx);
@@ -723,6 +730,7 @@ __global__ void __launch_bounds__(512) k_row_flux(Geom g, const cplx* __restrict
   load_phys_pair<N>(hh, h, ya, t);
   load_phys_pair<N>(ux, vx, ya, t);
   load_phys_pair<N>(uy, vy, ya, t);
+  if (rk.pred && rk.pred->done != 1) return;  // tested after the (in-bounds) loads are issued
 #pragma unroll
   for (int r = 0; r < E; ++r) sx[r] = mul_ik(s[r], wavenumber(t + r * TPF, N, g.inv_Lx));
   fft<N, true, decltype(map)>(s, buf, t, twx, map);   // sigma
@@ -1287,12 +1295,12 @@ __global__ void __launch_bounds__(1024) k_col_precond_new(Geom g, const cplx* __
                                                           const cplx* __restrict__ Q, const cplx* __restrict__ W,
                                                           cplx* __restrict__ V, cplx* __restrict__ Wn, size_t vstride,
                                                           int j, const GmresState* st, double* partials) {
-  if (st->st.done) return;
   COL2_SETUP(N)
   __shared__ double red[(2 * (kMaxRestart + 1) + 1) * 16];
-  const double ib = 1.0 / st->beta;
   cplx v[E];
   load_col<N>(v, chain == 0 ? P : Q, g.nh, col, t, valid);
+  if (st->st.done) return;  // tested after the loads are issued (they are in bounds whatever the state)
+  const double ib = 1.0 / st->beta;
   fft<N, false, ColMap>(v, buf, t, twy, map);
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -1748,11 +1756,11 @@ __global__ void __launch_bounds__(512) k_col_dy(Geom g, const real* __restrict__
 template <int N>
 __global__ void __launch_bounds__(512) k_col_flux(Geom g, const real* __restrict__ dhp, const real* __restrict__ qy,
                                                    const real* __restrict__ Bf, RkStage rk, RkField fh, RkField fvy) {
-  if (rk.pred && rk.pred->done != 1) return;
   COL_SETUP(N)
   cplx v[E], u[E];
   load_col<N>(v, reinterpret_cast<const cplx*>(qy), g.nh, col, t, valid);
   load_col<N>(u, reinterpret_cast<const cplx*>(Bf), g.nh, col, t, valid);
+  if (rk.pred && rk.pred->done != 1) return;  // tested after the (in-bounds) loads are issued
   fft<N, false, decltype(map)>(v, buf, t, twy, map);
 #pragma unroll
   for (int r = 0; r < E; ++r) v[r] = mul_ik(v[r], -wavenumber(t + r * TPF, N, g.inv_Ly) * g.inv_ny);
@@ -1780,10 +1788,10 @@ template <int N>
 __global__ void __launch_bounds__(1024) k_col_flux2(Geom g, const real* __restrict__ dhp, const real* __restrict__ qy,
                                                     const real* __restrict__ Bf, RkStage rk, RkField fh,
                                                     RkField fvy) {
-  if (rk.pred && rk.pred->done != 1) return;
   COL2_SETUP(N)
   cplx v[E];
   load_col<N>(v, reinterpret_cast<const cplx*>(chain == 0 ? qy : Bf), g.nh, col, t, valid);
+  if (rk.pred && rk.pred->done != 1) return;  // tested after the (in-bounds) loads are issued
   fft<N, false, ColMap>(v, buf, t, twy, map);
 #pragma unroll
   for (int r = 0; r < E; ++r) v[r] = mul_ik(v[r], -wavenumber(t + r * TPF, N, g.inv_Ly) * g.inv_ny);
