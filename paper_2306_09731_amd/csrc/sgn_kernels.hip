@@ -555,15 +555,16 @@ __global__ void __launch_bounds__(512) k_row_op(Geom g, const cplx* __restrict__
                                                 const real* __restrict__ vy, cplx* __restrict__ P,
                                                 cplx* __restrict__ Q, cplx* __restrict__ R1, cplx* __restrict__ R2,
                                                 int need_b, int predicate, const GmresState* __restrict__ st) {
-  if (MODE == 0 && predicate && st->st.done) return;
   ROW_SETUP(N)
-  // every global load first, so their latencies overlap
+  // every global load first, so their latencies overlap (the GMRES status
+  // too: the loads are in bounds whatever it is)
   cplx v[E], u[E], w[E], hi[E], x[E], y[E];
   load_spec_pair<N>(v, Es, ya, t, g.inv_nx);
   load_spec_pair<N>(w, Gs, ya, t, g.inv_nx);
   load_phys_pair<N>(hi, h, ya, t);
   if constexpr (MODE != 0) load_phys_pair<N>(x, vx, ya, t);
   if constexpr (MODE == 1) load_phys_pair<N>(y, vy, ya, t);
+  if (MODE == 0 && predicate && st->st.done) return;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     hi[r] = make_cplx(1.0 / hi[r].x, 1.0 / hi[r].y);
@@ -1078,11 +1079,11 @@ __global__ void __launch_bounds__(1024) k_col_precond_dot2(Geom g, const cplx* _
                                                            const cplx* __restrict__ Q, const cplx* __restrict__ V,
                                                            size_t vstride, int j, const GmresState* st,
                                                            cplx* __restrict__ W, double* partials) {
-  if (st->st.done) return;
   COL2_SETUP(N)
   __shared__ double red[(kMaxRestart + 1) * 16];
   cplx v[E];
   load_col<N>(v, chain == 0 ? P : Q, g.nh, col, t, valid);
+  if (st->st.done) return;  // tested after the (in-bounds) loads are issued
   fft<N, false, ColMap>(v, buf, t, twy, map);
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -1150,8 +1151,8 @@ __global__ void __launch_bounds__(1024) k_col_precond_dot2(Geom g, const cplx* _
 // partials pin, then c = (2I - G) s into coef (LDS), i <= jc.  write: this
 // block stores s, the new row and column of G and c.  The other blocks read
 // only the Gram entries of earlier steps, which this step does not change.
-__device__ void cgs_coefficients(const Geom& g, GmresState* st, int jc, const double* pin, int nb, double* outv,
-                                 double* coef, bool write, double& beta) {
+__device__ bool cgs_coefficients(const Geom& g, GmresState* st, int jc, const double* pin, int nb, double* outv,
+                                 double* coef, bool write, double& beta, int done) {
   const int tid = flat_tid(), nthr = block_threads();
   constexpr int ld = kMaxRestart + 1;
   // G_ik, i, k < jc, from earlier steps: for jc <= kPreG staged in LDS,
@@ -1167,6 +1168,9 @@ __device__ void cgs_coefficients(const Geom& g, GmresState* st, int jc, const do
     gq[u] = e < ng ? st->G[(e / jc) * ld + e % jc] : 0.0;
   }
   reduce_partials<false>(pin, nb, 2 * (jc + 1) + 1, nullptr, outv);
+  // the GMRES status (read by the caller before these loads were issued,
+  // uniform over the block): a stopped cycle writes nothing
+  if (done) return false;
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int e = tid + u * nthr;
@@ -1218,6 +1222,7 @@ __device__ void cgs_coefficients(const Geom& g, GmresState* st, int jc, const do
       st->cproj[i] = coef[i];
     }
   }
+  return true;
 }
 
 // Kernel A (j >= 1; the residual pass does step 0's).  win: w_{j-1}; u_j ->
@@ -1230,13 +1235,13 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
                                                    size_t vstride, int j, GmresState* st, cplx* __restrict__ Eo,
                                                    cplx* __restrict__ Go,
                                                    const double* __restrict__ pin) {
-  if (st->st.done) return;
+  const int done = st->st.done;  // tested once the loads of the prologue are in flight
   __shared__ double coef[kMaxRestart + 1];
   __shared__ double outv[2 * (kMaxRestart + 1) + 1];
   {
     const FinishPre pre = finish_prefetch(st, j - 1, false);
     double beta;
-    cgs_coefficients(g, st, j - 1, pin, gridDim.x, outv, coef, blockIdx.x == 0, beta);
+    if (!cgs_coefficients(g, st, j - 1, pin, gridDim.x, outv, coef, blockIdx.x == 0, beta, done)) return;
     // a new direction too small for the Gram identity to measure: close the
     // cycle on the columns so far (H(j, j-1) = 0) and restart, so that
     // convergence is judged on a freshly computed residual
