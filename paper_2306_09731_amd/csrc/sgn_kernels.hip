@@ -1384,13 +1384,17 @@ __global__ void __launch_bounds__(512) k_col_update_eg(Geom g, cplx* __restrict_
                                                         size_t vstride, const GmresState* __restrict__ st,
                                                         cplx* __restrict__ Eo, cplx* __restrict__ Go,
                                                         cplx* __restrict__ D, int spec) {
-  if (spec && st->st.done != 1) return;
   COL_SETUP(N)
   __shared__ double coef[kMaxRestart];
   const int tid = flat_tid();
-  const int k = st->st.jdone;
-  const int zero = st->st.zero;
-  for (int i = tid; i < k; i += block_threads()) coef[i] = st->y[i];
+  // the status, all the coefficient slots and sigma are loaded together (in
+  // bounds whatever the status); the speculative launch's test follows
+  const int done = st->st.done, k = st->st.jdone, zero = st->st.zero;
+  for (int i = tid; i < kMaxRestart; i += block_threads()) coef[i] = st->y[i];
+  cplx sg[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) sg[r] = valid ? SIG[sidx(g, t + r * TPF, col)] : make_cplx(0.0, 0.0);
+  if (spec && done != 1) return;
   __syncthreads();
   cplx v[E];
 #pragma unroll
@@ -1399,7 +1403,7 @@ __global__ void __launch_bounds__(512) k_col_update_eg(Geom g, cplx* __restrict_
     const size_t idx = sidx(g, p, col);
     cplx x = make_cplx(0.0, 0.0);
     if (valid) {
-      const cplx old = (D || !zero) ? SIG[idx] : make_cplx(0.0, 0.0);
+      const cplx old = (D || !zero) ? sg[r] : make_cplx(0.0, 0.0);
       if (!zero) {
         x = old;
         for (int i0 = 0; i0 < k; i0 += 4) {
