@@ -592,10 +592,12 @@ int graph_for(sgn_ctx* ctx, int kind, void* h, void* vx, void* vy, double dt, in
   const int timed = ctx->timed_kind;  // no timing events inside a graph
   ctx->timed_kind = -1;
   HIPCK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
+  ctx->g.status_first = 1;  // most of a budget's steps after convergence exit at once
   const int rc = enqueue_graph_step(ctx, kind, h, vx, vy, dt, budget);
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
   ctx->timed_kind = timed;
+  ctx->g.status_first = 0;
   if (rc || e != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
     return rc ? rc : fail(ctx, e, "hipStreamEndCapture");
@@ -720,6 +722,7 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   // several row pairs (powers of two)
   g.tile_blocks = 256;
   g.row_threads = 64;
+  g.status_first = 0;
   if (const char* tb = std::getenv("SGN_TILE_BLOCKS")) {
     const int v = std::atoi(tb);
     if (v >= 1 && v <= 4096 && (v & (v - 1)) == 0) g.tile_blocks = v;

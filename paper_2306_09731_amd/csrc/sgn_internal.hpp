@@ -26,6 +26,8 @@ struct Geom {
   int m;                   // GMRES restart length (sizes the back-substitution scratch)
   int tile_blocks;         // column passes: the widest tiles that still give this many blocks (256)
   int row_threads;         // row passes: row pairs per block for at least this many threads (64)
+  int status_first;        // 1: kernels test the GMRES status before their loads (captured graphs,
+                           // whose fixed budgets launch many steps after convergence); 0: after
 };
 
 // GMRES state kept in device memory.  Written only by the single "last

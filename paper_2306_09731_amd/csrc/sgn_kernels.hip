@@ -549,12 +549,13 @@ __global__ void __launch_bounds__(512) k_row_dx(Geom g, const real* __restrict__
 // MODE 1: residual with b = -div v:  B1 = -i kx F_x vx, B2 = F_x vy,
 //         P = B1 - A1, Q = B2 - A2 (and R1 = B1, R2 = B2 if need_b).
 // MODE 2: residual with an explicit b (passed in vx): B1 = F_x b, B2 = 0.
-template <int N, int MODE>
+template <int N, int MODE, bool SF = false>
 __global__ void __launch_bounds__(512) k_row_op(Geom g, const cplx* __restrict__ Es, const cplx* __restrict__ Gs,
                                                 const real* __restrict__ h, const real* __restrict__ vx,
                                                 const real* __restrict__ vy, cplx* __restrict__ P,
                                                 cplx* __restrict__ Q, cplx* __restrict__ R1, cplx* __restrict__ R2,
                                                 int need_b, int predicate, const GmresState* __restrict__ st) {
+  if (MODE == 0 && predicate && SF && st->st.done) return;
   ROW_SETUP(N)
   // every global load first, so their latencies overlap (the GMRES status
   // too: the loads are in bounds whatever it is)
@@ -620,10 +621,11 @@ __global__ void __launch_bounds__(512) k_row_op(Geom g, const cplx* __restrict__
 //   chain 2: d_y sigma -> / h -> F_x                      (= A2)
 // A1 = chain 0 + chain 1 and A2 are split into half spectra through LDS.
 // Block: (TPF, 3 * rows-pairs-per-block).
-template <int N>
+template <int N, bool SF>
 __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __restrict__ Es, const cplx* __restrict__ Gs,
                                                       const real* __restrict__ h, cplx* __restrict__ P,
                                                       cplx* __restrict__ Q, const GmresState* st) {
+  if (SF && st->st.done) return;
   constexpr int E = Row<N>::E;
   constexpr int TPF = Row<N>::TPF;
   constexpr int H = N / 2;
@@ -1074,11 +1076,12 @@ __global__ void __launch_bounds__(1024) k_col_basis2(Geom g, const cplx* __restr
 // Same result as k_col_precond_dot: chain 0 transforms P, chain 1 transforms
 // Q (times -i ky); w = (sum) / M is formed through LDS and each chain then
 // owns half of the thread's positions for the store and the projections.
-template <int N>
+template <int N, bool SF>
 __global__ void __launch_bounds__(1024) k_col_precond_dot2(Geom g, const cplx* __restrict__ P,
                                                            const cplx* __restrict__ Q, const cplx* __restrict__ V,
                                                            size_t vstride, int j, const GmresState* st,
                                                            cplx* __restrict__ W, double* partials) {
+  if (SF && st->st.done) return;
   COL2_SETUP(N)
   __shared__ double red[(kMaxRestart + 1) * 16];
   cplx v[E];
@@ -1230,11 +1233,12 @@ __device__ bool cgs_coefficients(const Geom& g, GmresState* st, int jc, const do
 // finishes Arnoldi step j - 1 from them (projection coefficients, H(j, j-1)
 // by the Gram identity, Givens update and test; block 0 stores the step)
 // and exits if the cycle stops there, so the last step costs no pass.
-template <int N>
+template <int N, bool SF>
 __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx* W, const cplx* __restrict__ V,
                                                    size_t vstride, int j, GmresState* st, cplx* __restrict__ Eo,
                                                    cplx* __restrict__ Go,
                                                    const double* __restrict__ pin) {
+  if (SF && st->st.done) return;
   const int done = st->st.done;  // tested once the loads of the prologue are in flight
   __shared__ double coef[kMaxRestart + 1];
   __shared__ double outv[2 * (kMaxRestart + 1) + 1];
@@ -1295,11 +1299,12 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
 // Kernel C.  P, Q: x-part outputs of B_j for u_j; W: u_j; writes V_j and
 // w_j (into Wn) and the block partials of the projections s and of the Gram
 // column.
-template <int N>
+template <int N, bool SF>
 __global__ void __launch_bounds__(1024) k_col_precond_new(Geom g, const cplx* __restrict__ P,
                                                           const cplx* __restrict__ Q, const cplx* __restrict__ W,
                                                           cplx* __restrict__ V, cplx* __restrict__ Wn, size_t vstride,
                                                           int j, const GmresState* st, double* partials) {
+  if (SF && st->st.done) return;
   COL2_SETUP(N)
   __shared__ double red[(2 * (kMaxRestart + 1) + 1) * 16];
   cplx v[E];
@@ -2147,6 +2152,7 @@ template <int N>
 static hipError_t row_op_n(const Geom& g, int mode, const cplx* E, const cplx* G, const real* h, const real* vx,
                            const real* vy, cplx* P, cplx* Q, cplx* R1, cplx* R2, int need_b, int pred,
                            const GmresState* st, hipStream_t s) {
+  if (mode == 0 && g.status_first) ROW_LAUNCH((k_row_op<N, 0, true>), g, E, G, h, vx, vy, P, Q, R1, R2, need_b, pred, st);
   if (mode == 0) ROW_LAUNCH((k_row_op<N, 0>), g, E, G, h, vx, vy, P, Q, R1, R2, need_b, pred, st);
   if (mode == 1) ROW_LAUNCH((k_row_op<N, 1>), g, E, G, h, vx, vy, P, Q, R1, R2, need_b, pred, st);
   ROW_LAUNCH((k_row_op<N, 2>), g, E, G, h, vx, vy, P, Q, R1, R2, need_b, pred, st);
@@ -2341,9 +2347,11 @@ static hipError_t row_matvec3_n(const Geom& g, const cplx* E, const cplx* G, con
     const int r = Chain<N>::rpb(g);
     const dim3 block(Row<N>::TPF, 3 * r);
     const size_t lb = (size_t)3 * r * Row<N>::LDS * sizeof(cplx);
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(k_row_matvec3<N>), lb);
+    // the status tested first in captured graphs, after the loads otherwise
+    auto* const kf = g.status_first ? &k_row_matvec3<N, true> : &k_row_matvec3<N, false>;
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(kf), lb);
     if (e != hipSuccess) return e;
-    launch(k_row_matvec3<N>, dim3((g.ny / 2) / r), block, lb, s, g, E, G, h, P, Q, st);
+    launch(kf, dim3((g.ny / 2) / r), block, lb, s, g, E, G, h, P, Q, st);
     return hipGetLastError();
   }
 }
@@ -2426,9 +2434,11 @@ static hipError_t col_precond_dot2_n(const Geom& g, const cplx* P, const cplx* Q
   const dim3 block(tc, Col<N>::TPF, 2);
   const int nb = (g.nh + tc - 1) / tc;
   const size_t lb = (size_t)2 * tc * N * sizeof(cplx);
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_precond_dot2<N>), lb);
+  // the status tested first in captured graphs, after the loads otherwise
+  auto* const kf = g.status_first ? &k_col_precond_dot2<N, true> : &k_col_precond_dot2<N, false>;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(kf), lb);
   if (e != hipSuccess) return e;
-  launch(k_col_precond_dot2<N>, dim3(nb), block, lb, s, g, P, Q, V, vs, j, st, W, partials);
+  launch(kf, dim3(nb), block, lb, s, g, P, Q, V, vs, j, st, W, partials);
   return hipGetLastError();
 }
 
@@ -2439,9 +2449,11 @@ static hipError_t col_proj_n(const Geom& g, const cplx* win, cplx* W, const cplx
   const dim3 block(tc, Col<N>::TPF, 2);
   const int nb = (g.nh + tc - 1) / tc;
   const size_t lb = with_finish_lds(g, (size_t)2 * tc * N * sizeof(cplx), true);
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_proj<N>), lb);
+  // the status tested first in captured graphs, after the loads otherwise
+  auto* const kf = g.status_first ? &k_col_proj<N, true> : &k_col_proj<N, false>;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(kf), lb);
   if (e != hipSuccess) return e;
-  launch(k_col_proj<N>, dim3(nb), block, lb, s, g, win, W, V, vs, j, st, Eo, Go, pin);
+  launch(kf, dim3(nb), block, lb, s, g, win, W, V, vs, j, st, Eo, Go, pin);
   return hipGetLastError();
 }
 
@@ -2452,9 +2464,11 @@ static hipError_t col_precond_new_n(const Geom& g, const cplx* P, const cplx* Q,
   const dim3 block(tc, Col<N>::TPF, 2);
   const int nb = (g.nh + tc - 1) / tc;
   const size_t lb = (size_t)2 * tc * N * sizeof(cplx);
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(k_col_precond_new<N>), lb);
+  // the status tested first in captured graphs, after the loads otherwise
+  auto* const kf = g.status_first ? &k_col_precond_new<N, true> : &k_col_precond_new<N, false>;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(kf), lb);
   if (e != hipSuccess) return e;
-  launch(k_col_precond_new<N>, dim3(nb), block, lb, s, g, P, Q, W, V, Z, vs, j, st, partials);
+  launch(kf, dim3(nb), block, lb, s, g, P, Q, W, V, Z, vs, j, st, partials);
   return hipGetLastError();
 }
 
