@@ -153,8 +153,13 @@ def test_fp32_rk4_line_soliton_128x64():
 def test_fp32_vs_fp64_gaussian_2048():
     """The 2048^2 Gaussian workload, 100 steps (t = 0.5), FP32 mode against the
     FP64 GPU path (tol 1e-10 there, 1e-6 in the FP32 mode): per-field error
-    reported, relative to max |h - 1|, max |v| and max |sigma|; the gates are
-    3x the values measured when the mode was introduced."""
+    reported.  Gates from the single-call bound of the mode, accumulated
+    linearly over the steps: each step may add 1e-5 of the field's scale
+    (the gate of one RK4 step against the oracle), so after n steps
+    n * 1e-5 relative to max |h - 1| for h and to max |sigma| for sigma;
+    v starts at rest, so its error is measured against the velocity scale
+    of the hump's long waves, sqrt(g / h_inf) max |h0 - h_inf| = 0.5
+    (u = c eta / h_inf with c = sqrt(g h_inf)), not against max |v|."""
     box, (h, vx, vy, s), w = workload("gaussian_2048x2048")
     n = 100
     res = {}
@@ -168,7 +173,35 @@ def test_fp32_vs_fp64_gaussian_2048():
     (a64, i64), (a32, i32) = res[sgn.SGN_FP64], res[sgn.SGN_FP32_MIXED]
     eh = rel(a32[0], a64[0], 1.0)
     ev = max(rel(a32[1], a64[1]), rel(a32[2], a64[2]))
+    ev_scale = max(np.abs(a32[1] - a64[1]).max(), np.abs(a32[2] - a64[2]).max()) / 0.5
     es = rel(a32[3], a64[3])
-    say(f"fp32 vs fp64 2048^2 Gaussian at t = {n * w['dt']}: h {eh:.2e} v {ev:.2e} sigma {es:.2e}; "
+    say(f"fp32 vs fp64 2048^2 Gaussian at t = {n * w['dt']}: h {eh:.2e} v {ev:.2e} (of the velocity "
+        f"scale 0.5: {ev_scale:.2e}) sigma {es:.2e}; "
         f"iters/solve fp32 {i32.total_iters / i32.solves:.2f} fp64 {i64.total_iters / i64.solves:.2f}")
-    assert eh < 2e-4 and ev < 3e-3 and es < 2e-4
+    gate = n * 1e-5
+    assert eh < gate and ev_scale < gate and es < gate
+
+
+@pytest.mark.parametrize("amp", [1e-2, 1e-4, 1e-5])
+def test_fp32_elliptic_solve_nearly_constant_depth(amp):
+    """h = 1 + amp * (smooth field): M^-1 L = I + O(amp), so the first Arnoldi
+    step leaves a new direction of relative size ~amp, where the Gram identity
+    cannot measure its norm in FP32 (cutoff 1e-6 of ||w||^2 in this mode).  The
+    solve must reach the mode's tolerance (1e-6) in the true preconditioned
+    residual that the FP64 oracle computes from the returned sigma, allowing
+    the FP32 rounding of the operator (4e-7 measured on M^-1 L): gate 2e-6."""
+    nx, ny = 64, 32
+    ctx, g = mk32(nx, ny, 1.0, 1.0)
+    rng = np.random.default_rng(17)
+    h = r32(1.0 + amp * random_smooth_field(rng, ny, nx, kmax=4))
+    b = r32(random_smooth_field(rng, ny, nx, kmax=6))
+    ref, rinfo = O.gmres(g, h, b, np.zeros_like(b), 1e-13, 20, 400)
+    sig = torch.zeros(ny, nx, dtype=torch.float32, device=DEV)
+    info = sgn.sgn_elliptic_solve(ctx, dev32(h), dev32(b), sig)
+    s = host(sig)
+    pr = O.apply_Minv(g, b - O.apply_L(g, h, s))
+    rel_pre = np.sqrt(np.sum(pr ** 2)) / np.sqrt(np.sum(O.apply_Minv(g, b) ** 2))
+    say(f"fp32 solve, depth 1 + {amp:g} f: iters {info.iters} (oracle {rinfo.iters}), restarts {info.restarts}, "
+        f"true preconditioned residual {rel_pre:.1e}, sigma {rel(s, ref):.1e}")
+    assert info.converged and rel_pre < 2e-6
+    assert rel(s, ref) < TOL32

@@ -399,6 +399,49 @@ def test_soliton_invariants_match_quadrature():
     assert abs(inv["px"] - p.c * inv["mass"]) < 1e-10
 
 
+def test_y_soliton_momentum_matches_quadrature():
+    """The y-momentum of Section 2.3 on a solitary wave travelling along y:
+    P_y = integral of h u_y equals adaptive quadrature of the analytic h u
+    and c times the mass (the travelling-wave flux relation of Section 2.4),
+    while P_x vanishes.  A momentum that used u_x, or v_y - h d_y sigma, or
+    that dropped the factor h, misses these values by O(1)."""
+    g, _ = soliton_grid(nx=4, ny=512, Lx=1.0, Ly=10.0)
+    box = Box(4, 512, 1.0, 10.0)
+    a = 0.5
+    p = soliton_params(a=a)
+    h, vx, vy, sig = line_soliton(box, a=a, along="y")
+    inv, _ = O.invariants(g, h, vx, vy, sig)
+    Px = 2 * np.pi * 1.0
+
+    def hu(y):
+        pr = soliton_profile(np.array([y]), p)
+        return pr["h"][0] * pr["u"][0]
+
+    lim = np.pi * 10.0
+    q, _ = integrate.quad(hu, -lim, lim, epsabs=1e-14, epsrel=1e-13, limit=400)
+    assert abs(inv["py"] - q * Px) < 1e-10 * abs(q * Px)
+    assert abs(inv["py"] - p.c * inv["mass"]) < 1e-10
+    assert abs(inv["px"]) < 1e-13
+
+
+def test_momentum_components_swap_under_transpose():
+    """On a square torus, exchanging x and y (and v_x with v_y) exchanges P_x
+    and P_y and leaves the scalars unchanged; the random state has P_x and
+    P_y of different size, so a P_y built from x-quantities fails."""
+    g = grid(32, 32, 1.5, 1.5, invariants_tol=1e-14)
+    rng = np.random.default_rng(13)
+    h, vx, vy, s0 = random_state(rng, Box(32, 32, 1.5, 1.5), amp_h=0.2, amp_v=0.3, kmax=4)
+    vx = vx + 0.2
+    vy = vy - 0.1
+    a, _ = O.invariants(g, h, vx, vy, s0)
+    b, _ = O.invariants(g, h.T.copy(), vy.T.copy(), vx.T.copy(), s0.T.copy())
+    assert abs(a["px"] - a["py"]) > 0.1 * abs(a["px"])
+    assert abs(a["py"] - b["px"]) < 1e-12 * abs(a["py"])
+    assert abs(a["px"] - b["py"]) < 1e-12 * abs(a["px"])
+    for key in ("mass", "energy", "curl_l2", "min_h", "max_h"):
+        assert abs(a[key] - b[key]) <= 1e-12 * max(1.0, abs(a[key])), key
+
+
 # --- whole steps -----------------------------------------------------------------
 
 
