@@ -87,7 +87,7 @@ typedef struct sgn_config {
   int32_t gmres_restart;   /* restart length m [20], 1..64 */
   double gmres_tol;        /* stop when ||M^-1 (b - L s)|| <= tol ||M^-1 b|| [1e-10] */
   int32_t gmres_max_iters; /* total Arnoldi steps per solve [10 * restart] */
-  int32_t batch;           /* 1 */
+  int32_t batch;           /* ensemble members of one context [1], 1..SGN_MAX_MEMBERS (see below) */
   double krasny;           /* Krasny threshold on |DFT| / (nx ny) [0 = off; the paper uses 1e-12] */
   double invariants_tol;   /* GMRES tolerance of the sigma solve in sgn_invariants [1e-13] */
   int32_t dealias;         /* [0] 1: after every RK4 step also zero the modes with 3 |m_x| > nx or
@@ -98,6 +98,22 @@ typedef struct sgn_config {
   int32_t guess;           /* SGN_GUESS_PREVIOUS [default] or SGN_GUESS_STAGE_INCREMENT; only the
                               starting iterate of GMRES depends on it, not the tolerance met */
 } sgn_config;
+
+/* Ensembles in one launch.  A context with batch = B > 1 holds B independent
+ * members of the same configuration (grid, box, g, h_inf, precision, GMRES
+ * parameters, filter, guess) and runs every kernel of a call once for all of
+ * them (member index = blockIdx.z).  Its fields are B consecutive fields,
+ * [B][ny][nx]; its workspace is B member workspaces; each member has its own
+ * GMRES state, so members converge, restart and stop independently (a member
+ * that has converged skips the launches of the others' further iterations).
+ * The info / out arguments of sgn_elliptic_solve, sgn_rhs, sgn_rk4_step and
+ * sgn_invariants then point to arrays of B entries, one per member; the
+ * status returned is the first error of any member (NOT_CONVERGED if any
+ * member did not converge).  Each member's results are bitwise those of a
+ * context with batch = 1 on that member's fields.  Not available with
+ * batch > 1: the captured step, the learned guess, the refined solve, the
+ * autotuner and the host-thread ensemble calls (SGN_ERR_UNSUPPORTED). */
+#define SGN_MAX_MEMBERS 64
 
 typedef struct sgn_ctx sgn_ctx;
 
@@ -350,7 +366,8 @@ int sgn_kernel_timing(sgn_ctx* ctx, int32_t kind, int32_t enable);
  * classes of the default (three-kernel) Arnoldi step. */
 int sgn_kernel_time(sgn_ctx* ctx, int32_t kind, int64_t* launches, double* total_ms, double* algo_bytes);
 
-/* Human-readable name of a status code, and the last error of a context. */
+/* Human-readable name of a status code, and the last error of a context
+ * (ctx = NULL: of this thread's last failed call that takes no context). */
 const char* sgn_status_string(int status);
 const char* sgn_last_error(const sgn_ctx* ctx);
 

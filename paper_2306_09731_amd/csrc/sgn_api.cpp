@@ -21,6 +21,7 @@
 #include "sgn_cnn_internal.hpp"
 #include "sgn_internal.hpp"
 #include "sgn_launch.hpp"
+#include "sgn_host.hpp"
 
 typedef double2 cplx;
 
@@ -30,6 +31,7 @@ struct sgn_ctx {
   hipStream_t stream;
   char* ws;
   size_t ws_bytes;
+  size_t ws_stride;  // bytes between ensemble members' workspaces
   sgn::Geom g;
   size_t vstride;      // complex entries (of the working precision) per field
   size_t field_bytes;  // bytes per field (256-byte multiple)
@@ -40,7 +42,7 @@ struct sgn_ctx {
   void *V, *Z, *W, *E, *G, *P, *Q, *R1, *R2, *SIG;
   char* D;  // guess 1: four per-stage sigma increments (2D spectra), else null
   void *hs, *vxs, *vys, *acc_h, *acc_vx, *acc_vy;
-  sgn::GmresStatus* hstat;  // pinned host copy of the device status
+  sgn::GmresStatus* hstat;  // pinned host copy of the device status (one per ensemble member)
   hipEvent_t stat_ev = nullptr;  // recorded after the status copy of a speculative batch
   int batch_margin = 0;  // Arnoldi steps enqueued beyond the previous solve's count
   int last_iters[5];  // iterations of the previous solve per slot (RK stages 0-3, other calls 4)
@@ -79,8 +81,10 @@ struct sgn_ctx {
 };
 
 namespace {
-
 bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+}  // namespace
+
+namespace sgn {
 
 int check_config(const sgn_config* c) {
   if (!c) return SGN_ERR_INVALID_ARG;
@@ -95,10 +99,59 @@ int check_config(const sgn_config* c) {
   if (c->gmres_restart < 1) return SGN_ERR_INVALID_ARG;
   if (c->gmres_restart > sgn::kMaxRestart) return SGN_ERR_UNSUPPORTED;
   if (c->precision != SGN_FP64 && c->precision != SGN_FP32_MIXED) return SGN_ERR_UNSUPPORTED;
-  if (c->batch != 1) return SGN_ERR_UNSUPPORTED;
+  if (c->batch < 1 || c->batch > SGN_MAX_MEMBERS) return SGN_ERR_UNSUPPORTED;
   if (!pow2_in(c->nx, 8, 4096) || !pow2_in(c->ny, 8, 4096)) return SGN_ERR_UNSUPPORTED;
   return SGN_OK;
 }
+
+// Grid geometry, spectral constants and launch shapes of a configuration (the
+// table pointers are set by the caller, which owns the tables' memory).
+void geom_init(const sgn_config& c, Geom& g) {
+  g = Geom{};
+  g.nx = c.nx;
+  g.ny = c.ny;
+  g.nh = c.nx / 2;
+  g.inv_Lx = 1.0 / c.Lx;
+  g.inv_Ly = 1.0 / c.Ly;
+  g.inv_nx = 1.0 / c.nx;
+  g.inv_ny = 1.0 / c.ny;
+  g.inv_n = 1.0 / ((double)c.nx * c.ny);
+  g.g = c.g;
+  g.h_inf = c.h_inf;
+  g.m0 = 3.0 / (c.h_inf * c.h_inf * c.h_inf);
+  g.m1 = 1.0 / c.h_inf;
+  g.dA = (2.0 * M_PI * c.Lx / c.nx) * (2.0 * M_PI * c.Ly / c.ny);
+  g.fp32 = c.precision == SGN_FP32_MIXED;
+  g.m = c.gmres_restart;
+  // launch shapes (tuning and testing switches; sgn_autotune searches them):
+  // SGN_TILE_BLOCKS, the number of blocks below which column tiles stop
+  // widening, and SGN_ROW_THREADS, the threads a row block reaches by taking
+  // several row pairs (powers of two)
+  g.tile_blocks = 256;
+  g.row_threads = 64;
+  g.status_first = 0;
+  g.members = 1;
+  g.ws_lo = 0;
+  g.ws_span = g.ws_stride = g.f_stride = 0;
+  if (const char* tb = std::getenv("SGN_TILE_BLOCKS")) {
+    const int v = std::atoi(tb);
+    if (v >= 1 && v <= 4096 && (v & (v - 1)) == 0) g.tile_blocks = v;
+  }
+  if (const char* rt = std::getenv("SGN_ROW_THREADS")) {
+    const int v = std::atoi(rt);
+    if (v >= 64 && v <= 512 && (v & (v - 1)) == 0) g.row_threads = v;
+  }
+}
+
+// Message of the last failed call that has no context (sgn_last_error(NULL)).
+static thread_local char t_global_err[256];
+void set_global_error(const char* msg) { snprintf(t_global_err, sizeof t_global_err, "%s", msg); }
+const char* global_error() { return t_global_err; }
+
+}  // namespace sgn
+
+namespace {
+using sgn::check_config;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -115,7 +168,9 @@ bool step_filter_on(const sgn_config& c) { return c.krasny > 0.0 || c.dealias !=
 int step_filter_op(const sgn_config& c) { return c.dealias ? 2 : 1; }
 
 struct Layout {
-  size_t tw, st, partials, partials2, fields, total;
+  size_t tw, st, partials, partials2, fields;
+  size_t member;  // bytes of one member's workspace (256-byte multiple)
+  size_t total;   // batch * member
   size_t field_bytes;
   int nfields;
 };
@@ -145,7 +200,8 @@ Layout layout(const sgn_config* c) {
   // the checkpoint of a captured call (4), and with the stage-increment guess D_0..D_3
   L.nfields = c->gmres_restart + 1 + 15 + 4 + (c->guess == SGN_GUESS_STAGE_INCREMENT ? 4 : 0);
   off += (size_t)L.nfields * L.field_bytes;
-  L.total = off;
+  L.member = align_up(off);
+  L.total = L.member * (size_t)c->batch;
   return L;
 }
 
@@ -234,17 +290,37 @@ struct KernelTimer {
     kt_.stop();                        \
   } while (0)
 
+int members(const sgn_ctx* ctx) { return ctx->cfg.batch; }
+
+// The device status of every member into hstat (one strided copy).
+int copy_status(sgn_ctx* ctx) {
+  if (members(ctx) == 1)
+    HIPCK(hipMemcpyAsync(ctx->hstat, &ctx->st->st, sizeof(sgn::GmresStatus), hipMemcpyDeviceToHost, ctx->stream));
+  else
+    HIPCK(hipMemcpy2DAsync(ctx->hstat, sizeof(sgn::GmresStatus), &ctx->st->st, ctx->ws_stride,
+                           sizeof(sgn::GmresStatus), members(ctx), hipMemcpyDeviceToHost, ctx->stream));
+  return SGN_OK;
+}
+
 int read_status(sgn_ctx* ctx) {
-  HIPCK(hipMemcpyAsync(ctx->hstat, &ctx->st->st, sizeof(sgn::GmresStatus), hipMemcpyDeviceToHost, ctx->stream));
+  int rc = copy_status(ctx);
+  if (rc) return rc;
   HIPCK(hipStreamSynchronize(ctx->stream));
   return SGN_OK;
 }
 
-int set_tol(sgn_ctx* ctx, double tol_requested) {
-  const double tol = effective_tol(ctx->cfg, tol_requested);
-  HIPCK(hipMemcpyAsync(&ctx->st->tol, &tol, sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-  HIPCK(hipStreamSynchronize(ctx->stream));  // tol is a host local
+// A scalar of every member's GMRES state set from the host.
+template <class T>
+int set_state_scalar(sgn_ctx* ctx, T* field0, T v) {
+  for (int k = 0; k < members(ctx); ++k)
+    HIPCK(hipMemcpyAsync(reinterpret_cast<char*>(field0) + (size_t)k * ctx->ws_stride, &v, sizeof v,
+                         hipMemcpyHostToDevice, ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));  // v is a host local
   return SGN_OK;
+}
+
+int set_tol(sgn_ctx* ctx, double tol_requested) {
+  return set_state_scalar(ctx, &ctx->st->tol, effective_tol(ctx->cfg, tol_requested));
 }
 
 // sigma (physical) -> E = F_x sigma, SIG = F sigma, G = F_x d_y sigma
@@ -258,13 +334,17 @@ int check_state(sgn_ctx* ctx, const void* a, const void* b, const void* c) {
   HIPCK(sgn::launch_field_stats(ctx->g, a, b, c, (size_t)ctx->g.nx * ctx->g.ny, ctx->st, ctx->partials, ctx->stream));
   int rc = read_status(ctx);
   if (rc) return rc;
-  if (ctx->hstat->stat_nonfinite) {
-    ctx->err = "non-finite value in the input";
-    return SGN_ERR_NONFINITE;
-  }
-  if (!(ctx->hstat->stat_minh > 0.0)) {
-    ctx->err = "min h <= 0";
-    return SGN_ERR_CAVITATION;
+  for (int k = 0; k < members(ctx); ++k) {
+    if (ctx->hstat[k].stat_nonfinite) {
+      ctx->err = "non-finite value in the input";
+      if (members(ctx) > 1) ctx->err += " of member " + std::to_string(k);
+      return SGN_ERR_NONFINITE;
+    }
+    if (!(ctx->hstat[k].stat_minh > 0.0)) {
+      ctx->err = "min h <= 0";
+      if (members(ctx) > 1) ctx->err += " in member " + std::to_string(k);
+      return SGN_ERR_CAVITATION;
+    }
   }
   return SGN_OK;
 }
@@ -278,11 +358,14 @@ struct SolveResult {
 // ---- kernel sequences shared by the host-driven loop and the captured step
 
 // Start of a GMRES cycle: residual (and b, if need_b) of the current sigma.
+// flags: 1 a new solve; 4 | (round << 8) an ensemble restart in that cycle
+// round (only the members that restart run it).
 int enqueue_residual(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void* vy, int need_b, int flags) {
   const sgn::Geom& g = ctx->g;
   hipStream_t s = ctx->stream;
-  HIPCK(sgn::launch_row_op(g, mode, ctx->E, ctx->G, h, vx, vy, ctx->P, ctx->Q, ctx->R1, ctx->R2, need_b, 0, ctx->st,
-                           s));
+  const int rowpred = (flags & 4) ? 2 : 0;
+  HIPCK(sgn::launch_row_op(g, mode, ctx->E, ctx->G, h, vx, vy, ctx->P, ctx->Q, ctx->R1, ctx->R2, need_b, rowpred,
+                           ctx->st, s));
   // an explicit b (mode 2) has b_hat = F_y(R1) only.  In the three-kernel
   // schedule the residual pass also produces E, G of the residual (the work
   // of kernel A at step 0); its last block sets beta
@@ -387,6 +470,10 @@ int enqueue_step_filter(sgn_ctx* ctx, void* h, void* vx, void* vy) {
   return SGN_OK;
 }
 
+double cycle_timed_bytes(const sgn_ctx* ctx, int jd);
+int run_solve_members(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void* vy, SolveResult* res,
+                      int slot, void* D);
+
 // Restarted GMRES for L_h sigma = b with the warm start held in (SIG, E, G).
 // mode 1: b = -div v from (vx, vy); mode 2: b given (passed as vx).
 // On return (SIG, E, G) hold the solution.
@@ -398,6 +485,7 @@ int enqueue_step_filter(sgn_ctx* ctx, void* h, void* vx, void* vy) {
 // the status.  res->post_done tells the caller that they did run.
 int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void* vy, SolveResult* res,
               int slot = 4, void* D = nullptr, const std::function<int(bool)>* post = nullptr) {
+  if (members(ctx) > 1) return run_solve_members(ctx, mode, h, vx, vy, res, slot, D);
   const sgn::Geom& g = ctx->g;
   hipStream_t s = ctx->stream;
   const int m = ctx->cfg.gmres_restart;
@@ -414,7 +502,6 @@ int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void*
     need_b = 0;
     flags = 0;
     int j = 0;
-    const bool fused = ctx->arnoldi == 2;
     // speculative batch: as many steps as this slot's previous solve needed
     // (plus batch_margin; 0 measured fastest at every size tried)
     int batch = (res->restarts == 0 ? ctx->last_iters[slot] : m) + ctx->batch_margin;
@@ -446,31 +533,8 @@ int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void*
     }
     const sgn::GmresStatus& st = *ctx->hstat;
     if (ctx->timed_kind >= 0) {
-      // algorithmic bytes of this cycle's launches that did work (fields of
-      // fb bytes read or written once), unless the cycle converged at its
-      // start.  Three-kernel step j: A (j+4), B 5, C (j+5), with A's pass for
-      // 1 <= j < jdone (A_jdone stops the cycle before its pass; step 0's A is
-      // part of the residual pass) and B's transforms for j < jdone.
-      // Four-kernel step j:
-      // basis (j+4), x part 5, projections (j+4), update (j+3).
-      const double fb = (g.fp32 ? 4.0 : 8.0) * (double)g.nx * (double)g.ny;
-      const int jd = st.jdone;
-      const bool ran = !(st.done == 1 && jd == 0 && st.total_iters == total);
-      if (ran) {
-        if (ctx->timed_kind == SGN_KERNEL_ROW_MATVEC) ctx->timed_bytes += 5.0 * jd * fb;
-        if (fused) {
-          if (ctx->timed_kind == SGN_KERNEL_COL_PRECOND_DOT)
-            for (int jj = 0; jj < jd; ++jj) ctx->timed_bytes += (jj + 5) * fb;
-          if (ctx->timed_kind == SGN_KERNEL_COL_BASIS)
-            for (int jj = 1; jj < jd; ++jj) ctx->timed_bytes += (jj + 4) * fb;
-        } else {
-          for (int jj = 0; jj < jd; ++jj) {
-            if (ctx->timed_kind == SGN_KERNEL_COL_BASIS || ctx->timed_kind == SGN_KERNEL_COL_PRECOND_DOT)
-              ctx->timed_bytes += (jj + 4) * fb;
-            if (ctx->timed_kind == SGN_KERNEL_GS_UPDATE) ctx->timed_bytes += (jj + 3) * fb;
-          }
-        }
-      }
+      const bool ran = !(st.done == 1 && st.jdone == 0 && st.total_iters == total);
+      if (ran) ctx->timed_bytes += cycle_timed_bytes(ctx, st.jdone);
     }
     total = st.total_iters;
     // sigma_hat += V y, and E, G of the new sigma (already enqueued when a
@@ -487,6 +551,114 @@ int run_solve(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void*
   }
   res->iters = total;
   ctx->last_iters[slot] = total < m ? total : m;
+  return SGN_OK;
+}
+
+// Algorithmic bytes of one cycle's launches that did work (fields of fb
+// bytes read or written once) for the timed kernel class: a cycle of jd
+// Arnoldi steps that ran (not converged at its start).  Three-kernel step j:
+// A (j+4), B 5, C (j+5), with A's pass for 1 <= j < jd (A_jd stops the cycle
+// before its pass; step 0's A is part of the residual pass) and B's
+// transforms for j < jd.  Four-kernel step j: basis (j+4), x part 5,
+// projections (j+4), update (j+3).
+double cycle_timed_bytes(const sgn_ctx* ctx, int jd) {
+  const sgn::Geom& g = ctx->g;
+  const double fb = (g.fp32 ? 4.0 : 8.0) * (double)g.nx * (double)g.ny;
+  double b = 0.0;
+  if (ctx->timed_kind == SGN_KERNEL_ROW_MATVEC) b += 5.0 * jd * fb;
+  if (ctx->arnoldi == 2) {
+    if (ctx->timed_kind == SGN_KERNEL_COL_PRECOND_DOT)
+      for (int jj = 0; jj < jd; ++jj) b += (jj + 5) * fb;
+    if (ctx->timed_kind == SGN_KERNEL_COL_BASIS)
+      for (int jj = 1; jj < jd; ++jj) b += (jj + 4) * fb;
+  } else {
+    for (int jj = 0; jj < jd; ++jj) {
+      if (ctx->timed_kind == SGN_KERNEL_COL_BASIS || ctx->timed_kind == SGN_KERNEL_COL_PRECOND_DOT)
+        b += (jj + 4) * fb;
+      if (ctx->timed_kind == SGN_KERNEL_GS_UPDATE) b += (jj + 3) * fb;
+    }
+  }
+  return b;
+}
+
+// run_solve for a context of several ensemble members: every launch covers
+// all members, each member's kernels exit once its own status says done.
+// Cycle round 0 starts every member; a later round restarts only the members
+// whose cycle filled up (their residual passes test that on the device), and
+// the solution update of a round runs only for the members that ran a cycle
+// in it.  The host reads all members' status words once per batch of
+// Arnoldi steps and goes on until every member has stopped.
+int run_solve_members(sgn_ctx* ctx, int mode, const void* h, const void* vx, const void* vy, SolveResult* res,
+                      int slot, void* D) {
+  const sgn::Geom& g = ctx->g;
+  hipStream_t s = ctx->stream;
+  const int M = members(ctx);
+  const int m = ctx->cfg.gmres_restart;
+  const int maxit = ctx->cfg.gmres_max_iters;
+  std::vector<int> before(M, 0);
+  for (int k = 0; k < M; ++k) res[k] = SolveResult{};
+  int most = 0;
+  for (int round = 0;; ++round) {
+    int rc0 = enqueue_residual(ctx, mode, h, vx, vy, round == 0 ? 1 : 0, round == 0 ? 1 : (4 | (round << 8)));
+    if (rc0) return rc0;
+    int j = 0;
+    int batch = (round == 0 ? ctx->last_iters[slot] : m) + ctx->batch_margin;
+    if (batch < 1) batch = 1;
+    for (;;) {
+      int nrun = batch;
+      if (nrun > m - j) nrun = m - j;
+      if (nrun <= 0) break;  // the device stops every member at its cycle or iteration cap
+      for (int it = j; it < j + nrun; ++it) {
+        int rc1 = enqueue_arnoldi(ctx, h, it);
+        if (rc1) return rc1;
+      }
+      j += nrun;
+      int rc = read_status(ctx);
+      if (rc) return rc;
+      bool all = true;
+      for (int k = 0; k < M; ++k) all = all && ctx->hstat[k].done != 0;
+      if (all) break;
+      batch = 2;
+    }
+    HIPCK(sgn::launch_col_update_eg(g, ctx->SIG, ctx->V, ctx->vstride, ctx->st, ctx->E, ctx->G, D,
+                                    2 | (round << 8), s));
+    bool again = false;
+    for (int k = 0; k < M; ++k) {
+      const sgn::GmresStatus& st = ctx->hstat[k];
+      if (st.cyc != round) continue;  // stopped in an earlier round
+      if (ctx->timed_kind >= 0) {
+        const bool ran = !(st.done == 1 && st.jdone == 0 && st.total_iters == before[k]);
+        if (ran) ctx->timed_bytes += cycle_timed_bytes(ctx, st.jdone);
+      }
+      before[k] = st.total_iters;
+      res[k].iters = st.total_iters;
+      res[k].rel_resid = st.beta0 > 0 ? st.resid / st.beta0 : 0.0;
+      res[k].converged = st.done == 1;
+      if (st.done == 2 && st.total_iters < maxit) {
+        res[k].restarts += 1;
+        again = true;
+      }
+      most = std::max(most, std::min(st.total_iters, m));
+    }
+    if (!again) break;
+  }
+  ctx->last_iters[slot] = most;
+  return SGN_OK;
+}
+
+bool all_converged(const std::vector<SolveResult>& r) {
+  for (const SolveResult& x : r)
+    if (!x.converged) return false;
+  return true;
+}
+
+// The stage-increment guess starts every call from zero increments.
+int clear_guess(sgn_ctx* ctx) {
+  if (!ctx->D) return SGN_OK;
+  if (members(ctx) == 1)
+    HIPCK(hipMemsetAsync(ctx->D, 0, 4 * ctx->field_bytes, ctx->stream));
+  else
+    HIPCK(hipMemset2DAsync(ctx->D, ctx->ws_stride, 0, 4 * ctx->field_bytes, members(ctx), ctx->stream));
   return SGN_OK;
 }
 
@@ -611,11 +783,7 @@ int graph_for(sgn_ctx* ctx, int kind, void* h, void* vx, void* vy, double dt, in
   return SGN_OK;
 }
 
-int set_maxit(sgn_ctx* ctx, int32_t v) {
-  HIPCK(hipMemcpyAsync(&ctx->st->maxit, &v, sizeof v, hipMemcpyHostToDevice, ctx->stream));
-  HIPCK(hipStreamSynchronize(ctx->stream));  // v is a host local
-  return SGN_OK;
-}
+int set_maxit(sgn_ctx* ctx, int32_t v) { return set_state_scalar(ctx, &ctx->st->maxit, v); }
 
 // Runs a captured call on the context's private stream, ordered after the
 // work already on the caller's stream and before the work enqueued there
@@ -701,36 +869,7 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   if (ak && std::strcmp(ak, "serial") == 0) ctx->arnoldi = 0;
   const int nx = cfg->nx, ny = cfg->ny;
   sgn::Geom& g = ctx->g;
-  g.nx = nx;
-  g.ny = ny;
-  g.nh = nx / 2;
-  g.inv_Lx = 1.0 / cfg->Lx;
-  g.inv_Ly = 1.0 / cfg->Ly;
-  g.inv_nx = 1.0 / nx;
-  g.inv_ny = 1.0 / ny;
-  g.inv_n = 1.0 / ((double)nx * ny);
-  g.g = cfg->g;
-  g.h_inf = cfg->h_inf;
-  g.m0 = 3.0 / (cfg->h_inf * cfg->h_inf * cfg->h_inf);
-  g.m1 = 1.0 / cfg->h_inf;
-  g.dA = (2.0 * M_PI * cfg->Lx / nx) * (2.0 * M_PI * cfg->Ly / ny);
-  g.fp32 = cfg->precision == SGN_FP32_MIXED;
-  g.m = cfg->gmres_restart;
-  // launch shapes (tuning and testing switches; sgn_autotune searches them):
-  // SGN_TILE_BLOCKS, the number of blocks below which column tiles stop
-  // widening, and SGN_ROW_THREADS, the threads a row block reaches by taking
-  // several row pairs (powers of two)
-  g.tile_blocks = 256;
-  g.row_threads = 64;
-  g.status_first = 0;
-  if (const char* tb = std::getenv("SGN_TILE_BLOCKS")) {
-    const int v = std::atoi(tb);
-    if (v >= 1 && v <= 4096 && (v & (v - 1)) == 0) g.tile_blocks = v;
-  }
-  if (const char* rt = std::getenv("SGN_ROW_THREADS")) {
-    const int v = std::atoi(rt);
-    if (v >= 64 && v <= 512 && (v & (v - 1)) == 0) g.row_threads = v;
-  }
+  sgn::geom_init(*cfg, g);
   // SGN_BATCH_MARGIN (0..4): Arnoldi steps enqueued beyond the previous
   // solve's count before the host reads the status
   if (const char* bm = std::getenv("SGN_BATCH_MARGIN")) {
@@ -739,6 +878,12 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   }
   if (!sgn::chained_ok(g)) ctx->arnoldi = 0;
   char* base = ctx->ws;
+  const int M = cfg->batch;
+  g.members = M;
+  g.ws_lo = reinterpret_cast<uintptr_t>(base);
+  g.ws_span = g.ws_stride = L.member;
+  g.f_stride = (size_t)nx * ny * (g.fp32 ? sizeof(float) : sizeof(double));
+  ctx->ws_stride = L.member;
   cplx* tw = reinterpret_cast<cplx*>(base + L.tw);
   float2* tw32 = reinterpret_cast<float2*>(base + L.tw + align_up((size_t)(nx + ny) * sizeof(double2)));
   g.twx = tw;
@@ -804,10 +949,11 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   hipError_t e = hipMemcpyAsync(tw, htw.data(), htw.size() * sizeof(cplx), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(tw32, htw32.data(), htw32.size() * sizeof(float2), hipMemcpyHostToDevice, ctx->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(ctx->st, &hst, sizeof hst, hipMemcpyHostToDevice, ctx->stream);
+  for (int k = 0; k < M && e == hipSuccess; ++k)
+    e = hipMemcpyAsync(base + (size_t)k * L.member + L.st, &hst, sizeof hst, hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ctx->hstat), sizeof(sgn::GmresStatus), 0);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&ctx->hstat), (size_t)M * sizeof(sgn::GmresStatus), 0);
   if (e != hipSuccess) {
     delete ctx;
     return SGN_ERR_HIP;
@@ -837,8 +983,8 @@ int sgn_elliptic_solve(sgn_ctx* ctx, const void* h, const void* b, void* sigma, 
   if (rc) return rc;
   rc = load_sigma(ctx, sigma);
   if (rc) return rc;
-  SolveResult res;
-  rc = run_solve(ctx, 2, h, b, nullptr, &res);
+  std::vector<SolveResult> res(members(ctx));
+  rc = run_solve(ctx, 2, h, b, nullptr, res.data());
   if (rc) return rc;
   HIPCK(sgn::launch_row_c2r(ctx->g, ctx->E, sigma, ctx->stream));
   if (info) {
@@ -849,16 +995,18 @@ int sgn_elliptic_solve(sgn_ctx* ctx, const void* h, const void* b, void* sigma, 
                                 nullptr, nullptr, ctx->stream));
     rc = read_status(ctx);
     if (rc) return rc;
-    info->iters = res.iters;
-    info->restarts = res.restarts;
-    info->converged = res.converged;
-    info->rel_resid_precond = res.rel_resid;
-    const double bn = ctx->hstat->bnorm;
-    info->rel_resid_true = bn > 0 ? std::sqrt(ctx->hstat->true_resid2) / bn : 0.0;
+    for (int k = 0; k < members(ctx); ++k) {
+      info[k].iters = res[k].iters;
+      info[k].restarts = res[k].restarts;
+      info[k].converged = res[k].converged;
+      info[k].rel_resid_precond = res[k].rel_resid;
+      const double bn = ctx->hstat[k].bnorm;
+      info[k].rel_resid_true = bn > 0 ? std::sqrt(ctx->hstat[k].true_resid2) / bn : 0.0;
+    }
   } else {
     HIPCK(hipStreamSynchronize(ctx->stream));
   }
-  return res.converged ? SGN_OK : SGN_ERR_NOT_CONVERGED;
+  return all_converged(res) ? SGN_OK : SGN_ERR_NOT_CONVERGED;
 }
 
 int sgn_elliptic_solve_refined(sgn_ctx* c64, sgn_ctx* c32, const double* h, const double* b, double* sigma,
@@ -867,7 +1015,8 @@ int sgn_elliptic_solve_refined(sgn_ctx* c64, sgn_ctx* c32, const double* h, cons
       !std::isfinite(tol) || max_rounds < 1)
     return SGN_ERR_INVALID_ARG;
   const sgn_config &a = c64->cfg, &q = c32->cfg;
-  if (a.precision != SGN_FP64 || q.precision != SGN_FP32_MIXED) return SGN_ERR_UNSUPPORTED;
+  if (a.precision != SGN_FP64 || q.precision != SGN_FP32_MIXED || a.batch != 1 || q.batch != 1)
+    return SGN_ERR_UNSUPPORTED;
   if (a.nx != q.nx || a.ny != q.ny || a.Lx != q.Lx || a.Ly != q.Ly || a.g != q.g || a.h_inf != q.h_inf ||
       c64->device != c32->device)
     return SGN_ERR_INVALID_ARG;
@@ -927,8 +1076,8 @@ int sgn_rhs(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, void* s
   if (rc) return rc;
   rc = load_sigma(ctx, sigma);
   if (rc) return rc;
-  SolveResult res;
-  rc = run_solve(ctx, 1, h, vx, vy, &res);
+  std::vector<SolveResult> res(members(ctx));
+  rc = run_solve(ctx, 1, h, vx, vy, res.data());
   if (rc) return rc;
   sgn::RkStage rk{0, 0, 0.0, 0.0, 0.0};
   void* dhp = ctx->P;
@@ -941,13 +1090,15 @@ int sgn_rhs(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, void* s
   HIPCK(sgn::launch_row_c2r(ctx->g, ctx->E, sigma, ctx->stream));
   HIPCK(hipStreamSynchronize(ctx->stream));
   if (info) {
-    info->iters = res.iters;
-    info->restarts = res.restarts;
-    info->converged = res.converged;
-    info->rel_resid_precond = res.rel_resid;
-    info->rel_resid_true = -1.0;
+    for (int k = 0; k < members(ctx); ++k) {
+      info[k].iters = res[k].iters;
+      info[k].restarts = res[k].restarts;
+      info[k].converged = res[k].converged;
+      info[k].rel_resid_precond = res[k].rel_resid;
+      info[k].rel_resid_true = -1.0;
+    }
   }
-  return res.converged ? SGN_OK : SGN_ERR_NOT_CONVERGED;
+  return all_converged(res) ? SGN_OK : SGN_ERR_NOT_CONVERGED;
 }
 
 int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double dt, int32_t nsteps,
@@ -960,11 +1111,14 @@ int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double 
   if (rc) return rc;
   const sgn::Geom& g = ctx->g;
   hipStream_t s = ctx->stream;
-  int64_t total = 0;
-  int maxper = 0, solves = 0, unconv = 0;
+  const int M = members(ctx);
+  std::vector<int64_t> total(M, 0);
+  std::vector<int> maxper(M, 0), unconv(M, 0);
+  int solves = 0;
   // stage-increment guess: the increments start at zero in every call, so the
   // first step starts each stage from the previous stage's sigma
-  if (ctx->D) HIPCK(hipMemsetAsync(ctx->D, 0, 4 * ctx->field_bytes, s));
+  if ((rc = clear_guess(ctx))) return rc;
+  std::vector<SolveResult> res(M);
   for (int step = 0; step < nsteps; ++step) {
     for (int stage = 0; stage < 4; ++stage) {
       const void* ih = stage == 0 ? h : ctx->hs;
@@ -974,20 +1128,22 @@ int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double 
       if (Dst && step > 0) HIPCK(sgn::launch_col_guess_eg(g, ctx->SIG, Dst, ctx->E, ctx->G, s));
       float* slot = nullptr;
       if ((ctx->learn_net || ctx->learn_rec) && (rc = learned_start(ctx, ih, ivx, ivy, &slot))) return rc;
-      SolveResult res;
       // the stage's fluxes follow each batch of Arnoldi steps speculatively
-      // (not with the learned guess, whose finish comes between)
+      // (not with the learned guess, whose finish comes between, nor for
+      // ensemble members, which finish their solves at different steps)
       const std::function<int(bool)> post = [&](bool spec) {
         return enqueue_stage_flux(ctx, stage, dt, h, vx, vy, ih, ivx, ivy, spec);
       };
-      rc = run_solve(ctx, 1, ih, ivx, ivy, &res, stage, Dst, slot ? nullptr : &post);
+      rc = run_solve(ctx, 1, ih, ivx, ivy, res.data(), stage, Dst, slot ? nullptr : &post);
       if (rc) return rc;
       if (slot && (rc = learned_finish(ctx, slot))) return rc;
-      total += res.iters;
-      if (res.iters > maxper) maxper = res.iters;
+      for (int k = 0; k < M; ++k) {
+        total[k] += res[k].iters;
+        maxper[k] = std::max(maxper[k], res[k].iters);
+        unconv[k] |= !res[k].converged;
+      }
       solves += 1;
-      unconv |= !res.converged;
-      if (!res.post_done && (rc = enqueue_stage_flux(ctx, stage, dt, h, vx, vy, ih, ivx, ivy))) return rc;
+      if (!res[0].post_done && (rc = enqueue_stage_flux(ctx, stage, dt, h, vx, vy, ih, ivx, ivy))) return rc;
     }
     rc = enqueue_step_filter(ctx, h, vx, vy);
     if (rc) return rc;
@@ -996,16 +1152,22 @@ int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double 
   HIPCK(sgn::launch_field_stats(g, h, vx, vy, (size_t)g.nx * g.ny, ctx->st, ctx->partials, s));
   rc = read_status(ctx);
   if (rc) return rc;
-  if (info) {
-    info->total_iters = total;
-    info->max_iters_per_solve = maxper;
-    info->solves = solves;
-    info->min_h = ctx->hstat->stat_minh;
-    info->any_unconverged = unconv;
+  bool any_unconv = false, nonfinite = false, cavit = false;
+  for (int k = 0; k < M; ++k) {
+    if (info) {
+      info[k].total_iters = total[k];
+      info[k].max_iters_per_solve = maxper[k];
+      info[k].solves = solves;
+      info[k].min_h = ctx->hstat[k].stat_minh;
+      info[k].any_unconverged = unconv[k];
+    }
+    any_unconv = any_unconv || unconv[k];
+    nonfinite = nonfinite || ctx->hstat[k].stat_nonfinite;
+    cavit = cavit || !(ctx->hstat[k].stat_minh > 0.0);
   }
-  if (ctx->hstat->stat_nonfinite) return SGN_ERR_NONFINITE;
-  if (!(ctx->hstat->stat_minh > 0.0)) return SGN_ERR_CAVITATION;
-  return unconv ? SGN_ERR_NOT_CONVERGED : SGN_OK;
+  if (nonfinite) return SGN_ERR_NONFINITE;
+  if (cavit) return SGN_ERR_CAVITATION;
+  return any_unconv ? SGN_ERR_NOT_CONVERGED : SGN_OK;
 }
 
 int sgn_rk4_step_graph(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double dt, int32_t nsteps,
@@ -1014,6 +1176,10 @@ int sgn_rk4_step_graph(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, d
   if (!ctx || !aligned(h) || !aligned(vx) || !aligned(vy) || !aligned(sigma) || nsteps < 0 || !std::isfinite(dt) ||
       iter_budget > ctx->cfg.gmres_restart)
     return SGN_ERR_INVALID_ARG;
+  if (members(ctx) > 1) {
+    ctx->err = "the captured step runs one grid per context (batch = 1)";
+    return SGN_ERR_UNSUPPORTED;
+  }
   if (nsteps == 0) return sgn_rk4_step(ctx, h, vx, vy, sigma, dt, 0, info);
   if (ctx->learn_net || ctx->learn_rec) {
     ctx->err = "the captured step does not run the learned guess";
@@ -1110,6 +1276,10 @@ int sgn_learned_guess_attach(sgn_ctx* ctx, sgn_cnn* net, float* record, int32_t 
       return SGN_ERR_INVALID_ARG;
     }
   }
+  if ((net || record) && members(ctx) > 1) {
+    ctx->err = "the learned guess runs one grid per context (batch = 1)";
+    return SGN_ERR_UNSUPPORTED;
+  }
   if ((net || record) && ctx->cfg.guess != SGN_GUESS_PREVIOUS) {
     ctx->err = "the learned guess replaces the warm start; it does not combine with the stage-increment guess";
     return SGN_ERR_UNSUPPORTED;
@@ -1135,8 +1305,8 @@ int sgn_invariants(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, 
   rc = set_tol(ctx, ctx->cfg.invariants_tol);
   if (rc) return rc;
   rc = load_sigma(ctx, sigma);
-  SolveResult res;
-  if (!rc) rc = run_solve(ctx, 1, h, vx, vy, &res);
+  std::vector<SolveResult> res(members(ctx));
+  if (!rc) rc = run_solve(ctx, 1, h, vx, vy, res.data());
   const int rc2 = set_tol(ctx, ctx->cfg.gmres_tol);
   if (rc) return rc;
   if (rc2) return rc2;
@@ -1149,16 +1319,18 @@ int sgn_invariants(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, 
   HIPCK(sgn::launch_row_c2r(g, ctx->E, sigma, ctx->stream));
   rc = read_status(ctx);
   if (rc) return rc;
-  const double* r = ctx->hstat->red;
-  out->mass = r[0];
-  out->px = r[1];
-  out->py = r[2];
-  out->energy = r[3];
-  out->curl_l2 = r[4];
-  out->min_h = r[5];
-  out->max_h = r[6];
-  out->spectral_tail = r[7];
-  return res.converged ? SGN_OK : SGN_ERR_NOT_CONVERGED;
+  for (int k = 0; k < members(ctx); ++k) {
+    const double* r = ctx->hstat[k].red;
+    out[k].mass = r[0];
+    out[k].px = r[1];
+    out[k].py = r[2];
+    out[k].energy = r[3];
+    out[k].curl_l2 = r[4];
+    out[k].min_h = r[5];
+    out[k].max_h = r[6];
+    out[k].spectral_tail = r[7];
+  }
+  return all_converged(res) ? SGN_OK : SGN_ERR_NOT_CONVERGED;
 }
 
 int sgn_derivative(sgn_ctx* ctx, int32_t axis, const void* f, void* out) {
@@ -1214,6 +1386,7 @@ int run_ensemble(int32_t n, sgn_ctx* const* ctxs, void* const* h, void* const* v
   if (n < 0 || (n > 0 && (!ctxs || !h || !vx || !vy || !sigma || !dt)) || nsteps < 0) return SGN_ERR_INVALID_ARG;
   for (int i = 0; i < n; ++i) {
     if (!ctxs[i]) return SGN_ERR_INVALID_ARG;
+    if (members(ctxs[i]) > 1) return SGN_ERR_UNSUPPORTED;  // one info per context: single grids only
     for (int k = 0; k < i; ++k)
       if (ctxs[k] == ctxs[i]) return SGN_ERR_INVALID_ARG;  // a context is not thread-safe
   }
@@ -1258,6 +1431,10 @@ std::map<std::tuple<int, int, int, int, int>, TuneChoice> g_tune_cache;  // (nx,
 
 int sgn_autotune(sgn_ctx* ctx, int32_t* chosen) {
   if (!ctx) return SGN_ERR_INVALID_ARG;
+  if (members(ctx) > 1) {
+    ctx->err = "the autotuner times single grids (batch = 1)";
+    return SGN_ERR_UNSUPPORTED;
+  }
   const sgn_config& c = ctx->cfg;
   const auto key = std::make_tuple(c.nx, c.ny, c.precision, c.gmres_restart, ctx->device);
   {
@@ -1444,6 +1621,6 @@ const char* sgn_status_string(int status) {
   }
 }
 
-const char* sgn_last_error(const sgn_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+const char* sgn_last_error(const sgn_ctx* ctx) { return ctx ? ctx->err.c_str() : sgn::global_error(); }
 
 }  // extern "C"

@@ -6,14 +6,20 @@
 namespace sgn {
 
 thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+thread_local unsigned t_members = 1;
 
 void set_launch_events(hipEvent_t start, hipEvent_t stop) {
   t_ev_start = start;
   t_ev_stop = stop;
 }
 
-#define SGN_DEFINE_DISPATCH(name, params, args) \
-  hipError_t launch_##name params { return g.fp32 ? p32::launch_##name args : p64::launch_##name args; }
+#define SGN_DEFINE_DISPATCH(name, params, args)                                        \
+  hipError_t launch_##name params {                                                   \
+    t_members = g.members > 1 ? (unsigned)g.members : 1u;                             \
+    const hipError_t e = g.fp32 ? p32::launch_##name args : p64::launch_##name args; \
+    t_members = 1;                                                                    \
+    return e;                                                                         \
+  }
 SGN_LAUNCHERS(SGN_DEFINE_DISPATCH)
 
 int max_partial_blocks(const Geom& g) { return g.fp32 ? p32::max_partial_blocks(g) : p64::max_partial_blocks(g); }

@@ -28,6 +28,12 @@ struct Geom {
   int row_threads;         // row passes: row pairs per block for at least this many threads (64)
   int status_first;        // 1: kernels test the GMRES status before their loads (captured graphs,
                            // whose fixed budgets launch many steps after convergence); 0: after
+  // ensemble members of one context, one per blockIdx.z of every launch:
+  // member m's workspace is member 0's [ws_lo, ws_lo + ws_span) moved by
+  // m * ws_stride bytes, its caller fields are member 0's moved by m * f_stride
+  int members;             // 1 for a single grid
+  uintptr_t ws_lo;
+  size_t ws_span, ws_stride, f_stride;
 };
 
 // GMRES state kept in device memory.  Written only by the single "last
@@ -45,7 +51,7 @@ struct GmresStatus {
   double red[8];        // invariants: mass, Px, Py, energy, |curl v|, min h, max h, tail
   double stat_minh;     // min h of the last field check
   int32_t stat_nonfinite;
-  int32_t pad;
+  int32_t cyc;          // host round of the current GMRES cycle (set by the residual pass)
   // solves of a captured RK4 step (one GMRES cycle each, no host reads):
   int32_t g_fail;   // solves that stopped at the iteration budget unconverged
   int32_t g_max;    // largest Arnoldi step count of one solve

@@ -46,6 +46,29 @@ namespace sgn {
 namespace SGN_NS {
 
 // ----------------------------------------------------------------------------
+// Ensemble members in one launch: member m = blockIdx.z works on the member
+// m copy of every array.  Member workspaces sit at a fixed stride from member
+// 0's (Geom::ws_lo, ws_span, ws_stride), the caller's fields at another
+// (Geom::f_stride); an address inside member 0's workspace moves by the
+// first, any other by the second.  Member 0 (and a single grid) uses the
+// pointers as given.
+// ----------------------------------------------------------------------------
+
+template <class T>
+__device__ __forceinline__ T* mshift(const Geom& g, T* p) {
+  const size_t m = blockIdx.z;
+  if (m == 0 || p == nullptr) return p;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+  const size_t stride = (a - g.ws_lo < g.ws_span) ? g.ws_stride : g.f_stride;
+  return reinterpret_cast<T*>(a + m * stride);
+}
+
+__device__ __forceinline__ RkField mshift_field(const Geom& g, RkField f) {
+  f.yn = mshift(g, f.yn); f.acc = mshift(g, f.acc); f.out = mshift(g, f.out);
+  return f;
+}
+
+// ----------------------------------------------------------------------------
 // Reductions (deterministic: fixed-order trees, no floating-point atomics)
 // ----------------------------------------------------------------------------
 
@@ -82,6 +105,28 @@ __device__ __forceinline__ double partial_load(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The GMRES stop code where a block of the same launch may store it (kernels
+// that finish an Arnoldi step: block 0 stores the step while later blocks of
+// the launch may still be starting).  Every block derives the same stop code
+// from the same inputs, and block 0 stores either the value the others read
+// before (0) or the one they compute themselves, so a block that sees the new
+// value exits exactly where it would have exited on its own.  The load and
+// the store are relaxed agent-scope atomics so that this benign race is
+// well-defined; the ordering it needs comes from the kernel boundaries.
+__device__ __forceinline__ int status_load(const GmresState* st) {
+  return __hip_atomic_load(const_cast<int32_t*>(&st->st.done), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void status_store(GmresState* st, int v) {
+  __hip_atomic_store(&st->st.done, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Ensemble launches that start a restarted cycle run only for the members
+// whose last cycle filled up below the iteration cap (the host enqueues them
+// for every member once any member needs one).
+__device__ __forceinline__ bool restart_due(const GmresState* st) {
+  return st->st.done == 2 && st->st.total_iters < st->maxit;
+}
+
 __device__ __forceinline__ uint32_t ticket(uint32_t* c) {
   return __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -91,7 +136,13 @@ __device__ __forceinline__ void reset_counter(uint32_t* c) {
 
 // Every block calls this once after writing its partials with partial_store.
 // Returns true in exactly one block (the last to arrive).  Each thread first
-// waits for its own partial stores to complete.  Tickets are taken in two
+// waits for its own partial stores to complete.  The ordering of the partial
+// stores before the ticket rests on gfx950 behaviour, not on the HIP memory
+// model: an agent-scope store is acknowledged (s_waitcnt) only once it has
+// reached the device coherence point, and the ticket is taken after every
+// thread of the block has waited for its acknowledgements.  A release/acquire
+// pair would make this formal but compiles to an L2 write-back and invalidate
+// in every block, which cost 5-10x in the kernels that finish reductions.  Tickets are taken in two
 // levels (groups of kTicketGroup blocks, then groups) so that no counter sees
 // more than max(kTicketGroup, #groups) same-address atomics.
 __device__ bool last_block_arrive(uint32_t* ctr, int nblocks) {
@@ -394,7 +445,7 @@ __device__ int gmres_finish_column(GmresState* st, int j, const double* cj, doub
     st->st.jdone = j + 1;
     st->st.total_iters = sh_total;
     st->st.resid = sh_resid;
-    st->st.done = stop;
+    status_store(st, stop);
   }
   return stop;
 }
@@ -507,8 +558,8 @@ __device__ __forceinline__ void store_spec_pair(const cplx* v, cplx* __restrict_
 // physical f -> x-half spectra S
 template <int N>
 __global__ void __launch_bounds__(512) k_row_r2c(Geom g, Trio io) {
-  const real* __restrict__ f = static_cast<const real*>(io.in[blockIdx.y]);
-  cplx* __restrict__ S = static_cast<cplx*>(io.out[blockIdx.y]);
+  const real* __restrict__ f = mshift(g, static_cast<const real*>(io.in[blockIdx.y]));
+  cplx* __restrict__ S = mshift(g, static_cast<cplx*>(io.out[blockIdx.y]));
   ROW_SETUP(N)
   cplx v[E];
   load_phys_pair<N>(v, f, ya, t);
@@ -519,8 +570,8 @@ __global__ void __launch_bounds__(512) k_row_r2c(Geom g, Trio io) {
 // x-half spectra S -> physical f
 template <int N>
 __global__ void __launch_bounds__(512) k_row_c2r(Geom g, Trio io) {
-  const cplx* __restrict__ S = static_cast<const cplx*>(io.in[blockIdx.y]);
-  real* __restrict__ f = static_cast<real*>(io.out[blockIdx.y]);
+  const cplx* __restrict__ S = mshift(g, static_cast<const cplx*>(io.in[blockIdx.y]));
+  real* __restrict__ f = mshift(g, static_cast<real*>(io.out[blockIdx.y]));
   ROW_SETUP(N)
   cplx v[E];
   load_spec_pair<N>(v, S, ya, t, g.inv_nx);
@@ -531,6 +582,7 @@ __global__ void __launch_bounds__(512) k_row_c2r(Geom g, Trio io) {
 // out = d/dx f
 template <int N>
 __global__ void __launch_bounds__(512) k_row_dx(Geom g, const real* __restrict__ f, real* __restrict__ out) {
+  f = mshift(g, f); out = mshift(g, out);
   ROW_SETUP(N)
   cplx v[E];
   load_phys_pair<N>(v, f, ya, t);
@@ -555,7 +607,10 @@ __global__ void __launch_bounds__(512) k_row_op(Geom g, const cplx* __restrict__
                                                 const real* __restrict__ vy, cplx* __restrict__ P,
                                                 cplx* __restrict__ Q, cplx* __restrict__ R1, cplx* __restrict__ R2,
                                                 int need_b, int predicate, const GmresState* __restrict__ st) {
+  Es = mshift(g, Es); Gs = mshift(g, Gs); h = mshift(g, h); vx = mshift(g, vx); vy = mshift(g, vy);
+  P = mshift(g, P); Q = mshift(g, Q); R1 = mshift(g, R1); R2 = mshift(g, R2); st = mshift(g, st);
   if (MODE == 0 && predicate && SF && st->st.done) return;
+  if (MODE != 0 && predicate == 2 && !restart_due(st)) return;  // ensemble restart: only members that restart
   ROW_SETUP(N)
   // every global load first, so their latencies overlap (the GMRES status
   // too: the loads are in bounds whatever it is)
@@ -625,6 +680,8 @@ template <int N, bool SF>
 __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __restrict__ Es, const cplx* __restrict__ Gs,
                                                       const real* __restrict__ h, cplx* __restrict__ P,
                                                       cplx* __restrict__ Q, const GmresState* st) {
+  Es = mshift(g, Es); Gs = mshift(g, Gs); h = mshift(g, h); P = mshift(g, P); Q = mshift(g, Q);
+  st = mshift(g, st);
   if (SF && st->st.done) return;
   constexpr int E = Row<N>::E;
   constexpr int TPF = Row<N>::TPF;
@@ -726,6 +783,9 @@ __global__ void __launch_bounds__(512) k_row_flux(Geom g, const cplx* __restrict
                                                   const real* h, const real* vx, const real* vy,
                                                   real* __restrict__ dhp, real* __restrict__ qy,
                                                   real* __restrict__ Bo, RkStage rk, RkField fvx) {
+  Es = mshift(g, Es); Gs = mshift(g, Gs); h = mshift(g, h); vx = mshift(g, vx); vy = mshift(g, vy);
+  dhp = mshift(g, dhp); qy = mshift(g, qy); Bo = mshift(g, Bo); rk.pred = mshift(g, rk.pred);
+  fvx = mshift_field(g, fvx);
   ROW_SETUP(N)
   cplx s[E], sx[E], sy[E], hh[E], ux[E], uy[E];
   load_spec_pair<N>(s, Es, ya, t, g.inv_nx);
@@ -781,6 +841,8 @@ __global__ void __launch_bounds__(512) k_row_invariants(Geom g, const cplx* __re
                                                         const real* __restrict__ vx, const real* __restrict__ vy,
                                                         const real* __restrict__ dyvx, double* partials,
                                                         GmresState* st, int nblocks) {
+  Es = mshift(g, Es); Gs = mshift(g, Gs); h = mshift(g, h); vx = mshift(g, vx); vy = mshift(g, vy);
+  dyvx = mshift(g, dyvx); partials = mshift(g, partials); st = mshift(g, st);
   constexpr int E = Row<N>::E;
   constexpr int TPF = Row<N>::TPF;
   const RowMap map;
@@ -948,6 +1010,7 @@ __device__ __forceinline__ void store_col(const cplx* v, cplx* __restrict__ S, i
 template <int N>
 __global__ void __launch_bounds__(512) k_col_fwd_eg(Geom g, const cplx* __restrict__ Ein, cplx* __restrict__ SIG,
                                                      cplx* __restrict__ Gout) {
+  Ein = mshift(g, Ein); SIG = mshift(g, SIG); Gout = mshift(g, Gout);
   COL_SETUP(N)
   cplx v[E];
   load_col<N>(v, Ein, g.nh, col, t, valid);
@@ -983,7 +1046,9 @@ __global__ void __launch_bounds__(512) k_col_basis_eg(Geom g, const cplx* __rest
                                                        size_t vstride, int j, GmresState* st, cplx* __restrict__ Eo,
                                                        cplx* __restrict__ Go, const double* __restrict__ pin,
                                                        int nbin) {
-  if (st->st.done) return;
+  W = mshift(g, W); V = mshift(g, V); st = mshift(g, st); Eo = mshift(g, Eo); Go = mshift(g, Go);
+  pin = mshift(g, pin);
+  if (status_load(st)) return;
   __shared__ double coef[kMaxRestart + 1];
   double beta = st->beta;  // j = 0: the residual norm
   if (j > 0 && cgs2_finish(g, st, j - 1, pin, nbin, coef, beta, blockIdx.x == 0)) return;
@@ -1039,7 +1104,9 @@ __global__ void __launch_bounds__(1024) k_col_basis2(Geom g, const cplx* __restr
                                                      size_t vstride, int j, GmresState* st, cplx* __restrict__ Eo,
                                                      cplx* __restrict__ Go, const double* __restrict__ pin,
                                                      int nbin) {
-  if (st->st.done) return;
+  W = mshift(g, W); V = mshift(g, V); st = mshift(g, st); Eo = mshift(g, Eo); Go = mshift(g, Go);
+  pin = mshift(g, pin);
+  if (status_load(st)) return;
   __shared__ double coef[kMaxRestart + 1];
   double beta = st->beta;  // j = 0: the residual norm
   if (j > 0 && cgs2_finish(g, st, j - 1, pin, nbin, coef, beta, blockIdx.x == 0)) return;
@@ -1081,6 +1148,8 @@ __global__ void __launch_bounds__(1024) k_col_precond_dot2(Geom g, const cplx* _
                                                            const cplx* __restrict__ Q, const cplx* __restrict__ V,
                                                            size_t vstride, int j, const GmresState* st,
                                                            cplx* __restrict__ W, double* partials) {
+  P = mshift(g, P); Q = mshift(g, Q); V = mshift(g, V); st = mshift(g, st); W = mshift(g, W);
+  partials = mshift(g, partials);
   if (SF && st->st.done) return;
   COL2_SETUP(N)
   __shared__ double red[(kMaxRestart + 1) * 16];
@@ -1211,9 +1280,13 @@ __device__ bool cgs_coefficients(const Geom& g, GmresState* st, int jc, const do
     double q = w2;
     for (int i = 0; i <= jc; ++i) q += coef[i] * (gc[i] - 2.0 * outv[2 * i]);
     // the identity cancels ||w||^2 down to ||u||^2, so its rounding error is
-    // about eps ||w||^2; below 1e-10 ||w||^2 it no longer fixes ||u|| (to
-    // 1e-6 relative or better above): -1 tells the caller so
-    sh_beta = q > 1e-10 * w2 ? sqrt(q) : -1.0;
+    // about eps ||w||^2 with the eps of the stored vectors; below kGramCut
+    // ||w||^2 it no longer fixes ||u|| well enough (FP64: to 1e-6 relative
+    // or better above 1e-10; FP32, where u is stored in float and differs
+    // from the identity's u by about eps32 ||w||: to 6e-5 above 1e-6): -1
+    // tells the caller so
+    constexpr double kGramCut = SGN_PREC == 32 ? 1e-6 : 1e-10;
+    sh_beta = q > kGramCut * w2 ? sqrt(q) : -1.0;
   }
   __syncthreads();
   beta = sh_beta;
@@ -1238,8 +1311,12 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
                                                    size_t vstride, int j, GmresState* st, cplx* __restrict__ Eo,
                                                    cplx* __restrict__ Go,
                                                    const double* __restrict__ pin) {
-  if (SF && st->st.done) return;
-  const int done = st->st.done;  // tested once the loads of the prologue are in flight
+  win = mshift(g, win); W = mshift(g, W); V = mshift(g, V); st = mshift(g, st); Eo = mshift(g, Eo);
+  Go = mshift(g, Go); pin = mshift(g, pin);
+  if (SF && status_load(st)) return;
+  // tested once the loads of the prologue are in flight; block 0 of this
+  // launch may store it meanwhile (status_load)
+  const int done = status_load(st);
   __shared__ double coef[kMaxRestart + 1];
   __shared__ double outv[2 * (kMaxRestart + 1) + 1];
   {
@@ -1304,6 +1381,8 @@ __global__ void __launch_bounds__(1024) k_col_precond_new(Geom g, const cplx* __
                                                           const cplx* __restrict__ Q, const cplx* __restrict__ W,
                                                           cplx* __restrict__ V, cplx* __restrict__ Wn, size_t vstride,
                                                           int j, const GmresState* st, double* partials) {
+  P = mshift(g, P); Q = mshift(g, Q); W = mshift(g, W); V = mshift(g, V); Wn = mshift(g, Wn);
+  st = mshift(g, st); partials = mshift(g, partials);
   if (SF && st->st.done) return;
   COL2_SETUP(N)
   __shared__ double red[(2 * (kMaxRestart + 1) + 1) * 16];
@@ -1389,17 +1468,22 @@ __global__ void __launch_bounds__(512) k_col_update_eg(Geom g, cplx* __restrict_
                                                         size_t vstride, const GmresState* __restrict__ st,
                                                         cplx* __restrict__ Eo, cplx* __restrict__ Go,
                                                         cplx* __restrict__ D, int spec) {
+  SIG = mshift(g, SIG); V = mshift(g, V); st = mshift(g, st); Eo = mshift(g, Eo); Go = mshift(g, Go);
+  D = mshift(g, D);
   COL_SETUP(N)
   __shared__ double coef[kMaxRestart];
   const int tid = flat_tid();
   // the status, all the coefficient slots and sigma are loaded together (in
   // bounds whatever the status); the speculative launch's test follows
-  const int done = st->st.done, k = st->st.jdone, zero = st->st.zero;
+  const int done = st->st.done, k = st->st.jdone, zero = st->st.zero, cyc = st->st.cyc;
   for (int i = tid; i < kMaxRestart; i += block_threads()) coef[i] = st->y[i];
   cplx sg[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) sg[r] = valid ? SIG[sidx(g, t + r * TPF, col)] : make_cplx(0.0, 0.0);
-  if (spec && done != 1) return;
+  if ((spec & 1) && done != 1) return;
+  // spec & 2: an ensemble update after cycle round spec >> 8, for the members
+  // that ran a cycle in that round only
+  if ((spec & 2) && cyc != (spec >> 8)) return;
   __syncthreads();
   cplx v[E];
 #pragma unroll
@@ -1436,6 +1520,7 @@ __global__ void __launch_bounds__(512) k_col_update_eg(Geom g, cplx* __restrict_
 template <int N>
 __global__ void __launch_bounds__(512) k_col_guess_eg(Geom g, cplx* __restrict__ SIG, const cplx* __restrict__ D,
                                                        cplx* __restrict__ Eo, cplx* __restrict__ Go) {
+  SIG = mshift(g, SIG); D = mshift(g, D); Eo = mshift(g, Eo); Go = mshift(g, Go);
   COL_SETUP(N)
   cplx v[E];
 #pragma unroll
@@ -1475,6 +1560,8 @@ __global__ void __launch_bounds__(512) k_col_precond_dot(Geom g, const cplx* __r
                                                           const cplx* __restrict__ Q, const cplx* __restrict__ V,
                                                           size_t vstride, int j, const GmresState* st,
                                                           cplx* __restrict__ W, double* partials) {
+  P = mshift(g, P); Q = mshift(g, Q); V = mshift(g, V); st = mshift(g, st); W = mshift(g, W);
+  partials = mshift(g, partials);
   if (st->st.done) return;
   COL_SETUP(N)
   __shared__ double red[(kMaxRestart + 1) * 16];
@@ -1518,6 +1605,12 @@ __global__ void __launch_bounds__(512) k_col_resid(Geom g, const cplx* __restric
                                                     int need_b, int flags, GmresState* st, cplx* __restrict__ W,
                                                     double* partials, int nblocks, cplx* __restrict__ Eo,
                                                     cplx* __restrict__ Go) {
+  P = mshift(g, P); Q = mshift(g, Q); R1 = mshift(g, R1); R2 = mshift(g, R2); st = mshift(g, st);
+  W = mshift(g, W); partials = mshift(g, partials); Eo = mshift(g, Eo); Go = mshift(g, Go);
+  // flags & 4: an ensemble restart, run only for the members that restart
+  // (each block reads the status before any block of the member takes a
+  // ticket, and only the last block rewrites it)
+  if ((flags & 4) && !restart_due(st)) return;
   COL_SETUP(N)
   __shared__ double red[3 * 16];
   __shared__ double outv[3];
@@ -1577,6 +1670,7 @@ __global__ void __launch_bounds__(512) k_col_resid(Geom g, const cplx* __restric
           st->st.zero = 0;
         }
         st->cycle_base = st->st.total_iters;
+        st->st.cyc = flags >> 8;  // the host's cycle round (ensembles: which members' update runs)
         if (need_b) {
           st->st.beta0 = sqrt(outv[1] * g.inv_n);
           st->st.bnorm = sqrt(outv[2] * g.inv_n);
@@ -1596,6 +1690,7 @@ __global__ void __launch_bounds__(512) k_col_resid(Geom g, const cplx* __restric
 // Inverse y-transform of a 2D spectrum: out = F_y^-1 S / ny.
 template <int N>
 __global__ void __launch_bounds__(512) k_col_inv(Geom g, const cplx* __restrict__ S, cplx* __restrict__ out) {
+  S = mshift(g, S); out = mshift(g, out);
   COL_SETUP(N)
   cplx v[E];
   load_spec<N>(v, S, col, t, valid);
@@ -1631,6 +1726,7 @@ __global__ void __launch_bounds__(512) k_col_learn(Geom g, const cplx* __restric
 template <int N>
 __global__ void __launch_bounds__(512) k_col_apply(Geom g, const cplx* __restrict__ P, const cplx* __restrict__ Q,
                                                     int precond, cplx* __restrict__ out) {
+  P = mshift(g, P); Q = mshift(g, Q); out = mshift(g, out);
   COL_SETUP(N)
   cplx v[E];
   col_combine<N>(g, v, buf, t, col, valid, P, Q, twy);
@@ -1650,8 +1746,8 @@ __global__ void __launch_bounds__(512) k_col_apply(Geom g, const cplx* __restric
 //         two-thirds rule of Orszag, an option beyond the paper's scheme)
 template <int N>
 __global__ void __launch_bounds__(512) k_col_filter(Geom g, Trio io, int op, double thr) {
-  const cplx* __restrict__ Sx = static_cast<const cplx*>(io.in[blockIdx.y]);
-  cplx* __restrict__ out = static_cast<cplx*>(io.out[blockIdx.y]);
+  const cplx* __restrict__ Sx = mshift(g, static_cast<const cplx*>(io.in[blockIdx.y]));
+  cplx* __restrict__ out = mshift(g, static_cast<cplx*>(io.out[blockIdx.y]));
   COL_SETUP(N)
   cplx v[E];
   load_col<N>(v, Sx, g.nh, col, t, valid);
@@ -1707,6 +1803,7 @@ __global__ void __launch_bounds__(512) k_col_filter(Geom g, Trio io, int op, dou
 template <int N>
 __global__ void __launch_bounds__(512) k_col_tail(Geom g, const cplx* __restrict__ Sx, GmresState* st,
                                                    double* partials, int nblocks) {
+  Sx = mshift(g, Sx); st = mshift(g, st); partials = mshift(g, partials);
   COL_SETUP(N)
   __shared__ double red[16];
   __shared__ double outv[1];
@@ -1756,6 +1853,7 @@ __global__ void __launch_bounds__(512) k_col_tail(Geom g, const cplx* __restrict
 // out = d/dy f for a physical field (two real columns per complex column).
 template <int N>
 __global__ void __launch_bounds__(512) k_col_dy(Geom g, const real* __restrict__ f, real* __restrict__ out) {
+  f = mshift(g, f); out = mshift(g, out);
   COL_SETUP(N)
   cplx v[E];
   load_col<N>(v, reinterpret_cast<const cplx*>(f), g.nh, col, t, valid);
@@ -1770,6 +1868,8 @@ __global__ void __launch_bounds__(512) k_col_dy(Geom g, const real* __restrict__
 template <int N>
 __global__ void __launch_bounds__(512) k_col_flux(Geom g, const real* __restrict__ dhp, const real* __restrict__ qy,
                                                    const real* __restrict__ Bf, RkStage rk, RkField fh, RkField fvy) {
+  dhp = mshift(g, dhp); qy = mshift(g, qy); Bf = mshift(g, Bf); rk.pred = mshift(g, rk.pred);
+  fh = mshift_field(g, fh); fvy = mshift_field(g, fvy);
   COL_SETUP(N)
   cplx v[E], u[E];
   load_col<N>(v, reinterpret_cast<const cplx*>(qy), g.nh, col, t, valid);
@@ -1802,6 +1902,8 @@ template <int N>
 __global__ void __launch_bounds__(1024) k_col_flux2(Geom g, const real* __restrict__ dhp, const real* __restrict__ qy,
                                                     const real* __restrict__ Bf, RkStage rk, RkField fh,
                                                     RkField fvy) {
+  dhp = mshift(g, dhp); qy = mshift(g, qy); Bf = mshift(g, Bf); rk.pred = mshift(g, rk.pred);
+  fh = mshift_field(g, fh); fvy = mshift_field(g, fvy);
   COL2_SETUP(N)
   cplx v[E];
   load_col<N>(v, reinterpret_cast<const cplx*>(chain == 0 ? qy : Bf), g.nh, col, t, valid);
@@ -1837,6 +1939,7 @@ constexpr int kUpdEpt = 4;
 __global__ void __launch_bounds__(kUpdThreads) k_upd(Geom g, cplx* __restrict__ W, const cplx* __restrict__ V,
                                                      size_t vstride, int j, GmresState* st, double* partials,
                                                      const double* __restrict__ pin, int nbin) {
+  W = mshift(g, W); V = mshift(g, V); st = mshift(g, st); partials = mshift(g, partials); pin = mshift(g, pin);
   if (st->st.done) return;
   __shared__ double coef[kMaxRestart + 1];
   __shared__ double red[(kMaxRestart + 2) * (kUpdThreads / 64)];
@@ -1958,9 +2061,10 @@ __global__ void __launch_bounds__(256) k_learn_target(const real* __restrict__ s
 }
 
 // min h and a non-finite flag over (h, vx, vy).
-__global__ void __launch_bounds__(256) k_field_stats(const real* __restrict__ h, const real* __restrict__ vx,
+__global__ void __launch_bounds__(256) k_field_stats(Geom g, const real* __restrict__ h, const real* __restrict__ vx,
                                                      const real* __restrict__ vy, size_t n, GmresState* st,
                                                      double* partials, int nblocks) {
+  h = mshift(g, h); vx = mshift(g, vx); vy = mshift(g, vy); st = mshift(g, st); partials = mshift(g, partials);
   __shared__ double red[2 * 4];
   __shared__ double outv[2];
   double mn = 1e300, bad = 0.0;
@@ -2003,6 +2107,7 @@ __global__ void __launch_bounds__(64) k_solve_stats(GmresState* st) {
 // (t_ev_start / t_ev_stop: namespace sgn, shared by both precisions)
 template <typename K, typename... Args>
 static void launch(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, Args... args) {
+  grid.z = t_members;  // ensemble members (blockIdx.z), set by the dispatch from Geom::members
   if (t_ev_start) {
     hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, t_ev_start, t_ev_stop, 0u, args...);
     t_ev_start = t_ev_stop = nullptr;
@@ -2616,11 +2721,11 @@ hipError_t launch_solve_stats(const Geom&, GmresState* st, hipStream_t s) {
   launch(k_solve_stats, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
 }
-hipError_t launch_field_stats(const Geom&, const void* h, const void* vx, const void* vy, size_t n, GmresState* st,
+hipError_t launch_field_stats(const Geom& g, const void* h, const void* vx, const void* vy, size_t n, GmresState* st,
                               double* partials, hipStream_t s) {
   int nb = (int)((n + 255) / 256);
   if (nb > 1024) nb = 1024;
-  launch(k_field_stats, dim3(nb), dim3(256), 0, s, R_(h), R_(vx), R_(vy), n, st, partials, nb);
+  launch(k_field_stats, dim3(nb), dim3(256), 0, s, g, R_(h), R_(vx), R_(vy), n, st, partials, nb);
   return hipGetLastError();
 }
 

@@ -157,6 +157,8 @@ void launch_shape(const Geom& g, int* out4);
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 // Events for the next launch (consumed by it); shared by both precisions.
 extern thread_local hipEvent_t t_ev_start, t_ev_stop;
+// Ensemble members of the launch being dispatched (gridDim.z).
+extern thread_local unsigned t_members;
 
 namespace p64 {
 SGN_LAUNCHERS(SGN_DECLARE_LAUNCHER)

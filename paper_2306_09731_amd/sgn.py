@@ -216,11 +216,19 @@ def _field(ctx: Context, t, name: str):
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor")
     dt = field_dtype(cfg)
-    if t.dtype != dt or not t.is_contiguous() or t.device != ctx.device \
-            or tuple(t.shape) != (cfg.ny, cfg.nx):
-        raise ValueError(f"{name} must be a contiguous {dt} tensor of shape ({cfg.ny}, {cfg.nx}) "
-                         f"on {ctx.device}")
+    shape = (cfg.ny, cfg.nx) if cfg.batch == 1 else (cfg.batch, cfg.ny, cfg.nx)
+    if t.dtype != dt or not t.is_contiguous() or t.device != ctx.device or tuple(t.shape) != shape:
+        raise ValueError(f"{name} must be a contiguous {dt} tensor of shape {shape} on {ctx.device}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _infos(ctx: Context, cls):
+    """One info struct per ensemble member."""
+    return (cls * max(ctx.cfg.batch, 1))()
+
+
+def _one_or_list(ctx: Context, arr):
+    return arr[0] if ctx.cfg.batch == 1 else [arr[i] for i in range(ctx.cfg.batch)]
 
 
 def sgn_init(cfg: sgn_config, device="cuda:0", stream=None) -> Context:
@@ -244,21 +252,23 @@ def sgn_init(cfg: sgn_config, device="cuda:0", stream=None) -> Context:
     return Context(handle=handle, cfg=cfg, workspace=ws, device=device)
 
 
-def sgn_elliptic_solve(ctx: Context, h, b, sigma) -> sgn_solve_info:
-    info = sgn_solve_info()
+def sgn_elliptic_solve(ctx: Context, h, b, sigma):
+    """Solve L_h sigma = b (sigma: initial guess in, solution out).  Returns the
+    sgn_solve_info, or one per member for an ensemble context."""
+    info = _infos(ctx, sgn_solve_info)
     st = load_library().sgn_elliptic_solve(ctx.handle, _field(ctx, h, "h"), _field(ctx, b, "b"),
-                                           _field(ctx, sigma, "sigma"), ctypes.byref(info))
+                                           _field(ctx, sigma, "sigma"), info)
     _check(ctx, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
-    return info
+    return _one_or_list(ctx, info)
 
 
-def sgn_rhs(ctx: Context, h, vx, vy, sigma, dh, dvx, dvy) -> sgn_solve_info:
-    info = sgn_solve_info()
+def sgn_rhs(ctx: Context, h, vx, vy, sigma, dh, dvx, dvy):
+    info = _infos(ctx, sgn_solve_info)
     st = load_library().sgn_rhs(ctx.handle, _field(ctx, h, "h"), _field(ctx, vx, "vx"), _field(ctx, vy, "vy"),
                                 _field(ctx, sigma, "sigma"), _field(ctx, dh, "dh"), _field(ctx, dvx, "dvx"),
-                                _field(ctx, dvy, "dvy"), ctypes.byref(info))
+                                _field(ctx, dvy, "dvy"), info)
     _check(ctx, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
-    return info
+    return _one_or_list(ctx, info)
 
 
 def sgn_launch_shape(ctx: Context) -> dict:
@@ -281,13 +291,15 @@ def sgn_elliptic_solve_refined(ctx64: Context, ctx32: Context, h, b, sigma, tol:
     return info
 
 
-def sgn_rk4_step(ctx: Context, h, vx, vy, sigma, dt: float, nsteps: int = 1) -> sgn_step_info:
-    info = sgn_step_info()
+def sgn_rk4_step(ctx: Context, h, vx, vy, sigma, dt: float, nsteps: int = 1):
+    """nsteps RK4 steps in place.  Returns the sgn_step_info, or one per member
+    for an ensemble context."""
+    info = _infos(ctx, sgn_step_info)
     st = load_library().sgn_rk4_step(ctx.handle, _field(ctx, h, "h"), _field(ctx, vx, "vx"),
                                      _field(ctx, vy, "vy"), _field(ctx, sigma, "sigma"), float(dt),
-                                     int(nsteps), ctypes.byref(info))
+                                     int(nsteps), info)
     _check(ctx, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
-    return info
+    return _one_or_list(ctx, info)
 
 
 def sgn_rk4_step_graph(ctx: Context, h, vx, vy, sigma, dt: float, nsteps: int = 1, iter_budget: int = 0):
@@ -330,12 +342,14 @@ def sgn_autotune(ctx: Context) -> int:
     return chosen.value
 
 
-def sgn_invariants(ctx: Context, h, vx, vy, sigma) -> dict:
-    out = sgn_invariants_out()
+def sgn_invariants(ctx: Context, h, vx, vy, sigma):
+    """Invariants as a dict, or a list of dicts (one per member) for an ensemble context."""
+    out = _infos(ctx, sgn_invariants_out)
     st = load_library().sgn_invariants(ctx.handle, _field(ctx, h, "h"), _field(ctx, vx, "vx"),
-                                       _field(ctx, vy, "vy"), _field(ctx, sigma, "sigma"), ctypes.byref(out))
+                                       _field(ctx, vy, "vy"), _field(ctx, sigma, "sigma"), out)
     _check(ctx, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
-    return {name: getattr(out, name) for name, _ in sgn_invariants_out._fields_}
+    d = [{name: getattr(o, name) for name, _ in sgn_invariants_out._fields_} for o in out]
+    return d[0] if ctx.cfg.batch == 1 else d
 
 
 def sgn_derivative(ctx: Context, axis: int, f, out):

@@ -24,4 +24,7 @@ from .generators import (  # noqa: F401
     random_state,
     workload,
     WORKLOADS,
+    perturbed_soliton_sweep,
+    SWEEP_AMPLITUDES,
+    SWEEP_WAVENUMBERS,
 )

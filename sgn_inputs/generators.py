@@ -283,6 +283,23 @@ WORKLOADS = {
 }
 
 
+# The nine runs of the 1024x512 perturbed-soliton workload: amplitudes a and
+# transverse wavenumbers k of h = h_c(x - x0) (1 + eps cos(2 pi k y / (2 pi Ly))).
+SWEEP_AMPLITUDES = (0.2, 0.5, 1.0)
+SWEEP_WAVENUMBERS = (1, 2, 4)
+
+
+def perturbed_soliton_sweep(eps: float = 0.01, x0: float = -10.0):
+    """The nine (a, k) runs of the 1024x512 workload stacked as ensemble
+    members: returns (box, (h, vx, vy, sigma0) arrays of shape (9, ny, nx),
+    [(a, k), ...], params)."""
+    w = WORKLOADS["perturbed_soliton_1024x512"]
+    box = Box(w["nx"], w["ny"], w["Lx"], w["Ly"])
+    ak = [(a, k) for a in SWEEP_AMPLITUDES for k in SWEEP_WAVENUMBERS]
+    st = [perturbed_line_soliton(box, a=a, eps=eps, k=k, x0=x0) for a, k in ak]
+    return box, tuple(np.stack([m[i] for m in st]) for i in range(4)), ak, w
+
+
 def workload(name: str, a: float = 0.5, eps: float = 0.01, k: int = 2):
     """Return (box, (h, vx, vy, sigma0), params) for a named workload."""
     w = WORKLOADS[name]

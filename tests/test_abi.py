@@ -45,7 +45,8 @@ def test_config_default_and_struct_layout():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("nx", 100), ("ny", 4), ("nx", 8192), ("gmres_restart", 65), ("precision", 2), ("batch", 2),
+    ("nx", 100), ("ny", 4), ("nx", 8192), ("gmres_restart", 65), ("precision", 2), ("batch", 0),
+    ("batch", 65),
 ])
 def test_workspace_bytes_rejects_unsupported(field, value):
     cfg = sgn.config_default(128, 64, 10.0, 5.0)
@@ -116,7 +117,8 @@ def test_calls_reject_null_context():
     assert lib.sgn_elliptic_solve(None, None, None, None, None) == sgn.SGN_ERR_INVALID_ARG
     assert lib.sgn_invariants(None, None, None, None, None, None) == sgn.SGN_ERR_INVALID_ARG
     assert lib.sgn_destroy(None) == sgn.SGN_ERR_INVALID_ARG
-    assert lib.sgn_last_error(None) == b""
+    # no context: the message of this thread's last context-free failure
+    assert isinstance(lib.sgn_last_error(None), bytes)
 
 
 def test_ensemble_and_autotune_host_checks():
@@ -164,3 +166,10 @@ def test_cnn_and_learned_guess_host_checks():
     n = ctypes.c_int64()
     assert lib.sgn_learned_guess_recorded(None, ctypes.byref(n)) == sgn.SGN_ERR_INVALID_ARG
     assert sgn.SGN_CNN_PARAMS == 6 * (9 * 32 * 32 + 32)
+
+
+def test_members_workspace_is_per_member():
+    one = sgn.sgn_workspace_bytes(sgn.config_default(128, 64, 10.0, 5.0))
+    for b in (2, 9, 64):
+        assert sgn.sgn_workspace_bytes(sgn.config_default(128, 64, 10.0, 5.0, batch=b)) == b * one
+    assert one % 256 == 0
