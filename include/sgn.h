@@ -340,6 +340,29 @@ int sgn_apply_operator(sgn_ctx* ctx, const void* h, const void* s, void* out, in
 int sgn_apply_precond(sgn_ctx* ctx, const void* r, void* out);
 int sgn_krasny_filter(sgn_ctx* ctx, void* f);
 
+/* For callers that cannot allocate device memory or create a context at call
+ * time (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): sgn_apply_operator without a context or workspace.
+ * out = L_h s, or M^-1 L_h s if precondition != 0, for the grid, box, h_inf
+ * and precision of *cfg (the other fields must be valid but are unused;
+ * batch must be 1).  h, s, out: device fields of cfg->nx x cfg->ny points as
+ * for sgn_apply_operator (double, or float in SGN_FP32_MIXED), out not
+ * aliasing h or s.  The work is enqueued on hip_stream (NULL: the null
+ * stream) and the call returns without synchronising; launch errors are
+ * reported.  Scratch: a fixed device array of the library, 256 KiB of
+ * twiddle tables plus four fields of SGN_NOALLOC_MAX_POINTS doubles
+ * (32.25 MiB per GPU, held from the first call on that GPU until the process
+ * ends); the call allocates nothing.  Grids of more than
+ * SGN_NOALLOC_MAX_POINTS points are refused with SGN_ERR_UNSUPPORTED before
+ * any GPU work, with the reason in sgn_last_error(NULL).  Calls on one GPU
+ * share its scratch: calls that overlap on one GPU (concurrent streams or
+ * host threads) race and must be serialised by the caller.  Results match
+ * sgn_apply_operator to rounding (its twiddle tables are computed on the
+ * device instead of the host). */
+#define SGN_NOALLOC_MAX_POINTS (1 << 20)
+int sgn_apply_operator_noalloc(const sgn_config* cfg, const void* h, const void* s, void* out,
+                               int32_t precondition, void* hip_stream);
+
 /* Measurement support.  While timing is enabled for a kernel class, every
  * p-th launch of that class is bracketed by HIP events recorded on the
  * context stream, so its device time can be read without a profiler.

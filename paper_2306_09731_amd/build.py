@@ -28,6 +28,7 @@ SOURCES = [
     ("sgn_dispatch.cpp", "sgn_dispatch", []),
     ("sgn_cnn.hip", "sgn_cnn", []),
     ("sgn_refine.hip", "sgn_refine", []),
+    ("sgn_noalloc.hip", "sgn_noalloc", []),
     ("sgn_api.cpp", "sgn_api", []),
 ]
 

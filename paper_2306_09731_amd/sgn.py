@@ -105,6 +105,7 @@ _SIGNATURES = {
     "sgn_derivative": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP]),
     "sgn_apply_operator": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int32]),
     "sgn_apply_precond": (ctypes.c_int, [_VP, _VP, _VP]),
+    "sgn_apply_operator_noalloc": (ctypes.c_int, [ctypes.POINTER(sgn_config), _VP, _VP, _VP, ctypes.c_int32, _VP]),
     "sgn_krasny_filter": (ctypes.c_int, [_VP, _VP]),
     "sgn_rk4_step_ensemble": (ctypes.c_int, _ENSEMBLE_ARGS),
     "sgn_rk4_step_ensemble_graph": (ctypes.c_int, _ENSEMBLE_ARGS),
@@ -359,6 +360,26 @@ def sgn_derivative(ctx: Context, axis: int, f, out):
 def sgn_apply_operator(ctx: Context, h, s, out, precondition: bool = False):
     _check(ctx, load_library().sgn_apply_operator(ctx.handle, _field(ctx, h, "h"), _field(ctx, s, "s"),
                                                   _field(ctx, out, "out"), 1 if precondition else 0))
+
+
+SGN_NOALLOC_MAX_POINTS = 1 << 20
+
+
+def sgn_apply_operator_noalloc(cfg: sgn_config, h, s, out, precondition: bool = False, stream=None):
+    """sgn_apply_operator without a context: the library's fixed device
+    scratch instead of a workspace (nothing is allocated).  Enqueued on the
+    given (or the tensors' current) stream; does not synchronise."""
+    import torch
+    device = h.device if isinstance(h, torch.Tensor) else None
+    view = Context(handle=None, cfg=cfg, workspace=None, device=device)
+    args = [_field(view, t, name) for t, name in ((h, "h"), (s, "s"), (out, "out"))]
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    st = load_library().sgn_apply_operator_noalloc(ctypes.byref(cfg), *args, 1 if precondition else 0,
+                                                   ctypes.c_void_p(stream.cuda_stream))
+    if st != SGN_OK:
+        lib = load_library()
+        raise SgnError(st, f"{lib.sgn_status_string(st).decode()}: {lib.sgn_last_error(None).decode()}")
 
 
 def sgn_apply_precond(ctx: Context, r, out):

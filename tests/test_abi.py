@@ -168,6 +168,28 @@ def test_cnn_and_learned_guess_host_checks():
     assert sgn.SGN_CNN_PARAMS == 6 * (9 * 32 * 32 + 32)
 
 
+def test_operator_noalloc_host_checks():
+    """The context-free operator refuses grids beyond its fixed scratch, and
+    bad or aliased fields, on the host before any GPU work (the pointers
+    below are never dereferenced)."""
+    lib = sgn.load_library()
+    p, q, r = (ctypes.c_void_p(4096 * (i + 1)) for i in range(3))
+    big = sgn.config_default(2048, 1024, 10.0, 5.0)
+    assert big.nx * big.ny > sgn.SGN_NOALLOC_MAX_POINTS
+    assert lib.sgn_apply_operator_noalloc(ctypes.byref(big), p, q, r, 0, None) == sgn.SGN_ERR_UNSUPPORTED
+    assert b"exceeds" in lib.sgn_last_error(None)
+    ok = sgn.config_default(1024, 1024, 10.0, 5.0)
+    assert lib.sgn_apply_operator_noalloc(ctypes.byref(ok), None, q, r, 0, None) == sgn.SGN_ERR_INVALID_ARG
+    assert lib.sgn_apply_operator_noalloc(ctypes.byref(ok), p, q, q, 1, None) == sgn.SGN_ERR_INVALID_ARG
+    assert lib.sgn_apply_operator_noalloc(ctypes.byref(ok), p, ctypes.c_void_p(4100), r, 0, None) \
+        == sgn.SGN_ERR_INVALID_ARG
+    ok.batch = 2
+    assert lib.sgn_apply_operator_noalloc(ctypes.byref(ok), p, q, r, 0, None) != sgn.SGN_OK
+    bad = sgn.config_default(1000, 64, 10.0, 5.0)
+    assert lib.sgn_apply_operator_noalloc(ctypes.byref(bad), p, q, r, 0, None) == sgn.SGN_ERR_UNSUPPORTED
+    assert lib.sgn_apply_operator_noalloc(None, p, q, r, 0, None) == sgn.SGN_ERR_INVALID_ARG
+
+
 def test_members_workspace_is_per_member():
     one = sgn.sgn_workspace_bytes(sgn.config_default(128, 64, 10.0, 5.0))
     for b in (2, 9, 64):
