@@ -190,6 +190,32 @@ typedef struct sgn_refine_info {
 int sgn_elliptic_solve_refined(sgn_ctx* ctx64, sgn_ctx* ctx32, const double* h, const double* b, double* sigma,
                                double tol, int32_t max_rounds, sgn_refine_info* info);
 
+typedef struct sgn_refined_step_info {
+  int64_t inner_iters;          /* FP32 GMRES iterations of the correction solves, summed */
+  int64_t rounds;               /* correction solves, summed over the stage solves */
+  int32_t solves;               /* 4 per RK4 step */
+  int32_t max_rounds_per_solve;
+  double max_rel_resid;         /* largest ||b - L sigma|| / ||b|| returned by a stage solve (FP64) */
+  double min_h;                 /* min h after the last step */
+} sgn_refined_step_info;
+
+/* nsteps RK4 steps of sgn_rk4_step in FP64 (ctx64) whose stage solves are
+ * mixed-precision iterative refinements (sgn_elliptic_solve_refined, ctx32
+ * for the FP32 corrections): each stage forms b = -div v in FP64, refines
+ * sigma from the previous stage's until ||b - L sigma|| <= tol ||b|| in the
+ * FP64 residual (at most max_rounds corrections), and computes the fluxes,
+ * the Bernoulli function, the RK4 combine and the per-step filter in FP64.
+ * So the GMRES iterations run in FP32 while sigma and the state carry FP64
+ * accuracy: the precision form's FP64 residual refinement inside the RK4
+ * step.  h, vx, vy, sigma: FP64 device fields of ctx64's grid (in place;
+ * sigma in = first warm start, out = last stage's sigma).  Contexts as for
+ * sgn_elliptic_solve_refined, batch = 1.  Uses ctx64's Krylov-basis and
+ * checkpoint fields as scratch; synchronises both streams.  Returns
+ * SGN_ERR_NOT_CONVERGED (after finishing the steps) if a stage solve did not
+ * reach tol in max_rounds corrections.  info may be NULL. */
+int sgn_rk4_step_refined(sgn_ctx* ctx64, sgn_ctx* ctx32, double* h, double* vx, double* vy, double* sigma,
+                         double dt, int32_t nsteps, double tol, int32_t max_rounds, sgn_refined_step_info* info);
+
 /* One evaluation of the right-hand side of the (h, v) system (Section 3):
  *   b = -div v;  sigma = GMRES(L_h, b; x0 = sigma);
  *   dh = -div(h v - grad sigma);  dv = -grad B,

@@ -131,6 +131,8 @@ void geom_init(const sgn_config& c, Geom& g) {
   g.row_threads = 64;
   g.status_first = 0;
   g.members = 1;
+  g.row_split = 1;
+  if (const char* rs = std::getenv("SGN_ROW_SPLIT")) g.row_split = std::atoi(rs) != 0;
   g.ws_lo = 0;
   g.ws_span = g.ws_stride = g.f_stride = 0;
   if (const char* tb = std::getenv("SGN_TILE_BLOCKS")) {
@@ -1065,6 +1067,71 @@ int sgn_elliptic_solve_refined(sgn_ctx* c64, sgn_ctx* c32, const double* h, cons
   }
   if (info) *info = inf;
   return rc;
+}
+
+int sgn_rk4_step_refined(sgn_ctx* c64, sgn_ctx* c32, double* h, double* vx, double* vy, double* sigma, double dt,
+                         int32_t nsteps, double tol, int32_t max_rounds, sgn_refined_step_info* info) {
+  if (!c64 || !c32 || c64 == c32 || !aligned(h) || !aligned(vx) || !aligned(vy) || !aligned(sigma) || nsteps < 0 ||
+      !std::isfinite(dt) || !(tol > 0.0) || !std::isfinite(tol) || max_rounds < 1)
+    return SGN_ERR_INVALID_ARG;
+  const sgn_config &a = c64->cfg, &q = c32->cfg;
+  if (a.precision != SGN_FP64 || q.precision != SGN_FP32_MIXED || a.batch != 1 || q.batch != 1)
+    return SGN_ERR_UNSUPPORTED;
+  if (a.nx != q.nx || a.ny != q.ny || a.Lx != q.Lx || a.Ly != q.Ly || a.g != q.g || a.h_inf != q.h_inf ||
+      c64->device != c32->device)
+    return SGN_ERR_INVALID_ARG;
+  if (c64->learn_net || c64->learn_rec) return SGN_ERR_UNSUPPORTED;
+  sgn_ctx* ctx = c64;  // for HIPCK
+  const sgn::Geom& g = c64->g;
+  hipStream_t s = c64->stream;
+  const size_t n = (size_t)g.nx * g.ny;
+  int rc = check_state(c64, h, vx, vy);
+  if (rc) return rc;
+  // scratch in c64's Krylov basis, which this call never fills: the
+  // divergence terms and b (V_0 .. V_2) and the warm-start chain of sigma (V_3)
+  char* V = static_cast<char*>(c64->V);
+  const size_t fb = c64->field_bytes;
+  double* t1 = reinterpret_cast<double*>(V);
+  double* t2 = reinterpret_cast<double*>(V + fb);
+  double* b = reinterpret_cast<double*>(V + 2 * fb);
+  double* sg = reinterpret_cast<double*>(V + 3 * fb);
+  HIPCK(hipMemcpyAsync(sg, sigma, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  sgn_refined_step_info inf{};
+  inf.max_rel_resid = 0.0;
+  bool unconv = false;
+  for (int step = 0; step < nsteps; ++step) {
+    for (int stage = 0; stage < 4; ++stage) {
+      const double* ih = stage == 0 ? h : static_cast<const double*>(c64->hs);
+      const double* ivx = stage == 0 ? vx : static_cast<const double*>(c64->vxs);
+      const double* ivy = stage == 0 ? vy : static_cast<const double*>(c64->vys);
+      // b = -div v in FP64
+      HIPCK(sgn::launch_row_dx(g, ivx, t1, s));
+      HIPCK(sgn::launch_col_dy(g, ivy, t2, s));
+      HIPCK(sgn::launch_neg_sum(t1, t2, b, n, s));
+      // sigma from the previous stage's, refined to tol in the FP64 residual
+      sgn_refine_info ri{};
+      rc = sgn_elliptic_solve_refined(c64, c32, ih, b, sg, tol, max_rounds, &ri);
+      if (rc && rc != SGN_ERR_NOT_CONVERGED) return rc;
+      unconv = unconv || rc == SGN_ERR_NOT_CONVERGED;
+      inf.solves += 1;
+      inf.rounds += ri.rounds;
+      inf.inner_iters += ri.inner_iters;
+      inf.max_rounds_per_solve = std::max(inf.max_rounds_per_solve, ri.rounds);
+      inf.max_rel_resid = std::max(inf.max_rel_resid, ri.rel_resid_true);
+      // fluxes, Bernoulli function and the stage combine in FP64 from sigma
+      if ((rc = load_sigma(c64, sg))) return rc;
+      if ((rc = enqueue_stage_flux(c64, stage, dt, h, vx, vy, ih, ivx, ivy))) return rc;
+    }
+    if ((rc = enqueue_step_filter(c64, h, vx, vy))) return rc;
+  }
+  HIPCK(hipMemcpyAsync(sigma, sg, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCK(sgn::launch_field_stats(g, h, vx, vy, n, c64->st, c64->partials, s));
+  if ((rc = read_status(c64))) return rc;
+  inf.min_h = c64->hstat->stat_minh;
+  if (info) *info = inf;
+  if (c64->hstat->stat_nonfinite) return SGN_ERR_NONFINITE;
+  if (!(c64->hstat->stat_minh > 0.0)) return SGN_ERR_CAVITATION;
+  return unconv ? SGN_ERR_NOT_CONVERGED : SGN_OK;
 }
 
 int sgn_rhs(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, void* sigma, void* dh, void* dvx,

@@ -32,6 +32,7 @@ struct Geom {
   // member m's workspace is member 0's [ws_lo, ws_lo + ws_span) moved by
   // m * ws_stride bytes, its caller fields are member 0's moved by m * f_stride
   int members;             // 1 for a single grid
+  int row_split;           // 1: with several members, the Arnoldi row kernel in blocks of two chains
   uintptr_t ws_lo;
   size_t ws_span, ws_stride, f_stride;
 };

@@ -759,6 +759,98 @@ __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __rest
   }
 }
 
+// The same result as k_row_matvec3 with the three chains spread over blocks
+// of two chains (2 TPF threads), so that two blocks fit a CU where one
+// three-chain block does (the kernel needs about 126 VGPRs in FP64: four
+// waves per SIMD).  Blocks 0 .. npairs-1 run chains 0 and 1 of row pair
+// blockIdx.x and form A1 = chain 0 + chain 1 through LDS; blocks npairs ..
+// npairs + npairs/2 - 1 run chain 2 (A2) for two row pairs, one per thread
+// group.  Block: (TPF, 2); grid.x = npairs + npairs / 2 (npairs even).
+template <int N, bool SF>
+__global__ void __launch_bounds__(512) k_row_matvec2(Geom g, const cplx* __restrict__ Es, const cplx* __restrict__ Gs,
+                                                     const real* __restrict__ h, cplx* __restrict__ P,
+                                                     cplx* __restrict__ Q, const GmresState* st) {
+  Es = mshift(g, Es); Gs = mshift(g, Gs); h = mshift(g, h); P = mshift(g, P); Q = mshift(g, Q);
+  st = mshift(g, st);
+  if (SF && st->st.done) return;
+  constexpr int E = Row<N>::E;
+  constexpr int TPF = Row<N>::TPF;
+  constexpr int H = N / 2;
+  const RowMap map;
+  extern __shared__ cplx lds[];
+  const int t = threadIdx.x;
+  const int npairs = g.ny / 2;
+  const bool a1 = (int)blockIdx.x < npairs;  // chains 0 and 1 of one row pair, else chain 2 of two
+  const int chain = a1 ? threadIdx.y : 2;
+  const int ya = a1 ? 2 * blockIdx.x : 2 * (2 * (blockIdx.x - npairs) + threadIdx.y);
+  cplx* buf = lds + threadIdx.y * Row<N>::LDS;
+  TwiddleSet<N> twx;
+  gather_twiddles<N>(twx, t, TWX(g));
+  cplx v[E], hi[E];
+  load_spec_pair<N>(v, chain == 2 ? Gs : Es, ya, t, g.inv_nx);
+  load_phys_pair<N>(hi, h, ya, t);
+  if (st->st.done) return;  // tested after the (in-bounds) loads are issued
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    hi[r] = make_cplx(1.0 / hi[r].x, 1.0 / hi[r].y);
+    if (chain == 1) v[r] = mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Lx));
+  }
+  fft<N, true, RowMap>(v, buf, t, twx, map);
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const double ia = hi[r].x, ib = hi[r].y;
+    if (chain == 0)
+      v[r] = make_cplx(3.0 * v[r].x * ia * ia * ia, 3.0 * v[r].y * ib * ib * ib);
+    else
+      v[r] = make_cplx(v[r].x * ia, v[r].y * ib);
+  }
+  fft<N, false, RowMap>(v, buf, t, twx, map);
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    if (chain == 1) v[r] = mul_ik(v[r], -wavenumber(t + r * TPF, N, g.inv_Lx));
+    buf[map.at(t + r * TPF)] = v[r];
+  }
+  __syncthreads();
+  auto emit = [&](cplx* S, int k, cplx z, cplx zc) {
+    cplx* A = S + (size_t)ya * H;
+    cplx* B = A + H;
+    A[k] = make_cplx(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
+    B[k] = make_cplx(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
+  };
+  if (a1) {
+    // A1 = chain 0 + chain 1, each group unpacking every other k
+    const cplx* b0 = lds;
+    const cplx* b1 = lds + Row<N>::LDS;
+    auto at_A1 = [&](int k) { return cadd(b0[map.at(k)], b1[map.at(k)]); };
+#pragma unroll
+    for (int r = 0; r < E / 2; ++r) {
+      if (r % 2 != (int)threadIdx.y) continue;
+      const int k = t + r * TPF;
+      if (k == 0) {
+        const cplx z0 = at_A1(0), zn = at_A1(H);
+        cplx* A = P + (size_t)ya * H;
+        A[0] = make_cplx(z0.x, zn.x);
+        A[H] = make_cplx(z0.y, zn.y);
+      } else {
+        emit(P, k, at_A1(k), at_A1(N - k));
+      }
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < E / 2; ++r) {
+      const int k = t + r * TPF;
+      if (k == 0) {
+        const cplx z0 = buf[map.at(0)], zn = buf[map.at(H)];
+        cplx* A = Q + (size_t)ya * H;
+        A[0] = make_cplx(z0.x, zn.x);
+        A[H] = make_cplx(z0.y, zn.y);
+      } else {
+        emit(Q, k, buf[map.at(k)], buf[map.at(N - k)]);
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ void rk_one(const RkStage& rk, const RkField& f, size_t i, double k) {
   real* out = static_cast<real*>(f.out);
   real* acc = static_cast<real*>(f.acc);
@@ -2452,6 +2544,16 @@ static hipError_t row_matvec3_n(const Geom& g, const cplx* E, const cplx* G, con
     const int r = Chain<N>::rpb(g);
     const dim3 block(Row<N>::TPF, 3 * r);
     const size_t lb = (size_t)3 * r * Row<N>::LDS * sizeof(cplx);
+    if (g.members > 1 && 2 * Row<N>::TPF <= 512 && (g.ny / 2) % 2 == 0 && g.row_split) {
+      // several grids per launch: blocks of two chains, two of which share a CU
+      const int np = g.ny / 2;
+      const size_t lb2 = (size_t)2 * Row<N>::LDS * sizeof(cplx);
+      auto* const k2 = g.status_first ? &k_row_matvec2<N, true> : &k_row_matvec2<N, false>;
+      hipError_t e2 = allow_lds(reinterpret_cast<const void*>(k2), lb2);
+      if (e2 != hipSuccess) return e2;
+      launch(k2, dim3(np + np / 2), dim3(Row<N>::TPF, 2), lb2, s, g, E, G, h, P, Q, st);
+      return hipGetLastError();
+    }
     // the status tested first in captured graphs, after the loads otherwise
     auto* const kf = g.status_first ? &k_row_matvec3<N, true> : &k_row_matvec3<N, false>;
     hipError_t e = allow_lds(reinterpret_cast<const void*>(kf), lb);

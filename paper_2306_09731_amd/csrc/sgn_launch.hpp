@@ -144,6 +144,8 @@ hipError_t launch_to_f32(const double* in, float* out, size_t n, hipStream_t s);
 hipError_t launch_refine_resid(const double* b, double* r, float* r32, size_t n, double* partials, int nblocks,
                                hipStream_t s);
 hipError_t launch_refine_update(double* sigma, const float* d, size_t n, hipStream_t s);
+// out = -(a + c), n points (FP64).
+hipError_t launch_neg_sum(const double* a, const double* c, double* out, size_t n, hipStream_t s);
 
 // Largest number of blocks any reduction kernel launches for this grid.
 int max_partial_blocks(const Geom& g);

@@ -58,6 +58,13 @@ __global__ void __launch_bounds__(kThreads) k_refine_update(double* __restrict__
   if (i < n) sigma[i] += (double)d[i];
 }
 
+// out[i] = -(a[i] + c[i]) (the divergence from its two derivative terms).
+__global__ void __launch_bounds__(kThreads) k_neg_sum(const double* __restrict__ a, const double* __restrict__ c,
+                                                      double* __restrict__ out, size_t n) {
+  const size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) out[i] = -(a[i] + c[i]);
+}
+
 unsigned blocks_for(size_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
@@ -70,6 +77,11 @@ hipError_t launch_to_f32(const double* in, float* out, size_t n, hipStream_t s) 
 hipError_t launch_refine_resid(const double* b, double* r, float* r32, size_t n, double* partials, int nblocks,
                                hipStream_t s) {
   hipLaunchKernelGGL(k_refine_resid, dim3(nblocks), dim3(kThreads), 0, s, b, r, r32, n, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_neg_sum(const double* a, const double* c, double* out, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_neg_sum, dim3(blocks_for(n)), dim3(kThreads), 0, s, a, c, out, n);
   return hipGetLastError();
 }
 

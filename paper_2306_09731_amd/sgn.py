@@ -65,6 +65,12 @@ class sgn_refine_info(ctypes.Structure):
                 ("rel_resid_first", ctypes.c_double), ("rel_resid_true", ctypes.c_double)]
 
 
+class sgn_refined_step_info(ctypes.Structure):
+    _fields_ = [("inner_iters", ctypes.c_int64), ("rounds", ctypes.c_int64), ("solves", ctypes.c_int32),
+                ("max_rounds_per_solve", ctypes.c_int32), ("max_rel_resid", ctypes.c_double),
+                ("min_h", ctypes.c_double)]
+
+
 class sgn_step_info(ctypes.Structure):
     _fields_ = [
         ("total_iters", ctypes.c_int64), ("max_iters_per_solve", ctypes.c_int32),
@@ -96,6 +102,8 @@ _SIGNATURES = {
     "sgn_launch_shape": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32)]),
     "sgn_elliptic_solve_refined": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
                                                   ctypes.POINTER(sgn_refine_info)]),
+    "sgn_rk4_step_refined": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
+                                            ctypes.c_double, ctypes.c_int32, ctypes.POINTER(sgn_refined_step_info)]),
     "sgn_rk4_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
                                     ctypes.POINTER(sgn_step_info)]),
     "sgn_rk4_step_graph": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
@@ -301,6 +309,18 @@ def sgn_rk4_step(ctx: Context, h, vx, vy, sigma, dt: float, nsteps: int = 1):
                                      int(nsteps), info)
     _check(ctx, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
     return _one_or_list(ctx, info)
+
+
+def sgn_rk4_step_refined(ctx64: Context, ctx32: Context, h, vx, vy, sigma, dt: float, nsteps: int = 1,
+                         tol: float = 1e-10, max_rounds: int = 8) -> sgn_refined_step_info:
+    """FP64 RK4 steps whose stage solves are FP32-corrected refinements (FP64 fields of ctx64's grid)."""
+    info = sgn_refined_step_info()
+    st = load_library().sgn_rk4_step_refined(ctx64.handle, ctx32.handle, _field(ctx64, h, "h"),
+                                             _field(ctx64, vx, "vx"), _field(ctx64, vy, "vy"),
+                                             _field(ctx64, sigma, "sigma"), float(dt), int(nsteps), float(tol),
+                                             int(max_rounds), ctypes.byref(info))
+    _check(ctx64, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
+    return info
 
 
 def sgn_rk4_step_graph(ctx: Context, h, vx, vy, sigma, dt: float, nsteps: int = 1, iter_budget: int = 0):

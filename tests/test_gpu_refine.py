@@ -119,3 +119,32 @@ def test_refined_solve_argument_errors():
         sgn.sgn_elliptic_solve_refined(c64, c32, h, z, z.clone(), 0.0, 4)
     with pytest.raises(sgn.SgnError):
         sgn.sgn_elliptic_solve_refined(c64, c32, h, z, z.clone(), 1e-10, 0)
+
+
+def test_refined_rk4_step_matches_oracle_and_fp64():
+    """20 RK4 steps of a perturbed soliton on 256x128 with every stage solve
+    refined to 1e-12 (FP32 GMRES corrections, FP64 residuals, FP64 fluxes and
+    RK combine): against the oracle's 20 steps at GMRES tol 1e-12 and the FP64
+    path's at the same tolerance, both within the FP64 parity gate 1e-10."""
+    nx, ny = 256, 128
+    box = Box(nx, ny, 10.0 * nx / 1024, 5.0 * ny / 512)
+    h, vx, vy, s = perturbed_line_soliton(box, a=0.5, eps=0.01, k=2, x0=-0.5 * np.pi * box.Lx)
+    c64, c32 = contexts(nx, ny, box.Lx, box.Ly)
+    f = [dev(a) for a in (h, vx, vy, s)]
+    info = sgn.sgn_rk4_step_refined(c64, c32, *f, 0.005, 20, 1e-12, 8)
+    got = [t.cpu().numpy() for t in f]
+    c64b = sgn.sgn_init(sgn.config_default(nx, ny, box.Lx, box.Ly, gmres_tol=1e-12), DEV)
+    f64 = [dev(a) for a in (h, vx, vy, s)]
+    sgn.sgn_rk4_step(c64b, *f64, 0.005, 20)
+    ref64 = [t.cpu().numpy() for t in f64]
+    g = O.Grid(O.Config(nx=nx, ny=ny, Lx=box.Lx, Ly=box.Ly, gmres_tol=1e-12))
+    oh, ovx, ovy, _, _ = O.rk4(g, h, vx, vy, s, 0.005, 20)
+    eh = np.abs(got[0] - oh).max() / np.abs(oh - 1.0).max()
+    ev = np.abs(got[1] - ovx).max() / np.abs(ovx).max()
+    e64 = max(np.abs(got[0] - ref64[0]).max() / np.abs(ref64[0] - 1.0).max(),
+              np.abs(got[1] - ref64[1]).max() / np.abs(ref64[1]).max())
+    say(f"refined rk4 x20 256x128: rounds {info.rounds} over {info.solves} solves "
+        f"(max {info.max_rounds_per_solve}), FP32 iterations {info.inner_iters}, worst residual "
+        f"{info.max_rel_resid:.1e}; vs oracle h {eh:.1e} vx {ev:.1e}; vs FP64 path {e64:.1e}")
+    assert info.solves == 80 and info.max_rel_resid <= 1e-12
+    assert eh < 1e-10 and ev < 1e-10 and e64 < 1e-10
