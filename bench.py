@@ -2,17 +2,22 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
-Workload: the 1024x512 transversely perturbed line soliton (a = 0.5,
-eps = 0.01, k = 2, x0 = -10) on [-10pi, 10pi] x [-5pi, 5pi], FP64, RK4 with
-dt = 0.005, GMRES tol 1e-10, restart 20, Krasny filter 1e-12.  W untimed
-warm-up steps, then K timed steps (one library call), bracketed by
-device synchronisations; inputs are resident on the GPU before timing.
+Workload: the 1024x512 transversely perturbed line solitons on
+[-10pi, 10pi] x [-5pi, 5pi] (x0 = -10, eps = 0.01), all nine runs
+a in {0.2, 0.5, 1.0} x k in {1, 2, 4} advanced together as the members of one
+ensemble context (every kernel launch covers the nine grids, each with its
+own GMRES state), FP64, RK4 with dt = 0.005, GMRES tol 1e-10, restart 20,
+Krasny filter 1e-12.  W untimed warm-up steps, then K timed steps (one
+library call), bracketed by device synchronisations; inputs are resident on
+the GPU before timing.
 
-Prints one JSON line: grid-points x RK4 steps per second, GMRES iterations
-per solve, a roofline entry for the dominant kernel (algorithmic bytes per
-launch / its mean duration from HIP events recorded by the library on its
-stream during the timed steps), and the FP64 oracle timed on the host CPU on
-a bounded sample of the same workload.
+Prints one JSON line: grid-points x RK4 steps per second over the nine runs,
+GMRES iterations per solve (overall and per run), a roofline entry for the
+dominant kernel (algorithmic bytes per launch / its mean duration from HIP
+events recorded by the library on its stream during the timed steps), the
+same run one grid per context, the nine runs to t = 20 with their mass and
+energy drift, the other forms of the build, and the FP64 oracle timed on the
+host CPU on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -31,7 +36,8 @@ METRIC = "grid-pts×RK4 steps/s at GMRES tol; iters/solve, plain vs learned"
 UNIT = "grid-pts×RK4 steps/s"
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "perturbed_soliton_1024x512"
-PARAMS = dict(a=0.5, eps=0.01, k=2)
+SWEEP_WORKLOAD = "perturbed_soliton_1024x512_sweep"
+PARAMS = dict(a=0.5, eps=0.01, k=2)  # the run of the nine timed alone (single_grid, cpu_baseline)
 KRASNY = 1e-12
 
 # The roofline entry is for the kernel class with the largest share of device
@@ -51,7 +57,15 @@ def parse():
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--main-only", action="store_true",
-                   help="time only the headline 1024x512 run (no guess, precision or batched forms; for profiler runs)")
+                   help="time only the headline nine-run ensemble (no other forms; for profiler runs)")
+    p.add_argument("--single-only", action="store_true",
+                   help="time only the single 1024x512 grid (a = 0.5, k = 2; for profiler runs)")
+    p.add_argument("--precision-only", action="store_true",
+                   help="time only the 2048^2 precision form (for profiler runs)")
+    p.add_argument("--t5-steps", type=int, default=1000,
+                   help="steps of the 2048^2 precision comparison at t = 5 (dt = 0.005; 0 skips it)")
+    p.add_argument("--t20-steps", type=int, default=4000,
+                   help="steps of the nine-run to-t=20 leg (dt = 0.005; 0 skips it)")
     p.add_argument("--cpu-steps", type=int, default=5)
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of MIB MiB, --steps times (calibrates the "
@@ -74,11 +88,11 @@ def copy_calibration(mib: int, reps: int):
                       "gb_per_s": 2 * n * 8 * reps / dt / 1e9}), flush=True)
 
 
-def traffic_ratio_from_profile(kernel: str):
+def traffic_ratio_from_profile(kernel: str, workload: str = SWEEP_WORKLOAD):
     """Measured HBM bytes / algorithmic bytes of the kernel, from the rocprofv3
     FETCH_SIZE and WRITE_SIZE counters summarised in profiles/, if that summary
     was taken on the kernel source currently in the tree (else None)."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{WORKLOAD}_counters.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.txt")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -100,26 +114,147 @@ def kernel_source_hash() -> str:
     return d.hexdigest()
 
 
-def timed_guess_run(sgn, torch, box, state, w, dev, args):
-    """K timed steps (after W warm-up steps) of the same workload with
+def timed_kernel_run(sgn, torch, ctx, fields, dt, steps, kind=None, period=EVENT_PERIOD):
+    """steps timed RK4 steps in one call; with kind, every period-th launch of
+    that kernel class carries HIP events.  Returns (elapsed s, infos list,
+    (launches, total ms, algorithmic bytes) or None)."""
+    if kind is not None:
+        sgn.sgn_kernel_timing(ctx, kind, True, period)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = sgn.sgn_rk4_step(ctx, *fields, dt, steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = None
+    if kind is not None:
+        kt = sgn.sgn_kernel_time(ctx, kind)  # events recorded at dispatch start/end
+        sgn.sgn_kernel_timing(ctx, kind, False)
+    return el, (info if isinstance(info, list) else [info]), kt
+
+
+def iters_summary(infos):
+    return {"iters_per_solve_mean": sum(i.total_iters for i in infos) / max(sum(i.solves for i in infos), 1),
+            "iters_per_solve_max": max(i.max_iters_per_solve for i in infos),
+            "solves": sum(i.solves for i in infos)}
+
+
+def roofline_entry(kernel: str, kt, workload: str):
+    launches, kms, algo_total = kt
+    algo = algo_total / launches if launches else 0.0  # per launch, averaged over all timed launches
+    mean_s = (kms / launches) / 1e3 if launches else float("nan")
+    achieved = algo / mean_s / 1e9 if launches else None
+    ratio = traffic_ratio_from_profile(DOMINANT, workload)
+    traffic = ratio * algo if (ratio is not None and launches) else None  # HBM bytes per launch
+    return {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+            "algorithmic_bytes_per_launch": algo, "mean_launch_us": mean_s * 1e6, "launches": launches,
+            "events_on_every": EVENT_PERIOD}
+
+
+def sweep_context(sgn, torch, dev, guess=None):
+    """The nine runs as one ensemble context and its [9][ny][nx] fields."""
+    from sgn_inputs import perturbed_soliton_sweep
+    box, state, ak, w = perturbed_soliton_sweep(eps=PARAMS["eps"])
+    kw = dict(gmres_tol=w["tol"], gmres_restart=w["restart"], krasny=KRASNY, batch=len(ak))
+    if guess is not None:
+        kw["guess"] = guess
+    cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, **kw)
+    ctx = sgn.sgn_init(cfg, dev)
+    f = [torch.from_numpy(a).to(dev).contiguous() for a in state]
+    return box, ak, w, ctx, f
+
+
+def timed_guess_run(sgn, torch, dev, args):
+    """K timed steps (after W warm-up steps) of the nine runs with
     SGN_GUESS_STAGE_INCREMENT: each RK stage starts GMRES from the previous
     stage's sigma plus that stage's increment in the previous step."""
+    box, ak, w, ctx, f = sweep_context(sgn, torch, dev, guess=sgn.SGN_GUESS_STAGE_INCREMENT)
+    if args.warmup > 0:
+        sgn.sgn_rk4_step(ctx, *f, w["dt"], args.warmup)
+    el, infos, _ = timed_kernel_run(sgn, torch, ctx, f, w["dt"], args.steps)
+    ctx.close()
+    out = {"value": len(ak) * box.nx * box.ny * args.steps / el, "ms_per_step": el * 1e3 / args.steps}
+    out.update(iters_summary(infos))
+    out["note"] = "same tolerance; the first step of each call uses the plain warm start"
+    return out
+
+
+def single_grid_run(sgn, torch, dev, args, with_roofline=True):
+    """The run a = 0.5, k = 2 alone on a context of its own (one grid per
+    launch): K timed steps after W warm-up steps, kernel B timed."""
+    from sgn_inputs import workload
+    box, state, w = workload(WORKLOAD, **PARAMS)
     cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"], gmres_restart=w["restart"],
-                             krasny=KRASNY, guess=sgn.SGN_GUESS_STAGE_INCREMENT)
+                             krasny=KRASNY)
     ctx = sgn.sgn_init(cfg, dev)
     f = [torch.from_numpy(a).to(dev).contiguous() for a in state]
     if args.warmup > 0:
         sgn.sgn_rk4_step(ctx, *f, w["dt"], args.warmup)
+    kind = [k for k, v in sgn.KERNEL_NAMES.items() if v == DOMINANT][0]
+    el, infos, kt = timed_kernel_run(sgn, torch, ctx, f, w["dt"], args.steps, kind if with_roofline else None)
+    ctx.close()
+    out = {"workload": WORKLOAD, "a": PARAMS["a"], "k": PARAMS["k"],
+           "value": box.nx * box.ny * args.steps / el, "ms_per_step": el * 1e3 / args.steps}
+    out.update(iters_summary(infos))
+    if kt:
+        out["roofline"] = roofline_entry(f"k_row_matvec3<{box.nx}> (kernel B), one grid per launch", kt, WORKLOAD)
+    return out
+
+
+def sweep_single(sgn, torch, dev, args):
+    """Each of the nine runs on a context of its own, one after another: K
+    timed steps each (after W warm-up steps)."""
+    import numpy as np
+    from sgn_inputs import perturbed_soliton_sweep
+    box, state, ak, w = perturbed_soliton_sweep(eps=PARAMS["eps"])
+    cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"], gmres_restart=w["restart"],
+                             krasny=KRASNY)
+    runs, total = [], 0.0
+    for m, (a, k) in enumerate(ak):
+        ctx = sgn.sgn_init(cfg, dev)
+        f = [torch.from_numpy(np.ascontiguousarray(x[m])).to(dev) for x in state]
+        if args.warmup > 0:
+            sgn.sgn_rk4_step(ctx, *f, w["dt"], args.warmup)
+        el, infos, _ = timed_kernel_run(sgn, torch, ctx, f, w["dt"], args.steps)
+        ctx.close()
+        total += el
+        r = {"a": a, "k": k, "value": box.nx * box.ny * args.steps / el, "ms_per_step": el * 1e3 / args.steps}
+        r.update(iters_summary(infos))
+        runs.append(r)
+    return {"runs": runs, "value": len(ak) * box.nx * box.ny * args.steps / total,
+            "ms_per_step": total * 1e3 / args.steps,
+            "note": "the nine runs one after another, one grid per context; value over all nine"}
+
+
+def sweep_to_t20(sgn, torch, dev, steps):
+    """The nine runs from t = 0 as one ensemble context for `steps` steps of
+    dt = 0.005 (4000: t = 20): wall time, iterations, and each run's mass and
+    energy drift (invariants of Section 2.3 at the start and the end)."""
+    box, ak, w, ctx, f = sweep_context(sgn, torch, dev)
+    inv0 = sgn.sgn_invariants(ctx, *[t.clone() for t in f])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    info = sgn.sgn_rk4_step(ctx, *f, w["dt"], args.steps)
+    try:
+        info = sgn.sgn_rk4_step(ctx, *f, w["dt"], steps)
+        status = "ok"
+    except sgn.SgnError as e:
+        info, status = None, str(e)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    out = {"steps": steps, "t_end": steps * w["dt"], "status": status, "wall_s": el,
+           "value": len(ak) * box.nx * box.ny * steps / el}
+    if info is None:
+        ctx.close()
+        return out
+    inv1 = sgn.sgn_invariants(ctx, *f)
+    out.update(iters_summary(info))
+    out["runs"] = [{"a": a, "k": k, "mass_drift": abs(i1["mass"] - i0["mass"]) / abs(i0["mass"]),
+                    "energy_drift": abs(i1["energy"] - i0["energy"]) / abs(i0["energy"]),
+                    "max_h": i1["max_h"], "spectral_tail": i1["spectral_tail"],
+                    "iters_per_solve_mean": inf.total_iters / max(inf.solves, 1)}
+                   for (a, k), i0, i1, inf in zip(ak, inv0, inv1, info)]
     ctx.close()
-    return {"value": box.nx * box.ny * args.steps / el, "ms_per_step": el * 1e3 / args.steps,
-            "iters_per_solve_mean": info.total_iters / max(info.solves, 1),
-            "iters_per_solve_max": info.max_iters_per_solve,
-            "note": "same tolerance; the first step of each call uses the plain warm start"}
+    return out
 
 
 def graph_form(sgn, torch, box, state, w, dev, args):
@@ -168,6 +303,27 @@ def learned_form(sgn, torch, dev, args):
 
 
 PRECISION_WORKLOAD = "gaussian_2048x2048"
+_COPY_PEAK = {}
+
+
+def copy_peak_gbs(torch, dev, mib: int = 1024, reps: int = 20):
+    """Attainable HBM bandwidth: a device-to-device copy of 1 GiB (read and
+    write counted), best of `reps`."""
+    if "v" not in _COPY_PEAK:
+        n = mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.copy_(a)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            best = el if best is None or el < best else best
+        _COPY_PEAK["v"] = 2 * n * 8 / best / 1e9
+        del a, b
+    return _COPY_PEAK["v"]
 
 
 def precision_form(sgn, torch, dev, args):
@@ -200,32 +356,105 @@ def precision_form(sgn, torch, dev, args):
         final[name] = [t.double().cpu().numpy() for t in f[:2]]
         if prec == sgn.SGN_FP64:
             state_after = [t.clone() for t in f[:3]]
-        if prec == sgn.SGN_FP32_MIXED:
-            # time every Arnoldi kernel class over the same number of further steps
-            per = {}
-            for kind in (0, 1, 2, 3):
-                sgn.sgn_kernel_timing(ctx, kind, True)
-                sgn.sgn_rk4_step(ctx, *[t.clone() for t in f], w["dt"], steps)
-                n, ms, by = sgn.sgn_kernel_time(ctx, kind)
-                sgn.sgn_kernel_timing(ctx, kind, False)
-                if n:
-                    per[sgn.KERNEL_NAMES[kind]] = (n, ms, by)
-            dom = max(per, key=lambda k: per[k][1])
-            n, ms, by = per[dom]
-            ach = by / (ms * 1e-3) / 1e9 if ms else None
-            res["roofline"] = {"kernel_class": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                               "unit": "GB/s", "frac": ach / HBM_PEAK_GBS if ach else None,
-                               "traffic": None, "algorithmic_bytes_per_launch": by / n,
-                               "mean_launch_us": ms / n * 1e3, "launches": n,
-                               "share_of_arnoldi_kernel_time": ms / sum(v[1] for v in per.values())}
+        # time every Arnoldi kernel class over the same number of further steps
+        per = {}
+        for kind in (0, 1, 2, 3):
+            sgn.sgn_kernel_timing(ctx, kind, True)
+            sgn.sgn_rk4_step(ctx, *[t.clone() for t in f], w["dt"], steps)
+            n, ms, by = sgn.sgn_kernel_time(ctx, kind)
+            sgn.sgn_kernel_timing(ctx, kind, False)
+            if n:
+                per[sgn.KERNEL_NAMES[kind]] = (n, ms, by)
+        dom = max(per, key=lambda k: per[k][1])
+        n, ms, by = per[dom]
+        ach = by / (ms * 1e-3) / 1e9 if ms else None
+        ratio = traffic_ratio_from_profile(dom, f"{PRECISION_WORKLOAD}_{name}")
+        res["roofline"] = {"kernel_class": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": ach / HBM_PEAK_GBS if ach else None,
+                           "traffic": ratio * by / n if ratio is not None else None,
+                           "algorithmic_bytes_per_launch": by / n, "mean_launch_us": ms / n * 1e3, "launches": n,
+                           "share_of_arnoldi_kernel_time": ms / sum(v[1] for v in per.values()),
+                           "attainable_copy_gbs": copy_peak_gbs(torch, dev),
+                           "classes": {k: {"launches": v[0], "mean_launch_us": v[1] / v[0] * 1e3,
+                                           "achieved": v[2] / (v[1] * 1e-3) / 1e9 if v[1] else None}
+                                       for k, v in per.items()}}
         out[name] = res
         ctx.close()
     out["refined_solve"] = refined_solve_form(sgn, torch, dev, box, state_after, w["tol"])
+    out["refined_step"] = refined_step_form(sgn, torch, dev, box, state, w, steps, warm)
+    if args.t5_steps > 0:
+        out["errors_at_t5"] = t5_errors(sgn, torch, dev, box, state, w, args.t5_steps)
     h64, v64 = final["fp64"]
     h32, v32 = final["fp32_mixed"]
     out["fp32_vs_fp64_after_steps"] = {
         "h": float(np.abs(h32 - h64).max() / np.abs(h64 - 1.0).max()),
         "vx": float(np.abs(v32 - v64).max() / max(np.abs(v64).max(), 1e-300))}
+    return out
+
+
+def refined_step_form(sgn, torch, dev, box, state, w, steps, warm):
+    """The precision form's FP64 residual refinement inside the RK4 step
+    (sgn_rk4_step_refined): FP64 state, fluxes and RK combine, every stage
+    solve refined to the FP64 tolerance from FP32 GMRES corrections; K timed
+    steps after the warm-up, beside the FP64 step at the same tolerance."""
+    import numpy as np
+    c64 = sgn.sgn_init(sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"], krasny=KRASNY), dev)
+    c32 = sgn.sgn_init(sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=1e-6, krasny=KRASNY,
+                                          precision=sgn.SGN_FP32_MIXED), dev)
+    f = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in state]
+    if warm:
+        sgn.sgn_rk4_step_refined(c64, c32, *f, w["dt"], warm, w["tol"], 8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = sgn.sgn_rk4_step_refined(c64, c32, *f, w["dt"], steps, w["tol"], 8)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    c64.close()
+    c32.close()
+    return {"value": box.nx * box.ny * steps / el, "unit": UNIT, "ms_per_step": el * 1e3 / steps,
+            "tol": w["tol"], "rounds_per_solve": info.rounds / max(info.solves, 1),
+            "fp32_iters_per_solve": info.inner_iters / max(info.solves, 1),
+            "max_rel_resid_true": info.max_rel_resid}
+
+
+def t5_errors(sgn, torch, dev, box, state, w, nsteps):
+    """The 2048^2 Gaussian from t = 0 for nsteps steps (1000: t = 5) in FP64
+    (tol 1e-10), in the mixed-precision mode (FP32 state, GMRES at 1e-6) and
+    with the refined step (FP64 state, stage solves refined to 1e-10): each
+    field's difference from the FP64 run, relative to max |h - 1|, to the
+    velocity scale max |v| of the FP64 run and to max |sigma|, and each run's
+    wall time."""
+    import numpy as np
+    runs = {}
+    for name in ("fp64", "fp32_mixed", "fp64_refined"):
+        prec = sgn.SGN_FP32_MIXED if name == "fp32_mixed" else sgn.SGN_FP64
+        dtype = torch.float32 if name == "fp32_mixed" else torch.float64
+        ctx = sgn.sgn_init(sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"], krasny=KRASNY,
+                                              precision=prec), dev)
+        c32 = None
+        if name == "fp64_refined":
+            c32 = sgn.sgn_init(sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=1e-6, krasny=KRASNY,
+                                                  precision=sgn.SGN_FP32_MIXED), dev)
+        f = [torch.from_numpy(np.ascontiguousarray(a)).to(dev).to(dtype) for a in state]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if c32 is None:
+            sgn.sgn_rk4_step(ctx, *f, w["dt"], nsteps)
+        else:
+            sgn.sgn_rk4_step_refined(ctx, c32, *f, w["dt"], nsteps, w["tol"], 8)
+        torch.cuda.synchronize()
+        runs[name] = ([t.double().cpu().numpy() for t in f], time.perf_counter() - t0)
+        ctx.close()
+        if c32 is not None:
+            c32.close()
+    ref = runs["fp64"][0]
+    vs = max(np.abs(ref[1]).max(), np.abs(ref[2]).max())
+    out = {"steps": nsteps, "t": nsteps * w["dt"], "wall_s": {k: v[1] for k, v in runs.items()}}
+    for name in ("fp32_mixed", "fp64_refined"):
+        a = runs[name][0]
+        out[name] = {"h": float(np.abs(a[0] - ref[0]).max() / np.abs(ref[0] - 1.0).max()),
+                     "v": float(max(np.abs(a[1] - ref[1]).max(), np.abs(a[2] - ref[2]).max()) / vs),
+                     "sigma": float(np.abs(a[3] - ref[3]).max() / np.abs(ref[3]).max())}
     return out
 
 
@@ -273,58 +502,129 @@ def refined_solve_form(sgn, torch, dev, box, state, tol, reps: int = 3):
 def batched_form(sgn, torch, dev, args, per_grid: int = 16):
     """64 perturbed line solitons, 16 on each of 256x256, 512x512, 1024x512 and
     1024x1024 (dx = dy = pi/16, seeded amplitudes and transverse perturbations),
-    in the mixed-precision mode: each member has its own context and stream,
-    the Arnoldi schedule comes from the autotuner, and K steps of all members
-    run as one sgn_rk4_step_ensemble call; the same steps run one member after
-    another give the sequential rate, and with graph replays per member
-    (sgn_rk4_step_ensemble_graph) the graph rate."""
+    in the mixed-precision mode, K steps after a warm-up step:
+      members: one ensemble context per grid size (16 members each, every
+        kernel launch covers the 16 grids), the four contexts on four streams
+        driven by four host threads;
+      members_serial: the same four contexts one after another on one stream;
+      contexts: the 64 members on 64 contexts of their own (streams and host
+        threads, sgn_rk4_step_ensemble), the previous form; and with their
+        steps replayed as captured graphs (graph_value);
+      sequential: the 64 contexts one after another.
+    Kernel B of the 1024x1024 group is timed against the HBM roofline."""
+    import threading
     import numpy as np
     from sgn_inputs import ENSEMBLE_GRIDS, ensemble_member
-    members, seed, schedules = [], 0, {}
+    steps = max(1, min(args.steps, 10))
+    groups, seed = [], 0
     for nx, ny in ENSEMBLE_GRIDS:
+        states, dts = [], []
         for _ in range(per_grid):
             box, state, p = ensemble_member(seed, nx, ny)
             seed += 1
-            cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, krasny=KRASNY, precision=sgn.SGN_FP32_MIXED)
-            ctx = sgn.sgn_init(cfg, dev, stream=torch.cuda.Stream(dev))
-            f = [torch.from_numpy(np.ascontiguousarray(a)).to(dev).to(torch.float32) for a in state]
-            schedules[f"{nx}x{ny}"] = sgn.ARNOLDI_SCHEDULES[sgn.sgn_autotune(ctx)]
-            members.append((ctx, f, p["dt"], nx * ny))
-    ctxs, fields, dts = [m[0] for m in members], [m[1] for m in members], [m[2] for m in members]
-    pts = sum(m[3] for m in members)
-    steps = max(1, min(args.steps, 10))
-    sgn.sgn_rk4_step_ensemble(ctxs, fields, dts, min(args.warmup, 2) or 1)
+            states.append(state)
+            dts.append(p["dt"])
+        assert len(set(dts)) == 1
+        groups.append((box, states, dts[0]))
+    pts = sum(b.nx * b.ny * len(st) for b, st, _ in groups)
+    out = {"workload": "ensemble of 64 perturbed line solitons (16 each on 256^2, 512^2, 1024x512, 1024^2)",
+           "members": sum(len(st) for _, st, _ in groups), "points": pts, "precision": "fp32_mixed",
+           "steps": steps, "unit": UNIT}
+    # one ensemble context per grid size
+    ctxs = []
+    for box, states, dt in groups:
+        cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, krasny=KRASNY, precision=sgn.SGN_FP32_MIXED,
+                                 batch=len(states))
+        stream = torch.cuda.Stream(dev)
+        ctx = sgn.sgn_init(cfg, dev, stream=stream)
+        f = [torch.from_numpy(np.ascontiguousarray(np.stack([m[i] for m in states]))).to(dev).to(torch.float32)
+             for i in range(4)]
+        ctxs.append((ctx, f, dt, stream))
+    infos = [None] * len(ctxs)
+
+    def run(i, n):
+        c, f, dt, _ = ctxs[i]
+        infos[i] = sgn.sgn_rk4_step(c, *f, dt, n)
+
+    def all_threads(n):
+        th = [threading.Thread(target=run, args=(i, n)) for i in range(len(ctxs))]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+
+    all_threads(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = sgn.sgn_rk4_step_ensemble(ctxs, fields, dts, steps)
+    all_threads(steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    # the same members with their steps replayed as captured graphs (the
-    # first call captures and calibrates the iteration budgets)
-    sgn.sgn_rk4_step_ensemble(ctxs, fields, dts, min(args.warmup, 2) or 1, graphs=True)
+    flat = [i for grp in infos for i in grp]
+    out["value"] = pts * steps / el
+    out["ms_per_step"] = el * 1e3 / steps
+    out.update(iters_summary(flat))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sgn.sgn_rk4_step_ensemble(ctxs, fields, dts, steps, graphs=True)
+    for i in range(len(ctxs)):
+        run(i, steps)
+    torch.cuda.synchronize()
+    el_ser = time.perf_counter() - t0
+    out["members_serial"] = {"value": pts * steps / el_ser, "ms_per_step": el_ser * 1e3 / steps}
+    # kernel B of the largest group against the roofline
+    c, f, dt, _ = ctxs[-1]
+    kind = [k for k, v in sgn.KERNEL_NAMES.items() if v == DOMINANT][0]
+    _, _, kt = timed_kernel_run(sgn, torch, c, [t.clone() for t in f], dt, steps, kind, period=1)
+    n, ms, by = kt
+    ach = by / n / (ms / n * 1e-3) / 1e9 if n else None
+    out["roofline_1024x1024_group"] = {"kernel": "k_row_matvec3<1024> (kernel B), 16 grids per launch, FP32",
+                                       "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": ach / HBM_PEAK_GBS if ach else None,
+                                       "algorithmic_bytes_per_launch": by / n if n else None,
+                                       "mean_launch_us": ms / n * 1e3 if n else None, "launches": n}
+    for c, _, _, _ in ctxs:
+        c.close()
+    del ctxs
+    # the previous form: one context (and stream and host thread) per member
+    members, schedules = [], {}
+    for box, states, dt in groups:
+        for st in states:
+            cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, krasny=KRASNY, precision=sgn.SGN_FP32_MIXED)
+            ctx = sgn.sgn_init(cfg, dev, stream=torch.cuda.Stream(dev))
+            f = [torch.from_numpy(np.ascontiguousarray(a)).to(dev).to(torch.float32) for a in st]
+            schedules[f"{box.nx}x{box.ny}"] = sgn.ARNOLDI_SCHEDULES[sgn.sgn_autotune(ctx)]
+            members.append((ctx, f, dt))
+    cl, fields, dts = [m[0] for m in members], [m[1] for m in members], [m[2] for m in members]
+    sgn.sgn_rk4_step_ensemble(cl, fields, dts, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sgn.sgn_rk4_step_ensemble(cl, fields, dts, steps)
+    torch.cuda.synchronize()
+    el_ctx = time.perf_counter() - t0
+    sgn.sgn_rk4_step_ensemble(cl, fields, dts, 1, graphs=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sgn.sgn_rk4_step_ensemble(cl, fields, dts, steps, graphs=True)
     torch.cuda.synchronize()
     el_graph = time.perf_counter() - t0
     t0 = time.perf_counter()
-    for c, f, d in zip(ctxs, fields, dts):
+    for c, f, d in zip(cl, fields, dts):
         sgn.sgn_rk4_step(c, *f, d, steps)
     torch.cuda.synchronize()
     el_seq = time.perf_counter() - t0
-    for c in ctxs:
+    for c in cl:
         c.close()
-    return {"workload": "ensemble of 64 perturbed line solitons (16 each on 256^2, 512^2, 1024x512, 1024^2)",
-            "members": len(members), "points": pts, "precision": "fp32_mixed", "steps": steps,
-            "value": pts * steps / el, "unit": UNIT, "ms_per_step": el * 1e3 / steps,
-            "sequential_value": pts * steps / el_seq, "speedup_vs_sequential": el_seq / el,
-            "graph_value": pts * steps / el_graph, "graph_ms_per_step": el_graph * 1e3 / steps,
-            "iters_per_solve_mean": sum(i.total_iters for i in infos) / max(sum(i.solves for i in infos), 1),
-            "schedules": schedules}
+    out["contexts"] = {"value": pts * steps / el_ctx, "ms_per_step": el_ctx * 1e3 / steps,
+                       "graph_value": pts * steps / el_graph, "graph_ms_per_step": el_graph * 1e3 / steps,
+                       "schedules": schedules}
+    out["sequential"] = {"value": pts * steps / el_seq, "ms_per_step": el_seq * 1e3 / steps}
+    out["speedup_vs_contexts"] = el_ctx / el
+    out["speedup_vs_sequential"] = el_seq / el
+    return out
 
 
 def cpu_baseline(steps: int):
-    import numpy as np  # noqa: F401
+    """The FP64 oracle (numpy, one thread: numpy's FFTs are single-threaded)
+    on `steps` RK4 steps of one of the nine runs (a = 0.5, k = 2) from t = 0."""
     from oracle import sgn_oracle as O
     from sgn_inputs import workload
     box, (h, vx, vy, s), w = workload(WORKLOAD, **PARAMS)
@@ -333,14 +633,34 @@ def cpu_baseline(steps: int):
     t0 = time.perf_counter()
     O.rk4(g, h, vx, vy, s, w["dt"], steps)
     dt = time.perf_counter() - t0
+    usable, model = host_cpu()
     return {"value": box.nx * box.ny * steps / dt, "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": f"{steps} RK4 step(s) of the {box.nx}x{box.ny} workload from t=0 "
-                      f"(numpy FP64, single-threaded FFTs), {dt:.1f} s"}
+            "host_cores_usable": usable, "host_cpu": model,
+            "sample": f"{steps} RK4 step(s) of the {box.nx}x{box.ny} run a = {PARAMS['a']}, k = {PARAMS['k']} "
+                      f"from t=0 (numpy FP64, single-threaded FFTs, one of the host's {usable} usable cores), "
+                      f"{dt:.1f} s"}
 
 
 def progress(msg: str):
     """One progress line per phase on stderr (the JSON result goes to stdout)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def host_cpu():
+    """Host cores this process may use and the CPU model (for cpu_baseline)."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count()
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:  # pragma: no cover
+        pass
+    return usable, model
 
 
 def main():
@@ -354,44 +674,44 @@ def main():
         sys.exit(2)
     import torch
     from paper_2306_09731_amd import sgn
-    from sgn_inputs import workload
 
-    box, (h, vx, vy, s), w = workload(WORKLOAD, **PARAMS)
     dev = torch.device("cuda:0")
-    cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"], gmres_restart=w["restart"],
-                             krasny=KRASNY)
-    ctx = sgn.sgn_init(cfg, dev)
-    th, tvx, tvy, ts = (torch.from_numpy(a).to(dev).contiguous() for a in (h, vx, vy, s))
+    if args.precision_only:
+        print(json.dumps({"precision_form": precision_form(sgn, torch, dev, args)}), flush=True)
+        return
+    if args.single_only:
+        print(json.dumps({"single_grid": single_grid_run(sgn, torch, dev, args)}), flush=True)
+        return
+    box, ak, w, ctx, f = sweep_context(sgn, torch, dev)
     if args.warmup > 0:
-        sgn.sgn_rk4_step(ctx, th, tvx, tvy, ts, w["dt"], args.warmup)
-    # the same run with the stage-increment initial guess (same tolerance),
-    # timed first so that the headline run below is the last thing measured
+        sgn.sgn_rk4_step(ctx, *f, w["dt"], args.warmup)
     progress("warm-up done")
-    alt = None if args.main_only else timed_guess_run(sgn, torch, box, (h, vx, vy, s), w, dev, args)
+    # the same runs with the stage-increment initial guess (same tolerance),
+    # timed first so that the headline run below is the last thing measured
+    alt = None if args.main_only else timed_guess_run(sgn, torch, dev, args)
     progress("stage-increment guess run done")
-    dominant = DOMINANT
-    kind = [k for k, v in sgn.KERNEL_NAMES.items() if v == dominant][0]
+    kind = [k for k, v in sgn.KERNEL_NAMES.items() if v == DOMINANT][0]
     # events on every EVENT_PERIOD-th launch of the class: recording them on
     # every launch costs about 3% of the step
-    sgn.sgn_kernel_timing(ctx, kind, True, EVENT_PERIOD)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    info = sgn.sgn_rk4_step(ctx, th, tvx, tvy, ts, w["dt"], args.steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    elapsed, infos, kt = timed_kernel_run(sgn, torch, ctx, f, w["dt"], args.steps, kind)
     progress(f"timed run done: {elapsed * 1e3 / args.steps:.3f} ms per step")
-    launches, kms, algo_total = sgn.sgn_kernel_time(ctx, kind)  # events recorded at dispatch start/end
-    sgn.sgn_kernel_timing(ctx, kind, False)
-    npts = box.nx * box.ny
-    value = npts * args.steps / elapsed
-    algo = algo_total / launches if launches else 0.0  # per launch, averaged over all timed launches
-    mean_s = (kms / launches) / 1e3 if launches else float("nan")
-    achieved = algo / mean_s / 1e9 if launches else None
-    ratio = traffic_ratio_from_profile(dominant)
-    traffic = ratio * algo if (ratio is not None and launches) else None  # HBM bytes per launch
+    ctx.close()
+    npts = len(ak) * box.nx * box.ny
+    config = {
+        "workload": SWEEP_WORKLOAD, "runs": len(ak), "nx": box.nx, "ny": box.ny, "Lx": box.Lx, "Ly": box.Ly,
+        "a": sorted({a for a, _ in ak}), "k": sorted({k for _, k in ak}), "eps": PARAMS["eps"], "x0": -10.0,
+        "dt": w["dt"], "gmres_tol": w["tol"], "gmres_restart": w["restart"], "krasny": KRASNY,
+        "guess": "plain (warm start from the previous sigma)",
+        "launch": "the nine runs as members of one context: one launch per kernel for all of them "
+                  "(member index in blockIdx.z), each with its own GMRES state",
+    }
+    config.update(iters_summary(infos))
+    config["per_run"] = [dict(a=a, k=k, iters_per_solve_mean=i.total_iters / max(i.solves, 1),
+                              iters_per_solve_max=i.max_iters_per_solve) for (a, k), i in zip(ak, infos)]
+    config["stage_increment_guess"] = alt
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": npts * args.steps / elapsed,
         "unit": UNIT,
         "n_gpus": 1,
         "steps": args.steps,
@@ -402,33 +722,22 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {
-            "workload": WORKLOAD, "nx": box.nx, "ny": box.ny, "Lx": box.Lx, "Ly": box.Ly,
-            "a": PARAMS["a"], "eps": PARAMS["eps"], "k": PARAMS["k"], "dt": w["dt"],
-            "gmres_tol": w["tol"], "gmres_restart": w["restart"], "krasny": KRASNY,
-            "guess": "plain (warm start from the previous sigma)",
-            "iters_per_solve_mean": info.total_iters / max(info.solves, 1),
-            "iters_per_solve_max": info.max_iters_per_solve,
-            "solves": info.solves,
-            "stage_increment_guess": alt,
-        },
-        "roofline": {
-            "kernel": f"k_row_matvec3<{box.nx}> (Arnoldi kernel B: x part of the elliptic operator, "
-                      f"three transform chains per row pair)",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": algo,
-            "mean_launch_us": mean_s * 1e6,
-            "launches": launches,
-            "events_on_every": EVENT_PERIOD,
-        },
+        "config": config,
+        "roofline": roofline_entry(f"k_row_matvec3<{box.nx}> (Arnoldi kernel B: x part of the elliptic operator, "
+                                   f"three transform chains per row pair), nine grids per launch", kt,
+                                   SWEEP_WORKLOAD),
     }
     if not args.main_only:
-        out["graph_form"] = graph_form(sgn, torch, box, (h, vx, vy, s), w, dev, args)
+        out["single_grid"] = single_grid_run(sgn, torch, dev, args)
+        progress("single-grid run done")
+        out["sweep_single"] = sweep_single(sgn, torch, dev, args)
+        progress("sweep one grid per context done")
+        if args.t20_steps > 0:
+            out["sweep_to_t20"] = sweep_to_t20(sgn, torch, dev, args.t20_steps)
+            progress("nine runs to t = 20 done")
+        from sgn_inputs import workload
+        sbox, sstate, sw = workload(WORKLOAD, **PARAMS)
+        out["graph_form"] = graph_form(sgn, torch, sbox, sstate, sw, dev, args)
         progress("graph form done")
         out["learned_form"] = learned_form(sgn, torch, dev, args)
         progress("learned form done")
