@@ -62,6 +62,9 @@ def parse():
                    help="time only the single 1024x512 grid (a = 0.5, k = 2; for profiler runs)")
     p.add_argument("--precision-only", action="store_true",
                    help="time only the 2048^2 precision form (for profiler runs)")
+    p.add_argument("--c3-only", choices=("fp64", "fp32_mixed"),
+                   help="time only the 2048^2 Gaussian in one precision, events on every launch of its "
+                        "dominant Arnoldi kernel class (for profiler runs)")
     p.add_argument("--t5-steps", type=int, default=1000,
                    help="steps of the 2048^2 precision comparison at t = 5 (dt = 0.005; 0 skips it)")
     p.add_argument("--t20-steps", type=int, default=4000,
@@ -368,7 +371,7 @@ def precision_form(sgn, torch, dev, args):
         dom = max(per, key=lambda k: per[k][1])
         n, ms, by = per[dom]
         ach = by / (ms * 1e-3) / 1e9 if ms else None
-        ratio = traffic_ratio_from_profile(dom, f"{PRECISION_WORKLOAD}_{name}")
+        ratio = traffic_ratio_from_profile(dom, f"{PRECISION_WORKLOAD}_{name}") if dom == C3_DOMINANT else None
         res["roofline"] = {"kernel_class": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": ach / HBM_PEAK_GBS if ach else None,
                            "traffic": ratio * by / n if ratio is not None else None,
@@ -389,6 +392,37 @@ def precision_form(sgn, torch, dev, args):
     out["fp32_vs_fp64_after_steps"] = {
         "h": float(np.abs(h32 - h64).max() / np.abs(h64 - 1.0).max()),
         "vx": float(np.abs(v32 - v64).max() / max(np.abs(v64).max(), 1e-300))}
+    return out
+
+
+C3_DOMINANT = "col_basis"  # the Arnoldi basis kernel of the four-kernel step (2048-point columns)
+
+
+def c3_run(sgn, torch, dev, args, name):
+    """K steps of the 2048^2 Gaussian in one precision after W warm-up steps,
+    the dominant kernel class timed on every launch (all its dispatches of
+    the timed call): the library's algorithmic bytes over exactly the
+    dispatches a profiler of this run sees when W = 0."""
+    import numpy as np
+    from sgn_inputs import workload
+    box, state, w = workload(PRECISION_WORKLOAD)
+    prec, dtype = ((sgn.SGN_FP32_MIXED, torch.float32) if name == "fp32_mixed" else (sgn.SGN_FP64, torch.float64))
+    cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"], gmres_restart=w["restart"],
+                             krasny=KRASNY, precision=prec)
+    ctx = sgn.sgn_init(cfg, dev)
+    f = [torch.from_numpy(np.ascontiguousarray(a)).to(dev).to(dtype) for a in state]
+    if args.warmup > 0:
+        sgn.sgn_rk4_step(ctx, *f, w["dt"], args.warmup)
+    kind = [k for k, v in sgn.KERNEL_NAMES.items() if v == C3_DOMINANT][0]
+    el, infos, kt = timed_kernel_run(sgn, torch, ctx, f, w["dt"], args.steps, kind, period=1)
+    ctx.close()
+    n, ms, by = kt
+    out = {"workload": PRECISION_WORKLOAD, "precision": name, "steps": args.steps,
+           "ms_per_step": el * 1e3 / args.steps, "kernel_class": C3_DOMINANT, "launches": n,
+           "mean_launch_us": ms / n * 1e3 if n else None, "algorithmic_bytes_total": by,
+           "algorithmic_bytes_per_launch": by / n if n else None,
+           "achieved": by / (ms * 1e-3) / 1e9 if ms else None}
+    out.update(iters_summary(infos))
     return out
 
 
@@ -678,6 +712,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.precision_only:
         print(json.dumps({"precision_form": precision_form(sgn, torch, dev, args)}), flush=True)
+        return
+    if args.c3_only:
+        print(json.dumps({"c3": c3_run(sgn, torch, dev, args, args.c3_only)}), flush=True)
         return
     if args.single_only:
         print(json.dumps({"single_grid": single_grid_run(sgn, torch, dev, args)}), flush=True)

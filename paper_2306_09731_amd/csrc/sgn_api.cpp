@@ -882,6 +882,13 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   char* base = ctx->ws;
   const int M = cfg->batch;
   g.members = M;
+  // members test the GMRES status before their loads: members that have
+  // converged skip the loads of the launches for the others' further steps
+  // (SGN_MEMBER_STATUS_FIRST=0: after, as a single grid does)
+  if (M > 1) {
+    g.status_first = 1;
+    if (const char* sf = std::getenv("SGN_MEMBER_STATUS_FIRST")) g.status_first = std::atoi(sf) != 0;
+  }
   g.ws_lo = reinterpret_cast<uintptr_t>(base);
   g.ws_span = g.ws_stride = L.member;
   g.f_stride = (size_t)nx * ny * (g.fp32 ? sizeof(float) : sizeof(double));

@@ -780,9 +780,27 @@ __global__ void __launch_bounds__(512) k_row_matvec2(Geom g, const cplx* __restr
   extern __shared__ cplx lds[];
   const int t = threadIdx.x;
   const int npairs = g.ny / 2;
-  const bool a1 = (int)blockIdx.x < npairs;  // chains 0 and 1 of one row pair, else chain 2 of two
+  // Blocks come in groups of three for two row pairs (chains 0 and 1 of each
+  // pair, then chain 2 of both), which read the same h and E rows.  With
+  // npairs a multiple of 16, a group's three blocks take consecutive slots of
+  // one XCD (blocks are dealt to the eight XCDs by linear index), so the
+  // second reads of h and E hit that XCD's L2; otherwise the first npairs
+  // blocks take chains 0 and 1 and the rest chain 2.
+  int role, grp;
+  if ((npairs & 15) == 0) {
+    const int b = blockIdx.x, slot = b >> 3;
+    grp = (slot / 3) * 8 + (b & 7);
+    role = slot % 3;
+  } else if ((int)blockIdx.x < npairs) {
+    grp = blockIdx.x >> 1;
+    role = blockIdx.x & 1;
+  } else {
+    grp = blockIdx.x - npairs;
+    role = 2;
+  }
+  const bool a1 = role < 2;  // chains 0 and 1 of one row pair, else chain 2 of two
   const int chain = a1 ? threadIdx.y : 2;
-  const int ya = a1 ? 2 * blockIdx.x : 2 * (2 * (blockIdx.x - npairs) + threadIdx.y);
+  const int ya = 2 * (2 * grp + (a1 ? role : threadIdx.y));
   cplx* buf = lds + threadIdx.y * Row<N>::LDS;
   TwiddleSet<N> twx;
   gather_twiddles<N>(twx, t, TWX(g));

@@ -55,25 +55,27 @@ def host(t):
 PARAMS = [(0.2, 0.05, 1), (0.5, 0.01, 2), (1.0, 0.02, 4)]
 
 
+@pytest.mark.parametrize("nx,ny", [(128, 64), (64, 16)])
 @pytest.mark.parametrize("arnoldi", ["fused", "chained", "serial"])
 @pytest.mark.parametrize("prec", [sgn.SGN_FP64, sgn.SGN_FP32_MIXED])
-def test_members_rk4_bitwise_equal_to_single_contexts(arnoldi, prec):
-    nx, ny = 128, 64
-    box = Box(nx, ny, 10.0, 5.0)
+def test_members_rk4_bitwise_equal_to_single_contexts(arnoldi, prec, nx, ny):
+    """128x64 takes the XCD-grouped block order of the two-chain row kernel
+    (row pairs a multiple of 16), 64x16 the plain one."""
+    box = Box(nx, ny, 10.0 * nx / 128, 5.0 * ny / 64)
     fields = soliton_members(box, PARAMS)
     B = len(PARAMS)
     dt = torch.float64 if prec == sgn.SGN_FP64 else torch.float32
     kw = dict(precision=prec, gmres_tol=1e-10, krasny=1e-12)
-    cb = ctx_for(nx, ny, 10.0, 5.0, B, arnoldi, **kw)
+    cb = ctx_for(nx, ny, box.Lx, box.Ly, B, arnoldi, **kw)
     fb = [to_dev(a, dt) for a in fields]
     infos = sgn.sgn_rk4_step(cb, *fb, 0.01, 6)
     got = [host(t) for t in fb]
     for k in range(B):
-        cs = ctx_for(nx, ny, 10.0, 5.0, 1, arnoldi, **kw)
+        cs = ctx_for(nx, ny, box.Lx, box.Ly, 1, arnoldi, **kw)
         fs = [to_dev(a[k], dt) for a in fields]
         info = sgn.sgn_rk4_step(cs, *fs, 0.01, 6)
         same = all(np.array_equal(got[i][k], host(fs[i])) for i in range(4))
-        say(f"members {arnoldi} {'fp64' if prec == 0 else 'fp32'} member {k}: iters {infos[k].total_iters} "
+        say(f"members {nx}x{ny} {arnoldi} {'fp64' if prec == 0 else 'fp32'} member {k}: iters {infos[k].total_iters} "
             f"(single {info.total_iters}), bitwise equal {same}")
         assert same
         assert infos[k].total_iters == info.total_iters
