@@ -163,6 +163,7 @@ def sweep_context(sgn, torch, dev, guess=None):
         kw["guess"] = guess
     cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, **kw)
     ctx = sgn.sgn_init(cfg, dev)
+    sgn.sgn_autotune(ctx)  # schedule, launch shapes and row radix for nine members of this grid
     f = [torch.from_numpy(a).to(dev).contiguous() for a in state]
     return box, ak, w, ctx, f
 
@@ -571,6 +572,7 @@ def batched_form(sgn, torch, dev, args, per_grid: int = 16):
                                  batch=len(states))
         stream = torch.cuda.Stream(dev)
         ctx = sgn.sgn_init(cfg, dev, stream=stream)
+        sgn.sgn_autotune(ctx)
         f = [torch.from_numpy(np.ascontiguousarray(np.stack([m[i] for m in states]))).to(dev).to(torch.float32)
              for i in range(4)]
         ctxs.append((ctx, f, dt, stream))
@@ -732,6 +734,7 @@ def main():
     # every launch costs about 3% of the step
     elapsed, infos, kt = timed_kernel_run(sgn, torch, ctx, f, w["dt"], args.steps, kind)
     progress(f"timed run done: {elapsed * 1e3 / args.steps:.3f} ms per step")
+    shape = sgn.sgn_launch_shape(ctx)
     ctx.close()
     npts = len(ak) * box.nx * box.ny
     config = {
@@ -741,6 +744,7 @@ def main():
         "guess": "plain (warm start from the previous sigma)",
         "launch": "the nine runs as members of one context: one launch per kernel for all of them "
                   "(member index in blockIdx.z), each with its own GMRES state",
+        "launch_shape": shape,
     }
     config.update(iters_summary(infos))
     config["per_run"] = [dict(a=a, k=k, iters_per_solve_mean=i.total_iters / max(i.solves, 1),

@@ -284,9 +284,11 @@ int sgn_rk4_step_ensemble_graph(int32_t n, sgn_ctx* const* ctxs, void* const* h,
  * with one transform chain per block; four kernels with two chains; the
  * three-kernel step), then, for the fastest, the column tile widths (the
  * widest tiles that keep 128, 256, 512 or 1024 blocks) and rows per row block
- * (64, 128 or 256 threads) that give a launch shape not yet timed; keeps the
- * fastest for the context and caches the choice per (nx, ny, precision,
- * restart, device) for the process.  All choices compute the same
+ * (64, 128 or 256 threads) that give a launch shape not yet timed, and, for
+ * an ensemble context on the three-kernel step with 512 or 1024 points per
+ * row, the radix of the members' two-chain row transforms (4 or 8 values per
+ * thread); keeps the fastest for the context and caches the choice per (nx,
+ * ny, precision, restart, members, device) for the process.  All choices compute the same
  * quantities (reductions may sum in another order).  Uses the context's RK4
  * stage buffers (their contents are overwritten) and its stream;
  * synchronises.  *chosen (may be NULL): the schedule, 0, 1 or 2 in the order
@@ -297,7 +299,9 @@ int sgn_autotune(sgn_ctx* ctx, int32_t* chosen);
  * out[1] the column-tile block target, out[2] the row-block thread target,
  * out[3], out[4] row pairs per block of the single-chain and three-chain row
  * kernels, out[5], out[6] columns per tile of the single-chain and two-chain
- * column kernels (0: no such kernel at this size).  out: 7 host int32. */
+ * column kernels (0: no such kernel at this size), out[7] the values per
+ * thread of the members' two-chain row kernel (0: the default radix).
+ * out: 8 host int32. */
 int sgn_launch_shape(const sgn_ctx* ctx, int32_t* out);
 
 /* ---- Learned initial guess (a network of the project, not of the paper) ----

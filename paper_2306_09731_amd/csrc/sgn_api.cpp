@@ -133,6 +133,8 @@ void geom_init(const sgn_config& c, Geom& g) {
   g.members = 1;
   g.row_split = 1;
   if (const char* rs = std::getenv("SGN_ROW_SPLIT")) g.row_split = std::atoi(rs) != 0;
+  g.row_radix = 0;
+  if (const char* rr = std::getenv("SGN_ROW_RADIX")) g.row_radix = std::atoi(rr) == 8 ? 8 : 0;
   g.ws_lo = 0;
   g.ws_span = g.ws_stride = g.f_stride = 0;
   if (const char* tb = std::getenv("SGN_TILE_BLOCKS")) {
@@ -1499,18 +1501,17 @@ namespace {
 std::mutex g_tune_mutex;
 struct TuneChoice {
   int arnoldi, tile_blocks, row_threads;
+  int row_radix = 0;  // values per thread of the members' two-chain row kernel (0: default)
 };
-std::map<std::tuple<int, int, int, int, int>, TuneChoice> g_tune_cache;  // (nx, ny, precision, restart, device)
+// (nx, ny, precision, restart, members, device)
+std::map<std::tuple<int, int, int, int, int, int>, TuneChoice> g_tune_cache;
 }  // namespace
 
 int sgn_autotune(sgn_ctx* ctx, int32_t* chosen) {
   if (!ctx) return SGN_ERR_INVALID_ARG;
-  if (members(ctx) > 1) {
-    ctx->err = "the autotuner times single grids (batch = 1)";
-    return SGN_ERR_UNSUPPORTED;
-  }
   const sgn_config& c = ctx->cfg;
-  const auto key = std::make_tuple(c.nx, c.ny, c.precision, c.gmres_restart, ctx->device);
+  const int M = members(ctx);
+  const auto key = std::make_tuple(c.nx, c.ny, c.precision, c.gmres_restart, M, ctx->device);
   {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     auto it = g_tune_cache.find(key);
@@ -1518,6 +1519,7 @@ int sgn_autotune(sgn_ctx* ctx, int32_t* chosen) {
       ctx->arnoldi = it->second.arnoldi;
       ctx->g.tile_blocks = it->second.tile_blocks;
       ctx->g.row_threads = it->second.row_threads;
+      ctx->g.row_radix = it->second.row_radix;
       if (chosen) *chosen = it->second.arnoldi;
       return SGN_OK;
     }
@@ -1534,34 +1536,44 @@ int sgn_autotune(sgn_ctx* ctx, int32_t* chosen) {
       hh[(size_t)y * c.nx + x] = 1.0 + 0.3 * std::sin(X) * std::cos(2.0 * Y);
       bb[(size_t)y * c.nx + x] = std::cos(3.0 * X + Y);
     }
+  // every member gets the same problem (its stage buffers, at the member stride)
   auto upload = [&](void* dst, const std::vector<double>& src) -> hipError_t {
-    if (!g.fp32) return hipMemcpyAsync(dst, src.data(), npts * sizeof(double), hipMemcpyHostToDevice, s);
-    std::vector<float> f(src.begin(), src.end());
-    hipError_t e = hipMemcpyAsync(dst, f.data(), npts * sizeof(float), hipMemcpyHostToDevice, s);
+    hipError_t e = hipSuccess;
+    std::vector<float> f;
+    if (g.fp32) f.assign(src.begin(), src.end());
+    for (int k = 0; k < M && e == hipSuccess; ++k) {
+      char* d = static_cast<char*>(dst) + (size_t)k * ctx->ws_stride;
+      e = g.fp32 ? hipMemcpyAsync(d, f.data(), npts * sizeof(float), hipMemcpyHostToDevice, s)
+                 : hipMemcpyAsync(d, src.data(), npts * sizeof(double), hipMemcpyHostToDevice, s);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // f is a host local
     return e;
   };
   HIPCK(upload(ctx->hs, hh));
   HIPCK(upload(ctx->vxs, bb));
-  HIPCK(hipMemsetAsync(ctx->vys, 0, ctx->field_bytes, s));
+  if (M == 1)
+    HIPCK(hipMemsetAsync(ctx->vys, 0, ctx->field_bytes, s));
+  else
+    HIPCK(hipMemset2DAsync(ctx->vys, ctx->ws_stride, 0, ctx->field_bytes, M, s));
   HIPCK(hipStreamSynchronize(s));
   hipEvent_t e0, e1;
   HIPCK(hipEventCreate(&e0));
   HIPCK(hipEventCreate(&e1));
-  const TuneChoice saved{ctx->arnoldi, g.tile_blocks, g.row_threads};
+  const TuneChoice saved{ctx->arnoldi, g.tile_blocks, g.row_threads, g.row_radix};
   int rc = SGN_OK;
   // time one candidate: three solves from zero after a warm-up solve
   auto time_it = [&](const TuneChoice& t, float* out) {
     ctx->arnoldi = t.arnoldi;
     g.tile_blocks = t.tile_blocks;
     g.row_threads = t.row_threads;
+    g.row_radix = t.row_radix;
     float total = 0.0f;
     for (int rep = 0; rep < 4 && rc == SGN_OK; ++rep) {  // rep 0 warms up
       rc = load_sigma(ctx, ctx->vys);
       if (rc) break;
       if (hipEventRecord(e0, s) != hipSuccess) rc = SGN_ERR_HIP;
-      SolveResult res;
-      if (!rc) rc = run_solve(ctx, 2, ctx->hs, ctx->vxs, nullptr, &res);
+      std::vector<SolveResult> res(M);
+      if (!rc) rc = run_solve(ctx, 2, ctx->hs, ctx->vxs, nullptr, res.data());
       if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = SGN_ERR_HIP;
       if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = SGN_ERR_HIP;
       float ms = 0.0f;
@@ -1580,7 +1592,7 @@ int sgn_autotune(sgn_ctx* ctx, int32_t* chosen) {
   float best_ms = 1e30f;
   for (int v : sched) {
     if (rc) break;
-    const TuneChoice t{v, saved.tile_blocks, saved.row_threads};
+    const TuneChoice t{v, saved.tile_blocks, saved.row_threads, saved.row_radix};
     float ms;
     time_it(t, &ms);
     if (!rc && ms < best_ms) {
@@ -1604,10 +1616,25 @@ int sgn_autotune(sgn_ctx* ctx, int32_t* chosen) {
   for (int tb : {128, 256, 512, 1024}) {
     for (int rt : {64, 128, 256}) {
       if (rc) break;
-      const TuneChoice t{base.arnoldi, tb, rt};
+      const TuneChoice t{base.arnoldi, tb, rt, base.row_radix};
       const auto a = shape_of(t);
       if (std::find(seen.begin(), seen.end(), a) != seen.end()) continue;
       seen.push_back(a);
+      float ms;
+      time_it(t, &ms);
+      if (!rc && ms < best_ms) {
+        best_ms = ms;
+        best = t;
+      }
+    }
+  }
+  // 3. with several members on the three-kernel step, the radix of the
+  // two-chain row kernel's transforms (4 or 8 values per thread)
+  if (!rc && M > 1 && best.arnoldi == 2 && g.row_split && (c.nx == 512 || c.nx == 1024)) {
+    for (int rr : {0, 8}) {
+      if (rc || rr == best.row_radix) continue;
+      TuneChoice t = best;
+      t.row_radix = rr;
       float ms;
       time_it(t, &ms);
       if (!rc && ms < best_ms) {
@@ -1622,6 +1649,7 @@ int sgn_autotune(sgn_ctx* ctx, int32_t* chosen) {
   ctx->arnoldi = use.arnoldi;
   g.tile_blocks = use.tile_blocks;
   g.row_threads = use.row_threads;
+  g.row_radix = use.row_radix;
   if (rc) return rc;
   {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
@@ -1639,6 +1667,7 @@ int sgn_launch_shape(const sgn_ctx* ctx, int32_t* out) {
   out[1] = ctx->g.tile_blocks;
   out[2] = ctx->g.row_threads;
   for (int i = 0; i < 4; ++i) out[3 + i] = a[i];
+  out[7] = ctx->g.row_radix;
   return SGN_OK;
 }
 

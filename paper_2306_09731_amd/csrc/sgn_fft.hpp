@@ -161,9 +161,9 @@ constexpr int mid_twiddles() {
   }
 }
 
-template <int N>
+template <int N, int EE = FftShape<N>::E>
 struct TwiddleSet {
-  static constexpr int E = FftShape<N>::E;
+  static constexpr int E = EE;
   static constexpr int MID = (N == E) ? 0 : mid_twiddles<N, E, E>();
   static constexpr int COUNT = (N == E) ? 1 : MID + (E - 1);
   cplx w[COUNT];
@@ -186,15 +186,17 @@ __device__ __forceinline__ void gather_mid_twiddles(cplx* w, int t, const cplx* 
 }
 
 // tw: the length-N table exp(-2 pi i k / N); t: the thread's index in its transform.
-template <int N>
-__device__ __forceinline__ void gather_twiddles(TwiddleSet<N>& ts, int t, const cplx* __restrict__ tw) {
-  constexpr int E = FftShape<N>::E;
+// EE: values per thread (the default of FftShape, or another radix with
+// E^2 | N that a kernel is instantiated for).
+template <int N, int EE>
+__device__ __forceinline__ void gather_twiddles(TwiddleSet<N, EE>& ts, int t, const cplx* __restrict__ tw) {
+  constexpr int E = EE;
   if constexpr (N == E) {
     ts.w[0] = make_cplx(real(1), real(0));
   } else {
     gather_mid_twiddles<N, E, E, 0>(ts.w, t, tw);
 #pragma unroll
-    for (int r = 1; r < E; ++r) ts.w[TwiddleSet<N>::MID + r - 1] = tw[t * r];
+    for (int r = 1; r < E; ++r) ts.w[TwiddleSet<N, EE>::MID + r - 1] = tw[t * r];
   }
 }
 
@@ -245,10 +247,11 @@ __device__ __forceinline__ void fft_middle_stages(cplx* buf, int t, const cplx* 
 // out).  buf: this transform's LDS region (map addressing); ts: the thread's
 // twiddles.  Unnormalised in both directions.  Ends with a barrier so buf
 // may be reused at once.
-template <int N, bool INV, class Map>
-__device__ __forceinline__ void fft(cplx* v, cplx* buf, int t, const TwiddleSet<N>& ts, const Map& map) {
-  constexpr int E = FftShape<N>::E;
-  constexpr int TPF = FftShape<N>::TPF;
+template <int N, bool INV, class Map, int EE>
+__device__ __forceinline__ void fft(cplx* v, cplx* buf, int t, const TwiddleSet<N, EE>& ts, const Map& map) {
+  constexpr int E = EE;
+  constexpr int TPF = N / E;
+  static_assert(N == E || N % (E * E) == 0, "plan needs N == E or E^2 | N");
   dft<E, INV>(v);
   if constexpr (N == E) return;
   // first stage output (Ns = 1): position t*E + r
@@ -261,7 +264,7 @@ __device__ __forceinline__ void fft(cplx* v, cplx* buf, int t, const TwiddleSet<
   for (int r = 0; r < E; ++r) v[r] = buf[map.at(t + r * TPF)];
   __syncthreads();
 #pragma unroll
-  for (int r = 1; r < E; ++r) v[r] = twmul<INV>(v[r], ts.w[TwiddleSet<N>::MID + r - 1]);
+  for (int r = 1; r < E; ++r) v[r] = twmul<INV>(v[r], ts.w[TwiddleSet<N, EE>::MID + r - 1]);
   dft<E, INV>(v);
 }
 

@@ -33,6 +33,7 @@ struct Geom {
   // m * ws_stride bytes, its caller fields are member 0's moved by m * f_stride
   int members;             // 1 for a single grid
   int row_split;           // 1: with several members, the Arnoldi row kernel in blocks of two chains
+  int row_radix;           // that kernel's values per thread: 0 the engine's default, 8 radix-8 (512, 1024 points)
   uintptr_t ws_lo;
   size_t ws_span, ws_stride, f_stride;
 };

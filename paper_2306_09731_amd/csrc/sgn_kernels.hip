@@ -454,20 +454,22 @@ __device__ int gmres_finish_column(GmresState* st, int j, const double* cj, doub
 // Row passes
 // ----------------------------------------------------------------------------
 
-template <int N>
+// EE: values per thread of the row transforms (the engine's default, or
+// another radix a kernel is instantiated for).
+template <int N, int EE = FftShape<N>::E>
 struct Row {
-  static constexpr int E = FftShape<N>::E;
-  static constexpr int TPF = FftShape<N>::TPF;
+  static constexpr int E = EE;
+  static constexpr int TPF = N / EE;
   static constexpr int LDS = RowMap::size(N);  // cplx per row pair
 };
 
-template <int N>
+template <int N, int EE = FftShape<N>::E>
 __device__ __forceinline__ void load_phys_pair(cplx* v, const real* __restrict__ f, int ya, int t) {
   const real* a = f + (size_t)ya * N;
   const real* b = a + N;
 #pragma unroll
-  for (int r = 0; r < Row<N>::E; ++r) {
-    const int p = t + r * Row<N>::TPF;
+  for (int r = 0; r < Row<N, EE>::E; ++r) {
+    const int p = t + r * Row<N, EE>::TPF;
     v[r] = make_cplx(a[p], b[p]);
   }
 }
@@ -485,24 +487,24 @@ __device__ __forceinline__ void store_phys_pair(const cplx* v, real* __restrict_
 }
 
 // Full spectrum of (row ya) + i (row ya+1) from their x-half spectra, times s.
-template <int N>
+template <int N, int EE = FftShape<N>::E>
 __device__ __forceinline__ void load_spec_pair(cplx* v, const cplx* __restrict__ S, int ya, int t, double s) {
   constexpr int H = N / 2;
   const cplx* A = S + (size_t)ya * H;
   const cplx* B = A + H;
   // one unconditional load pair per value, all issued before any is used,
   // so that they are in flight together
-  cplx la[Row<N>::E], lb[Row<N>::E];
+  cplx la[Row<N, EE>::E], lb[Row<N, EE>::E];
 #pragma unroll
-  for (int r = 0; r < Row<N>::E; ++r) {
-    const int p = t + r * Row<N>::TPF;
+  for (int r = 0; r < Row<N, EE>::E; ++r) {
+    const int p = t + r * Row<N, EE>::TPF;
     const int q = (p == 0 || p == H) ? 0 : (p < H ? p : N - p);
     la[r] = A[q];
     lb[r] = B[q];
   }
 #pragma unroll
-  for (int r = 0; r < Row<N>::E; ++r) {
-    const int p = t + r * Row<N>::TPF;
+  for (int r = 0; r < Row<N, EE>::E; ++r) {
+    const int p = t + r * Row<N, EE>::TPF;
     const cplx a = la[r], b = lb[r];
     cplx z;
     if (p == 0)
@@ -766,15 +768,15 @@ __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __rest
 // blockIdx.x and form A1 = chain 0 + chain 1 through LDS; blocks npairs ..
 // npairs + npairs/2 - 1 run chain 2 (A2) for two row pairs, one per thread
 // group.  Block: (TPF, 2); grid.x = npairs + npairs / 2 (npairs even).
-template <int N, bool SF>
+template <int N, bool SF, int EE = FftShape<N>::E>
 __global__ void __launch_bounds__(512) k_row_matvec2(Geom g, const cplx* __restrict__ Es, const cplx* __restrict__ Gs,
                                                      const real* __restrict__ h, cplx* __restrict__ P,
                                                      cplx* __restrict__ Q, const GmresState* st) {
   Es = mshift(g, Es); Gs = mshift(g, Gs); h = mshift(g, h); P = mshift(g, P); Q = mshift(g, Q);
   st = mshift(g, st);
   if (SF && st->st.done) return;
-  constexpr int E = Row<N>::E;
-  constexpr int TPF = Row<N>::TPF;
+  constexpr int E = Row<N, EE>::E;
+  constexpr int TPF = Row<N, EE>::TPF;
   constexpr int H = N / 2;
   const RowMap map;
   extern __shared__ cplx lds[];
@@ -802,11 +804,11 @@ __global__ void __launch_bounds__(512) k_row_matvec2(Geom g, const cplx* __restr
   const int chain = a1 ? threadIdx.y : 2;
   const int ya = 2 * (2 * grp + (a1 ? role : threadIdx.y));
   cplx* buf = lds + threadIdx.y * Row<N>::LDS;
-  TwiddleSet<N> twx;
-  gather_twiddles<N>(twx, t, TWX(g));
+  TwiddleSet<N, EE> twx;
+  gather_twiddles<N, EE>(twx, t, TWX(g));
   cplx v[E], hi[E];
-  load_spec_pair<N>(v, chain == 2 ? Gs : Es, ya, t, g.inv_nx);
-  load_phys_pair<N>(hi, h, ya, t);
+  load_spec_pair<N, EE>(v, chain == 2 ? Gs : Es, ya, t, g.inv_nx);
+  load_phys_pair<N, EE>(hi, h, ya, t);
   if (st->st.done) return;  // tested after the (in-bounds) loads are issued
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -2566,10 +2568,18 @@ static hipError_t row_matvec3_n(const Geom& g, const cplx* E, const cplx* G, con
       // several grids per launch: blocks of two chains, two of which share a CU
       const int np = g.ny / 2;
       const size_t lb2 = (size_t)2 * Row<N>::LDS * sizeof(cplx);
-      auto* const k2 = g.status_first ? &k_row_matvec2<N, true> : &k_row_matvec2<N, false>;
+      auto* k2 = g.status_first ? &k_row_matvec2<N, true> : &k_row_matvec2<N, false>;
+      int tpf = Row<N>::TPF;
+      if constexpr (N == 512 || N == 1024) {
+        // radix-8 row transforms (a tuning choice, Geom::row_radix)
+        if (g.row_radix == 8) {
+          k2 = g.status_first ? &k_row_matvec2<N, true, 8> : &k_row_matvec2<N, false, 8>;
+          tpf = N / 8;
+        }
+      }
       hipError_t e2 = allow_lds(reinterpret_cast<const void*>(k2), lb2);
       if (e2 != hipSuccess) return e2;
-      launch(k2, dim3(np + np / 2), dim3(Row<N>::TPF, 2), lb2, s, g, E, G, h, P, Q, st);
+      launch(k2, dim3(np + np / 2), dim3(tpf, 2), lb2, s, g, E, G, h, P, Q, st);
       return hipGetLastError();
     }
     // the status tested first in captured graphs, after the loads otherwise

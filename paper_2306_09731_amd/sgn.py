@@ -282,10 +282,10 @@ def sgn_rhs(ctx: Context, h, vx, vy, sigma, dh, dvx, dvy):
 
 def sgn_launch_shape(ctx: Context) -> dict:
     """The context's Arnoldi schedule, tile targets and resulting block shapes."""
-    out = (ctypes.c_int32 * 7)()
+    out = (ctypes.c_int32 * 8)()
     _check(ctx, load_library().sgn_launch_shape(ctx.handle, out))
     keys = ("arnoldi", "tile_blocks", "row_threads", "row_pairs_per_block", "row_pairs_per_block3",
-            "cols_per_tile", "cols_per_tile2")
+            "cols_per_tile", "cols_per_tile2", "row_radix")
     return dict(zip(keys, list(out)))
 
 

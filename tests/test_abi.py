@@ -133,7 +133,7 @@ def test_ensemble_and_autotune_host_checks():
         assert fn(1, null, null, null, null, null, dts, 1, None) == sgn.SGN_ERR_INVALID_ARG
         assert fn(0, null, null, null, null, null, None, 1, None) == sgn.SGN_OK
     assert lib.sgn_autotune(None, None) == sgn.SGN_ERR_INVALID_ARG
-    out = (ctypes.c_int32 * 7)()
+    out = (ctypes.c_int32 * 8)()
     assert lib.sgn_launch_shape(None, out) == sgn.SGN_ERR_INVALID_ARG
 
 

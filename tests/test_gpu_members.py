@@ -200,9 +200,6 @@ def test_members_refusals_and_layout():
     with pytest.raises(sgn.SgnError) as e:
         sgn.sgn_rk4_step_graph(cb, *f, 0.01, 1)
     assert e.value.status == sgn.SGN_ERR_UNSUPPORTED
-    with pytest.raises(sgn.SgnError) as e:
-        sgn.sgn_autotune(cb)
-    assert e.value.status == sgn.SGN_ERR_UNSUPPORTED
     with pytest.raises(ValueError):
         sgn.sgn_rk4_step(cb, *[torch.ones(64, 64, dtype=torch.float64, device=DEV)] * 4, 0.01, 1)
     # a bad member is reported
@@ -211,3 +208,46 @@ def test_members_refusals_and_layout():
     with pytest.raises(sgn.SgnError) as e:
         sgn.sgn_rk4_step(cb, bad, f[1], f[2], f[3], 0.01, 1)
     assert e.value.status == sgn.SGN_ERR_CAVITATION and "member 2" in str(e.value)
+
+
+def test_members_autotune_radix_and_results():
+    """The autotuner on a four-member 1024x512 context: it may pick the radix-8
+    two-chain row kernel; whatever it picks, each member's RK4 steps equal a
+    single context's to the FP64 parity gate (the radix changes the rounding
+    of the row transforms only), and member 1 matches the oracle."""
+    nx, ny = 1024, 512
+    box = Box(nx, ny, 10.0, 5.0)
+    params = [(0.2, 0.01, 1), (0.5, 0.01, 2), (1.0, 0.01, 4), (0.5, 0.02, 1)]
+    st = [perturbed_line_soliton(box, a=a, eps=e, k=k, x0=-10.0) for a, e, k in params]
+    fields = [np.stack([m[i] for m in st]) for i in range(4)]
+    kw = dict(gmres_tol=1e-10, krasny=1e-12)
+    results = {}
+    for rr in ("0", "8"):
+        os.environ["SGN_ROW_RADIX"] = rr
+        try:
+            cb = ctx_for(nx, ny, 10.0, 5.0, len(params), **kw)
+        finally:
+            os.environ.pop("SGN_ROW_RADIX", None)
+        assert sgn.sgn_launch_shape(cb)["row_radix"] == int(rr)
+        fb = [to_dev(a, torch.float64) for a in fields]
+        sgn.sgn_rk4_step(cb, *fb, 0.005, 2)
+        results[rr] = [host(t) for t in fb]
+        cb.close()
+    e = max(np.abs(results["8"][i] - results["0"][i]).max() / max(np.abs(results["0"][i] - (1.0 if i == 0 else 0.0)).max(), 1e-300)
+            for i in range(3))
+    say(f"members radix 8 vs 4 after two steps: {e:.1e}")
+    assert e < 1e-12
+    g = O.Grid(O.Config(nx=nx, ny=ny, Lx=10.0, Ly=5.0, gmres_tol=1e-10, krasny=1e-12))
+    oh, ovx, _, _, _ = O.rk4(g, *(a[1] for a in fields), 0.005, 2)
+    assert np.abs(results["8"][0][1] - oh).max() / np.abs(oh - 1.0).max() < 1e-10
+    cb = ctx_for(nx, ny, 10.0, 5.0, len(params), **kw)
+    chosen = sgn.sgn_autotune(cb)
+    shape = sgn.sgn_launch_shape(cb)
+    say(f"members autotune: schedule {chosen}, shape {shape}")
+    fb = [to_dev(a, torch.float64) for a in fields]
+    infos = sgn.sgn_rk4_step(cb, *fb, 0.005, 2)
+    for k in (0, 3):
+        got = host(fb[0])[k]
+        assert np.abs(got - results["0"][0][k]).max() / np.abs(results["0"][0][k] - 1.0).max() < 1e-12
+    assert all(i.any_unconverged == 0 for i in infos)
+    cb.close()
