@@ -41,12 +41,16 @@ PARAMS = dict(a=0.5, eps=0.01, k=2)  # the run of the nine timed alone (single_g
 KRASNY = 1e-12
 
 # The roofline entry is for the kernel class with the largest share of device
-# time on this workload: the x part of the elliptic operator in the Arnoldi
-# step (kernel B, k_row_matvec3: inverse x-transforms of E and G, the
-# pointwise products with 1/h, forward x-transforms into P and Q).  Its
-# algorithmic bytes per launch, 5 fields (E, G, h read; P, Q written), are
-# summed by the library over the launches that did work.
-DOMINANT = "row_matvec"
+# time on the headline workload (rocprofv3 kernel statistics of the nine-run
+# context): kernel A of the three-kernel Arnoldi step, k_col_proj, which
+# finishes step j - 1 from C's block partials, forms u_j = w_{j-1} - sum_i
+# c_i V_i and the inverse y-transforms E, G of it.  Its algorithmic bytes in
+# step j are j + 4 fields (w_{j-1} and V_0..V_{j-1} read; u_j, E, G written),
+# summed by the library over the launches that did work.  --time-class picks
+# another class for profiler runs; the single grid and the 16-grid FP32 group
+# report kernel B (the x part of the operator), which leads there.
+DOMINANT = "col_basis"
+ROW_CLASS = "row_matvec"
 EVENT_PERIOD = 7  # launches of the timed class per launch that carries events
 
 
@@ -65,6 +69,13 @@ def parse():
     p.add_argument("--c3-only", choices=("fp64", "fp32_mixed"),
                    help="time only the 2048^2 Gaussian in one precision, events on every launch of its "
                         "dominant Arnoldi kernel class (for profiler runs)")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="keep the library's default launch choices (or those set by SGN_* variables) instead of "
+                        "autotuning the member contexts; for profiler runs, whose counters would include the "
+                        "autotuner's trial dispatches")
+    p.add_argument("--time-class", choices=("col_basis", "row_matvec", "col_precond_dot"), default=DOMINANT,
+                   help="kernel class of the headline run that carries HIP events and gives the roofline entry "
+                        "(default: the class with the largest share of device time)")
     p.add_argument("--t5-steps", type=int, default=1000,
                    help="steps of the 2048^2 precision comparison at t = 5 (dt = 0.005; 0 skips it)")
     p.add_argument("--t20-steps", type=int, default=4000,
@@ -141,17 +152,32 @@ def iters_summary(infos):
             "solves": sum(i.solves for i in infos)}
 
 
-def roofline_entry(kernel: str, kt, workload: str):
+def sweep_kernel_labels(box, shape) -> dict:
+    """Names of the three Arnoldi kernel classes of the nine-member context."""
+    return {
+        "col_basis": f"k_col_proj<{box.ny}> (Arnoldi kernel A: finishes step j-1, u_j = w_(j-1) - sum_i c_i V_i, "
+                     f"inverse y-transforms E, G of u_j), nine grids per launch",
+        "row_matvec": f"k_row_matvec2<{box.nx}> (Arnoldi kernel B: x part of the elliptic operator, two transform "
+                      f"chains per block, {shape['row_radix'] or 4} values per thread), nine grids per launch",
+        "col_precond_dot": f"k_col_precond_new<{box.ny}> (Arnoldi kernel C: forward y-transforms of P, Q, the "
+                           f"preconditioner, V_j and the projections onto the basis), nine grids per launch",
+    }
+
+
+def roofline_entry(kernel: str, kt, workload: str, klass: str):
     launches, kms, algo_total = kt
     algo = algo_total / launches if launches else 0.0  # per launch, averaged over all timed launches
     mean_s = (kms / launches) / 1e3 if launches else float("nan")
     achieved = algo / mean_s / 1e9 if launches else None
-    ratio = traffic_ratio_from_profile(DOMINANT, workload)
+    ratio = traffic_ratio_from_profile(klass, workload)
     traffic = ratio * algo if (ratio is not None and launches) else None  # HBM bytes per launch
     return {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
             "algorithmic_bytes_per_launch": algo, "mean_launch_us": mean_s * 1e6, "launches": launches,
             "events_on_every": EVENT_PERIOD}
+
+
+AUTOTUNE = True
 
 
 def sweep_context(sgn, torch, dev, guess=None):
@@ -163,7 +189,8 @@ def sweep_context(sgn, torch, dev, guess=None):
         kw["guess"] = guess
     cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, **kw)
     ctx = sgn.sgn_init(cfg, dev)
-    sgn.sgn_autotune(ctx)  # schedule, launch shapes and row radix for nine members of this grid
+    if AUTOTUNE:
+        sgn.sgn_autotune(ctx)  # schedule, launch shapes and row radix for nine members of this grid
     f = [torch.from_numpy(a).to(dev).contiguous() for a in state]
     return box, ak, w, ctx, f
 
@@ -194,14 +221,15 @@ def single_grid_run(sgn, torch, dev, args, with_roofline=True):
     f = [torch.from_numpy(a).to(dev).contiguous() for a in state]
     if args.warmup > 0:
         sgn.sgn_rk4_step(ctx, *f, w["dt"], args.warmup)
-    kind = [k for k, v in sgn.KERNEL_NAMES.items() if v == DOMINANT][0]
+    kind = [k for k, v in sgn.KERNEL_NAMES.items() if v == ROW_CLASS][0]
     el, infos, kt = timed_kernel_run(sgn, torch, ctx, f, w["dt"], args.steps, kind if with_roofline else None)
     ctx.close()
     out = {"workload": WORKLOAD, "a": PARAMS["a"], "k": PARAMS["k"],
            "value": box.nx * box.ny * args.steps / el, "ms_per_step": el * 1e3 / args.steps}
     out.update(iters_summary(infos))
     if kt:
-        out["roofline"] = roofline_entry(f"k_row_matvec3<{box.nx}> (kernel B), one grid per launch", kt, WORKLOAD)
+        out["roofline"] = roofline_entry(f"k_row_matvec3<{box.nx}> (kernel B), one grid per launch", kt, WORKLOAD,
+                                         ROW_CLASS)
     return out
 
 
@@ -608,7 +636,7 @@ def batched_form(sgn, torch, dev, args, per_grid: int = 16):
     out["members_serial"] = {"value": pts * steps / el_ser, "ms_per_step": el_ser * 1e3 / steps}
     # kernel B of the largest group against the roofline
     c, f, dt, _ = ctxs[-1]
-    kind = [k for k, v in sgn.KERNEL_NAMES.items() if v == DOMINANT][0]
+    kind = [k for k, v in sgn.KERNEL_NAMES.items() if v == ROW_CLASS][0]
     _, _, kt = timed_kernel_run(sgn, torch, c, [t.clone() for t in f], dt, steps, kind, period=1)
     n, ms, by = kt
     ach = by / n / (ms / n * 1e-3) / 1e9 if n else None
@@ -701,6 +729,8 @@ def host_cpu():
 
 def main():
     args = parse()
+    global AUTOTUNE
+    AUTOTUNE = not args.no_autotune
     if args.copy_calibration:
         copy_calibration(args.copy_calibration, max(args.steps, 1))
         return
@@ -729,12 +759,24 @@ def main():
     # timed first so that the headline run below is the last thing measured
     alt = None if args.main_only else timed_guess_run(sgn, torch, dev, args)
     progress("stage-increment guess run done")
-    kind = [k for k, v in sgn.KERNEL_NAMES.items() if v == DOMINANT][0]
+    shape = sgn.sgn_launch_shape(ctx)
+    labels = sweep_kernel_labels(box, shape)
+    # the other Arnoldi kernel classes against the roofline, each on a copy
+    # of the warm state (so the headline run starts where it would alone)
+    others = {}
+    if not args.main_only:
+        for klass in labels:
+            if klass == args.time_class:
+                continue
+            kk = [k for k, v in sgn.KERNEL_NAMES.items() if v == klass][0]
+            _, _, kto = timed_kernel_run(sgn, torch, ctx, [t.clone() for t in f], w["dt"], args.steps, kk)
+            others[klass] = roofline_entry(labels[klass], kto, SWEEP_WORKLOAD, klass)
+        progress("other kernel classes timed")
+    kind = [k for k, v in sgn.KERNEL_NAMES.items() if v == args.time_class][0]
     # events on every EVENT_PERIOD-th launch of the class: recording them on
     # every launch costs about 3% of the step
     elapsed, infos, kt = timed_kernel_run(sgn, torch, ctx, f, w["dt"], args.steps, kind)
     progress(f"timed run done: {elapsed * 1e3 / args.steps:.3f} ms per step")
-    shape = sgn.sgn_launch_shape(ctx)
     ctx.close()
     npts = len(ak) * box.nx * box.ny
     config = {
@@ -764,10 +806,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": config,
-        "roofline": roofline_entry(f"k_row_matvec3<{box.nx}> (Arnoldi kernel B: x part of the elliptic operator, "
-                                   f"three transform chains per row pair), nine grids per launch", kt,
-                                   SWEEP_WORKLOAD),
+        "roofline": roofline_entry(labels[args.time_class], kt, SWEEP_WORKLOAD, args.time_class),
     }
+    if others:
+        out["roofline_other_classes"] = others
     if not args.main_only:
         out["single_grid"] = single_grid_run(sgn, torch, dev, args)
         progress("single-grid run done")
