@@ -291,24 +291,29 @@ def sweep_to_t20(sgn, torch, dev, steps):
 
 def graph_form(sgn, torch, box, state, w, dev, args):
     """The same K steps (after W warm-up steps) with every RK4 step replayed as
-    one captured HIP graph (sgn_rk4_step_graph, automatic iteration budget),
-    beside the host-driven loop on a fresh context: bitwise the same states."""
+    one captured HIP graph (sgn_rk4_step_graph, automatic per-stage iteration
+    budgets), beside the host-driven loop on a fresh context: bitwise the same
+    states; steps_replayed counts the timed steps that ran as replays (the
+    others were chunks redone host-driven)."""
     out = {}
     for mode in ("host", "graph"):
         cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"], gmres_restart=w["restart"],
                                  krasny=KRASNY)
         ctx = sgn.sgn_init(cfg, dev)
         f = [torch.from_numpy(a).to(dev).contiguous() for a in state]
-        step = (lambda n: sgn.sgn_rk4_step(ctx, *f, w["dt"], n)) if mode == "host" else \
-            (lambda n: sgn.sgn_rk4_step_graph(ctx, *f, w["dt"], n)[0])
+        step = (lambda n: (sgn.sgn_rk4_step(ctx, *f, w["dt"], n), n)) if mode == "host" else \
+            (lambda n: sgn.sgn_rk4_step_graph(ctx, *f, w["dt"], n))
         if args.warmup > 0:
             step(args.warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        step(args.steps)
+        info, nrep = step(args.steps)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        out[mode] = {"value": box.nx * box.ny * args.steps / el, "ms_per_step": el * 1e3 / args.steps}
+        out[mode] = {"value": box.nx * box.ny * args.steps / el, "ms_per_step": el * 1e3 / args.steps,
+                     "iters_per_solve_mean": info.total_iters / max(info.solves, 1)}
+        if mode == "graph":
+            out[mode]["steps_replayed"] = nrep
         out[mode + "_state"] = [t.clone() for t in f]
         ctx.close()
     same = all(torch.equal(a, b) for a, b in zip(out.pop("host_state"), out.pop("graph_state")))
@@ -640,7 +645,10 @@ def batched_form(sgn, torch, dev, args, per_grid: int = 16):
     _, _, kt = timed_kernel_run(sgn, torch, c, [t.clone() for t in f], dt, steps, kind, period=1)
     n, ms, by = kt
     ach = by / n / (ms / n * 1e-3) / 1e9 if n else None
-    out["roofline_1024x1024_group"] = {"kernel": "k_row_matvec3<1024> (kernel B), 16 grids per launch, FP32",
+    shp = sgn.sgn_launch_shape(c)
+    kname = (f"k_row_matvec2<1024> (kernel B, two transform chains per block, {shp['row_radix'] or 4} values "
+             f"per thread)" if shp["arnoldi"] == 2 else "Arnoldi x-part kernel")
+    out["roofline_1024x1024_group"] = {"kernel": f"{kname}, 16 grids per launch, FP32", "launch_shape": shp,
                                        "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                        "frac": ach / HBM_PEAK_GBS if ach else None,
                                        "algorithmic_bytes_per_launch": by / n if n else None,

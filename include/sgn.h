@@ -233,23 +233,28 @@ int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double 
                  sgn_step_info* info);
 
 /* The same RK4 steps with each step replayed as one captured HIP graph, so
- * that a step costs no host round trips.  In a graph every solve is a single
- * GMRES cycle of iter_budget Arnoldi steps (1 <= iter_budget <= gmres_restart;
- * iter_budget <= 0: automatic), each kernel predicated on the device status,
- * so the solve stops at convergence exactly as in sgn_rk4_step; a device
- * counter records any solve that reaches the budget unconverged.  Automatic
- * budget: the context's previous one, else the first step of the call runs
- * host-driven and sets it to its largest solve + 2.  If any solve of the call
- * reaches the budget, the call restores (h, vx, vy, sigma) from a checkpoint
- * taken at its start (workspace), redoes all nsteps with sgn_rk4_step and
- * (automatic budget) raises the budget to that run's largest solve + 2.
- * Results are bitwise those of sgn_rk4_step with the same arguments.  The
- * graphs are captured on a stream private to the context, ordered after the
- * work on the context's stream and before work enqueued there later, and are
- * cached per (h, vx, vy, dt, budget, launch shapes).  Kernel timing (sgn_kernel_timing)
- * counts host-driven launches only.  *replayed (may be NULL): 1 if graph
- * replays ran the steps, 0 if the call ran host-driven.  Errors: as
- * sgn_rk4_step; SGN_ERR_INVALID_ARG for iter_budget > gmres_restart. */
+ * that a step costs no host round trips.  In a graph the solve of RK stage s
+ * is a single GMRES cycle of budget[s] Arnoldi steps, each kernel predicated
+ * on the device status and the device's iteration cap set to budget[s], so the
+ * solve stops at convergence exactly as in sgn_rk4_step; a device counter
+ * records any solve that reaches its budget unconverged.  Budgets: iter_budget
+ * for every stage (1 <= iter_budget <= gmres_restart), or with iter_budget <= 0
+ * automatic: per stage, the most iterations that stage needed in the
+ * host-driven steps of the context so far (the first two steps of the first
+ * call run host-driven to measure them), plus SGN_GRAPH_MARGIN (environment at
+ * sgn_init, 0..4, default 0).  The steps run in chunks of 8 replays: each
+ * chunk starts from a checkpoint of (h, vx, vy) and of the solver state carried
+ * between steps (workspace), and ends with one status read; a chunk in which a
+ * solve reached its budget is restored and redone host-driven, and automatic
+ * budgets grow to what the redone steps needed.  Solves that need restarts
+ * keep the rest of the call host-driven.  Results are bitwise those of
+ * sgn_rk4_step with the same arguments.  The graphs are captured on a stream
+ * private to the context, ordered after the work on the context's stream and
+ * before work enqueued there later, and are cached per (h, vx, vy, dt,
+ * budgets, launch shapes).  Kernel timing (sgn_kernel_timing) counts
+ * host-driven launches only.  *replayed (may be NULL): the number of steps run
+ * as graph replays (0 if the call ran host-driven).  Errors: as sgn_rk4_step;
+ * SGN_ERR_INVALID_ARG for iter_budget > gmres_restart. */
 int sgn_rk4_step_graph(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double dt, int32_t nsteps,
                        int32_t iter_budget, sgn_step_info* info, int32_t* replayed);
 
@@ -355,6 +360,13 @@ const char* sgn_cnn_last_error(const sgn_cnn* net);
  * otherwise); the captured step (sgn_rk4_step_graph) refuses contexts with a
  * network or recorder attached.  Resets the recorded count. */
 int sgn_learned_guess_attach(sgn_ctx* ctx, sgn_cnn* net, float* record, int32_t capacity);
+
+/* Which RK stages' solves the attached network corrects: bit s of stage_mask
+ * (s = 0..3) for stage s; the other stages start from the plain warm start
+ * (the recorder, if attached, still records every solve).  Default 0xF (every
+ * stage); 0x1 runs the network once per RK4 step.  Errors: SGN_ERR_INVALID_ARG
+ * for a mask outside 0..15. */
+int sgn_learned_guess_stages(sgn_ctx* ctx, int32_t stage_mask);
 /* Samples recorded since the last attach. */
 int sgn_learned_guess_recorded(sgn_ctx* ctx, int64_t* count);
 

@@ -58,23 +58,34 @@ struct sgn_ctx {
   double timed_ms = 0.0;
   double timed_bytes = 0.0;  // algorithmic bytes of the timed launches that did work
   // captured RK4 step (sgn_rk4_step_graph)
-  char* ckpt = nullptr;             // h, vx, vy, sigma at the start of a captured call
+  // h, vx, vy and the carried solver state (SIG, E, G, with the stage-increment
+  // guess D_0..D_3) at the start of a chunk of captured steps
+  char* ckpt = nullptr;
   hipStream_t gstream = nullptr;    // private stream: capture and replays
   hipEvent_t gev[2] = {nullptr, nullptr};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};  // first step of a call, later steps
   struct GraphKey {
     const void *h = nullptr, *vx = nullptr, *vy = nullptr;
     double dt = 0.0;
-    int budget = 0;
+    int budget[4] = {0, 0, 0, 0};
     int arnoldi = 0, tile_blocks = 0, row_threads = 0;  // the launch shapes captured
     bool operator==(const GraphKey& o) const {
-      return h == o.h && vx == o.vx && vy == o.vy && dt == o.dt && budget == o.budget && arnoldi == o.arnoldi &&
-             tile_blocks == o.tile_blocks && row_threads == o.row_threads;
+      return h == o.h && vx == o.vx && vy == o.vy && dt == o.dt && std::equal(budget, budget + 4, o.budget) &&
+             arnoldi == o.arnoldi && tile_blocks == o.tile_blocks && row_threads == o.row_threads;
     }
   } gkey[2];
-  int graph_budget = 0;  // Arnoldi steps per captured solve (0: not yet calibrated)
+  // Arnoldi steps per captured solve, per RK stage (0: not yet calibrated):
+  // the most the stage needed in the host-driven steps seen, plus graph_margin
+  int graph_budgets[4] = {0, 0, 0, 0};
+  int graph_margin = 0;
+  // captured kernels test the GMRES status before their loads (1) or after (0,
+  // as the host-driven loop does); 1 measured faster in replays (1024x512
+  // FP64: 1.874 against 1.958 ms per step)
+  int graph_status_first = 1;
+  int stage_max[4] = {0, 0, 0, 0};  // most iterations per RK stage in the host-driven steps since a reset
   // learned initial guess (sgn_learned_guess_attach)
   sgn_cnn* learn_net = nullptr;  // network correcting the warm start, or null
+  int32_t learn_stages = 0xF;    // RK stages whose solves the network corrects (bit s: stage s)
   float* learn_rec = nullptr;    // recorder: learn_cap slots of (input [n][3], target [n])
   int32_t learn_cap = 0;
   int64_t learn_count = 0;       // solves recorded
@@ -179,6 +190,8 @@ struct Layout {
   int nfields;
 };
 
+int ckpt_fields(const sgn_config* c) { return 6 + (c->guess == SGN_GUESS_STAGE_INCREMENT ? 4 : 0); }
+
 Layout layout(const sgn_config* c) {
   Layout L;
   const size_t n = (size_t)c->nx * c->ny;
@@ -201,8 +214,9 @@ Layout layout(const sgn_config* c) {
   off += align_up((size_t)pblocks * sgn::kPartialStride * sizeof(double));
   L.fields = off;
   // V (restart + 1), Z, W, E, G, P, Q, R1, R2, SIG, hs, vxs, vys, acc_h, acc_vx, acc_vy,
-  // the checkpoint of a captured call (4), and with the stage-increment guess D_0..D_3
-  L.nfields = c->gmres_restart + 1 + 15 + 4 + (c->guess == SGN_GUESS_STAGE_INCREMENT ? 4 : 0);
+  // the checkpoint of captured steps (h, vx, vy, SIG, E, G, and D_0..D_3 with the
+  // stage-increment guess), and with that guess D_0..D_3
+  L.nfields = c->gmres_restart + 1 + 15 + ckpt_fields(c) + (c->guess == SGN_GUESS_STAGE_INCREMENT ? 4 : 0);
   off += (size_t)L.nfields * L.field_bytes;
   L.member = align_up(off);
   L.total = L.member * (size_t)c->batch;
@@ -671,11 +685,11 @@ int clear_guess(sgn_ctx* ctx) {
 // Start of a solve with the learned guess or the recorder: r0 = b - L sigma_prev
 // and M^-1 r0 from the GMRES start kernels, their scale |r0| (RMS, in the
 // device state), the network input (into the recorder's slot when recording)
-// and, with a network, sigma_prev replaced by sigma_prev + |r0| net(input).
+// and, with use_net, sigma_prev replaced by sigma_prev + |r0| net(input).
 // Scratch: V_0, V_1, V_2 (physical r0, M^-1 r0, the guess; the solve
 // overwrites them afterwards), R1, R2 (x-half spectra) and the first
 // checkpoint field (sigma_prev, kept for the recorder's target).
-int learned_start(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, float** slot) {
+int learned_start(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, float** slot, bool use_net) {
   const sgn::Geom& g = ctx->g;
   hipStream_t s = ctx->stream;
   const size_t n = (size_t)g.nx * g.ny;
@@ -700,7 +714,7 @@ int learned_start(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, f
     in3 = sgn_cnn_in3_buffer(ctx->learn_net);
   }
   HIPCK(sgn::launch_learn_pack(g, r0, mr0, h, n, ctx->st, in3, s));
-  if (!ctx->learn_net) return SGN_OK;
+  if (!use_net) return SGN_OK;
   float* out = sgn_cnn_out_buffer(ctx->learn_net);
   if (sgn_cnn_forward_on(ctx->learn_net, in3, out, s) != SGN_OK) {
     ctx->err = "learned guess: network forward pass failed";
@@ -723,12 +737,14 @@ int learned_finish(sgn_ctx* ctx, float* slot) {
 
 // ---- the captured RK4 step
 
-// One RK4 step for capture: each solve is a single GMRES cycle of `budget`
-// Arnoldi steps, all predicated on the device status (the caller sets the
-// iteration cap to the budget, so the device stops at convergence or there),
-// followed by the solve counters.  kind 0: first step of a call (sigma
-// itself is the guess); kind 1: later steps (stage-increment guess, if on).
-int enqueue_graph_step(sgn_ctx* ctx, int kind, void* h, void* vx, void* vy, double dt, int budget) {
+// One RK4 step for capture: the solve of stage s is a single GMRES cycle of
+// budget[s] Arnoldi steps, all predicated on the device status, with the
+// device's iteration cap at budget[s] (so the device closes the cycle at
+// convergence or there): the caller sets budget[0] before the first replay,
+// and each solve's counter kernel sets the cap of the next (stage 3's that of
+// the next step's stage 0).  kind 0: first step of a call (sigma itself is
+// the guess); kind 1: later steps (stage-increment guess, if on).
+int enqueue_graph_step(sgn_ctx* ctx, int kind, void* h, void* vx, void* vy, double dt, const int* budget) {
   const sgn::Geom& g = ctx->g;
   hipStream_t s = ctx->stream;
   int rc;
@@ -739,24 +755,24 @@ int enqueue_graph_step(sgn_ctx* ctx, int kind, void* h, void* vx, void* vy, doub
     void* Dst = ctx->D ? ctx->D + (size_t)stage * ctx->field_bytes : nullptr;
     if (Dst && kind == 1) HIPCK(sgn::launch_col_guess_eg(g, ctx->SIG, Dst, ctx->E, ctx->G, s));
     if ((rc = enqueue_residual(ctx, 1, ih, ivx, ivy, 1, 1))) return rc;
-    for (int it = 0; it < budget; ++it)
+    for (int it = 0; it < budget[stage]; ++it)
       if ((rc = enqueue_arnoldi(ctx, ih, it))) return rc;
     HIPCK(sgn::launch_col_update_eg(g, ctx->SIG, ctx->V, ctx->vstride, ctx->st, ctx->E, ctx->G, Dst, 0, s));
-    HIPCK(sgn::launch_solve_stats(g, ctx->st, s));
+    HIPCK(sgn::launch_solve_stats(g, ctx->st, budget[(stage + 1) & 3], s));
     if ((rc = enqueue_stage_flux(ctx, stage, dt, h, vx, vy, ih, ivx, ivy))) return rc;
   }
   return enqueue_step_filter(ctx, h, vx, vy);
 }
 
 // Instantiated graph of one step of this kind, captured on ctx->stream (the
-// private stream) unless the cached one has the same fields, dt and budget.
-int graph_for(sgn_ctx* ctx, int kind, void* h, void* vx, void* vy, double dt, int budget) {
+// private stream) unless the cached one has the same fields, dt and budgets.
+int graph_for(sgn_ctx* ctx, int kind, void* h, void* vx, void* vy, double dt, const int* budget) {
   sgn_ctx::GraphKey key;
   key.h = h;
   key.vx = vx;
   key.vy = vy;
   key.dt = dt;
-  key.budget = budget;
+  std::copy(budget, budget + 4, key.budget);
   key.arnoldi = ctx->arnoldi;
   key.tile_blocks = ctx->g.tile_blocks;
   key.row_threads = ctx->g.row_threads;
@@ -768,7 +784,7 @@ int graph_for(sgn_ctx* ctx, int kind, void* h, void* vx, void* vy, double dt, in
   const int timed = ctx->timed_kind;  // no timing events inside a graph
   ctx->timed_kind = -1;
   HIPCK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeRelaxed));
-  ctx->g.status_first = 1;  // most of a budget's steps after convergence exit at once
+  ctx->g.status_first = ctx->graph_status_first;
   const int rc = enqueue_graph_step(ctx, kind, h, vx, vy, dt, budget);
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
@@ -786,8 +802,6 @@ int graph_for(sgn_ctx* ctx, int kind, void* h, void* vx, void* vy, double dt, in
   ctx->gkey[kind] = key;
   return SGN_OK;
 }
-
-int set_maxit(sgn_ctx* ctx, int32_t v) { return set_state_scalar(ctx, &ctx->st->maxit, v); }
 
 // Runs a captured call on the context's private stream, ordered after the
 // work already on the caller's stream and before the work enqueued there
@@ -880,6 +894,13 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
     const int v = std::atoi(bm);
     if (v >= 0 && v <= 4) ctx->batch_margin = v;
   }
+  // SGN_GRAPH_MARGIN (0..4): Arnoldi steps a captured solve runs beyond the
+  // most its stage needed in the host-driven steps seen
+  if (const char* gm = std::getenv("SGN_GRAPH_MARGIN")) {
+    const int v = std::atoi(gm);
+    if (v >= 0 && v <= 4) ctx->graph_margin = v;
+  }
+  if (const char* gs = std::getenv("SGN_GRAPH_STATUS_FIRST")) ctx->graph_status_first = std::atoi(gs) != 0;
   if (!sgn::chained_ok(g)) ctx->arnoldi = 0;
   char* base = ctx->ws;
   const int M = cfg->batch;
@@ -931,7 +952,7 @@ int sgn_init(const sgn_config* cfg, void* ws, size_t ws_bytes, void* hip_stream,
   ctx->acc_vx = next();
   ctx->acc_vy = next();
   ctx->ckpt = f;
-  f += 4 * L.field_bytes;
+  f += (size_t)ckpt_fields(cfg) * L.field_bytes;
   ctx->D = nullptr;
   if (cfg->guess == SGN_GUESS_STAGE_INCREMENT) {
     ctx->D = f;
@@ -1177,25 +1198,26 @@ int sgn_rhs(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, void* s
   return all_converged(res) ? SGN_OK : SGN_ERR_NOT_CONVERGED;
 }
 
-int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double dt, int32_t nsteps,
-                 sgn_step_info* info) {
-  if (!ctx || !aligned(h) || !aligned(vx) || !aligned(vy) || !aligned(sigma) || nsteps < 0 || !std::isfinite(dt))
-    return SGN_ERR_INVALID_ARG;
-  int rc = check_state(ctx, h, vx, vy);
-  if (rc) return rc;
-  rc = load_sigma(ctx, sigma);
-  if (rc) return rc;
+namespace {
+
+// Per-member totals of the steps of one call.
+struct StepTally {
+  std::vector<int64_t> total;
+  std::vector<int> maxper, unconv;
+  int solves = 0;
+  explicit StepTally(int M) : total(M, 0), maxper(M, 0), unconv(M, 0) {}
+};
+
+// Steps [first, first + n) of a call, host-driven, continuing from the
+// carried state as it stands (SIG, E, G and, with the stage-increment guess,
+// D).  Records the most iterations of each stage in ctx->stage_max (member 0).
+int rk4_host_steps(sgn_ctx* ctx, void* h, void* vx, void* vy, double dt, int first, int n, StepTally& t) {
   const sgn::Geom& g = ctx->g;
   hipStream_t s = ctx->stream;
   const int M = members(ctx);
-  std::vector<int64_t> total(M, 0);
-  std::vector<int> maxper(M, 0), unconv(M, 0);
-  int solves = 0;
-  // stage-increment guess: the increments start at zero in every call, so the
-  // first step starts each stage from the previous stage's sigma
-  if ((rc = clear_guess(ctx))) return rc;
+  int rc;
   std::vector<SolveResult> res(M);
-  for (int step = 0; step < nsteps; ++step) {
+  for (int step = first; step < first + n; ++step) {
     for (int stage = 0; stage < 4; ++stage) {
       const void* ih = stage == 0 ? h : ctx->hs;
       const void* ivx = stage == 0 ? vx : ctx->vxs;
@@ -1203,7 +1225,8 @@ int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double 
       void* Dst = ctx->D ? ctx->D + (size_t)stage * ctx->field_bytes : nullptr;
       if (Dst && step > 0) HIPCK(sgn::launch_col_guess_eg(g, ctx->SIG, Dst, ctx->E, ctx->G, s));
       float* slot = nullptr;
-      if ((ctx->learn_net || ctx->learn_rec) && (rc = learned_start(ctx, ih, ivx, ivy, &slot))) return rc;
+      const bool use_net = ctx->learn_net && ((ctx->learn_stages >> stage) & 1);
+      if ((use_net || ctx->learn_rec) && (rc = learned_start(ctx, ih, ivx, ivy, &slot, use_net))) return rc;
       // the stage's fluxes follow each batch of Arnoldi steps speculatively
       // (not with the learned guess, whose finish comes between, nor for
       // ensemble members, which finish their solves at different steps)
@@ -1214,30 +1237,52 @@ int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double 
       if (rc) return rc;
       if (slot && (rc = learned_finish(ctx, slot))) return rc;
       for (int k = 0; k < M; ++k) {
-        total[k] += res[k].iters;
-        maxper[k] = std::max(maxper[k], res[k].iters);
-        unconv[k] |= !res[k].converged;
+        t.total[k] += res[k].iters;
+        t.maxper[k] = std::max(t.maxper[k], res[k].iters);
+        t.unconv[k] |= !res[k].converged;
       }
-      solves += 1;
+      ctx->stage_max[stage] = std::max(ctx->stage_max[stage], res[0].iters);
+      t.solves += 1;
       if (!res[0].post_done && (rc = enqueue_stage_flux(ctx, stage, dt, h, vx, vy, ih, ivx, ivy))) return rc;
     }
-    rc = enqueue_step_filter(ctx, h, vx, vy);
-    if (rc) return rc;
+    if ((rc = enqueue_step_filter(ctx, h, vx, vy))) return rc;
   }
-  HIPCK(sgn::launch_row_c2r(g, ctx->E, sigma, s));
-  HIPCK(sgn::launch_field_stats(g, h, vx, vy, (size_t)g.nx * g.ny, ctx->st, ctx->partials, s));
-  rc = read_status(ctx);
+  return SGN_OK;
+}
+
+// The checkpoint of a chunk of captured steps (save) or its restoration:
+// the caller's h, vx, vy and the carried solver state SIG, E, G (and D_0..D_3).
+int chunk_checkpoint(sgn_ctx* ctx, void* h, void* vx, void* vy, bool save) {
+  const sgn::Geom& g = ctx->g;
+  const size_t nb = (size_t)g.nx * g.ny * (g.fp32 ? sizeof(float) : sizeof(double));
+  std::vector<void*> f = {h, vx, vy, ctx->SIG, ctx->E, ctx->G};
+  if (ctx->D)
+    for (int k = 0; k < 4; ++k) f.push_back(ctx->D + (size_t)k * ctx->field_bytes);
+  for (size_t i = 0; i < f.size(); ++i) {
+    void* c = ctx->ckpt + i * ctx->field_bytes;
+    HIPCK(hipMemcpyAsync(save ? c : f[i], save ? f[i] : c, nb, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  return SGN_OK;
+}
+
+// Status words, outputs and return code of a call of K steps.
+int finish_call(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, const StepTally& t, sgn_step_info* info) {
+  const sgn::Geom& g = ctx->g;
+  const int M = members(ctx);
+  HIPCK(sgn::launch_row_c2r(g, ctx->E, sigma, ctx->stream));
+  HIPCK(sgn::launch_field_stats(g, h, vx, vy, (size_t)g.nx * g.ny, ctx->st, ctx->partials, ctx->stream));
+  int rc = read_status(ctx);
   if (rc) return rc;
   bool any_unconv = false, nonfinite = false, cavit = false;
   for (int k = 0; k < M; ++k) {
     if (info) {
-      info[k].total_iters = total[k];
-      info[k].max_iters_per_solve = maxper[k];
-      info[k].solves = solves;
+      info[k].total_iters = t.total[k];
+      info[k].max_iters_per_solve = t.maxper[k];
+      info[k].solves = t.solves;
       info[k].min_h = ctx->hstat[k].stat_minh;
-      info[k].any_unconverged = unconv[k];
+      info[k].any_unconverged = t.unconv[k];
     }
-    any_unconv = any_unconv || unconv[k];
+    any_unconv = any_unconv || t.unconv[k];
     nonfinite = nonfinite || ctx->hstat[k].stat_nonfinite;
     cavit = cavit || !(ctx->hstat[k].stat_minh > 0.0);
   }
@@ -1246,6 +1291,33 @@ int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double 
   return any_unconv ? SGN_ERR_NOT_CONVERGED : SGN_OK;
 }
 
+constexpr int kGraphChunk = 8;  // captured steps between status reads (and checkpoints)
+
+}  // namespace
+
+int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double dt, int32_t nsteps,
+                 sgn_step_info* info) {
+  if (!ctx || !aligned(h) || !aligned(vx) || !aligned(vy) || !aligned(sigma) || nsteps < 0 || !std::isfinite(dt))
+    return SGN_ERR_INVALID_ARG;
+  int rc = check_state(ctx, h, vx, vy);
+  if (rc) return rc;
+  rc = load_sigma(ctx, sigma);
+  if (rc) return rc;
+  // stage-increment guess: the increments start at zero in every call, so the
+  // first step starts each stage from the previous stage's sigma
+  if ((rc = clear_guess(ctx))) return rc;
+  StepTally t(members(ctx));
+  if ((rc = rk4_host_steps(ctx, h, vx, vy, dt, 0, nsteps, t))) return rc;
+  return finish_call(ctx, h, vx, vy, sigma, t, info);
+}
+
+// Captured steps: after a host-driven calibration step (automatic budgets),
+// chunks of kGraphChunk graph replays, each from a checkpoint of the fields
+// and the carried state, followed by one status read.  A chunk in which a
+// solve needed more than its stage's budget is restored and redone
+// host-driven (continuing exactly where the replays started, so the call ends
+// bit for bit where sgn_rk4_step does), and the budgets grow to what the
+// redone steps needed.
 int sgn_rk4_step_graph(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double dt, int32_t nsteps,
                        int32_t iter_budget, sgn_step_info* info, int32_t* replayed) {
   if (replayed) *replayed = 0;
@@ -1263,82 +1335,76 @@ int sgn_rk4_step_graph(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, d
   }
   PrivateStream ps(ctx);
   if (!ps.ok) return fail(ctx, hipErrorInvalidValue, "private stream for the captured step");
-  const sgn::Geom& g = ctx->g;
   hipStream_t s = ctx->stream;
   int rc = check_state(ctx, h, vx, vy);
   if (rc) return rc;
-  // checkpoint: a call whose budget turns out too small is redone host-driven
-  const size_t nb = (size_t)g.nx * g.ny * (g.fp32 ? sizeof(float) : sizeof(double));
-  void* fs[4] = {h, vx, vy, sigma};
-  for (int i = 0; i < 4; ++i)
-    HIPCK(hipMemcpyAsync(ctx->ckpt + (size_t)i * ctx->field_bytes, fs[i], nb, hipMemcpyDeviceToDevice, s));
+  if ((rc = load_sigma(ctx, sigma))) return rc;
+  if ((rc = clear_guess(ctx))) return rc;
   const int m = ctx->cfg.gmres_restart;
   const int cap = m < ctx->cfg.gmres_max_iters ? m : ctx->cfg.gmres_max_iters;
-  int64_t total = 0;
-  int maxper = 0, first = 0;
-  int budget = iter_budget > 0 ? iter_budget : ctx->graph_budget;
-  if (budget > ctx->cfg.gmres_max_iters) budget = ctx->cfg.gmres_max_iters;
-  if (budget <= 0) {
-    // calibration: the first step host-driven; its largest solve plus two
-    sgn_step_info i1;
-    rc = sgn_rk4_step(ctx, h, vx, vy, sigma, dt, 1, &i1);
-    if (rc && rc != SGN_ERR_NOT_CONVERGED) return rc;
-    total = i1.total_iters;
-    maxper = i1.max_iters_per_solve;
-    budget = maxper + 2 < cap ? maxper + 2 : cap;
-    ctx->graph_budget = budget;
-    first = 1;
-    if (rc == SGN_ERR_NOT_CONVERGED) budget = 0;  // needs restarts: stay host-driven
+  const bool fixed = iter_budget > 0;
+  StepTally t(1);
+  int step = 0;
+  int budget[4];
+  auto from_stage_max = [&]() {
+    for (int k = 0; k < 4; ++k) {
+      const int b = std::min(std::max(ctx->stage_max[k] + ctx->graph_margin, 1), cap);
+      ctx->graph_budgets[k] = std::max(ctx->graph_budgets[k], b);
+    }
+  };
+  if (fixed) {
+    for (int k = 0; k < 4; ++k) budget[k] = std::min(iter_budget, cap);
+  } else {
+    if (ctx->graph_budgets[0] <= 0) {
+      // calibration: the first two steps host-driven (the second is the first
+      // that starts from the stage-increment guess, if on)
+      const int nc = std::min(nsteps, 2);
+      std::fill(ctx->stage_max, ctx->stage_max + 4, 0);
+      if ((rc = rk4_host_steps(ctx, h, vx, vy, dt, 0, nc, t))) return rc;
+      from_stage_max();
+      step = nc;
+    }
+    std::copy(ctx->graph_budgets, ctx->graph_budgets + 4, budget);
   }
-  bool ok = budget > 0;
-  if (ok && first < nsteps) {
-    // after a calibration step E, G, SIG and D hold exactly what the host
-    // loop would continue from; otherwise start as the host loop does
-    if (!first) {
-      if ((rc = load_sigma(ctx, sigma))) return rc;
-      if (ctx->D) HIPCK(hipMemsetAsync(ctx->D, 0, 4 * ctx->field_bytes, s));
+  // solves that need restarts stay host-driven
+  bool host_only = t.unconv[0] != 0;
+  const bool two = ctx->D != nullptr;
+  int32_t nrep = 0;
+  while (step < nsteps) {
+    const int n = std::min(kGraphChunk, nsteps - step);
+    if (host_only) {
+      if ((rc = rk4_host_steps(ctx, h, vx, vy, dt, step, nsteps - step, t))) return rc;
+      break;
     }
     // with the stage-increment guess the first step of a call differs
-    const bool two = ctx->D != nullptr;
-    if ((!two || !first) && (rc = graph_for(ctx, 0, h, vx, vy, dt, budget))) return rc;
-    if (two && (first || nsteps > 1) && (rc = graph_for(ctx, 1, h, vx, vy, dt, budget))) return rc;
+    if ((!two || step == 0) && (rc = graph_for(ctx, 0, h, vx, vy, dt, budget))) return rc;
+    if (two && step + n > 1 && (rc = graph_for(ctx, 1, h, vx, vy, dt, budget))) return rc;
+    if ((rc = chunk_checkpoint(ctx, h, vx, vy, true))) return rc;
     HIPCK(hipMemsetAsync(&ctx->st->st.g_fail, 0, 2 * sizeof(int32_t) + sizeof(int64_t), s));
-    if ((rc = set_maxit(ctx, budget))) return rc;
-    for (int step = first; step < nsteps; ++step)
-      HIPCK(hipGraphLaunch(ctx->gexec[two && step > 0 ? 1 : 0], s));
-    if ((rc = set_maxit(ctx, ctx->cfg.gmres_max_iters))) return rc;
-    HIPCK(sgn::launch_row_c2r(g, ctx->E, sigma, s));
-    HIPCK(sgn::launch_field_stats(g, h, vx, vy, (size_t)g.nx * g.ny, ctx->st, ctx->partials, s));
+    if ((rc = set_state_scalar(ctx, &ctx->st->maxit, budget[0]))) return rc;
+    for (int k = step; k < step + n; ++k) HIPCK(hipGraphLaunch(ctx->gexec[two && k > 0 ? 1 : 0], s));
+    if ((rc = set_state_scalar(ctx, &ctx->st->maxit, ctx->cfg.gmres_max_iters))) return rc;
     if ((rc = read_status(ctx))) return rc;
-    ok = ctx->hstat->g_fail == 0;
-    total += ctx->hstat->g_total;
-    if (ctx->hstat->g_max > maxper) maxper = ctx->hstat->g_max;
+    if (ctx->hstat->g_fail == 0) {
+      t.total[0] += ctx->hstat->g_total;
+      t.maxper[0] = std::max(t.maxper[0], (int)ctx->hstat->g_max);
+      t.solves += 4 * n;
+      nrep += n;
+    } else {
+      // a solve needed more than its budget: redo the chunk host-driven
+      if ((rc = chunk_checkpoint(ctx, h, vx, vy, false))) return rc;
+      std::fill(ctx->stage_max, ctx->stage_max + 4, 0);
+      if ((rc = rk4_host_steps(ctx, h, vx, vy, dt, step, n, t))) return rc;
+      host_only = t.unconv[0] != 0;
+      if (!fixed) {
+        from_stage_max();
+        std::copy(ctx->graph_budgets, ctx->graph_budgets + 4, budget);
+      }
+    }
+    step += n;
   }
-  if (!ok) {
-    // a solve needed more than the budget: redo the call host-driven from the
-    // checkpoint, and size the next budget from what it needed
-    for (int i = 0; i < 4; ++i)
-      HIPCK(hipMemcpyAsync(fs[i], ctx->ckpt + (size_t)i * ctx->field_bytes, nb, hipMemcpyDeviceToDevice, s));
-    sgn_step_info ih;
-    rc = sgn_rk4_step(ctx, h, vx, vy, sigma, dt, nsteps, &ih);
-    if (iter_budget <= 0) ctx->graph_budget = ih.max_iters_per_solve + 2 < cap ? ih.max_iters_per_solve + 2 : cap;
-    if (info) *info = ih;
-    return rc;
-  }
-  if (first == nsteps) {  // the calibration step was the whole call
-    if ((rc = read_status(ctx))) return rc;
-  }
-  if (info) {
-    info->total_iters = total;
-    info->max_iters_per_solve = maxper;
-    info->solves = 4 * nsteps;
-    info->min_h = ctx->hstat->stat_minh;
-    info->any_unconverged = 0;
-  }
-  if (replayed) *replayed = first < nsteps ? 1 : 0;
-  if (ctx->hstat->stat_nonfinite) return SGN_ERR_NONFINITE;
-  if (!(ctx->hstat->stat_minh > 0.0)) return SGN_ERR_CAVITATION;
-  return SGN_OK;
+  if (replayed) *replayed = nrep;
+  return finish_call(ctx, h, vx, vy, sigma, t, info);
 }
 
 int sgn_learned_guess_attach(sgn_ctx* ctx, sgn_cnn* net, float* record, int32_t capacity) {
@@ -1364,6 +1430,12 @@ int sgn_learned_guess_attach(sgn_ctx* ctx, sgn_cnn* net, float* record, int32_t 
   ctx->learn_rec = record;
   ctx->learn_cap = record ? capacity : 0;
   ctx->learn_count = 0;
+  return SGN_OK;
+}
+
+int sgn_learned_guess_stages(sgn_ctx* ctx, int32_t stage_mask) {
+  if (!ctx || stage_mask < 0 || stage_mask > 0xF) return SGN_ERR_INVALID_ARG;
+  ctx->learn_stages = stage_mask;
   return SGN_OK;
 }
 

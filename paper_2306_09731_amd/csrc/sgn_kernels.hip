@@ -2202,13 +2202,15 @@ __global__ void __launch_bounds__(256) k_field_stats(Geom g, const real* __restr
 }
 
 // Adds the solve that just finished to the captured-step counters (one GMRES
-// cycle per solve there: anything but convergence counts as a failure).
-__global__ void __launch_bounds__(64) k_solve_stats(GmresState* st) {
+// cycle per solve there: anything but convergence counts as a failure) and
+// sets the iteration cap of the next solve (the next stage's budget).
+__global__ void __launch_bounds__(64) k_solve_stats(GmresState* st, int next_maxit) {
   if (threadIdx.x != 0) return;
   const int it = st->st.total_iters;
   st->st.g_total += it;
   if (it > st->st.g_max) st->st.g_max = it;
   if (st->st.done != 1) st->st.g_fail += 1;
+  if (next_maxit >= 0) st->maxit = next_maxit;
 }
 
 // ----------------------------------------------------------------------------
@@ -2847,8 +2849,8 @@ hipError_t launch_upd(const Geom& g, void* W, const void* V, size_t vs, int j, G
   launch(k_upd, dim3(nb), dim3(kUpdThreads), 0, s, g, WC_(W), RC_(V), vs, j, st, partials, pin, nbin);
   return hipGetLastError();
 }
-hipError_t launch_solve_stats(const Geom&, GmresState* st, hipStream_t s) {
-  launch(k_solve_stats, dim3(1), dim3(64), 0, s, st);
+hipError_t launch_solve_stats(const Geom&, GmresState* st, int next_maxit, hipStream_t s) {
+  launch(k_solve_stats, dim3(1), dim3(64), 0, s, st, next_maxit);
   return hipGetLastError();
 }
 hipError_t launch_field_stats(const Geom& g, const void* h, const void* vx, const void* vy, size_t n, GmresState* st,

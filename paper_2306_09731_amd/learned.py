@@ -133,22 +133,63 @@ def train(samples, device, epochs: int = 12, seed: int = 0, params=None, log=Non
     return sgn.cnn_get_params(net), losses
 
 
+def _bf16(t):
+    """Round to BF16 and back (round to nearest even), the precision of the
+    network's activations and weights."""
+    import torch
+    return t.to(torch.bfloat16).to(t.dtype)
+
+
+def ideal_guess_bound(ctx, box, f, dt_unused=None):
+    """GMRES iterations of one stage-1 solve at the workload's tolerance from
+    (a) the warm start sigma_prev, (b) sigma_prev + BF16(sigma* - sigma_prev),
+    the best a network whose output carries BF16 rounding could return, and
+    (c) the exact sigma* (to 1e-13): the most iterations any BF16 guess can
+    save.  f = (h, vx, vy, sigma_prev) of the current state."""
+    import torch
+    h, vx, vy, sp = f
+    b = torch.empty_like(h)
+    t = torch.empty_like(h)
+    sgn.sgn_derivative(ctx, 0, vx, b)
+    sgn.sgn_derivative(ctx, 1, vy, t)
+    b = -(b + t)
+    tight = sgn.sgn_init(sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=1e-13, gmres_max_iters=400),
+                         h.device)
+    star = sp.clone()
+    sgn.sgn_elliptic_solve(tight, h, b, star)
+    tight.close()
+    out = {}
+    for key, guess in (("warm_start", sp.clone()), ("bf16_exact_correction", sp + _bf16(star - sp)),
+                       ("exact", star.clone())):
+        info = sgn.sgn_elliptic_solve(ctx, h, b, guess)
+        out[key] = int(info.iters)
+    return out
+
+
 def evaluate(params, device, name: str, steps: int = 40, warmup_steps: int = 10, record_n: int = 16):
-    """Warm start against the learned guess on a named workload."""
+    """The paper's warm start against the stage-increment guess and the
+    learned guess (every stage, and once per RK4 step), on a named workload at
+    its tolerance: ms per RK4 step (time to solution per step), GMRES
+    iterations per solve; the network's mean squared error on recorded samples
+    beside the zero and M^-1 r0 predictors; the cost of one forward pass; and
+    the iterations of one solve from an ideal BF16-accurate guess."""
     import torch
     from sgn_inputs import workload
     box, state, w = workload(name)
     out = {"workload": name, "tol": w["tol"], "steps": steps}
-    for mode in ("warm_start", "learned"):
-        cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"], krasny=1e-12)
+    modes = (("warm_start", None), ("stage_increment", None), ("learned", 0xF), ("learned_once_per_step", 0x1))
+    for mode, mask in modes:
+        guess = sgn.SGN_GUESS_STAGE_INCREMENT if mode == "stage_increment" else sgn.SGN_GUESS_PREVIOUS
+        cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"], krasny=1e-12, guess=guess)
         ctx = sgn.sgn_init(cfg, device)
         f = _tensors(state, device)
         sgn.sgn_rk4_step(ctx, *f, DT, warmup_steps)
         net = None
-        if mode == "learned":
+        if mask is not None:
             net = sgn.cnn_init(box.ny, box.nx, device)
             sgn.cnn_set_params(net, params)
             sgn.learned_guess_attach(ctx, net)
+            sgn.learned_guess_stages(ctx, mask)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         info = sgn.sgn_rk4_step(ctx, *f, DT, steps)
@@ -157,6 +198,7 @@ def evaluate(params, device, name: str, steps: int = 40, warmup_steps: int = 10,
         out[mode] = {"ms_per_step": el * 1e3 / steps, "iters_per_solve": info.total_iters / info.solves,
                      "value": box.nx * box.ny * steps / el}
         if mode == "warm_start":
+            out["ideal_guess_iters"] = ideal_guess_bound(ctx, box, f)
             # network error on samples of this workload beside the zero and M^-1 r0 predictors
             rec = torch.zeros(record_n, 4, box.ny, box.nx, dtype=torch.float32, device=device)
             sgn.learned_guess_attach(ctx, None, rec)
@@ -174,6 +216,30 @@ def evaluate(params, device, name: str, steps: int = 40, warmup_steps: int = 10,
                 e_mr.append(float(((x[..., 1] - t) ** 2).mean()))
             out["sample_mse"] = {"network": float(np.mean(e_net)), "zero": float(np.mean(e_zero)),
                                  "minv_r0": float(np.mean(e_mr))}
+            # one forward pass (input packing excluded), mean of 20
+            x = sgn.record_sample(rec, 0)[0].contiguous()
+            sgn.cnn_forward(net, x, pred)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(20):
+                sgn.cnn_forward(net, x, pred)
+            torch.cuda.synchronize()
+            out["forward_ms"] = (time.perf_counter() - t0) * 1e3 / 20
+            # marginal cost of one GMRES iteration: the same steps at a 100x
+            # tighter tolerance from the same state, time and iterations differenced
+            cfg2 = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"] / 100, krasny=1e-12)
+            ctx2 = sgn.sgn_init(cfg2, device)
+            f2 = _tensors(state, device)
+            sgn.sgn_rk4_step(ctx2, *f2, DT, warmup_steps)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info2 = sgn.sgn_rk4_step(ctx2, *f2, DT, steps)
+            torch.cuda.synchronize()
+            ms2 = (time.perf_counter() - t0) * 1e3 / steps
+            it2 = info2.total_iters / info2.solves
+            ctx2.close()
+            d_it = 4 * (it2 - out[mode]["iters_per_solve"])
+            out["marginal_ms_per_gmres_iteration"] = (ms2 - out[mode]["ms_per_step"]) / d_it if d_it > 0 else None
         ctx.close()
     return out
 

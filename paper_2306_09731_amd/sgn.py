@@ -133,6 +133,7 @@ _SIGNATURES = {
     "sgn_cnn_last_error": (ctypes.c_char_p, [_VP]),
     "sgn_learned_guess_attach": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32]),
     "sgn_learned_guess_recorded": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64)]),
+    "sgn_learned_guess_stages": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "sgn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sgn_last_error": (ctypes.c_char_p, [_VP]),
 }
@@ -325,14 +326,14 @@ def sgn_rk4_step_refined(ctx64: Context, ctx32: Context, h, vx, vy, sigma, dt: f
 
 def sgn_rk4_step_graph(ctx: Context, h, vx, vy, sigma, dt: float, nsteps: int = 1, iter_budget: int = 0):
     """sgn_rk4_step with every step replayed as one captured HIP graph.
-    Returns (sgn_step_info, replayed)."""
+    Returns (sgn_step_info, number of steps run as graph replays)."""
     info = sgn_step_info()
     rep = ctypes.c_int32(0)
     st = load_library().sgn_rk4_step_graph(ctx.handle, _field(ctx, h, "h"), _field(ctx, vx, "vx"),
                                            _field(ctx, vy, "vy"), _field(ctx, sigma, "sigma"), float(dt),
                                            int(nsteps), int(iter_budget), ctypes.byref(info), ctypes.byref(rep))
     _check(ctx, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
-    return info, bool(rep.value)
+    return info, int(rep.value)
 
 
 def sgn_rk4_step_ensemble(ctxs, fields, dts, nsteps: int, graphs: bool = False):
@@ -554,6 +555,12 @@ def learned_guess_recorded(ctx: Context) -> int:
     n = ctypes.c_int64()
     _check(ctx, load_library().sgn_learned_guess_recorded(ctx.handle, ctypes.byref(n)))
     return n.value
+
+
+def learned_guess_stages(ctx: Context, stage_mask: int):
+    """RK stages whose solves the attached network corrects (bit s: stage s;
+    0xF every stage, 0x1 once per step)."""
+    _check(ctx, load_library().sgn_learned_guess_stages(ctx.handle, int(stage_mask)))
 
 
 def record_sample(record, i: int):

@@ -75,16 +75,17 @@ def test_invalid_config(field, value):
 def test_workspace_fp32_mode_halves_the_fields():
     a = sgn.sgn_workspace_bytes(sgn.config_default(256, 128, 10.0, 5.0))
     b = sgn.sgn_workspace_bytes(sgn.config_default(256, 128, 10.0, 5.0, precision=sgn.SGN_FP32_MIXED))
-    nfields = 21 + 15 + 4  # basis, working fields, checkpoint of a captured call
+    nfields = 21 + 15 + 6  # basis, working fields, checkpoint of captured steps (h, vx, vy, SIG, E, G)
     # FP32 fields are half as large (both twiddle tables exist in either mode)
     assert a - b == nfields * 256 * 128 * 4
 
 
-def test_workspace_stage_increment_guess_adds_four_fields():
+def test_workspace_stage_increment_guess_adds_eight_fields():
+    # the four stage increments and their copies in the checkpoint of captured steps
     a = sgn.sgn_workspace_bytes(sgn.config_default(128, 64, 10.0, 5.0))
     b = sgn.sgn_workspace_bytes(sgn.config_default(128, 64, 10.0, 5.0, guess=sgn.SGN_GUESS_STAGE_INCREMENT))
     field = 128 * 64 * 8
-    assert b - a == 4 * field
+    assert b - a == 8 * field
 
 
 def test_workspace_size_scales_with_grid_and_restart():
@@ -92,7 +93,7 @@ def test_workspace_size_scales_with_grid_and_restart():
     b = sgn.sgn_workspace_bytes(sgn.config_default(256, 64, 10.0, 5.0))
     c = sgn.sgn_workspace_bytes(sgn.config_default(128, 64, 10.0, 5.0, gmres_restart=40))
     field = 128 * 64 * 8
-    # Krylov basis: restart + 1 fields, plus 15 working fields and a 4-field checkpoint
+    # Krylov basis: restart + 1 fields, plus 15 working fields and a 6-field checkpoint
     assert a >= 40 * field and b > a and c - a == 20 * field
 
 
@@ -165,6 +166,7 @@ def test_cnn_and_learned_guess_host_checks():
     assert lib.sgn_learned_guess_attach(None, None, None, 0) == sgn.SGN_ERR_INVALID_ARG
     n = ctypes.c_int64()
     assert lib.sgn_learned_guess_recorded(None, ctypes.byref(n)) == sgn.SGN_ERR_INVALID_ARG
+    assert lib.sgn_learned_guess_stages(None, 1) == sgn.SGN_ERR_INVALID_ARG
     assert sgn.SGN_CNN_PARAMS == 6 * (9 * 32 * 32 + 32)
 
 

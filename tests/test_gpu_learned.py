@@ -104,6 +104,33 @@ def test_zero_network_changes_nothing_but_rounding():
     assert abs(i1.total_iters - i0.total_iters) <= 2 and e < 1e-10
 
 
+def test_stage_mask_selects_the_corrected_solves():
+    """Mask 0: the attached network is never applied, so the steps are bit for
+    bit the warm start's.  Mask 0x1 (once per RK4 step): the passthrough guess
+    corrects stage 0 only; the state agrees with the warm start's to the
+    solver tolerance and costs no more iterations."""
+    ctx0, f0, _, _ = setup()
+    i0 = sgn.sgn_rk4_step(ctx0, *f0, 0.01, 4)
+    net = sgn.cnn_init(64, 128, DEV)
+    sgn.cnn_set_params(net, passthrough_params())
+    res = {}
+    for mask in (0x0, 0x1):
+        ctx, f, _, _ = setup()
+        sgn.learned_guess_attach(ctx, net)
+        sgn.learned_guess_stages(ctx, mask)
+        res[mask] = (sgn.sgn_rk4_step(ctx, *f, 0.01, 4), f)
+    torch.cuda.synchronize()
+    i_none, f_none = res[0x0]
+    i_once, f_once = res[0x1]
+    e = max(float((a - b).abs().max()) for a, b in zip(f0[:3], f_once[:3]))
+    say(f"stage mask: none {i_none.total_iters}, once per step {i_once.total_iters}, warm start {i0.total_iters}; "
+        f"once-per-step state difference {e:.1e}")
+    assert all(torch.equal(a, b) for a, b in zip(f0, f_none)) and i_none.total_iters == i0.total_iters
+    assert i_once.total_iters <= i0.total_iters and e < 1e-9
+    with pytest.raises(sgn.SgnError):
+        sgn.learned_guess_stages(ctx0, 16)
+
+
 def test_attach_errors():
     ctx, f, _, _ = setup()
     with pytest.raises(sgn.SgnError):
@@ -115,7 +142,7 @@ def test_attach_errors():
     with pytest.raises(sgn.SgnError):
         sgn.sgn_rk4_step_graph(ctx, *f, 0.01, 2)
     sgn.learned_guess_attach(ctx, None)
-    _, rep = sgn.sgn_rk4_step_graph(ctx, *f, 0.01, 2)
+    _, rep = sgn.sgn_rk4_step_graph(ctx, *f, 0.01, 4)  # two calibration steps, then replays
     assert rep
 
 
