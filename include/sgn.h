@@ -367,6 +367,33 @@ int sgn_learned_guess_attach(sgn_ctx* ctx, sgn_cnn* net, float* record, int32_t 
  * stage); 0x1 runs the network once per RK4 step.  Errors: SGN_ERR_INVALID_ARG
  * for a mask outside 0..15. */
 int sgn_learned_guess_stages(sgn_ctx* ctx, int32_t stage_mask);
+
+typedef struct sgn_fgmres_info {
+  int32_t fgmres_iters;       /* flexible GMRES iterations (network applications) */
+  int32_t fgmres_cycles;      /* restart cycles */
+  int32_t gmres_iters;        /* iterations of the plain GMRES judge that follows */
+  int32_t converged;          /* the judge's verdict at cfg.gmres_tol */
+  double fgmres_rel_resid;    /* ||b - L sigma|| / ||b|| when the flexible solve stopped (its estimate) */
+  double rel_resid_true;      /* ||b - L sigma|| / ||b|| of the returned sigma */
+} sgn_fgmres_info;
+
+/* The learned preconditioner: flexible GMRES (Saad's FGMRES, restart
+ * gmres_restart / 2, at most 15) on L_h sigma = b (eq. (sigmav) with a given
+ * b), right-preconditioned by the network: z_j = s net(v_j / s, M^-1 v_j / s,
+ * h - h_inf) with s the RMS of v_j, the map the learned guess was trained as
+ * (an approximation of L^-1 applied to a residual).  Arnoldi with two passes
+ * of classical Gram-Schmidt on FP64 physical fields; the basis V and the
+ * preconditioned directions Z share the Krylov fields of the workspace.  It
+ * stops when its residual estimate reaches cfg.gmres_tol ||b||, after
+ * max_iters network applications, or when a direction adds nothing (a
+ * network output of zero); then plain GMRES (sgn_elliptic_solve, left
+ * preconditioned by M) runs from the result to cfg.gmres_tol: the fallback
+ * and the judge of the error.  net: attached to no other context, grid H =
+ * cfg.ny, W = cfg.nx.  sigma: in = initial guess, out = solution.  FP64
+ * contexts with batch = 1 only (SGN_ERR_UNSUPPORTED otherwise); synchronises
+ * the stream.  Returns what the judge returns. */
+int sgn_elliptic_solve_fgmres(sgn_ctx* ctx, sgn_cnn* net, const void* h, const void* b, void* sigma,
+                              int32_t max_iters, sgn_fgmres_info* info);
 /* Samples recorded since the last attach. */
 int sgn_learned_guess_recorded(sgn_ctx* ctx, int64_t* count);
 

@@ -29,6 +29,7 @@ SOURCES = [
     ("sgn_cnn.hip", "sgn_cnn", []),
     ("sgn_refine.hip", "sgn_refine", []),
     ("sgn_noalloc.hip", "sgn_noalloc", []),
+    ("sgn_fgmres.hip", "sgn_fgmres", []),
     ("sgn_api.cpp", "sgn_api", []),
 ]
 

@@ -1433,6 +1433,186 @@ int sgn_learned_guess_attach(sgn_ctx* ctx, sgn_cnn* net, float* record, int32_t 
   return SGN_OK;
 }
 
+namespace {
+
+// L_h applied to a physical FP64 field (the launches of sgn_apply_operator,
+// without its synchronisation).  Scratch: E, R1, G, P, Q, W, R2.
+int fg_apply_L(sgn_ctx* ctx, const void* h, const void* x, void* out) {
+  const sgn::Geom& g = ctx->g;
+  hipStream_t s = ctx->stream;
+  HIPCK(sgn::launch_row_r2c(g, x, ctx->E, s));
+  HIPCK(sgn::launch_col_fwd_eg(g, ctx->E, ctx->R1, ctx->G, s));
+  HIPCK(sgn::launch_row_op(g, 0, ctx->E, ctx->G, h, nullptr, nullptr, ctx->P, ctx->Q, nullptr, nullptr, 0, 0, ctx->st,
+                           s));
+  HIPCK(sgn::launch_col_apply(g, ctx->P, ctx->Q, 0, ctx->W, s));
+  HIPCK(sgn::launch_col_inv(g, ctx->W, ctx->R2, s));
+  HIPCK(sgn::launch_row_c2r(g, ctx->R2, out, s));
+  return SGN_OK;
+}
+
+// Inner products <V_k, w>, k < nv (fixed-order sums of the block partials).
+int fg_dots(sgn_ctx* ctx, const double* V, size_t vstride, int nv, const double* w, double* out) {
+  const size_t n = (size_t)ctx->g.nx * ctx->g.ny;
+  const int nb = sgn::fg_blocks(n);
+  HIPCK(sgn::launch_fg_dots(V, vstride, nv, w, n, ctx->partials2, ctx->stream));
+  std::vector<double> part((size_t)nb * nv);
+  HIPCK(hipMemcpyAsync(part.data(), ctx->partials2, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                       ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < nv; ++k) {
+    double a = 0.0;
+    for (int bl = 0; bl < nb; ++bl) a += part[(size_t)bl * nv + k];
+    out[k] = a;
+  }
+  return SGN_OK;
+}
+
+}  // namespace
+
+int sgn_elliptic_solve_fgmres(sgn_ctx* ctx, sgn_cnn* net, const void* h, const void* b, void* sigma,
+                              int32_t max_iters, sgn_fgmres_info* info) {
+  if (!ctx || !net || !aligned(h) || !aligned(b) || !aligned(sigma) || max_iters < 0 || sigma == b || sigma == h)
+    return SGN_ERR_INVALID_ARG;
+  if (ctx->g.fp32 || members(ctx) > 1) {
+    ctx->err = "the flexible GMRES solve runs FP64 contexts with batch = 1";
+    return SGN_ERR_UNSUPPORTED;
+  }
+  int H = 0, W = 0;
+  sgn_cnn_grid(net, &H, &W);
+  if (H != ctx->cfg.ny || W != ctx->cfg.nx) {
+    ctx->err = "network grid differs from the solver grid";
+    return SGN_ERR_INVALID_ARG;
+  }
+  int rc = check_state(ctx, h, b, b);
+  if (rc) return rc;
+  const sgn::Geom& g = ctx->g;
+  hipStream_t s = ctx->stream;
+  const size_t n = (size_t)g.nx * g.ny;
+  const size_t vs = ctx->field_bytes / sizeof(double);  // field stride in doubles
+  const int m = std::min(ctx->cfg.gmres_restart / 2, sgn::kFgMaxVecs - 1);
+  if (m < 1) {
+    ctx->err = "the flexible GMRES solve needs gmres_restart >= 2";
+    return SGN_ERR_UNSUPPORTED;
+  }
+  // V_0..V_m and Z_0..Z_{m-1} in the Krylov fields (restart + 1 >= 2 m + 1)
+  double* V = static_cast<double*>(ctx->V);
+  double* Z = V + (size_t)(m + 1) * vs;
+  double* w = static_cast<double*>(ctx->Z);
+  double* mr = static_cast<double*>(ctx->acc_h);
+  double* zero = static_cast<double*>(ctx->acc_vx);
+  double* lx = static_cast<double*>(ctx->acc_vy);
+  double* sg = static_cast<double*>(sigma);
+  const double* bb = static_cast<const double*>(b);
+  HIPCK(hipMemsetAsync(zero, 0, n * sizeof(double), s));
+  float* in3 = sgn_cnn_in3_buffer(net);
+  float* nout = sgn_cnn_out_buffer(net);
+  const sgn::FgCoefs none{};
+  double bn2 = 0.0;
+  if ((rc = fg_dots(ctx, bb, 0, 1, bb, &bn2))) return rc;
+  const double bnorm = std::sqrt(bn2);
+  const double tol = ctx->cfg.gmres_tol;
+  int total = 0, cycles = 0;
+  double rel = 0.0;
+  bool stalled = false;
+  std::vector<double> Hm((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
+  while (bnorm > 0.0) {
+    // r = b - L sigma into V_0
+    if ((rc = fg_apply_L(ctx, h, sg, lx))) return rc;
+    HIPCK(sgn::launch_fg_combine(V, lx, -1.0, bb, 1.0, nullptr, 0, 0, none, n, s));
+    double beta2 = 0.0;
+    if ((rc = fg_dots(ctx, V, 0, 1, V, &beta2))) return rc;
+    const double beta = std::sqrt(beta2);
+    rel = beta / bnorm;
+    if (rel <= tol || total >= max_iters || stalled) break;
+    HIPCK(sgn::launch_fg_combine(V, V, 1.0 / beta, nullptr, 0.0, nullptr, 0, 0, none, n, s));
+    std::fill(Hm.begin(), Hm.end(), 0.0);
+    std::fill(gv.begin(), gv.end(), 0.0);
+    gv[0] = beta;
+    int jd = 0;
+    for (int j = 0; j < m && total < max_iters; ++j) {
+      double* vj = V + (size_t)j * vs;
+      double* zj = Z + (size_t)j * vs;
+      // z_j = s net(v_j / s, M^-1 v_j / s, h - h_inf), s = RMS of v_j
+      HIPCK(sgn::launch_learn_norm(g, vj, n, ctx->st, ctx->partials, s));
+      HIPCK(sgn::launch_row_r2c(g, vj, ctx->E, s));
+      HIPCK(sgn::launch_col_filter(g, ctx->E, 0, 0.0, ctx->P, s));
+      HIPCK(sgn::launch_row_c2r(g, ctx->P, mr, s));
+      HIPCK(sgn::launch_learn_pack(g, vj, mr, h, n, ctx->st, in3, s));
+      if (sgn_cnn_forward_on(net, in3, nout, s) != SGN_OK) {
+        ctx->err = "flexible GMRES: network forward pass failed";
+        return SGN_ERR_HIP;
+      }
+      HIPCK(sgn::launch_learn_apply(g, zero, nout, ctx->st, zj, n, s));
+      // w = L z_j, orthogonalised against V_0..V_j (two classical passes)
+      if ((rc = fg_apply_L(ctx, h, zj, w))) return rc;
+      double hc[sgn::kFgMaxVecs] = {}, h2[sgn::kFgMaxVecs];
+      for (int pass = 0; pass < 2; ++pass) {
+        if ((rc = fg_dots(ctx, V, vs, j + 1, w, h2))) return rc;
+        sgn::FgCoefs c{};
+        for (int i = 0; i <= j; ++i) {
+          c.c[i] = -h2[i];
+          hc[i] += h2[i];
+        }
+        HIPCK(sgn::launch_fg_combine(w, w, 1.0, nullptr, 0.0, V, vs, j + 1, c, n, s));
+      }
+      double hn2 = 0.0;
+      if ((rc = fg_dots(ctx, w, 0, 1, w, &hn2))) return rc;
+      const double hn = std::sqrt(hn2);
+      total += 1;
+      for (int i = 0; i <= j; ++i) Hm[(size_t)i * m + j] = hc[i];
+      Hm[(size_t)(j + 1) * m + j] = hn;
+      // Givens rotations of the column
+      for (int i = 0; i < j; ++i) {
+        const double a = Hm[(size_t)i * m + j], c2 = Hm[(size_t)(i + 1) * m + j];
+        Hm[(size_t)i * m + j] = cs[i] * a + sn[i] * c2;
+        Hm[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c2;
+      }
+      const double a = Hm[(size_t)j * m + j], c2 = Hm[(size_t)(j + 1) * m + j];
+      const double r = std::hypot(a, c2);
+      // a direction that adds nothing (zero network output): stop here
+      if (!(r > 1e-14 * beta)) {
+        stalled = true;
+        break;
+      }
+      cs[j] = a / r;
+      sn[j] = c2 / r;
+      Hm[(size_t)j * m + j] = r;
+      Hm[(size_t)(j + 1) * m + j] = 0.0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      jd = j + 1;
+      if (std::fabs(gv[j + 1]) <= tol * bnorm || !(hn > 0.0)) break;
+      HIPCK(sgn::launch_fg_combine(V + (size_t)(j + 1) * vs, w, 1.0 / hn, nullptr, 0.0, nullptr, 0, 0, none, n, s));
+    }
+    if (jd > 0) {
+      // sigma += Z y, R y = g
+      for (int i = jd - 1; i >= 0; --i) {
+        double t = gv[i];
+        for (int k = i + 1; k < jd; ++k) t -= Hm[(size_t)i * m + k] * y[k];
+        y[i] = t / Hm[(size_t)i * m + i];
+      }
+      sgn::FgCoefs c{};
+      for (int i = 0; i < jd; ++i) c.c[i] = y[i];
+      HIPCK(sgn::launch_fg_combine(sg, sg, 1.0, nullptr, 0.0, Z, vs, jd, c, n, s));
+    }
+    cycles += 1;
+    if (jd == 0) break;
+  }
+  // plain GMRES from the result: the fallback and the judge
+  sgn_solve_info ji{};
+  const int jrc = sgn_elliptic_solve(ctx, h, b, sigma, &ji);
+  if (jrc && jrc != SGN_ERR_NOT_CONVERGED) return jrc;
+  if (info) {
+    info->fgmres_iters = total;
+    info->fgmres_cycles = cycles;
+    info->gmres_iters = ji.iters;
+    info->converged = ji.converged;
+    info->fgmres_rel_resid = rel;
+    info->rel_resid_true = ji.rel_resid_true;
+  }
+  return jrc;
+}
+
 int sgn_learned_guess_stages(sgn_ctx* ctx, int32_t stage_mask) {
   if (!ctx || stage_mask < 0 || stage_mask > 0xF) return SGN_ERR_INVALID_ARG;
   ctx->learn_stages = stage_mask;

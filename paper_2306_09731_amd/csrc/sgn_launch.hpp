@@ -148,6 +148,21 @@ hipError_t launch_refine_update(double* sigma, const float* d, size_t n, hipStre
 // out = -(a + c), n points (FP64).
 hipError_t launch_neg_sum(const double* a, const double* c, double* out, size_t n, hipStream_t s);
 
+// Flexible GMRES vector work (FP64 physical fields, n points): block partials
+// of the inner products of w with V_0..V_{nv-1} (fields vstride doubles apart)
+// into partials[block * nv + k] over fg_blocks(n) blocks; and
+// out = a y + bx x + sum_k c_k V_k (y, x may be null; out may alias y).
+constexpr int kFgMaxVecs = 16;  // basis fields per call (restart + 1 at most)
+constexpr int kFgBlocks = 512;
+struct FgCoefs {
+  double c[kFgMaxVecs];
+};
+int fg_blocks(size_t n);
+hipError_t launch_fg_dots(const double* V, size_t vstride, int nv, const double* w, size_t n, double* partials,
+                          hipStream_t s);
+hipError_t launch_fg_combine(double* out, const double* y, double a, const double* x, double bx, const double* V,
+                             size_t vstride, int nv, const FgCoefs& c, size_t n, hipStream_t s);
+
 // Largest number of blocks any reduction kernel launches for this grid.
 int max_partial_blocks(const Geom& g);
 // Whether this grid can use the chain-parallel Arnoldi passes.

@@ -166,6 +166,47 @@ def ideal_guess_bound(ctx, box, f, dt_unused=None):
     return out
 
 
+def fgmres_time_to_solution(ctx, box, f, params, reps: int = 3):
+    """One elliptic solve of the current state (b = -div v) at the context's
+    tolerance, from the warm start sigma_prev and from zero: plain GMRES
+    against flexible GMRES preconditioned by the network (then the plain
+    judge).  ms per solve (mean of reps) and iterations."""
+    import torch
+    h, vx, vy, sp = f
+    b = torch.empty_like(h)
+    t = torch.empty_like(h)
+    sgn.sgn_derivative(ctx, 0, vx, b)
+    sgn.sgn_derivative(ctx, 1, vy, t)
+    b = -(b + t)
+    net = sgn.cnn_init(box.ny, box.nx, h.device)
+    sgn.cnn_set_params(net, params)
+    out = {}
+    for start in ("warm_start", "zero"):
+        g0 = sp if start == "warm_start" else torch.zeros_like(sp)
+        res = {}
+        for solver in ("plain", "fgmres_learned"):
+            el, info = 0.0, None
+            for rep in range(reps + 1):  # the first run is not timed
+                sig = g0.clone()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = (sgn.sgn_elliptic_solve(ctx, h, b, sig) if solver == "plain"
+                        else sgn.sgn_elliptic_solve_fgmres(ctx, net, h, b, sig))
+                torch.cuda.synchronize()
+                if rep > 0:
+                    el += time.perf_counter() - t0
+            r = {"ms": el * 1e3 / reps}
+            if solver == "plain":
+                r["iters"] = int(info.iters)
+            else:
+                r.update(fgmres_iters=int(info.fgmres_iters), judge_iters=int(info.gmres_iters),
+                         converged=bool(info.converged))
+            res[solver] = r
+        out[start] = res
+    net.close()
+    return out
+
+
 def evaluate(params, device, name: str, steps: int = 40, warmup_steps: int = 10, record_n: int = 16):
     """The paper's warm start against the stage-increment guess and the
     learned guess (every stage, and once per RK4 step), on a named workload at
@@ -199,6 +240,7 @@ def evaluate(params, device, name: str, steps: int = 40, warmup_steps: int = 10,
                      "value": box.nx * box.ny * steps / el}
         if mode == "warm_start":
             out["ideal_guess_iters"] = ideal_guess_bound(ctx, box, f)
+            out["fgmres_learned_preconditioner"] = fgmres_time_to_solution(ctx, box, f, params)
             # network error on samples of this workload beside the zero and M^-1 r0 predictors
             rec = torch.zeros(record_n, 4, box.ny, box.nx, dtype=torch.float32, device=device)
             sgn.learned_guess_attach(ctx, None, rec)

@@ -65,6 +65,12 @@ class sgn_refine_info(ctypes.Structure):
                 ("rel_resid_first", ctypes.c_double), ("rel_resid_true", ctypes.c_double)]
 
 
+class sgn_fgmres_info(ctypes.Structure):
+    _fields_ = [("fgmres_iters", ctypes.c_int32), ("fgmres_cycles", ctypes.c_int32),
+                ("gmres_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("fgmres_rel_resid", ctypes.c_double), ("rel_resid_true", ctypes.c_double)]
+
+
 class sgn_refined_step_info(ctypes.Structure):
     _fields_ = [("inner_iters", ctypes.c_int64), ("rounds", ctypes.c_int64), ("solves", ctypes.c_int32),
                 ("max_rounds_per_solve", ctypes.c_int32), ("max_rel_resid", ctypes.c_double),
@@ -134,6 +140,8 @@ _SIGNATURES = {
     "sgn_learned_guess_attach": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32]),
     "sgn_learned_guess_recorded": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int64)]),
     "sgn_learned_guess_stages": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "sgn_elliptic_solve_fgmres": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int32,
+                                                 ctypes.POINTER(sgn_fgmres_info)]),
     "sgn_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sgn_last_error": (ctypes.c_char_p, [_VP]),
 }
@@ -561,6 +569,16 @@ def learned_guess_stages(ctx: Context, stage_mask: int):
     """RK stages whose solves the attached network corrects (bit s: stage s;
     0xF every stage, 0x1 once per step)."""
     _check(ctx, load_library().sgn_learned_guess_stages(ctx.handle, int(stage_mask)))
+
+
+def sgn_elliptic_solve_fgmres(ctx: Context, net: CnnContext, h, b, sigma, max_iters: int = 40) -> sgn_fgmres_info:
+    """Flexible GMRES with the network as right preconditioner, then plain
+    GMRES from its result (sigma: initial guess in, solution out)."""
+    info = sgn_fgmres_info()
+    st = load_library().sgn_elliptic_solve_fgmres(ctx.handle, net.handle, _field(ctx, h, "h"), _field(ctx, b, "b"),
+                                                  _field(ctx, sigma, "sigma"), int(max_iters), ctypes.byref(info))
+    _check(ctx, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
+    return info
 
 
 def record_sample(record, i: int):

@@ -167,6 +167,7 @@ def test_cnn_and_learned_guess_host_checks():
     n = ctypes.c_int64()
     assert lib.sgn_learned_guess_recorded(None, ctypes.byref(n)) == sgn.SGN_ERR_INVALID_ARG
     assert lib.sgn_learned_guess_stages(None, 1) == sgn.SGN_ERR_INVALID_ARG
+    assert lib.sgn_elliptic_solve_fgmres(None, None, None, None, None, 10, None) == sgn.SGN_ERR_INVALID_ARG
     assert sgn.SGN_CNN_PARAMS == 6 * (9 * 32 * 32 + 32)
 
 
