@@ -69,6 +69,8 @@ def parse():
     p.add_argument("--c3-only", choices=("fp64", "fp32_mixed"),
                    help="time only the 2048^2 Gaussian in one precision, events on every launch of its "
                         "dominant Arnoldi kernel class (for profiler runs)")
+    p.add_argument("--cnn-only", action="store_true",
+                   help="time only the learned network's forward pass at 1024^2 (inference path), --steps passes")
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the library's default launch choices (or those set by SGN_* variables) instead of "
                         "autotuning the member contexts; for profiler runs, whose counters would include the "
@@ -336,7 +338,8 @@ def learned_form(sgn, torch, dev, args):
     steps = max(1, min(args.steps, 40))
     return {"weights": os.path.relpath(learned.PARAMS_FILE, ROOT),
             "runs": [learned.evaluate(params, dev, name, steps=steps)
-                     for name in ("crossing_solitons_1024x1024", WORKLOAD)]}
+                     for name in ("crossing_solitons_1024x1024", WORKLOAD)],
+            "forward_1024x1024": cnn_forward_run(sgn, torch, dev, 50)}
 
 
 PRECISION_WORKLOAD = "gaussian_2048x2048"
@@ -430,6 +433,42 @@ def precision_form(sgn, torch, dev, args):
 
 
 C3_DOMINANT = "col_basis"  # the Arnoldi basis kernel of the four-kernel step (2048-point columns)
+
+
+# the learned network's forward pass: 6 layers of 3x3 convolutions, 32 -> 32
+# channels as run (padded), 2 * 9 * 32 * 32 flop per point and layer; HBM
+# bytes per point of the inference path: the FP32 input triplets (12 B) and
+# the BF16 output activation (64 B) of layer 1, 64 B in and out of layers
+# 2-5, 64 B in and the FP32 output (4 B) of layer 6
+CNN_FLOP_PER_POINT = 6 * 2 * 9 * 32 * 32
+CNN_BYTES_PER_POINT = 12 + 64 + 4 * 128 + 64 + 4
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def cnn_forward_run(sgn, torch, dev, passes: int, H: int = 1024, W: int = 1024):
+    """passes forward passes of the network at H x W on random input
+    triplets: mean ms, TFLOP/s against the dense BF16 MFMA peak, GB/s."""
+    import numpy as np
+    net = sgn.cnn_init(H, W, dev)
+    rng = np.random.default_rng(0)
+    sgn.cnn_set_params(net, (0.05 * rng.standard_normal(sgn.SGN_CNN_PARAMS)).astype(np.float32))
+    x = torch.from_numpy(rng.standard_normal((H, W, 3)).astype(np.float32)).to(dev)
+    out = torch.empty(H, W, dtype=torch.float32, device=dev)
+    for _ in range(3):
+        sgn.cnn_forward(net, x, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(passes):
+        sgn.cnn_forward(net, x, out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / passes
+    net.close()
+    n = H * W
+    tflops = CNN_FLOP_PER_POINT * n / (ms * 1e-3) / 1e12
+    gbs = CNN_BYTES_PER_POINT * n / (ms * 1e-3) / 1e9
+    return {"grid": [H, W], "passes": passes, "ms_per_forward": ms, "tflops": tflops,
+            "mfma_frac": tflops / BF16_PEAK_TFLOPS, "gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+            "flop_per_point": CNN_FLOP_PER_POINT, "bytes_per_point": CNN_BYTES_PER_POINT}
 
 
 def c3_run(sgn, torch, dev, args, name):
@@ -752,6 +791,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.precision_only:
         print(json.dumps({"precision_form": precision_form(sgn, torch, dev, args)}), flush=True)
+        return
+    if args.cnn_only:
+        print(json.dumps({"cnn_forward": cnn_forward_run(sgn, torch, dev, args.steps)}), flush=True)
         return
     if args.c3_only:
         print(json.dumps({"c3": c3_run(sgn, torch, dev, args, args.c3_only)}), flush=True)

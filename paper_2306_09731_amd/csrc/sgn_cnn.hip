@@ -107,6 +107,116 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Convolution on an LDS tile: a block of four waves computes kRowsLds output
+// rows x 128 points x 32 output channels.  The (kRowsLds + 2) x 130-point
+// input tile with its periodic halo is staged once in LDS (64 B per point,
+// the four 16-byte channel chunks of a point swizzled by ((q >> 1) & 3) so
+// that the eight lanes of an LDS access phase hit distinct banks); wave w
+// takes points 32 w .. 32 w + 31 of every row.  Each A fragment read from LDS
+// (input row r, tap column kx, channel half) feeds the MFMAs of every output
+// row it reaches (ky = r - o), so a wave reads 36 fragments for 72 MFMAs.
+// The BF16 outputs are gathered in LDS (the input tile's space, once every
+// wave has read it) and written as whole 16-byte channel chunks, the mask
+// applied there.  IN3: the input is the solver's FP32 [n][3] triplets, packed
+// to BF16 (zero channels 3..31) while the tile is staged.
+// ---------------------------------------------------------------------------
+constexpr int kRowsLds = 4;
+constexpr int kTileW = 128;
+constexpr int kTileQ = kTileW + 2;
+
+__device__ __forceinline__ int swz(int q, int chunk) { return chunk ^ ((q >> 1) & 3); }
+
+// The 8 BF16 values of x with those whose mask value is not > 0 zeroed.
+__device__ __forceinline__ uint4 apply_mask(uint4 x, uint4 m) {
+  uint32_t xv[4] = {x.x, x.y, x.z, x.w};
+  const uint32_t mv[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t lo = bf2f((bf16)(mv[k] & 0xffffu)) > 0.f ? 0x0000ffffu : 0u;
+    const uint32_t hi = bf2f((bf16)(mv[k] >> 16)) > 0.f ? 0xffff0000u : 0u;
+    xv[k] &= lo | hi;
+  }
+  return make_uint4(xv[0], xv[1], xv[2], xv[3]);
+}
+
+template <bool IN3>
+__global__ void __launch_bounds__(256) k_conv_lds(ConvArgs a, const float* __restrict__ in3) {
+  __shared__ uint4 tile[(kRowsLds + 2) * kTileQ * 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 31, kh = lane >> 5;
+  const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kRowsLds;
+  // stage the input rows y0 - 1 .. y0 + kRowsLds, points x0 - 1 .. x0 + kTileW
+  if (IN3) {
+    for (int c = tid; c < (kRowsLds + 2) * kTileQ; c += 256) {
+      const int r = c / kTileQ, q = c % kTileQ;
+      const size_t p = (size_t)((y0 - 1 + r) & (a.H - 1)) * a.W + ((x0 - 1 + q) & (a.W - 1));
+      const uint32_t c0 = f2bf(in3[3 * p]), c1 = f2bf(in3[3 * p + 1]), c2 = f2bf(in3[3 * p + 2]);
+      uint4* dst = tile + (r * kTileQ + q) * 4;
+      dst[swz(q, 0)] = make_uint4(c0 | (c1 << 16), c2, 0u, 0u);
+#pragma unroll
+      for (int chunk = 1; chunk < 4; ++chunk) dst[swz(q, chunk)] = make_uint4(0u, 0u, 0u, 0u);
+    }
+  } else {
+    for (int c = tid; c < (kRowsLds + 2) * kTileQ * 4; c += 256) {
+      const int r = c / (kTileQ * 4), rem = c % (kTileQ * 4), q = rem >> 2, chunk = rem & 3;
+      const size_t p = (size_t)((y0 - 1 + r) & (a.H - 1)) * a.W + ((x0 - 1 + q) & (a.W - 1));
+      tile[(r * kTileQ + q) * 4 + swz(q, chunk)] = reinterpret_cast<const uint4*>(a.x + p * C)[chunk];
+    }
+  }
+  bf8 wv[TAPS][2];
+#pragma unroll
+  for (int tap = 0; tap < TAPS; ++tap)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      wv[tap][h] = *reinterpret_cast<const bf8*>(a.w + (size_t)tap * C * C + (size_t)i * C + 16 * h + 8 * kh);
+  const int co = i;
+  const float bb = a.bias ? a.bias[co] : 0.f;
+  __syncthreads();
+  f16v acc[kRowsLds] = {};
+#pragma unroll
+  for (int r = 0; r < kRowsLds + 2; ++r)
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int q = 32 * wave + i + kx;
+        const uint4 u = tile[(r * kTileQ + q) * 4 + swz(q, 2 * h + kh)];
+        const bf8 av = __builtin_bit_cast(bf8, u);
+#pragma unroll
+        for (int o = 0; o < kRowsLds; ++o) {
+          const int ky = r - o;
+          if (ky >= 0 && ky <= 2)
+            acc[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, wv[3 * ky + kx][h], acc[o], 0, 0, 0);
+        }
+      }
+  __syncthreads();  // every wave has read its fragments: the tile space takes the outputs
+  bf16* ob = reinterpret_cast<bf16*>(tile);
+#pragma unroll
+  for (int o = 0; o < kRowsLds; ++o) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int pt = 32 * wave + 8 * (v >> 2) + 4 * kh + (v & 3);
+      float out = acc[o][v] + bb;
+      if (a.relu) out = fmaxf(out, 0.f);
+      if (a.y0 && co == 0) {
+        const size_t p = (size_t)(y0 + o) * a.W + x0 + pt;
+        a.y0[p] = (a.mask && !(bf2f(a.mask[p * C]) > 0.f)) ? 0.f : out;
+      }
+      ob[(o * kTileW + pt) * C + co] = f2bf(out);
+    }
+  }
+  if (!a.y) return;
+  __syncthreads();
+  for (int u = tid; u < kRowsLds * kTileW * 4; u += 256) {
+    const int o = u / (kTileW * 4), pt = (u >> 2) % kTileW, chunk = u & 3;
+    const size_t p = (size_t)(y0 + o) * a.W + x0 + pt;
+    uint4 val = tile[u];
+    if (a.mask) val = apply_mask(val, reinterpret_cast<const uint4*>(a.mask + p * C)[chunk]);
+    reinterpret_cast<uint4*>(a.y + p * C)[chunk] = val;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Weight and bias gradients: dw[tap][co][ci] = sum_p dz[p][co] x[p + off][ci],
 // db[co] = sum_p dz[p][co].  A block walks row segments of SEG points, stages
 // dz and the three input rows around the segment transposed in LDS ([c][p]),
@@ -357,23 +467,45 @@ int cfail(sgn_cnn* c, hipError_t e, const char* what) {
     if (e_ != hipSuccess) return cfail(c, e_, #expr);  \
   } while (0)
 
+// The LDS-tile kernel needs whole 128-point row segments and 4-row bands.
+bool lds_tiles(const sgn_cnn* c) { return c->W % kTileW == 0 && c->H % kRowsLds == 0; }
+
+// One convolution layer; in3 (with x null): the layer reads the FP32 input
+// triplets directly (LDS-tile grids only).
 int conv(sgn_cnn* c, const bf16* x, const bf16* w, const float* bias, const bf16* mask, bf16* y, float* y0,
-         int relu) {
+         int relu, const float* in3 = nullptr) {
   ConvArgs a{x, w, bias, mask, y, y0, c->H, c->W, relu};
-  const int tiles = c->n / 32;
-  const int per_block = 4 * kTilesPerWave;
-  hipLaunchKernelGGL(k_conv, dim3((tiles + per_block - 1) / per_block), dim3(256), 0, c->stream, a);
+  if (lds_tiles(c)) {
+    const dim3 grid(c->W / kTileW, c->H / kRowsLds);
+    if (in3)
+      hipLaunchKernelGGL(k_conv_lds<true>, grid, dim3(256), 0, c->stream, a, in3);
+    else
+      hipLaunchKernelGGL(k_conv_lds<false>, grid, dim3(256), 0, c->stream, a, nullptr);
+  } else {
+    const int tiles = c->n / 32;
+    const int per_block = 4 * kTilesPerWave;
+    hipLaunchKernelGGL(k_conv, dim3((tiles + per_block - 1) / per_block), dim3(256), 0, c->stream, a);
+  }
   CK(hipGetLastError());
   return SGN_OK;
 }
 
-int forward_pass(sgn_cnn* c, const float* in3) {
-  hipLaunchKernelGGL(k_pack3, dim3((c->n + 255) / 256), dim3(256), 0, c->stream, in3, c->act[0], c->n);
-  CK(hipGetLastError());
+// The six layers.  Inference on grids of the LDS-tile kernel reads the FP32
+// input triplets in the first layer; otherwise (training, whose backward pass
+// reads the packed input, or other grids) the input is packed first;
+// the last layer writes only its FP32 output channel (the backward pass
+// never reads the BF16 output of the last layer).
+int forward_pass(sgn_cnn* c, const float* in3, bool keep_input = true) {
+  const bool fused_input = !keep_input && lds_tiles(c);
+  if (!fused_input) {
+    hipLaunchKernelGGL(k_pack3, dim3((c->n + 255) / 256), dim3(256), 0, c->stream, in3, c->act[0], c->n);
+    CK(hipGetLastError());
+  }
   for (int l = 0; l < L; ++l) {
     const bool last = l == L - 1;
-    int rc = conv(c, c->act[l], c->wf + (size_t)l * WL, c->w + (size_t)l * PL + WL, nullptr, c->act[l + 1],
-                  last ? c->pred : nullptr, last ? 0 : 1);
+    int rc = conv(c, fused_input && l == 0 ? nullptr : c->act[l], c->wf + (size_t)l * WL,
+                  c->w + (size_t)l * PL + WL, nullptr, last ? nullptr : c->act[l + 1], last ? c->pred : nullptr,
+                  last ? 0 : 1, fused_input && l == 0 ? in3 : nullptr);
     if (rc) return rc;
   }
   return SGN_OK;
@@ -496,7 +628,7 @@ int sgn_cnn_get_params(sgn_cnn* c, float* params) {
 
 int sgn_cnn_forward(sgn_cnn* c, const float* in3, float* out) {
   if (!c || !dev_ok(in3) || !dev_ok(out)) return SGN_ERR_INVALID_ARG;
-  int rc = forward_pass(c, in3);
+  int rc = forward_pass(c, in3, false);
   if (rc) return rc;
   CK(hipMemcpyAsync(out, c->pred, (size_t)c->n * sizeof(float), hipMemcpyDeviceToDevice, c->stream));
   return SGN_OK;
@@ -544,7 +676,7 @@ float* sgn_cnn_out_buffer(sgn_cnn* c) { return c->out; }
 int sgn_cnn_forward_on(sgn_cnn* c, const float* in3, float* out, hipStream_t s) {
   const hipStream_t own = c->stream;
   c->stream = s;
-  int rc = forward_pass(c, in3);
+  int rc = forward_pass(c, in3, false);
   if (!rc && hipMemcpyAsync(out, c->pred, (size_t)c->n * sizeof(float), hipMemcpyDeviceToDevice, s) != hipSuccess)
     rc = SGN_ERR_HIP;
   c->stream = own;
