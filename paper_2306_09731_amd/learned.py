@@ -6,9 +6,11 @@ recording, training and evaluation all run in the library's kernels).
 1. Record: RK4 trajectories of the solver at grid spacing dx = dy = 2 pi / 102.4
    (the spacing of the benchmark workloads) with the recorder attached; every
    solve writes the network input of its warm start and the target
-   (sigma - sigma_prev) / |r0|.  Sources: transversely perturbed line solitons
-   and Gaussian humps on 1024 x 512, oblique crossing solitons on 512 x 512
-   with amplitudes other than the evaluation's.
+   (sigma - sigma_prev) / |r0|.  Sources (about 10^4 samples): eight of the
+   nine perturbed line solitons of the 1024 x 512 sweep and two Gaussian
+   humps on 1024 x 512, the 2048^2 Gaussian of the precision form (cut into
+   512 x 1024 tiles), oblique crossing solitons on 512 x 512 with amplitudes
+   other than the evaluation's.
 2. Train: Adam over the recorded samples, one sample per step, in a seeded
    order; the parameters start from He-normal weights (seeded).
 3. Evaluate on two held-out workloads: the oblique crossing solitons on
@@ -57,41 +59,55 @@ def _tensors(state, device):
 
 
 def training_sources():
-    """(nx, ny, Lx, Ly, state) of the recorded trajectories."""
-    from sgn_inputs import Box, perturbed_line_soliton
-    from sgn_inputs.generators import oblique_crossing_solitons
+    """(nx, ny, Lx, Ly, state, steps) of the recorded trajectories, all at the
+    grid spacing of the benchmark workloads (2 pi / 102.4), none of them the
+    held-out workloads of the evaluation: eight of the nine perturbed-soliton
+    runs of the 1024 x 512 sweep (a in {0.2, 0.5, 1}, k in {1, 2, 4}, without
+    the evaluated a = 0.5, k = 2), two
+    Gaussian humps on 1024 x 512, the 2048^2 Gaussian of the precision form, and
+    oblique crossing solitons on 512 x 512 with other amplitudes.  4 samples per
+    step; about 10^4 samples in all."""
+    from sgn_inputs import Box, gaussian_hump, perturbed_line_soliton
+    from sgn_inputs.generators import SWEEP_AMPLITUDES, SWEEP_WAVENUMBERS, oblique_crossing_solitons
     out = []
     box = Box(1024, 512, 10.0, 5.0)
-    for a, eps, k in ((0.2, 0.05, 1), (0.7, 0.02, 2), (1.0, 0.01, 4), (0.35, 0.05, 2)):
-        out.append((1024, 512, 10.0, 5.0, perturbed_line_soliton(box, a=a, eps=eps, k=k, x0=-10.0)))
+    for a in SWEEP_AMPLITUDES:
+        for k in SWEEP_WAVENUMBERS:
+            if (a, k) != (0.5, 2):
+                out.append((1024, 512, 10.0, 5.0, perturbed_line_soliton(box, a=a, eps=0.01, k=k, x0=-10.0), 220))
     X, Y = box.mesh()
     for alpha in (0.3, 0.6):
         h = 1.0 + alpha * np.exp(-X * X - Y * Y)
         z = np.zeros_like(h)
-        out.append((1024, 512, 10.0, 5.0, (h, z.copy(), z.copy(), z.copy())))
+        out.append((1024, 512, 10.0, 5.0, (h, z.copy(), z.copy(), z.copy()), 100))
+    big = Box(2048, 2048, 20.0, 20.0)
+    out.append((2048, 2048, 20.0, 20.0, gaussian_hump(big, alpha=0.5), 50))
     sq = Box(512, 512, 5.0, 5.0)
     for a in (0.2, 0.7):
-        out.append((512, 512, 5.0, 5.0, oblique_crossing_solitons(sq, a=a)))
+        out.append((512, 512, 5.0, 5.0, oblique_crossing_solitons(sq, a=a), 60))
     return out
 
 
-def record(device, steps_per_source: int = 20, warmup_steps: int = 10, tol: float = 1e-10):
-    """Record 4 * steps_per_source samples from each source (one recorder
-    tensor per source)."""
+def record(device, steps_scale: float = 1.0, warmup_steps: int = 10, tol: float = 1e-10, log=None):
+    """Record 4 samples per step of each source (one recorder tensor per
+    source); steps_scale scales every source's step count."""
     import torch
     recs = []
-    for nx, ny, Lx, Ly, state in training_sources():
+    for nx, ny, Lx, Ly, state, steps in training_sources():
+        steps = max(1, int(round(steps * steps_scale)))
         cfg = sgn.config_default(nx, ny, Lx, Ly, gmres_tol=tol, krasny=1e-12)
         ctx = sgn.sgn_init(cfg, device)
         f = _tensors(state, device)
         sgn.sgn_rk4_step(ctx, *f, DT, warmup_steps)
-        rec = torch.zeros(4 * steps_per_source, 4, ny, nx, dtype=torch.float32, device=device)
+        rec = torch.zeros(4 * steps, 4, ny, nx, dtype=torch.float32, device=device)
         sgn.learned_guess_attach(ctx, None, rec)
-        sgn.sgn_rk4_step(ctx, *f, DT, steps_per_source)
+        sgn.sgn_rk4_step(ctx, *f, DT, steps)
         sgn.learned_guess_attach(ctx, None)
         torch.cuda.synchronize()
         recs.append(rec)
         ctx.close()
+        if log:
+            log(source=f"{nx}x{ny}", samples=4 * steps)
     return recs
 
 
@@ -101,21 +117,30 @@ TRAIN_H, TRAIN_W = 512, 1024
 def training_samples(recs):
     """(input, target) pairs on the 512 x 1024 training grid: samples of 512 x
     512 sources are repeated once along x (still periodic fields of the same
-    spacing, which a translation-equivariant network sees alike)."""
+    spacing, which a translation-equivariant network sees alike); samples of
+    2048 x 2048 sources are cut into eight 512 x 1024 tiles (the network's
+    periodic padding then meets a seam at the tile edges, a few points of each
+    tile)."""
     import torch
     out = []
     for rec in recs:
         for i in range(rec.shape[0]):
             x, t = sgn.record_sample(rec, i)
-            if x.shape[1] != TRAIN_W:
-                reps = TRAIN_W // x.shape[1]
-                x = torch.cat([x] * reps, dim=1)
-                t = torch.cat([t] * reps, dim=1)
-            out.append((x.contiguous(), t.contiguous()))
+            H, W = t.shape
+            if W < TRAIN_W:
+                reps = TRAIN_W // W
+                out.append((torch.cat([x] * reps, dim=1).contiguous(), torch.cat([t] * reps, dim=1).contiguous()))
+            elif H > TRAIN_H:
+                for y0 in range(0, H, TRAIN_H):
+                    for x0 in range(0, W, TRAIN_W):
+                        out.append((x[y0:y0 + TRAIN_H, x0:x0 + TRAIN_W].contiguous(),
+                                    t[y0:y0 + TRAIN_H, x0:x0 + TRAIN_W].contiguous()))
+            else:
+                out.append((x.contiguous(), t.contiguous()))
     return out
 
 
-def train(samples, device, epochs: int = 12, seed: int = 0, params=None, log=None):
+def train(samples, device, epochs: int = 6, seed: int = 0, params=None, log=None):
     """Adam, one sample per step, in a seeded order; lr 1e-3, then 3e-4 for the
     last third of the epochs."""
     import torch
@@ -289,8 +314,9 @@ def evaluate(params, device, name: str, steps: int = 40, warmup_steps: int = 10,
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.dirname(PARAMS_FILE))
-    ap.add_argument("--epochs", type=int, default=12)
-    ap.add_argument("--steps-per-source", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=6)
+    ap.add_argument("--steps-scale", type=float, default=1.0,
+                    help="scales every source's recorded steps (1: about 10^4 samples)")
     ap.add_argument("--device", default="cuda:0")
     args = ap.parse_args()
     t0 = time.time()
@@ -299,12 +325,11 @@ def main():
         kw["t"] = round(time.time() - t0, 1)
         print(json.dumps(kw), flush=True)
 
-    recs = record(args.device, args.steps_per_source)
+    recs = record(args.device, args.steps_scale, log=log)
     samples = training_samples(recs)
-    del recs
     log(recorded=len(samples))
     params, losses = train(samples, args.device, args.epochs, log=log)
-    del samples
+    del samples, recs
     os.makedirs(args.out, exist_ok=True)
     np.save(os.path.join(args.out, "learned_guess_params.npy"), params)
     summary = {"losses": losses, "evaluation": []}
