@@ -165,7 +165,7 @@ def _bf16(t):
     return t.to(torch.bfloat16).to(t.dtype)
 
 
-def ideal_guess_bound(ctx, box, f, dt_unused=None):
+def ideal_guess_bound(ctx, box, f):
     """GMRES iterations of one stage-1 solve at the workload's tolerance from
     (a) the warm start sigma_prev, (b) sigma_prev + BF16(sigma* - sigma_prev),
     the best a network whose output carries BF16 rounding could return, and
