@@ -876,6 +876,11 @@ def main():
         progress("learned form done")
         out["precision_form"] = precision_form(sgn, torch, dev, args)
         progress("precision form done")
+        # the measured device-to-device copy rate beside the 8 TB/s peak
+        copy_gbs = copy_peak_gbs(torch, dev)
+        for entry in [out["roofline"]] + list(out.get("roofline_other_classes", {}).values()):
+            entry["attainable_copy_gbs"] = copy_gbs
+            entry["frac_of_copy"] = entry["achieved"] / copy_gbs if entry.get("achieved") else None
         out["batched_form"] = batched_form(sgn, torch, dev, args)
         progress("batched form done")
     if not args.no_cpu_baseline:
