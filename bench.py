@@ -197,6 +197,62 @@ def sweep_context(sgn, torch, dev, guess=None):
     return box, ak, w, ctx, f
 
 
+STREAM_SPLIT = (3, 3, 3)
+
+
+def streams_form(sgn, torch, dev, args, ref_final):
+    """The nine runs as three member contexts of three runs each, on three
+    streams driven from three host threads, so that the kernels of one
+    context overlap those of the others (memory-bound column passes beside
+    transform-bound row passes, and the tails of launches): W warm-up and K
+    timed steps, the final states compared bitwise with the one-context run's
+    (ref_final, after the same steps)."""
+    import threading
+
+    import numpy as np
+    from sgn_inputs import perturbed_soliton_sweep
+    box, state, ak, w = perturbed_soliton_sweep(eps=PARAMS["eps"])
+    ctxs, i0 = [], 0
+    for nm in STREAM_SPLIT:
+        cfg = sgn.config_default(box.nx, box.ny, box.Lx, box.Ly, gmres_tol=w["tol"], gmres_restart=w["restart"],
+                                 krasny=KRASNY, batch=nm)
+        ctx = sgn.sgn_init(cfg, dev, stream=torch.cuda.Stream(dev))
+        if AUTOTUNE:
+            sgn.sgn_autotune(ctx)
+        ctxs.append((ctx, [torch.from_numpy(np.ascontiguousarray(a[i0:i0 + nm])).to(dev) for a in state]))
+        i0 += nm
+    torch.cuda.synchronize()
+    infos = [None] * len(ctxs)
+
+    def run(i, n):
+        c, fl = ctxs[i]
+        infos[i] = sgn.sgn_rk4_step(c, *fl, w["dt"], n)
+
+    def all_threads(n):
+        th = [threading.Thread(target=run, args=(i, n)) for i in range(len(ctxs))]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+
+    if args.warmup > 0:
+        all_threads(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    all_threads(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    final = [torch.cat([fl[i] for _, fl in ctxs]) for i in range(4)]
+    out = {"split": list(STREAM_SPLIT), "value": len(ak) * box.nx * box.ny * args.steps / el,
+           "ms_per_step": el * 1e3 / args.steps,
+           "identical_to_one_context": all(torch.equal(a, b) for a, b in zip(final, ref_final)),
+           "launch_shapes": [sgn.sgn_launch_shape(c) for c, _ in ctxs]}
+    out.update(iters_summary([i for grp in infos for i in grp]))
+    for c, _ in ctxs:
+        c.close()
+    return out
+
+
 def timed_guess_run(sgn, torch, dev, args):
     """K timed steps (after W warm-up steps) of the nine runs with
     SGN_GUESS_STAGE_INCREMENT: each RK stage starts GMRES from the previous
@@ -861,6 +917,8 @@ def main():
     if others:
         out["roofline_other_classes"] = others
     if not args.main_only:
+        out["streams_form"] = streams_form(sgn, torch, dev, args, [t.clone() for t in f])
+        progress("streams form done")
         out["single_grid"] = single_grid_run(sgn, torch, dev, args)
         progress("single-grid run done")
         out["sweep_single"] = sweep_single(sgn, torch, dev, args)
