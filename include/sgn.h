@@ -242,7 +242,7 @@ int sgn_rk4_step(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, double 
  * automatic: per stage, the most iterations that stage needed in the
  * host-driven steps of the context so far (the first two steps of the first
  * call run host-driven to measure them), plus SGN_GRAPH_MARGIN (environment at
- * sgn_init, 0..4, default 0).  The steps run in chunks of 8 replays: each
+ * sgn_init, 0..4, default 0).  The steps run in chunks of 16 replays: each
  * chunk starts from a checkpoint of (h, vx, vy) and of the solver state carried
  * between steps (workspace), and ends with one status read; a chunk in which a
  * solve reached its budget is restored and redone host-driven, and automatic

@@ -741,8 +741,8 @@ int learned_finish(sgn_ctx* ctx, float* slot) {
 // budget[s] Arnoldi steps, all predicated on the device status, with the
 // device's iteration cap at budget[s] (so the device closes the cycle at
 // convergence or there): the caller sets budget[0] before the first replay,
-// and each solve's counter kernel sets the cap of the next (stage 3's that of
-// the next step's stage 0).  kind 0: first step of a call (sigma itself is
+// and each solve's update kernel counts the solve and sets the cap of the
+// next (stage 3's that of the next step's stage 0).  kind 0: first step of a call (sigma itself is
 // the guess); kind 1: later steps (stage-increment guess, if on).
 int enqueue_graph_step(sgn_ctx* ctx, int kind, void* h, void* vx, void* vy, double dt, const int* budget) {
   const sgn::Geom& g = ctx->g;
@@ -757,8 +757,8 @@ int enqueue_graph_step(sgn_ctx* ctx, int kind, void* h, void* vx, void* vy, doub
     if ((rc = enqueue_residual(ctx, 1, ih, ivx, ivy, 1, 1))) return rc;
     for (int it = 0; it < budget[stage]; ++it)
       if ((rc = enqueue_arnoldi(ctx, ih, it))) return rc;
-    HIPCK(sgn::launch_col_update_eg(g, ctx->SIG, ctx->V, ctx->vstride, ctx->st, ctx->E, ctx->G, Dst, 0, s));
-    HIPCK(sgn::launch_solve_stats(g, ctx->st, budget[(stage + 1) & 3], s));
+    HIPCK(sgn::launch_col_update_eg(g, ctx->SIG, ctx->V, ctx->vstride, ctx->st, ctx->E, ctx->G, Dst,
+                                    4 | (budget[(stage + 1) & 3] << 16), s));
     if ((rc = enqueue_stage_flux(ctx, stage, dt, h, vx, vy, ih, ivx, ivy))) return rc;
   }
   return enqueue_step_filter(ctx, h, vx, vy);
@@ -1291,7 +1291,7 @@ int finish_call(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, const St
   return any_unconv ? SGN_ERR_NOT_CONVERGED : SGN_OK;
 }
 
-constexpr int kGraphChunk = 8;  // captured steps between status reads (and checkpoints)
+constexpr int kGraphChunk = 16;  // captured steps between status reads (and checkpoints)
 
 }  // namespace
 

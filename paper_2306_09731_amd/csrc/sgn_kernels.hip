@@ -1572,12 +1572,15 @@ __global__ void __launch_bounds__(1024) k_col_precond_new(Geom g, const cplx* __
 
 // sigma_hat += sum_{i<k} y_i V_i (or 0 when b == 0), then E, G of sigma_hat.
 // D (optional): the stage increment of the extrapolated guess, D += (new -
-// old sigma_hat), so that over a solve D collects sigma - guess.  spec: a
+// old sigma_hat), so that over a solve D collects sigma - guess.  spec & 1: a
 // launch enqueued before the host knew the outcome of the solve; it does
-// nothing unless the solve has converged.
+// nothing unless the solve has converged.  spec & 4 (captured steps, one
+// grid): thread 0 of block 0 adds the solve to the captured-step counters
+// (anything but convergence counts as a failure: one GMRES cycle per solve
+// there) and sets the iteration cap of the next solve to spec >> 16.
 template <int N>
 __global__ void __launch_bounds__(512) k_col_update_eg(Geom g, cplx* __restrict__ SIG, const cplx* __restrict__ V,
-                                                        size_t vstride, const GmresState* __restrict__ st,
+                                                        size_t vstride, GmresState* __restrict__ st,
                                                         cplx* __restrict__ Eo, cplx* __restrict__ Go,
                                                         cplx* __restrict__ D, int spec) {
   SIG = mshift(g, SIG); V = mshift(g, V); st = mshift(g, st); Eo = mshift(g, Eo); Go = mshift(g, Go);
@@ -1589,6 +1592,13 @@ __global__ void __launch_bounds__(512) k_col_update_eg(Geom g, cplx* __restrict_
   // bounds whatever the status); the speculative launch's test follows
   const int done = st->st.done, k = st->st.jdone, zero = st->st.zero, cyc = st->st.cyc;
   for (int i = tid; i < kMaxRestart; i += block_threads()) coef[i] = st->y[i];
+  if ((spec & 4) && blockIdx.x == 0 && tid == 0) {
+    const int it = st->st.total_iters;
+    st->st.g_total += it;
+    if (it > st->st.g_max) st->st.g_max = it;
+    if (done != 1) st->st.g_fail += 1;
+    st->maxit = spec >> 16;
+  }
   cplx sg[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) sg[r] = valid ? SIG[sidx(g, t + r * TPF, col)] : make_cplx(0.0, 0.0);
@@ -2201,18 +2211,6 @@ __global__ void __launch_bounds__(256) k_field_stats(Geom g, const real* __restr
   }
 }
 
-// Adds the solve that just finished to the captured-step counters (one GMRES
-// cycle per solve there: anything but convergence counts as a failure) and
-// sets the iteration cap of the next solve (the next stage's budget).
-__global__ void __launch_bounds__(64) k_solve_stats(GmresState* st, int next_maxit) {
-  if (threadIdx.x != 0) return;
-  const int it = st->st.total_iters;
-  st->st.g_total += it;
-  if (it > st->st.g_max) st->st.g_max = it;
-  if (st->st.done != 1) st->st.g_fail += 1;
-  if (next_maxit >= 0) st->maxit = next_maxit;
-}
-
 // ----------------------------------------------------------------------------
 // Launch helper: the next launch can carry a pair of HIP events that the
 // runtime records at the start and end of that dispatch (kernel timing).
@@ -2418,7 +2416,7 @@ static hipError_t col_basis_eg_n(const Geom& g, const cplx* W, cplx* V, size_t v
 }
 
 template <int N>
-static hipError_t col_update_eg_n(const Geom& g, cplx* SIG, const cplx* V, size_t vs, const GmresState* st, cplx* Eo,
+static hipError_t col_update_eg_n(const Geom& g, cplx* SIG, const cplx* V, size_t vs, GmresState* st, cplx* Eo,
                                   cplx* Go, cplx* D, int spec, hipStream_t s) {
   COL_LAUNCH(k_col_update_eg<N>, g, SIG, V, vs, st, Eo, Go, D, spec);
 }
@@ -2764,7 +2762,7 @@ hipError_t launch_col_basis2(const Geom& g, const void* W, void* V, size_t vs, i
                              void* Go, const double* pin, hipStream_t s) {
   DISPATCH_NY(col_basis2_n, g, RC_(W), WC_(V), vs, j, st, WC_(Eo), WC_(Go), pin, s)
 }
-hipError_t launch_col_update_eg(const Geom& g, void* SIG, const void* V, size_t vs, const GmresState* st, void* Eo,
+hipError_t launch_col_update_eg(const Geom& g, void* SIG, const void* V, size_t vs, GmresState* st, void* Eo,
                                 void* Go, void* D, int spec, hipStream_t s) {
   DISPATCH_NY(col_update_eg_n, g, WC_(SIG), RC_(V), vs, st, WC_(Eo), WC_(Go), WC_(D), spec, s)
 }
@@ -2847,10 +2845,6 @@ hipError_t launch_upd(const Geom& g, void* W, const void* V, size_t vs, int j, G
   const int nb = upd_blocks(g);
   const int nbin = chained ? col2_blocks(g) : col1_blocks(g);  // blocks of the projection kernel
   launch(k_upd, dim3(nb), dim3(kUpdThreads), 0, s, g, WC_(W), RC_(V), vs, j, st, partials, pin, nbin);
-  return hipGetLastError();
-}
-hipError_t launch_solve_stats(const Geom&, GmresState* st, int next_maxit, hipStream_t s) {
-  launch(k_solve_stats, dim3(1), dim3(64), 0, s, st, next_maxit);
   return hipGetLastError();
 }
 hipError_t launch_field_stats(const Geom& g, const void* h, const void* vx, const void* vy, size_t n, GmresState* st,

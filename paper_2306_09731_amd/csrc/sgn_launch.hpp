@@ -43,7 +43,7 @@
      const double* pin, hipStream_t s),                                                                         \
     (g, W, V, vs, j, st, Eo, Go, pin, s))                                                                       \
   X(col_update_eg,                                                                                              \
-    (const Geom& g, void* SIG, const void* V, size_t vs, const GmresState* st, void* Eo, void* Go, void* D,     \
+    (const Geom& g, void* SIG, const void* V, size_t vs, GmresState* st, void* Eo, void* Go, void* D,           \
      int spec, hipStream_t s),                                                                                  \
     (g, SIG, V, vs, st, Eo, Go, D, spec, s))                                                                    \
   X(col_guess_eg, (const Geom& g, void* SIG, const void* D, void* Eo, void* Go, hipStream_t s),                \
@@ -83,7 +83,6 @@
   X(upd, (const Geom& g, void* W, const void* V, size_t vs, int j, GmresState* st, double* partials,           \
           const double* pin, int chained, hipStream_t s),                                                       \
     (g, W, V, vs, j, st, partials, pin, chained, s))                                                            \
-  X(solve_stats, (const Geom& g, GmresState* st, int next_maxit, hipStream_t s), (g, st, next_maxit, s))                                 \
   X(col_learn, (const Geom& g, const void* W, void* out_r, void* out_m, hipStream_t s), (g, W, out_r, out_m, s))   \
   X(learn_norm, (const Geom& g, const void* r0, size_t n, GmresState* st, double* partials, hipStream_t s),       \
     (g, r0, n, st, partials, s))                                                                                \
@@ -122,11 +121,10 @@
 //     leaves block partials that the next kernel of the step reduces (col_proj
 //     reads those of col_precond_new from pin, so the two need distinct
 //     partials buffers);
-//   col_update_eg: sigma_hat += V y (and the guess increment D);
+//   col_update_eg: sigma_hat += V y (and the guess increment D; in captured
+//     steps also the solve counters and the next solve's iteration cap);
 //   col_guess_eg: sigma_hat += D; col_resid: start of a GMRES cycle;
 //   col_inv / col_apply / col_filter / col_dy: building blocks;
-//   solve_stats: adds the finished solve to the captured-step counters and,
-//     for next_maxit >= 0, sets the iteration cap of the next solve;
 //   col_learn / learn_norm / learn_pack / learn_apply / learn_target: the
 //     learned guess (r0 and M^-1 r0 from the GMRES start, their scale, the
 //     network input, the corrected sigma, the training target);

@@ -109,14 +109,14 @@ def test_graph_budget_too_small_falls_back():
 @pytest.mark.parametrize("name,kw", [("plain", {}), ("stage-increment guess",
                                                    {"guess": sgn.SGN_GUESS_STAGE_INCREMENT})])
 def test_graph_chunk_redone_mid_call(name, kw):
-    """Fixed budgets below what some solves need: the call's chunks of eight
+    """Fixed budgets below what some solves need: the call's chunks of sixteen
     replays either pass or are restored and redone host-driven.  The first
     solves of a call start from a poor sigma and need the most iterations, so
     a budget between the later solves' need and the first ones' makes the
     first chunk fail and later chunks pass; every outcome must equal the host
     loop bit for bit."""
     say(f"graph chunks redone mid-call: {name}")
-    nsteps = 24
+    nsteps = 40
     ctx_h, fh, dt = make(11, 128, 64, **kw)
     ih = sgn.sgn_rk4_step(ctx_h, *fh, dt, nsteps)
     torch.cuda.synchronize()
