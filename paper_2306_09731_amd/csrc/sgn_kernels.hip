@@ -1431,6 +1431,19 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
   const int done = status_load(st);
   __shared__ double coef[kMaxRestart + 1];
   __shared__ double outv[2 * (kMaxRestart + 1) + 1];
+  // w_{j-1} at this thread's points, loaded before the prologue (it does not
+  // depend on the coefficients), so that its loads overlap the reduction
+  constexpr int EH = Col<N>::E / 2;
+  cplx u[EH];
+  size_t uidx[EH];
+  {
+    const int col0 = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < EH; ++q) {
+      uidx[q] = sidx(g, threadIdx.y + (threadIdx.z * EH + q) * Col<N>::TPF, col0);
+      u[q] = col0 < g.nh ? win[uidx[q]] : make_cplx(0.0, 0.0);
+    }
+  }
   {
     const FinishPre pre = finish_prefetch(st, j - 1, false);
     double beta;
@@ -1442,28 +1455,26 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
     if (gmres_finish_column(st, j - 1, coef, unsure ? 0.0 : beta, nullptr, blockIdx.x == 0, &pre, unsure)) return;
   }
   COL2_SETUP(N)
-  constexpr int EH = E / 2;
-  cplx u[EH];
+  // u_j = w_{j-1} - sum_i c_i V_i, two basis vectors at a time at all of the
+  // thread's points
+  if (valid) {
+    for (int i0 = 0; i0 < j; i0 += 2) {
+      cplx b[2][EH];
 #pragma unroll
-  for (int q = 0; q < EH; ++q) {
-    const int p = t + (chain * EH + q) * TPF;
-    const size_t idx = sidx(g, p, col);
-    cplx x = make_cplx(0.0, 0.0);
-    if (valid) {
-      x = win[idx];
-      for (int i0 = 0; i0 < j; i0 += 4) {
-        cplx b[4];
+      for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) b[k] = i0 + k < j ? V[(i0 + k) * vstride + idx] : make_cplx(0.0, 0.0);
+        for (int q = 0; q < EH; ++q)
+          b[k][q] = i0 + k < j ? V[(i0 + k) * vstride + uidx[q]] : make_cplx(0.0, 0.0);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const double cf = i0 + k < j ? coef[i0 + k] : 0.0;
-          x.x -= cf * b[k].x;
-          x.y -= cf * b[k].y;
+      for (int k = 0; k < 2; ++k) {
+        const double cf = i0 + k < j ? coef[i0 + k] : 0.0;
+#pragma unroll
+        for (int q = 0; q < EH; ++q) {
+          u[q].x -= cf * b[k][q].x;
+          u[q].y -= cf * b[k][q].y;
         }
       }
     }
-    u[q] = x;
   }
   __syncthreads();  // every read of win (which may alias W) is done
 #pragma unroll
