@@ -1166,29 +1166,40 @@ __global__ void __launch_bounds__(512) k_col_basis_eg(Geom g, const cplx* __rest
   if (j > 0 && cgs2_finish(g, st, j - 1, pin, nbin, coef, beta, blockIdx.x == 0)) return;
   COL_SETUP(N)
   const double ib = 1.0 / beta;
+  // V_j = (W - sum_i c_i V_i) / beta at all of the thread's points, KB basis
+  // vectors at a time (for each point the terms are subtracted in the order
+  // i = 0, 1, ...)
+  constexpr int KB = N <= 512 ? 2 : 1;
   cplx v[E];
+  size_t idx[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const int p = t + r * TPF;
-    const size_t idx = sidx(g, p, col);
-    cplx x = make_cplx(0.0, 0.0);
-    if (valid) {
-      x = W[idx];
-      for (int i0 = 0; i0 < j; i0 += 4) {
-        cplx b[4];
+    idx[r] = sidx(g, t + r * TPF, col);
+    v[r] = valid ? W[idx[r]] : make_cplx(0.0, 0.0);
+  }
+  if (valid) {
+    for (int i0 = 0; i0 < j; i0 += KB) {
+      cplx b[KB][E];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) b[q] = i0 + q < j ? V[(i0 + q) * vstride + idx] : make_cplx(0.0, 0.0);
+      for (int q = 0; q < KB; ++q)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double c = i0 + q < j ? coef[i0 + q] : 0.0;
-          x.x -= c * b[q].x;
-          x.y -= c * b[q].y;
+        for (int r = 0; r < E; ++r)
+          b[q][r] = i0 + q < j ? V[(i0 + q) * vstride + idx[r]] : make_cplx(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < KB; ++q) {
+        const double c = i0 + q < j ? coef[i0 + q] : 0.0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          v[r].x -= c * b[q][r].x;
+          v[r].y -= c * b[q][r].y;
         }
       }
-      x = cscale(x, ib);
-      V[j * vstride + idx] = x;
     }
-    v[r] = x;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      v[r] = cscale(v[r], ib);
+      V[j * vstride + idx[r]] = v[r];
+    }
   }
   col_emit_eg<N>(g, v, buf, t, col, valid, Eo, Go, twy);
 }
@@ -1618,32 +1629,43 @@ __global__ void __launch_bounds__(512) k_col_update_eg(Geom g, cplx* __restrict_
   // that ran a cycle in that round only
   if ((spec & 2) && cyc != (spec >> 8)) return;
   __syncthreads();
-  cplx v[E];
+  // sigma_hat + V y at all of the thread's points, KB basis vectors at a time
+  // (for each point the terms are added in the order i = 0, 1, ...); one at a
+  // time for longer columns, whose threads hold more points
+  constexpr int KB = N <= 512 ? 2 : 1;
+  cplx v[E], old[E];
+  size_t idx[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const int p = t + r * TPF;
-    const size_t idx = sidx(g, p, col);
-    cplx x = make_cplx(0.0, 0.0);
-    if (valid) {
-      const cplx old = (D || !zero) ? sg[r] : make_cplx(0.0, 0.0);
-      if (!zero) {
-        x = old;
-        for (int i0 = 0; i0 < k; i0 += 4) {
-          cplx b[4];
+    idx[r] = sidx(g, t + r * TPF, col);
+    old[r] = (valid && (D || !zero)) ? sg[r] : make_cplx(0.0, 0.0);
+    v[r] = (valid && !zero) ? old[r] : make_cplx(0.0, 0.0);
+  }
+  if (valid && !zero) {
+    for (int i0 = 0; i0 < k; i0 += KB) {
+      cplx b[KB][E];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) b[q] = i0 + q < k ? V[(i0 + q) * vstride + idx] : make_cplx(0.0, 0.0);
+      for (int q = 0; q < KB; ++q)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const double c = i0 + q < k ? coef[i0 + q] : 0.0;
-            x.x += c * b[q].x;
-            x.y += c * b[q].y;
-          }
+        for (int r = 0; r < E; ++r)
+          b[q][r] = i0 + q < k ? V[(i0 + q) * vstride + idx[r]] : make_cplx(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < KB; ++q) {
+        const double c = i0 + q < k ? coef[i0 + q] : 0.0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          v[r].x += c * b[q][r].x;
+          v[r].y += c * b[q][r].y;
         }
       }
-      SIG[idx] = x;
-      if (D) D[idx] = cadd(D[idx], csub(x, old));
     }
-    v[r] = x;
+  }
+  if (valid) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      SIG[idx[r]] = v[r];
+      if (D) D[idx[r]] = cadd(D[idx[r]], csub(v[r], old[r]));
+    }
   }
   col_emit_eg<N>(g, v, buf, t, col, valid, Eo, Go, twy);
 }
