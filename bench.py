@@ -75,9 +75,11 @@ def parse():
                    help="keep the library's default launch choices (or those set by SGN_* variables) instead of "
                         "autotuning the member contexts; for profiler runs, whose counters would include the "
                         "autotuner's trial dispatches")
-    p.add_argument("--time-class", choices=("col_basis", "row_matvec", "col_precond_dot"), default=DOMINANT,
-                   help="kernel class of the headline run that carries HIP events and gives the roofline entry "
-                        "(default: the class with the largest share of device time)")
+    p.add_argument("--time-class", choices=("col_basis", "row_matvec", "col_precond_dot", "gs_update"),
+                   default=DOMINANT,
+                   help="kernel class of the headline run (or of --c3-only) that carries HIP events and gives "
+                        "the roofline entry (default: the class with the largest share of device time; "
+                        "gs_update exists in the four-kernel step of --c3-only only)")
     p.add_argument("--t5-steps", type=int, default=1000,
                    help="steps of the 2048^2 precision comparison at t = 5 (dt = 0.005; 0 skips it)")
     p.add_argument("--t20-steps", type=int, default=4000,
@@ -464,7 +466,7 @@ def precision_form(sgn, torch, dev, args):
         dom = max(per, key=lambda k: per[k][1])
         n, ms, by = per[dom]
         ach = by / (ms * 1e-3) / 1e9 if ms else None
-        ratio = traffic_ratio_from_profile(dom, f"{PRECISION_WORKLOAD}_{name}") if dom == C3_DOMINANT else None
+        ratio = traffic_ratio_from_profile(dom, f"{PRECISION_WORKLOAD}_{name}")
         res["roofline"] = {"kernel_class": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": ach / HBM_PEAK_GBS if ach else None,
                            "traffic": ratio * by / n if ratio is not None else None,
@@ -488,7 +490,6 @@ def precision_form(sgn, torch, dev, args):
     return out
 
 
-C3_DOMINANT = "col_basis"  # the Arnoldi basis kernel of the four-kernel step (2048-point columns)
 
 
 # the learned network's forward pass: 6 layers of 3x3 convolutions, 32 -> 32
@@ -529,9 +530,9 @@ def cnn_forward_run(sgn, torch, dev, passes: int, H: int = 1024, W: int = 1024):
 
 def c3_run(sgn, torch, dev, args, name):
     """K steps of the 2048^2 Gaussian in one precision after W warm-up steps,
-    the dominant kernel class timed on every launch (all its dispatches of
-    the timed call): the library's algorithmic bytes over exactly the
-    dispatches a profiler of this run sees when W = 0."""
+    one Arnoldi kernel class (--time-class) timed on every launch (all its
+    dispatches of the timed call): the library's algorithmic bytes over
+    exactly the dispatches a profiler of this run sees when W = 0."""
     import numpy as np
     from sgn_inputs import workload
     box, state, w = workload(PRECISION_WORKLOAD)
@@ -542,12 +543,12 @@ def c3_run(sgn, torch, dev, args, name):
     f = [torch.from_numpy(np.ascontiguousarray(a)).to(dev).to(dtype) for a in state]
     if args.warmup > 0:
         sgn.sgn_rk4_step(ctx, *f, w["dt"], args.warmup)
-    kind = [k for k, v in sgn.KERNEL_NAMES.items() if v == C3_DOMINANT][0]
+    kind = [k for k, v in sgn.KERNEL_NAMES.items() if v == args.time_class][0]
     el, infos, kt = timed_kernel_run(sgn, torch, ctx, f, w["dt"], args.steps, kind, period=1)
     ctx.close()
     n, ms, by = kt
     out = {"workload": PRECISION_WORKLOAD, "precision": name, "steps": args.steps,
-           "ms_per_step": el * 1e3 / args.steps, "kernel_class": C3_DOMINANT, "launches": n,
+           "ms_per_step": el * 1e3 / args.steps, "kernel_class": args.time_class, "launches": n,
            "mean_launch_us": ms / n * 1e3 if n else None, "algorithmic_bytes_total": by,
            "algorithmic_bytes_per_launch": by / n if n else None,
            "achieved": by / (ms * 1e-3) / 1e9 if ms else None}
