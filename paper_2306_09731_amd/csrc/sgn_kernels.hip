@@ -2116,8 +2116,11 @@ __global__ void __launch_bounds__(kUpdThreads) k_upd(Geom g, cplx* __restrict__ 
     w[e] = ok ? W[idx[e]] : make_cplx(0.0, 0.0);
     wt[e] = ok ? col_weight((int)(idx[e] / g.ny)) : 0.0;  // column-major 2D spectra
   }
+  // b keeps the last batch (V_last..V_j) for the second pass, which re-reads
+  // only the earlier vectors (the re-reads miss L2 once the basis is long)
+  const int last = (j / 4) * 4;
+  cplx b[4][kUpdEpt];
   for (int i0 = 0; i0 <= j; i0 += 4) {
-    cplx b[4][kUpdEpt];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -2139,22 +2142,37 @@ __global__ void __launch_bounds__(kUpdThreads) k_upd(Geom g, cplx* __restrict__ 
     if (idx[e] < total) W[idx[e]] = w[e];
     nr += wt[e] * cnorm2(w[e]);
   }
-  // value 0: ||w1||^2; value 1 + i: <V_i, w1> (V_i re-read from cache)
+  // value 0: ||w1||^2; value 1 + i: <V_i, w1> (V_i re-read for i < last;
+  // the last batch's from the registers that still hold it)
+  double dl0 = 0.0, dl1 = 0.0, dl2 = 0.0, dl3 = 0.0;
+#pragma unroll
+  for (int e = 0; e < kUpdEpt; ++e) {
+    if (idx[e] < total) {
+      dl0 += wt[e] * cdot(b[0][e], w[e]);
+      dl1 += wt[e] * cdot(b[1][e], w[e]);
+      dl2 += wt[e] * cdot(b[2][e], w[e]);
+      dl3 += wt[e] * cdot(b[3][e], w[e]);
+    }
+  }
   for (int k0 = 0; k0 <= j + 1; k0 += 8) {
     double a[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int k = k0 + q;
+      const int k = k0 + q, i = k - 1, sel = i - last;
       double d = 0.0;
       if (k == 0) {
         d = nr;
       } else if (k <= j + 1) {
+        if (sel < 0) {
 #pragma unroll
-        for (int e = 0; e < kUpdEpt; ++e) {
-          if (idx[e] < total) {
-            const cplx b = V[(k - 1) * vstride + idx[e]];
-            d += wt[e] * cdot(b, w[e]);
+          for (int e = 0; e < kUpdEpt; ++e) {
+            if (idx[e] < total) {
+              const cplx bv = V[i * vstride + idx[e]];
+              d += wt[e] * cdot(bv, w[e]);
+            }
           }
+        } else {
+          d = sel == 0 ? dl0 : sel == 1 ? dl1 : sel == 2 ? dl2 : dl3;
         }
       }
       a[q] = d;
