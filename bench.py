@@ -85,6 +85,8 @@ def parse():
     p.add_argument("--t20-steps", type=int, default=4000,
                    help="steps of the nine-run to-t=20 leg (dt = 0.005; 0 skips it)")
     p.add_argument("--cpu-steps", type=int, default=5)
+    p.add_argument("--cpu-worker", type=int, default=-1, metavar="RUN",
+                   help="internal: one process of the all-core CPU baseline (the oracle on run RUN of the nine)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of MIB MiB, --steps times (calibrates the "
                         "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
@@ -809,6 +811,49 @@ def cpu_baseline(steps: int):
                       f"{dt:.1f} s"}
 
 
+def cpu_worker(run: int, steps: int):
+    """One process of the all-core CPU baseline: the oracle, as it stands, on
+    `steps` RK4 steps of run `run` of the nine from t = 0; prints its own
+    start and end times (wall clock) as one JSON line."""
+    from oracle import sgn_oracle as O
+    from sgn_inputs import perturbed_soliton_sweep
+    box, state, ak, w = perturbed_soliton_sweep(eps=PARAMS["eps"])
+    h, vx, vy, s = (a[run].copy() for a in state)
+    g = O.Grid(O.Config(nx=box.nx, ny=box.ny, Lx=box.Lx, Ly=box.Ly, gmres_tol=w["tol"],
+                        gmres_restart=w["restart"], krasny=KRASNY))
+    t0 = time.time()
+    O.rk4(g, h, vx, vy, s, w["dt"], steps)
+    t1 = time.time()
+    print(json.dumps({"run": run, "t0": t0, "t1": t1, "points": box.nx * box.ny, "steps": steps}), flush=True)
+
+
+def cpu_baseline_all_cores(steps: int):
+    """The oracle on the host's cores: the nine runs (fewer if fewer cores may
+    be used), one process each with one thread, `steps` RK4 steps from t = 0,
+    all started together.  Throughput = the points x steps of all of them over
+    the span from the first start to the last end.  Runs before the GPU is
+    touched, so that every child is started from a process without it."""
+    import subprocess
+    usable, model = host_cpu()
+    n = min(9, usable)
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(i),
+                               "--cpu-steps", str(steps)], stdout=subprocess.PIPE, env=env) for i in range(n)]
+    outs = []
+    for pr in procs:
+        so, _ = pr.communicate()
+        if pr.returncode != 0:
+            raise RuntimeError(f"CPU baseline worker exited with status {pr.returncode}")
+        outs.append(json.loads(so.decode().strip().splitlines()[-1]))
+    span = max(o["t1"] for o in outs) - min(o["t0"] for o in outs)
+    work = sum(o["points"] * o["steps"] for o in outs)
+    return {"value": work / span, "unit": UNIT, "cores": n, "kind": "oracle", "host_cores_usable": usable,
+            "host_cpu": model,
+            "sample": f"{steps} RK4 step(s) of each of {n} of the nine 1024x512 runs from t=0, one single-threaded "
+                      f"numpy FP64 process per run, all started together, {span:.1f} s from the first start to "
+                      f"the last end"}
+
+
 def progress(msg: str):
     """One progress line per phase on stderr (the JSON result goes to stdout)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -833,6 +878,9 @@ def host_cpu():
 
 def main():
     args = parse()
+    if args.cpu_worker >= 0:
+        cpu_worker(args.cpu_worker, args.cpu_steps)
+        return
     global AUTOTUNE
     AUTOTUNE = not args.no_autotune
     if args.copy_calibration:
@@ -842,6 +890,11 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver is single-GPU.",
               file=sys.stderr)
         sys.exit(2)
+    only = (args.precision_only or args.cnn_only or args.c3_only or args.single_only or args.main_only)
+    cpu_all = None
+    if not args.no_cpu_baseline and not only:
+        cpu_all = cpu_baseline_all_cores(args.cpu_steps)
+        progress("all-core CPU baseline done")
     import torch
     from paper_2306_09731_amd import sgn
 
@@ -944,6 +997,8 @@ def main():
         progress("batched form done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+        if cpu_all is not None:
+            out["cpu_baseline"]["all_cores"] = cpu_all
     print(json.dumps(out), flush=True)
 
 

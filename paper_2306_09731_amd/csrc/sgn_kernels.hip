@@ -187,29 +187,48 @@ __device__ __forceinline__ double wave_sum8_scatter(const double (&a)[8]) {
   return d;
 }
 
+// The same for four values a[0..3]: the sum of a[i] over the wave ends in
+// lanes 16 i .. 16 i + 15.
+__device__ __forceinline__ double wave_sum4_scatter(const double (&a)[8]) {
+  const int lane = flat_tid() & 63;
+  const bool h5 = lane & 32, h4 = lane & 16;
+  double b[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) b[i] = (h5 ? a[2 + i] : a[i]) + __shfl_xor(h5 ? a[i] : a[2 + i], 32, 64);
+  double d = (h4 ? b[1] : b[0]) + __shfl_xor(h4 ? b[0] : b[1], 16, 64);
+  d += __shfl_xor(d, 8, 64);
+  d += __shfl_xor(d, 4, 64);
+  d += __shfl_xor(d, 2, 64);
+  d += __shfl_xor(d, 1, 64);
+  return d;
+}
+
 // kind: 0 sum, 1 min, 2 max.  out[k] (LDS) = reduction over blocks of
 // partials[b * kPartialStride + k], in a fixed order.
 // kAtomic = false: the partials were written by an earlier kernel on the
 // stream (visible to plain loads after the kernel boundary).
-template <bool kAtomic = true>
+// VW: values per wave in a sum (8, or 4 for a caller that holds other loads
+// in registers meanwhile).
+template <bool kAtomic = true, int VW = 8>
 __device__ void reduce_partials(const double* partials, int nblocks, int nvals, const int* kind,
                                 double* out) {
+  static_assert(VW == 8 || VW == 4, "eight or four values per wave");
   const int tid = flat_tid();
   const int lane = tid & 63, wave = tid >> 6, nw = block_threads() >> 6;
   if (!kind) {
-    // sums: each wave takes eight values and keeps the loads of 256 blocks in
+    // sums: each wave takes VW values and keeps the loads of 256 blocks in
     // flight together
-    for (int k0 = 8 * wave; k0 < nvals; k0 += 8 * nw) {
+    for (int k0 = VW * wave; k0 < nvals; k0 += VW * nw) {
       double a[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) a[q] = 0.0;
       for (int b0 = 0; b0 < nblocks; b0 += 256) {
-        double x[4][8];
+        double x[4][VW];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int b = b0 + 64 * u + lane;
 #pragma unroll
-          for (int q = 0; q < 8; ++q)
+          for (int q = 0; q < VW; ++q)
             x[u][q] = (b < nblocks && k0 + q < nvals)
                           ? (kAtomic ? partial_load(&partials[(size_t)b * kPartialStride + k0 + q])
                                      : partials[(size_t)b * kPartialStride + k0 + q])
@@ -218,10 +237,15 @@ __device__ void reduce_partials(const double* partials, int nblocks, int nvals, 
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int q = 0; q < 8; ++q) a[q] += x[u][q];
+          for (int q = 0; q < VW; ++q) a[q] += x[u][q];
       }
-      const double r = wave_sum8_scatter(a);
-      if ((lane & 7) == 0 && k0 + (lane >> 3) < nvals) out[k0 + (lane >> 3)] = r;
+      if constexpr (VW == 8) {
+        const double r = wave_sum8_scatter(a);
+        if ((lane & 7) == 0 && k0 + (lane >> 3) < nvals) out[k0 + (lane >> 3)] = r;
+      } else {
+        const double r = wave_sum4_scatter(a);
+        if ((lane & 15) == 0 && k0 + (lane >> 4) < nvals) out[k0 + (lane >> 4)] = r;
+      }
     }
     __syncthreads();
     return;
@@ -1206,7 +1230,7 @@ __global__ void __launch_bounds__(512) k_col_basis_eg(Geom g, const cplx* __rest
 
 // Two-chain variants of the Arnoldi column passes: threadIdx.z selects the
 // chain; each chain has its own LDS region of tc x N.
-#define COL2_SETUP(N)                                        \
+#define COL2_SETUP_NOTW(N)                                   \
   constexpr int E = Col<N>::E;                               \
   constexpr int TPF = Col<N>::TPF;                           \
   extern __shared__ cplx lds[];                              \
@@ -1216,7 +1240,9 @@ __global__ void __launch_bounds__(512) k_col_basis_eg(Geom g, const cplx* __rest
   const ColMap map{(int)blockDim.x};                         \
   const int col = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + c; \
   const bool valid = col < g.nh;                             \
-  cplx* buf = lds + chain * (blockDim.x * N) + c;            \
+  cplx* buf = lds + chain * (blockDim.x * N) + c;
+#define COL2_SETUP(N)                                        \
+  COL2_SETUP_NOTW(N)                                         \
   TwiddleSet<N> twy;                                         \
   gather_twiddles<N>(twy, t, TWY(g));
 
@@ -1362,7 +1388,7 @@ __device__ bool cgs_coefficients(const Geom& g, GmresState* st, int jc, const do
     const int e = tid + u * nthr;
     gq[u] = e < ng ? st->G[(e / jc) * ld + e % jc] : 0.0;
   }
-  reduce_partials<false>(pin, nb, 2 * (jc + 1) + 1, nullptr, outv);
+  reduce_partials<false, 4>(pin, nb, 2 * (jc + 1) + 1, nullptr, outv);
   // the GMRES status (read by the caller before these loads were issued,
   // uniform over the block): a stopped cycle writes nothing
   if (done) return false;
@@ -1424,6 +1450,24 @@ __device__ bool cgs_coefficients(const Geom& g, GmresState* st, int jc, const do
   return true;
 }
 
+// Kernel A's pass over the basis: vectors loaded per batch (BATCH; _E8 for
+// transforms of eight values per thread, which hold twice the registers) and
+// vectors loaded with w before the prologue (PRE).  Measured on nine
+// 1024x512 members: batches of 4 and 8 take the same time; PRE 2 is 1.7%
+// faster than none, PRE 4 slower.
+#ifndef SGN_PROJ_BATCH
+#define SGN_PROJ_BATCH 4
+#endif
+#ifndef SGN_PROJ_PRE
+#define SGN_PROJ_PRE 2
+#endif
+#ifndef SGN_PROJ_PRE_E8
+#define SGN_PROJ_PRE_E8 0
+#endif
+#ifndef SGN_PROJ_BATCH_E8
+#define SGN_PROJ_BATCH_E8 2
+#endif
+
 // Kernel A (j >= 1; the residual pass does step 0's).  win: w_{j-1}; u_j ->
 // W.  pin: the block partials of C_{j-1} (same grid).  Every block first
 // finishes Arnoldi step j - 1 from them (projection coefficients, H(j, j-1)
@@ -1447,6 +1491,10 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
   constexpr int EH = Col<N>::E / 2;
   cplx u[EH];
   size_t uidx[EH];
+  // the first KP basis vectors too (speculative: a cycle that stops in the
+  // prologue has loaded them for nothing)
+  constexpr int KP = Col<N>::E >= 8 ? SGN_PROJ_PRE_E8 : SGN_PROJ_PRE;
+  cplx bp[KP > 0 ? KP : 1][EH];
   {
     const int col0 = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
 #pragma unroll
@@ -1454,6 +1502,11 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
       uidx[q] = sidx(g, threadIdx.y + (threadIdx.z * EH + q) * Col<N>::TPF, col0);
       u[q] = col0 < g.nh ? win[uidx[q]] : make_cplx(0.0, 0.0);
     }
+#pragma unroll
+    for (int k = 0; k < KP; ++k)
+#pragma unroll
+      for (int q = 0; q < EH; ++q)
+        bp[k][q] = col0 < g.nh && k < j ? V[k * vstride + uidx[q]] : make_cplx(0.0, 0.0);
   }
   {
     const FinishPre pre = finish_prefetch(st, j - 1, false);
@@ -1465,19 +1518,30 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
     const bool unsure = beta < 0.0;
     if (gmres_finish_column(st, j - 1, coef, unsure ? 0.0 : beta, nullptr, blockIdx.x == 0, &pre, unsure)) return;
   }
-  COL2_SETUP(N)
-  // u_j = w_{j-1} - sum_i c_i V_i, two basis vectors at a time at all of the
-  // thread's points
+  COL2_SETUP_NOTW(N)
+  // u_j = w_{j-1} - sum_i c_i V_i, KA basis vectors at a time at all of the
+  // thread's points; the transform's twiddles are gathered after this pass,
+  // so that their registers hold loads in flight during it
+  constexpr int KA = E >= 8 ? SGN_PROJ_BATCH_E8 : SGN_PROJ_BATCH;
   if (valid) {
-    for (int i0 = 0; i0 < j; i0 += 2) {
-      cplx b[2][EH];
 #pragma unroll
-      for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < KP; ++k) {
+      const double cf = k < j ? coef[k] : 0.0;
+#pragma unroll
+      for (int q = 0; q < EH; ++q) {
+        u[q].x -= cf * bp[k][q].x;
+        u[q].y -= cf * bp[k][q].y;
+      }
+    }
+    for (int i0 = KP; i0 < j; i0 += KA) {
+      cplx b[KA][EH];
+#pragma unroll
+      for (int k = 0; k < KA; ++k)
 #pragma unroll
         for (int q = 0; q < EH; ++q)
           b[k][q] = i0 + k < j ? V[(i0 + k) * vstride + uidx[q]] : make_cplx(0.0, 0.0);
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
+      for (int k = 0; k < KA; ++k) {
         const double cf = i0 + k < j ? coef[i0 + k] : 0.0;
 #pragma unroll
         for (int q = 0; q < EH; ++q) {
@@ -1487,6 +1551,8 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
       }
     }
   }
+  TwiddleSet<N> twy;
+  gather_twiddles<N>(twy, t, TWY(g));
   __syncthreads();  // every read of win (which may alias W) is done
 #pragma unroll
   for (int q = 0; q < EH; ++q)
@@ -1755,7 +1821,7 @@ __global__ void __launch_bounds__(512) k_col_precond_dot(Geom g, const cplx* __r
 // beta0 = ||M^-1 b|| and ||b||.  flags: 1 = new solve (reset the counters),
 // 2 = report the unpreconditioned residual only (no cycle set-up).
 template <int N>
-__global__ void __launch_bounds__(512) k_col_resid(Geom g, const cplx* __restrict__ P, const cplx* __restrict__ Q,
+__global__ void __launch_bounds__(512, N <= 1024 ? 4 : 2) k_col_resid(Geom g, const cplx* __restrict__ P, const cplx* __restrict__ Q,
                                                     const cplx* __restrict__ R1, const cplx* __restrict__ R2,
                                                     int need_b, int flags, GmresState* st, cplx* __restrict__ W,
                                                     double* partials, int nblocks, cplx* __restrict__ Eo,

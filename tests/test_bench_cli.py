@@ -36,3 +36,15 @@ def test_traffic_ratio_only_for_matching_sources():
         assert ratio is not None and 0.9 < ratio < 2.0
     else:
         assert ratio is None
+
+
+def test_cpu_worker_reports_one_run():
+    # one process of the all-core CPU baseline: the oracle on one of the nine
+    # runs, started without the GPU, reporting its own start and end
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--cpu-worker", "4", "--cpu-steps", "1"],
+                       capture_output=True, text=True, cwd=ROOT, timeout=300)
+    assert r.returncode == 0, r.stderr
+    import json
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert out["run"] == 4 and out["steps"] == 1 and out["points"] == 1024 * 512
+    assert out["t1"] > out["t0"]
