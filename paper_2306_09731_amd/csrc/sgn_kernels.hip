@@ -1451,18 +1451,16 @@ __device__ bool cgs_coefficients(const Geom& g, GmresState* st, int jc, const do
 }
 
 // Kernel A's pass over the basis: vectors loaded per batch (BATCH; _E8 for
-// transforms of eight values per thread, which hold twice the registers) and
-// vectors loaded with w before the prologue (PRE).  Measured on nine
-// 1024x512 members: batches of 4 and 8 take the same time; PRE 2 is 1.7%
-// faster than none, PRE 4 slower.
+// transforms of eight values per thread, which hold twice the registers);
+// waves per SIMD the kernel is compiled for at lengths <= 1024 (96 VGPRs at
+// 5, two of them spilled at 512 points).  Measured on nine 1024x512
+// members: batches of 4 and 8 take the same time; 5 waves 62.4 us per
+// launch against 62.9 at 4.
 #ifndef SGN_PROJ_BATCH
 #define SGN_PROJ_BATCH 4
 #endif
-#ifndef SGN_PROJ_PRE
-#define SGN_PROJ_PRE 2
-#endif
-#ifndef SGN_PROJ_PRE_E8
-#define SGN_PROJ_PRE_E8 0
+#ifndef SGN_PROJ_WAVES_SHORT
+#define SGN_PROJ_WAVES_SHORT 5
 #endif
 #ifndef SGN_PROJ_BATCH_E8
 #define SGN_PROJ_BATCH_E8 2
@@ -1474,7 +1472,7 @@ __device__ bool cgs_coefficients(const Geom& g, GmresState* st, int jc, const do
 // by the Gram identity, Givens update and test; block 0 stores the step)
 // and exits if the cycle stops there, so the last step costs no pass.
 template <int N, bool SF>
-__global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx* W, const cplx* __restrict__ V,
+__global__ void __launch_bounds__(1024, N <= 1024 ? SGN_PROJ_WAVES_SHORT : 4) k_col_proj(Geom g, const cplx* win, cplx* W, const cplx* __restrict__ V,
                                                    size_t vstride, int j, GmresState* st, cplx* __restrict__ Eo,
                                                    cplx* __restrict__ Go,
                                                    const double* __restrict__ pin) {
@@ -1491,10 +1489,6 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
   constexpr int EH = Col<N>::E / 2;
   cplx u[EH];
   size_t uidx[EH];
-  // the first KP basis vectors too (speculative: a cycle that stops in the
-  // prologue has loaded them for nothing)
-  constexpr int KP = Col<N>::E >= 8 ? SGN_PROJ_PRE_E8 : SGN_PROJ_PRE;
-  cplx bp[KP > 0 ? KP : 1][EH];
   {
     const int col0 = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
 #pragma unroll
@@ -1502,11 +1496,6 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
       uidx[q] = sidx(g, threadIdx.y + (threadIdx.z * EH + q) * Col<N>::TPF, col0);
       u[q] = col0 < g.nh ? win[uidx[q]] : make_cplx(0.0, 0.0);
     }
-#pragma unroll
-    for (int k = 0; k < KP; ++k)
-#pragma unroll
-      for (int q = 0; q < EH; ++q)
-        bp[k][q] = col0 < g.nh && k < j ? V[k * vstride + uidx[q]] : make_cplx(0.0, 0.0);
   }
   {
     const FinishPre pre = finish_prefetch(st, j - 1, false);
@@ -1524,16 +1513,7 @@ __global__ void __launch_bounds__(1024) k_col_proj(Geom g, const cplx* win, cplx
   // so that their registers hold loads in flight during it
   constexpr int KA = E >= 8 ? SGN_PROJ_BATCH_E8 : SGN_PROJ_BATCH;
   if (valid) {
-#pragma unroll
-    for (int k = 0; k < KP; ++k) {
-      const double cf = k < j ? coef[k] : 0.0;
-#pragma unroll
-      for (int q = 0; q < EH; ++q) {
-        u[q].x -= cf * bp[k][q].x;
-        u[q].y -= cf * bp[k][q].y;
-      }
-    }
-    for (int i0 = KP; i0 < j; i0 += KA) {
+    for (int i0 = 0; i0 < j; i0 += KA) {
       cplx b[KA][EH];
 #pragma unroll
       for (int k = 0; k < KA; ++k)
