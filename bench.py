@@ -840,11 +840,17 @@ def cpu_baseline_all_cores(steps: int):
     procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", str(i),
                                "--cpu-steps", str(steps)], stdout=subprocess.PIPE, env=env) for i in range(n)]
     outs = []
-    for pr in procs:
-        so, _ = pr.communicate()
-        if pr.returncode != 0:
-            raise RuntimeError(f"CPU baseline worker exited with status {pr.returncode}")
-        outs.append(json.loads(so.decode().strip().splitlines()[-1]))
+    try:
+        for pr in procs:
+            so, _ = pr.communicate(timeout=600)
+            if pr.returncode != 0:
+                raise RuntimeError(f"CPU baseline worker exited with status {pr.returncode}")
+            outs.append(json.loads(so.decode().strip().splitlines()[-1]))
+    finally:
+        for pr in procs:  # a worker still running after an error or the time limit
+            if pr.poll() is None:
+                pr.kill()
+                pr.wait()
     span = max(o["t1"] for o in outs) - min(o["t0"] for o in outs)
     work = sum(o["points"] * o["steps"] for o in outs)
     return {"value": work / span, "unit": UNIT, "cores": n, "kind": "oracle", "host_cores_usable": usable,
