@@ -206,13 +206,12 @@ STREAM_SPLIT = (3, 3, 3)
 
 def streams_form(sgn, torch, dev, args, ref_final):
     """The nine runs as three member contexts of three runs each, on three
-    streams driven from three host threads, so that the kernels of one
-    context overlap those of the others (memory-bound column passes beside
-    transform-bound row passes, and the tails of launches): W warm-up and K
-    timed steps, the final states compared bitwise with the one-context run's
-    (ref_final, after the same steps)."""
-    import threading
-
+    streams, advanced by one sgn_rk4_step_ensemble call (a host thread per
+    context inside the library), so that the kernels of one context overlap
+    those of the others (memory-bound column passes beside transform-bound row
+    passes, and the tails of launches): W warm-up and K timed steps, the final
+    states compared bitwise with the one-context run's (ref_final, after the
+    same steps)."""
     import numpy as np
     from sgn_inputs import perturbed_soliton_sweep
     box, state, ak, w = perturbed_soliton_sweep(eps=PARAMS["eps"])
@@ -226,24 +225,12 @@ def streams_form(sgn, torch, dev, args, ref_final):
         ctxs.append((ctx, [torch.from_numpy(np.ascontiguousarray(a[i0:i0 + nm])).to(dev) for a in state]))
         i0 += nm
     torch.cuda.synchronize()
-    infos = [None] * len(ctxs)
-
-    def run(i, n):
-        c, fl = ctxs[i]
-        infos[i] = sgn.sgn_rk4_step(c, *fl, w["dt"], n)
-
-    def all_threads(n):
-        th = [threading.Thread(target=run, args=(i, n)) for i in range(len(ctxs))]
-        for t in th:
-            t.start()
-        for t in th:
-            t.join()
-
+    cl, fl, dts = [c for c, _ in ctxs], [f for _, f in ctxs], [w["dt"]] * len(ctxs)
     if args.warmup > 0:
-        all_threads(args.warmup)
+        sgn.sgn_rk4_step_ensemble(cl, fl, dts, args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    all_threads(args.steps)
+    infos = sgn.sgn_rk4_step_ensemble(cl, fl, dts, args.steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     final = [torch.cat([fl[i] for _, fl in ctxs]) for i in range(4)]
@@ -251,7 +238,7 @@ def streams_form(sgn, torch, dev, args, ref_final):
            "ms_per_step": el * 1e3 / args.steps,
            "identical_to_one_context": all(torch.equal(a, b) for a, b in zip(final, ref_final)),
            "launch_shapes": [sgn.sgn_launch_shape(c) for c, _ in ctxs]}
-    out.update(iters_summary([i for grp in infos for i in grp]))
+    out.update(iters_summary(infos))
     for c, _ in ctxs:
         c.close()
     return out
@@ -671,14 +658,13 @@ def batched_form(sgn, torch, dev, args, per_grid: int = 16):
     in the mixed-precision mode, K steps after a warm-up step:
       members: one ensemble context per grid size (16 members each, every
         kernel launch covers the 16 grids), the four contexts on four streams
-        driven by four host threads;
+        advanced by one sgn_rk4_step_ensemble call (a host thread each);
       members_serial: the same four contexts one after another on one stream;
       contexts: the 64 members on 64 contexts of their own (streams and host
         threads, sgn_rk4_step_ensemble), the previous form; and with their
         steps replayed as captured graphs (graph_value);
       sequential: the 64 contexts one after another.
     Kernel B of the 1024x1024 group is timed against the HBM roofline."""
-    import threading
     import numpy as np
     from sgn_inputs import ENSEMBLE_GRIDS, ensemble_member
     steps = max(1, min(args.steps, 10))
@@ -707,26 +693,17 @@ def batched_form(sgn, torch, dev, args, per_grid: int = 16):
         f = [torch.from_numpy(np.ascontiguousarray(np.stack([m[i] for m in states]))).to(dev).to(torch.float32)
              for i in range(4)]
         ctxs.append((ctx, f, dt, stream))
-    infos = [None] * len(ctxs)
-
     def run(i, n):
         c, f, dt, _ = ctxs[i]
-        infos[i] = sgn.sgn_rk4_step(c, *f, dt, n)
+        sgn.sgn_rk4_step(c, *f, dt, n)
 
-    def all_threads(n):
-        th = [threading.Thread(target=run, args=(i, n)) for i in range(len(ctxs))]
-        for t in th:
-            t.start()
-        for t in th:
-            t.join()
-
-    all_threads(1)
+    cl, fl, dl = [c[0] for c in ctxs], [c[1] for c in ctxs], [c[2] for c in ctxs]
+    sgn.sgn_rk4_step_ensemble(cl, fl, dl, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    all_threads(steps)
+    flat = sgn.sgn_rk4_step_ensemble(cl, fl, dl, steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    flat = [i for grp in infos for i in grp]
     out["value"] = pts * steps / el
     out["ms_per_step"] = el * 1e3 / steps
     out.update(iters_summary(flat))

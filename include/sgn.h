@@ -265,22 +265,25 @@ int sgn_rk4_step_graph(sgn_ctx* ctx, void* h, void* vx, void* vy, void* sigma, d
 int sgn_invariants(sgn_ctx* ctx, const void* h, const void* vx, const void* vy, void* sigma,
                    sgn_invariants_out* out);
 
-/* Ensembles: nsteps RK4 steps of n independent members at once.  Member i is
- * its own context ctxs[i] (own grid, precision, workspace and stream; the
- * contexts must be distinct) with its fields h[i], vx[i], vy[i], sigma[i] and
- * step dt[i]; each member is advanced exactly as by sgn_rk4_step, on a host
- * thread of its own, so that the GPU runs the other members' kernels while
- * one member's thread waits for its GMRES status.  Give the members different
- * streams for their work to overlap.  infos: NULL or n entries.  Every member
- * is run; the first non-OK member status is returned. */
+/* Ensembles: nsteps RK4 steps of n independent contexts at once.  Context i
+ * is ctxs[i] (own grid, precision, workspace and stream; the contexts must be
+ * distinct) with its fields h[i], vx[i], vy[i], sigma[i] and step dt[i]; each
+ * is advanced exactly as by sgn_rk4_step, on a host thread of its own, so that
+ * the GPU runs the other contexts' kernels while one context's thread waits
+ * for its GMRES status.  Give the contexts different streams for their work to
+ * overlap.  A context may hold several members (cfg.batch > 1): its fields are
+ * then [batch][ny][nx] and its infos the batch consecutive entries that follow
+ * those of ctxs[0..i-1].  infos: NULL or (sum of the contexts' batch) entries.
+ * Every context is run; the first non-OK status is returned. */
 int sgn_rk4_step_ensemble(int32_t n, sgn_ctx* const* ctxs, void* const* h, void* const* vx, void* const* vy,
                           void* const* sigma, const double* dt, int32_t nsteps, sgn_step_info* infos);
 
-/* The same, each member's steps run by sgn_rk4_step_graph (automatic
+/* The same, each context's steps run by sgn_rk4_step_graph (automatic
  * iteration budget) on its thread: no host round trip per solve, so the
- * members' kernels interleave more densely.  Results are bitwise those of
- * sgn_rk4_step_ensemble.  A member with a learned guess attached is refused
- * (SGN_ERR_UNSUPPORTED), as by sgn_rk4_step_graph. */
+ * contexts' kernels interleave more densely.  Results are bitwise those of
+ * sgn_rk4_step_ensemble.  A context with a learned guess attached, or with
+ * several members, is refused (SGN_ERR_UNSUPPORTED), as by
+ * sgn_rk4_step_graph. */
 int sgn_rk4_step_ensemble_graph(int32_t n, sgn_ctx* const* ctxs, void* const* h, void* const* vx, void* const* vy,
                                 void* const* sigma, const double* dt, int32_t nsteps, sgn_step_info* infos);
 

@@ -1712,11 +1712,14 @@ namespace {
 int run_ensemble(int32_t n, sgn_ctx* const* ctxs, void* const* h, void* const* vx, void* const* vy,
                  void* const* sigma, const double* dt, int32_t nsteps, sgn_step_info* infos, bool graphs) {
   if (n < 0 || (n > 0 && (!ctxs || !h || !vx || !vy || !sigma || !dt)) || nsteps < 0) return SGN_ERR_INVALID_ARG;
+  // infos of context i: members(ctxs[i]) entries after those of the earlier contexts
+  std::vector<int> off(n > 0 ? n : 1, 0);
   for (int i = 0; i < n; ++i) {
     if (!ctxs[i]) return SGN_ERR_INVALID_ARG;
-    if (members(ctxs[i]) > 1) return SGN_ERR_UNSUPPORTED;  // one info per context: single grids only
+    if (graphs && members(ctxs[i]) > 1) return SGN_ERR_UNSUPPORTED;  // the captured step runs single grids
     for (int k = 0; k < i; ++k)
       if (ctxs[k] == ctxs[i]) return SGN_ERR_INVALID_ARG;  // a context is not thread-safe
+    if (i + 1 < n) off[i + 1] = off[i] + members(ctxs[i]);
   }
   std::vector<int> rc(n, SGN_OK);
   std::vector<std::thread> threads;
@@ -1727,7 +1730,7 @@ int run_ensemble(int32_t n, sgn_ctx* const* ctxs, void* const* h, void* const* v
         rc[i] = SGN_ERR_HIP;
         return;
       }
-      sgn_step_info* inf = infos ? &infos[i] : nullptr;
+      sgn_step_info* inf = infos ? &infos[off[i]] : nullptr;
       rc[i] = graphs ? sgn_rk4_step_graph(ctxs[i], h[i], vx[i], vy[i], sigma[i], dt[i], nsteps, 0, inf, nullptr)
                      : sgn_rk4_step(ctxs[i], h[i], vx[i], vy[i], sigma[i], dt[i], nsteps, inf);
     });

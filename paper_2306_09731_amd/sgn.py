@@ -345,21 +345,24 @@ def sgn_rk4_step_graph(ctx: Context, h, vx, vy, sigma, dt: float, nsteps: int = 
 
 
 def sgn_rk4_step_ensemble(ctxs, fields, dts, nsteps: int, graphs: bool = False):
-    """nsteps RK4 steps of every member; fields[i] = (h, vx, vy, sigma) of
-    member i, dts[i] its step; graphs: each member's steps as captured-graph
-    replays.  Returns the list of sgn_step_info."""
+    """nsteps RK4 steps of every context; fields[i] = (h, vx, vy, sigma) of
+    context i ([batch][ny][nx] for a context of several members), dts[i] its
+    step; graphs: each context's steps as captured-graph replays (single-grid
+    contexts only).  Returns the list of sgn_step_info, one per member, the
+    contexts' members in order."""
     n = len(ctxs)
     if not (len(fields) == n and len(dts) == n):
         raise ValueError("one field tuple and one dt per context")
     arr = lambda vals: (_VP * max(n, 1))(*vals)
     ptrs = [[_field(c, f[k], name) for c, f in zip(ctxs, fields)] for k, name in enumerate(("h", "vx", "vy", "sigma"))]
-    infos = (sgn_step_info * max(n, 1))()
+    total = sum(c.cfg.batch for c in ctxs)
+    infos = (sgn_step_info * max(total, 1))()
     lib = load_library()
     fn = lib.sgn_rk4_step_ensemble_graph if graphs else lib.sgn_rk4_step_ensemble
     st = fn(n, arr([c.handle for c in ctxs]), *(arr(p) for p in ptrs), (ctypes.c_double * max(n, 1))(*dts), nsteps,
             infos)
     _check(None, st, (SGN_OK, SGN_ERR_NOT_CONVERGED))
-    return [infos[i] for i in range(n)]
+    return [infos[i] for i in range(total)]
 
 
 ARNOLDI_SCHEDULES = {0: "four kernels, one chain", 1: "four kernels, two chains", 2: "three kernels"}

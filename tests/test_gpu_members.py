@@ -251,3 +251,40 @@ def test_members_autotune_radix_and_results():
         assert np.abs(got - results["0"][0][k]).max() / np.abs(results["0"][0][k] - 1.0).max() < 1e-12
     assert all(i.any_unconverged == 0 for i in infos)
     cb.close()
+
+
+def test_member_contexts_in_one_ensemble_call():
+    """Two member contexts (three and two members of a 128x64 grid) advanced by
+    one sgn_rk4_step_ensemble call, each on a stream of its own, end bitwise
+    equal to the same contexts stepped one after the other, with one info per
+    member in order; the captured-graph ensemble refuses member contexts."""
+    nx, ny = 128, 64
+    box = Box(nx, ny, 2.0, 2.0)
+    params = PARAMS + [(0.3, 0.02, 2), (0.7, 0.01, 1)]
+    fields = soliton_members(box, params)
+    splits = [(0, 3), (3, 5)]
+
+    def make():
+        cs, fs = [], []
+        for a, b in splits:
+            cfg = sgn.config_default(nx, ny, 2.0, 2.0, batch=b - a, gmres_tol=1e-10)
+            cs.append(sgn.sgn_init(cfg, DEV, stream=torch.cuda.Stream(DEV)))
+            fs.append([to_dev(x[a:b], torch.float64) for x in fields])
+        torch.cuda.synchronize()
+        return cs, fs
+
+    c1, f1 = make()
+    infos = sgn.sgn_rk4_step_ensemble(c1, f1, [0.005, 0.005], 3)
+    c2, f2 = make()
+    ref = []
+    for c, f in zip(c2, f2):
+        ref += sgn.sgn_rk4_step(c, *f, 0.005, 3)
+    say("member contexts in one ensemble call, iterations: " + " ".join(str(i.total_iters) for i in infos))
+    assert len(infos) == len(params)
+    assert [i.total_iters for i in infos] == [r.total_iters for r in ref]
+    for fa, fb in zip(f1, f2):
+        assert all(np.array_equal(host(fa[i]), host(fb[i])) for i in range(4))
+    with pytest.raises(sgn.SgnError):
+        sgn.sgn_rk4_step_ensemble(c1, f1, [0.005, 0.005], 1, graphs=True)
+    for c in c1 + c2:
+        c.close()
