@@ -619,6 +619,28 @@ __global__ void __launch_bounds__(512) k_row_dx(Geom g, const real* __restrict__
   store_phys_pair<N>(v, out, ya, t);
 }
 
+#ifndef SGN_FAST_RECIP
+#define SGN_FAST_RECIP 1
+#endif
+// 1 / x for a positive normal x (the depth h, which the field checks keep
+// positive, and the preconditioner symbol, at least m0 = 3 / h_inf^3): the
+// hardware reciprocal estimate refined by two Newton steps, within an ulp of
+// the quotient, instead of the full division sequence (scaling and fix-up for
+// zeros, infinities and denormals, which these operands never are; a depth
+// or symbol beyond the normal range would give a non-finite result, which the
+// field checks report)
+__device__ __forceinline__ double recip_pos(double x) {
+#if SGN_FAST_RECIP
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+
 // Elliptic operator, x part, in x-spectral form.  From E = F_x sigma and
 // G = F_x d_y sigma (x-half spectra) and the depth h:
 //   A1 = F_x(3 sigma / h^3) - i kx F_x(d_x sigma / h),   A2 = F_x(d_y sigma / h)
@@ -649,7 +671,7 @@ __global__ void __launch_bounds__(512) k_row_op(Geom g, const cplx* __restrict__
   if (MODE == 0 && predicate && st->st.done) return;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    hi[r] = make_cplx(1.0 / hi[r].x, 1.0 / hi[r].y);
+    hi[r] = make_cplx(recip_pos(hi[r].x), recip_pos(hi[r].y));
     u[r] = mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Lx));
   }
   fft<N, true, decltype(map)>(v, buf, t, twx, map);  // sigma
@@ -729,7 +751,7 @@ __global__ void __launch_bounds__(1024) k_row_matvec3(Geom g, const cplx* __rest
   if (st->st.done) return;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    hi[r] = make_cplx(1.0 / hi[r].x, 1.0 / hi[r].y);
+    hi[r] = make_cplx(recip_pos(hi[r].x), recip_pos(hi[r].y));
     if (chain == 1) v[r] = mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Lx));
   }
   fft<N, true, RowMap>(v, buf, t, twx, map);
@@ -836,7 +858,7 @@ __global__ void __launch_bounds__(512) k_row_matvec2(Geom g, const cplx* __restr
   if (st->st.done) return;  // tested after the (in-bounds) loads are issued
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    hi[r] = make_cplx(1.0 / hi[r].x, 1.0 / hi[r].y);
+    hi[r] = make_cplx(recip_pos(hi[r].x), recip_pos(hi[r].y));
     if (chain == 1) v[r] = mul_ik(v[r], wavenumber(t + r * TPF, N, g.inv_Lx));
   }
   fft<N, true, RowMap>(v, buf, t, twx, map);
@@ -939,7 +961,7 @@ __global__ void __launch_bounds__(512) k_row_flux(Geom g, const cplx* __restrict
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const double a = hh[r].x, b = hh[r].y;
-    const double ia = 1.0 / a, ib = 1.0 / b;
+    const double ia = recip_pos(a), ib = recip_pos(b);
     const double sa = s[r].x * ia * ia, sb = s[r].y * ib * ib;
     const double rxa = sx[r].x * ia, rxb = sx[r].y * ib, rya = sy[r].x * ia, ryb = sy[r].y * ib;
     B[r].x = 0.5 * (ux[r].x * ux[r].x + uy[r].x * uy[r].x) - 0.5 * (rxa * rxa + rya * rya) + g.g * a - 4.5 * sa * sa;
@@ -1082,7 +1104,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 }
 
 __device__ __forceinline__ double inv_symbol(const Geom& g, double kx, double ky) {
-  return 1.0 / (g.m0 + g.m1 * (kx * kx + ky * ky));
+  return recip_pos(g.m0 + g.m1 * (kx * kx + ky * ky));
 }
 
 // Weight of a half-spectrum column in a physical inner product:
